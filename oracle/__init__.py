@@ -1,0 +1,227 @@
+"""CPU oracle for one refinement step (Algorithm 4 with Algorithm 1) of
+Terao, Ozaki, Imamura and Ogita, arXiv 2602.23778.
+
+TEST INFRASTRUCTURE ONLY: only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  The GPU library
+never links, imports or calls it, and it shares no code with that library.
+
+The arithmetic lives in ``oracle.c`` (plain C loops, IEEE double, fixed
+ascending summation order); this module only marshals numpy arrays into it.
+Every function states the passage of the paper it follows.  Functions that
+are not pinned by an independent check say "parity unpinned" here; at present
+every exported function is pinned by ``tests/test_oracle_pins.py``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+OK = 0
+EINVAL = -1
+SINGULAR = -4
+NONFINITE = -6
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so with gcc (OpenMP, no FP contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+               "-std=c11", "-shared", "-fPIC", _SRC, "-o", tmp, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+class _Matrix(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("kind", ctypes.c_int32),
+                ("a", ctypes.c_void_p), ("lda", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p),
+                ("val", ctypes.c_void_p)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_double), ("delta_c", ctypes.c_double),
+                ("norm_a", ctypes.c_double), ("beta_zero", ctypes.c_int32),
+                ("normalize", ctypes.c_int32), ("dd", ctypes.c_int32),
+                ("shift_in_denominators", ctypes.c_int32),
+                ("plant_printed_sign", ctypes.c_int32)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("corr_fro", ctypes.c_double), ("resid_rel", ctypes.c_double),
+                ("cond_y1", ctypes.c_double)]
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        i64, vp, dbl = ctypes.c_int64, ctypes.c_void_p, ctypes.c_double
+        lib.orc_gemm_dense.argtypes = [i64, i64, vp, i64, vp, i64, vp, i64]
+        lib.orc_gemm_dense_dd.argtypes = [i64, i64, vp, i64, vp, i64, vp, vp, i64]
+        lib.orc_gemm_csr.argtypes = [i64, i64, vp, vp, vp, vp, i64, vp, i64]
+        lib.orc_gemm_csr_dd.argtypes = [i64, i64, vp, vp, vp, vp, i64, vp, vp, i64]
+        lib.orc_compact_wy.argtypes = [i64, i64, vp, i64, vp, vp, vp]
+        lib.orc_compact_wy.restype = ctypes.c_int
+        lib.orc_apply_h.argtypes = [i64, i64, vp, vp, ctypes.c_int, vp, i64, vp]
+        lib.orc_refine_step.argtypes = [ctypes.POINTER(_Matrix), i64, vp, i64, vp, i64,
+                                        ctypes.POINTER(_Opts), ctypes.POINTER(_Stats), vp, vp]
+        lib.orc_refine_step.restype = ctypes.c_int
+        lib.orc_norm_inf_dense.argtypes = [i64, vp, i64]
+        lib.orc_norm_inf_dense.restype = dbl
+        lib.orc_norm_inf_csr.argtypes = [i64, vp, vp]
+        lib.orc_norm_inf_csr.restype = dbl
+        _lib = lib
+    return _lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+@dataclass
+class Csr:
+    """Symmetric matrix in CSR form (int32 indices, float64 values)."""
+    n: int
+    row_ptr: np.ndarray
+    col_idx: np.ndarray
+    val: np.ndarray
+
+    def __post_init__(self):
+        self.row_ptr = np.ascontiguousarray(self.row_ptr, dtype=np.int32)
+        self.col_idx = np.ascontiguousarray(self.col_idx, dtype=np.int32)
+        self.val = np.ascontiguousarray(self.val, dtype=np.float64)
+
+
+def matmul(A, X, dd: bool = False):
+    """Line 1 of Algorithm 4, W = A X (dense ndarray or Csr).  With dd=True
+    returns (W_hi, W_lo) from the compensated dot product Dot2."""
+    lib = _load()
+    X = _f64(X)
+    n, k = X.shape
+    W = np.empty((n, k))
+    Wlo = np.empty((n, k))
+    if isinstance(A, Csr):
+        if dd:
+            lib.orc_gemm_csr_dd(n, k, _p(A.row_ptr), _p(A.col_idx), _p(A.val), _p(X), k,
+                                _p(W), _p(Wlo), k)
+        else:
+            lib.orc_gemm_csr(n, k, _p(A.row_ptr), _p(A.col_idx), _p(A.val), _p(X), k, _p(W), k)
+    else:
+        A = _f64(A)
+        if dd:
+            lib.orc_gemm_dense_dd(n, k, _p(A), A.shape[1], _p(X), k, _p(W), _p(Wlo), k)
+        else:
+            lib.orc_gemm_dense(n, k, _p(A), A.shape[1], _p(X), k, _p(W), k)
+    return (W, Wlo) if dd else W
+
+
+def compact_wy(X):
+    """Algorithm 1: Y = X - I_{n,k}, T = -Y1^{-T}.  Returns (status, Y, T, cond1)."""
+    lib = _load()
+    X = _f64(X)
+    n, k = X.shape
+    Y = np.empty((n, k))
+    T = np.empty((k, k))
+    c = ctypes.c_double(0.0)
+    rc = lib.orc_compact_wy(n, k, _p(X), k, _p(Y), _p(T), ctypes.byref(c))
+    return rc, Y, T, c.value
+
+
+def apply_h(Y, T, B, trans: bool = False):
+    """H B or H^T B with H = I - Y T Y^T, without forming H (after Table 1)."""
+    lib = _load()
+    Y, T, B = _f64(Y), _f64(T), _f64(B)
+    n, k = Y.shape
+    m = B.shape[1]
+    out = np.empty((n, m))
+    lib.orc_apply_h(n, k, _p(Y), _p(T), 1 if trans else 0, _p(B), m, _p(out))
+    return out
+
+
+def norm_inf(A) -> float:
+    lib = _load()
+    if isinstance(A, Csr):
+        return lib.orc_norm_inf_csr(A.n, _p(A.row_ptr), _p(A.val))
+    A = _f64(A)
+    return lib.orc_norm_inf_dense(A.shape[0], _p(A), A.shape[1])
+
+
+@dataclass
+class StepResult:
+    status: int
+    X: np.ndarray
+    corr_fro: float
+    resid_rel: float
+    cond_y1: float
+    d: np.ndarray
+    E: np.ndarray
+
+
+def refine_step(A, X, *, mu: float = 0.0, norm_a: float | None = None,
+                delta_c: float = 10.0, beta_zero: bool = False,
+                normalize: bool = True, dd: bool = False,
+                shift_in_denominators: bool = False,
+                plant_printed_sign: bool = False) -> StepResult:
+    """One step of Algorithm 4 (with Algorithm 1) on A (dense or Csr).
+
+    mu: the method runs on A - mu I (Sec. 5.1); norm_a: ||A|| in delta and in
+    the residual statistic (default ||A||_inf); dd: line 1 in double-double.
+    plant_printed_sign exists only so that a test can show that the sign
+    printed in eq. (V-def) makes the iteration diverge."""
+    lib = _load()
+    X = _f64(X)
+    n, k = X.shape
+    if norm_a is None:
+        norm_a = norm_inf(A)
+    m = _Matrix()
+    m.n = n
+    keep = []
+    if isinstance(A, Csr):
+        m.kind = 1
+        m.row_ptr, m.col_idx, m.val = _p(A.row_ptr), _p(A.col_idx), _p(A.val)
+        m.a, m.lda = None, 0
+    else:
+        A = _f64(A)
+        keep.append(A)
+        m.kind = 0
+        m.a, m.lda = _p(A), A.shape[1]
+    o = _Opts(mu, delta_c, norm_a, int(beta_zero), int(normalize), int(dd),
+              int(shift_in_denominators), int(plant_printed_sign))
+    st = _Stats()
+    Xout = np.zeros((n, k))
+    d = np.zeros(k)
+    E = np.zeros((n, k))
+    rc = lib.orc_refine_step(ctypes.byref(m), k, _p(X), k, _p(Xout), k, ctypes.byref(o),
+                             ctypes.byref(st), _p(d), _p(E))
+    return StepResult(rc, Xout, st.corr_fro, st.resid_rel, st.cond_y1, d, E)
+
+
+def refine(A, X, steps: int, **kw):
+    """Repeated steps (the paper's driver loop); returns (X, [StepResult])."""
+    hist = []
+    for _ in range(steps):
+        r = refine_step(A, X, **kw)
+        hist.append(r)
+        if r.status != OK:
+            break
+        X = r.X
+    return X, hist

@@ -1,0 +1,364 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Each test names the passage of the paper (or the mathematical fact) it checks.
+They are chosen so that a plausible slip in the oracle -- a dropped term, a
+wrong sign or index, T instead of T^T, a missing shift -- fails at least one.
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests._util import align_signs, max_abs_diff_aligned
+
+U = 2.0 ** -53
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _sym_problem(n, lam, seed):
+    Q = synth.householder_q(n, n, seed).numpy()
+    A = (Q * lam) @ Q.T
+    A = 0.5 * (A + A.T)
+    return A, Q
+
+
+def _orthonormal(n, k, seed):
+    rng = np.random.default_rng(seed)
+    q, r = np.linalg.qr(rng.standard_normal((n, k)))
+    return q * np.sign(np.diag(r))
+
+
+# --------------------------------------------------------------------------
+# Algorithm 1 (compact WY)
+# --------------------------------------------------------------------------
+def test_wy_maps_first_columns_to_x_for_any_x():
+    """Alg. 1 ensures (I - Y T Y^T) I_{n,k} = Q.  The identity holds for any X
+    with a nonsingular Y1, orthonormal or not: H I_{n,k} = I_{n,k} + Y."""
+    rng = np.random.default_rng(1)
+    for n, k in ((9, 1), (30, 4), (64, 13)):
+        X = 0.3 * rng.standard_normal((n, k))
+        rc, Y, T, _ = oracle.compact_wy(X)
+        assert rc == oracle.OK
+        Ink = np.eye(n)[:, :k]
+        HX = oracle.apply_h(Y, T, Ink)
+        assert np.max(np.abs(HX - X)) < 1e-14
+        # Y itself is X - I_{n,k}
+        assert np.max(np.abs(Y - (X - Ink))) == 0.0
+
+
+def test_wy_is_orthogonal_for_orthonormal_x():
+    """Alg. 1 ensures I - Y T Y^T is orthogonal when Q has orthonormal columns."""
+    n, k = 50, 7
+    X = _orthonormal(n, k, 2)
+    rc, Y, T, _ = oracle.compact_wy(X)
+    assert rc == oracle.OK
+    H = oracle.apply_h(Y, T, np.eye(n))
+    assert np.max(np.abs(H.T @ H - np.eye(n))) < 1e-14
+    HT = oracle.apply_h(Y, T, np.eye(n), trans=True)
+    assert np.max(np.abs(HT - H.T)) < 1e-15
+    # H^T maps X onto I_{n,k} (eq. HX-and-HAX, first half)
+    assert np.max(np.abs(H.T @ X - np.eye(n)[:, :k])) < 1e-14
+
+
+def test_wy_singular_leading_block_is_reported():
+    """Sec. 3.1: Alg. 1 needs a nonsingular Y1; X = I_{n,k} gives Y1 = 0."""
+    n, k = 12, 3
+    rc, *_ = oracle.compact_wy(np.eye(n)[:, :k])
+    assert rc == oracle.SINGULAR
+    # nearly singular: first row of Y1 is (-2^-51, 0, 0), cond1(Y1) ~ 2^51 > 1/(n u)
+    X = _orthonormal(n, k, 3) * 1e-3
+    X[0, :] = 0.0
+    X[0, 0] = 1.0 - 2.0 ** -51
+    rc, *_ = oracle.compact_wy(X)
+    assert rc == oracle.SINGULAR
+
+
+# --------------------------------------------------------------------------
+# Line 1: W = A X, plain and double-double
+# --------------------------------------------------------------------------
+def _exact_product(A, X):
+    n, k = X.shape
+    Af = [[Fraction(float(v)) for v in row] for row in A]
+    Xf = [[Fraction(float(v)) for v in row] for row in X]
+    return [[sum(Af[i][l] * Xf[l][j] for l in range(n)) for j in range(k)] for i in range(n)]
+
+
+def test_matmul_error_bounds_against_exact_rationals():
+    """The plain product meets the textbook bound |W - AX| <= n u |A||X|; the
+    Dot2 pair meets u|AX| + (n u)^2 |A||X| (Ogita, Rump and Oishi 2005)."""
+    rng = np.random.default_rng(4)
+    n, k = 23, 3
+    A = rng.standard_normal((n, n))
+    A = A + A.T
+    # strong cancellation: make the last column nearly orthogonal to the rows
+    X = rng.standard_normal((n, k))
+    W = oracle.matmul(A, X)
+    Whi, Wlo = oracle.matmul(A, X, dd=True)
+    ex = _exact_product(A, X)
+    absAX = np.abs(A) @ np.abs(X)
+    for i in range(n):
+        for j in range(k):
+            e = ex[i][j]
+            assert abs(Fraction(W[i, j]) - e) <= Fraction(n * U * absAX[i, j])
+            err_dd = abs(Fraction(Whi[i, j]) + Fraction(Wlo[i, j]) - e)
+            bound = Fraction(U) * abs(e) * Fraction(1, 2 ** 50) + Fraction((n * U) ** 2 * absAX[i, j])
+            assert err_dd <= bound
+            # the high part is the nearest double (or next to it)
+            assert abs(Fraction(Whi[i, j]) - e) <= Fraction(U) * abs(e) * 2 + Fraction((n * U) ** 2 * absAX[i, j])
+
+
+def test_csr_matmul_matches_dense_library_product():
+    P = synth.laplacian3d(5, seed=11)
+    n = P.n
+    D = np.zeros((n, n))
+    for i in range(n):
+        for e in range(P.row_ptr[i], P.row_ptr[i + 1]):
+            D[i, P.col_idx[e]] = P.val[e]
+    assert np.array_equal(D, D.T)
+    X = np.random.default_rng(5).standard_normal((n, 6))
+    C = oracle.Csr(n, P.row_ptr, P.col_idx, P.val)
+    W = oracle.matmul(C, X)
+    assert np.max(np.abs(W - D @ X)) < 1e-13
+    Whi, Wlo = oracle.matmul(C, X, dd=True)
+    assert np.max(np.abs(Whi - D @ X)) < 1e-13
+    assert oracle.norm_inf(C) == pytest.approx(np.max(np.abs(D).sum(1)), rel=1e-15)
+
+
+# --------------------------------------------------------------------------
+# Lines 3-7 of Algorithm 4
+# --------------------------------------------------------------------------
+def test_top_block_of_v_is_xt_r():
+    """From eqs. (HhatX-block)-(HhatAX-block): the leading k rows of
+    H^T (W - X D) equal X^T (W - X D) for H built by Alg. 1 from X."""
+    n, k = 40, 6
+    A, Q = _sym_problem(n, np.linspace(0.1, 1.0, n), 6)
+    X = synth.fp32_round(Q[:, -k:]) + 1e-4 * np.random.default_rng(6).standard_normal((n, k))
+    rc, Y, T, _ = oracle.compact_wy(X)
+    W = A @ X
+    d = np.sum(X * W, 0) / np.sum(X * X, 0)
+    R = W - X * d
+    V = oracle.apply_h(Y, T, R, trans=True)
+    assert np.max(np.abs(V[:k] - X.T @ R)) < 1e-17
+
+
+def test_correction_structure_and_update():
+    """Line 6 of Alg. 4: e_jj = (1 - x_j^T x_j)/2; for i != j in the top block
+    e_ij + e_ji = -x_i^T x_j (the two branches v_ij/(d_j - d_i) and
+    v_ji/(d_i - d_j) combine to that); line 7: X~ - X = H E_L."""
+    n, k = 48, 7
+    A, Q = _sym_problem(n, np.linspace(0.05, 1.0, n), 7)
+    rng = np.random.default_rng(7)
+    X = Q[:, -k:] + 1e-5 * rng.standard_normal((n, k))
+    r = oracle.refine_step(A, X, norm_a=1.0, normalize=False)
+    assert r.status == 0
+    E = r.E
+    G = X.T @ X
+    assert np.max(np.abs(np.diag(E[:k]) - (1 - np.diag(G)) / 2)) < 1e-16
+    S = E[:k] + E[:k].T
+    off = ~np.eye(k, dtype=bool)
+    # rounding of v_ij is about u ||A||, divided by the gap d_j - d_i
+    gaps = np.abs(r.d[:, None] - r.d[None, :])[off]
+    tol = 64 * U / np.min(gaps)
+    assert np.max(np.abs(S[off] + G[off])) < tol
+    assert np.max(np.abs(G[off])) > 1e4 * tol   # the identity is not vacuous
+    # bottom block: e_ij = v_ij / d_j with V = H^T R
+    rc, Y, T, _ = oracle.compact_wy(X)
+    W = A @ X
+    d = np.sum(X * W, 0) / np.sum(X * X, 0)
+    V = oracle.apply_h(Y, T, W - X * d, trans=True)
+    assert np.max(np.abs(E[k:] - V[k:] / d)) < 64 * U / np.min(np.abs(d))
+    # update: H E = X~ - X with H formed explicitly by numpy
+    H = np.eye(n) - Y @ T @ Y.T
+    assert np.max(np.abs((r.X - X) - H @ E)) < 1e-15
+    # statistics describe the input
+    assert r.corr_fro == pytest.approx(np.linalg.norm(E), rel=1e-12)
+    assert r.resid_rel == pytest.approx(np.linalg.norm(W - X * d), rel=1e-6)
+
+
+def test_exact_eigenvectors_are_a_fixed_point():
+    """eq. (update-X): with E = 0 the correction vanishes; Q's columns are the
+    eigenvectors of A up to the rounding of A."""
+    n, k = 64, 8
+    A, Q = _sym_problem(n, np.arange(1, n + 1) / n, 8)
+    X = Q[:, -k:]
+    r = oracle.refine_step(A, X, norm_a=1.0)
+    assert r.status == 0
+    assert r.corr_fro < 1e-13
+    assert r.resid_rel < 1e-14
+    assert max_abs_diff_aligned(r.X, X) < 1e-14
+
+
+@pytest.mark.parametrize("mu", [0.0, 1.7])
+def test_k1_is_the_power_method(mu):
+    """For k = 1 the step reduces to one power iteration on A - mu I:
+    x~ = (A - mu I) x / ||(A - mu I) x|| for a unit x (Ĥ is then a reflector,
+    Ĥ Ĥ^T = I and v_1 = x^T r = 0)."""
+    n = 37
+    A, Q = _sym_problem(n, np.linspace(-1.0, 0.9, n), 9)
+    rng = np.random.default_rng(9)
+    x = Q[:, :1] + 0.05 * rng.standard_normal((n, 1))
+    x /= np.linalg.norm(x)
+    r = oracle.refine_step(A, x, mu=mu, norm_a=2.0)
+    y = A @ x - mu * x
+    y /= np.linalg.norm(y)
+    assert max_abs_diff_aligned(r.X, y) < 1e-15
+    r2 = oracle.refine_step(A, x, mu=mu, norm_a=2.0, shift_in_denominators=True)
+    assert max_abs_diff_aligned(r2.X, y) < 1e-15
+
+
+def test_linear_rate_matches_gamma():
+    """Sec. 3.2: each target converges linearly with factor
+    max_{i>k}|lam_i| / |lam_j|.  lam_i = i/64, k = 8: the slowest target
+    (lam = 57/64) has gamma = 56/57."""
+    n, k = 64, 8
+    A, Q = _sym_problem(n, np.arange(1, n + 1) / n, 10)
+    Xt = Q[:, ::-1][:, :k]
+    rng = np.random.default_rng(10)
+    X = Xt + 1e-4 * rng.standard_normal((n, k))
+    errs = []
+    for _ in range(420):
+        r = oracle.refine_step(A, X, norm_a=1.0)
+        X = r.X
+        errs.append(np.linalg.norm(align_signs(X, Xt) - Xt, axis=0))
+    errs = np.array(errs)
+    rate_slowest = (errs[400, k - 1] / errs[300, k - 1]) ** (1 / 100)
+    assert rate_slowest == pytest.approx(56 / 57, abs=2e-3)
+    # second slowest (lam = 58/64): gamma = 56/58
+    rate2 = (errs[200, k - 2] / errs[100, k - 2]) ** (1 / 100)
+    assert rate2 == pytest.approx(56 / 58, abs=3e-3)
+
+
+def test_printed_sign_of_v_def_diverges():
+    """eq. (V-def) prints the top block as D E11 - E11 D; eqs. (R) and (S) give
+    E11 D - D E11, which is what eq. (Eoffdiag) and Alg. 4 use.  Planting the
+    printed sign in the oracle makes the top-block error double every step,
+    while the oracle as written converges."""
+    n, k = 64, 8
+    A, Q = _sym_problem(n, np.arange(1, n + 1) / n, 11)
+    Xt = Q[:, ::-1][:, :k]
+    rng = np.random.default_rng(11)
+    X0 = Xt + 1e-9 * rng.standard_normal((n, k))
+    good, bad = X0.copy(), X0.copy()
+    eg, eb = [], []
+    for _ in range(12):
+        good = oracle.refine_step(A, good, norm_a=1.0).X
+        bad = oracle.refine_step(A, bad, norm_a=1.0, plant_printed_sign=True).X
+        eg.append(np.abs(align_signs(good, Xt) - Xt).max())
+        eb.append(np.abs(align_signs(bad, Xt) - Xt).max())
+    assert eg[-1] < eg[0]
+    ratio = (eb[-1] / eb[-5]) ** (1 / 4)
+    assert ratio == pytest.approx(2.0, rel=0.02)
+
+
+def test_shift_forms_agree():
+    """Sec. 5.1: refining the smallest eigenvalues through B = A - mu I.
+    The literal form (W_B = A X - mu X), the derived form (mu only in the
+    bottom denominators) and the method applied to mu I - A all give the same
+    update up to rounding."""
+    n, k = 60, 5
+    lam = np.concatenate([[0.1, 0.2, 0.3, 0.4, 0.5], np.linspace(1.5, 3.0, n - k)])
+    A, Q = _sym_problem(n, lam, 12)
+    mu = 3.5   # makes the k smallest the dominant ones of A - mu I (gamma = 2/3)
+    Xt = Q[:, :k]
+    X = synth.fp32_round(Xt)
+    r1 = oracle.refine_step(A, X, mu=mu, norm_a=3.0)
+    r2 = oracle.refine_step(A, X, mu=mu, norm_a=3.0, shift_in_denominators=True)
+    r3 = oracle.refine_step(-A, X, mu=-mu, norm_a=3.0)
+    assert np.max(np.abs(r1.X - r2.X)) < 1e-14
+    assert np.max(np.abs(r1.X - r3.X)) < 1e-14
+    # and it converges to the k smallest
+    Xc, hist = oracle.refine(A, X, 60, mu=mu, norm_a=3.0)
+    assert max_abs_diff_aligned(Xc, Xt) < 1e-12
+
+
+def test_converged_against_high_precision_jacobi():
+    """Known answer: the refined vectors of a small FP64 matrix agree with its
+    exact eigenvectors computed by cyclic Jacobi at 40 digits to a few u
+    (Sec. 4.2: the attainable accuracy is set by double-precision rounding)."""
+    from tests.mp_jacobi import jacobi_eigh
+    n, k = 20, 4
+    lam = np.concatenate([np.linspace(0.05, 0.5, n - k), [0.8, 0.85, 0.9, 1.0]])
+    A, Q = _sym_problem(n, lam, 13)
+    lam_mp, V = jacobi_eigh(A.tolist(), dps=40)
+    order = sorted(range(n), key=lambda i: -float(lam_mp[i]))[:k]
+    Xex = np.array([[float(V[r][c]) for c in order] for r in range(n)])
+    X = synth.fp32_round(Q[:, ::-1][:, :k])
+    Xd, _ = oracle.refine(A, X, 80, norm_a=1.0, dd=True)
+    Xf, _ = oracle.refine(A, X, 80, norm_a=1.0)
+    assert max_abs_diff_aligned(Xd, Xex) < 8 * U
+    assert max_abs_diff_aligned(Xf, Xex) < 40 * U
+    # the Rayleigh quotients of the result equal the exact eigenvalues
+    r = oracle.refine_step(A, Xd, norm_a=1.0, dd=True)
+    lam_ex = np.array([float(lam_mp[i]) for i in order])
+    assert np.max(np.abs(r.d - lam_ex)) < 4 * U
+    # residual floor O(u)||A|| (Sec. 4.2)
+    assert r.resid_rel < 20 * U
+
+
+def test_clustered_pair_needs_accurate_residual():
+    """Two target eigenvalues 1e-6 apart: the double-double residual lets the
+    iteration reach the exact eigenvectors (Jacobi, 40 digits) far more
+    closely than plain FP64, whose error is about u / gap."""
+    from tests.mp_jacobi import jacobi_eigh
+    n, k = 24, 4
+    lam = np.concatenate([np.linspace(0.05, 0.6, n - k), [0.98, 0.98 + 1e-6, 0.99, 0.99 + 1e-6]])
+    A, Q = _sym_problem(n, lam, 14)
+    lam_mp, V = jacobi_eigh(A.tolist(), dps=40)
+    order = sorted(range(n), key=lambda i: -float(lam_mp[i]))[:k]
+    Xex = np.array([[float(V[r][c]) for c in order] for r in range(n)])
+    X = synth.fp32_round(Q[:, ::-1][:, :k])     # descending lam, like Xex
+    Xd, hd = oracle.refine(A, X, 120, norm_a=1.0, dd=True)
+    Xf, hf = oracle.refine(A, X, 120, norm_a=1.0)
+    ed = max_abs_diff_aligned(Xd, Xex)
+    ef = max_abs_diff_aligned(Xf, Xex)
+    assert ed < 1e-13
+    assert ed < ef
+
+
+def test_forced_failures():
+    """Status codes: singular Y1 (Sec. 3.1), non-finite input, invalid sizes."""
+    n, k = 16, 3
+    A, Q = _sym_problem(n, np.linspace(0.1, 1, n), 15)
+    r = oracle.refine_step(A, np.eye(n)[:, :k], norm_a=1.0)
+    assert r.status == oracle.SINGULAR
+    X = Q[:, -k:].copy()
+    X[3, 1] = np.nan
+    assert oracle.refine_step(A, X, norm_a=1.0).status == oracle.NONFINITE
+    assert oracle.refine_step(A, Q, norm_a=1.0).status == oracle.EINVAL   # k == n
+
+
+def test_beta_branch_for_exact_ties():
+    """Line 6 of Alg. 4: equal Rayleigh quotients take beta_ij = -x_i^T x_j/2
+    (or 0 after preprocessing) instead of dividing by d_j - d_i."""
+    n, k = 30, 2
+    lam = np.concatenate([np.linspace(0.1, 0.5, n - 2), [1.0, 1.0]])
+    A, Q = _sym_problem(n, lam, 16)
+    # two vectors spanning the exact double eigenvalue: their Rayleigh
+    # quotients coincide to rounding
+    X = Q[:, -2:] @ np.array([[np.cos(0.3), -np.sin(0.3)], [np.sin(0.3), np.cos(0.3)]])
+    X = X + 1e-12 * np.random.default_rng(16).standard_normal((n, k))
+    r = oracle.refine_step(A, X, norm_a=1.0, normalize=False, delta_c=1e6)
+    G = X.T @ X
+    assert abs(r.d[0] - r.d[1]) < 1e6 * 10 * U      # the tie is detected
+    assert r.E[0, 1] == pytest.approx(-G[0, 1] / 2, abs=1e-15)
+    assert r.E[1, 0] == pytest.approx(-G[1, 0] / 2, abs=1e-15)
+    r0 = oracle.refine_step(A, X, norm_a=1.0, normalize=False, delta_c=1e6, beta_zero=True)
+    assert r0.E[0, 1] == 0.0 and r0.E[1, 0] == 0.0
+
+
+def test_golden_k1_power_iteration_values():
+    """Golden fixture: a 3x3 closed-form case (tests/golden/k1_power_3x3.json)
+    whose expected vector is the normalised A x, written out by hand."""
+    with open(os.path.join(GOLDEN, "k1_power_3x3.json")) as f:
+        g = json.load(f)
+    A = np.array(g["A"], dtype=np.float64)
+    x = np.array(g["x"], dtype=np.float64)[:, None]
+    r = oracle.refine_step(A, x, norm_a=g["norm_a"])
+    exp = np.array(g["expected"], dtype=np.float64)[:, None]
+    assert max_abs_diff_aligned(r.X, exp) < 4 * U
+    assert r.d[0] == pytest.approx(g["rayleigh"], abs=4 * U)
