@@ -1,0 +1,189 @@
+/*
+ * refine.h -- C ABI of the MI355X (gfx950) library for iterative refinement
+ * of a subset of eigenvectors of a real symmetric matrix (Terao, Ozaki,
+ * Imamura and Ogita, "Iterative Refinement for a Subset of Eigenvectors of
+ * Symmetric Matrices via Matrix Multiplications", arXiv 2602.23778).
+ *
+ * Problem (Sec. 1 and Sec. 3, eqs. HX-and-HAX and update-X): A is n x n real
+ * symmetric, X (n x k, k < n) approximates k eigenvectors of A.  One
+ * refinement step (Algorithm 4 with Algorithm 1) computes
+ *     W = A X,  d_j = x_j^T w_j / x_j^T x_j,  R = W - X diag(d),
+ *     the compact WY factors Y = X - I_{n,k}, T = -Y1^{-T},
+ *     V = H^T R,  the correction matrix E_L (line 6 of Algorithm 4),
+ *     X <- X + H E_L,  and normalises the columns of X.
+ * The targets are the k eigenvalues of largest |lambda - mu| (eq. condition,
+ * Sec. 5.1 for the shifted variants); mu = 0 is the paper's default.
+ *
+ * Conventions for every entry point:
+ *   - All matrix and iterate pointers are DEVICE pointers owned by the caller.
+ *   - Dense A is row-major with leading dimension lda >= n (A is symmetric,
+ *     so row- and column-major coincide).  CSR A has int32 row_ptr[n+1],
+ *     int32 col_idx[nnz] (full symmetric pattern) and double val[nnz].
+ *   - X is row-major n x k with leading dimension ldx >= k (the layout of a
+ *     contiguous PyTorch tensor of shape (n, k)); it is updated in place.
+ *   - Work is issued on the HIP stream given at init (NULL = the null
+ *     stream).  Calls on one context must not overlap; contexts are not
+ *     thread-safe.  A context owns its workspace, its INT8 slices of A (split
+ *     mode) and its HIP graphs; A is borrowed and must stay valid until
+ *     refine_destroy (in split mode A is read only during refine_init).
+ *   - Return values are the status codes below; no C++ exception crosses
+ *     the ABI.  On an error status X holds the last iterate that was
+ *     accepted (a step whose correction is rejected does not write X).
+ */
+#ifndef REFINE_H
+#define REFINE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define REFINE_OK 0
+#define REFINE_NOT_CONVERGED 1   /* refine_run: max_iters reached before tol */
+#define REFINE_EINVAL (-1)       /* bad argument (sizes, pointers, options) */
+#define REFINE_ENOMEM (-2)       /* device or host allocation failed */
+#define REFINE_EHIP (-3)         /* a HIP runtime call failed */
+#define REFINE_EWY_SINGULAR (-4) /* Y1 = X(1:k,:) - I_k singular or cond_1 > 1/(n u)
+                                    (Algorithm 1 needs Y1 nonsingular, Sec. 3.1);
+                                    the one-time sign flip X <- X Sigma of Sec. 3.1
+                                    is left to the caller */
+#define REFINE_EDIVERGED (-5)    /* ||E_L||_F >= 1 (the Neumann expansion of
+                                    eq. Neumann needs ||E|| < 1), or ||E_L||_F grew
+                                    tenfold over three steps (Sec. 4.3 guidance) */
+#define REFINE_ENONFINITE (-6)   /* NaN or Inf in X or in the step's reductions */
+
+typedef struct refine_ctx refine_ctx;
+typedef struct refine_batch refine_batch;
+
+typedef enum { REFINE_DENSE = 0, REFINE_CSR = 1 } refine_kind;
+
+/* Arithmetic of the product W = A X (line 1 of Algorithm 4).
+ *   REFINE_FP64: every step in IEEE double (the paper's experiments, Sec. 3.3).
+ *   REFINE_SPLIT_INT8: A X by error-free splitting of A and X into INT8
+ *     slices with exact INT32 accumulation on the matrix cores, recombined
+ *     into a double-double W; the residual R = W - X diag(d) is then formed
+ *     with an exact product, the rest of the step in double (the
+ *     mixed-precision direction of Sec. 3.3).  Dense only. */
+typedef enum { REFINE_FP64 = 0, REFINE_SPLIT_INT8 = 1 } refine_precision;
+
+/* Which eigenpairs are targeted (eq. condition and Sec. 5.1):
+ *   LARGEST_ABS: mu = 0, the k eigenvalues of largest |lambda|;
+ *   SMALLEST:    mu = max_i (a_ii + sum_{j!=i} |a_ij|) (Gershgorin upper bound);
+ *   LARGEST:     mu = min_i (a_ii - sum_{j!=i} |a_ij|) (Gershgorin lower bound);
+ *   SHIFT:       mu = options.shift, e.g. (||A||_inf + lambda_{k+1})/2 (Sec. 5.1). */
+typedef enum {
+  REFINE_TARGET_LARGEST_ABS = 0,
+  REFINE_TARGET_SMALLEST = 1,
+  REFINE_TARGET_LARGEST = 2,
+  REFINE_TARGET_SHIFT = 3
+} refine_target;
+
+/* beta_ij for (near-)equal Rayleigh quotients (line 6 of Algorithm 4):
+ * -x_i^T x_j / 2, or 0 after Rayleigh-Ritz preprocessing (Sec. 3.4). */
+typedef enum { REFINE_BETA_HALF_GRAM = 0, REFINE_BETA_ZERO = 1 } refine_beta;
+
+/* Stopping rules of Sec. 3.3: a fixed number of steps, ||E_L||_F <= tol,
+ * or ||A X - X D||_F / ||A|| <= tol.  The test is made after each step; the
+ * statistics describe the iterate that entered that step. */
+typedef enum {
+  REFINE_STOP_ITERS = 0,
+  REFINE_STOP_CORRECTION = 1,
+  REFINE_STOP_RESIDUAL = 2
+} refine_stop;
+
+typedef struct {
+  refine_kind kind;
+  int64_t n;
+  const double* a;         /* dense: device pointer, row-major, lda >= n */
+  int64_t lda;
+  const int32_t* row_ptr;  /* CSR: device pointers */
+  const int32_t* col_idx;
+  const double* val;
+  int64_t nnz;
+} refine_matrix;
+
+typedef struct {
+  refine_precision precision;
+  refine_target target;
+  double shift;            /* mu for REFINE_TARGET_SHIFT */
+  double delta_c;          /* delta = delta_c * ||A|| * 2^-53; the paper uses 10 (Sec. 3.3) */
+  double norm_a;           /* ||A|| for delta and the residual statistic; <= 0: ||A||_inf */
+  refine_beta beta;
+  int32_t normalize;       /* 1: normalise columns after each update (Sec. 3.3) */
+  int32_t slices;          /* split mode: INT8 slices per operand, 0 = 8 */
+} refine_options;
+
+typedef struct {
+  double corr_fro;         /* ||E_L||_F of the last step */
+  double resid_rel;        /* ||A X - X D||_F / ||A|| of the last step's input */
+  int32_t iters;           /* steps applied */
+  int32_t status;          /* status code of the last step */
+} refine_stats;
+
+/* Fills *opt with the defaults: FP64, LARGEST_ABS, delta_c = 10, norm_a = 0
+ * (use ||A||_inf), beta = -x_i^T x_j / 2, normalize = 1, slices = 0. */
+void refine_options_default(refine_options* opt);
+
+/* Creates a context for one problem with k target vectors, 1 <= k <= 128,
+ * k < n, n < 2^31 (CSR nnz < 2^31; split mode n <= 65536).  Computes ||A||_inf
+ * and the Gershgorin bounds on the device, slices A in split mode, allocates
+ * the workspace and records the step as a HIP graph.  hip_stream is a
+ * hipStream_t (NULL for the null stream).  Synchronises the stream. */
+int refine_init(refine_ctx** ctx, const refine_matrix* A, int32_t k,
+                const refine_options* opt, void* hip_stream);
+
+/* One refinement step on X (device, n x k row-major, leading dimension ldx),
+ * in place.  stats == NULL: the step is only enqueued (no host
+ * synchronisation) and errors surface at the next call that reports them;
+ * otherwise the stream is synchronised and *stats filled. */
+int refine_step(refine_ctx* ctx, double* X, int64_t ldx, refine_stats* stats);
+
+/* Up to max_iters steps, stopping early when the rule `stop` meets tol or on
+ * an error status.  The stopping test runs on the device; the host checks it
+ * once per chunk of steps.  Returns REFINE_OK when the rule was met,
+ * REFINE_NOT_CONVERGED when max_iters steps ran without meeting it (always
+ * for REFINE_STOP_ITERS, which then returns REFINE_OK), or an error code. */
+int refine_run(refine_ctx* ctx, double* X, int64_t ldx, int32_t max_iters,
+               refine_stop stop, double tol, refine_stats* stats);
+
+/* Scalars computed at init: mu (the shift in use), ||A||_inf, the norm used
+ * for delta and the residual, and delta itself. */
+int refine_get_info(const refine_ctx* ctx, double* mu, double* norm_inf,
+                    double* norm_used, double* delta);
+
+int refine_destroy(refine_ctx* ctx);
+
+/* Measurement hook for the roofline figures: enqueues `reps` launches of the
+ * product W = A X alone (line 1 of Algorithm 4; its cost is the O(nnz(A) k)
+ * row of Table 1), in the context's precision and launch configuration, on
+ * the context's stream between two HIP events, waits for them and stores the
+ * mean time of one launch in *ms.  X is only read; the context's workspace
+ * copy of W is overwritten, so call it between steps, not inside one. */
+int refine_time_product(refine_ctx* ctx, double* X, int64_t ldx, int32_t reps, float* ms);
+
+/* Batched problems (independent dense A_p, n_p x n_p, with k_p targets):
+ * every step of every problem runs in one grouped launch per kernel, over
+ * (problem, tile) work items, and the whole step is one HIP graph.  Options
+ * apply to all problems; As[p], ks[p] as in refine_init.  X pointers are
+ * given per call.  REFINE_SPLIT_INT8 is not available for batches. */
+int refine_batch_init(refine_batch** b, int32_t count, const refine_matrix* As,
+                      const int32_t* ks, const refine_options* opt,
+                      void* hip_stream);
+
+/* iters steps on all problems (Xs[p]: device n_p x k_p row-major, ld ldxs[p]).
+ * per_problem (count entries) may be NULL: no host synchronisation. */
+int refine_batch_run(refine_batch* b, double* const* Xs, const int64_t* ldxs,
+                     int32_t iters, refine_stats* per_problem);
+
+int refine_batch_destroy(refine_batch* b);
+
+/* Static string for a status code. */
+const char* refine_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* REFINE_H */

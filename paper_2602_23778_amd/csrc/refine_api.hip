@@ -1,0 +1,723 @@
+// Host runtime and C ABI of the refinement library (declared in refine.h).
+//
+// A context holds a "plan": the device table of problem descriptors, the
+// work-item tables of every pass, and one contiguous workspace.  The step is
+// enqueued as a fixed sequence of launches (product, Rayleigh quotients, Gram,
+// Gram reduction, k-by-k solve, update, normalisation) and recorded once as a
+// HIP graph; refine_step replays the graph, refine_run replays it in chunks
+// and polls the device-side control word between chunks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "common.h"
+#include "refine.h"
+#include "split.h"
+
+namespace rfk {
+hipError_t launch_gemm_f64(const Prob*, const GemmItem*, int, int, int, bool, hipStream_t);
+int gemm_rows_per_block();
+hipError_t launch_wreduce(const Prob*, const RowItem*, int, hipStream_t);
+hipError_t launch_gram(const Prob*, const RowItem*, int, int, hipStream_t);
+struct GramRedItem {
+  int32_t prob, s0;
+};
+hipError_t launch_gram_reduce(const Prob*, const GramRedItem*, int, hipStream_t);
+int kxk_lds_doubles(int);
+hipError_t launch_kxk(const Prob*, int, int, hipStream_t);
+hipError_t launch_update(const Prob*, const RowItem*, int, int, hipStream_t);
+hipError_t launch_normalize(const Prob*, const RowItem*, int, hipStream_t);
+hipError_t launch_ctrl_reset(const Prob*, int, int, double, hipStream_t);
+hipError_t launch_set_x(Prob*, int, double*, int64_t, hipStream_t);
+hipError_t launch_spmm(const Prob*, const RowItem*, int, hipStream_t);
+hipError_t launch_rowstats(int, int, const double*, int64_t, const int32_t*, const int32_t*,
+                           const double*, double*, int, hipStream_t);
+hipError_t kxk_set_attributes();
+}  // namespace rfk
+
+using namespace rfk;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+int iceil(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// One set of problems sharing launches.
+struct Plan {
+  std::vector<Prob> hprob;
+  Prob* dprob = nullptr;
+  GemmItem* gemm_items = nullptr;
+  int n_gemm = 0;
+  RowItem* row_items = nullptr;
+  int n_row = 0;
+  RowItem* gram_items = nullptr;
+  int n_gram = 0;
+  GramRedItem* gred_items = nullptr;
+  int n_gred = 0;
+  int kmax = 0;
+  bool vec2 = true;
+  bool csr = false;
+  bool split = false;
+  SplitPlan sp;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  Ctrl* ctrl = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap_stream = nullptr;
+};
+
+struct Options {
+  refine_options o;
+};
+
+// Per-problem sizes chosen by the planner.
+struct Shape {
+  int ksplit, kchunk, nrb, rbrows, ngb, gbrows;
+};
+
+Shape choose_shape(int64_t n, int k, bool single, bool csr) {
+  Shape s{};
+  const int bm = gemm_rows_per_block();
+  const int nrbg = iceil(n, bm);
+  s.ksplit = 1;
+  if (single && !csr) {
+    int ks = std::max(1, iceil(512, nrbg));
+    ks = std::min(ks, 16);
+    ks = std::min<int64_t>(ks, std::max<int64_t>(1, n / 256));
+    s.ksplit = ks;
+  }
+  s.kchunk = (int)((iceil(n, s.ksplit) + 31) / 32 * 32);
+  s.ksplit = iceil(n, s.kchunk);
+  if (single) {
+    const int target = 512;
+    s.rbrows = std::max<int64_t>(128, ((n + target - 1) / target + 127) / 128 * 128);
+    s.gbrows = std::max<int64_t>(128, ((n + 255) / 256 + 3) / 4 * 4);
+  } else {
+    s.rbrows = 128;
+    s.gbrows = 128;
+  }
+  s.nrb = iceil(n, s.rbrows);
+  s.ngb = iceil(n, s.gbrows);
+  return s;
+}
+
+template <class T>
+hipError_t upload(T** dst, const std::vector<T>& v) {
+  if (v.empty()) {
+    *dst = nullptr;
+    return hipSuccess;
+  }
+  hipError_t e = hipMalloc((void**)dst, sizeof(T) * v.size());
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice);
+}
+
+void free_plan(Plan& p) {
+  if (p.exec) (void)hipGraphExecDestroy(p.exec);
+  if (p.graph) (void)hipGraphDestroy(p.graph);
+  if (p.cap_stream) (void)hipStreamDestroy(p.cap_stream);
+  (void)hipFree(p.dprob);
+  (void)hipFree(p.gemm_items);
+  (void)hipFree(p.row_items);
+  (void)hipFree(p.gram_items);
+  (void)hipFree(p.gred_items);
+  (void)hipFree(p.ws);
+  split_free(p.sp);
+  p = Plan();
+}
+
+#define RF_CHECK(expr)                         \
+  do {                                         \
+    hipError_t e_ = (expr);                    \
+    if (e_ != hipSuccess) return REFINE_EHIP;  \
+  } while (0)
+
+// Builds descriptors, work items and the workspace for a set of problems.
+// mus/deltas/norms are per problem.
+int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector<int>& ks,
+               const refine_options& opt, const std::vector<double>& mus,
+               const std::vector<double>& deltas, const std::vector<double>& norms) {
+  const int np = (int)As.size();
+  const bool single = np == 1;
+  pl.csr = As[0].kind == REFINE_CSR;
+  pl.split = opt.precision == REFINE_SPLIT_INT8;
+  pl.hprob.resize(np);
+  std::vector<Shape> shapes(np);
+  size_t bytes = 0;
+  std::vector<size_t> off(np);
+  pl.kmax = 0;
+  pl.vec2 = true;
+  for (int p = 0; p < np; ++p) {
+    const int64_t n = As[p].n;
+    const int k = ks[p];
+    pl.kmax = std::max(pl.kmax, k);
+    Shape s = choose_shape(n, k, single, pl.csr);
+    if (pl.split) s.ksplit = 1;
+    shapes[p] = s;
+    off[p] = bytes;
+    const size_t nk = (size_t)n * k * sizeof(double);
+    size_t b = 0;
+    if (s.ksplit > 1) b += align_up(nk * s.ksplit);
+    b += align_up(nk);                                   // w
+    if (pl.split) b += align_up(nk);                     // wlo
+    b += align_up(nk);                                   // xn
+    b += align_up((size_t)s.nrb * 5 * k * sizeof(double));
+    b += align_up((size_t)s.ngb * (2 * k * k + k) * sizeof(double));
+    b += align_up((size_t)KK_COUNT * k * k * sizeof(double));
+    b += align_up((size_t)VEC_COUNT * k * sizeof(double));
+    bytes += b;
+    if (As[p].kind == REFINE_DENSE) {
+      if ((As[p].lda & 1) || ((uintptr_t)As[p].a & 15)) pl.vec2 = false;
+    }
+  }
+  const size_t ctrl_off = bytes;
+  bytes += align_up(sizeof(Ctrl) * np);
+  if (hipMalloc((void**)&pl.ws, bytes) != hipSuccess) return REFINE_ENOMEM;
+  pl.ws_bytes = bytes;
+  RF_CHECK(hipMemset(pl.ws, 0, bytes));
+  pl.ctrl = (Ctrl*)(pl.ws + ctrl_off);
+
+  std::vector<GemmItem> gi;
+  std::vector<RowItem> ri, gri;
+  std::vector<GramRedItem> rr;
+  for (int p = 0; p < np; ++p) {
+    const refine_matrix& A = As[p];
+    const Shape& s = shapes[p];
+    const int64_t n = A.n;
+    const int k = ks[p];
+    const size_t nk = (size_t)n * k * sizeof(double);
+    Prob& P = pl.hprob[p];
+    memset(&P, 0, sizeof(P));
+    P.a = A.a;
+    P.lda = A.lda;
+    P.rp = A.row_ptr;
+    P.ci = A.col_idx;
+    P.av = A.val;
+    P.x = nullptr;
+    P.ldx = k;
+    P.n = (int32_t)n;
+    P.k = k;
+    P.kind = A.kind;
+    P.ksplit = s.ksplit;
+    P.nrb = s.nrb;
+    P.rbrows = s.rbrows;
+    P.ngb = s.ngb;
+    P.gbrows = s.gbrows;
+    char* base = pl.ws + off[p];
+    if (s.ksplit > 1) {
+      P.wp = (double*)base;
+      base += align_up(nk * s.ksplit);
+    }
+    P.w = (double*)base;
+    base += align_up(nk);
+    if (pl.split) {
+      P.wlo = (double*)base;
+      base += align_up(nk);
+    }
+    P.xn = (double*)base;
+    base += align_up(nk);
+    P.part = (double*)base;
+    base += align_up((size_t)s.nrb * 5 * k * sizeof(double));
+    P.gpart = (double*)base;
+    base += align_up((size_t)s.ngb * (2 * k * k + k) * sizeof(double));
+    P.kk = (double*)base;
+    base += align_up((size_t)KK_COUNT * k * k * sizeof(double));
+    P.vec = (double*)base;
+    P.ctrl = pl.ctrl + p;
+    P.mu = mus[p];
+    P.delta = deltas[p];
+    P.norm_a = norms[p];
+    P.beta_zero = opt.beta == REFINE_BETA_ZERO;
+    P.normalize = opt.normalize != 0;
+
+    if (!pl.csr && !pl.split) {
+      const int bm = gemm_rows_per_block();
+      const int nrbg = iceil(n, bm);
+      for (int rb = 0; rb < nrbg; ++rb)
+        for (int sp = 0; sp < s.ksplit; ++sp) {
+          GemmItem g{};
+          g.prob = p;
+          g.row0 = rb * bm;
+          g.k0 = sp * s.kchunk;
+          g.k1 = (int)std::min<int64_t>(n, (int64_t)(sp + 1) * s.kchunk);
+          g.split = sp;
+          gi.push_back(g);
+        }
+    }
+    for (int b = 0; b < s.nrb; ++b) ri.push_back(RowItem{p, b});
+    for (int b = 0; b < s.ngb; ++b) gri.push_back(RowItem{p, b});
+    const int S = 2 * k * k + k;
+    for (int s0 = 0; s0 < S; s0 += 256) rr.push_back(GramRedItem{p, s0});
+  }
+  if (!single) {
+    // larger problems first: a rough longest-processing-time order
+    auto bigger = [&](int a, int b) { return As[a].n > As[b].n; };
+    auto sort_items = [&](auto& v) {
+      std::stable_sort(v.begin(), v.end(), [&](const auto& x, const auto& y) { return bigger(x.prob, y.prob); });
+    };
+    sort_items(gi);
+    sort_items(ri);
+    sort_items(gri);
+  }
+  RF_CHECK(upload(&pl.dprob, pl.hprob));
+  RF_CHECK(upload(&pl.gemm_items, gi));
+  RF_CHECK(upload(&pl.row_items, ri));
+  RF_CHECK(upload(&pl.gram_items, gri));
+  RF_CHECK(upload(&pl.gred_items, rr));
+  pl.n_gemm = (int)gi.size();
+  pl.n_row = (int)ri.size();
+  pl.n_gram = (int)gri.size();
+  pl.n_gred = (int)rr.size();
+  return REFINE_OK;
+}
+
+hipError_t enqueue_step(Plan& pl, hipStream_t st) {
+  hipError_t e;
+  const int np = (int)pl.hprob.size();
+  if (pl.csr) {
+    if ((e = launch_spmm(pl.dprob, pl.row_items, pl.n_row, st)) != hipSuccess) return e;
+  } else {
+    if (pl.split) {
+      if ((e = split_product(pl.sp, pl.dprob, st)) != hipSuccess) return e;
+    } else {
+      if ((e = launch_gemm_f64(pl.dprob, pl.gemm_items, pl.n_gemm, pl.n_gemm, pl.kmax, pl.vec2, st)) !=
+          hipSuccess)
+        return e;
+    }
+    if ((e = launch_wreduce(pl.dprob, pl.row_items, pl.n_row, st)) != hipSuccess) return e;
+  }
+  if ((e = launch_gram(pl.dprob, pl.gram_items, pl.n_gram, pl.kmax, st)) != hipSuccess) return e;
+  if ((e = launch_gram_reduce(pl.dprob, pl.gred_items, pl.n_gred, st)) != hipSuccess) return e;
+  if ((e = launch_kxk(pl.dprob, np, pl.kmax, st)) != hipSuccess) return e;
+  if ((e = launch_update(pl.dprob, pl.row_items, pl.n_row, pl.kmax, st)) != hipSuccess) return e;
+  if ((e = launch_normalize(pl.dprob, pl.row_items, pl.n_row, st)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+int capture_graph(Plan& pl) {
+  RF_CHECK(hipStreamCreateWithFlags(&pl.cap_stream, hipStreamNonBlocking));
+  RF_CHECK(hipStreamBeginCapture(pl.cap_stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = enqueue_step(pl, pl.cap_stream);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(pl.cap_stream, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return REFINE_EHIP;
+  }
+  pl.graph = g;
+  RF_CHECK(hipGraphInstantiate(&pl.exec, g, nullptr, nullptr, 0));
+  return REFINE_OK;
+}
+
+int status_from_ctrl(const Ctrl& c) { return c.status; }
+
+}  // namespace
+
+struct refine_ctx {
+  hipStream_t stream = nullptr;
+  refine_matrix A{};
+  refine_options opt{};
+  int k = 0;
+  double mu = 0, norm_inf = 0, norm_used = 0, delta = 0, g_lo = 0, g_hi = 0;
+  Plan plan;
+  double* cur_x = nullptr;
+  int64_t cur_ldx = -1;
+  int stop_mode = 0;
+};
+
+struct refine_batch {
+  hipStream_t stream = nullptr;
+  std::vector<refine_matrix> As;
+  std::vector<int> ks;
+  refine_options opt{};
+  Plan plan;
+  std::vector<double*> cur_x;
+  std::vector<int64_t> cur_ldx;
+  double* d_xs = nullptr;   // staging: (x, ldx) pairs
+};
+
+namespace {
+
+int validate_matrix(const refine_matrix* A, int32_t k, const refine_options& opt) {
+  if (!A || A->n <= 0 || A->n >= (int64_t)1 << 31) return REFINE_EINVAL;
+  if (k < 1 || k > KMAX || (int64_t)k >= A->n) return REFINE_EINVAL;
+  if (A->kind == REFINE_DENSE) {
+    if (!A->a || A->lda < A->n) return REFINE_EINVAL;
+  } else if (A->kind == REFINE_CSR) {
+    if (!A->row_ptr || !A->col_idx || !A->val || A->nnz < 0 || A->nnz >= (int64_t)1 << 31)
+      return REFINE_EINVAL;
+    if (opt.precision != REFINE_FP64) return REFINE_EINVAL;
+  } else {
+    return REFINE_EINVAL;
+  }
+  if (opt.precision != REFINE_FP64 && opt.precision != REFINE_SPLIT_INT8) return REFINE_EINVAL;
+  if (opt.precision == REFINE_SPLIT_INT8 && A->n > SPLIT_NMAX) return REFINE_EINVAL;
+  if (!(opt.delta_c >= 0.0)) return REFINE_EINVAL;
+  return REFINE_OK;
+}
+
+// ||A||_inf and Gershgorin bounds, synchronously on `st`.
+int matrix_stats(const refine_matrix& A, hipStream_t st, double* ninf, double* lo, double* hi) {
+  const int grid = std::min<int64_t>(1024, (A.n + 3) / 4);
+  double* d = nullptr;
+  RF_CHECK(hipMalloc((void**)&d, sizeof(double) * 3 * grid));
+  hipError_t e = launch_rowstats(A.kind == REFINE_CSR ? 1 : 0, (int)A.n, A.a, A.lda, A.row_ptr,
+                                 A.col_idx, A.val, d, grid, st);
+  std::vector<double> h(3 * grid);
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d, sizeof(double) * 3 * grid, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(d);
+  if (e != hipSuccess) return REFINE_EHIP;
+  double m = 0.0, gh = -INFINITY, gl = INFINITY;
+  for (int b = 0; b < grid; ++b) {
+    m = std::max(m, h[3 * b]);
+    gh = std::max(gh, h[3 * b + 1]);
+    gl = std::min(gl, h[3 * b + 2]);
+  }
+  *ninf = m;
+  *lo = gl;
+  *hi = gh;
+  if (!std::isfinite(m) || !std::isfinite(gl) || !std::isfinite(gh)) return REFINE_ENONFINITE;
+  return REFINE_OK;
+}
+
+double shift_for(const refine_options& opt, double lo, double hi) {
+  switch (opt.target) {
+    case REFINE_TARGET_SMALLEST:
+      return hi;
+    case REFINE_TARGET_LARGEST:
+      return lo;
+    case REFINE_TARGET_SHIFT:
+      return opt.shift;
+    default:
+      return 0.0;
+  }
+}
+
+int read_ctrl(Plan& pl, hipStream_t st, std::vector<Ctrl>& out) {
+  out.resize(pl.hprob.size());
+  RF_CHECK(hipMemcpyAsync(out.data(), pl.ctrl, sizeof(Ctrl) * out.size(), hipMemcpyDeviceToHost, st));
+  RF_CHECK(hipStreamSynchronize(st));
+  return REFINE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void refine_options_default(refine_options* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->precision = REFINE_FP64;
+  o->target = REFINE_TARGET_LARGEST_ABS;
+  o->shift = 0.0;
+  o->delta_c = 10.0;
+  o->norm_a = 0.0;
+  o->beta = REFINE_BETA_HALF_GRAM;
+  o->normalize = 1;
+  o->slices = 0;
+}
+
+const char* refine_status_string(int s) {
+  switch (s) {
+    case REFINE_OK:
+      return "ok";
+    case REFINE_NOT_CONVERGED:
+      return "not converged within max_iters";
+    case REFINE_EINVAL:
+      return "invalid argument";
+    case REFINE_ENOMEM:
+      return "out of memory";
+    case REFINE_EHIP:
+      return "HIP runtime error";
+    case REFINE_EWY_SINGULAR:
+      return "Y1 = X(1:k,:) - I singular or ill-conditioned (compact WY needs it nonsingular)";
+    case REFINE_EDIVERGED:
+      return "refinement diverged (||E_L||_F >= 1 or growing)";
+    case REFINE_ENONFINITE:
+      return "non-finite values";
+    default:
+      return "unknown status";
+  }
+}
+
+int refine_init(refine_ctx** out, const refine_matrix* A, int32_t k, const refine_options* optp,
+                void* hip_stream) {
+  if (!out) return REFINE_EINVAL;
+  *out = nullptr;
+  refine_options opt;
+  if (optp)
+    opt = *optp;
+  else
+    refine_options_default(&opt);
+  if (opt.delta_c == 0.0 && !optp) opt.delta_c = 10.0;
+  int rc = validate_matrix(A, k, opt);
+  if (rc != REFINE_OK) return rc;
+  if (kxk_set_attributes() != hipSuccess) return REFINE_EHIP;
+  refine_ctx* c = new (std::nothrow) refine_ctx();
+  if (!c) return REFINE_ENOMEM;
+  c->stream = (hipStream_t)hip_stream;
+  c->A = *A;
+  c->opt = opt;
+  c->k = k;
+  rc = matrix_stats(*A, c->stream, &c->norm_inf, &c->g_lo, &c->g_hi);
+  if (rc != REFINE_OK) {
+    delete c;
+    return rc;
+  }
+  c->mu = shift_for(opt, c->g_lo, c->g_hi);
+  c->norm_used = opt.norm_a > 0.0 ? opt.norm_a : c->norm_inf;
+  c->delta = opt.delta_c * c->norm_used * UNIT_ROUNDOFF;
+  std::vector<refine_matrix> As{*A};
+  std::vector<int> ks{k};
+  rc = build_plan(c->plan, As, ks, opt, {c->mu}, {c->delta}, {c->norm_used});
+  if (rc == REFINE_OK && c->plan.split) {
+    rc = split_init(c->plan.sp, *A, k, opt.slices > 0 ? opt.slices : 8, c->plan.hprob[0], c->plan.dprob,
+                    c->stream);
+  }
+  if (rc == REFINE_OK) rc = capture_graph(c->plan);
+  if (rc == REFINE_OK && launch_ctrl_reset(c->plan.dprob, 1, 0, 0.0, c->stream) != hipSuccess)
+    rc = REFINE_EHIP;
+  if (rc == REFINE_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = REFINE_EHIP;
+  if (rc != REFINE_OK) {
+    free_plan(c->plan);
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return REFINE_OK;
+}
+
+static int set_x(refine_ctx* c, double* X, int64_t ldx) {
+  if (!X || ldx < c->k) return REFINE_EINVAL;
+  if (X != c->cur_x || ldx != c->cur_ldx) {
+    if (launch_set_x(c->plan.dprob, 0, X, ldx, c->stream) != hipSuccess) return REFINE_EHIP;
+    c->cur_x = X;
+    c->cur_ldx = ldx;
+  }
+  return REFINE_OK;
+}
+
+int refine_step(refine_ctx* c, double* X, int64_t ldx, refine_stats* stats) {
+  if (!c) return REFINE_EINVAL;
+  int rc = set_x(c, X, ldx);
+  if (rc != REFINE_OK) return rc;
+  if (hipGraphLaunch(c->plan.exec, c->stream) != hipSuccess) return REFINE_EHIP;
+  if (!stats) return REFINE_OK;
+  std::vector<Ctrl> cs;
+  rc = read_ctrl(c->plan, c->stream, cs);
+  if (rc != REFINE_OK) return rc;
+  stats->corr_fro = cs[0].corr_fro;
+  stats->resid_rel = cs[0].resid_rel;
+  stats->iters = cs[0].iters;
+  stats->status = cs[0].status;
+  const int st = cs[0].status;
+  if (st != 0) {
+    // report once, then let the next step start afresh
+    if (launch_ctrl_reset(c->plan.dprob, 1, 0, 0.0, c->stream) != hipSuccess) return REFINE_EHIP;
+  }
+  return st;
+}
+
+int refine_run(refine_ctx* c, double* X, int64_t ldx, int32_t max_iters, refine_stop stop,
+               double tol, refine_stats* stats) {
+  if (!c || max_iters < 0) return REFINE_EINVAL;
+  if (stop != REFINE_STOP_ITERS && stop != REFINE_STOP_CORRECTION && stop != REFINE_STOP_RESIDUAL)
+    return REFINE_EINVAL;
+  int rc = set_x(c, X, ldx);
+  if (rc != REFINE_OK) return rc;
+  if (launch_ctrl_reset(c->plan.dprob, 1, (int)stop, tol, c->stream) != hipSuccess) return REFINE_EHIP;
+  std::vector<Ctrl> cs(1);
+  int done = 0;
+  const int chunk = 8;
+  while (done < max_iters) {
+    const int m = std::min(chunk, max_iters - done);
+    for (int i = 0; i < m; ++i)
+      if (hipGraphLaunch(c->plan.exec, c->stream) != hipSuccess) return REFINE_EHIP;
+    done += m;
+    rc = read_ctrl(c->plan, c->stream, cs);
+    if (rc != REFINE_OK) return rc;
+    if (cs[0].stopped) break;
+  }
+  if (stats) {
+    stats->corr_fro = cs[0].corr_fro;
+    stats->resid_rel = cs[0].resid_rel;
+    stats->iters = cs[0].iters;
+    stats->status = cs[0].status;
+  }
+  int result;
+  if (cs[0].status != 0)
+    result = cs[0].status;
+  else if (stop == REFINE_STOP_ITERS || cs[0].converged)
+    result = REFINE_OK;
+  else
+    result = REFINE_NOT_CONVERGED;
+  if (launch_ctrl_reset(c->plan.dprob, 1, 0, 0.0, c->stream) != hipSuccess) return REFINE_EHIP;
+  return result;
+}
+
+int refine_time_product(refine_ctx* c, double* X, int64_t ldx, int32_t reps, float* ms) {
+  if (!c || reps <= 0 || !ms) return REFINE_EINVAL;
+  int rc = set_x(c, X, ldx);
+  if (rc != REFINE_OK) return rc;
+  if (launch_ctrl_reset(c->plan.dprob, 1, 0, 0.0, c->stream) != hipSuccess) return REFINE_EHIP;
+  hipEvent_t e0, e1;
+  RF_CHECK(hipEventCreate(&e0));
+  RF_CHECK(hipEventCreate(&e1));
+  Plan& pl = c->plan;
+  hipError_t e = hipEventRecord(e0, c->stream);
+  for (int i = 0; i < reps && e == hipSuccess; ++i) {
+    if (pl.csr)
+      e = launch_spmm(pl.dprob, pl.row_items, pl.n_row, c->stream);
+    else if (pl.split)
+      e = split_product(pl.sp, pl.dprob, c->stream);
+    else
+      e = launch_gemm_f64(pl.dprob, pl.gemm_items, pl.n_gemm, pl.n_gemm, pl.kmax, pl.vec2, c->stream);
+  }
+  if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return REFINE_EHIP;
+  *ms = t / (float)reps;
+  if (launch_ctrl_reset(c->plan.dprob, 1, 0, 0.0, c->stream) != hipSuccess) return REFINE_EHIP;
+  return REFINE_OK;
+}
+
+int refine_get_info(const refine_ctx* c, double* mu, double* norm_inf, double* norm_used,
+                    double* delta) {
+  if (!c) return REFINE_EINVAL;
+  if (mu) *mu = c->mu;
+  if (norm_inf) *norm_inf = c->norm_inf;
+  if (norm_used) *norm_used = c->norm_used;
+  if (delta) *delta = c->delta;
+  return REFINE_OK;
+}
+
+int refine_destroy(refine_ctx* c) {
+  if (!c) return REFINE_EINVAL;
+  (void)hipStreamSynchronize(c->stream);
+  free_plan(c->plan);
+  delete c;
+  return REFINE_OK;
+}
+
+int refine_batch_init(refine_batch** out, int32_t count, const refine_matrix* As,
+                      const int32_t* ks, const refine_options* optp, void* hip_stream) {
+  if (!out || count <= 0 || !As || !ks) return REFINE_EINVAL;
+  *out = nullptr;
+  refine_options opt;
+  if (optp)
+    opt = *optp;
+  else
+    refine_options_default(&opt);
+  if (opt.precision != REFINE_FP64) return REFINE_EINVAL;
+  for (int p = 0; p < count; ++p) {
+    if (As[p].kind != REFINE_DENSE) return REFINE_EINVAL;
+    int rc = validate_matrix(&As[p], ks[p], opt);
+    if (rc != REFINE_OK) return rc;
+  }
+  if (kxk_set_attributes() != hipSuccess) return REFINE_EHIP;
+  refine_batch* b = new (std::nothrow) refine_batch();
+  if (!b) return REFINE_ENOMEM;
+  b->stream = (hipStream_t)hip_stream;
+  b->opt = opt;
+  b->As.assign(As, As + count);
+  b->ks.assign(ks, ks + count);
+  std::vector<double> mus(count), deltas(count), norms(count);
+  for (int p = 0; p < count; ++p) {
+    double ninf, lo, hi;
+    int rc = matrix_stats(As[p], b->stream, &ninf, &lo, &hi);
+    if (rc != REFINE_OK) {
+      delete b;
+      return rc;
+    }
+    mus[p] = shift_for(opt, lo, hi);
+    norms[p] = opt.norm_a > 0.0 ? opt.norm_a : ninf;
+    deltas[p] = opt.delta_c * norms[p] * UNIT_ROUNDOFF;
+  }
+  int rc = build_plan(b->plan, b->As, b->ks, opt, mus, deltas, norms);
+  if (rc == REFINE_OK) rc = capture_graph(b->plan);
+  if (rc == REFINE_OK && hipMalloc((void**)&b->d_xs, sizeof(double*) * 2 * count) != hipSuccess)
+    rc = REFINE_ENOMEM;
+  if (rc == REFINE_OK && launch_ctrl_reset(b->plan.dprob, count, 0, 0.0, b->stream) != hipSuccess)
+    rc = REFINE_EHIP;
+  if (rc == REFINE_OK && hipStreamSynchronize(b->stream) != hipSuccess) rc = REFINE_EHIP;
+  if (rc != REFINE_OK) {
+    free_plan(b->plan);
+    (void)hipFree(b->d_xs);
+    delete b;
+    return rc;
+  }
+  b->cur_x.assign(count, nullptr);
+  b->cur_ldx.assign(count, -1);
+  *out = b;
+  return REFINE_OK;
+}
+
+int refine_batch_run(refine_batch* b, double* const* Xs, const int64_t* ldxs, int32_t iters,
+                     refine_stats* per) {
+  if (!b || !Xs || iters < 0) return REFINE_EINVAL;
+  const int np = (int)b->As.size();
+  bool changed = false;
+  for (int p = 0; p < np; ++p) {
+    const int64_t ld = ldxs ? ldxs[p] : b->ks[p];
+    if (!Xs[p] || ld < b->ks[p]) return REFINE_EINVAL;
+    if (Xs[p] != b->cur_x[p] || ld != b->cur_ldx[p]) changed = true;
+  }
+  if (changed) {
+    // descriptors are rewritten in place; wait for queued work first
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return REFINE_EHIP;
+    for (int p = 0; p < np; ++p) {
+      b->plan.hprob[p].x = Xs[p];
+      b->plan.hprob[p].ldx = ldxs ? ldxs[p] : b->ks[p];
+      b->cur_x[p] = Xs[p];
+      b->cur_ldx[p] = b->plan.hprob[p].ldx;
+    }
+    if (hipMemcpy(b->plan.dprob, b->plan.hprob.data(), sizeof(Prob) * np, hipMemcpyHostToDevice) !=
+        hipSuccess)
+      return REFINE_EHIP;
+  }
+  for (int i = 0; i < iters; ++i)
+    if (hipGraphLaunch(b->plan.exec, b->stream) != hipSuccess) return REFINE_EHIP;
+  if (!per) return REFINE_OK;
+  std::vector<Ctrl> cs;
+  int rc = read_ctrl(b->plan, b->stream, cs);
+  if (rc != REFINE_OK) return rc;
+  int worst = REFINE_OK;
+  bool any_bad = false;
+  for (int p = 0; p < np; ++p) {
+    per[p].corr_fro = cs[p].corr_fro;
+    per[p].resid_rel = cs[p].resid_rel;
+    per[p].iters = cs[p].iters;
+    per[p].status = cs[p].status;
+    if (cs[p].status != 0) {
+      any_bad = true;
+      if (worst == REFINE_OK) worst = cs[p].status;
+    }
+  }
+  if (any_bad && launch_ctrl_reset(b->plan.dprob, np, 0, 0.0, b->stream) != hipSuccess)
+    return REFINE_EHIP;
+  return worst;
+}
+
+int refine_batch_destroy(refine_batch* b) {
+  if (!b) return REFINE_EINVAL;
+  (void)hipStreamSynchronize(b->stream);
+  free_plan(b->plan);
+  (void)hipFree(b->d_xs);
+  delete b;
+  return REFINE_OK;
+}
+
+}  // extern "C"
