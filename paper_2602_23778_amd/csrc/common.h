@@ -104,9 +104,15 @@ struct RowItem {
 
 constexpr double UNIT_ROUNDOFF = 1.1102230246251565e-16;  // 2^-53
 
+// v_mfma_f64_16x16x4_f64: lane l supplies a[i = l%16][k = l/16] and
+// b[k = l/16][j = l%16]; the 16x16 result sits in four registers per lane,
+// register r of lane l holding d[i = l/16 + 4r][j = l%16] (checked on gfx950
+// with a lane-layout probe).
 __device__ __forceinline__ v4d mfma_f64(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+// Row of the 16x16 result held in register r by a lane of group g = l/16.
+__device__ __forceinline__ int mfma_row(int g, int r) { return g + 4 * r; }
 
 // Exact transformations used by the accurate residual (Dekker / Knuth).
 __device__ __forceinline__ void two_prod(double a, double b, double& p, double& e) {

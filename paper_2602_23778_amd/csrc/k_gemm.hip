@@ -11,7 +11,8 @@
 //     through a double-buffered LDS tile (row stride BN+2 doubles to spread
 //     the four lane groups over different banks);
 //   * v_mfma_f64_16x16x4_f64: each lane holds a[row = l%16][k = l/16] and
-//     b[k = l/16][col = l%16]; the K index inside a 32-wide chunk is permuted
+//     b[k = l/16][col = l%16] (result layout: see mfma_row in common.h); the
+//     K index inside a 32-wide chunk is permuted
 //     identically for A and B (lane group g uses k = 8g + m for step m), which
 //     leaves the sum unchanged and lets a lane read 8 contiguous doubles;
 //   * split-K over the work-item table gives enough workgroups to fill 256
@@ -128,16 +129,19 @@ __global__ __launch_bounds__(WAVES * 64) void gemm_f64_kernel(const Prob* __rest
       for (int m = 0; m < 8; ++m) a_cur[m] = a_nxt[m];
     }
 
-    // Epilogue: lane holds D[4g + r][r16] of each 16x16 tile.
+    // Epilogue: register r of the lane holds row mfma_row(g, r), column r16
+    // of each 16x16 tile.
     double* __restrict__ out = (P.ksplit > 1) ? P.wp + (int64_t)item.split * n * k : P.w;
-    const int orow = item.row0 + wave * 16 + 4 * g;
+    const int orow = item.row0 + wave * 16;
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
       const int col = ct * 16 + r16;
       if (col < k) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (orow + r < n) out[(int64_t)(orow + r) * k + col] = acc[ct][r];
+        for (int r = 0; r < 4; ++r) {
+          const int orr = orow + mfma_row(g, r);
+          if (orr < n) out[(int64_t)orr * k + col] = acc[ct][r];
+        }
       }
     }
   }

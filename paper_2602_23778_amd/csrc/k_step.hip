@@ -187,7 +187,7 @@ __global__ __launch_bounds__(CT * 64) void gram_kernel(const Prob* __restrict__ 
             }
           }
         }
-        // store the tiles: lane holds entry (ti*16 + 4g + r, t*16 + r16)
+        // store the tiles: register r holds entry (ti*16 + mfma_row(g, r), t*16 + r16)
         double* dstP;
         double* dstG;
         if (phase == 0) {
@@ -203,7 +203,7 @@ __global__ __launch_bounds__(CT * 64) void gram_kernel(const Prob* __restrict__ 
           if (t < ct_used && c < k) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-              const int i = ti * 16 + 4 * g + r;
+              const int i = ti * 16 + mfma_row(g, r);
               if (i < k) {
                 dstP[i * k + c] = accP[t][r];
                 if (t >= ti) dstG[i * k + c] = accG[t][r];
@@ -567,14 +567,14 @@ __global__ __launch_bounds__(512) void update_kernel(const Prob* __restrict__ pr
           }
         }
       }
-      // epilogue: lane holds rows rc + wave*16 + 4g + r, column t*16 + r16
+      // epilogue: register r holds row rc + wave*16 + mfma_row(g, r), column t*16 + r16
 #pragma unroll
       for (int t = 0; t < CT; ++t) {
         const int c = t * 16 + r16;
         if (c < k) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int row = rc + wave * 16 + 4 * g + r;
+            const int row = rc + wave * 16 + mfma_row(g, r);
             if (row < r1) {
               double xt;
               if (row < k) {

@@ -721,3 +721,14 @@ int refine_batch_destroy(refine_batch* b) {
 }
 
 }  // extern "C"
+
+// Diagnostic hook (not part of refine.h): device addresses of the workspace
+// of a single-problem context, in the order w, wlo, xn, kk, vec, ctrl, wp,
+// part, gpart.  Used by the tests to inspect intermediate quantities.
+extern "C" int refine_debug_workspace(const refine_ctx* c, void** out, int32_t count) {
+  if (!c || !out || count < 9) return REFINE_EINVAL;
+  const Prob& P = c->plan.hprob[0];
+  void* v[9] = {P.w, P.wlo, P.xn, P.kk, P.vec, P.ctrl, P.wp, P.part, P.gpart};
+  for (int i = 0; i < 9; ++i) out[i] = v[i];
+  return REFINE_OK;
+}

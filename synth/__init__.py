@@ -152,6 +152,21 @@ def dense_clustered(n, k, seed, device="cpu", torch_out=False, gap=1e-6):
                         {"workload": "dense_clustered", "n": n, "k": k, "seed": seed})
 
 
+def dense_spectrum(n, k, seed, top_lo=0.9, top_hi=1.0, rest_hi=0.8, device="cpu",
+                   torch_out=False):
+    """k targets evenly spaced in [top_lo, top_hi] (descending in X0's column
+    order), the rest iid U[0, rest_hi).  X0 = fl32(Q_top)."""
+    rng = np.random.default_rng(seed)
+    rest = rng.uniform(0.0, rest_hi, n - k)
+    top = np.linspace(top_lo, top_hi, k) if k > 1 else np.array([top_hi])
+    lam = np.concatenate([rest, top])
+    targets = np.arange(n - 1, n - 1 - k, -1)
+    Q = householder_q(n, n, seed + 1, device)
+    A, Xt = _assemble(Q, lam, targets, torch_out)
+    return DenseProblem(A, lam, targets, Xt, fp32_round(Xt), 0.0, float(lam.max()),
+                        {"workload": "dense_spectrum", "n": n, "k": k, "seed": seed})
+
+
 def batch_shapes(count=512, seed=SEED_BASE + 5, n_lo=128, n_hi=2048, k_lo=4, k_hi=32):
     """Sizes of the batched workload: n ~ U_int[n_lo, n_hi], k ~ U_int[k_lo, k_hi]."""
     rng = np.random.default_rng(seed)
