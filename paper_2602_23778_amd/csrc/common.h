@@ -25,8 +25,6 @@ struct Ctrl {
   int32_t iters;      // steps applied since the last reset
   int32_t stop_mode;  // 0 fixed count, 1 ||E_L||_F <= tol, 2 residual <= tol
   int32_t converged;
-  int32_t ticket_a;   // arrival counters of the last-block reductions
-  int32_t ticket_b;
   double tol;
   double corr_fro;    // statistics of the last step
   double resid_rel;
@@ -77,8 +75,9 @@ enum {
   KK_R1 = 4,    // R1, the leading k rows of R
   KK_CM = 5,    // [M | N], k x 2k (occupies 5 and 6)
   KK_X1N = 7,   // updated leading rows
-  KK_S0 = 8,    // scratch for the k-by-k solver when it does not fit in LDS
-  KK_COUNT = 12
+  KK_S0 = 8,    // scratch for the k-by-k solver when it does not fit in LDS (8..11)
+  KK_Z = 12,    // Y1^{-1} of the previous step (warm start)
+  KK_COUNT = 13
 };
 // Offsets (in units of k doubles) inside Prob::vec.
 enum {

@@ -13,43 +13,67 @@ __device__ __forceinline__ int pow2ceil(int v) {
 
 // Block-wide deterministic sum of per-block partials:
 //   out[s] = sum_{b < nb} src[b * stride + s]   for s < S,
-// with a fixed team of threads per slot and a fixed LDS tree.  `scratch`
-// holds blockDim.x doubles; out may alias nothing that src uses.
+// with a fixed team of threads per slot (each summing every ts-th block with
+// eight independent loads in flight) and a fixed LDS tree across the team.
+// `scratch` holds blockDim.x doubles.  All threads of the block must call it.
 __device__ inline void team_reduce(const double* __restrict__ src, int stride, int S, int nb,
-                            double* scratch, double* out) {
+                                   double* scratch, double* out) {
   const int NT = blockDim.x, tid = threadIdx.x;
   int ts = 1;
   while (ts * 2 * S <= NT) ts *= 2;
   for (int s0 = 0; s0 < S; s0 += NT / ts) {
     const int s = s0 + tid / ts, m = tid % ts;
-    double acc = 0.0;
-    if (tid / ts < NT / ts && s < S)
-      for (int b = m; b < nb; b += ts) acc += src[(int64_t)b * stride + s];
-    scratch[tid] = acc;
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (s < S) {
+      int b = m;
+      for (; b + 7 * ts < nb; b += 8 * ts) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = src[(int64_t)(b + u * ts) * stride + s];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] += v[u];
+      }
+      for (; b < nb; b += ts) acc[0] += src[(int64_t)b * stride + s];
+    }
+    scratch[tid] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     __syncthreads();
     for (int h = ts / 2; h >= 1; h /= 2) {
       if (m < h) scratch[tid] += scratch[tid + h];
       __syncthreads();
     }
-    if (m == 0 && s < S && tid / ts < NT / ts) out[s] = scratch[tid];
+    if (m == 0 && s < S) out[s] = scratch[tid];
     __syncthreads();
   }
 }
 
-// Arrival counter of the last-block pattern: returns true in exactly one block
-// (the last to arrive) once all nb blocks of the problem have published their
-// partials; that block resets the counter for the next launch.
-__device__ inline bool last_block_arrival(int32_t* counter, int nb, int* flag) {
-  __threadfence();
+// Per-column block sums for the Rayleigh quotients (eq. Rayleigh).  Threads
+// are laid out as [NT/KP rows][KP columns], KP = pow2ceil(k): thread
+// (trow, col) holds sums of x*w and x*x over its rows of column col.  The
+// block's column sums are written as partial `blk` (slots [0, k) and
+// [k, 2k) of a 5k-wide row of Prob::part); a separate kernel forms d.
+// red holds 2*NT doubles.  Block-uniform call.
+template <int NT>
+__device__ void rayleigh_block_partial(const Prob& P, int blk, double sxw, double sxx,
+                                       double* red) {
+  const int tid = threadIdx.x;
+  const int k = P.k, kp = pow2ceil(k), tr = NT / kp;
+  const int col = tid % kp, trow = tid / kp;
+  red[tid] = sxw;
+  red[NT + tid] = sxx;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const int t = atomicAdd(counter, 1);
-    *flag = (t == nb - 1);
+  for (int h = tr / 2; h >= 1; h /= 2) {
+    if (trow < h) {
+      red[tid] += red[tid + h * kp];
+      red[NT + tid] += red[NT + tid + h * kp];
+    }
+    __syncthreads();
+  }
+  const int stride = 5 * k;
+  if (trow == 0 && col < k) {
+    P.part[(int64_t)blk * stride + col] = red[tid];
+    P.part[(int64_t)blk * stride + k + col] = red[NT + tid];
   }
   __syncthreads();
-  const bool last = *flag;
-  if (last) __threadfence();
-  return last;
 }
 
 }  // namespace rfk

@@ -1,6 +1,6 @@
 // Line 1 of Algorithm 4 for sparse A in CSR form, fused with the first
-// reduction of the step (eq. Rayleigh): W = A X, and per row block
-// x_j^T w_j and x_j^T x_j; the last block forms d_j.
+// reduction of the step (eq. Rayleigh): W = A X, and per row block the
+// column sums of x_j * w_j and x_j * x_j.
 //
 // Layout: a block of NT threads works on [NT/KP rows] x [KP columns] with KP
 // the power of two >= k, so a row's nonzeros (col_idx, val) are broadcast to
@@ -16,9 +16,7 @@ namespace rfk {
 template <int NT>
 __global__ __launch_bounds__(NT) void spmm_kernel(const Prob* __restrict__ probs,
                                                  const RowItem* __restrict__ items, int nitems) {
-  __shared__ double red[2][NT];
-  __shared__ double tot[2 * KMAX];
-  __shared__ int flag;
+  __shared__ double red[2 * NT];
   const int tid = threadIdx.x;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const RowItem item = items[it];
@@ -44,39 +42,7 @@ __global__ __launch_bounds__(NT) void spmm_kernel(const Prob* __restrict__ probs
         sxx = __builtin_fma(x, x, sxx);
       }
     }
-    red[0][tid] = sxw;
-    red[1][tid] = sxx;
-    __syncthreads();
-    for (int h = tr / 2; h >= 1; h /= 2) {
-      if (trow < h) {
-        red[0][tid] += red[0][tid + h * kp];
-        red[1][tid] += red[1][tid + h * kp];
-      }
-      __syncthreads();
-    }
-    const int stride = 5 * k;
-    if (trow == 0 && col < k) {
-      P.part[(int64_t)item.blk * stride + col] = red[0][tid];
-      P.part[(int64_t)item.blk * stride + k + col] = red[1][tid];
-    }
-    if (last_block_arrival(&P.ctrl->ticket_a, P.nrb, &flag)) {
-      team_reduce(P.part, stride, 2 * k, P.nrb, &red[0][0], tot);
-      bool bad = false;
-      for (int j = tid; j < k; j += NT) {
-        const double a = tot[k + j];
-        const double d = tot[j] / a;
-        P.vec[VEC_D * k + j] = d;
-        P.vec[VEC_ALPHA * k + j] = a;
-        P.vec[VEC_DINV * k + j] = 1.0 / (d - P.mu);
-        if (!__builtin_isfinite(d) || !(a > 0.0)) bad = true;
-      }
-      if (bad) {
-        P.ctrl->status = -6;
-        P.ctrl->stopped = 1;
-      }
-      if (tid == 0) P.ctrl->ticket_a = 0;
-    }
-    __syncthreads();
+    rayleigh_block_partial<NT>(P, item.blk, sxw, sxx, red);
   }
 }
 

@@ -144,6 +144,7 @@ __global__ __launch_bounds__(WAVES * 64) void gemm_f64_kernel(const Prob* __rest
         }
       }
     }
+
   }
 }
 

@@ -22,7 +22,6 @@
 namespace rfk {
 hipError_t launch_gemm_f64(const Prob*, const GemmItem*, int, int, int, bool, hipStream_t);
 int gemm_rows_per_block();
-hipError_t launch_wreduce(const Prob*, const RowItem*, int, hipStream_t);
 hipError_t launch_gram(const Prob*, const RowItem*, int, int, hipStream_t);
 struct GramRedItem {
   int32_t prob, s0;
@@ -32,6 +31,9 @@ int kxk_lds_doubles(int);
 hipError_t launch_kxk(const Prob*, int, int, hipStream_t);
 hipError_t launch_update(const Prob*, const RowItem*, int, int, hipStream_t);
 hipError_t launch_normalize(const Prob*, const RowItem*, int, hipStream_t);
+hipError_t launch_wsum(const Prob*, const RowItem*, int, hipStream_t);
+hipError_t launch_fin_d(const Prob*, int, hipStream_t);
+hipError_t launch_fin_stats(const Prob*, int, hipStream_t);
 hipError_t launch_ctrl_reset(const Prob*, int, int, double, hipStream_t);
 hipError_t launch_set_x(Prob*, int, double*, int64_t, hipStream_t);
 hipError_t launch_spmm(const Prob*, const RowItem*, int, hipStream_t);
@@ -96,13 +98,20 @@ Shape choose_shape(int64_t n, int k, bool single, bool csr) {
   }
   s.kchunk = (int)((iceil(n, s.ksplit) + 31) / 32 * 32);
   s.ksplit = iceil(n, s.kchunk);
-  if (single) {
+  // Dense row blocks coincide with the 128-row tiles of the product, whose
+  // epilogue publishes the Rayleigh-quotient partials per row block.
+  if (single && csr) {
     const int target = 512;
     s.rbrows = std::max<int64_t>(128, ((n + target - 1) / target + 127) / 128 * 128);
-    s.gbrows = std::max<int64_t>(128, ((n + 255) / 256 + 3) / 4 * 4);
   } else {
-    s.rbrows = 128;
-    s.gbrows = 128;
+    s.rbrows = bm;
+  }
+  // Gram blocks: at least k rows (the leading k rows must sit in block 0),
+  // about 128 blocks per problem when alone.
+  {
+    const int64_t kr = (k + 3) / 4 * 4;
+    const int64_t per = single ? ((n + 127) / 128 + 3) / 4 * 4 : 128;
+    s.gbrows = (int)std::max<int64_t>(std::max<int64_t>(kr, per), 16);
   }
   s.nrb = iceil(n, s.rbrows);
   s.ngb = iceil(n, s.gbrows);
@@ -255,7 +264,7 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
     for (int b = 0; b < s.nrb; ++b) ri.push_back(RowItem{p, b});
     for (int b = 0; b < s.ngb; ++b) gri.push_back(RowItem{p, b});
     const int S = 2 * k * k + k;
-    for (int s0 = 0; s0 < S; s0 += 256) rr.push_back(GramRedItem{p, s0});
+    for (int s0 = 0; s0 < S; s0 += 64) rr.push_back(GramRedItem{p, s0});
   }
   if (!single) {
     // larger problems first: a rough longest-processing-time order
@@ -292,12 +301,14 @@ hipError_t enqueue_step(Plan& pl, hipStream_t st) {
           hipSuccess)
         return e;
     }
-    if ((e = launch_wreduce(pl.dprob, pl.row_items, pl.n_row, st)) != hipSuccess) return e;
+    if ((e = launch_wsum(pl.dprob, pl.row_items, pl.n_row, st)) != hipSuccess) return e;
   }
+  if ((e = launch_fin_d(pl.dprob, np, st)) != hipSuccess) return e;
   if ((e = launch_gram(pl.dprob, pl.gram_items, pl.n_gram, pl.kmax, st)) != hipSuccess) return e;
   if ((e = launch_gram_reduce(pl.dprob, pl.gred_items, pl.n_gred, st)) != hipSuccess) return e;
   if ((e = launch_kxk(pl.dprob, np, pl.kmax, st)) != hipSuccess) return e;
   if ((e = launch_update(pl.dprob, pl.row_items, pl.n_row, pl.kmax, st)) != hipSuccess) return e;
+  if ((e = launch_fin_stats(pl.dprob, np, st)) != hipSuccess) return e;
   if ((e = launch_normalize(pl.dprob, pl.row_items, pl.n_row, st)) != hipSuccess) return e;
   return hipSuccess;
 }
