@@ -42,6 +42,10 @@ def main() -> int:
     ap.add_argument("--k", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--product-reps", type=int, default=20)
+    ap.add_argument("--product-only", action="store_true",
+                    help="counter runs: one copy of A (a plain copy kernel of known size, "
+                         "for calibrating byte counters) then --product-reps launches of the "
+                         "product alone; prints their mean time")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -67,6 +71,14 @@ def main() -> int:
 
     ctx = rf.RefineContext(A, k, norm_a=P.norm_a)
     X = X0.clone()
+    if args.product_only:
+        Acopy = A.clone()          # reads and writes 8 n^2 bytes
+        torch.cuda.synchronize()
+        del Acopy
+        ms = ctx.time_product(X, args.product_reps)
+        print(json.dumps({"product_ms": ms, "n": n, "k": k, "copy_bytes": 8 * n * n}), flush=True)
+        ctx.close()
+        return 0
     # first step: checked against the oracle below
     st1 = ctx.step(X)
     X_first = X.clone()

@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <map>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -20,8 +22,9 @@
 #include "split.h"
 
 namespace rfk {
-hipError_t launch_gemm_f64(const Prob*, const GemmItem*, int, int, int, bool, hipStream_t);
-int gemm_rows_per_block();
+hipError_t launch_gemm_f64(const Prob*, const GemmItem*, int, int, bool, int, hipStream_t);
+int gemm_rows_per_block(int cfg);
+int gemm_num_cfgs();
 hipError_t launch_gram(const Prob*, const RowItem*, int, int, hipStream_t);
 struct GramRedItem {
   int32_t prob, s0;
@@ -64,6 +67,9 @@ struct Plan {
   GramRedItem* gred_items = nullptr;
   int n_gred = 0;
   int kmax = 0;
+  int gemm_cfg = 1;
+  int gemm_ks = 1;
+  float gemm_ms = 0.f;
   bool vec2 = true;
   bool csr = false;
   bool split = false;
@@ -87,24 +93,14 @@ struct Shape {
 
 Shape choose_shape(int64_t n, int k, bool single, bool csr) {
   Shape s{};
-  const int bm = gemm_rows_per_block();
-  const int nrbg = iceil(n, bm);
   s.ksplit = 1;
-  if (single && !csr) {
-    int ks = std::max(1, iceil(512, nrbg));
-    ks = std::min(ks, 16);
-    ks = std::min<int64_t>(ks, std::max<int64_t>(1, n / 256));
-    s.ksplit = ks;
-  }
-  s.kchunk = (int)((iceil(n, s.ksplit) + 31) / 32 * 32);
-  s.ksplit = iceil(n, s.kchunk);
-  // Dense row blocks coincide with the 128-row tiles of the product, whose
-  // epilogue publishes the Rayleigh-quotient partials per row block.
+  s.kchunk = (int)n;
+  // Row blocks of the streaming passes (split-K sum, update, normalisation).
   if (single && csr) {
     const int target = 512;
     s.rbrows = std::max<int64_t>(128, ((n + target - 1) / target + 127) / 128 * 128);
   } else {
-    s.rbrows = bm;
+    s.rbrows = 128;
   }
   // Gram blocks: at least k rows (the leading k rows must sit in block 0),
   // about 128 blocks per problem when alone.
@@ -117,6 +113,8 @@ Shape choose_shape(int64_t n, int k, bool single, bool csr) {
   s.ngb = iceil(n, s.gbrows);
   return s;
 }
+
+constexpr int KSPLIT_MAX = 16;
 
 template <class T>
 hipError_t upload(T** dst, const std::vector<T>& v) {
@@ -149,6 +147,139 @@ void free_plan(Plan& p) {
     if (e_ != hipSuccess) return REFINE_EHIP;  \
   } while (0)
 
+// Work items of the dense product for launch configuration `cfg` with K
+// split `ks` (single problem; batches use ks = 1).  Item it = rb * ks + sp, so
+// blockIdx % 8 (the XCD running the block) fixes the K range when ks divides
+// or is a multiple of 8.
+std::vector<GemmItem> gemm_items(const std::vector<refine_matrix>& As, int cfg, int ks,
+                                 std::vector<int>* kchunks) {
+  std::vector<GemmItem> gi;
+  const int bm = gemm_rows_per_block(cfg);
+  kchunks->assign(As.size(), 0);
+  for (size_t p = 0; p < As.size(); ++p) {
+    const int64_t n = As[p].n;
+    const int kchunk = (int)((iceil(n, ks) + 31) / 32 * 32);
+    const int nks = iceil(n, kchunk);
+    (*kchunks)[p] = nks;
+    const int nrbg = iceil(n, bm);
+    for (int rb = 0; rb < nrbg; ++rb)
+      for (int sp = 0; sp < nks; ++sp) {
+        GemmItem g{};
+        g.prob = (int)p;
+        g.row0 = rb * bm;
+        g.k0 = sp * kchunk;
+        g.k1 = (int)std::min<int64_t>(n, (int64_t)(sp + 1) * kchunk);
+        g.split = sp;
+        gi.push_back(g);
+      }
+  }
+  if (As.size() > 1)  // larger problems first
+    std::stable_sort(gi.begin(), gi.end(),
+                     [&](const GemmItem& x, const GemmItem& y) { return As[x.prob].n > As[y.prob].n; });
+  return gi;
+}
+
+int install_gemm(Plan& pl, const std::vector<refine_matrix>& As, int cfg, int ks) {
+  std::vector<int> nks;
+  std::vector<GemmItem> gi = gemm_items(As, cfg, ks, &nks);
+  (void)hipFree(pl.gemm_items);
+  pl.gemm_items = nullptr;
+  RF_CHECK(upload(&pl.gemm_items, gi));
+  pl.n_gemm = (int)gi.size();
+  pl.gemm_cfg = cfg;
+  pl.gemm_ks = ks;
+  for (size_t p = 0; p < As.size(); ++p) pl.hprob[p].ksplit = nks[p];
+  RF_CHECK(hipMemcpy(pl.dprob, pl.hprob.data(), sizeof(Prob) * pl.hprob.size(), hipMemcpyHostToDevice));
+  return REFINE_OK;
+}
+
+// Tuning cache: (n, k, vector width) -> (launch configuration, K split).
+struct TuneKey {
+  int64_t n;
+  int k, vec2;
+  bool operator<(const TuneKey& o) const {
+    return n != o.n ? n < o.n : (k != o.k ? k < o.k : vec2 < o.vec2);
+  }
+};
+std::map<TuneKey, std::pair<int, int>>& tune_cache() {
+  static std::map<TuneKey, std::pair<int, int>> m;
+  return m;
+}
+
+// Picks the product's launch configuration: REFINE_GEMM="cfg,ks" forces one;
+// batches use a fixed configuration; a single problem times every
+// configuration and K split on its own shape (a few milliseconds, once per
+// shape and process) and keeps the fastest.
+int choose_gemm(Plan& pl, const std::vector<refine_matrix>& As, bool single,
+                const std::vector<Shape>& shapes) {
+  if (const char* env = getenv("REFINE_GEMM")) {
+    int cfg = 0, ks = 1;
+    if (sscanf(env, "%d,%d", &cfg, &ks) == 2 && cfg >= 0 && cfg < gemm_num_cfgs() && ks >= 1 &&
+        ks <= shapes[0].ksplit)
+      return install_gemm(pl, As, cfg, single ? ks : 1);
+  }
+  if (!single) return install_gemm(pl, As, 1, 1);
+  const TuneKey key{As[0].n, pl.hprob[0].k, pl.vec2 ? 1 : 0};
+  auto hit = tune_cache().find(key);
+  if (hit != tune_cache().end()) return install_gemm(pl, As, hit->second.first, hit->second.second);
+  // time the candidates on a zero X (the workspace copy of the update)
+  Prob& P = pl.hprob[0];
+  double* const saved_x = P.x;
+  const int64_t saved_ldx = P.ldx;
+  P.x = P.xn;
+  P.ldx = P.k;
+  hipStream_t st = nullptr;
+  RF_CHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  hipEvent_t e0, e1;
+  RF_CHECK(hipEventCreate(&e0));
+  RF_CHECK(hipEventCreate(&e1));
+  float best = 1e30f;
+  int best_cfg = 1, best_ks = 1;
+  const int ks_max = shapes[0].ksplit;
+  for (int cfg = 0; cfg < gemm_num_cfgs(); ++cfg) {
+    for (int ks = 1; ks <= ks_max; ks *= 2) {
+      // at least one block per CU unless this is the largest split
+      if ((int64_t)iceil(As[0].n, gemm_rows_per_block(cfg)) * ks < 256 && 2 * ks <= ks_max) continue;
+      if (install_gemm(pl, As, cfg, ks) != REFINE_OK) return REFINE_EHIP;
+      float t = 0.f, t1 = 0.f;
+      hipError_t e = hipEventRecord(e0, st);
+      if (e == hipSuccess)
+        e = launch_gemm_f64(pl.dprob, pl.gemm_items, pl.n_gemm, pl.kmax, pl.vec2, cfg, st);
+      if (e == hipSuccess) e = hipEventRecord(e1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&t1, e0, e1);
+      if (e != hipSuccess) return REFINE_EHIP;
+      if (t1 > 3.f * best / 3.f) continue;  // clearly slower than the best so far
+      if (e == hipSuccess) e = hipEventRecord(e0, st);
+      for (int r = 0; r < 3 && e == hipSuccess; ++r)
+        e = launch_gemm_f64(pl.dprob, pl.gemm_items, pl.n_gemm, pl.kmax, pl.vec2, cfg, st);
+      if (e == hipSuccess) e = hipEventRecord(e1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+      if (e != hipSuccess) return REFINE_EHIP;
+      if (getenv("REFINE_LOG") && atoi(getenv("REFINE_LOG")) >= 2)
+        fprintf(stderr, "refine: tune n=%lld k=%d cfg %d ks %d: %.1f us\n", (long long)As[0].n,
+                P.k, cfg, ks, t * 1000.f / 3.f);
+      if (t < best) {
+        best = t;
+        best_cfg = cfg;
+        best_ks = ks;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(st);
+  P.x = saved_x;
+  P.ldx = saved_ldx;
+  tune_cache()[key] = {best_cfg, best_ks};
+  pl.gemm_ms = best / 3.f;
+  if (getenv("REFINE_LOG"))
+    fprintf(stderr, "refine: product n=%lld k=%d: cfg %d, K split %d, %.1f us\n", (long long)As[0].n,
+            P.k, best_cfg, best_ks, best * 1000.f / 3.f);
+  return install_gemm(pl, As, best_cfg, best_ks);
+}
+
 // Builds descriptors, work items and the workspace for a set of problems.
 // mus/deltas/norms are per problem.
 int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector<int>& ks,
@@ -169,7 +300,8 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
     const int k = ks[p];
     pl.kmax = std::max(pl.kmax, k);
     Shape s = choose_shape(n, k, single, pl.csr);
-    if (pl.split) s.ksplit = 1;
+    // single dense FP64 problems may split K (chosen by the tuner below)
+    if (single && !pl.csr && !pl.split) s.ksplit = std::min<int64_t>(KSPLIT_MAX, std::max<int64_t>(1, n / 256));
     shapes[p] = s;
     off[p] = bytes;
     const size_t nk = (size_t)n * k * sizeof(double);
@@ -194,7 +326,6 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
   RF_CHECK(hipMemset(pl.ws, 0, bytes));
   pl.ctrl = (Ctrl*)(pl.ws + ctrl_off);
 
-  std::vector<GemmItem> gi;
   std::vector<RowItem> ri, gri;
   std::vector<GramRedItem> rr;
   for (int p = 0; p < np; ++p) {
@@ -247,20 +378,6 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
     P.beta_zero = opt.beta == REFINE_BETA_ZERO;
     P.normalize = opt.normalize != 0;
 
-    if (!pl.csr && !pl.split) {
-      const int bm = gemm_rows_per_block();
-      const int nrbg = iceil(n, bm);
-      for (int rb = 0; rb < nrbg; ++rb)
-        for (int sp = 0; sp < s.ksplit; ++sp) {
-          GemmItem g{};
-          g.prob = p;
-          g.row0 = rb * bm;
-          g.k0 = sp * s.kchunk;
-          g.k1 = (int)std::min<int64_t>(n, (int64_t)(sp + 1) * s.kchunk);
-          g.split = sp;
-          gi.push_back(g);
-        }
-    }
     for (int b = 0; b < s.nrb; ++b) ri.push_back(RowItem{p, b});
     for (int b = 0; b < s.ngb; ++b) gri.push_back(RowItem{p, b});
     const int S = 2 * k * k + k;
@@ -272,19 +389,20 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
     auto sort_items = [&](auto& v) {
       std::stable_sort(v.begin(), v.end(), [&](const auto& x, const auto& y) { return bigger(x.prob, y.prob); });
     };
-    sort_items(gi);
     sort_items(ri);
     sort_items(gri);
   }
   RF_CHECK(upload(&pl.dprob, pl.hprob));
-  RF_CHECK(upload(&pl.gemm_items, gi));
   RF_CHECK(upload(&pl.row_items, ri));
   RF_CHECK(upload(&pl.gram_items, gri));
   RF_CHECK(upload(&pl.gred_items, rr));
-  pl.n_gemm = (int)gi.size();
   pl.n_row = (int)ri.size();
   pl.n_gram = (int)gri.size();
   pl.n_gred = (int)rr.size();
+  if (!pl.csr && !pl.split) {
+    int rc = choose_gemm(pl, As, single, shapes);
+    if (rc != REFINE_OK) return rc;
+  }
   return REFINE_OK;
 }
 
@@ -297,8 +415,8 @@ hipError_t enqueue_step(Plan& pl, hipStream_t st) {
     if (pl.split) {
       if ((e = split_product(pl.sp, pl.dprob, st)) != hipSuccess) return e;
     } else {
-      if ((e = launch_gemm_f64(pl.dprob, pl.gemm_items, pl.n_gemm, pl.n_gemm, pl.kmax, pl.vec2, st)) !=
-          hipSuccess)
+      if ((e = launch_gemm_f64(pl.dprob, pl.gemm_items, pl.n_gemm, pl.kmax, pl.vec2, pl.gemm_cfg,
+                               st)) != hipSuccess)
         return e;
     }
     if ((e = launch_wsum(pl.dprob, pl.row_items, pl.n_row, st)) != hipSuccess) return e;
@@ -591,7 +709,8 @@ int refine_time_product(refine_ctx* c, double* X, int64_t ldx, int32_t reps, flo
     else if (pl.split)
       e = split_product(pl.sp, pl.dprob, c->stream);
     else
-      e = launch_gemm_f64(pl.dprob, pl.gemm_items, pl.n_gemm, pl.n_gemm, pl.kmax, pl.vec2, c->stream);
+      e = launch_gemm_f64(pl.dprob, pl.gemm_items, pl.n_gemm, pl.kmax, pl.vec2, pl.gemm_cfg,
+                          c->stream);
   }
   if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
   if (e == hipSuccess) e = hipEventSynchronize(e1);

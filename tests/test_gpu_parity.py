@@ -185,3 +185,14 @@ def test_step_is_deterministic():
         outs.append(X.cpu().numpy())
         ctx.close()
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("cfg", list(range(14)))
+def test_every_product_configuration(cfg, monkeypatch):
+    """Every launch configuration of the dense product (the tuner may pick
+    any of them) gives the oracle's step, on ragged shapes, with and without
+    a K split."""
+    for (n, k), ks in (((777, 13), 1), ((1000, 64), 2), ((1280, 33), 4)):
+        monkeypatch.setenv("REFINE_GEMM", "%d,%d" % (cfg, ks))
+        P = synth.dense_spectrum(n, k, 4000 + n)
+        _compare_steps(P.A, P.X0, 1, norm_a=1.0)
