@@ -54,7 +54,9 @@ struct Prob {
   double* w;              // W = A X (high part in split mode), n x k
   double* wlo;            // low part of W (split mode) or nullptr
   double* xn;             // unnormalised update, n x k
-  double* part;           // row-block partials, nrb x (5 k)
+  double* part;           // row-block partials of the update, nrb x (5 k)
+  double* dpart;          // Rayleigh-quotient partials, ndp x (2 k): sums of x*w, x*x
+  int32_t ndp;
   double* gpart;          // Gram partials, ngb x (2 k k + k)
   double* kk;             // k-by-k area (see KK_* offsets)
   double* vec;            // vectors of length k (see VEC_* offsets)

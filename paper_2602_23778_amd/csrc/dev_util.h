@@ -49,8 +49,8 @@ __device__ inline void team_reduce(const double* __restrict__ src, int stride, i
 // Per-column block sums for the Rayleigh quotients (eq. Rayleigh).  Threads
 // are laid out as [NT/KP rows][KP columns], KP = pow2ceil(k): thread
 // (trow, col) holds sums of x*w and x*x over its rows of column col.  The
-// block's column sums are written as partial `blk` (slots [0, k) and
-// [k, 2k) of a 5k-wide row of Prob::part); a separate kernel forms d.
+// block's column sums are written as partial `blk` of Prob::dpart; a
+// separate kernel forms d.
 // red holds 2*NT doubles.  Block-uniform call.
 template <int NT>
 __device__ void rayleigh_block_partial(const Prob& P, int blk, double sxw, double sxx,
@@ -68,10 +68,9 @@ __device__ void rayleigh_block_partial(const Prob& P, int blk, double sxw, doubl
     }
     __syncthreads();
   }
-  const int stride = 5 * k;
   if (trow == 0 && col < k) {
-    P.part[(int64_t)blk * stride + col] = red[tid];
-    P.part[(int64_t)blk * stride + k + col] = red[NT + tid];
+    P.dpart[(int64_t)blk * 2 * k + col] = red[tid];
+    P.dpart[(int64_t)blk * 2 * k + k + col] = red[NT + tid];
   }
   __syncthreads();
 }

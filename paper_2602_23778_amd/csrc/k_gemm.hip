@@ -1,190 +1,30 @@
 // Line 1 of Algorithm 4 for dense A: W = A X on the FP64 matrix cores.
 //
 // Shape: A is n x n (streamed once from HBM), X is n x k with k <= 128, so
-// the product is a tall-skinny GEMM whose work per byte of A is k/4 flop/B.
+// the product is a tall-skinny GEMM whose work per byte of A is k/4 flop/B
+// (16 flop/B at k = 64, just above the FP64 ridge of about 9.8 flop/B).
 // Design for gfx950:
-//   * one wavefront owns 16 rows of A and all BN = 16*CT columns of W; its
-//     A fragments are loaded straight from global memory into registers
-//     (16 rows x 64 contiguous bytes per lane group, full 128-byte lines per
-//     two chunks), so A never touches LDS and each A element feeds CT MFMAs;
-//   * the X chunk (32 x BN) is shared by the WAVES wavefronts of a workgroup
-//     through a double-buffered LDS tile (row stride BN+2 doubles to spread
-//     the four lane groups over different banks);
-//   * v_mfma_f64_16x16x4_f64: each lane holds a[row = l%16][k = l/16] and
-//     b[k = l/16][col = l%16] (result layout: see mfma_row in common.h); the
-//     K index inside a 32-wide chunk is permuted
-//     identically for A and B (lane group g uses k = 8g + m for step m), which
-//     leaves the sum unchanged and lets a lane read 8 contiguous doubles;
-//   * split-K over the work-item table gives enough workgroups to fill 256
-//     CUs; items are ordered on the host so that blockIdx % 8 (the XCD that
-//     runs the block) fixes the K range, keeping each XCD's X chunk in its L2.
+//   * the product is computed as W^T = X^T A (A is symmetric), which puts A
+//     in the B operand of v_mfma_f64_16x16x4_f64: lane l supplies
+//     b[k = l/16][j = l%16], so each load instruction reads whole 128-byte
+//     segments of four A rows (the A-operand form reads 16 rows x 16 bytes and
+//     measured 2.3 TB/s against 2.8 TB/s here); A goes straight from HBM to
+//     registers, one chunk ahead, with non-temporal loads;
+//   * each A value feeds CT = ceil(k/16) MFMAs (one per 16-column tile of X);
+//     the X chunk (KC x 16 CT) is shared by the block's wavefronts through a
+//     double-buffered LDS tile;
+//   * split-K over the work-item table gives enough blocks to fill 256 CUs;
+//     items are ordered so that blockIdx % 8 (the XCD that runs the block)
+//     fixes the K range, keeping each XCD's X chunk in its L2;
+//   * the epilogue transposes each 16x16 result tile through LDS and writes
+//     whole W row segments, and adds the block's column sums of x*w (and of
+//     x*x for the first K range) for the Rayleigh quotients;
+//   * the launch configuration and K split are picked per shape by a
+//     measuring tuner in the host runtime.
 #include "common.h"
+#include "dev_util.h"
 
 namespace rfk {
-
-template <int CT, int WAVES, int RT, int KC, bool BLDS, bool VEC2>
-__global__ __launch_bounds__(WAVES * 64) void gemm_f64_kernel(const Prob* __restrict__ probs,
-                                                             const GemmItem* __restrict__ items,
-                                                             int nitems) {
-  constexpr int BN = CT * 16;
-  constexpr int AM = KC / 4;       // K values per lane group per chunk
-  constexpr int LDB = BN + 2;
-  constexpr int NT = WAVES * 64;
-  constexpr int BPT = (KC * BN + NT - 1) / NT;  // X chunk elements per thread
-  constexpr int BM = WAVES * RT * 16;
-  __shared__ double Bs[BLDS ? 2 : 1][BLDS ? KC * LDB : 1];
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int g = lane >> 4, r16 = lane & 15;
-
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const GemmItem item = items[it];
-    const Prob& P = probs[item.prob];
-    if (P.ctrl->stopped) continue;  // uniform over the block
-    const int n = P.n, k = P.k;
-    const double* __restrict__ A = P.a;
-    const int64_t lda = P.lda;
-    const double* __restrict__ X = P.x;
-    const int64_t ldx = P.ldx;
-    const int k0 = item.k0, k1 = item.k1;
-    const double* arow[RT];
-    bool row_ok[RT];
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt) {
-      const int row = item.row0 + (wave * RT + rt) * 16 + r16;
-      row_ok[rt] = row < n;
-      arow[rt] = A + (int64_t)(row_ok[rt] ? row : 0) * lda;
-    }
-
-    v4d acc[RT][CT];
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int c = 0; c < CT; ++c) acc[rt][c] = v4d{0.0, 0.0, 0.0, 0.0};
-
-    double a_cur[RT][AM], a_nxt[RT][AM];
-    double bst[BLDS ? BPT : 1];
-
-    auto load_a = [&](double (*dst)[AM], int kb) {
-      const int kk = kb + AM * g;
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt) {
-        if (kb + KC <= k1) {
-          if (VEC2) {
-            typedef double v2d __attribute__((ext_vector_type(2)));
-            const v2d* p = reinterpret_cast<const v2d*>(arow[rt] + kk);
-#pragma unroll
-            for (int m = 0; m < AM / 2; ++m) {
-              v2d v = __builtin_nontemporal_load(p + m);
-              dst[rt][2 * m] = v.x;
-              dst[rt][2 * m + 1] = v.y;
-            }
-          } else {
-#pragma unroll
-            for (int m = 0; m < AM; ++m) dst[rt][m] = arow[rt][kk + m];
-          }
-        } else {
-#pragma unroll
-          for (int m = 0; m < AM; ++m) dst[rt][m] = (kk + m < k1) ? arow[rt][kk + m] : 0.0;
-        }
-        if (!row_ok[rt]) {
-#pragma unroll
-          for (int m = 0; m < AM; ++m) dst[rt][m] = 0.0;
-        }
-      }
-    };
-    auto load_b = [&](int kb) {
-#pragma unroll
-      for (int s = 0; s < BPT; ++s) {
-        const int e = tid + s * NT;
-        const int kr = e / BN, col = e - kr * BN;
-        double v = 0.0;
-        if (e < KC * BN && kb + kr < k1 && col < k) v = X[(int64_t)(kb + kr) * ldx + col];
-        bst[s] = v;
-      }
-    };
-    auto store_b = [&](int buf) {
-#pragma unroll
-      for (int s = 0; s < BPT; ++s) {
-        const int e = tid + s * NT;
-        if (e < KC * BN) {
-          const int kr = e / BN, col = e - kr * BN;
-          Bs[buf][kr * LDB + col] = bst[s];
-        }
-      }
-    };
-
-    const int nchunks = (k1 - k0 + KC - 1) / KC;
-    load_a(a_cur, k0);
-    if (BLDS) {
-      load_b(k0);
-      store_b(0);
-      __syncthreads();
-    }
-    for (int c = 0; c < nchunks; ++c) {
-      const int buf = c & 1;
-      const bool more = c + 1 < nchunks;
-      const int kb = k0 + c * KC;
-      if (more) {
-        load_a(a_nxt, kb + KC);
-        if (BLDS) load_b(kb + KC);
-      }
-      if (BLDS) {
-        const double* bs = &Bs[buf][0];
-#pragma unroll
-        for (int m = 0; m < AM; ++m) {
-          const double* brow = bs + (AM * g + m) * LDB + r16;
-#pragma unroll
-          for (int ct = 0; ct < CT; ++ct) {
-            const double bv = brow[ct * 16];
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt) acc[rt][ct] = mfma_f64(a_cur[rt][m], bv, acc[rt][ct]);
-          }
-        }
-        if (more) store_b(buf ^ 1);
-        __syncthreads();
-      } else {
-        // B fragments straight from X (shared by the block's wavefronts in L1)
-#pragma unroll
-        for (int m = 0; m < AM; ++m) {
-          const int kr = kb + AM * g + m;
-          const bool kok = kr < k1;
-          const double* xr = X + (int64_t)(kok ? kr : k0) * ldx + r16;
-#pragma unroll
-          for (int ct = 0; ct < CT; ++ct) {
-            const double bv = (kok && ct * 16 + r16 < k) ? xr[ct * 16] : 0.0;
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt) acc[rt][ct] = mfma_f64(a_cur[rt][m], bv, acc[rt][ct]);
-          }
-        }
-      }
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int m = 0; m < AM; ++m) a_cur[rt][m] = a_nxt[rt][m];
-    }
-
-    // Epilogue: register r of the lane holds row mfma_row(g, r), column r16
-    // of each 16x16 tile.
-    double* __restrict__ out = (P.ksplit > 1) ? P.wp + (int64_t)item.split * n * k : P.w;
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt) {
-      const int orow = item.row0 + (wave * RT + rt) * 16;
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct) {
-        const int col = ct * 16 + r16;
-        if (col < k) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int orr = orow + mfma_row(g, r);
-            if (orr < n) out[(int64_t)orr * k + col] = acc[rt][ct][r];
-          }
-        }
-      }
-    }
-  }
-}
 
 // Transposed form W^T = X^T A (A is symmetric), which puts A in the MFMA B
 // operand: for each 4-row K step, lane group g reads row kk+g of A at columns
@@ -204,8 +44,10 @@ __global__ __launch_bounds__(WAVES * 64) void gemm_f64_t_kernel(const Prob* __re
   constexpr int NT = WAVES * 64;
   constexpr int BPT = (KC * BN + NT - 1) / NT;
   constexpr int WROWS = RT * 16;   // W rows per wavefront
+  constexpr int BM = WAVES * WROWS;
   constexpr int TT = 16 * 17;      // epilogue transpose tile per wavefront (doubles)
-  constexpr int BUF = (2 * KC * LDB > WAVES * TT) ? 2 * KC * LDB : WAVES * TT;
+  constexpr int BUF0 = (2 * KC * LDB > WAVES * TT) ? 2 * KC * LDB : WAVES * TT;
+  constexpr int BUF = BUF0 > 2 * WAVES * BN ? BUF0 : 2 * WAVES * BN;
   __shared__ double smem[BUF];
   double* Bs0 = smem;
   double* Bs1 = smem + KC * LDB;
@@ -320,6 +162,14 @@ __global__ __launch_bounds__(WAVES * 64) void gemm_f64_t_kernel(const Prob* __re
     double* tw = smem + wave * TT;
     double* __restrict__ out = (P.ksplit > 1) ? P.wp + (int64_t)item.split * n * k : P.w;
     const int tc = lane >> 2, tq = lane & 3;
+    double sxw[CT][4], sxx[CT][4];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        sxw[ct][u] = 0.0;
+        sxx[ct][u] = 0.0;
+      }
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
       const int row = j0 + RT * tc + rt;
@@ -334,25 +184,68 @@ __global__ __launch_bounds__(WAVES * 64) void gemm_f64_t_kernel(const Prob* __re
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const int col = ct * 16 + 4 * tq + u;
-            if (col < k) out[(int64_t)row * k + col] = v[u];
+            if (col < k) {
+              out[(int64_t)row * k + col] = v[u];
+              const double x = X[(int64_t)row * ldx + col];
+              sxw[ct][u] = __builtin_fma(x, v[u], sxw[ct][u]);
+              sxx[ct][u] = __builtin_fma(x, x, sxx[ct][u]);
+            }
           }
         }
       }
     }
+    // Rayleigh partials of this item: column sums over its rows of x*w
+    // (linear in w, so the K ranges add up) and of x*x (first K range only).
+    // Lanes with equal tq hold the same columns.
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        double a = sxw[ct][u], b = sxx[ct][u];
+#pragma unroll
+        for (int o = 4; o < 64; o *= 2) {
+          a += __shfl_xor(a, o);
+          b += __shfl_xor(b, o);
+        }
+        sxw[ct][u] = a;
+        sxx[ct][u] = b;
+      }
+    __syncthreads();
+    double* red = smem;  // [WAVES][2][BN]
+    if (lane < 4) {
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          red[(wave * 2) * BN + ct * 16 + 4 * lane + u] = sxw[ct][u];
+          red[(wave * 2 + 1) * BN + ct * 16 + 4 * lane + u] = sxx[ct][u];
+        }
+    }
+    __syncthreads();
+    if (tid < k) {
+      double a = 0.0, b = 0.0;
+      for (int w = 0; w < WAVES; ++w) {
+        a += red[(w * 2) * BN + tid];
+        b += red[(w * 2 + 1) * BN + tid];
+      }
+      double* dst = P.dpart + (int64_t)(item.row0 / BM * P.ksplit + item.split) * 2 * k;
+      dst[tid] = a;
+      dst[k + tid] = item.split == 0 ? b : 0.0;
+    }
+    __syncthreads();
     __syncthreads();
   }
 }
 
 // Launch configurations: wavefronts per block, row tiles per wavefront,
 // K chunk, and whether the X chunk goes through LDS (else through L1).
-// Configurations 6.. use the transposed kernel (rt = interleaved A tiles).
+// Launch configurations: wavefronts per block, interleaved 16-column A tiles
+// per wavefront, K chunk.
 struct GemmCfg {
-  int waves, rt, kc, blds;
+  int waves, rt, kc;
 };
 static const GemmCfg kGemmCfgs[] = {
-    {8, 1, 32, 1}, {8, 1, 32, 0}, {4, 2, 32, 1}, {4, 2, 32, 0}, {8, 1, 64, 1}, {4, 1, 32, 0},
-    {8, 1, 32, 1}, {8, 2, 32, 1}, {4, 2, 32, 1}, {4, 1, 32, 1}, {8, 2, 16, 1},
-    {8, 1, 64, 1}, {16, 1, 32, 1}, {4, 1, 64, 1},
+    {8, 1, 32}, {8, 2, 32}, {4, 2, 32}, {4, 1, 32}, {8, 2, 16}, {8, 1, 64}, {16, 1, 32}, {4, 1, 64},
 };
 constexpr int kNumGemmCfgs = sizeof(kGemmCfgs) / sizeof(kGemmCfgs[0]);
 
@@ -363,31 +256,19 @@ template <int CT, bool VEC2>
 static hipError_t launch_ct(int cfg, const Prob* probs, const GemmItem* items, int nitems,
                             hipStream_t st) {
   switch (cfg) {
-#define RFK_G(ID, W, R, K, L)                                                                \
-  case ID:                                                                                   \
-    hipLaunchKernelGGL((gemm_f64_kernel<CT, W, R, K, L, VEC2>), dim3(nitems), dim3(W * 64), 0, \
-                       st, probs, items, nitems);                                            \
-    break;
-    RFK_G(0, 8, 1, 32, true)
-    RFK_G(1, 8, 1, 32, false)
-    RFK_G(2, 4, 2, 32, true)
-    RFK_G(3, 4, 2, 32, false)
-    RFK_G(4, 8, 1, 64, true)
-    RFK_G(5, 4, 1, 32, false)
-#undef RFK_G
 #define RFK_T(ID, W, R, K)                                                                   \
   case ID:                                                                                   \
     hipLaunchKernelGGL((gemm_f64_t_kernel<CT, W, R, K, VEC2>), dim3(nitems), dim3(W * 64), 0, \
                        st, probs, items, nitems);                                            \
     break;
-    RFK_T(6, 8, 1, 32)
-    RFK_T(7, 8, 2, 32)
-    RFK_T(8, 4, 2, 32)
-    RFK_T(9, 4, 1, 32)
-    RFK_T(10, 8, 2, 16)
-    RFK_T(11, 8, 1, 64)
-    RFK_T(12, 16, 1, 32)
-    RFK_T(13, 4, 1, 64)
+    RFK_T(0, 8, 1, 32)
+    RFK_T(1, 8, 2, 32)
+    RFK_T(2, 4, 2, 32)
+    RFK_T(3, 4, 1, 32)
+    RFK_T(4, 8, 2, 16)
+    RFK_T(5, 8, 1, 64)
+    RFK_T(6, 16, 1, 32)
+    RFK_T(7, 4, 1, 64)
 #undef RFK_T
     default:
       return hipErrorInvalidValue;

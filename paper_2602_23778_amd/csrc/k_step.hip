@@ -3,9 +3,9 @@
 // explicit H is formed (Sec. 3.2, after Table 1) and so that every pass over
 // the n x k arrays streams them once:
 //
-//   pass 1  (wsum)     W = sum of split-K partials, and per row block the
-//                      column sums of x_j * w_j and x_j * x_j (the CSR product
-//                      fuses this); fin_d forms d_j = x_j^T w_j / alpha_j
+//   pass 1  (products) the product kernels write the column sums of x_j * w_j
+//                      and x_j * x_j per block; wsum adds the split-K partials
+//                      of the dense product; fin_d forms d_j = x_j^T w_j / alpha_j
 //                      (eq. Rayleigh).  Cross-block sums always go through
 //                      memory and a later kernel: no in-kernel device-wide
 //                      fences, which on this GPU write back the whole L2.
@@ -251,15 +251,17 @@ __global__ __launch_bounds__(1024) void gram_reduce_kernel(const Prob* __restric
 }
 
 // ---------------------------------------------------------------------------
-// pass 3: update of the bottom rows on the matrix cores, statistics and the
-// accept/reject decision.  Each wavefront owns 16 rows; the B operand
-// [M | N] (k x 2k, small and shared by all blocks) is read through the
-// caches; A is the X row block.
+// pass 3: update of the bottom rows on the matrix cores.  Each wavefront owns
+// 16 rows; the B operand [M | N] (k x 2k) is staged in LDS (whole when
+// k <= 64, else in chunks of 32 rows) and shared by the block's four
+// wavefronts; A is the X row block.  The block writes per-column partials of
+// sum x~^2 and sum e^2; fin_stats finishes them.
 // ---------------------------------------------------------------------------
 template <int CT>
-__global__ __launch_bounds__(512) void update_kernel(const Prob* __restrict__ probs,
+__global__ __launch_bounds__(256) void update_kernel(const Prob* __restrict__ probs,
                                                     const RowItem* __restrict__ items, int nitems) {
-  constexpr int NT = 512, WAVES = 8;
+  constexpr int NT = 256, WAVES = 4, KCH = CT <= 4 ? 64 : 32, BW = 2 * CT * 16, LDC = BW + 2;
+  __shared__ double Cs[KCH * LDC];
   __shared__ double colred[2][WAVES][CT * 16];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, r16 = lane & 15;
@@ -285,6 +287,22 @@ __global__ __launch_bounds__(512) void update_kernel(const Prob* __restrict__ pr
       xsq[t] = 0.0;
       esq[t] = 0.0;
     }
+    // stage rows [kc0, kc0 + KCH) of [M | N] (columns padded to 16 CT)
+    auto stage = [&](int kc0) {
+      for (int e = tid; e < KCH * BW; e += NT) {
+        const int rr = e / BW, cc = e - rr * BW;
+        const int half = cc / (CT * 16), cj = cc - half * (CT * 16);
+        const int kr = kc0 + rr;
+        double v = 0.0;
+        if (kr < k && cj < k) v = Cm[kr * k2 + half * k + cj];
+        Cs[rr * LDC + cc] = v;
+      }
+    };
+    const bool one_stage = k <= KCH;
+    if (one_stage) {
+      stage(0);
+      __syncthreads();
+    }
     for (int rc = r0; rc < r1; rc += WAVES * 16) {
       v4d accM[CT], accN[CT];
 #pragma unroll
@@ -295,21 +313,28 @@ __global__ __launch_bounds__(512) void update_kernel(const Prob* __restrict__ pr
       const int arow = rc + wave * 16 + r16;
       const bool arok = arow < r1;
       const double* xr = X + (int64_t)(arok ? arow : r0) * ldx;
-      for (int kc = 0; kc < k; kc += 16) {
+      for (int kc0 = 0; kc0 < k; kc0 += KCH) {
+        if (!one_stage) {
+          __syncthreads();
+          stage(kc0);
+          __syncthreads();
+        }
+        const int kend = min(k, kc0 + KCH);
+        for (int kc = kc0; kc < kend; kc += 16) {
+          double a[4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const int kk = kc + 4 * s + g;
-          const bool kok = kk < k;
-          const double a = (arok && kok) ? xr[kk] : 0.0;
-          const double* brow = Cm + (int64_t)(kok ? kk : 0) * k2;
+          for (int s = 0; s < 4; ++s) {
+            const int kk = kc + 4 * s + g;
+            a[s] = (arok && kk < k) ? xr[kk] : 0.0;
+          }
 #pragma unroll
-          for (int t = 0; t < CT; ++t) {
-            const int c = t * 16 + r16;
-            const bool ok = kok && cok[t];
-            const double bm = ok ? brow[c] : 0.0;
-            const double bn = ok ? brow[k + c] : 0.0;
-            accM[t] = mfma_f64(a, bm, accM[t]);
-            accN[t] = mfma_f64(a, bn, accN[t]);
+          for (int s = 0; s < 4; ++s) {
+            const double* brow = Cs + (kc - kc0 + 4 * s + g) * LDC + r16;
+#pragma unroll
+            for (int t = 0; t < CT; ++t) {
+              accM[t] = mfma_f64(a[s], brow[t * 16], accM[t]);
+              accN[t] = mfma_f64(a[s], brow[CT * 16 + t * 16], accN[t]);
+            }
           }
         }
       }
@@ -435,8 +460,8 @@ __global__ __launch_bounds__(1024) void fin_stats_kernel(const Prob* __restrict_
   }
 }
 
-// Rayleigh quotients, one workgroup per problem: sums the row-block partials
-// of x_j^T w_j and x_j^T x_j (fixed order) and forms d_j (eq. Rayleigh),
+// Rayleigh quotients, one workgroup per problem: sums the partials of
+// x_j^T w_j and x_j^T x_j (fixed order) and forms d_j (eq. Rayleigh),
 // alpha_j = x_j^T x_j and 1/(d_j - mu).
 __global__ __launch_bounds__(1024) void fin_d_kernel(const Prob* __restrict__ probs, int nprob) {
   constexpr int NT = 1024;
@@ -448,7 +473,7 @@ __global__ __launch_bounds__(1024) void fin_d_kernel(const Prob* __restrict__ pr
     __syncthreads();
     if (P.ctrl->stopped) continue;
     const int k = P.k;
-    team_reduce(P.part, 5 * k, 2 * k, P.nrb, scr, tot);
+    team_reduce(P.dpart, 2 * k, 2 * k, P.ndp, scr, tot);
     int bad = 0;
     for (int j = tid; j < k; j += NT) {
       const double a = tot[k + j];
@@ -465,51 +490,34 @@ __global__ __launch_bounds__(1024) void fin_d_kernel(const Prob* __restrict__ pr
   }
 }
 
-// Split-K sum and Rayleigh partials for dense A: W = sum of the ksplit
-// partial products in split order (when ksplit > 1), and the per-row-block
-// column sums of x*w and x*x.
-template <int NT>
-__global__ __launch_bounds__(NT) void wsum_kernel(const Prob* __restrict__ probs,
-                                                 const RowItem* __restrict__ items, int nitems) {
-  __shared__ double red[2 * NT];
-  const int tid = threadIdx.x;
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const RowItem item = items[it];
-    const Prob& P = probs[item.prob];
-    if (P.ctrl->stopped) continue;
-    const int n = P.n, k = P.k, kp = pow2ceil(k), tr = NT / kp;
-    const int col = tid % kp, trow = tid / kp;
-    const int r0 = item.blk * P.rbrows, r1 = min(n, r0 + P.rbrows);
-    const int S = P.ksplit;
-    const int64_t nk = (int64_t)n * k;
-    double sxw = 0.0, sxx = 0.0;
-    if (col < k) {
-#pragma unroll 2
-      for (int row = r0 + trow; row < r1; row += tr) {
-        const int64_t o = (int64_t)row * k + col;
-        double w;
-        if (S > 1) {
-          double v[4];
-          w = P.wp[o];
-          int s = 1;
-          for (; s + 3 < S; s += 4) {
+// Split-K sum for dense A: W = sum of the ksplit partial products in split
+// order; each thread sums two adjacent doubles of every partial (n*k even
+// keeps the paired loads aligned; an odd tail element is summed alone).
+__global__ __launch_bounds__(256) void wsum_kernel(const Prob* __restrict__ probs, int p) {
+  typedef double v2d __attribute__((ext_vector_type(2)));
+  const Prob& P = probs[p];
+  if (P.ctrl->stopped) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nk = (int64_t)P.n * P.k;
+  const int S = P.ksplit;
+  if (nk % 2 == 0 && 2 * i + 1 < nk) {
+    const v2d* src = reinterpret_cast<const v2d*>(P.wp) + i;
+    const int64_t st = nk / 2;
+    v2d v[16];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = P.wp[o + (s + u) * nk];
+    for (int s = 0; s < 16; ++s)
+      if (s < S) v[s] = src[s * st];
+    v2d w = v[0];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) w += v[u];
-          }
-          for (; s < S; ++s) w += P.wp[o + s * nk];
-          P.w[o] = w;
-        } else {
-          w = P.w[o];
-        }
-        if (P.wlo) w += P.wlo[o];
-        const double x = P.x[(int64_t)row * P.ldx + col];
-        sxw = __builtin_fma(x, w, sxw);
-        sxx = __builtin_fma(x, x, sxx);
-      }
+    for (int s = 1; s < 16; ++s)
+      if (s < S) w += v[s];
+    reinterpret_cast<v2d*>(P.w)[i] = w;
+  } else {
+    for (int64_t e = 2 * i; e < 2 * i + 2 && e < nk; ++e) {
+      double w = P.wp[e];
+      for (int s = 1; s < S; ++s) w += P.wp[e + s * nk];
+      P.w[e] = w;
     }
-    rayleigh_block_partial<NT>(P, item.blk, sxw, sxx, red);
   }
 }
 
@@ -593,7 +601,7 @@ hipError_t launch_update(const Prob* probs, const RowItem* items, int nitems, in
   const int ct = (kmax + 15) / 16;
 #define RFK_CASE(CTV)                                                                   \
   case CTV:                                                                             \
-    hipLaunchKernelGGL((update_kernel<CTV>), dim3(nitems), dim3(512), 0, st, probs, items, \
+    hipLaunchKernelGGL((update_kernel<CTV>), dim3(nitems), dim3(256), 0, st, probs, items, \
                        nitems);                                                         \
     break;
   switch (ct) {
@@ -605,8 +613,9 @@ hipError_t launch_update(const Prob* probs, const RowItem* items, int nitems, in
   return hipGetLastError();
 }
 
-hipError_t launch_wsum(const Prob* probs, const RowItem* items, int nitems, hipStream_t st) {
-  hipLaunchKernelGGL((wsum_kernel<1024>), dim3(nitems), dim3(1024), 0, st, probs, items, nitems);
+hipError_t launch_wsum(const Prob* probs, int p, int64_t n, int k, hipStream_t st) {
+  const int64_t npairs = (n * k + 1) / 2;
+  hipLaunchKernelGGL(wsum_kernel, dim3((unsigned)((npairs + 255) / 256)), dim3(256), 0, st, probs, p);
   return hipGetLastError();
 }
 

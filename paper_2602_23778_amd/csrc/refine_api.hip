@@ -34,7 +34,7 @@ int kxk_lds_doubles(int);
 hipError_t launch_kxk(const Prob*, int, int, hipStream_t);
 hipError_t launch_update(const Prob*, const RowItem*, int, int, hipStream_t);
 hipError_t launch_normalize(const Prob*, const RowItem*, int, hipStream_t);
-hipError_t launch_wsum(const Prob*, const RowItem*, int, hipStream_t);
+hipError_t launch_wsum(const Prob*, int, int64_t, int, hipStream_t);
 hipError_t launch_fin_d(const Prob*, int, hipStream_t);
 hipError_t launch_fin_stats(const Prob*, int, hipStream_t);
 hipError_t launch_ctrl_reset(const Prob*, int, int, double, hipStream_t);
@@ -100,7 +100,7 @@ Shape choose_shape(int64_t n, int k, bool single, bool csr) {
     const int target = 512;
     s.rbrows = std::max<int64_t>(128, ((n + target - 1) / target + 127) / 128 * 128);
   } else {
-    s.rbrows = 128;
+    s.rbrows = 64;
   }
   // Gram blocks: at least k rows (the leading k rows must sit in block 0),
   // about 128 blocks per problem when alone.
@@ -115,6 +115,12 @@ Shape choose_shape(int64_t n, int k, bool single, bool csr) {
 }
 
 constexpr int KSPLIT_MAX = 16;
+
+// Upper bound of the Rayleigh partials: per row block of the smallest
+// product tile (64 rows) and K split, or per streaming row block.
+int64_t dpart_entries(int64_t n, const Shape& s) {
+  return std::max<int64_t>((int64_t)iceil(n, 64) * std::max(1, s.ksplit), s.nrb);
+}
 
 template <class T>
 hipError_t upload(T** dst, const std::vector<T>& v) {
@@ -188,7 +194,10 @@ int install_gemm(Plan& pl, const std::vector<refine_matrix>& As, int cfg, int ks
   pl.n_gemm = (int)gi.size();
   pl.gemm_cfg = cfg;
   pl.gemm_ks = ks;
-  for (size_t p = 0; p < As.size(); ++p) pl.hprob[p].ksplit = nks[p];
+  for (size_t p = 0; p < As.size(); ++p) {
+    pl.hprob[p].ksplit = nks[p];
+    pl.hprob[p].ndp = iceil(As[p].n, gemm_rows_per_block(cfg)) * nks[p];
+  }
   RF_CHECK(hipMemcpy(pl.dprob, pl.hprob.data(), sizeof(Prob) * pl.hprob.size(), hipMemcpyHostToDevice));
   return REFINE_OK;
 }
@@ -218,7 +227,7 @@ int choose_gemm(Plan& pl, const std::vector<refine_matrix>& As, bool single,
         ks <= shapes[0].ksplit)
       return install_gemm(pl, As, cfg, single ? ks : 1);
   }
-  if (!single) return install_gemm(pl, As, 1, 1);
+  if (!single) return install_gemm(pl, As, 3, 1);
   const TuneKey key{As[0].n, pl.hprob[0].k, pl.vec2 ? 1 : 0};
   auto hit = tune_cache().find(key);
   if (hit != tune_cache().end()) return install_gemm(pl, As, hit->second.first, hit->second.second);
@@ -311,6 +320,7 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
     if (pl.split) b += align_up(nk);                     // wlo
     b += align_up(nk);                                   // xn
     b += align_up((size_t)s.nrb * 5 * k * sizeof(double));
+    b += align_up((size_t)dpart_entries(n, s) * 2 * k * sizeof(double));
     b += align_up((size_t)s.ngb * (2 * k * k + k) * sizeof(double));
     b += align_up((size_t)KK_COUNT * k * k * sizeof(double));
     b += align_up((size_t)VEC_COUNT * k * sizeof(double));
@@ -366,6 +376,9 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
     base += align_up(nk);
     P.part = (double*)base;
     base += align_up((size_t)s.nrb * 5 * k * sizeof(double));
+    P.dpart = (double*)base;
+    P.ndp = s.nrb;  // CSR: one partial per row block; dense: set with the product's items
+    base += align_up((size_t)dpart_entries(n, s) * 2 * k * sizeof(double));
     P.gpart = (double*)base;
     base += align_up((size_t)s.ngb * (2 * k * k + k) * sizeof(double));
     P.kk = (double*)base;
@@ -419,7 +432,10 @@ hipError_t enqueue_step(Plan& pl, hipStream_t st) {
                                st)) != hipSuccess)
         return e;
     }
-    if ((e = launch_wsum(pl.dprob, pl.row_items, pl.n_row, st)) != hipSuccess) return e;
+    for (int p = 0; p < np; ++p)
+      if (pl.hprob[p].ksplit > 1 &&
+          (e = launch_wsum(pl.dprob, p, pl.hprob[p].n, pl.hprob[p].k, st)) != hipSuccess)
+        return e;
   }
   if ((e = launch_fin_d(pl.dprob, np, st)) != hipSuccess) return e;
   if ((e = launch_gram(pl.dprob, pl.gram_items, pl.n_gram, pl.kmax, st)) != hipSuccess) return e;
