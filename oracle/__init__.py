@@ -56,7 +56,8 @@ class _Opts(ctypes.Structure):
                 ("norm_a", ctypes.c_double), ("beta_zero", ctypes.c_int32),
                 ("normalize", ctypes.c_int32), ("dd", ctypes.c_int32),
                 ("shift_in_denominators", ctypes.c_int32),
-                ("plant_printed_sign", ctypes.c_int32)]
+                ("plant_printed_sign", ctypes.c_int32),
+                ("split_slices", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -81,6 +82,10 @@ def _load():
         lib.orc_refine_step.argtypes = [ctypes.POINTER(_Matrix), i64, vp, i64, vp, i64,
                                         ctypes.POINTER(_Opts), ctypes.POINTER(_Stats), vp, vp]
         lib.orc_refine_step.restype = ctypes.c_int
+        lib.orc_split_digits.argtypes = [i64, i64, vp, i64, ctypes.c_int32, ctypes.c_int32,
+                                         vp, vp]
+        lib.orc_gemm_split.argtypes = [i64, i64, vp, i64, vp, i64, ctypes.c_int32, vp, vp, i64]
+        lib.orc_gemm_split.restype = ctypes.c_int
         lib.orc_norm_inf_dense.argtypes = [i64, vp, i64]
         lib.orc_norm_inf_dense.restype = dbl
         lib.orc_norm_inf_csr.argtypes = [i64, vp, vp]
@@ -134,6 +139,36 @@ def matmul(A, X, dd: bool = False):
     return (W, Wlo) if dd else W
 
 
+def split_digits(M, s: int, by_row: bool):
+    """Slicing of the split form (Sec. 3.3; Ozaki et al. 2012): returns
+    (D, E) with D of shape (s, rows, cols), int8 digits in [-64, 64], and E
+    the per-row (by_row) or per-column power-of-two exponents, such that
+    M = 2^(E-6) sum_p D_p 2^(-7(p-1)) + r with |r| <= 2^(E-7s)."""
+    lib = _load()
+    M = _f64(M)
+    rows, cols = M.shape
+    D = np.empty((s, rows, cols), dtype=np.int8)
+    E = np.empty(rows if by_row else cols, dtype=np.int32)
+    lib.orc_split_digits(rows, cols, _p(M), cols, int(by_row), s, _p(D), _p(E))
+    return D, E
+
+
+def matmul_split(A, X, s: int):
+    """Line 1 of Algorithm 4 by the split form with s slices per operand: the
+    products of digit matrices with p + q <= s + 1, combined exactly; returns
+    (W_hi, W_lo) with W_hi + W_lo equal to that sum.  A need not be
+    symmetric (rows of A are scaled, columns of X)."""
+    lib = _load()
+    A, X = _f64(A), _f64(X)
+    n, k = X.shape
+    W = np.empty((n, k))
+    Wlo = np.empty((n, k))
+    rc = lib.orc_gemm_split(n, k, _p(A), A.shape[1], _p(X), k, s, _p(W), _p(Wlo), k)
+    if rc != OK:
+        raise ValueError("orc_gemm_split: status %d" % rc)
+    return W, Wlo
+
+
 def compact_wy(X):
     """Algorithm 1: Y = X - I_{n,k}, T = -Y1^{-T}.  Returns (status, Y, T, cond1)."""
     lib = _load()
@@ -180,11 +215,13 @@ def refine_step(A, X, *, mu: float = 0.0, norm_a: float | None = None,
                 delta_c: float = 10.0, beta_zero: bool = False,
                 normalize: bool = True, dd: bool = False,
                 shift_in_denominators: bool = False,
-                plant_printed_sign: bool = False) -> StepResult:
+                plant_printed_sign: bool = False, split: int = 0) -> StepResult:
     """One step of Algorithm 4 (with Algorithm 1) on A (dense or Csr).
 
     mu: the method runs on A - mu I (Sec. 5.1); norm_a: ||A|| in delta and in
-    the residual statistic (default ||A||_inf); dd: line 1 in double-double.
+    the residual statistic (default ||A||_inf); dd: line 1 in double-double;
+    split: line 1 by the split form with that many slices (dense A), its
+    pair (W_hi, W_lo) then used like the double-double one.
     plant_printed_sign exists only so that a test can show that the sign
     printed in eq. (V-def) makes the iteration diverge."""
     lib = _load()
@@ -205,7 +242,7 @@ def refine_step(A, X, *, mu: float = 0.0, norm_a: float | None = None,
         m.kind = 0
         m.a, m.lda = _p(A), A.shape[1]
     o = _Opts(mu, delta_c, norm_a, int(beta_zero), int(normalize), int(dd),
-              int(shift_in_denominators), int(plant_printed_sign))
+              int(shift_in_denominators), int(plant_printed_sign), int(split))
     st = _Stats()
     Xout = np.zeros((n, k))
     d = np.zeros(k)

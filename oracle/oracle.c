@@ -112,6 +112,110 @@ void orc_gemm_dense_dd(int64_t n, int64_t k, const double* A, int64_t lda,
   }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Split form of line 1 of Algorithm 4 (the accelerator direction of        */
+/* Sec. 3.3): the error-free splitting of Ozaki, Ogita, Oishi and Rump      */
+/* (2012) with integer slices, as Ootomo, Ozaki and Yokota (2024) run it on  */
+/* integer matrix units.                                                     */
+/*                                                                           */
+/* Slicing.  Every row of A (every column of X) gets a power-of-two scale    */
+/* 2^E with E the smallest integer such that max |entry| < 2^E (E = 0 for an */
+/* all-zero line).  The scaled value v = m * 2^(6-E) lies in (-64, 64) and   */
+/* is peeled into s signed digits by rounding to nearest (ties to even):     */
+/*     d_1 = rint(v),  v <- (v - d_1) * 2^7,  d_2 = rint(v),  ...            */
+/* so every digit lies in [-64, 64] and                                      */
+/*     m = 2^(E-6) * sum_p d_p 2^(-7(p-1))  +  r,   |r| <= 2^(E-7s).        */
+/* Each step is exact in FP64 (scaling by powers of two, and subtracting the */
+/* nearest integer).                                                         */
+/*                                                                           */
+/* Product.  With A_p, X_q the digit matrices, every product A_p X_q is an   */
+/* exact integer matrix.  The products with p + q <= s + 1 are kept and      */
+/* binned by t = p + q (the leading s(s+1)/2 terms of the expansion); the    */
+/* result is                                                                 */
+/*     W_ij = 2^(E_i + F_j - 12) * sum_t B_t[i][j] * 2^(-7(t-2)),            */
+/* computed here exactly as a 128-bit integer and returned as a double-      */
+/* double pair (hi, lo) with hi + lo equal to that value.                    */
+/* ------------------------------------------------------------------------ */
+
+/* Digits of a rows x cols row-major matrix M (leading dimension ld).
+ * by_row = 1: one scale per row (A); 0: one scale per column (X).
+ * D is s x rows x cols (plane p at D + p*rows*cols); Eexp has rows (or
+ * cols) entries. */
+void orc_split_digits(int64_t rows, int64_t cols, const double* M, int64_t ld,
+                      int32_t by_row, int32_t s, int8_t* D, int32_t* Eexp) {
+  const int64_t nline = by_row ? rows : cols;
+  for (int64_t a = 0; a < nline; ++a) {
+    double mx = 0.0;
+    const int64_t len = by_row ? cols : rows;
+    for (int64_t b = 0; b < len; ++b) {
+      double v = by_row ? M[a * ld + b] : M[b * ld + a];
+      if (fabs(v) > mx) mx = fabs(v);
+    }
+    int e = 0;
+    if (mx > 0.0) frexp(mx, &e); /* mx = f 2^e with f in [1/2, 1): mx < 2^e */
+    Eexp[a] = e;
+  }
+  for (int64_t i = 0; i < rows; ++i)
+    for (int64_t j = 0; j < cols; ++j) {
+      const int e = Eexp[by_row ? i : j];
+      double v = ldexp(M[i * ld + j], 6 - e);
+      for (int32_t p = 0; p < s; ++p) {
+        double d = rint(v);
+        D[(int64_t)p * rows * cols + i * cols + j] = (int8_t)d;
+        v = ldexp(v - d, 7);
+      }
+    }
+}
+
+/* W = A X by the split form with s slices per operand (1 <= s <= 12).
+ * A is n x n (row-major, lda), X is n x k (ldx); W and Wlo are n x k (ldw).
+ * Bins are accumulated in 64-bit integers (exact for any n here). */
+int orc_gemm_split(int64_t n, int64_t k, const double* A, int64_t lda,
+                   const double* X, int64_t ldx, int32_t s, double* Whi,
+                   double* Wlo, int64_t ldw) {
+  if (s < 1 || s > 12) return ORC_EINVAL;
+  int8_t* DA = (int8_t*)malloc((size_t)s * (size_t)(n * n));
+  int8_t* DX = (int8_t*)malloc((size_t)s * (size_t)(n * k));
+  int32_t* EA = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t* EX = (int32_t*)malloc(sizeof(int32_t) * (size_t)k);
+  if (!DA || !DX || !EA || !EX) {
+    free(DA); free(DX); free(EA); free(EX);
+    return ORC_ENOMEM;
+  }
+  orc_split_digits(n, n, A, lda, 1, s, DA, EA);
+  orc_split_digits(n, k, X, ldx, 0, s, DX, EX);
+#pragma omp parallel
+  {
+    int64_t* bins = (int64_t*)malloc(sizeof(int64_t) * (size_t)(s + 2));
+#pragma omp for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t j = 0; j < k; ++j) {
+        for (int t = 0; t < s + 2; ++t) bins[t] = 0;
+        for (int32_t p = 1; p <= s; ++p)
+          for (int32_t q = 1; p + q <= s + 1; ++q) {
+            const int8_t* ap = DA + (int64_t)(p - 1) * n * n + i * n;
+            const int8_t* xq = DX + (int64_t)(q - 1) * n * k + j;
+            int64_t acc = 0;
+            for (int64_t l = 0; l < n; ++l) acc += (int64_t)ap[l] * (int64_t)xq[l * k];
+            bins[p + q] += acc;
+          }
+        /* exact integer value of sum_t B_t 2^(7(s+1-t)) */
+        __int128 tot = 0;
+        for (int t = 2; t <= s + 1; ++t) tot += (__int128)bins[t] << (7 * (s + 1 - t));
+        double hi = (double)tot;
+        double lo = (double)(tot - (__int128)hi); /* |.| <= ulp(hi): exact */
+        double h2, l2;
+        two_sum(hi, lo, &h2, &l2);
+        const int sc = EA[i] + EX[j] - 12 - 7 * (s - 1);
+        Whi[i * ldw + j] = ldexp(h2, sc);
+        Wlo[i * ldw + j] = ldexp(l2, sc);
+      }
+    free(bins);
+  }
+  free(DA); free(DX); free(EA); free(EX);
+  return ORC_OK;
+}
+
 /* W = A * X for A in CSR form (row_ptr[n+1], col_idx[nnz], val[nnz]).        */
 void orc_gemm_csr(int64_t n, int64_t k, const int32_t* row_ptr,
                   const int32_t* col_idx, const double* val, const double* X,
@@ -295,6 +399,8 @@ typedef struct {
   int32_t dd;            /* 1: W = A*X as a double-double pair, R from it */
   int32_t shift_in_denominators; /* 1: derived form, mu only in d_j - mu */
   int32_t plant_printed_sign;    /* 1: use the sign printed in eq. (V-def) */
+  int32_t split_slices;  /* > 0: W by the split form with that many slices
+                            (dense only), kept as a pair like dd */
 } orc_opts;
 
 typedef struct {
@@ -329,15 +435,20 @@ int orc_refine_step(const orc_matrix* M, int64_t k, const double* X,
     goto done;
   }
 
-  /* Line 1: W = A X  (double-double pair when o->dd). */
-  if (M->kind == 0) {
+  /* Line 1: W = A X  (double-double pair when o->dd or split). */
+  const int pair = o->dd || o->split_slices > 0;
+  if (o->split_slices > 0) {
+    if (M->kind != 0) { rc = ORC_EINVAL; goto done; }
+    rc = orc_gemm_split(n, k, M->a, M->lda, X, ldx, o->split_slices, W, Wlo, k);
+    if (rc != ORC_OK) goto done;
+  } else if (M->kind == 0) {
     if (o->dd) orc_gemm_dense_dd(n, k, M->a, M->lda, X, ldx, W, Wlo, k);
     else orc_gemm_dense(n, k, M->a, M->lda, X, ldx, W, k);
   } else {
     if (o->dd) orc_gemm_csr_dd(n, k, M->row_ptr, M->col_idx, M->val, X, ldx, W, Wlo, k);
     else orc_gemm_csr(n, k, M->row_ptr, M->col_idx, M->val, X, ldx, W, k);
   }
-  if (!o->dd) memset(Wlo, 0, sizeof(double) * nk);
+  if (!pair) memset(Wlo, 0, sizeof(double) * nk);
 
   /* Shift, as the paper's variant does it: the method runs on B = A - mu I,
    * so W_B = W - mu X.  The derived form keeps W and puts mu only into the
@@ -346,7 +457,7 @@ int orc_refine_step(const orc_matrix* M, int64_t k, const double* X,
   if (literal_shift) {
     for (int64_t i = 0; i < n; ++i)
       for (int64_t j = 0; j < k; ++j) {
-        if (o->dd) {
+        if (pair) {
           /* (W_hi + W_lo) - mu x, kept as a pair */
           double p, pe, s, se;
           two_prod(o->mu, X[i * ldx + j], &p, &pe);
@@ -383,7 +494,7 @@ int orc_refine_step(const orc_matrix* M, int64_t k, const double* X,
   for (int64_t i = 0; i < n; ++i)
     for (int64_t j = 0; j < k; ++j) {
       double x = X[i * ldx + j];
-      if (o->dd) {
+      if (pair) {
         double p, pe;
         two_prod(x, d[j], &p, &pe);
         R[i * k + j] = (W[i * k + j] - p) + (Wlo[i * k + j] - pe);

@@ -362,3 +362,115 @@ def test_golden_k1_power_iteration_values():
     exp = np.array(g["expected"], dtype=np.float64)[:, None]
     assert max_abs_diff_aligned(r.X, exp) < 4 * U
     assert r.d[0] == pytest.approx(g["rayleigh"], abs=4 * U)
+
+
+# --------------------------------------------------------------------------
+# Split form of line 1 (Sec. 3.3; Ozaki, Ogita, Oishi and Rump 2012)
+# --------------------------------------------------------------------------
+def _wide_range_matrix(rows, cols, seed):
+    """Entries spanning many binades within each row and column."""
+    rng = np.random.default_rng(seed)
+    M = rng.standard_normal((rows, cols)) * np.exp2(rng.integers(-30, 4, (rows, cols)))
+    M[rng.random((rows, cols)) < 0.05] = 0.0
+    return M
+
+
+@pytest.mark.parametrize("s", [1, 3, 8, 9])
+def test_split_digits_reconstruct_within_bound(s):
+    """Every digit lies in [-64, 64]; the digits reconstruct each entry to
+    within 2^(E-7s) in exact rational arithmetic, E being the line's scale
+    (the smallest power of two above the line's largest magnitude); entries
+    whose last bit lies above the last digit's unit are reconstructed exactly."""
+    M = _wide_range_matrix(9, 13, 40 + s)
+    M[4, :] = 0.0                                   # an all-zero row
+    for by_row in (True, False):
+        D, E = oracle.split_digits(M, s, by_row)
+        assert D.min() >= -64 and D.max() <= 64
+        lines = M if by_row else M.T
+        for a, line in enumerate(lines):
+            mx = np.max(np.abs(line))
+            e = int(E[a])
+            if mx == 0.0:
+                assert e == 0
+            else:
+                assert Fraction(2) ** (e - 1) <= Fraction(float(mx)) < Fraction(2) ** e
+        for i in range(M.shape[0]):
+            for j in range(M.shape[1]):
+                e = int(E[i] if by_row else E[j])
+                rec = sum(Fraction(int(D[p, i, j])) * Fraction(2) ** (e - 6 - 7 * p) for p in range(s))
+                err = abs(Fraction(float(M[i, j])) - rec)
+                assert err <= Fraction(2) ** (e - 7 * s)
+                m, ex = math.frexp(float(M[i, j]))
+                if M[i, j] != 0.0 and ex - 53 >= e - 6 - 7 * (s - 1):
+                    assert err == 0
+
+
+def _short_digit_matrix(rows, cols, digits, seed, by_row):
+    """Entries m * 2^(e - 6 - 7(digits-1)) with |m| < 2^(6 + 7(digits-1)), so
+    that, whatever the line scale comes out as, each entry is an exact
+    multiple of the unit of digit number `digits`."""
+    rng = np.random.default_rng(seed)
+    bits = 6 + 7 * (digits - 1)
+    m = rng.integers(-(2 ** bits) + 1, 2 ** bits, (rows, cols)).astype(np.float64)
+    ex = rng.integers(-8, 8, rows if by_row else cols)
+    scale = np.exp2(ex - bits)
+    return m * (scale[:, None] if by_row else scale[None, :])
+
+
+@pytest.mark.parametrize("s", [8, 9])
+def test_split_product_is_exact_when_nothing_is_truncated(s):
+    """With at most floor((s+1)/2) digits per entry every term of the digit
+    expansion has p + q <= s + 1, so the split form must return the exact
+    product (Python integers), to the last bit of the (hi, lo) pair.  A is not
+    symmetric here, so a transposed operand or a swapped scale fails."""
+    n, k = 37, 5
+    half = (s + 1) // 2
+    A = _short_digit_matrix(n, n, half, 71 + s, True)
+    X = _short_digit_matrix(n, k, half, 72 + s, False)
+    assert not np.array_equal(A, A.T)
+    hi, lo = oracle.matmul_split(A, X, s)
+    ex = _exact_product(A, X)
+    for i in range(n):
+        for j in range(k):
+            assert Fraction(float(hi[i, j])) + Fraction(float(lo[i, j])) == ex[i][j]
+            assert abs(lo[i, j]) <= 0.5 * np.spacing(abs(hi[i, j])) or hi[i, j] == 0.0
+
+
+def test_split_product_truncation_bound_and_rate():
+    """Full 53-bit operands: the split product stays within the truncation
+    bound n (s + 2) 2^(E_i + F_j - 7s) of the exact product (the dropped terms
+    p + q > s + 1 and the slicing remainders), and each extra slice cuts the
+    error by about 2^7."""
+    n, k = 29, 4
+    A = _wide_range_matrix(n, n, 81)
+    X = _wide_range_matrix(n, k, 82)
+    ex = _exact_product(A, X)
+    _, EA = oracle.split_digits(A, 1, True)
+    _, EX = oracle.split_digits(X, 1, False)
+    worst = {}
+    for s in (4, 6, 8, 9):
+        hi, lo = oracle.matmul_split(A, X, s)
+        w = 0.0
+        for i in range(n):
+            for j in range(k):
+                err = abs(Fraction(float(hi[i, j])) + Fraction(float(lo[i, j])) - ex[i][j])
+                bound = Fraction(n * (s + 2)) * Fraction(2) ** (int(EA[i]) + int(EX[j]) - 7 * s)
+                assert err <= bound
+                w = max(w, float(err / Fraction(2) ** (int(EA[i]) + int(EX[j]))))
+        worst[s] = w
+    assert worst[6] < worst[4] * 2.0 ** -10
+    assert worst[8] < worst[6] * 2.0 ** -10
+    assert worst[9] < worst[8] * 2.0 ** -4
+
+
+def test_split_step_agrees_with_double_double_step():
+    """A step whose line 1 comes from the split form (9 slices, error about
+    2^-60 relative to the line scales) matches the Dot2 step to about u; with
+    1 slice it must not (guards against the option being ignored)."""
+    P = synth.dense_well_separated(256, 8)
+    r_dd = oracle.refine_step(P.A, P.X0, norm_a=P.norm_a, dd=True)
+    r_s9 = oracle.refine_step(P.A, P.X0, norm_a=P.norm_a, split=9)
+    r_s1 = oracle.refine_step(P.A, P.X0, norm_a=P.norm_a, split=1)
+    assert r_s9.status == 0 and r_dd.status == 0
+    assert np.max(np.abs(r_s9.X - r_dd.X)) < 1e-15
+    assert np.max(np.abs(r_s1.X - r_dd.X)) > 1e-6
