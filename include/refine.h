@@ -112,7 +112,10 @@ typedef struct {
   double norm_a;           /* ||A|| for delta and the residual statistic; <= 0: ||A||_inf */
   refine_beta beta;
   int32_t normalize;       /* 1: normalise columns after each update (Sec. 3.3) */
-  int32_t slices;          /* split mode: INT8 slices per operand, 0 = 8 */
+  int32_t slices;          /* split mode: INT8 digit slices per operand, 7..10;
+                              0 = 9 (45 slice products; W then carries about
+                              2^-60 of the row and column scales, below the
+                              rounding of an FP64 product) */
 } refine_options;
 
 typedef struct {
@@ -157,7 +160,8 @@ int refine_destroy(refine_ctx* ctx);
 
 /* Measurement hook for the roofline figures: enqueues `reps` launches of the
  * product W = A X alone (line 1 of Algorithm 4; its cost is the O(nnz(A) k)
- * row of Table 1), in the context's precision and launch configuration, on
+ * row of Table 1; in split mode the slicing of X, the INT8 products and the
+ * K-split sum), in the context's precision and launch configuration, on
  * the context's stream between two HIP events, waits for them and stores the
  * mean time of one launch in *ms.  X is only read; the context's workspace
  * copy of W is overwritten, so call it between steps, not inside one. */

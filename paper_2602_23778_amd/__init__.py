@@ -92,6 +92,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.refine_batch_run.argtypes = [vp, P(vp), P(i64), i32, P(refine_stats)]
     lib.refine_batch_destroy.argtypes = [vp]
     lib.refine_time_product.argtypes = [vp, vp, i64, i32, P(ctypes.c_float)]
+    lib.refine_debug_workspace.argtypes = [vp, P(vp), i32]
+    lib.refine_debug_workspace.restype = ctypes.c_int
     lib.refine_status_string.argtypes = [ctypes.c_int]
     lib.refine_status_string.restype = ctypes.c_char_p
     for name in ("refine_init", "refine_step", "refine_run", "refine_get_info", "refine_destroy",
@@ -276,6 +278,28 @@ class RefineContext:
         if rc != OK:
             raise RefineError(rc, "refine_time_product")
         return ms
+
+    def debug_product(self):
+        """Test hook: device copies (W_hi, W_lo) of the last step's product
+        W = A X of its input X (W_lo is None outside split mode), read from
+        the context's workspace after synchronising its stream."""
+        ptrs = (ctypes.c_void_p * 2)()
+        rc = _l().refine_debug_workspace(self._ctx, ptrs, 2)
+        if rc != OK:
+            raise RefineError(rc, "refine_debug_workspace")
+        (self.stream or torch.cuda.current_stream()).synchronize()
+        hip = ctypes.CDLL("libamdhip64.so.7")
+        hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        out = []
+        for p in ptrs:
+            if not p:
+                out.append(None)
+                continue
+            t = torch.empty((self.n, self.k), dtype=torch.float64, device="cuda")
+            if hip.hipMemcpy(t.data_ptr(), p, 8 * self.n * self.k, 3) != 0:  # device to device
+                raise RefineError(EHIP, "hipMemcpy")
+            out.append(t)
+        return out[0], out[1]
 
     def info(self) -> dict:
         rc, (mu, ninf, nused, delta) = refine_get_info(self._ctx)

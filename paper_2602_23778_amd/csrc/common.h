@@ -66,6 +66,18 @@ struct Prob {
   double norm_a;          // ||A|| used in the residual statistic
   int32_t beta_zero;
   int32_t normalize;
+  // split form of the dense product (INT8 slices); unused otherwise
+  const uint8_t* asl;     // slices of A: row i, chunk c at asl + i*asl_rs + c*32*s
+  int64_t asl_rs;         // bytes per row of asl (nch chunks)
+  const int32_t* aexp;    // per-row scale exponents of A (rows padded with 0)
+  uint8_t* xsl;           // slices of X^T: chunk c, column j at xsl + (c*kpad + j)*32*s
+  int32_t* xexp;          // per-column scale exponents of X (kpad entries)
+  double* xmaxp;          // per-row-block column maxima of |X|, nbx x kpad
+  double* swp;            // K-split partials of the split product: ksplit x (hi, lo) x n x k
+  int32_t nch;            // 32-wide contraction chunks (ceil(n / 32))
+  int32_t kpad;           // k rounded up to 32
+  int32_t nbx;            // row blocks of the column-maximum pass
+  int32_t xrows;          // rows per such block
 };
 
 // Offsets (in units of k*k doubles) inside Prob::kk.

@@ -46,8 +46,8 @@ __global__ __launch_bounds__(WAVES * 64) void gemm_f64_t_kernel(const Prob* __re
   constexpr int WROWS = RT * 16;   // W rows per wavefront
   constexpr int BM = WAVES * WROWS;
   constexpr int TT = 16 * 17;      // epilogue transpose tile per wavefront (doubles)
-  constexpr int BUF0 = (2 * KC * LDB > WAVES * TT) ? 2 * KC * LDB : WAVES * TT;
-  constexpr int BUF = BUF0 > 2 * WAVES * BN ? BUF0 : 2 * WAVES * BN;
+  constexpr int EPI = WAVES * TT + 2 * WAVES * BN;   // transpose tiles + column sums
+  constexpr int BUF = (2 * KC * LDB > EPI) ? 2 * KC * LDB : EPI;
   __shared__ double smem[BUF];
   double* Bs0 = smem;
   double* Bs1 = smem + KC * LDB;
@@ -160,21 +160,16 @@ __global__ __launch_bounds__(WAVES * 64) void gemm_f64_t_kernel(const Prob* __re
     // buffers are free after the last barrier) so that every W row segment of
     // 16 doubles is written by four lanes, 32 contiguous bytes each.
     double* tw = smem + wave * TT;
+    double* red = smem + WAVES * TT;  // [WAVES][2][BN]
     double* __restrict__ out = (P.ksplit > 1) ? P.wp + (int64_t)item.split * n * k : P.w;
     const int tc = lane >> 2, tq = lane & 3;
-    double sxw[CT][4], sxx[CT][4];
+    // One column tile at a time, so that only its 4 + 4 partial sums are live.
 #pragma unroll
-    for (int ct = 0; ct < CT; ++ct)
+    for (int ct = 0; ct < CT; ++ct) {
+      double sxw[4] = {0.0, 0.0, 0.0, 0.0}, sxx[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        sxw[ct][u] = 0.0;
-        sxx[ct][u] = 0.0;
-      }
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt) {
-      const int row = j0 + RT * tc + rt;
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct) {
+      for (int rt = 0; rt < RT; ++rt) {
+        const int row = j0 + RT * tc + rt;
 #pragma unroll
         for (int r = 0; r < 4; ++r) tw[r16 * 17 + mfma_row(g, r)] = acc[rt][ct][r];
         double v[4];
@@ -187,39 +182,28 @@ __global__ __launch_bounds__(WAVES * 64) void gemm_f64_t_kernel(const Prob* __re
             if (col < k) {
               out[(int64_t)row * k + col] = v[u];
               const double x = X[(int64_t)row * ldx + col];
-              sxw[ct][u] = __builtin_fma(x, v[u], sxw[ct][u]);
-              sxx[ct][u] = __builtin_fma(x, x, sxx[ct][u]);
+              sxw[u] = __builtin_fma(x, v[u], sxw[u]);
+              sxx[u] = __builtin_fma(x, x, sxx[u]);
             }
           }
         }
       }
-    }
-    // Rayleigh partials of this item: column sums over its rows of x*w
-    // (linear in w, so the K ranges add up) and of x*x (first K range only).
-    // Lanes with equal tq hold the same columns.
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct)
+      // Rayleigh partials of this item: column sums over its rows of x*w
+      // (linear in w, so the K ranges add up) and of x*x (first K range
+      // only).  Lanes with equal tq hold the same columns.
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        double a = sxw[ct][u], b = sxx[ct][u];
+        double a = sxw[u], b = sxx[u];
 #pragma unroll
         for (int o = 4; o < 64; o *= 2) {
           a += __shfl_xor(a, o);
           b += __shfl_xor(b, o);
         }
-        sxw[ct][u] = a;
-        sxx[ct][u] = b;
-      }
-    __syncthreads();
-    double* red = smem;  // [WAVES][2][BN]
-    if (lane < 4) {
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          red[(wave * 2) * BN + ct * 16 + 4 * lane + u] = sxw[ct][u];
-          red[(wave * 2 + 1) * BN + ct * 16 + 4 * lane + u] = sxx[ct][u];
+        if (lane < 4) {
+          red[(wave * 2) * BN + ct * 16 + 4 * lane + u] = a;
+          red[(wave * 2 + 1) * BN + ct * 16 + 4 * lane + u] = b;
         }
+      }
     }
     __syncthreads();
     if (tid < k) {
@@ -233,12 +217,9 @@ __global__ __launch_bounds__(WAVES * 64) void gemm_f64_t_kernel(const Prob* __re
       dst[k + tid] = item.split == 0 ? b : 0.0;
     }
     __syncthreads();
-    __syncthreads();
   }
 }
 
-// Launch configurations: wavefronts per block, row tiles per wavefront,
-// K chunk, and whether the X chunk goes through LDS (else through L1).
 // Launch configurations: wavefronts per block, interleaved 16-column A tiles
 // per wavefront, K chunk.
 struct GemmCfg {

@@ -1,15 +1,655 @@
-// Split-precision product (INT8 slices on the matrix cores); see split.h.
+// Split form of line 1 of Algorithm 4: W = A X by error-free splitting into
+// INT8 digit slices with exact INT32 products on the matrix cores (the
+// accelerator direction of Sec. 3.3; Ozaki, Ogita, Oishi and Rump 2012, with
+// integer slices as in Ootomo, Ozaki and Yokota 2024).
+//
+// Slicing.  Row i of A gets the scale 2^E_i, column j of X the scale 2^F_j,
+// E being the smallest integer with max |entry| < 2^E (0 for a zero line).
+// A scaled value v = m 2^(6-E) in (-64, 64) is peeled into s digits by
+// rounding to nearest: d = rint(v), v <- (v - d) 2^7, so every digit lies in
+// [-64, 64] and m = 2^(E-6) sum_p d_p 2^(-7(p-1)) + r with |r| <= 2^(E-7s).
+// Every step is exact in FP64.
+//
+// Product.  The digit products A_p X_q with p + q <= s + 1 (s(s+1)/2 of them)
+// are summed exactly in INT32 into s bins by t = p + q, then
+//     W_ij = 2^(E_i + F_j - 12) sum_t B_t 2^(-7(t-2))
+// is formed in double-double (Horner in 2^-7 from the smallest bin) and
+// stored as (W_hi, W_lo).  |digit products| <= 2^12, so a bin of at most s
+// products over a contraction of length L stays below s 2^12 L < 2^31 for
+// the K-split lengths the host allows.
+//
+// Layouts (bytes).  A slice unit = 16 consecutive columns of one row in one
+// plane.  A row holds nch = ceil(n/32) chunks of 32 columns; a chunk holds its
+// two halves, each as s planes of 16 bytes: row i, chunk c, half h, plane p at
+//     asl + i*(nch*32*s) + c*32*s + h*16*s + p*16.
+// X^T is stored the same way with the column j of X as the "row", the chunks
+// outermost so that one chunk of all kpad columns is contiguous:
+//     xsl + (c*kpad + j)*32*s + h*16*s + q*16.
+// Rows of A are padded to a multiple of 256 and columns to nch*32 with zero
+// digits; X^T likewise to kpad columns and nch*32 rows, so the product loop
+// needs no bounds checks.
+//
+// Matrix-core tile: v_mfma_i32_32x32x32_i8 computes C[j][i] = sum_kk
+// X^T[j][kk] A[i][kk], i.e. W^T, with the X slice in the A operand and the A
+// slice in the B operand.  Both operands of a 32-wide contraction chunk are
+// one 16-byte load per lane from the LDS tile.
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <vector>
+
+#include "dev_util.h"
 #include "split.h"
 
 namespace rfk {
 
-int split_init(SplitPlan& sp, const refine_matrix&, int, int, const Prob&, Prob*, hipStream_t) {
-  sp = SplitPlan();
-  return REFINE_EINVAL;
+typedef int v16i __attribute__((ext_vector_type(16)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+
+// v_mfma_i32_32x32x32_i8 (gfx950), checked with a lane-layout probe: lane l
+// supplies a[m = l%32][kk = 16(l/32) + b] and b[kk = 16(l/32) + b][n = l%32]
+// for the bytes b = 0..15 of its 16-byte operand; register r of the result
+// holds c[m = 8(r/4) + 4(l/32) + r%4][n = l%32].
+__device__ __forceinline__ v16i mfma_i8(v4i a, v4i b, v16i c) {
+  return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ int mfma32_row(int lane, int r) {
+  return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
 }
 
-hipError_t split_product(SplitPlan&, const Prob*, hipStream_t) { return hipErrorNotSupported; }
+// The s digits of 16 values sharing the scale 2^e, packed as s 16-byte
+// planes (byte b of plane p = digit p of value b).
+template <int S>
+__device__ __forceinline__ void digits16(const double (&v)[16], int e, u4v (&out)[S]) {
+#pragma unroll
+  for (int p = 0; p < S; ++p) out[p] = u4v{0u, 0u, 0u, 0u};
+#pragma unroll
+  for (int b = 0; b < 16; ++b) {
+    double t = ldexp(v[b], 6 - e);
+#pragma unroll
+    for (int p = 0; p < S; ++p) {
+      const double d = __builtin_rint(t);
+      out[p][b >> 2] |= ((unsigned)(int)d & 0xffu) << (8 * (b & 3));
+      t = ldexp(t - d, 7);
+    }
+  }
+}
 
-void split_free(SplitPlan& sp) { sp = SplitPlan(); }
+__device__ __forceinline__ int scale_exponent(double mx) {
+  int e = 0;
+  if (mx > 0.0) (void)frexp(mx, &e);  // mx = f 2^e, f in [1/2, 1): mx < 2^e
+  return e;
+}
+
+// ---------------------------------------------------------------------------
+// Slicing of A (once, at init)
+// ---------------------------------------------------------------------------
+
+// Row scales: one wavefront per row (rows >= n get 0).
+__global__ __launch_bounds__(256) void split_aexp_kernel(const double* __restrict__ a, int64_t lda,
+                                                         int n, int rows_pad,
+                                                         int32_t* __restrict__ aexp) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= rows_pad) return;
+  double m = 0.0;
+  if (row < n)
+    for (int c = lane; c < n; c += 64) m = fmax(m, fabs(a[(int64_t)row * lda + c]));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  if (lane == 0) aexp[row] = scale_exponent(m);
+}
+
+// Digits: one thread per 16-column unit (row, chunk, half).
+template <int S>
+__global__ __launch_bounds__(256) void split_aslice_kernel(const double* __restrict__ a,
+                                                           int64_t lda, int n, int nch,
+                                                           int rows_pad,
+                                                           const int32_t* __restrict__ aexp,
+                                                           uint8_t* __restrict__ asl) {
+  const int64_t units = (int64_t)rows_pad * nch * 2;
+  const int64_t rs = (int64_t)nch * 32 * S;
+  for (int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x; u < units;
+       u += (int64_t)gridDim.x * 256) {
+    const int row = (int)(u / (2 * nch));
+    const int cu = (int)(u - (int64_t)row * 2 * nch);  // 2 * chunk + half
+    const int col0 = cu * 16;
+    double v[16];
+#pragma unroll
+    for (int b = 0; b < 16; ++b)
+      v[b] = (row < n && col0 + b < n) ? a[(int64_t)row * lda + col0 + b] : 0.0;
+    u4v out[S];
+    digits16<S>(v, aexp[row], out);
+    u4v* dst = reinterpret_cast<u4v*>(asl + row * rs + (int64_t)cu * 16 * S);
+#pragma unroll
+    for (int p = 0; p < S; ++p) dst[p] = out[p];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Slicing of X (every step)
+// ---------------------------------------------------------------------------
+
+// Column maxima of |X|: each block reduces xrows rows and merges its maxima
+// into xmaxp[j] with an atomic maximum on the bit patterns (for non-negative
+// doubles the unsigned order of the bits is the numeric order, and a maximum
+// does not depend on the order of the merges).  xmaxp is zeroed by the
+// product kernel after use.
+__global__ __launch_bounds__(256) void split_xmax_kernel(const Prob* __restrict__ probs) {
+  const Prob& P = probs[0];
+  if (P.ctrl->stopped) return;
+  __shared__ double red[256];
+  const int k = P.k, kp = pow2ceil(k), rl = 256 / kp;
+  const int tid = threadIdx.x, j = tid % kp, r = tid / kp;
+  const int r0 = blockIdx.x * P.xrows, r1 = min(P.n, r0 + P.xrows);
+  double m = 0.0;
+  if (j < k)
+    for (int i = r0 + r; i < r1; i += rl) m = fmax(m, fabs(P.x[(int64_t)i * P.ldx + j]));
+  red[tid] = m;
+  __syncthreads();
+  for (int s = rl / 2; s > 0; s >>= 1) {
+    if (r < s) red[tid] = fmax(red[tid], red[tid + s * kp]);
+    __syncthreads();
+  }
+  if (tid < k)
+    atomicMax(reinterpret_cast<unsigned long long*>(P.xmaxp) + tid,
+              (unsigned long long)__double_as_longlong(red[tid]));
+}
+
+// Digits of X^T: one thread per 16-row unit (chunk, column, half).
+template <int S>
+__global__ __launch_bounds__(256) void split_xslice_kernel(const Prob* __restrict__ probs) {
+  const Prob& P = probs[0];
+  if (P.ctrl->stopped) return;
+  const int kpad = P.kpad, k = P.k, n = P.n;
+  const int64_t units = (int64_t)P.nch * kpad * 2;
+  const unsigned long long* mx = reinterpret_cast<const unsigned long long*>(P.xmaxp);
+  for (int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x; u < units;
+       u += (int64_t)gridDim.x * 256) {
+    const int h = (int)(u & 1);
+    const int64_t cj = u >> 1;
+    const int c = (int)(cj / kpad);
+    const int j = (int)(cj - (int64_t)c * kpad);
+    const int e = j < k ? scale_exponent(__longlong_as_double((long long)mx[j])) : 0;
+    if (c == 0 && h == 0) P.xexp[j] = e;
+    const int r0 = c * 32 + h * 16;
+    double v[16];
+#pragma unroll
+    for (int b = 0; b < 16; ++b)
+      v[b] = (j < k && r0 + b < n) ? P.x[(int64_t)(r0 + b) * P.ldx + j] : 0.0;
+    u4v out[S];
+    digits16<S>(v, e, out);
+    u4v* dst = reinterpret_cast<u4v*>(P.xsl + u * 16 * S);
+#pragma unroll
+    for (int p = 0; p < S; ++p) dst[p] = out[p];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The product
+// ---------------------------------------------------------------------------
+
+// Block = WM x WN wavefronts; wavefront (wi, wj) owns rows row0 + 32 wi ..
+// +31 of W and columns 32 wj .. +31 (BN = 32 WN = kpad).  Per 32-wide
+// contraction chunk the block stages the A tile (BM rows) and the X^T tile
+// (BN columns) of all s planes through a double-buffered LDS tile (rows padded
+// by 16 bytes, which keeps the 16-byte fragment reads of 16 lanes on distinct
+// banks), and each wavefront issues the s(s+1)/2 products of its 32 x 32 tile.
+template <int S, int WM, int WN>
+__global__ __launch_bounds__(WM* WN * 64) void gemm_split_kernel(const Prob* __restrict__ probs,
+                                                                 const GemmItem* __restrict__ items,
+                                                                 int nitems) {
+  constexpr int NW = WM * WN, NT = NW * 64;
+  constexpr int BM = 32 * WM, BN = 32 * WN;
+  constexpr int UB = 32 * S;  // bytes of one row (or column) of a chunk
+  constexpr int LS = UB + 16;
+  constexpr int TILE = (BM + BN) * LS;
+  constexpr int UA = BM * 2 * S, UX = BN * 2 * S;  // 16-byte units per chunk
+  constexpr int UPT = (UA + UX + NT - 1) / NT;
+  constexpr int TT = 32 * 33;                      // epilogue transpose tile (doubles)
+  constexpr int EPI = (NW * 2 * TT + 2 * WM * BN) * 8;
+  constexpr int SMEM = 2 * TILE > EPI ? 2 * TILE : EPI;
+  __shared__ __attribute__((aligned(16))) uint8_t smem[SMEM];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wi = wave / WN, wj = wave % WN;
+  const int l32 = lane & 31, hh = lane >> 5;
+
+  // The column maxima of this step have been consumed by the slicing pass.
+  if (blockIdx.x == 0 && tid < probs[0].kpad)
+    reinterpret_cast<unsigned long long*>(probs[0].xmaxp)[tid] = 0ull;
+
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const GemmItem item = items[it];
+    const Prob& P = probs[item.prob];
+    if (P.ctrl->stopped) continue;
+    const int n = P.n, k = P.k;
+    const int row0 = item.row0;
+    const int c0 = item.k0 >> 5, c1 = item.k1 >> 5;
+    const int64_t rs = P.asl_rs;
+    const uint8_t* __restrict__ Ab = P.asl + (int64_t)row0 * rs;
+    const uint8_t* __restrict__ Xb = P.xsl;
+
+    v16i acc[S];
+#pragma unroll
+    for (int t = 0; t < S; ++t) acc[t] = v16i{};
+
+    u4v stg[UPT];
+    auto gload = [&](int c) {
+#pragma unroll
+      for (int u = 0; u < UPT; ++u) {
+        const int e = tid + u * NT;
+        if (e < UA) {
+          const int row = e / (2 * S), part = e - row * (2 * S);
+          stg[u] = __builtin_nontemporal_load(
+              reinterpret_cast<const u4v*>(Ab + row * rs + (int64_t)c * UB + part * 16));
+        } else if (e < UA + UX) {
+          stg[u] = *reinterpret_cast<const u4v*>(Xb + (int64_t)c * BN * UB + (e - UA) * 16);
+        }
+      }
+    };
+    auto lstore = [&](uint8_t* buf) {
+#pragma unroll
+      for (int u = 0; u < UPT; ++u) {
+        const int e = tid + u * NT;
+        if (e < UA) {
+          const int row = e / (2 * S), part = e - row * (2 * S);
+          *reinterpret_cast<u4v*>(buf + row * LS + part * 16) = stg[u];
+        } else if (e < UA + UX) {
+          const int e2 = e - UA;
+          const int j = e2 / (2 * S), part = e2 - j * (2 * S);
+          *reinterpret_cast<u4v*>(buf + (BM + j) * LS + part * 16) = stg[u];
+        }
+      }
+    };
+
+    uint8_t* buf0 = smem;
+    uint8_t* buf1 = smem + TILE;
+    const int xoff = (BM + wj * 32 + l32) * LS + hh * 16 * S;
+    const int aoff = (wi * 32 + l32) * LS + hh * 16 * S;
+    gload(c0);
+    lstore(buf0);
+    __syncthreads();
+    for (int c = c0; c < c1; ++c) {
+      const bool more = c + 1 < c1;
+      const uint8_t* cur = ((c - c0) & 1) ? buf1 : buf0;
+      if (more) gload(c + 1);
+      v4i xf[S];
+#pragma unroll
+      for (int q = 0; q < S; ++q) xf[q] = *reinterpret_cast<const v4i*>(cur + xoff + q * 16);
+#pragma unroll
+      for (int p = 0; p < S; ++p) {
+        const v4i af = *reinterpret_cast<const v4i*>(cur + aoff + p * 16);
+#pragma unroll
+        for (int q = 0; q < S - p; ++q) acc[p + q] = mfma_i8(xf[q], af, acc[p + q]);
+      }
+      if (more) lstore(((c - c0) & 1) ? buf0 : buf1);
+      __syncthreads();
+    }
+
+    // Epilogue.  Register r of bin t holds B_t[j][i] for the column
+    // j = 32 wj + mfma32_row(lane, r) of W and the row i = row0 + 32 wi + l32.
+    // Each (hi, lo) goes straight to the wavefront's two LDS transpose tiles,
+    // so that 32 lanes then write 32 consecutive columns of a row.
+    const int ea = P.aexp[row0 + wi * 32 + l32];
+    double* Th = reinterpret_cast<double*>(smem) + wave * 2 * TT;
+    double* Tl = Th + TT;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      double h = (double)acc[S - 1][r], l = 0.0;
+#pragma unroll
+      for (int t = S - 2; t >= 0; --t) {
+        double s, e;
+        two_sum((double)acc[t][r], h * 0x1p-7, s, e);
+        l = __builtin_fma(l, 0x1p-7, e);
+        two_sum(s, l, h, l);
+      }
+      const int jr = mfma32_row(lane, r);
+      const int sc = ea + P.xexp[wj * 32 + jr] - 12;
+      Th[l32 * 33 + jr] = ldexp(h, sc);
+      Tl[l32 * 33 + jr] = ldexp(l, sc);
+    }
+    __builtin_amdgcn_wave_barrier();
+    const bool part = P.ksplit > 1;
+    double* __restrict__ out_hi = part ? P.swp + (int64_t)item.split * 2 * n * k : P.w;
+    double* __restrict__ out_lo = part ? out_hi + (int64_t)n * k : P.wlo;
+    double* red = reinterpret_cast<double*>(smem) + NW * 2 * TT;  // [WM][2][BN]
+    const int col = wj * 32 + l32;
+    double sxw = 0.0, sxx = 0.0;
+#pragma unroll 4
+    for (int v = 0; v < 16; ++v) {
+      const int il = 2 * v + hh;
+      const int row = row0 + wi * 32 + il;
+      if (row < n && col < k) {
+        const double w = Th[il * 33 + l32];
+        out_hi[(int64_t)row * k + col] = w;
+        out_lo[(int64_t)row * k + col] = Tl[il * 33 + l32];
+        const double x = P.x[(int64_t)row * P.ldx + col];
+        sxw = __builtin_fma(x, w, sxw);
+        sxx = __builtin_fma(x, x, sxx);
+      }
+    }
+    // Rayleigh partials (x*w_hi over the block's rows; x*x for the first K range)
+    sxw += __shfl_xor(sxw, 32);
+    sxx += __shfl_xor(sxx, 32);
+    if (lane < 32) {
+      red[(wi * 2) * BN + col] = sxw;
+      red[(wi * 2 + 1) * BN + col] = sxx;
+    }
+    __syncthreads();
+    if (tid < k) {
+      double a = 0.0, b = 0.0;
+      for (int w = 0; w < WM; ++w) {
+        a += red[(w * 2) * BN + tid];
+        b += red[(w * 2 + 1) * BN + tid];
+      }
+      double* dst = P.dpart + (int64_t)(row0 / BM * P.ksplit + item.split) * 2 * k;
+      dst[tid] = a;
+      dst[k + tid] = item.split == 0 ? b : 0.0;
+    }
+    __syncthreads();
+  }
+}
+
+// K-split sum of the (hi, lo) partials in split order, in double-double.
+__global__ __launch_bounds__(256) void split_wsum_kernel(const Prob* __restrict__ probs) {
+  const Prob& P = probs[0];
+  if (P.ctrl->stopped) return;
+  const int64_t nk = (int64_t)P.n * P.k;
+  const int ks = P.ksplit;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < nk; e += (int64_t)gridDim.x * 256) {
+    double s = P.swp[e], t = P.swp[nk + e];
+    for (int sp = 1; sp < ks; ++sp) {
+      const double* b = P.swp + (int64_t)sp * 2 * nk;
+      double s2, e2;
+      two_sum(s, b[e], s2, e2);
+      s = s2;
+      t += e2 + b[nk + e];
+    }
+    double h, l;
+    two_sum(s, t, h, l);
+    P.w[e] = h;
+    P.wlo[e] = l;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct Layout {
+  int wm, wn;
+};
+Layout layout_for(int k) {
+  const int wn = (k + 31) / 32;
+  return Layout{wn <= 2 ? 4 : 2, wn};
+}
+
+template <int S>
+hipError_t launch_product_s(const Layout& L, const Prob* probs, const GemmItem* items, int nitems,
+                            hipStream_t st) {
+#define RFK_SPLIT(WM, WN)                                                                 \
+  if (L.wm == WM && L.wn == WN) {                                                         \
+    hipLaunchKernelGGL((gemm_split_kernel<S, WM, WN>), dim3(nitems), dim3(WM * WN * 64), 0, \
+                       st, probs, items, nitems);                                         \
+    return hipGetLastError();                                                             \
+  }
+  RFK_SPLIT(4, 1)
+  RFK_SPLIT(4, 2)
+  RFK_SPLIT(2, 3)
+  RFK_SPLIT(2, 4)
+#undef RFK_SPLIT
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_product(int s, const Layout& L, const Prob* probs, const GemmItem* items,
+                          int nitems, hipStream_t st) {
+  switch (s) {
+    case 7: return launch_product_s<7>(L, probs, items, nitems, st);
+    case 8: return launch_product_s<8>(L, probs, items, nitems, st);
+    case 9: return launch_product_s<9>(L, probs, items, nitems, st);
+    case 10: return launch_product_s<10>(L, probs, items, nitems, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int S>
+hipError_t launch_slicing_s(bool a_side, const double* a, int64_t lda, int n, int nch, int rows_pad,
+                            const int32_t* aexp, uint8_t* asl, const Prob* probs, int64_t units,
+                            hipStream_t st) {
+  const int grid = (int)std::min<int64_t>((units + 255) / 256, 16384);
+  if (a_side)
+    hipLaunchKernelGGL((split_aslice_kernel<S>), dim3(grid), dim3(256), 0, st, a, lda, n, nch,
+                       rows_pad, aexp, asl);
+  else
+    hipLaunchKernelGGL((split_xslice_kernel<S>), dim3(grid), dim3(256), 0, st, probs);
+  return hipGetLastError();
+}
+
+hipError_t launch_slicing(int s, bool a_side, const double* a, int64_t lda, int n, int nch,
+                          int rows_pad, const int32_t* aexp, uint8_t* asl, const Prob* probs,
+                          int64_t units, hipStream_t st) {
+  switch (s) {
+    case 7: return launch_slicing_s<7>(a_side, a, lda, n, nch, rows_pad, aexp, asl, probs, units, st);
+    case 8: return launch_slicing_s<8>(a_side, a, lda, n, nch, rows_pad, aexp, asl, probs, units, st);
+    case 9: return launch_slicing_s<9>(a_side, a, lda, n, nch, rows_pad, aexp, asl, probs, units, st);
+    case 10: return launch_slicing_s<10>(a_side, a, lda, n, nch, rows_pad, aexp, asl, probs, units, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Longest contraction one K range may have: a bin sums at most s digit
+// products of magnitude <= 2^12 per contraction index.
+int64_t max_k_range(int s) { return ((((int64_t)1 << 31) - 1) / ((int64_t)s << 12)) / 32 * 32; }
+
+std::vector<GemmItem> split_items(int64_t n, int nch, int bm, int ks, int* nks_out) {
+  const int64_t kc = ((int64_t)nch + ks - 1) / ks * 32;
+  const int nks = (int)(((int64_t)nch * 32 + kc - 1) / kc);
+  std::vector<GemmItem> gi;
+  const int nrb = (int)((n + bm - 1) / bm);
+  for (int rb = 0; rb < nrb; ++rb)
+    for (int sp = 0; sp < nks; ++sp) {
+      GemmItem g{};
+      g.prob = 0;
+      g.row0 = rb * bm;
+      g.k0 = (int)(sp * kc);
+      g.k1 = (int)std::min<int64_t>((int64_t)nch * 32, (sp + 1) * kc);
+      g.split = sp;
+      gi.push_back(g);
+    }
+  *nks_out = nks;
+  return gi;
+}
+
+struct SplitKey {
+  int64_t n;
+  int k, s;
+  bool operator<(const SplitKey& o) const {
+    return n != o.n ? n < o.n : (k != o.k ? k < o.k : s < o.s);
+  }
+};
+std::map<SplitKey, int>& split_tune_cache() {
+  static std::map<SplitKey, int> m;
+  return m;
+}
+
+int install_items(SplitPlan& sp, int64_t n, int nch, int ks, Prob& hp, Prob* dprob) {
+  int nks = 1;
+  std::vector<GemmItem> gi = split_items(n, nch, sp.bm, ks, &nks);
+  (void)hipFree(sp.items);
+  sp.items = nullptr;
+  if (hipMalloc((void**)&sp.items, sizeof(GemmItem) * gi.size()) != hipSuccess) return REFINE_ENOMEM;
+  if (hipMemcpy(sp.items, gi.data(), sizeof(GemmItem) * gi.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return REFINE_EHIP;
+  sp.nitems = (int)gi.size();
+  sp.ks = nks;
+  hp.ksplit = nks;
+  hp.ndp = (int)((n + sp.bm - 1) / sp.bm) * nks;
+  if (hipMemcpy(dprob, &hp, sizeof(Prob), hipMemcpyHostToDevice) != hipSuccess) return REFINE_EHIP;
+  return REFINE_OK;
+}
+
+}  // namespace
+
+int split_rows_per_block(int k) { return 32 * layout_for(k).wm; }
+
+hipError_t split_product(const SplitPlan& sp, const Prob* dprob, hipStream_t st) {
+  hipError_t e;
+  hipLaunchKernelGGL(split_xmax_kernel, dim3(sp.nbx), dim3(256), 0, st, dprob);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = launch_slicing(sp.s, false, nullptr, 0, 0, 0, 0, nullptr, nullptr, dprob,
+                          (int64_t)sp.nch * sp.kpad * 2, st)) != hipSuccess)
+    return e;
+  if ((e = launch_product(sp.s, layout_for(sp.k), dprob, sp.items, sp.nitems, st)) != hipSuccess)
+    return e;
+  if (sp.ks > 1) {
+    const int64_t nk = sp.n * sp.k;
+    const int grid = (int)std::min<int64_t>((nk + 255) / 256, 4096);
+    hipLaunchKernelGGL(split_wsum_kernel, dim3(grid), dim3(256), 0, st, dprob);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+int split_init(SplitPlan& sp, const refine_matrix& A, int k, int slices, Prob& hp, Prob* dprob,
+               hipStream_t st) {
+  sp = SplitPlan();
+  if (A.kind != REFINE_DENSE || slices < SPLIT_S_MIN || slices > SPLIT_S_MAX || k < 1 || k > KMAX ||
+      A.n > SPLIT_NMAX)
+    return REFINE_EINVAL;
+  const int64_t n = A.n;
+  const int s = slices;
+  const int nch = (int)((n + 31) / 32);
+  const int kpad = (k + 31) / 32 * 32;
+  const int64_t rows_pad = (n + SPLIT_ROW_PAD - 1) / SPLIT_ROW_PAD * SPLIT_ROW_PAD;
+  const Layout L = layout_for(k);
+  sp.s = s;
+  sp.n = n;
+  sp.k = k;
+  sp.nch = nch;
+  sp.kpad = kpad;
+  sp.bm = 32 * L.wm;
+  sp.xrows = 256;
+  sp.nbx = (int)((n + sp.xrows - 1) / sp.xrows);
+  const size_t asl_bytes = (size_t)rows_pad * nch * 32 * s;
+  const size_t xsl_bytes = (size_t)nch * kpad * 32 * s;
+  if (hipMalloc((void**)&sp.asl, asl_bytes) != hipSuccess ||
+      hipMalloc((void**)&sp.aexp, sizeof(int32_t) * rows_pad) != hipSuccess ||
+      hipMalloc((void**)&sp.xsl, xsl_bytes) != hipSuccess ||
+      hipMalloc((void**)&sp.xexp, sizeof(int32_t) * kpad) != hipSuccess ||
+      hipMalloc((void**)&sp.xmaxp, sizeof(double) * kpad) != hipSuccess ||
+      hipMalloc((void**)&sp.swp, sizeof(double) * 2 * SPLIT_KS_MAX * n * k) != hipSuccess) {
+    split_free(sp);
+    return REFINE_ENOMEM;
+  }
+  hipError_t e = hipMemsetAsync(sp.xmaxp, 0, sizeof(double) * kpad, st);
+  if (e == hipSuccess) e = hipMemsetAsync(sp.xexp, 0, sizeof(int32_t) * kpad, st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(split_aexp_kernel, dim3((unsigned)((rows_pad + 3) / 4)), dim3(256), 0, st,
+                       A.a, A.lda, (int)n, (int)rows_pad, sp.aexp);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess)
+    e = launch_slicing(s, true, A.a, A.lda, (int)n, nch, (int)rows_pad, sp.aexp, sp.asl, nullptr,
+                       rows_pad * nch * 2, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    split_free(sp);
+    return REFINE_EHIP;
+  }
+  hp.asl = sp.asl;
+  hp.asl_rs = (int64_t)nch * 32 * s;
+  hp.aexp = sp.aexp;
+  hp.xsl = sp.xsl;
+  hp.xexp = sp.xexp;
+  hp.xmaxp = sp.xmaxp;
+  hp.swp = sp.swp;
+  hp.nch = nch;
+  hp.kpad = kpad;
+  hp.nbx = sp.nbx;
+  hp.xrows = sp.xrows;
+
+  // K split: REFINE_SPLIT_KS forces one; otherwise time 1, 2, 4, 8 (those
+  // whose K range fits the exact INT32 bins) once per shape and process.
+  const int64_t kmax_range = max_k_range(s);
+  auto fits = [&](int ks) { return ((int64_t)nch + ks - 1) / ks * 32 <= kmax_range; };
+  int best_ks = 0;
+  if (const char* env = getenv("REFINE_SPLIT_KS")) {
+    const int ks = atoi(env);
+    if (ks >= 1 && ks <= SPLIT_KS_MAX && fits(ks)) best_ks = ks;
+  }
+  const SplitKey key{n, k, s};
+  if (!best_ks) {
+    auto hit = split_tune_cache().find(key);
+    if (hit != split_tune_cache().end()) best_ks = hit->second;
+  }
+  if (!best_ks) {
+    // time on a zero X (the workspace copy of the update)
+    double* const saved_x = hp.x;
+    const int64_t saved_ldx = hp.ldx;
+    hp.x = hp.xn;
+    hp.ldx = k;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+      split_free(sp);
+      return REFINE_EHIP;
+    }
+    float best = 1e30f;
+    for (int ks = 1; ks <= SPLIT_KS_MAX; ks *= 2) {
+      if (!fits(ks)) continue;
+      int rc = install_items(sp, n, nch, ks, hp, dprob);
+      if (rc != REFINE_OK) {
+        split_free(sp);
+        return rc;
+      }
+      float t = 0.f;
+      e = split_product(sp, dprob, st);  // warm-up
+      if (e == hipSuccess) e = hipEventRecord(e0, st);
+      for (int r = 0; r < 3 && e == hipSuccess; ++r) e = split_product(sp, dprob, st);
+      if (e == hipSuccess) e = hipEventRecord(e1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+      if (e != hipSuccess) {
+        split_free(sp);
+        return REFINE_EHIP;
+      }
+      if (getenv("REFINE_LOG") && atoi(getenv("REFINE_LOG")) >= 2)
+        fprintf(stderr, "refine: tune split n=%lld k=%d s=%d ks %d: %.1f us\n", (long long)n, k, s,
+                ks, t * 1000.f / 3.f);
+      if (t < best) {
+        best = t;
+        best_ks = ks;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    hp.x = saved_x;
+    hp.ldx = saved_ldx;
+    sp.ms = best / 3.f;
+    split_tune_cache()[key] = best_ks;
+    if (getenv("REFINE_LOG"))
+      fprintf(stderr, "refine: split product n=%lld k=%d s=%d: K split %d, %.1f us\n",
+              (long long)n, k, s, best_ks, best * 1000.f / 3.f);
+  }
+  if (!best_ks) {
+    split_free(sp);
+    return REFINE_EINVAL;
+  }
+  return install_items(sp, n, nch, best_ks, hp, dprob);
+}
+
+void split_free(SplitPlan& sp) {
+  (void)hipFree(sp.asl);
+  (void)hipFree(sp.aexp);
+  (void)hipFree(sp.xsl);
+  (void)hipFree(sp.xexp);
+  (void)hipFree(sp.xmaxp);
+  (void)hipFree(sp.swp);
+  (void)hipFree(sp.items);
+  sp = SplitPlan();
+}
 
 }  // namespace rfk

@@ -118,8 +118,9 @@ constexpr int KSPLIT_MAX = 16;
 
 // Upper bound of the Rayleigh partials: per row block of the smallest
 // product tile (64 rows) and K split, or per streaming row block.
-int64_t dpart_entries(int64_t n, const Shape& s) {
-  return std::max<int64_t>((int64_t)iceil(n, 64) * std::max(1, s.ksplit), s.nrb);
+int64_t dpart_entries(int64_t n, const Shape& s, bool split) {
+  const int ks = split ? SPLIT_KS_MAX : std::max(1, s.ksplit);
+  return std::max<int64_t>((int64_t)iceil(n, 64) * ks, s.nrb);
 }
 
 template <class T>
@@ -320,7 +321,7 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
     if (pl.split) b += align_up(nk);                     // wlo
     b += align_up(nk);                                   // xn
     b += align_up((size_t)s.nrb * 5 * k * sizeof(double));
-    b += align_up((size_t)dpart_entries(n, s) * 2 * k * sizeof(double));
+    b += align_up((size_t)dpart_entries(n, s, pl.split) * 2 * k * sizeof(double));
     b += align_up((size_t)s.ngb * (2 * k * k + k) * sizeof(double));
     b += align_up((size_t)KK_COUNT * k * k * sizeof(double));
     b += align_up((size_t)VEC_COUNT * k * sizeof(double));
@@ -378,7 +379,7 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
     base += align_up((size_t)s.nrb * 5 * k * sizeof(double));
     P.dpart = (double*)base;
     P.ndp = s.nrb;  // CSR: one partial per row block; dense: set with the product's items
-    base += align_up((size_t)dpart_entries(n, s) * 2 * k * sizeof(double));
+    base += align_up((size_t)dpart_entries(n, s, pl.split) * 2 * k * sizeof(double));
     P.gpart = (double*)base;
     base += align_up((size_t)s.ngb * (2 * k * k + k) * sizeof(double));
     P.kk = (double*)base;
@@ -433,7 +434,7 @@ hipError_t enqueue_step(Plan& pl, hipStream_t st) {
         return e;
     }
     for (int p = 0; p < np; ++p)
-      if (pl.hprob[p].ksplit > 1 &&
+      if (!pl.split && pl.hprob[p].ksplit > 1 &&
           (e = launch_wsum(pl.dprob, p, pl.hprob[p].n, pl.hprob[p].k, st)) != hipSuccess)
         return e;
   }
@@ -504,7 +505,9 @@ int validate_matrix(const refine_matrix* A, int32_t k, const refine_options& opt
     return REFINE_EINVAL;
   }
   if (opt.precision != REFINE_FP64 && opt.precision != REFINE_SPLIT_INT8) return REFINE_EINVAL;
-  if (opt.precision == REFINE_SPLIT_INT8 && A->n > SPLIT_NMAX) return REFINE_EINVAL;
+  if (opt.precision == REFINE_SPLIT_INT8 &&
+      (A->n > SPLIT_NMAX || (opt.slices != 0 && (opt.slices < SPLIT_S_MIN || opt.slices > SPLIT_S_MAX))))
+    return REFINE_EINVAL;
   if (!(opt.delta_c >= 0.0)) return REFINE_EINVAL;
   return REFINE_OK;
 }
@@ -625,8 +628,8 @@ int refine_init(refine_ctx** out, const refine_matrix* A, int32_t k, const refin
   std::vector<int> ks{k};
   rc = build_plan(c->plan, As, ks, opt, {c->mu}, {c->delta}, {c->norm_used});
   if (rc == REFINE_OK && c->plan.split) {
-    rc = split_init(c->plan.sp, *A, k, opt.slices > 0 ? opt.slices : 8, c->plan.hprob[0], c->plan.dprob,
-                    c->stream);
+    rc = split_init(c->plan.sp, *A, k, opt.slices > 0 ? opt.slices : SPLIT_S_DEFAULT, c->plan.hprob[0],
+                    c->plan.dprob, c->stream);
   }
   if (rc == REFINE_OK) rc = capture_graph(c->plan);
   if (rc == REFINE_OK && launch_ctrl_reset(c->plan.dprob, 1, 0, 0.0, c->stream) != hipSuccess)
@@ -872,9 +875,9 @@ int refine_batch_destroy(refine_batch* b) {
 // of a single-problem context, in the order w, wlo, xn, kk, vec, ctrl, wp,
 // part, gpart.  Used by the tests to inspect intermediate quantities.
 extern "C" int refine_debug_workspace(const refine_ctx* c, void** out, int32_t count) {
-  if (!c || !out || count < 9) return REFINE_EINVAL;
+  if (!c || !out || count < 1) return REFINE_EINVAL;
   const Prob& P = c->plan.hprob[0];
   void* v[9] = {P.w, P.wlo, P.xn, P.kk, P.vec, P.ctrl, P.wp, P.part, P.gpart};
-  for (int i = 0; i < 9; ++i) out[i] = v[i];
+  for (int i = 0; i < 9 && i < count; ++i) out[i] = v[i];
   return REFINE_OK;
 }

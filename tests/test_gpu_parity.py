@@ -31,7 +31,7 @@ def _dev(a):
 
 
 def _compare_steps(A_np, X0, steps, *, norm_a, mu=0.0, target="largest_abs", shift=0.0,
-                   A_dev=None, csr=None, tol=TOL, dd=False, **opts):
+                   A_dev=None, csr=None, tol=TOL, dd=False, split=0, **opts):
     rf = _lib()
     A_host = oracle.Csr(csr.n, csr.row_ptr, csr.col_idx, csr.val) if csr is not None else A_np
     if csr is not None:
@@ -47,7 +47,7 @@ def _compare_steps(A_np, X0, steps, *, norm_a, mu=0.0, target="largest_abs", shi
     for s in range(steps):
         st = ctx.step(Xg)
         assert st.status == rf.OK, rf.status_string(st.status)
-        r = oracle.refine_step(A_host, Xo, mu=info["mu"], norm_a=norm_a, dd=dd)
+        r = oracle.refine_step(A_host, Xo, mu=info["mu"], norm_a=norm_a, dd=dd, split=split)
         assert r.status == 0
         Xo = r.X
         got = Xg.cpu().numpy()
@@ -196,3 +196,77 @@ def test_every_product_configuration(cfg, monkeypatch):
         monkeypatch.setenv("REFINE_GEMM", "%d,%d" % (cfg, ks))
         P = synth.dense_spectrum(n, k, 4000 + n)
         _compare_steps(P.A, P.X0, 1, norm_a=1.0)
+
+
+# --------------------------------------------------------------------------
+# Split form of the product (INT8 slices on the matrix cores)
+# --------------------------------------------------------------------------
+def _split_product_check(P, n, k, slices, ks, monkeypatch):
+    """One split-mode step: the product W = A X of the step's input, read
+    back as (W_hi, W_lo), equals the oracle's split product (exact binned
+    digit products) up to the double-double rounding of the recombination."""
+    rf = _lib()
+    monkeypatch.setenv("REFINE_SPLIT_KS", str(ks))
+    ctx = rf.RefineContext(_dev(P.A), k, norm_a=1.0, precision="split_int8", slices=slices)
+    X = _dev(P.X0).clone()
+    st = ctx.step(X)
+    assert st.status == rf.OK, rf.status_string(st.status)
+    wh, wl = ctx.debug_product()
+    ctx.close()
+    oh, ol = oracle.matmul_split(P.A, P.X0, slices)
+    d = (wh.cpu().numpy() - oh) + (wl.cpu().numpy() - ol)
+    scale = np.max(np.abs(oh))
+    err = float(np.max(np.abs(d)))
+    assert err <= 2.0 ** -100 * scale, "n=%d k=%d s=%d ks=%d: |dW| = %.3e (max|W| %.3e)" % (
+        n, k, slices, ks, err, scale)
+
+
+@pytest.mark.parametrize("n,k,ks", [(777, 13, 1), (1000, 64, 2), (1280, 33, 4), (640, 128, 1),
+                                    (300, 1, 1), (513, 96, 8)])
+def test_split_product_matches_oracle(n, k, ks, monkeypatch):
+    """Ragged n (not a multiple of the 32-wide chunks or of the row blocks),
+    every column-tile layout (k <= 32, 64, 96, 128) and K splits 1-8."""
+    P = synth.dense_spectrum(n, k, 5000 + n)
+    _split_product_check(P, n, k, 9, ks, monkeypatch)
+
+
+@pytest.mark.parametrize("slices", [7, 8, 10])
+def test_split_product_other_slice_counts(slices, monkeypatch):
+    P = synth.dense_spectrum(700, 40, 5100 + slices)
+    _split_product_check(P, 700, 40, slices, 2, monkeypatch)
+
+
+@pytest.mark.parametrize("n,k", [(777, 13), (640, 64), (513, 17)])
+def test_split_steps_match_oracle(n, k):
+    """Whole split-mode steps against the oracle's split-mode steps (the same
+    product definition), and against its Dot2 steps."""
+    P = synth.dense_spectrum(n, k, 5200 + n)
+    worst, X = _compare_steps(P.A, P.X0, 3, norm_a=1.0, split=9, precision="split_int8")
+    Xd, _ = oracle.refine(P.A, P.X0, 3, norm_a=1.0, dd=True)
+    assert np.max(np.abs(align_signs(X, Xd) - Xd)) <= TOL
+
+
+def test_split_uniform_top_reduced():
+    """The uniform spectrum with 128 targets 1e-3 apart (n = 2048, k = 128):
+    two split-mode steps against the double-double oracle."""
+    P = synth.dense_uniform_top(2048, 128)
+    worst, X = _compare_steps(P.A, P.X0, 2, norm_a=1.0, split=9, precision="split_int8")
+    Xd, _ = oracle.refine(P.A, P.X0, 2, norm_a=1.0, dd=True)
+    assert np.max(np.abs(align_signs(X, Xd) - Xd)) <= TOL
+
+
+def test_split_invalid_arguments():
+    rf = _lib()
+    A = _dev(np.eye(64))
+    for bad in (6, 11, -1):
+        with pytest.raises(rf.RefineError) as e:
+            rf.RefineContext(A, 4, precision="split_int8", slices=bad)
+        assert e.value.status == rf.EINVAL
+    L = synth.laplacian3d(4, seed=1)
+    C = rf.CsrMatrix(L.n, _dev(L.row_ptr), _dev(L.col_idx), _dev(L.val))
+    with pytest.raises(rf.RefineError) as e:
+        rf.RefineContext(C, 4, precision="split_int8")
+    assert e.value.status == rf.EINVAL
+    with pytest.raises(rf.RefineError) as e:
+        rf.RefineBatch([A, A], [4, 4], precision="split_int8")
+    assert e.value.status == rf.EINVAL
