@@ -127,6 +127,21 @@ __device__ __forceinline__ v4d mfma_f64(double a, double b, v4d c) {
 // Row of the 16x16 result held in register r by a lane of group g = l/16.
 __device__ __forceinline__ int mfma_row(int g, int r) { return g + 4 * r; }
 
+// Global-memory views of generic pointers.  A load or store through a
+// generic pointer (every pointer read from a Prob) compiles to a FLAT
+// instruction, which also counts against the LDS wait counter: a kernel that
+// waits for its LDS reads then waits for its global prefetches as well.  The
+// global forms keep the two apart.
+#define RFK_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ const RFK_GLOBAL T* gld(const T* p) {
+  return (const RFK_GLOBAL T*)p;
+}
+template <class T>
+__device__ __forceinline__ RFK_GLOBAL T* gst(T* p) {
+  return (RFK_GLOBAL T*)p;
+}
+
 // Exact transformations used by the accurate residual (Dekker / Knuth).
 __device__ __forceinline__ void two_prod(double a, double b, double& p, double& e) {
   p = a * b;

@@ -87,18 +87,18 @@ __global__ __launch_bounds__(WAVES * 64) void gemm_f64_t_kernel(const Prob* __re
           const double* p = A + (int64_t)kk * lda + jl;
           if (VECA && RT == 2) {
             typedef double v2d __attribute__((ext_vector_type(2)));
-            const v2d v = __builtin_nontemporal_load(reinterpret_cast<const v2d*>(p));
+            const v2d v = __builtin_nontemporal_load(gld(reinterpret_cast<const v2d*>(p)));
             dst[s][0] = v.x;
             dst[s][RT - 1] = v.y;
           } else {
 #pragma unroll
-            for (int rt = 0; rt < RT; ++rt) dst[s][rt] = __builtin_nontemporal_load(p + rt);
+            for (int rt = 0; rt < RT; ++rt) dst[s][rt] = __builtin_nontemporal_load(gld(p + rt));
           }
         } else {
           const bool kok = kk < k1;
           const double* p = A + (int64_t)(kok ? kk : k0) * lda;
 #pragma unroll
-          for (int rt = 0; rt < RT; ++rt) dst[s][rt] = (kok && jl + rt < n) ? p[jl + rt] : 0.0;
+          for (int rt = 0; rt < RT; ++rt) dst[s][rt] = (kok && jl + rt < n) ? *gld(p + jl + rt) : 0.0;
         }
       }
     };
@@ -108,7 +108,7 @@ __global__ __launch_bounds__(WAVES * 64) void gemm_f64_t_kernel(const Prob* __re
         const int e = tid + s * NT;
         const int kr = e / BN, col = e - kr * BN;
         double v = 0.0;
-        if (e < KC * BN && kb + kr < k1 && col < k) v = X[(int64_t)(kb + kr) * ldx + col];
+        if (e < KC * BN && kb + kr < k1 && col < k) v = *gld(X + (int64_t)(kb + kr) * ldx + col);
         bst[s] = v;
       }
     };
@@ -180,8 +180,8 @@ __global__ __launch_bounds__(WAVES * 64) void gemm_f64_t_kernel(const Prob* __re
           for (int u = 0; u < 4; ++u) {
             const int col = ct * 16 + 4 * tq + u;
             if (col < k) {
-              out[(int64_t)row * k + col] = v[u];
-              const double x = X[(int64_t)row * ldx + col];
+              *gst(out + (int64_t)row * k + col) = v[u];
+              const double x = *gld(X + (int64_t)row * ldx + col);
               sxw[u] = __builtin_fma(x, v[u], sxw[u]);
               sxx[u] = __builtin_fma(x, x, sxx[u]);
             }
@@ -213,8 +213,8 @@ __global__ __launch_bounds__(WAVES * 64) void gemm_f64_t_kernel(const Prob* __re
         b += red[(w * 2 + 1) * BN + tid];
       }
       double* dst = P.dpart + (int64_t)(item.row0 / BM * P.ksplit + item.split) * 2 * k;
-      dst[tid] = a;
-      dst[k + tid] = item.split == 0 ? b : 0.0;
+      *gst(dst + tid) = a;
+      *gst(dst + k + tid) = item.split == 0 ? b : 0.0;
     }
     __syncthreads();
   }

@@ -196,7 +196,7 @@ __global__ __launch_bounds__(256) void split_xslice_kernel(const Prob* __restric
 // (BN columns) of all s planes through a double-buffered LDS tile (rows padded
 // by 16 bytes, which keeps the 16-byte fragment reads of 16 lanes on distinct
 // banks), and each wavefront issues the s(s+1)/2 products of its 32 x 32 tile.
-template <int S, int WM, int WN>
+template <int S, int WM, int WN, bool DMA>
 __global__ __launch_bounds__(WM* WN * 64) void gemm_split_kernel(const Prob* __restrict__ probs,
                                                                  const GemmItem* __restrict__ items,
                                                                  int nitems) {
@@ -206,7 +206,13 @@ __global__ __launch_bounds__(WM* WN * 64) void gemm_split_kernel(const Prob* __r
   constexpr int LS = UB + 16;
   constexpr int TILE = (BM + BN) * LS;
   constexpr int UA = BM * 2 * S, UX = BN * 2 * S;  // 16-byte units per chunk
-  constexpr int UPT = (UA + UX + NT - 1) / NT;
+  constexpr int UPT = DMA ? 1 : (UA + UX + NT - 1) / NT;
+  // direct-to-LDS form: 16-byte slots of the tile (one padding slot per row),
+  // 64 consecutive slots per wavefront instruction
+  constexpr int SROW = 2 * S + 1;
+  constexpr int TSLOTS = (BM + BN) * SROW;
+  constexpr int NINS = (TSLOTS + 63) / 64;
+  constexpr int IPW = (NINS + NW - 1) / NW;
   constexpr int TT = 32 * 33;                      // epilogue transpose tile (doubles)
   constexpr int EPI = (NW * 2 * TT + 2 * WM * BN) * 8;
   constexpr int SMEM = 2 * TILE > EPI ? 2 * TILE : EPI;
@@ -243,9 +249,9 @@ __global__ __launch_bounds__(WM* WN * 64) void gemm_split_kernel(const Prob* __r
         if (e < UA) {
           const int row = e / (2 * S), part = e - row * (2 * S);
           stg[u] = __builtin_nontemporal_load(
-              reinterpret_cast<const u4v*>(Ab + row * rs + (int64_t)c * UB + part * 16));
+              gld(reinterpret_cast<const u4v*>(Ab + row * rs + (int64_t)c * UB + part * 16)));
         } else if (e < UA + UX) {
-          stg[u] = *reinterpret_cast<const u4v*>(Xb + (int64_t)c * BN * UB + (e - UA) * 16);
+          stg[u] = *gld(reinterpret_cast<const u4v*>(Xb + (int64_t)c * BN * UB + (e - UA) * 16));
         }
       }
     };
@@ -264,17 +270,47 @@ __global__ __launch_bounds__(WM* WN * 64) void gemm_split_kernel(const Prob* __r
       }
     };
 
+    // DMA: each lane copies one 16-byte slot from global memory straight into
+    // the LDS tile (lane l of a wavefront instruction writes slot 64 ii + l);
+    // completion is awaited (vmcnt) before the barrier that publishes it.
+    auto dma = [&](uint8_t* buf, int c) {
+#pragma unroll
+      for (int i = 0; i < IPW; ++i) {
+        const int ii = wave + i * NW;
+        if (ii < NINS) {
+          const int f = ii * 64 + lane;
+          const int row = f / SROW, part = f - row * SROW;
+          if (f < TSLOTS && part < 2 * S) {
+            const uint8_t* src = row < BM ? Ab + row * rs + (int64_t)c * UB + part * 16
+                                          : Xb + ((int64_t)c * BN + (row - BM)) * UB + part * 16;
+            __builtin_amdgcn_global_load_lds(
+                (const RFK_GLOBAL void*)src,
+                (__attribute__((address_space(3))) void*)(buf + ii * 1024), 16, 0, 0);
+          }
+        }
+      }
+    };
     uint8_t* buf0 = smem;
     uint8_t* buf1 = smem + TILE;
     const int xoff = (BM + wj * 32 + l32) * LS + hh * 16 * S;
     const int aoff = (wi * 32 + l32) * LS + hh * 16 * S;
-    gload(c0);
-    lstore(buf0);
+    if (DMA) {
+      dma(buf0, c0);
+      __builtin_amdgcn_s_waitcnt(0);
+    } else {
+      gload(c0);
+      lstore(buf0);
+    }
     __syncthreads();
     for (int c = c0; c < c1; ++c) {
       const bool more = c + 1 < c1;
       const uint8_t* cur = ((c - c0) & 1) ? buf1 : buf0;
-      if (more) gload(c + 1);
+      if (more) {
+        if (DMA)
+          dma(((c - c0) & 1) ? buf0 : buf1, c + 1);
+        else
+          gload(c + 1);
+      }
       v4i xf[S];
 #pragma unroll
       for (int q = 0; q < S; ++q) xf[q] = *reinterpret_cast<const v4i*>(cur + xoff + q * 16);
@@ -284,7 +320,10 @@ __global__ __launch_bounds__(WM* WN * 64) void gemm_split_kernel(const Prob* __r
 #pragma unroll
         for (int q = 0; q < S - p; ++q) acc[p + q] = mfma_i8(xf[q], af, acc[p + q]);
       }
-      if (more) lstore(((c - c0) & 1) ? buf0 : buf1);
+      if (DMA)
+        __builtin_amdgcn_s_waitcnt(0);
+      else if (more)
+        lstore(((c - c0) & 1) ? buf0 : buf1);
       __syncthreads();
     }
 
@@ -292,7 +331,7 @@ __global__ __launch_bounds__(WM* WN * 64) void gemm_split_kernel(const Prob* __r
     // j = 32 wj + mfma32_row(lane, r) of W and the row i = row0 + 32 wi + l32.
     // Each (hi, lo) goes straight to the wavefront's two LDS transpose tiles,
     // so that 32 lanes then write 32 consecutive columns of a row.
-    const int ea = P.aexp[row0 + wi * 32 + l32];
+    const int ea = *gld(P.aexp + row0 + wi * 32 + l32);
     double* Th = reinterpret_cast<double*>(smem) + wave * 2 * TT;
     double* Tl = Th + TT;
 #pragma unroll
@@ -306,7 +345,7 @@ __global__ __launch_bounds__(WM* WN * 64) void gemm_split_kernel(const Prob* __r
         two_sum(s, l, h, l);
       }
       const int jr = mfma32_row(lane, r);
-      const int sc = ea + P.xexp[wj * 32 + jr] - 12;
+      const int sc = ea + *gld(P.xexp + wj * 32 + jr) - 12;
       Th[l32 * 33 + jr] = ldexp(h, sc);
       Tl[l32 * 33 + jr] = ldexp(l, sc);
     }
@@ -323,9 +362,9 @@ __global__ __launch_bounds__(WM* WN * 64) void gemm_split_kernel(const Prob* __r
       const int row = row0 + wi * 32 + il;
       if (row < n && col < k) {
         const double w = Th[il * 33 + l32];
-        out_hi[(int64_t)row * k + col] = w;
-        out_lo[(int64_t)row * k + col] = Tl[il * 33 + l32];
-        const double x = P.x[(int64_t)row * P.ldx + col];
+        *gst(out_hi + (int64_t)row * k + col) = w;
+        *gst(out_lo + (int64_t)row * k + col) = Tl[il * 33 + l32];
+        const double x = *gld(P.x + (int64_t)row * P.ldx + col);
         sxw = __builtin_fma(x, w, sxw);
         sxx = __builtin_fma(x, x, sxx);
       }
@@ -345,8 +384,8 @@ __global__ __launch_bounds__(WM* WN * 64) void gemm_split_kernel(const Prob* __r
         b += red[(w * 2 + 1) * BN + tid];
       }
       double* dst = P.dpart + (int64_t)(row0 / BM * P.ksplit + item.split) * 2 * k;
-      dst[tid] = a;
-      dst[k + tid] = item.split == 0 ? b : 0.0;
+      *gst(dst + tid) = a;
+      *gst(dst + k + tid) = item.split == 0 ? b : 0.0;
     }
     __syncthreads();
   }
@@ -389,13 +428,17 @@ Layout layout_for(int k) {
 }
 
 template <int S>
-hipError_t launch_product_s(const Layout& L, const Prob* probs, const GemmItem* items, int nitems,
-                            hipStream_t st) {
-#define RFK_SPLIT(WM, WN)                                                                 \
-  if (L.wm == WM && L.wn == WN) {                                                         \
-    hipLaunchKernelGGL((gemm_split_kernel<S, WM, WN>), dim3(nitems), dim3(WM * WN * 64), 0, \
-                       st, probs, items, nitems);                                         \
-    return hipGetLastError();                                                             \
+hipError_t launch_product_s(const Layout& L, int variant, const Prob* probs, const GemmItem* items,
+                            int nitems, hipStream_t st) {
+#define RFK_SPLIT(WM, WN)                                                                      \
+  if (L.wm == WM && L.wn == WN) {                                                              \
+    if (variant == 1)                                                                          \
+      hipLaunchKernelGGL((gemm_split_kernel<S, WM, WN, true>), dim3(nitems), dim3(WM * WN * 64), \
+                         0, st, probs, items, nitems);                                         \
+    else                                                                                       \
+      hipLaunchKernelGGL((gemm_split_kernel<S, WM, WN, false>), dim3(nitems),                  \
+                         dim3(WM * WN * 64), 0, st, probs, items, nitems);                     \
+    return hipGetLastError();                                                                  \
   }
   RFK_SPLIT(4, 1)
   RFK_SPLIT(4, 2)
@@ -405,13 +448,13 @@ hipError_t launch_product_s(const Layout& L, const Prob* probs, const GemmItem* 
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_product(int s, const Layout& L, const Prob* probs, const GemmItem* items,
-                          int nitems, hipStream_t st) {
+hipError_t launch_product(int s, const Layout& L, int variant, const Prob* probs,
+                          const GemmItem* items, int nitems, hipStream_t st) {
   switch (s) {
-    case 7: return launch_product_s<7>(L, probs, items, nitems, st);
-    case 8: return launch_product_s<8>(L, probs, items, nitems, st);
-    case 9: return launch_product_s<9>(L, probs, items, nitems, st);
-    case 10: return launch_product_s<10>(L, probs, items, nitems, st);
+    case 7: return launch_product_s<7>(L, variant, probs, items, nitems, st);
+    case 8: return launch_product_s<8>(L, variant, probs, items, nitems, st);
+    case 9: return launch_product_s<9>(L, variant, probs, items, nitems, st);
+    case 10: return launch_product_s<10>(L, variant, probs, items, nitems, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -471,8 +514,8 @@ struct SplitKey {
     return n != o.n ? n < o.n : (k != o.k ? k < o.k : s < o.s);
   }
 };
-std::map<SplitKey, int>& split_tune_cache() {
-  static std::map<SplitKey, int> m;
+std::map<SplitKey, std::pair<int, int>>& split_tune_cache() {
+  static std::map<SplitKey, std::pair<int, int>> m;
   return m;
 }
 
@@ -503,7 +546,8 @@ hipError_t split_product(const SplitPlan& sp, const Prob* dprob, hipStream_t st)
   if ((e = launch_slicing(sp.s, false, nullptr, 0, 0, 0, 0, nullptr, nullptr, dprob,
                           (int64_t)sp.nch * sp.kpad * 2, st)) != hipSuccess)
     return e;
-  if ((e = launch_product(sp.s, layout_for(sp.k), dprob, sp.items, sp.nitems, st)) != hipSuccess)
+  if ((e = launch_product(sp.s, layout_for(sp.k), sp.variant, dprob, sp.items, sp.nitems, st)) !=
+      hipSuccess)
     return e;
   if (sp.ks > 1) {
     const int64_t nk = sp.n * sp.k;
@@ -572,19 +616,27 @@ int split_init(SplitPlan& sp, const refine_matrix& A, int k, int slices, Prob& h
   hp.nbx = sp.nbx;
   hp.xrows = sp.xrows;
 
-  // K split: REFINE_SPLIT_KS forces one; otherwise time 1, 2, 4, 8 (those
-  // whose K range fits the exact INT32 bins) once per shape and process.
+  // K split and tile-loading variant: REFINE_SPLIT_KS="ks[,variant]" forces
+  // them; otherwise every K split of 1, 2, 4, 8 whose K range fits the exact
+  // INT32 bins is timed with both variants, once per shape and process.
   const int64_t kmax_range = max_k_range(s);
   auto fits = [&](int ks) { return ((int64_t)nch + ks - 1) / ks * 32 <= kmax_range; };
-  int best_ks = 0;
+  int best_ks = 0, best_var = 0;
   if (const char* env = getenv("REFINE_SPLIT_KS")) {
-    const int ks = atoi(env);
-    if (ks >= 1 && ks <= SPLIT_KS_MAX && fits(ks)) best_ks = ks;
+    int ks = 0, var = 0;
+    const int got = sscanf(env, "%d,%d", &ks, &var);
+    if (got >= 1 && ks >= 1 && ks <= SPLIT_KS_MAX && fits(ks) && var >= 0 && var <= 1) {
+      best_ks = ks;
+      best_var = got == 2 ? var : 0;
+    }
   }
   const SplitKey key{n, k, s};
   if (!best_ks) {
     auto hit = split_tune_cache().find(key);
-    if (hit != split_tune_cache().end()) best_ks = hit->second;
+    if (hit != split_tune_cache().end()) {
+      best_ks = hit->second.first;
+      best_var = hit->second.second;
+    }
   }
   if (!best_ks) {
     // time on a zero X (the workspace copy of the update)
@@ -598,46 +650,50 @@ int split_init(SplitPlan& sp, const refine_matrix& A, int k, int slices, Prob& h
       return REFINE_EHIP;
     }
     float best = 1e30f;
-    for (int ks = 1; ks <= SPLIT_KS_MAX; ks *= 2) {
-      if (!fits(ks)) continue;
-      int rc = install_items(sp, n, nch, ks, hp, dprob);
-      if (rc != REFINE_OK) {
-        split_free(sp);
-        return rc;
+    for (int var = 0; var <= 1; ++var)
+      for (int ks = 1; ks <= SPLIT_KS_MAX; ks *= 2) {
+        if (!fits(ks)) continue;
+        sp.variant = var;
+        int rc = install_items(sp, n, nch, ks, hp, dprob);
+        if (rc != REFINE_OK) {
+          split_free(sp);
+          return rc;
+        }
+        float t = 0.f;
+        e = split_product(sp, dprob, st);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        for (int r = 0; r < 3 && e == hipSuccess; ++r) e = split_product(sp, dprob, st);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        if (e != hipSuccess) {
+          split_free(sp);
+          return REFINE_EHIP;
+        }
+        if (getenv("REFINE_LOG") && atoi(getenv("REFINE_LOG")) >= 2)
+          fprintf(stderr, "refine: tune split n=%lld k=%d s=%d variant %d ks %d: %.1f us\n",
+                  (long long)n, k, s, var, ks, t * 1000.f / 3.f);
+        if (t < best) {
+          best = t;
+          best_ks = ks;
+          best_var = var;
+        }
       }
-      float t = 0.f;
-      e = split_product(sp, dprob, st);  // warm-up
-      if (e == hipSuccess) e = hipEventRecord(e0, st);
-      for (int r = 0; r < 3 && e == hipSuccess; ++r) e = split_product(sp, dprob, st);
-      if (e == hipSuccess) e = hipEventRecord(e1, st);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
-      if (e != hipSuccess) {
-        split_free(sp);
-        return REFINE_EHIP;
-      }
-      if (getenv("REFINE_LOG") && atoi(getenv("REFINE_LOG")) >= 2)
-        fprintf(stderr, "refine: tune split n=%lld k=%d s=%d ks %d: %.1f us\n", (long long)n, k, s,
-                ks, t * 1000.f / 3.f);
-      if (t < best) {
-        best = t;
-        best_ks = ks;
-      }
-    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     hp.x = saved_x;
     hp.ldx = saved_ldx;
     sp.ms = best / 3.f;
-    split_tune_cache()[key] = best_ks;
+    split_tune_cache()[key] = {best_ks, best_var};
     if (getenv("REFINE_LOG"))
-      fprintf(stderr, "refine: split product n=%lld k=%d s=%d: K split %d, %.1f us\n",
-              (long long)n, k, s, best_ks, best * 1000.f / 3.f);
+      fprintf(stderr, "refine: split product n=%lld k=%d s=%d: variant %d, K split %d, %.1f us\n",
+              (long long)n, k, s, best_var, best_ks, best * 1000.f / 3.f);
   }
   if (!best_ks) {
     split_free(sp);
     return REFINE_EINVAL;
   }
+  sp.variant = best_var;
   return install_items(sp, n, nch, best_ks, hp, dprob);
 }
 

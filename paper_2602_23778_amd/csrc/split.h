@@ -27,6 +27,7 @@ constexpr int SPLIT_ROW_PAD = 256;
 struct SplitPlan {
   int s = 0;                  // slices per operand
   int ks = 1;                 // K split
+  int variant = 0;            // 0: tiles staged through registers, 1: direct-to-LDS loads
   int bm = 0;                 // rows per block of the product
   int64_t n = 0;
   int k = 0;

@@ -201,12 +201,14 @@ def test_every_product_configuration(cfg, monkeypatch):
 # --------------------------------------------------------------------------
 # Split form of the product (INT8 slices on the matrix cores)
 # --------------------------------------------------------------------------
-def _split_product_check(P, n, k, slices, ks, monkeypatch):
+def _split_product_check(P, n, k, slices, ks, monkeypatch, variant=0):
     """One split-mode step: the product W = A X of the step's input, read
     back as (W_hi, W_lo), equals the oracle's split product (exact binned
-    digit products) up to the double-double rounding of the recombination."""
+    digit products) up to the double-double rounding of the recombination.
+    variant 0 stages the tiles through registers, 1 loads them straight
+    into LDS."""
     rf = _lib()
-    monkeypatch.setenv("REFINE_SPLIT_KS", str(ks))
+    monkeypatch.setenv("REFINE_SPLIT_KS", "%d,%d" % (ks, variant))
     ctx = rf.RefineContext(_dev(P.A), k, norm_a=1.0, precision="split_int8", slices=slices)
     X = _dev(P.X0).clone()
     st = ctx.step(X)
@@ -221,19 +223,22 @@ def _split_product_check(P, n, k, slices, ks, monkeypatch):
         n, k, slices, ks, err, scale)
 
 
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("n,k,ks", [(777, 13, 1), (1000, 64, 2), (1280, 33, 4), (640, 128, 1),
                                     (300, 1, 1), (513, 96, 8)])
-def test_split_product_matches_oracle(n, k, ks, monkeypatch):
+def test_split_product_matches_oracle(n, k, ks, variant, monkeypatch):
     """Ragged n (not a multiple of the 32-wide chunks or of the row blocks),
-    every column-tile layout (k <= 32, 64, 96, 128) and K splits 1-8."""
+    every column-tile layout (k <= 32, 64, 96, 128), K splits 1-8, both
+    tile-loading variants."""
     P = synth.dense_spectrum(n, k, 5000 + n)
-    _split_product_check(P, n, k, 9, ks, monkeypatch)
+    _split_product_check(P, n, k, 9, ks, monkeypatch, variant)
 
 
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("slices", [7, 8, 10])
-def test_split_product_other_slice_counts(slices, monkeypatch):
+def test_split_product_other_slice_counts(slices, variant, monkeypatch):
     P = synth.dense_spectrum(700, 40, 5100 + slices)
-    _split_product_check(P, 700, 40, slices, 2, monkeypatch)
+    _split_product_check(P, 700, 40, slices, 2, monkeypatch, variant)
 
 
 @pytest.mark.parametrize("n,k", [(777, 13), (640, 64), (513, 17)])
