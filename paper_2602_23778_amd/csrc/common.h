@@ -29,6 +29,8 @@ struct Ctrl {
   double corr_fro;    // statistics of the last step
   double resid_rel;
   double hist[4];     // ||E_L||_F of the last applied steps (ring)
+  int32_t kxk_fb;     // this step's k-by-k work falls back to the one-workgroup solver
+  int32_t pad0;
 };
 
 // One problem: a symmetric matrix, its iterate and its workspace slices.
@@ -59,6 +61,7 @@ struct Prob {
   int32_t ndp;
   double* gpart;          // Gram partials, ngb x (2 k k + k)
   double* kk;             // k-by-k area (see KK_* offsets)
+  double* kpp;            // partial sums of the k-by-k panel pipeline (16 + 16 k doubles)
   double* vec;            // vectors of length k (see VEC_* offsets)
   Ctrl* ctrl;
   double mu;              // shift: targets are the largest |lambda - mu|
@@ -91,7 +94,8 @@ enum {
   KK_X1N = 7,   // updated leading rows
   KK_S0 = 8,    // scratch for the k-by-k solver when it does not fit in LDS (8..11)
   KK_Z = 12,    // Y1^{-1} of the previous step (warm start)
-  KK_COUNT = 13
+  KK_Q = 13,    // Y1 Z^T (panel pipeline)
+  KK_COUNT = 14
 };
 // Offsets (in units of k doubles) inside Prob::vec.
 enum {

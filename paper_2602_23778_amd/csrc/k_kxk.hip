@@ -152,7 +152,8 @@ __device__ bool gauss_jordan_inverse(double* Yi, int k, int* piv, double* fcol, 
 }
 
 template <bool LDS>
-__global__ __launch_bounds__(KXK_NT) void kxk_kernel(const Prob* __restrict__ probs, int nprob) {
+__global__ __launch_bounds__(KXK_NT) void kxk_kernel(const Prob* __restrict__ probs, int nprob,
+                                                      int only_fb) {
   constexpr int KQ = LDS ? 16 : 32;  // k <= 64 in LDS, k <= 128 otherwise
   extern __shared__ double smem[];
   __shared__ double red[KXK_NW];
@@ -164,8 +165,12 @@ __global__ __launch_bounds__(KXK_NT) void kxk_kernel(const Prob* __restrict__ pr
     const Prob& P = probs[p];
     Ctrl* ctrl = P.ctrl;
     __syncthreads();
-    if (tid == 0) ctrl->apply = 0;
-    if (ctrl->stopped) continue;
+    if (only_fb) {
+      if (ctrl->stopped || !ctrl->kxk_fb) continue;
+    } else {
+      if (tid == 0) ctrl->apply = 0;
+      if (ctrl->stopped) continue;
+    }
     const int n = P.n, k = P.k, kk2 = k * k;
     const int64_t ldx = P.ldx;
     const double* __restrict__ X = P.x;
@@ -426,7 +431,8 @@ __device__ __forceinline__ void ks_zero(v4d (&res)[KS_SLOTS]) {
   for (int sl = 0; sl < KS_SLOTS; ++sl) res[sl] = v4d{0.0, 0.0, 0.0, 0.0};
 }
 
-__global__ __launch_bounds__(KS_NT) void kxk_small_kernel(const Prob* __restrict__ probs, int nprob) {
+__global__ __launch_bounds__(KS_NT) void kxk_small_kernel(const Prob* __restrict__ probs, int nprob,
+                                                           int only_fb) {
   __shared__ double B0[KS_K * KS_K], B1[KS_K * KS_K], B2[KS_K * KS_K], B3[KS_K * KS_K];
   __shared__ double red[KS_NW];
   __shared__ int piv[KS_K];
@@ -437,8 +443,12 @@ __global__ __launch_bounds__(KS_NT) void kxk_small_kernel(const Prob* __restrict
     const Prob& P = probs[p];
     Ctrl* ctrl = P.ctrl;
     __syncthreads();
-    if (tid == 0) ctrl->apply = 0;
-    if (ctrl->stopped) continue;
+    if (only_fb) {
+      if (ctrl->stopped || !ctrl->kxk_fb) continue;
+    } else {
+      if (tid == 0) ctrl->apply = 0;
+      if (ctrl->stopped) continue;
+    }
     const int n = P.n, k = P.k, kk2 = k * k;
     const int64_t ldx = P.ldx;
     const double* __restrict__ X = P.x;
@@ -684,13 +694,345 @@ __global__ __launch_bounds__(KS_NT) void kxk_small_kernel(const Prob* __restrict
   }
 }
 
+// ---------------------------------------------------------------------------
+// Panel pipeline (one problem, any k <= 128): the same k-by-k work spread
+// over np = ceil(k/16) workgroups, one per 16-row panel, one wavefront per
+// 16x16 tile of the panel, in four launches:
+//   1. F0 = I - Z0 Y1 with Z0 the previous step's Y1^{-1} (left residual);
+//      C = X^T R - R1; E11 (line 6 of Algorithm 4); column sums of |Y1|.
+//   2. Z = (I + F0 + F0^2 + F0^3) Z0, whose left residual is F0^4, so Z is
+//      accepted when ||F0||_F^4 <= 16 k u; M = -Z C; column sums of |Z|.
+//      Otherwise the step's k-by-k work falls back to the one-workgroup
+//      solver (Newton-Schulz from -I or Gauss-Jordan), launched next.
+//   3. cond_1(Y1) check; F = X1^T E11 + (X2^T R2 - X2^T X2 M) diag(1/(d-mu))
+//      - E11; Q = Y1 Z^T; Z kept as the next warm start.
+//   4. N = -Z^T F and the new leading rows X1 + E11 - Y1 N = X1 + E11 + Q F.
+// Every product has the panel's rows on the left (a 16 x k panel in LDS) and
+// a whole k x k matrix on the right (read from L2), so a panel needs no other
+// panel's results within a launch.
+// Partial sums (kpp): [0, 8) ||F0||^2 per panel, [8, 16) ||E11||^2 per panel,
+// 16 + p k + j column sums of |Y1|, 16 + 8 k + p k + j column sums of |Z|.
+// ---------------------------------------------------------------------------
+constexpr int PP_LDA = KMAX + 4;  // LDS panel row stride (doubles)
+
+// Loads the 16 x k panel a(r, l) (rows r < 16 of the panel, zero-padded to
+// a multiple of 4 columns and beyond k rows) into LDS.  Ends with a barrier.
+template <class FA>
+__device__ __forceinline__ void pp_load(int k, int pi, double* As, FA a) {
+  const int kp = (k + 3) / 4 * 4;
+  for (int e = threadIdx.x; e < 16 * kp; e += blockDim.x) {
+    const int r = e / kp, l = e - r * kp;
+    const int i = pi * 16 + r;
+    As[r * PP_LDA + l] = (i < k && l < k) ? a(i, l) : 0.0;
+  }
+  __syncthreads();
+}
+
+// 16x16 tile tj of (panel in LDS) x b: register r of the result holds row
+// pi*16 + g + 4r and column tj*16 + (lane % 16).
+template <class FB>
+__device__ __forceinline__ v4d pp_tile(int k, const double* As, FB b, int tj) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, r16 = lane & 15;
+  const int j = tj * 16 + r16;
+  const bool jok = j < k;
+  const int kq = (k + 3) / 4;
+  double bv[KMAX / 4];
+#pragma unroll
+  for (int q = 0; q < KMAX / 4; ++q) {
+    const int l = 4 * q + g;
+    bv[q] = (q < kq && l < k && jok) ? b(l, j) : 0.0;
+  }
+  v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < KMAX / 4; q += 2) {
+    if (q < kq) acc0 = mfma_f64(As[r16 * PP_LDA + 4 * q + g], bv[q], acc0);
+    if (q + 1 < kq) acc1 = mfma_f64(As[r16 * PP_LDA + 4 * q + 4 + g], bv[q + 1], acc1);
+  }
+  return acc0 + acc1;
+}
+
+// Calls f(i, j, v) for the valid entries of a tile result.
+template <class FS>
+__device__ __forceinline__ void pp_each(int k, int pi, int tj, const v4d& acc, FS f) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, r16 = lane & 15;
+  const int j = tj * 16 + r16;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = pi * 16 + mfma_row(g, r);
+    if (i < k && j < k) f(i, j, acc[r]);
+  }
+}
+
+// Block sum of one value per thread (all threads call it).
+__device__ __forceinline__ double pp_sum(double v, double* red) {
+  for (int o = 32; o >= 1; o /= 2) v += __shfl_xor(v, o);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+  return t;
+}
+
+__device__ __forceinline__ double pp_y1(const Prob& P, int i, int l) {
+  return *gld(P.x + (int64_t)i * P.ldx + l) - (i == l ? 1.0 : 0.0);
+}
+
+__global__ __launch_bounds__(512) void pp_res_kernel(const Prob* __restrict__ probs) {
+  __shared__ double As[16 * PP_LDA];
+  __shared__ double red[8];
+  const Prob& P = probs[0];
+  Ctrl* ctrl = P.ctrl;
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->apply = 0;
+  if (ctrl->stopped) return;
+  const int k = P.k, kk2 = k * k, pi = blockIdx.x, tj = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const double* Zg = P.kk + KK_Z * kk2;
+  double* F0 = P.kk + KK_S0 * kk2;
+  double* Cb = P.kk + (KK_S0 + 1) * kk2;
+  double* E1 = P.kk + (KK_S0 + 2) * kk2;
+  const double* PT = P.kk + KK_PT * kk2;
+  const double* P2 = P.kk + KK_P2 * kk2;
+  const double* GT = P.kk + KK_GT * kk2;
+  const double* G2 = P.kk + KK_G2 * kk2;
+  const double* R1 = P.kk + KK_R1 * kk2;
+  const double* d = P.vec + VEC_D * k;
+  const double* alpha = P.vec + VEC_ALPHA * k;
+  // F0 = I - Z0 Y1
+  pp_load(k, pi, As, [&](int i, int l) { return *gld(Zg + i * k + l); });
+  const v4d acc = pp_tile(k, As, [&](int l, int j) { return pp_y1(P, l, j); }, tj);
+  double f2 = 0.0, e2 = 0.0;
+  pp_each(k, pi, tj, acc, [&](int i, int j, double v) {
+    const double f = (i == j ? 1.0 : 0.0) - v;
+    *gst(F0 + i * k + j) = f;
+    f2 = __builtin_fma(f, f, f2);
+    // C and E11 for the same entry
+    const int e = i * k + j;
+    const double v1 = *gld(PT + e) + *gld(P2 + e);
+    *gst(Cb + e) = v1 - *gld(R1 + e);
+    double ev;
+    if (i == j) {
+      ev = (1.0 - alpha[i]) * 0.5;
+    } else if (fabs(d[j] - d[i]) <= P.delta) {
+      ev = P.beta_zero ? 0.0 : -(*gld(GT + e) + *gld(G2 + e)) * 0.5;
+    } else {
+      ev = v1 / (d[j] - d[i]);
+    }
+    *gst(E1 + e) = ev;
+    e2 = __builtin_fma(ev, ev, e2);
+  });
+  f2 = pp_sum(f2, red);
+  e2 = pp_sum(e2, red);
+  if (threadIdx.x == 0) {
+    P.kpp[pi] = f2;
+    P.kpp[8 + pi] = e2;
+  }
+  // column sums of |Y1| over the panel's rows
+  for (int j = threadIdx.x; j < k; j += blockDim.x) {
+    double c = 0.0;
+    for (int r = 0; r < 16 && pi * 16 + r < k; ++r) c += fabs(pp_y1(P, pi * 16 + r, j));
+    P.kpp[16 + pi * k + j] = c;
+  }
+  (void)lane;
+}
+
+__global__ __launch_bounds__(512) void pp_ns_kernel(const Prob* __restrict__ probs) {
+  __shared__ double As[16 * PP_LDA];
+  __shared__ double Bs[16 * PP_LDA];
+  const Prob& P = probs[0];
+  Ctrl* ctrl = P.ctrl;
+  if (ctrl->stopped) return;
+  const int k = P.k, kk2 = k * k, pi = blockIdx.x, tj = threadIdx.x >> 6;
+  const int np = (k + 15) / 16;
+  double f2 = 0.0;
+  for (int p = 0; p < np; ++p) f2 += P.kpp[p];
+  const double eres = sqrt(f2);
+  const double tol = 16.0 * k * UNIT_ROUNDOFF;
+  const bool accept = (eres * eres) * (eres * eres) <= tol;
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->kxk_fb = accept ? 0 : 1;
+  if (!accept) return;
+  const double* Zg = P.kk + KK_Z * kk2;
+  const double* F0 = P.kk + KK_S0 * kk2;
+  const double* Cb = P.kk + (KK_S0 + 1) * kk2;
+  double* Zn = P.kk + (KK_S0 + 3) * kk2;
+  double* Cm = P.kk + KK_CM * kk2;
+  // T = I + F0 + F0^2 + F0^3 on this panel, accumulated in Bs
+  pp_load(k, pi, As, [&](int i, int l) { return *gld(F0 + i * k + l); });  // As = F0 panel
+  {
+    const int kp = (k + 3) / 4 * 4;
+    for (int e = threadIdx.x; e < 16 * kp; e += blockDim.x) {
+      const int r = e / kp, l = e - r * kp;
+      const int i = pi * 16 + r;
+      Bs[r * PP_LDA + l] = (i < k && l < k) ? As[r * PP_LDA + l] + (i == l ? 1.0 : 0.0) : 0.0;
+    }
+  }
+  for (int pw = 2; pw <= 3; ++pw) {
+    // As <- As F0 (F0^pw on the panel); Bs += As
+    const v4d acc = pp_tile(k, As, [&](int l, int j) { return *gld(F0 + l * k + j); }, tj);
+    __syncthreads();
+    pp_each(k, pi, tj, acc, [&](int i, int j, double v) {
+      const int r = i - pi * 16;
+      As[r * PP_LDA + j] = v;
+      Bs[r * PP_LDA + j] += v;
+    });
+    __syncthreads();
+  }
+  // Z = T Z0 on this panel -> As and Zn
+  {
+    const v4d acc = pp_tile(k, Bs, [&](int l, int j) { return *gld(Zg + l * k + j); }, tj);
+    __syncthreads();
+    pp_each(k, pi, tj, acc, [&](int i, int j, double v) {
+      As[(i - pi * 16) * PP_LDA + j] = v;
+      *gst(Zn + i * k + j) = v;
+    });
+    __syncthreads();
+  }
+  // M = -Z C
+  {
+    const v4d acc = pp_tile(k, As, [&](int l, int j) { return *gld(Cb + l * k + j); }, tj);
+    pp_each(k, pi, tj, acc, [&](int i, int j, double v) { *gst(Cm + i * 2 * k + j) = -v; });
+  }
+  // column sums of |Z| over the panel's rows
+  for (int j = threadIdx.x; j < k; j += blockDim.x) {
+    double c = 0.0;
+    for (int r = 0; r < 16 && pi * 16 + r < k; ++r) c += fabs(As[r * PP_LDA + j]);
+    P.kpp[16 + 8 * k + pi * k + j] = c;
+  }
+}
+
+__global__ __launch_bounds__(512) void pp_f_kernel(const Prob* __restrict__ probs) {
+  __shared__ double As[16 * PP_LDA];
+  __shared__ double red[8];
+  const Prob& P = probs[0];
+  Ctrl* ctrl = P.ctrl;
+  if (ctrl->stopped || ctrl->kxk_fb) return;
+  const int n = P.n, k = P.k, kk2 = k * k, pi = blockIdx.x, tj = threadIdx.x >> 6;
+  const int np = (k + 15) / 16;
+  // cond_1(Y1) = ||Y1||_1 ||Z||_1 (the same sums in every block)
+  double cy = 0.0, cz = 0.0;
+  for (int j = threadIdx.x; j < k; j += blockDim.x) {
+    double a = 0.0, b = 0.0;
+    for (int p = 0; p < np; ++p) {
+      a += P.kpp[16 + p * k + j];
+      b += P.kpp[16 + 8 * k + p * k + j];
+    }
+    cy = fmax(cy, a);
+    cz = fmax(cz, b);
+  }
+  for (int o = 32; o >= 1; o /= 2) {
+    cy = fmax(cy, __shfl_xor(cy, o));
+    cz = fmax(cz, __shfl_xor(cz, o));
+  }
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = cy;
+  }
+  __syncthreads();
+  double ny = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) ny = fmax(ny, red[w]);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = cz;
+  __syncthreads();
+  double nz = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) nz = fmax(nz, red[w]);
+  const double cond = ny * nz;
+  if (!(cond <= 1.0 / ((double)n * UNIT_ROUNDOFF))) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      ctrl->status = -4;
+      ctrl->stopped = 1;
+    }
+    return;
+  }
+  const double* Zn = P.kk + (KK_S0 + 3) * kk2;
+  double* Zg = P.kk + KK_Z * kk2;
+  double* Fm = P.kk + KK_S0 * kk2;  // F0 is no longer needed
+  const double* E1 = P.kk + (KK_S0 + 2) * kk2;
+  const double* P2 = P.kk + KK_P2 * kk2;
+  const double* G2 = P.kk + KK_G2 * kk2;
+  const double* Cm = P.kk + KK_CM * kk2;
+  double* Q = P.kk + KK_Q * kk2;
+  const double* dinv = P.vec + VEC_DINV * k;
+  // the next step's warm start
+  for (int e = threadIdx.x; e < 16 * k; e += blockDim.x) {
+    const int i = pi * 16 + e / k, j = e % k;
+    if (i < k) Zg[i * k + j] = Zn[i * k + j];
+  }
+  // F = X1^T E11 + (P2 - G2 M) diag(dinv) - E11
+  pp_load(k, pi, As, [&](int i, int l) { return *gld(P.x + (int64_t)l * P.ldx + i); });
+  const v4d fa = pp_tile(k, As, [&](int l, int j) { return *gld(E1 + l * k + j); }, tj);
+  __syncthreads();
+  pp_load(k, pi, As, [&](int i, int l) { return *gld(G2 + i * k + l); });
+  const v4d fb = pp_tile(k, As, [&](int l, int j) { return *gld(Cm + l * 2 * k + j); }, tj);
+  {
+    v4d f;
+    for (int r = 0; r < 4; ++r) f[r] = fa[r];
+    pp_each(k, pi, tj, fb, [&](int i, int j, double v) {
+      const int e = i * k + j;
+      const int r = (i - pi * 16 - ((threadIdx.x & 63) >> 4)) / 4;
+      *gst(Fm + e) = f[r] + (*gld(P2 + e) - v) * dinv[j] - *gld(E1 + e);
+    });
+  }
+  __syncthreads();
+  // Q = Y1 Z^T
+  pp_load(k, pi, As, [&](int i, int l) { return pp_y1(P, i, l); });
+  const v4d qa = pp_tile(k, As, [&](int l, int j) { return *gld(Zn + j * k + l); }, tj);
+  pp_each(k, pi, tj, qa, [&](int i, int j, double v) { *gst(Q + i * k + j) = v; });
+}
+
+__global__ __launch_bounds__(512) void pp_n_kernel(const Prob* __restrict__ probs) {
+  __shared__ double As[16 * PP_LDA];
+  const Prob& P = probs[0];
+  Ctrl* ctrl = P.ctrl;
+  if (ctrl->stopped || ctrl->kxk_fb) return;
+  const int k = P.k, kk2 = k * k, pi = blockIdx.x, tj = threadIdx.x >> 6;
+  const int np = (k + 15) / 16;
+  const double* Zn = P.kk + (KK_S0 + 3) * kk2;
+  const double* Fm = P.kk + KK_S0 * kk2;
+  const double* E1 = P.kk + (KK_S0 + 2) * kk2;
+  const double* Q = P.kk + KK_Q * kk2;
+  double* Cm = P.kk + KK_CM * kk2;
+  double* X1n = P.kk + KK_X1N * kk2;
+  // N = -Z^T F
+  pp_load(k, pi, As, [&](int i, int l) { return *gld(Zn + l * k + i); });
+  const v4d na = pp_tile(k, As, [&](int l, int j) { return *gld(Fm + l * k + j); }, tj);
+  pp_each(k, pi, tj, na, [&](int i, int j, double v) { *gst(Cm + i * 2 * k + k + j) = -v; });
+  __syncthreads();
+  // X1 + E11 + Q F
+  pp_load(k, pi, As, [&](int i, int l) { return *gld(Q + i * k + l); });
+  const v4d xa = pp_tile(k, As, [&](int l, int j) { return *gld(Fm + l * k + j); }, tj);
+  pp_each(k, pi, tj, xa, [&](int i, int j, double v) {
+    *gst(X1n + i * k + j) = *gld(P.x + (int64_t)i * P.ldx + j) + *gld(E1 + i * k + j) + v;
+  });
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double e2 = 0.0;
+    for (int p = 0; p < np; ++p) e2 += P.kpp[8 + p];
+    P.vec[VEC_E1SQ * k] = e2;
+  }
+}
+
 int kxk_lds_doubles(int kmax) { return 0; }
 
+// One problem: the panel pipeline with the one-workgroup solver as its
+// fallback (which runs only when the warm start is not close enough).
+// Batches: the one-workgroup solver per problem.
 hipError_t launch_kxk(const Prob* probs, int nprob, int kmax, hipStream_t st) {
+  if (nprob == 1) {
+    const int np = (kmax + 15) / 16;
+    const dim3 grid(np), block(64 * np);
+    hipLaunchKernelGGL(pp_res_kernel, grid, block, 0, st, probs);
+    hipLaunchKernelGGL(pp_ns_kernel, grid, block, 0, st, probs);
+    if (kmax <= KS_K)
+      hipLaunchKernelGGL(kxk_small_kernel, dim3(1), dim3(KS_NT), 0, st, probs, 1, 1);
+    else
+      hipLaunchKernelGGL(kxk_kernel<false>, dim3(1), dim3(KXK_NT), 0, st, probs, 1, 1);
+    hipLaunchKernelGGL(pp_f_kernel, grid, block, 0, st, probs);
+    hipLaunchKernelGGL(pp_n_kernel, grid, block, 0, st, probs);
+    return hipGetLastError();
+  }
   if (kmax <= KS_K)
-    hipLaunchKernelGGL(kxk_small_kernel, dim3(nprob), dim3(KS_NT), 0, st, probs, nprob);
+    hipLaunchKernelGGL(kxk_small_kernel, dim3(nprob), dim3(KS_NT), 0, st, probs, nprob, 0);
   else
-    hipLaunchKernelGGL(kxk_kernel<false>, dim3(nprob), dim3(KXK_NT), 0, st, probs, nprob);
+    hipLaunchKernelGGL(kxk_kernel<false>, dim3(nprob), dim3(KXK_NT), 0, st, probs, nprob, 0);
   return hipGetLastError();
 }
 

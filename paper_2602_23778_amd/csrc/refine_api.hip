@@ -324,6 +324,7 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
     b += align_up((size_t)dpart_entries(n, s, pl.split) * 2 * k * sizeof(double));
     b += align_up((size_t)s.ngb * (2 * k * k + k) * sizeof(double));
     b += align_up((size_t)KK_COUNT * k * k * sizeof(double));
+    b += align_up((size_t)(16 + 16 * k) * sizeof(double));  // kpp
     b += align_up((size_t)VEC_COUNT * k * sizeof(double));
     bytes += b;
     if (As[p].kind == REFINE_DENSE) {
@@ -384,6 +385,8 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
     base += align_up((size_t)s.ngb * (2 * k * k + k) * sizeof(double));
     P.kk = (double*)base;
     base += align_up((size_t)KK_COUNT * k * k * sizeof(double));
+    P.kpp = (double*)base;
+    base += align_up((size_t)(16 + 16 * k) * sizeof(double));
     P.vec = (double*)base;
     P.ctrl = pl.ctrl + p;
     P.mu = mus[p];

@@ -275,3 +275,47 @@ def test_split_invalid_arguments():
     with pytest.raises(rf.RefineError) as e:
         rf.RefineBatch([A, A], [4, 4], precision="split_int8")
     assert e.value.status == rf.EINVAL
+
+
+# --------------------------------------------------------------------------
+# k-by-k stage: the panel pipeline (warm-started Newton-Schulz) and its
+# one-workgroup fallback
+# --------------------------------------------------------------------------
+def _ctrl_fallback_flag(ctx):
+    """Reads the control word's fallback flag (int32 after the fixed
+    fields: 6 int32, 1 + 2 + 4 doubles)."""
+    import ctypes
+    rf = _lib()
+    ptrs = (ctypes.c_void_p * 6)()
+    assert rf.load_library().refine_debug_workspace(ctx._ctx, ptrs, 6) == 0
+    torch.cuda.synchronize()
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    buf = (ctypes.c_int32 * 2)()
+    off = 6 * 4 + 7 * 8
+    assert hip.hipMemcpy(ctypes.addressof(buf), ptrs[5] + off, 8, 2) == 0
+    return buf[0]
+
+
+@pytest.mark.parametrize("n,k", [(1500, 128), (1100, 100), (900, 48)])
+def test_kxk_panel_pipeline_steps(n, k):
+    """Several FP64 steps at k up to 128: the first step has no warm start
+    and takes the one-workgroup solver, the later ones the panel pipeline;
+    every step matches the oracle."""
+    P = synth.dense_spectrum(n, k, 6000 + n)
+    rf = _lib()
+    ctx = rf.RefineContext(_dev(P.A), k, norm_a=1.0)
+    Xg = _dev(P.X0).clone()
+    Xo = np.array(P.X0, copy=True)
+    flags = []
+    for s in range(4):
+        st = ctx.step(Xg)
+        assert st.status == rf.OK
+        flags.append(_ctrl_fallback_flag(ctx))
+        r = oracle.refine_step(P.A, Xo, norm_a=1.0)
+        Xo = r.X
+        err = float(np.max(np.abs(align_signs(Xg.cpu().numpy(), Xo) - Xo)))
+        assert err <= TOL, "step %d: %.3e" % (s, err)
+        assert st.corr_fro == pytest.approx(r.corr_fro, rel=1e-6)
+    ctx.close()
+    assert flags[0] == 1 and flags[-1] == 0, flags
