@@ -12,38 +12,39 @@ __device__ __forceinline__ int pow2ceil(int v) {
 }
 
 // Block-wide deterministic sum of per-block partials:
-//   out[s] = sum_{b < nb} src[b * stride + s]   for s < S,
-// with a fixed team of threads per slot (each summing every ts-th block with
-// eight independent loads in flight) and a fixed LDS tree across the team.
-// `scratch` holds blockDim.x doubles.  All threads of the block must call it.
+//   out[s] = sum_{b < nb} src[b * stride + s]   for s < S <= blockDim.x,
+// with ts (a power of two) teams of S threads: thread m*S + s sums the blocks
+// b = m, m + ts, ... of slot s, sixteen loads in flight per round trip
+// (consecutive threads read consecutive slots of one block row), then a
+// fixed LDS tree across the teams.  `scratch` holds blockDim.x doubles.  All
+// threads of the block must call it.
 __device__ inline void team_reduce(const double* __restrict__ src, int stride, int S, int nb,
                                    double* scratch, double* out) {
   const int NT = blockDim.x, tid = threadIdx.x;
   int ts = 1;
   while (ts * 2 * S <= NT) ts *= 2;
-  for (int s0 = 0; s0 < S; s0 += NT / ts) {
-    const int s = s0 + tid / ts, m = tid % ts;
-    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (s < S) {
-      int b = m;
-      for (; b + 7 * ts < nb; b += 8 * ts) {
-        double v[8];
+  const int s = tid % S, m = tid / S;
+  double acc = 0.0;
+  if (m < ts) {
+    for (int b0 = m; b0 < nb; b0 += 16 * ts) {
+      double v[16];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = src[(int64_t)(b + u * ts) * stride + s];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) acc[u] += v[u];
+      for (int u = 0; u < 16; ++u) {
+        const int b = b0 + u * ts;
+        v[u] = b < nb ? *gld(src + (int64_t)b * stride + s) : 0.0;
       }
-      for (; b < nb; b += ts) acc[0] += src[(int64_t)b * stride + s];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc += v[u];
     }
-    scratch[tid] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-    __syncthreads();
-    for (int h = ts / 2; h >= 1; h /= 2) {
-      if (m < h) scratch[tid] += scratch[tid + h];
-      __syncthreads();
-    }
-    if (m == 0 && s < S) out[s] = scratch[tid];
+  }
+  scratch[tid] = acc;
+  __syncthreads();
+  for (int h = ts / 2; h >= 1; h /= 2) {
+    if (m < h) scratch[tid] += scratch[tid + h * S];
     __syncthreads();
   }
+  if (m == 0) out[s] = scratch[tid];
+  __syncthreads();
 }
 
 // Per-column block sums for the Rayleigh quotients (eq. Rayleigh).  Threads

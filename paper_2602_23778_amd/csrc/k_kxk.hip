@@ -699,14 +699,15 @@ __global__ __launch_bounds__(KS_NT) void kxk_small_kernel(const Prob* __restrict
 // over np = ceil(k/16) workgroups, one per 16-row panel, one wavefront per
 // 16x16 tile of the panel, in four launches:
 //   1. F0 = I - Z0 Y1 with Z0 the previous step's Y1^{-1} (left residual);
-//      C = X^T R - R1; E11 (line 6 of Algorithm 4); column sums of |Y1|.
+//      C = X^T R - R1; E11 (line 6 of Algorithm 4).
 //   2. Z = (I + F0 + F0^2 + F0^3) Z0, whose left residual is F0^4, so Z is
 //      accepted when ||F0||_F^4 <= 16 k u; M = -Z C; column sums of |Z|.
 //      Otherwise the step's k-by-k work falls back to the one-workgroup
 //      solver (Newton-Schulz from -I or Gauss-Jordan), launched next.
-//   3. cond_1(Y1) check; F = X1^T E11 + (X2^T R2 - X2^T X2 M) diag(1/(d-mu))
-//      - E11; Q = Y1 Z^T; Z kept as the next warm start.
-//   4. N = -Z^T F and the new leading rows X1 + E11 - Y1 N = X1 + E11 + Q F.
+//   3. F = X1^T E11 + (X2^T R2 - X2^T X2 M) diag(1/(d-mu)) - E11;
+//      Q = Y1 Z^T; column sums of |Y1|; Z kept as the next warm start.
+//   4. cond_1(Y1) check (a failure stops the step before the update applies
+//      it); N = -Z^T F and the leading rows X1 + E11 - Y1 N = X1 + E11 + Q F.
 // Every product has the panel's rows on the left (a 16 x k panel in LDS) and
 // a whole k x k matrix on the right (read from L2), so a panel needs no other
 // panel's results within a launch.
@@ -719,11 +720,21 @@ constexpr int PP_LDA = KMAX + 4;  // LDS panel row stride (doubles)
 // a multiple of 4 columns and beyond k rows) into LDS.  Ends with a barrier.
 template <class FA>
 __device__ __forceinline__ void pp_load(int k, int pi, double* As, FA a) {
+  // 16 * kp <= 4 * blockDim (kp <= 16 np, blockDim = 64 np): four loads per
+  // thread at most, all issued before the first LDS store
   const int kp = (k + 3) / 4 * 4;
-  for (int e = threadIdx.x; e < 16 * kp; e += blockDim.x) {
+  double v[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = threadIdx.x + u * blockDim.x;
     const int r = e / kp, l = e - r * kp;
     const int i = pi * 16 + r;
-    As[r * PP_LDA + l] = (i < k && l < k) ? a(i, l) : 0.0;
+    v[u] = (e < 16 * kp && i < k && l < k) ? a(i, l) : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = threadIdx.x + u * blockDim.x;
+    if (e < 16 * kp) As[(e / kp) * PP_LDA + e % kp] = v[u];
   }
   __syncthreads();
 }
@@ -786,7 +797,7 @@ __global__ __launch_bounds__(512) void pp_res_kernel(const Prob* __restrict__ pr
   if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->apply = 0;
   if (ctrl->stopped) return;
   const int k = P.k, kk2 = k * k, pi = blockIdx.x, tj = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, g = lane >> 4, r16 = lane & 15;
   const double* Zg = P.kk + KK_Z * kk2;
   double* F0 = P.kk + KK_S0 * kk2;
   double* Cb = P.kk + (KK_S0 + 1) * kk2;
@@ -798,42 +809,54 @@ __global__ __launch_bounds__(512) void pp_res_kernel(const Prob* __restrict__ pr
   const double* R1 = P.kk + KK_R1 * kk2;
   const double* d = P.vec + VEC_D * k;
   const double* alpha = P.vec + VEC_ALPHA * k;
+  // this lane's four entries (rows pi*16 + g + 4r, column tj*16 + r16): every
+  // load of the elementwise part is issued before the product
+  const int j = tj * 16 + r16;
+  double vpt[4], vp2[4], vr1[4], vg[4], di[4], ai[4];
+  const double dj = j < k ? *gld(d + j) : 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = pi * 16 + mfma_row(g, r);
+    const bool ok = i < k && j < k;
+    const int e = ok ? i * k + j : 0;
+    vpt[r] = ok ? *gld(PT + e) : 0.0;
+    vp2[r] = ok ? *gld(P2 + e) : 0.0;
+    vr1[r] = ok ? *gld(R1 + e) : 0.0;
+    vg[r] = ok ? *gld(GT + e) + *gld(G2 + e) : 0.0;
+    di[r] = i < k ? *gld(d + i) : 0.0;
+    ai[r] = i < k ? *gld(alpha + i) : 0.0;
+  }
   // F0 = I - Z0 Y1
   pp_load(k, pi, As, [&](int i, int l) { return *gld(Zg + i * k + l); });
-  const v4d acc = pp_tile(k, As, [&](int l, int j) { return pp_y1(P, l, j); }, tj);
+  const v4d acc = pp_tile(k, As, [&](int l, int jj) { return pp_y1(P, l, jj); }, tj);
   double f2 = 0.0, e2 = 0.0;
-  pp_each(k, pi, tj, acc, [&](int i, int j, double v) {
-    const double f = (i == j ? 1.0 : 0.0) - v;
-    *gst(F0 + i * k + j) = f;
-    f2 = __builtin_fma(f, f, f2);
-    // C and E11 for the same entry
-    const int e = i * k + j;
-    const double v1 = *gld(PT + e) + *gld(P2 + e);
-    *gst(Cb + e) = v1 - *gld(R1 + e);
-    double ev;
-    if (i == j) {
-      ev = (1.0 - alpha[i]) * 0.5;
-    } else if (fabs(d[j] - d[i]) <= P.delta) {
-      ev = P.beta_zero ? 0.0 : -(*gld(GT + e) + *gld(G2 + e)) * 0.5;
-    } else {
-      ev = v1 / (d[j] - d[i]);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = pi * 16 + mfma_row(g, r);
+    if (i < k && j < k) {
+      const int e = i * k + j;
+      const double f = (i == j ? 1.0 : 0.0) - acc[r];
+      *gst(F0 + e) = f;
+      f2 = __builtin_fma(f, f, f2);
+      const double v1 = vpt[r] + vp2[r];
+      *gst(Cb + e) = v1 - vr1[r];
+      double ev;
+      if (i == j)
+        ev = (1.0 - ai[r]) * 0.5;
+      else if (fabs(dj - di[r]) <= P.delta)
+        ev = P.beta_zero ? 0.0 : -vg[r] * 0.5;
+      else
+        ev = v1 / (dj - di[r]);
+      *gst(E1 + e) = ev;
+      e2 = __builtin_fma(ev, ev, e2);
     }
-    *gst(E1 + e) = ev;
-    e2 = __builtin_fma(ev, ev, e2);
-  });
+  }
   f2 = pp_sum(f2, red);
   e2 = pp_sum(e2, red);
   if (threadIdx.x == 0) {
     P.kpp[pi] = f2;
     P.kpp[8 + pi] = e2;
   }
-  // column sums of |Y1| over the panel's rows
-  for (int j = threadIdx.x; j < k; j += blockDim.x) {
-    double c = 0.0;
-    for (int r = 0; r < 16 && pi * 16 + r < k; ++r) c += fabs(pp_y1(P, pi * 16 + r, j));
-    P.kpp[16 + pi * k + j] = c;
-  }
-  (void)lane;
 }
 
 __global__ __launch_bounds__(512) void pp_ns_kernel(const Prob* __restrict__ probs) {
@@ -902,47 +925,11 @@ __global__ __launch_bounds__(512) void pp_ns_kernel(const Prob* __restrict__ pro
 
 __global__ __launch_bounds__(512) void pp_f_kernel(const Prob* __restrict__ probs) {
   __shared__ double As[16 * PP_LDA];
-  __shared__ double red[8];
   const Prob& P = probs[0];
   Ctrl* ctrl = P.ctrl;
   if (ctrl->stopped || ctrl->kxk_fb) return;
-  const int n = P.n, k = P.k, kk2 = k * k, pi = blockIdx.x, tj = threadIdx.x >> 6;
-  const int np = (k + 15) / 16;
-  // cond_1(Y1) = ||Y1||_1 ||Z||_1 (the same sums in every block)
-  double cy = 0.0, cz = 0.0;
-  for (int j = threadIdx.x; j < k; j += blockDim.x) {
-    double a = 0.0, b = 0.0;
-    for (int p = 0; p < np; ++p) {
-      a += P.kpp[16 + p * k + j];
-      b += P.kpp[16 + 8 * k + p * k + j];
-    }
-    cy = fmax(cy, a);
-    cz = fmax(cz, b);
-  }
-  for (int o = 32; o >= 1; o /= 2) {
-    cy = fmax(cy, __shfl_xor(cy, o));
-    cz = fmax(cz, __shfl_xor(cz, o));
-  }
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) {
-    red[threadIdx.x >> 6] = cy;
-  }
-  __syncthreads();
-  double ny = 0.0;
-  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) ny = fmax(ny, red[w]);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = cz;
-  __syncthreads();
-  double nz = 0.0;
-  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) nz = fmax(nz, red[w]);
-  const double cond = ny * nz;
-  if (!(cond <= 1.0 / ((double)n * UNIT_ROUNDOFF))) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      ctrl->status = -4;
-      ctrl->stopped = 1;
-    }
-    return;
-  }
+  const int k = P.k, kk2 = k * k, pi = blockIdx.x, tj = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, g = lane >> 4, r16 = lane & 15;
   const double* Zn = P.kk + (KK_S0 + 3) * kk2;
   double* Zg = P.kk + KK_Z * kk2;
   double* Fm = P.kk + KK_S0 * kk2;  // F0 is no longer needed
@@ -951,40 +938,54 @@ __global__ __launch_bounds__(512) void pp_f_kernel(const Prob* __restrict__ prob
   const double* G2 = P.kk + KK_G2 * kk2;
   const double* Cm = P.kk + KK_CM * kk2;
   double* Q = P.kk + KK_Q * kk2;
-  const double* dinv = P.vec + VEC_DINV * k;
-  // the next step's warm start
-  for (int e = threadIdx.x; e < 16 * k; e += blockDim.x) {
-    const int i = pi * 16 + e / k, j = e % k;
-    if (i < k) Zg[i * k + j] = Zn[i * k + j];
+  const int j = tj * 16 + r16;
+  // loads of the elementwise parts first
+  double vp2[4], ve1[4], zc[4];
+  const double dj = j < k ? *gld(P.vec + VEC_DINV * k + j) : 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = pi * 16 + mfma_row(g, r);
+    const bool ok = i < k && j < k;
+    const int e = ok ? i * k + j : 0;
+    vp2[r] = ok ? *gld(P2 + e) : 0.0;
+    ve1[r] = ok ? *gld(E1 + e) : 0.0;
+    zc[r] = ok ? *gld(Zn + e) : 0.0;
   }
   // F = X1^T E11 + (P2 - G2 M) diag(dinv) - E11
   pp_load(k, pi, As, [&](int i, int l) { return *gld(P.x + (int64_t)l * P.ldx + i); });
-  const v4d fa = pp_tile(k, As, [&](int l, int j) { return *gld(E1 + l * k + j); }, tj);
+  const v4d fa = pp_tile(k, As, [&](int l, int jj) { return *gld(E1 + l * k + jj); }, tj);
   __syncthreads();
   pp_load(k, pi, As, [&](int i, int l) { return *gld(G2 + i * k + l); });
-  const v4d fb = pp_tile(k, As, [&](int l, int j) { return *gld(Cm + l * 2 * k + j); }, tj);
-  {
-    v4d f;
-    for (int r = 0; r < 4; ++r) f[r] = fa[r];
-    pp_each(k, pi, tj, fb, [&](int i, int j, double v) {
+  const v4d fb = pp_tile(k, As, [&](int l, int jj) { return *gld(Cm + l * 2 * k + jj); }, tj);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = pi * 16 + mfma_row(g, r);
+    if (i < k && j < k) {
       const int e = i * k + j;
-      const int r = (i - pi * 16 - ((threadIdx.x & 63) >> 4)) / 4;
-      *gst(Fm + e) = f[r] + (*gld(P2 + e) - v) * dinv[j] - *gld(E1 + e);
-    });
+      *gst(Fm + e) = fa[r] + (vp2[r] - fb[r]) * dj - ve1[r];
+      *gst(Zg + e) = zc[r];  // the next step's warm start
+    }
   }
   __syncthreads();
-  // Q = Y1 Z^T
+  // Q = Y1 Z^T, and the column sums of |Y1| over this panel's rows
   pp_load(k, pi, As, [&](int i, int l) { return pp_y1(P, i, l); });
-  const v4d qa = pp_tile(k, As, [&](int l, int j) { return *gld(Zn + j * k + l); }, tj);
-  pp_each(k, pi, tj, qa, [&](int i, int j, double v) { *gst(Q + i * k + j) = v; });
+  const v4d qa = pp_tile(k, As, [&](int l, int jj) { return *gld(Zn + jj * k + l); }, tj);
+  pp_each(k, pi, tj, qa, [&](int i, int jj, double v) { *gst(Q + i * k + jj) = v; });
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    double a = 0.0;
+    for (int r = 0; r < 16; ++r) a += fabs(As[r * PP_LDA + c]);  // zero rows beyond k
+    P.kpp[16 + pi * k + c] = a;
+  }
 }
 
 __global__ __launch_bounds__(512) void pp_n_kernel(const Prob* __restrict__ probs) {
   __shared__ double As[16 * PP_LDA];
+  __shared__ double red[2][8];
   const Prob& P = probs[0];
   Ctrl* ctrl = P.ctrl;
   if (ctrl->stopped || ctrl->kxk_fb) return;
-  const int k = P.k, kk2 = k * k, pi = blockIdx.x, tj = threadIdx.x >> 6;
+  const int n = P.n, k = P.k, kk2 = k * k, pi = blockIdx.x, tj = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, g = lane >> 4, r16 = lane & 15;
   const int np = (k + 15) / 16;
   const double* Zn = P.kk + (KK_S0 + 3) * kk2;
   const double* Fm = P.kk + KK_S0 * kk2;
@@ -992,17 +993,61 @@ __global__ __launch_bounds__(512) void pp_n_kernel(const Prob* __restrict__ prob
   const double* Q = P.kk + KK_Q * kk2;
   double* Cm = P.kk + KK_CM * kk2;
   double* X1n = P.kk + KK_X1N * kk2;
+  const int j = tj * 16 + r16;
+  double vx[4], ve1[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = pi * 16 + mfma_row(g, r);
+    const bool ok = i < k && j < k;
+    vx[r] = ok ? *gld(P.x + (int64_t)i * P.ldx + j) : 0.0;
+    ve1[r] = ok ? *gld(E1 + i * k + j) : 0.0;
+  }
+  // cond_1(Y1) = ||Y1||_1 ||Z||_1 from the panel column sums (the same in
+  // every block); a failure stops the step before the update applies it
+  double cy = 0.0, cz = 0.0;
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    double a = 0.0, b = 0.0;
+    for (int p = 0; p < np; ++p) {
+      a += P.kpp[16 + p * k + c];
+      b += P.kpp[16 + 8 * k + p * k + c];
+    }
+    cy = fmax(cy, a);
+    cz = fmax(cz, b);
+  }
+  for (int o = 32; o >= 1; o /= 2) {
+    cy = fmax(cy, __shfl_xor(cy, o));
+    cz = fmax(cz, __shfl_xor(cz, o));
+  }
+  if (lane == 0) {
+    red[0][tj] = cy;
+    red[1][tj] = cz;
+  }
+  __syncthreads();
+  double ny = 0.0, nz = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+    ny = fmax(ny, red[0][w]);
+    nz = fmax(nz, red[1][w]);
+  }
+  if (!(ny * nz <= 1.0 / ((double)n * UNIT_ROUNDOFF))) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      ctrl->status = -4;
+      ctrl->stopped = 1;
+    }
+    return;
+  }
   // N = -Z^T F
   pp_load(k, pi, As, [&](int i, int l) { return *gld(Zn + l * k + i); });
-  const v4d na = pp_tile(k, As, [&](int l, int j) { return *gld(Fm + l * k + j); }, tj);
-  pp_each(k, pi, tj, na, [&](int i, int j, double v) { *gst(Cm + i * 2 * k + k + j) = -v; });
+  const v4d na = pp_tile(k, As, [&](int l, int jj) { return *gld(Fm + l * k + jj); }, tj);
+  pp_each(k, pi, tj, na, [&](int i, int jj, double v) { *gst(Cm + i * 2 * k + k + jj) = -v; });
   __syncthreads();
   // X1 + E11 + Q F
   pp_load(k, pi, As, [&](int i, int l) { return *gld(Q + i * k + l); });
-  const v4d xa = pp_tile(k, As, [&](int l, int j) { return *gld(Fm + l * k + j); }, tj);
-  pp_each(k, pi, tj, xa, [&](int i, int j, double v) {
-    *gst(X1n + i * k + j) = *gld(P.x + (int64_t)i * P.ldx + j) + *gld(E1 + i * k + j) + v;
-  });
+  const v4d xa = pp_tile(k, As, [&](int l, int jj) { return *gld(Fm + l * k + jj); }, tj);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = pi * 16 + mfma_row(g, r);
+    if (i < k && j < k) *gst(X1n + i * k + j) = vx[r] + ve1[r] + xa[r];
+  }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     double e2 = 0.0;
     for (int p = 0; p < np; ++p) e2 += P.kpp[8 + p];

@@ -62,7 +62,7 @@ __global__ __launch_bounds__(CT * RG * 64) void gram_kernel(const Prob* __restri
     for (int t = 0; t < CT; ++t) {
       const int c = t * 16 + r16;
       cok[t] = c < k;
-      dv[t] = cok[t] ? P.vec[VEC_D * k + c] : 0.0;
+      dv[t] = cok[t] ? *gld(P.vec + VEC_D * k + c) : 0.0;
     }
     const int ca = ti * 16 + r16;
     const bool aok = ca < k;
@@ -89,15 +89,15 @@ __global__ __launch_bounds__(CT * RG * 64) void gram_kernel(const Prob* __restri
           const double* xr = X + (int64_t)(rok ? row : lo) * ldx;
           const double* wr = P.w + (int64_t)(rok ? row : lo) * k;
           const double* wl = has_lo ? P.wlo + (int64_t)(rok ? row : lo) * k : nullptr;
-          const double xa = (rok && aok) ? xr[ca] : 0.0;
+          const double xa = (rok && aok) ? *gld(xr + ca) : 0.0;
           double xv[CT], rv[CT];
 #pragma unroll
           for (int t = 0; t < CT; ++t) {
             const int c = t * 16 + r16;
             if (rok && cok[t]) {
-              const double x = xr[c];
+              const double x = *gld(xr + c);
               xv[t] = x;
-              rv[t] = residual(wr[c], has_lo ? wl[c] : 0.0, x, dv[t], has_lo);
+              rv[t] = residual(*gld(wr + c), has_lo ? *gld(wl + c) : 0.0, x, dv[t], has_lo);
             } else {
               xv[t] = 0.0;
               rv[t] = 0.0;
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(CT * RG * 64) void gram_kernel(const Prob* __restri
             if (phase == 0 && rok) {
 #pragma unroll
               for (int t = 0; t < CT; ++t)
-                if (cok[t]) P.kk[KK_R1 * kk2 + row * k + t * 16 + r16] = rv[t];
+                if (cok[t]) *gst(P.kk + KK_R1 * kk2 + row * k + t * 16 + r16) = rv[t];
             }
           }
         }
@@ -159,8 +159,8 @@ __global__ __launch_bounds__(CT * RG * 64) void gram_kernel(const Prob* __restri
             for (int r = 0; r < 4; ++r) {
               const int i = ti * 16 + mfma_row(g, r);
               if (i < k) {
-                dstP[i * k + c] = accP[t][r];
-                if (t >= ti) dstG[i * k + c] = accG[t][r];
+                *gst(dstP + i * k + c) = accP[t][r];
+                if (t >= ti) *gst(dstG + i * k + c) = accG[t][r];
               }
             }
           }
@@ -170,7 +170,7 @@ __global__ __launch_bounds__(CT * RG * 64) void gram_kernel(const Prob* __restri
     // blocks without rows >= k still publish zero partials
     if (max(r0, k) >= r1) {
       double* dst = P.gpart + (int64_t)item.blk * (2 * kk2 + k);
-      for (int e = threadIdx.x; e < 2 * kk2; e += blockDim.x) dst[e] = 0.0;
+      for (int e = threadIdx.x; e < 2 * kk2; e += blockDim.x) *gst(dst + e) = 0.0;
     }
     // column sums of r^2 over the block's rows
     if (ti == 0) {
@@ -185,7 +185,7 @@ __global__ __launch_bounds__(CT * RG * 64) void gram_kernel(const Prob* __restri
         for (int q = 0; q < RG; ++q)
           s += (rsq_x[q][t * 64 + c16] + rsq_x[q][t * 64 + 16 + c16]) +
                (rsq_x[q][t * 64 + 32 + c16] + rsq_x[q][t * 64 + 48 + c16]);
-        P.gpart[(int64_t)item.blk * (2 * kk2 + k) + 2 * kk2 + c] = s;
+        *gst(P.gpart + (int64_t)item.blk * (2 * kk2 + k) + 2 * kk2 + c) = s;
       }
     }
     __syncthreads();
@@ -220,16 +220,16 @@ __global__ __launch_bounds__(1024) void gram_reduce_kernel(const Prob* __restric
       const int nb = P.ngb;
       int b = bg;
       for (; b + 48 < nb; b += 64) {
-        const double v0 = P.gpart[(int64_t)b * S + src];
-        const double v1 = P.gpart[(int64_t)(b + 16) * S + src];
-        const double v2 = P.gpart[(int64_t)(b + 32) * S + src];
-        const double v3 = P.gpart[(int64_t)(b + 48) * S + src];
+        const double v0 = *gld(P.gpart + (int64_t)b * S + src);
+        const double v1 = *gld(P.gpart + (int64_t)(b + 16) * S + src);
+        const double v2 = *gld(P.gpart + (int64_t)(b + 32) * S + src);
+        const double v3 = *gld(P.gpart + (int64_t)(b + 48) * S + src);
         acc0 += v0;
         acc1 += v1;
         acc2 += v2;
         acc3 += v3;
       }
-      for (; b < nb; b += 16) acc0 += P.gpart[(int64_t)b * S + src];
+      for (; b < nb; b += 16) acc0 += *gld(P.gpart + (int64_t)b * S + src);
     }
     sh[bg][c] = (acc0 + acc1) + (acc2 + acc3);
     __syncthreads();
@@ -261,6 +261,9 @@ template <int CT>
 __global__ __launch_bounds__(256) void update_kernel(const Prob* __restrict__ probs,
                                                     const RowItem* __restrict__ items, int nitems) {
   constexpr int NT = 256, WAVES = 4, KCH = CT <= 4 ? 64 : 32, BW = 2 * CT * 16, LDC = BW + 2;
+  // k <= 64: the epilogue's X and W values are loaded before the products
+  constexpr bool PRE = CT <= 4;
+  constexpr int PC = PRE ? CT : 1;
   __shared__ double Cs[KCH * LDC];
   __shared__ double colred[2][WAVES][CT * 16];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -282,20 +285,31 @@ __global__ __launch_bounds__(256) void update_kernel(const Prob* __restrict__ pr
     for (int t = 0; t < CT; ++t) {
       const int c = t * 16 + r16;
       cok[t] = c < k;
-      dv[t] = cok[t] ? P.vec[VEC_D * k + c] : 0.0;
-      di[t] = cok[t] ? P.vec[VEC_DINV * k + c] : 0.0;
+      dv[t] = cok[t] ? *gld(P.vec + VEC_D * k + c) : 0.0;
+      di[t] = cok[t] ? *gld(P.vec + VEC_DINV * k + c) : 0.0;
       xsq[t] = 0.0;
       esq[t] = 0.0;
     }
     // stage rows [kc0, kc0 + KCH) of [M | N] (columns padded to 16 CT)
+    // (every thread issues sixteen loads before their LDS stores)
     auto stage = [&](int kc0) {
-      for (int e = tid; e < KCH * BW; e += NT) {
-        const int rr = e / BW, cc = e - rr * BW;
-        const int half = cc / (CT * 16), cj = cc - half * (CT * 16);
-        const int kr = kc0 + rr;
-        double v = 0.0;
-        if (kr < k && cj < k) v = Cm[kr * k2 + half * k + cj];
-        Cs[rr * LDC + cc] = v;
+      constexpr int PER = (KCH * BW + NT - 1) / NT, BAT = PER < 16 ? PER : 16;
+#pragma unroll 1
+      for (int u0 = 0; u0 < PER; u0 += BAT) {
+        double v[BAT];
+#pragma unroll
+        for (int u = 0; u < BAT; ++u) {
+          const int e = tid + (u0 + u) * NT;
+          const int rr = e / BW, cc = e - rr * BW;
+          const int half = cc / (CT * 16), cj = cc - half * (CT * 16);
+          const int kr = kc0 + rr;
+          v[u] = (e < KCH * BW && kr < k && cj < k) ? *gld(Cm + kr * k2 + half * k + cj) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < BAT; ++u) {
+          const int e = tid + (u0 + u) * NT;
+          if (e < KCH * BW) Cs[(e / BW) * LDC + e % BW] = v[u];
+        }
       }
     };
     const bool one_stage = k <= KCH;
@@ -313,27 +327,48 @@ __global__ __launch_bounds__(256) void update_kernel(const Prob* __restrict__ pr
       const int arow = rc + wave * 16 + r16;
       const bool arok = arow < r1;
       const double* xr = X + (int64_t)(arok ? arow : r0) * ldx;
+      // the A operand of one K chunk (all of K when k <= 64), loaded at once
+      constexpr int AQ = KCH / 4;
+      double a_ch[AQ];
+      auto load_a = [&](int kc0) {
+#pragma unroll
+        for (int q = 0; q < AQ; ++q) {
+          const int kk = kc0 + 4 * q + g;
+          a_ch[q] = (arok && kk < k) ? *gld(xr + kk) : 0.0;
+        }
+      };
+      load_a(0);
+      double ex[PC][4], ew[PC][4], el[PC][4];
+      if (PRE) {
+#pragma unroll
+        for (int t = 0; t < PC; ++t)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = rc + wave * 16 + mfma_row(g, r);
+            const bool ok = cok[t] && row < r1 && row >= k;
+            const int64_t o = (int64_t)row * k + t * 16 + r16;
+            ex[t][r] = ok ? *gld(X + (int64_t)row * ldx + t * 16 + r16) : 0.0;
+            ew[t][r] = ok ? *gld(P.w + o) : 0.0;
+            el[t][r] = (ok && has_lo) ? *gld(P.wlo + o) : 0.0;
+          }
+      }
       for (int kc0 = 0; kc0 < k; kc0 += KCH) {
         if (!one_stage) {
+          if (kc0 > 0) load_a(kc0);
           __syncthreads();
           stage(kc0);
           __syncthreads();
         }
         const int kend = min(k, kc0 + KCH);
         for (int kc = kc0; kc < kend; kc += 16) {
-          double a[4];
 #pragma unroll
           for (int s = 0; s < 4; ++s) {
-            const int kk = kc + 4 * s + g;
-            a[s] = (arok && kk < k) ? xr[kk] : 0.0;
-          }
-#pragma unroll
-          for (int s = 0; s < 4; ++s) {
+            const double av = a_ch[(kc - kc0) / 4 + s];
             const double* brow = Cs + (kc - kc0 + 4 * s + g) * LDC + r16;
 #pragma unroll
             for (int t = 0; t < CT; ++t) {
-              accM[t] = mfma_f64(a[s], brow[t * 16], accM[t]);
-              accN[t] = mfma_f64(a[s], brow[CT * 16 + t * 16], accN[t]);
+              accM[t] = mfma_f64(av, brow[t * 16], accM[t]);
+              accN[t] = mfma_f64(av, brow[CT * 16 + t * 16], accN[t]);
             }
           }
         }
@@ -349,16 +384,25 @@ __global__ __launch_bounds__(256) void update_kernel(const Prob* __restrict__ pr
             if (row < r1) {
               double xt;
               if (row < k) {
-                xt = X1n[row * k + c];
+                xt = *gld(X1n + row * k + c);
               } else {
                 const int64_t o = (int64_t)row * k + c;
-                const double x = X[(int64_t)row * ldx + c];
-                const double rr = residual(P.w[o], has_lo ? P.wlo[o] : 0.0, x, dv[t], has_lo);
+                double x, w, wl;
+                if (PRE) {
+                  x = ex[t < PC ? t : 0][r];
+                  w = ew[t < PC ? t : 0][r];
+                  wl = el[t < PC ? t : 0][r];
+                } else {
+                  x = *gld(X + (int64_t)row * ldx + c);
+                  w = *gld(P.w + o);
+                  wl = has_lo ? *gld(P.wlo + o) : 0.0;
+                }
+                const double rr = residual(w, wl, x, dv[t], has_lo);
                 const double e = (rr - accM[t][r]) * di[t];
                 xt = (x + e) - accN[t][r];
                 esq[t] = __builtin_fma(e, e, esq[t]);
               }
-              P.xn[(int64_t)row * k + c] = xt;
+              *gst(P.xn + (int64_t)row * k + c) = xt;
               xsq[t] = __builtin_fma(xt, xt, xsq[t]);
             }
           }
@@ -386,8 +430,8 @@ __global__ __launch_bounds__(256) void update_kernel(const Prob* __restrict__ pr
         a += colred[0][w][tid];
         b += colred[1][w][tid];
       }
-      P.part[(int64_t)item.blk * stride + 2 * k + tid] = a;
-      P.part[(int64_t)item.blk * stride + 3 * k + tid] = b;
+      *gst(P.part + (int64_t)item.blk * stride + 2 * k + tid) = a;
+      *gst(P.part + (int64_t)item.blk * stride + 3 * k + tid) = b;
     }
     __syncthreads();
   }
