@@ -13,41 +13,114 @@
 
 namespace rfk {
 
-template <int NT>
+// Blocks of the SpMM (each takes every SPMM_GRID-th chunk of SPMM_ROWS rows).
+constexpr int SPMM_GRID = 512;
+constexpr int SPMM_ROWS = 256;
+
+// Latency: a row costs two dependent round trips (its nonzeros, then the X
+// rows they name), so each thread keeps RPT rows in flight at once: the row
+// pointers of the next RPT rows are requested while the current ones are
+// gathered, and up to eight nonzeros of a row are requested together.  The
+// sum over a row's nonzeros runs in CSR order.
+//
+// Row order: the block takes the row chunks blockIdx.x, blockIdx.x + grid,
+// ... (chunks of rbrows rows), so that at any moment the whole GPU works on
+// one contiguous window of rows and the far stencil neighbours (N^2 rows
+// away on a 3-D grid) are still in the caches.  The block's Rayleigh
+// partial covers all of its chunks (partial index = blockIdx.x).
+template <int NT, int RPT, int NZB>
 __global__ __launch_bounds__(NT) void spmm_kernel(const Prob* __restrict__ probs,
-                                                 const RowItem* __restrict__ items, int nitems) {
+                                                 const RowItem* __restrict__ items, int nitems,
+                                                 int chunk_rows) {
   __shared__ double red[2 * NT];
   const int tid = threadIdx.x;
+  const Prob& P = probs[0];
+  if (P.ctrl->stopped) return;
+  double sxw = 0.0, sxx = 0.0;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const RowItem item = items[it];
-    const Prob& P = probs[item.prob];
-    if (P.ctrl->stopped) continue;
     const int n = P.n, k = P.k, kp = pow2ceil(k), tr = NT / kp;
     const int col = tid % kp, trow = tid / kp;
-    const int r0 = item.blk * P.rbrows, r1 = min(n, r0 + P.rbrows);
+    const int r0 = item.blk * chunk_rows, r1 = min(n, r0 + chunk_rows);
     const int32_t* __restrict__ rp = P.rp;
     const int32_t* __restrict__ ci = P.ci;
     const double* __restrict__ av = P.av;
     const double* __restrict__ X = P.x;
     const int64_t ldx = P.ldx;
-    double sxw = 0.0, sxx = 0.0;
     if (col < k) {
-      for (int row = r0 + trow; row < r1; row += tr) {
-        const int e0 = rp[row], e1 = rp[row + 1];
-        double w = 0.0;
-        for (int e = e0; e < e1; ++e) w = __builtin_fma(av[e], X[(int64_t)ci[e] * ldx + col], w);
-        P.w[(int64_t)row * k + col] = w;
-        const double x = X[(int64_t)row * ldx + col];
-        sxw = __builtin_fma(x, w, sxw);
-        sxx = __builtin_fma(x, x, sxx);
+      // rows row0 + u*tr, u < RPT, per round; row pointers one round ahead
+      int e0[RPT], e1[RPT];
+      const int step = RPT * tr;
+      int row0 = r0 + trow;
+#pragma unroll
+      for (int u = 0; u < RPT; ++u) {
+        const int row = row0 + u * tr;
+        e0[u] = row < r1 ? *gld(rp + row) : 0;
+        e1[u] = row < r1 ? *gld(rp + row + 1) : 0;
+      }
+      for (; row0 < r1; row0 += step) {
+        int ne0[RPT], ne1[RPT];
+#pragma unroll
+        for (int u = 0; u < RPT; ++u) {
+          const int row = row0 + step + u * tr;
+          ne0[u] = row < r1 ? *gld(rp + row) : 0;
+          ne1[u] = row < r1 ? *gld(rp + row + 1) : 0;
+        }
+        double w[RPT], xs[RPT];
+        int len = 0;
+#pragma unroll
+        for (int u = 0; u < RPT; ++u) {
+          const int row = row0 + u * tr;
+          w[u] = 0.0;
+          xs[u] = row < r1 ? *gld(X + (int64_t)row * ldx + col) : 0.0;
+          len = max(len, e1[u] - e0[u]);
+        }
+        for (int b = 0; b < len; b += NZB) {
+          int c[RPT][NZB];
+          double a[RPT][NZB], xv[RPT][NZB];
+#pragma unroll
+          for (int u = 0; u < RPT; ++u)
+#pragma unroll
+            for (int z = 0; z < NZB; ++z) {
+              const int e = e0[u] + b + z;
+              const bool ok = e < e1[u];
+              c[u][z] = ok ? *gld(ci + e) : 0;
+              a[u][z] = ok ? *gld(av + e) : 0.0;
+            }
+#pragma unroll
+          for (int u = 0; u < RPT; ++u)
+#pragma unroll
+            for (int z = 0; z < NZB; ++z)
+              xv[u][z] = e0[u] + b + z < e1[u] ? *gld(X + (int64_t)c[u][z] * ldx + col) : 0.0;
+#pragma unroll
+          for (int u = 0; u < RPT; ++u)
+#pragma unroll
+            for (int z = 0; z < NZB; ++z)
+              if (e0[u] + b + z < e1[u]) w[u] = __builtin_fma(a[u][z], xv[u][z], w[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < RPT; ++u) {
+          const int row = row0 + u * tr;
+          if (row < r1) {
+            *gst(P.w + (int64_t)row * k + col) = w[u];
+            sxw = __builtin_fma(xs[u], w[u], sxw);
+            sxx = __builtin_fma(xs[u], xs[u], sxx);
+          }
+          e0[u] = ne0[u];
+          e1[u] = ne1[u];
+        }
       }
     }
-    rayleigh_block_partial<NT>(P, item.blk, sxw, sxx, red);
   }
+  rayleigh_block_partial<NT>(P, blockIdx.x, sxw, sxx, red);
 }
 
+int spmm_chunk_rows() { return SPMM_ROWS; }
+int spmm_grid(int nitems) { return nitems < SPMM_GRID ? nitems : SPMM_GRID; }
+
 hipError_t launch_spmm(const Prob* probs, const RowItem* items, int nitems, hipStream_t st) {
-  hipLaunchKernelGGL((spmm_kernel<1024>), dim3(nitems), dim3(1024), 0, st, probs, items, nitems);
+  hipLaunchKernelGGL((spmm_kernel<1024, 1, 8>), dim3(spmm_grid(nitems)), dim3(1024), 0, st, probs,
+                     items, nitems, SPMM_ROWS);
   return hipGetLastError();
 }
 

@@ -40,6 +40,8 @@ hipError_t launch_fin_stats(const Prob*, int, hipStream_t);
 hipError_t launch_ctrl_reset(const Prob*, int, int, double, hipStream_t);
 hipError_t launch_set_x(Prob*, int, double*, int64_t, hipStream_t);
 hipError_t launch_spmm(const Prob*, const RowItem*, int, hipStream_t);
+int spmm_chunk_rows();
+int spmm_grid(int nitems);
 hipError_t launch_rowstats(int, int, const double*, int64_t, const int32_t*, const int32_t*,
                            const double*, double*, int, hipStream_t);
 hipError_t kxk_set_attributes();
@@ -64,6 +66,8 @@ struct Plan {
   int n_row = 0;
   RowItem* gram_items = nullptr;
   int n_gram = 0;
+  RowItem* spmm_items = nullptr;  // CSR product: chunks of spmm_chunk_rows() rows
+  int n_spmm = 0;
   GramRedItem* gred_items = nullptr;
   int n_gred = 0;
   int kmax = 0;
@@ -79,6 +83,9 @@ struct Plan {
   Ctrl* ctrl = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  hipGraph_t graph_multi = nullptr;      // `multi` steps in one graph
+  hipGraphExec_t exec_multi = nullptr;
+  int multi = 0;
   hipStream_t cap_stream = nullptr;
 };
 
@@ -95,18 +102,22 @@ Shape choose_shape(int64_t n, int k, bool single, bool csr) {
   Shape s{};
   s.ksplit = 1;
   s.kchunk = (int)n;
-  // Row blocks of the streaming passes (split-K sum, update, normalisation).
-  if (single && csr) {
-    const int target = 512;
-    s.rbrows = std::max<int64_t>(128, ((n + target - 1) / target + 127) / 128 * 128);
+  // Row blocks of the streaming passes (split-K sum, update, normalisation):
+  // 64 rows for one dense problem; about 2048 blocks for a long one (every
+  // CU then has several blocks to overlap their latencies); a few blocks per
+  // problem in a batch (thousands of tiny blocks would each pay the fixed
+  // latency of staging [M | N] and of the partial writes).
+  if (single) {
+    s.rbrows = (int)std::max<int64_t>(64, (n + 2047) / 2048 + 63) / 64 * 64;
   } else {
-    s.rbrows = 64;
+    s.rbrows = 256;
   }
-  // Gram blocks: at least k rows (the leading k rows must sit in block 0),
-  // about 128 blocks per problem when alone.
+  // Gram blocks: at least k rows (the leading k rows must sit in block 0);
+  // about 1024 blocks for one long problem (the k-by-k partials stay a few
+  // percent of the pass's traffic), 256 rows in a batch.
   {
     const int64_t kr = (k + 3) / 4 * 4;
-    const int64_t per = single ? ((n + 127) / 128 + 3) / 4 * 4 : 128;
+    const int64_t per = single ? std::max<int64_t>(64, ((n + 1023) / 1024 + 3) / 4 * 4) : 256;
     s.gbrows = (int)std::max<int64_t>(std::max<int64_t>(kr, per), 16);
   }
   s.nrb = iceil(n, s.rbrows);
@@ -115,6 +126,10 @@ Shape choose_shape(int64_t n, int k, bool single, bool csr) {
 }
 
 constexpr int KSPLIT_MAX = 16;
+// refine_run checks the control word once per RUN_CHUNK steps (one graph);
+// batches replay BATCH_GRAPH_STEPS steps per graph.
+constexpr int RUN_CHUNK = 8;
+constexpr int BATCH_GRAPH_STEPS = 5;
 
 // Upper bound of the Rayleigh partials: per row block of the smallest
 // product tile (64 rows) and K split, or per streaming row block.
@@ -136,12 +151,15 @@ hipError_t upload(T** dst, const std::vector<T>& v) {
 
 void free_plan(Plan& p) {
   if (p.exec) (void)hipGraphExecDestroy(p.exec);
+  if (p.exec_multi) (void)hipGraphExecDestroy(p.exec_multi);
+  if (p.graph_multi) (void)hipGraphDestroy(p.graph_multi);
   if (p.graph) (void)hipGraphDestroy(p.graph);
   if (p.cap_stream) (void)hipStreamDestroy(p.cap_stream);
   (void)hipFree(p.dprob);
   (void)hipFree(p.gemm_items);
   (void)hipFree(p.row_items);
   (void)hipFree(p.gram_items);
+  (void)hipFree(p.spmm_items);
   (void)hipFree(p.gred_items);
   (void)hipFree(p.ws);
   split_free(p.sp);
@@ -228,16 +246,20 @@ int choose_gemm(Plan& pl, const std::vector<refine_matrix>& As, bool single,
         ks <= shapes[0].ksplit)
       return install_gemm(pl, As, cfg, single ? ks : 1);
   }
-  if (!single) return install_gemm(pl, As, 3, 1);
-  const TuneKey key{As[0].n, pl.hprob[0].k, pl.vec2 ? 1 : 0};
+  int64_t nsum = 0;
+  for (const auto& a : As) nsum += a.n;
+  const TuneKey key{single ? As[0].n : -nsum - (int64_t)As.size(), single ? pl.hprob[0].k : pl.kmax,
+                    pl.vec2 ? 1 : 0};
   auto hit = tune_cache().find(key);
   if (hit != tune_cache().end()) return install_gemm(pl, As, hit->second.first, hit->second.second);
   // time the candidates on a zero X (the workspace copy of the update)
   Prob& P = pl.hprob[0];
-  double* const saved_x = P.x;
-  const int64_t saved_ldx = P.ldx;
-  P.x = P.xn;
-  P.ldx = P.k;
+  std::vector<std::pair<double*, int64_t>> saved;
+  for (Prob& q : pl.hprob) {
+    saved.push_back({q.x, q.ldx});
+    q.x = q.xn;
+    q.ldx = q.k;
+  }
   hipStream_t st = nullptr;
   RF_CHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
   hipEvent_t e0, e1;
@@ -245,11 +267,12 @@ int choose_gemm(Plan& pl, const std::vector<refine_matrix>& As, bool single,
   RF_CHECK(hipEventCreate(&e1));
   float best = 1e30f;
   int best_cfg = 1, best_ks = 1;
-  const int ks_max = shapes[0].ksplit;
+  const int ks_max = single ? shapes[0].ksplit : 1;
   for (int cfg = 0; cfg < gemm_num_cfgs(); ++cfg) {
     for (int ks = 1; ks <= ks_max; ks *= 2) {
       // at least one block per CU unless this is the largest split
-      if ((int64_t)iceil(As[0].n, gemm_rows_per_block(cfg)) * ks < 256 && 2 * ks <= ks_max) continue;
+      if (single && (int64_t)iceil(As[0].n, gemm_rows_per_block(cfg)) * ks < 256 && 2 * ks <= ks_max)
+        continue;
       if (install_gemm(pl, As, cfg, ks) != REFINE_OK) return REFINE_EHIP;
       float t = 0.f, t1 = 0.f;
       hipError_t e = hipEventRecord(e0, st);
@@ -280,8 +303,10 @@ int choose_gemm(Plan& pl, const std::vector<refine_matrix>& As, bool single,
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipStreamDestroy(st);
-  P.x = saved_x;
-  P.ldx = saved_ldx;
+  for (size_t q = 0; q < pl.hprob.size(); ++q) {
+    pl.hprob[q].x = saved[q].first;
+    pl.hprob[q].ldx = saved[q].second;
+  }
   tune_cache()[key] = {best_cfg, best_ks};
   pl.gemm_ms = best / 3.f;
   if (getenv("REFINE_LOG"))
@@ -379,7 +404,8 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
     P.part = (double*)base;
     base += align_up((size_t)s.nrb * 5 * k * sizeof(double));
     P.dpart = (double*)base;
-    P.ndp = s.nrb;  // CSR: one partial per row block; dense: set with the product's items
+    // CSR: one partial per product block; dense: set with the product's items
+    P.ndp = pl.csr ? spmm_grid(iceil(n, spmm_chunk_rows())) : s.nrb;
     base += align_up((size_t)dpart_entries(n, s, pl.split) * 2 * k * sizeof(double));
     P.gpart = (double*)base;
     base += align_up((size_t)s.ngb * (2 * k * k + k) * sizeof(double));
@@ -413,6 +439,12 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
   RF_CHECK(upload(&pl.row_items, ri));
   RF_CHECK(upload(&pl.gram_items, gri));
   RF_CHECK(upload(&pl.gred_items, rr));
+  if (pl.csr) {
+    std::vector<RowItem> si;
+    for (int b = 0; b < iceil(As[0].n, spmm_chunk_rows()); ++b) si.push_back(RowItem{0, b});
+    RF_CHECK(upload(&pl.spmm_items, si));
+    pl.n_spmm = (int)si.size();
+  }
   pl.n_row = (int)ri.size();
   pl.n_gram = (int)gri.size();
   pl.n_gred = (int)rr.size();
@@ -427,7 +459,7 @@ hipError_t enqueue_step(Plan& pl, hipStream_t st) {
   hipError_t e;
   const int np = (int)pl.hprob.size();
   if (pl.csr) {
-    if ((e = launch_spmm(pl.dprob, pl.row_items, pl.n_row, st)) != hipSuccess) return e;
+    if ((e = launch_spmm(pl.dprob, pl.spmm_items, pl.n_spmm, st)) != hipSuccess) return e;
   } else {
     if (pl.split) {
       if ((e = split_product(pl.sp, pl.dprob, st)) != hipSuccess) return e;
@@ -451,19 +483,47 @@ hipError_t enqueue_step(Plan& pl, hipStream_t st) {
   return hipSuccess;
 }
 
-int capture_graph(Plan& pl) {
+// Records one step as a graph and, for the repeated-step loops, `multi`
+// consecutive steps as a second graph (the kernels of later steps skip their
+// work once the control word says stopped).
+int capture_graph(Plan& pl, int multi) {
   RF_CHECK(hipStreamCreateWithFlags(&pl.cap_stream, hipStreamNonBlocking));
-  RF_CHECK(hipStreamBeginCapture(pl.cap_stream, hipStreamCaptureModeThreadLocal));
-  hipError_t e = enqueue_step(pl, pl.cap_stream);
-  hipGraph_t g = nullptr;
-  hipError_t e2 = hipStreamEndCapture(pl.cap_stream, &g);
-  if (e != hipSuccess || e2 != hipSuccess) {
-    if (g) (void)hipGraphDestroy(g);
-    return REFINE_EHIP;
+  for (int which = 0; which < 2; ++which) {
+    const int steps = which == 0 ? 1 : multi;
+    if (steps < 2 && which == 1) break;
+    RF_CHECK(hipStreamBeginCapture(pl.cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < steps && e == hipSuccess; ++i) e = enqueue_step(pl, pl.cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(pl.cap_stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return REFINE_EHIP;
+    }
+    if (which == 0) {
+      pl.graph = g;
+      RF_CHECK(hipGraphInstantiate(&pl.exec, g, nullptr, nullptr, 0));
+    } else {
+      pl.graph_multi = g;
+      pl.multi = steps;
+      RF_CHECK(hipGraphInstantiate(&pl.exec_multi, g, nullptr, nullptr, 0));
+    }
   }
-  pl.graph = g;
-  RF_CHECK(hipGraphInstantiate(&pl.exec, g, nullptr, nullptr, 0));
   return REFINE_OK;
+}
+
+// Enqueues `count` steps: whole multi-step graphs first, then single steps.
+hipError_t launch_steps(Plan& pl, int count, hipStream_t st) {
+  while (pl.exec_multi && count >= pl.multi) {
+    hipError_t e = hipGraphLaunch(pl.exec_multi, st);
+    if (e != hipSuccess) return e;
+    count -= pl.multi;
+  }
+  for (int i = 0; i < count; ++i) {
+    hipError_t e = hipGraphLaunch(pl.exec, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 int status_from_ctrl(const Ctrl& c) { return c.status; }
@@ -634,7 +694,7 @@ int refine_init(refine_ctx** out, const refine_matrix* A, int32_t k, const refin
     rc = split_init(c->plan.sp, *A, k, opt.slices > 0 ? opt.slices : SPLIT_S_DEFAULT, c->plan.hprob[0],
                     c->plan.dprob, c->stream);
   }
-  if (rc == REFINE_OK) rc = capture_graph(c->plan);
+  if (rc == REFINE_OK) rc = capture_graph(c->plan, RUN_CHUNK);
   if (rc == REFINE_OK && launch_ctrl_reset(c->plan.dprob, 1, 0, 0.0, c->stream) != hipSuccess)
     rc = REFINE_EHIP;
   if (rc == REFINE_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = REFINE_EHIP;
@@ -688,11 +748,9 @@ int refine_run(refine_ctx* c, double* X, int64_t ldx, int32_t max_iters, refine_
   if (launch_ctrl_reset(c->plan.dprob, 1, (int)stop, tol, c->stream) != hipSuccess) return REFINE_EHIP;
   std::vector<Ctrl> cs(1);
   int done = 0;
-  const int chunk = 8;
   while (done < max_iters) {
-    const int m = std::min(chunk, max_iters - done);
-    for (int i = 0; i < m; ++i)
-      if (hipGraphLaunch(c->plan.exec, c->stream) != hipSuccess) return REFINE_EHIP;
+    const int m = std::min(RUN_CHUNK, max_iters - done);
+    if (launch_steps(c->plan, m, c->stream) != hipSuccess) return REFINE_EHIP;
     done += m;
     rc = read_ctrl(c->plan, c->stream, cs);
     if (rc != REFINE_OK) return rc;
@@ -727,7 +785,7 @@ int refine_time_product(refine_ctx* c, double* X, int64_t ldx, int32_t reps, flo
   hipError_t e = hipEventRecord(e0, c->stream);
   for (int i = 0; i < reps && e == hipSuccess; ++i) {
     if (pl.csr)
-      e = launch_spmm(pl.dprob, pl.row_items, pl.n_row, c->stream);
+      e = launch_spmm(pl.dprob, pl.spmm_items, pl.n_spmm, c->stream);
     else if (pl.split)
       e = split_product(pl.sp, pl.dprob, c->stream);
     else
@@ -799,7 +857,7 @@ int refine_batch_init(refine_batch** out, int32_t count, const refine_matrix* As
     deltas[p] = opt.delta_c * norms[p] * UNIT_ROUNDOFF;
   }
   int rc = build_plan(b->plan, b->As, b->ks, opt, mus, deltas, norms);
-  if (rc == REFINE_OK) rc = capture_graph(b->plan);
+  if (rc == REFINE_OK) rc = capture_graph(b->plan, BATCH_GRAPH_STEPS);
   if (rc == REFINE_OK && hipMalloc((void**)&b->d_xs, sizeof(double*) * 2 * count) != hipSuccess)
     rc = REFINE_ENOMEM;
   if (rc == REFINE_OK && launch_ctrl_reset(b->plan.dprob, count, 0, 0.0, b->stream) != hipSuccess)
@@ -840,8 +898,7 @@ int refine_batch_run(refine_batch* b, double* const* Xs, const int64_t* ldxs, in
         hipSuccess)
       return REFINE_EHIP;
   }
-  for (int i = 0; i < iters; ++i)
-    if (hipGraphLaunch(b->plan.exec, b->stream) != hipSuccess) return REFINE_EHIP;
+  if (launch_steps(b->plan, iters, b->stream) != hipSuccess) return REFINE_EHIP;
   if (!per) return REFINE_OK;
   std::vector<Ctrl> cs;
   int rc = read_ctrl(b->plan, b->stream, cs);

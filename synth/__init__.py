@@ -263,3 +263,66 @@ def laplacian_start(P: CsrProblem, k: int, seed: int, noise: float = 1e-6,
     q, r = np.linalg.qr(X)
     return q * np.sign(np.diag(r))
 
+
+
+def laplacian3d_separable(N: int, k: int, seed: int = SEED_BASE + 4, noise: float = 1e-6,
+                          start_seed: int = 7):
+    """The 7-point Dirichlet Laplacian of laplacian3d with the diagonal
+    perturbation split by axis: a_ii = 6 + dx[x] + dy[y] + dz[z] with
+    dx, dy, dz iid U[0, 1/3) (so a_ii in [6, 7), the same pattern and nnz).
+    A is then the Kronecker sum Tz + Ty + Tx of three tridiagonal N x N
+    matrices T = tridiag(-1, 2 + d, -1), whose eigenpairs give those of A
+    exactly: lambda = mu_x[a] + mu_y[b] + mu_z[c], v = vz[:, c] (x) vy[:, b] (x)
+    vx[:, a].  Returns (CsrProblem, lam_k, X_true, X0) for the k smallest
+    eigenpairs, X0 = X_true + N(0, noise^2) orthonormalised; used where the
+    grid is too large for a sparse eigensolver here."""
+    rng = np.random.default_rng(seed)
+    d = [rng.uniform(0.0, 1.0 / 3.0, N) for _ in range(3)]  # x, y, z
+    n = N ** 3
+    idx = np.arange(n, dtype=np.int64)
+    x = idx % N
+    y = (idx // N) % N
+    z = idx // (N * N)
+    diag = 6.0 + d[0][x] + d[1][y] + d[2][z]
+    cols = []
+    vals = []
+    for off, ok in ((-N * N, z > 0), (-N, y > 0), (-1, x > 0)):
+        cols.append(np.where(ok, idx + off, -1))
+        vals.append(np.where(ok, -1.0, 0.0))
+    cols.append(idx)
+    vals.append(diag)
+    for off, ok in ((1, x < N - 1), (N, y < N - 1), (N * N, z < N - 1)):
+        cols.append(np.where(ok, idx + off, -1))
+        vals.append(np.where(ok, -1.0, 0.0))
+    C = np.stack(cols, 1)
+    Vv = np.stack(vals, 1)
+    mask = C >= 0
+    counts = mask.sum(1)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    col_idx = C[mask].astype(np.int32)
+    val = Vv[mask].astype(np.float64)
+    del C, Vv, mask
+    sigma = float(np.max(diag + (counts - 1)))  # Gershgorin: off-diagonal entries are -1
+    P = CsrProblem(n, row_ptr.astype(np.int32), col_idx, val, sigma,
+                   {"workload": "laplacian3d_separable", "N": N, "seed": seed})
+    eig = []
+    for a in range(3):
+        T = np.diag(2.0 + d[a]) - np.eye(N, k=1) - np.eye(N, k=-1)
+        mu, V = np.linalg.eigh(T)
+        eig.append((mu, V))
+    m = min(N, 16)
+    cand = sorted((eig[0][0][a] + eig[1][0][b] + eig[2][0][c], a, b, c)
+                  for a in range(m) for b in range(m) for c in range(m))
+    top = cand[:k + 1]
+    lam = np.array([t[0] for t in top[:k]])
+    Xt = np.empty((n, k))
+    for j, (_, a, b, c) in enumerate(top[:k]):
+        vx, vy, vz = eig[0][1][:, a], eig[1][1][:, b], eig[2][1][:, c]
+        Xt[:, j] = (vz[:, None, None] * vy[None, :, None] * vx[None, None, :]).reshape(-1)
+    r = np.random.default_rng(start_seed)
+    X = Xt + noise * r.standard_normal(Xt.shape)
+    q, rr = np.linalg.qr(X)
+    X0 = q * np.sign(np.diag(rr))
+    P.meta["lam_next"] = float(top[k][0])
+    return P, lam, Xt, X0

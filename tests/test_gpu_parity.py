@@ -173,6 +173,23 @@ def test_batched_matches_oracle_per_problem():
     b.close()
 
 
+def test_batched_multi_step_graph():
+    """Seven batched steps: one five-step graph and two single-step graphs
+    give the oracle's seven steps for every problem."""
+    rf = _lib()
+    shapes = [(300, 8), (150, 4), (420, 20)]
+    probs = [synth.dense_spectrum(n, k, 950 + i) for i, (n, k) in enumerate(shapes)]
+    b = rf.RefineBatch([_dev(p.A) for p in probs], [k for _, k in shapes], norm_a=1.0)
+    Xs = [_dev(p.X0).clone() for p in probs]
+    rc, per = b.run(Xs, 7)
+    assert rc == rf.OK
+    for p, X, s in zip(probs, Xs, per):
+        Xo, hist = oracle.refine(p.A, p.X0, 7, norm_a=1.0)
+        assert np.max(np.abs(align_signs(X.cpu().numpy(), Xo) - Xo)) <= TOL
+        assert s.iters == 7
+    b.close()
+
+
 def test_step_is_deterministic():
     rf = _lib()
     P = synth.dense_logspace(1024, 32)

@@ -474,3 +474,22 @@ def test_split_step_agrees_with_double_double_step():
     assert r_s9.status == 0 and r_dd.status == 0
     assert np.max(np.abs(r_s9.X - r_dd.X)) < 1e-15
     assert np.max(np.abs(r_s1.X - r_dd.X)) > 1e-6
+
+
+def test_separable_laplacian_generator_eigenpairs():
+    """The separable-diagonal Laplacian used for the largest sparse timing
+    run: its Kronecker-product eigenvectors are eigenvectors of the CSR
+    matrix it builds (checked densely at N = 6), they are the k smallest, and
+    sigma is the Gershgorin upper bound."""
+    import scipy.sparse as sp
+    P, lam, Xt, X0 = synth.laplacian3d_separable(6, 8)
+    M = sp.csr_matrix((P.val, P.col_idx, P.row_ptr), shape=(P.n, P.n)).toarray()
+    assert np.array_equal(M, M.T)
+    assert np.max(np.abs(M @ Xt - Xt * lam)) < 1e-13
+    w = np.linalg.eigvalsh(M)
+    assert np.allclose(w[:8], lam, atol=1e-13) and w[8] == pytest.approx(P.meta["lam_next"], abs=1e-13)
+    off = np.abs(M).sum(1) - np.abs(np.diag(M))
+    assert P.sigma == pytest.approx(np.max(np.diag(M) + off), abs=1e-14)
+    # the same pattern as laplacian3d
+    L = synth.laplacian3d(6)
+    assert np.array_equal(L.row_ptr, P.row_ptr) and np.array_equal(L.col_idx, P.col_idx)
