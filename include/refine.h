@@ -171,7 +171,8 @@ int refine_time_product(refine_ctx* ctx, double* X, int64_t ldx, int32_t reps, f
  * every step of every problem runs in one grouped launch per kernel, over
  * (problem, tile) work items, and the whole step is one HIP graph.  Options
  * apply to all problems; As[p], ks[p] as in refine_init.  X pointers are
- * given per call.  REFINE_SPLIT_INT8 is not available for batches. */
+ * given per call.  In REFINE_SPLIT_INT8 mode every A is sliced at init and
+ * the products of all problems share one launch. */
 int refine_batch_init(refine_batch** b, int32_t count, const refine_matrix* As,
                       const int32_t* ks, const refine_options* opt,
                       void* hip_stream);

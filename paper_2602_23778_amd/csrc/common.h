@@ -147,11 +147,16 @@ __device__ __forceinline__ RFK_GLOBAL T* gst(T* p) {
 }
 
 // Exact transformations used by the accurate residual (Dekker / Knuth).
+// Floating-point contraction is off inside them: a product fused into a
+// later subtraction would be rounded differently from the product the error
+// term describes (the compiler fuses by default in device code).
 __device__ __forceinline__ void two_prod(double a, double b, double& p, double& e) {
+#pragma clang fp contract(off)
   p = a * b;
   e = __builtin_fma(a, b, -p);
 }
 __device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+#pragma clang fp contract(off)
   s = a + b;
   double z = s - a;
   e = (a - (s - z)) + (b - z);
@@ -160,6 +165,7 @@ __device__ __forceinline__ void two_sum(double a, double b, double& s, double& e
 // r = (w_hi + w_lo) - x d with x d formed exactly; without a low part it is
 // w - x d rounded once (a fused multiply-add).
 __device__ __forceinline__ double residual(double w, double wlo, double x, double d, bool has_lo) {
+#pragma clang fp contract(off)
   if (!has_lo) return __builtin_fma(-x, d, w);
   double p, pe;
   two_prod(x, d, p, pe);

@@ -131,42 +131,53 @@ __global__ __launch_bounds__(256) void split_aslice_kernel(const double* __restr
 // Slicing of X (every step)
 // ---------------------------------------------------------------------------
 
-// Column maxima of |X|: each block reduces xrows rows and merges its maxima
-// into xmaxp[j] with an atomic maximum on the bit patterns (for non-negative
-// doubles the unsigned order of the bits is the numeric order, and a maximum
-// does not depend on the order of the merges).  xmaxp is zeroed by the
-// product kernel after use.
-__global__ __launch_bounds__(256) void split_xmax_kernel(const Prob* __restrict__ probs) {
-  const Prob& P = probs[0];
-  if (P.ctrl->stopped) return;
+// Column maxima of |X|: work item (problem, block of xrows rows); each block
+// merges its maxima into the problem's xmaxp[j] with an atomic maximum on
+// the bit patterns (for non-negative doubles the unsigned order of the bits
+// is the numeric order, and a maximum does not depend on the order of the
+// merges).  xmaxp is zeroed by the product kernel after use.
+__global__ __launch_bounds__(256) void split_xmax_kernel(const Prob* __restrict__ probs,
+                                                         const RowItem* __restrict__ items,
+                                                         int nitems) {
   __shared__ double red[256];
-  const int k = P.k, kp = pow2ceil(k), rl = 256 / kp;
-  const int tid = threadIdx.x, j = tid % kp, r = tid / kp;
-  const int r0 = blockIdx.x * P.xrows, r1 = min(P.n, r0 + P.xrows);
-  double m = 0.0;
-  if (j < k)
-    for (int i = r0 + r; i < r1; i += rl) m = fmax(m, fabs(P.x[(int64_t)i * P.ldx + j]));
-  red[tid] = m;
-  __syncthreads();
-  for (int s = rl / 2; s > 0; s >>= 1) {
-    if (r < s) red[tid] = fmax(red[tid], red[tid + s * kp]);
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const RowItem item = items[it];
+    const Prob& P = probs[item.prob];
+    if (P.ctrl->stopped) continue;
+    const int k = P.k, kp = pow2ceil(k), rl = 256 / kp;
+    const int tid = threadIdx.x, j = tid % kp, r = tid / kp;
+    const int r0 = item.blk * P.xrows, r1 = min(P.n, r0 + P.xrows);
+    double m = 0.0;
+    if (j < k)
+      for (int i = r0 + r; i < r1; i += rl) m = fmax(m, fabs(*gld(P.x + (int64_t)i * P.ldx + j)));
+    red[tid] = m;
+    __syncthreads();
+    for (int s = rl / 2; s > 0; s >>= 1) {
+      if (r < s) red[tid] = fmax(red[tid], red[tid + s * kp]);
+      __syncthreads();
+    }
+    if (tid < k)
+      atomicMax(reinterpret_cast<unsigned long long*>(P.xmaxp) + tid,
+                (unsigned long long)__double_as_longlong(red[tid]));
     __syncthreads();
   }
-  if (tid < k)
-    atomicMax(reinterpret_cast<unsigned long long*>(P.xmaxp) + tid,
-              (unsigned long long)__double_as_longlong(red[tid]));
 }
 
-// Digits of X^T: one thread per 16-row unit (chunk, column, half).
+// Digits of X^T: work item (problem, 256 consecutive 16-row units), one
+// thread per unit (chunk, column, half).
 template <int S>
-__global__ __launch_bounds__(256) void split_xslice_kernel(const Prob* __restrict__ probs) {
-  const Prob& P = probs[0];
-  if (P.ctrl->stopped) return;
-  const int kpad = P.kpad, k = P.k, n = P.n;
-  const int64_t units = (int64_t)P.nch * kpad * 2;
-  const unsigned long long* mx = reinterpret_cast<const unsigned long long*>(P.xmaxp);
-  for (int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x; u < units;
-       u += (int64_t)gridDim.x * 256) {
+__global__ __launch_bounds__(256) void split_xslice_kernel(const Prob* __restrict__ probs,
+                                                           const RowItem* __restrict__ items,
+                                                           int nitems) {
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const RowItem item = items[it];
+    const Prob& P = probs[item.prob];
+    if (P.ctrl->stopped) continue;
+    const int kpad = P.kpad, k = P.k, n = P.n;
+    const int64_t units = (int64_t)P.nch * kpad * 2;
+    const int64_t u = (int64_t)item.blk * 256 + threadIdx.x;
+    if (u >= units) continue;
+    const unsigned long long* mx = reinterpret_cast<const unsigned long long*>(P.xmaxp);
     const int h = (int)(u & 1);
     const int64_t cj = u >> 1;
     const int c = (int)(cj / kpad);
@@ -177,7 +188,7 @@ __global__ __launch_bounds__(256) void split_xslice_kernel(const Prob* __restric
     double v[16];
 #pragma unroll
     for (int b = 0; b < 16; ++b)
-      v[b] = (j < k && r0 + b < n) ? P.x[(int64_t)(r0 + b) * P.ldx + j] : 0.0;
+      v[b] = (j < k && r0 + b < n) ? *gld(P.x + (int64_t)(r0 + b) * P.ldx + j) : 0.0;
     u4v out[S];
     digits16<S>(v, e, out);
     u4v* dst = reinterpret_cast<u4v*>(P.xsl + u * 16 * S);
@@ -222,13 +233,12 @@ __global__ __launch_bounds__(WM* WN * 64) void gemm_split_kernel(const Prob* __r
   const int wi = wave / WN, wj = wave % WN;
   const int l32 = lane & 31, hh = lane >> 5;
 
-  // The column maxima of this step have been consumed by the slicing pass.
-  if (blockIdx.x == 0 && tid < probs[0].kpad)
-    reinterpret_cast<unsigned long long*>(probs[0].xmaxp)[tid] = 0ull;
-
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const GemmItem item = items[it];
     const Prob& P = probs[item.prob];
+    // the column maxima of this step have been consumed by the slicing pass
+    if (item.row0 == 0 && item.split == 0 && tid < P.kpad)
+      reinterpret_cast<unsigned long long*>(P.xmaxp)[tid] = 0ull;
     if (P.ctrl->stopped) continue;
     const int n = P.n, k = P.k;
     const int row0 = item.row0;
@@ -460,58 +470,80 @@ hipError_t launch_product(int s, const Layout& L, int variant, const Prob* probs
 }
 
 template <int S>
-hipError_t launch_slicing_s(bool a_side, const double* a, int64_t lda, int n, int nch, int rows_pad,
-                            const int32_t* aexp, uint8_t* asl, const Prob* probs, int64_t units,
-                            hipStream_t st) {
+hipError_t launch_aslice_s(const double* a, int64_t lda, int n, int nch, int rows_pad,
+                           const int32_t* aexp, uint8_t* asl, hipStream_t st) {
+  const int64_t units = (int64_t)rows_pad * nch * 2;
   const int grid = (int)std::min<int64_t>((units + 255) / 256, 16384);
-  if (a_side)
-    hipLaunchKernelGGL((split_aslice_kernel<S>), dim3(grid), dim3(256), 0, st, a, lda, n, nch,
-                       rows_pad, aexp, asl);
-  else
-    hipLaunchKernelGGL((split_xslice_kernel<S>), dim3(grid), dim3(256), 0, st, probs);
+  hipLaunchKernelGGL((split_aslice_kernel<S>), dim3(grid), dim3(256), 0, st, a, lda, n, nch,
+                     rows_pad, aexp, asl);
   return hipGetLastError();
 }
 
-hipError_t launch_slicing(int s, bool a_side, const double* a, int64_t lda, int n, int nch,
-                          int rows_pad, const int32_t* aexp, uint8_t* asl, const Prob* probs,
-                          int64_t units, hipStream_t st) {
+hipError_t launch_aslice(int s, const double* a, int64_t lda, int n, int nch, int rows_pad,
+                         const int32_t* aexp, uint8_t* asl, hipStream_t st) {
   switch (s) {
-    case 7: return launch_slicing_s<7>(a_side, a, lda, n, nch, rows_pad, aexp, asl, probs, units, st);
-    case 8: return launch_slicing_s<8>(a_side, a, lda, n, nch, rows_pad, aexp, asl, probs, units, st);
-    case 9: return launch_slicing_s<9>(a_side, a, lda, n, nch, rows_pad, aexp, asl, probs, units, st);
-    case 10: return launch_slicing_s<10>(a_side, a, lda, n, nch, rows_pad, aexp, asl, probs, units, st);
+    case 7: return launch_aslice_s<7>(a, lda, n, nch, rows_pad, aexp, asl, st);
+    case 8: return launch_aslice_s<8>(a, lda, n, nch, rows_pad, aexp, asl, st);
+    case 9: return launch_aslice_s<9>(a, lda, n, nch, rows_pad, aexp, asl, st);
+    case 10: return launch_aslice_s<10>(a, lda, n, nch, rows_pad, aexp, asl, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_xslice(int s, const Prob* probs, const RowItem* items, int nitems,
+                         hipStream_t st) {
+  const dim3 grid(std::min(nitems, 16384)), block(256);
+  switch (s) {
+    case 7: hipLaunchKernelGGL(split_xslice_kernel<7>, grid, block, 0, st, probs, items, nitems); break;
+    case 8: hipLaunchKernelGGL(split_xslice_kernel<8>, grid, block, 0, st, probs, items, nitems); break;
+    case 9: hipLaunchKernelGGL(split_xslice_kernel<9>, grid, block, 0, st, probs, items, nitems); break;
+    case 10: hipLaunchKernelGGL(split_xslice_kernel<10>, grid, block, 0, st, probs, items, nitems); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 // Longest contraction one K range may have: a bin sums at most s digit
 // products of magnitude <= 2^12 per contraction index.
 int64_t max_k_range(int s) { return ((((int64_t)1 << 31) - 1) / ((int64_t)s << 12)) / 32 * 32; }
 
-std::vector<GemmItem> split_items(int64_t n, int nch, int bm, int ks, int* nks_out) {
-  const int64_t kc = ((int64_t)nch + ks - 1) / ks * 32;
-  const int nks = (int)(((int64_t)nch * 32 + kc - 1) / kc);
+// Product work items: row blocks of every problem (larger problems first)
+// times the K ranges of a K split (one problem only).
+std::vector<GemmItem> split_items(const std::vector<Prob>& hp, int bm, int ks, int* nks_out) {
   std::vector<GemmItem> gi;
-  const int nrb = (int)((n + bm - 1) / bm);
-  for (int rb = 0; rb < nrb; ++rb)
-    for (int sp = 0; sp < nks; ++sp) {
-      GemmItem g{};
-      g.prob = 0;
-      g.row0 = rb * bm;
-      g.k0 = (int)(sp * kc);
-      g.k1 = (int)std::min<int64_t>((int64_t)nch * 32, (sp + 1) * kc);
-      g.split = sp;
-      gi.push_back(g);
-    }
+  int nks = 1;
+  for (size_t p = 0; p < hp.size(); ++p) {
+    const int nch = hp[p].nch;
+    const int64_t kc = ((int64_t)nch + ks - 1) / ks * 32;
+    nks = (int)(((int64_t)nch * 32 + kc - 1) / kc);
+    const int nrb = (hp[p].n + bm - 1) / bm;
+    for (int rb = 0; rb < nrb; ++rb)
+      for (int sp = 0; sp < nks; ++sp) {
+        GemmItem g{};
+        g.prob = (int)p;
+        g.row0 = rb * bm;
+        g.k0 = (int)(sp * kc);
+        g.k1 = (int)std::min<int64_t>((int64_t)nch * 32, (sp + 1) * kc);
+        g.split = sp;
+        gi.push_back(g);
+      }
+  }
+  if (hp.size() > 1)
+    std::stable_sort(gi.begin(), gi.end(), [&](const GemmItem& x, const GemmItem& y) {
+      return hp[x.prob].n > hp[y.prob].n;
+    });
   *nks_out = nks;
   return gi;
 }
 
 struct SplitKey {
   int64_t n;
-  int k, s;
+  int k, s, np;
   bool operator<(const SplitKey& o) const {
-    return n != o.n ? n < o.n : (k != o.k ? k < o.k : s < o.s);
+    if (n != o.n) return n < o.n;
+    if (k != o.k) return k < o.k;
+    if (s != o.s) return s < o.s;
+    return np < o.np;
   }
 };
 std::map<SplitKey, std::pair<int, int>>& split_tune_cache() {
@@ -519,19 +551,28 @@ std::map<SplitKey, std::pair<int, int>>& split_tune_cache() {
   return m;
 }
 
-int install_items(SplitPlan& sp, int64_t n, int nch, int ks, Prob& hp, Prob* dprob) {
+template <class T>
+hipError_t upload_vec(T** dst, const std::vector<T>& v) {
+  (void)hipFree(*dst);
+  *dst = nullptr;
+  if (v.empty()) return hipSuccess;
+  hipError_t e = hipMalloc((void**)dst, sizeof(T) * v.size());
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice);
+}
+
+int install_items(SplitPlan& sp, int ks, std::vector<Prob>& hp, Prob* dprob) {
   int nks = 1;
-  std::vector<GemmItem> gi = split_items(n, nch, sp.bm, ks, &nks);
-  (void)hipFree(sp.items);
-  sp.items = nullptr;
-  if (hipMalloc((void**)&sp.items, sizeof(GemmItem) * gi.size()) != hipSuccess) return REFINE_ENOMEM;
-  if (hipMemcpy(sp.items, gi.data(), sizeof(GemmItem) * gi.size(), hipMemcpyHostToDevice) != hipSuccess)
-    return REFINE_EHIP;
+  std::vector<GemmItem> gi = split_items(hp, sp.bm, ks, &nks);
+  if (upload_vec(&sp.items, gi) != hipSuccess) return REFINE_ENOMEM;
   sp.nitems = (int)gi.size();
   sp.ks = nks;
-  hp.ksplit = nks;
-  hp.ndp = (int)((n + sp.bm - 1) / sp.bm) * nks;
-  if (hipMemcpy(dprob, &hp, sizeof(Prob), hipMemcpyHostToDevice) != hipSuccess) return REFINE_EHIP;
+  for (Prob& P : hp) {
+    P.ksplit = nks;
+    P.ndp = (P.n + sp.bm - 1) / sp.bm * nks;
+  }
+  if (hipMemcpy(dprob, hp.data(), sizeof(Prob) * hp.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return REFINE_EHIP;
   return REFINE_OK;
 }
 
@@ -541,16 +582,15 @@ int split_rows_per_block(int k) { return 32 * layout_for(k).wm; }
 
 hipError_t split_product(const SplitPlan& sp, const Prob* dprob, hipStream_t st) {
   hipError_t e;
-  hipLaunchKernelGGL(split_xmax_kernel, dim3(sp.nbx), dim3(256), 0, st, dprob);
+  hipLaunchKernelGGL(split_xmax_kernel, dim3(std::min(sp.n_xmax, 8192)), dim3(256), 0, st, dprob,
+                     sp.xmax_items, sp.n_xmax);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = launch_slicing(sp.s, false, nullptr, 0, 0, 0, 0, nullptr, nullptr, dprob,
-                          (int64_t)sp.nch * sp.kpad * 2, st)) != hipSuccess)
-    return e;
-  if ((e = launch_product(sp.s, layout_for(sp.k), sp.variant, dprob, sp.items, sp.nitems, st)) !=
+  if ((e = launch_xslice(sp.s, dprob, sp.xsl_items, sp.n_xsl, st)) != hipSuccess) return e;
+  if ((e = launch_product(sp.s, layout_for(sp.kmax), sp.variant, dprob, sp.items, sp.nitems, st)) !=
       hipSuccess)
     return e;
   if (sp.ks > 1) {
-    const int64_t nk = sp.n * sp.k;
+    const int64_t nk = sp.nk0;
     const int grid = (int)std::min<int64_t>((nk + 255) / 256, 4096);
     hipLaunchKernelGGL(split_wsum_kernel, dim3(grid), dim3(256), 0, st, dprob);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -558,79 +598,111 @@ hipError_t split_product(const SplitPlan& sp, const Prob* dprob, hipStream_t st)
   return hipSuccess;
 }
 
-int split_init(SplitPlan& sp, const refine_matrix& A, int k, int slices, Prob& hp, Prob* dprob,
-               hipStream_t st) {
+int split_init(SplitPlan& sp, const std::vector<refine_matrix>& As, const std::vector<int>& ks,
+               int slices, std::vector<Prob>& hp, Prob* dprob, hipStream_t st) {
   sp = SplitPlan();
-  if (A.kind != REFINE_DENSE || slices < SPLIT_S_MIN || slices > SPLIT_S_MAX || k < 1 || k > KMAX ||
-      A.n > SPLIT_NMAX)
-    return REFINE_EINVAL;
-  const int64_t n = A.n;
+  const int np = (int)As.size();
+  if (np < 1 || slices < SPLIT_S_MIN || slices > SPLIT_S_MAX) return REFINE_EINVAL;
+  int kmax = 0;
+  for (int p = 0; p < np; ++p) {
+    if (As[p].kind != REFINE_DENSE || ks[p] < 1 || ks[p] > KMAX || As[p].n > SPLIT_NMAX)
+      return REFINE_EINVAL;
+    kmax = std::max(kmax, ks[p]);
+  }
   const int s = slices;
-  const int nch = (int)((n + 31) / 32);
-  const int kpad = (k + 31) / 32 * 32;
-  const int64_t rows_pad = (n + SPLIT_ROW_PAD - 1) / SPLIT_ROW_PAD * SPLIT_ROW_PAD;
-  const Layout L = layout_for(k);
+  const Layout L = layout_for(kmax);
   sp.s = s;
-  sp.n = n;
-  sp.k = k;
-  sp.nch = nch;
-  sp.kpad = kpad;
+  sp.kmax = kmax;
+  sp.kpad = 32 * L.wn;
   sp.bm = 32 * L.wm;
-  sp.xrows = 256;
-  sp.nbx = (int)((n + sp.xrows - 1) / sp.xrows);
-  const size_t asl_bytes = (size_t)rows_pad * nch * 32 * s;
-  const size_t xsl_bytes = (size_t)nch * kpad * 32 * s;
-  if (hipMalloc((void**)&sp.asl, asl_bytes) != hipSuccess ||
-      hipMalloc((void**)&sp.aexp, sizeof(int32_t) * rows_pad) != hipSuccess ||
-      hipMalloc((void**)&sp.xsl, xsl_bytes) != hipSuccess ||
-      hipMalloc((void**)&sp.xexp, sizeof(int32_t) * kpad) != hipSuccess ||
-      hipMalloc((void**)&sp.xmaxp, sizeof(double) * kpad) != hipSuccess ||
-      hipMalloc((void**)&sp.swp, sizeof(double) * 2 * SPLIT_KS_MAX * n * k) != hipSuccess) {
+  sp.np = np;
+  sp.nk0 = As[0].n * ks[0];
+  constexpr int XROWS = 256;
+  // one allocation per array for all problems
+  std::vector<size_t> o_asl(np), o_aexp(np), o_xsl(np);
+  size_t t_asl = 0, t_aexp = 0, t_xsl = 0;
+  for (int p = 0; p < np; ++p) {
+    const int64_t n = As[p].n, nch = (n + 31) / 32;
+    const int64_t rows_pad = (n + SPLIT_ROW_PAD - 1) / SPLIT_ROW_PAD * SPLIT_ROW_PAD;
+    o_asl[p] = t_asl;
+    t_asl += ((size_t)rows_pad * nch * 32 * s + 255) / 256 * 256;
+    o_aexp[p] = t_aexp;
+    t_aexp += (size_t)rows_pad;
+    o_xsl[p] = t_xsl;
+    t_xsl += ((size_t)nch * sp.kpad * 32 * s + 255) / 256 * 256;
+  }
+  if (hipMalloc((void**)&sp.asl, t_asl) != hipSuccess ||
+      hipMalloc((void**)&sp.aexp, sizeof(int32_t) * t_aexp) != hipSuccess ||
+      hipMalloc((void**)&sp.xsl, t_xsl) != hipSuccess ||
+      hipMalloc((void**)&sp.xexp, sizeof(int32_t) * sp.kpad * np) != hipSuccess ||
+      hipMalloc((void**)&sp.xmaxp, sizeof(double) * sp.kpad * np) != hipSuccess ||
+      (np == 1 &&
+       hipMalloc((void**)&sp.swp, sizeof(double) * 2 * SPLIT_KS_MAX * As[0].n * ks[0]) != hipSuccess)) {
     split_free(sp);
     return REFINE_ENOMEM;
   }
-  hipError_t e = hipMemsetAsync(sp.xmaxp, 0, sizeof(double) * kpad, st);
-  if (e == hipSuccess) e = hipMemsetAsync(sp.xexp, 0, sizeof(int32_t) * kpad, st);
-  if (e == hipSuccess) {
+  hipError_t e = hipMemsetAsync(sp.xmaxp, 0, sizeof(double) * sp.kpad * np, st);
+  if (e == hipSuccess) e = hipMemsetAsync(sp.xexp, 0, sizeof(int32_t) * sp.kpad * np, st);
+  std::vector<RowItem> xm, xs;
+  for (int p = 0; p < np && e == hipSuccess; ++p) {
+    const refine_matrix& A = As[p];
+    const int64_t n = A.n;
+    const int nch = (int)((n + 31) / 32);
+    const int64_t rows_pad = (n + SPLIT_ROW_PAD - 1) / SPLIT_ROW_PAD * SPLIT_ROW_PAD;
     hipLaunchKernelGGL(split_aexp_kernel, dim3((unsigned)((rows_pad + 3) / 4)), dim3(256), 0, st,
-                       A.a, A.lda, (int)n, (int)rows_pad, sp.aexp);
+                       A.a, A.lda, (int)n, (int)rows_pad, sp.aexp + o_aexp[p]);
     e = hipGetLastError();
+    if (e == hipSuccess)
+      e = launch_aslice(s, A.a, A.lda, (int)n, nch, (int)rows_pad, sp.aexp + o_aexp[p],
+                        sp.asl + o_asl[p], st);
+    Prob& P = hp[p];
+    P.asl = sp.asl + o_asl[p];
+    P.asl_rs = (int64_t)nch * 32 * s;
+    P.aexp = sp.aexp + o_aexp[p];
+    P.xsl = sp.xsl + o_xsl[p];
+    P.xexp = sp.xexp + (size_t)sp.kpad * p;
+    P.xmaxp = sp.xmaxp + (size_t)sp.kpad * p;
+    P.swp = np == 1 ? sp.swp : nullptr;
+    P.nch = nch;
+    P.kpad = sp.kpad;
+    P.xrows = XROWS;
+    P.nbx = (int)((n + XROWS - 1) / XROWS);
+    for (int b = 0; b < P.nbx; ++b) xm.push_back(RowItem{p, b});
+    const int64_t units = (int64_t)nch * sp.kpad * 2;
+    for (int64_t b = 0; b < (units + 255) / 256; ++b) xs.push_back(RowItem{p, (int)b});
   }
-  if (e == hipSuccess)
-    e = launch_slicing(s, true, A.a, A.lda, (int)n, nch, (int)rows_pad, sp.aexp, sp.asl, nullptr,
-                       rows_pad * nch * 2, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = upload_vec(&sp.xmax_items, xm);
+  if (e == hipSuccess) e = upload_vec(&sp.xsl_items, xs);
   if (e != hipSuccess) {
     split_free(sp);
     return REFINE_EHIP;
   }
-  hp.asl = sp.asl;
-  hp.asl_rs = (int64_t)nch * 32 * s;
-  hp.aexp = sp.aexp;
-  hp.xsl = sp.xsl;
-  hp.xexp = sp.xexp;
-  hp.xmaxp = sp.xmaxp;
-  hp.swp = sp.swp;
-  hp.nch = nch;
-  hp.kpad = kpad;
-  hp.nbx = sp.nbx;
-  hp.xrows = sp.xrows;
+  sp.n_xmax = (int)xm.size();
+  sp.n_xsl = (int)xs.size();
 
-  // K split and tile-loading variant: REFINE_SPLIT_KS="ks[,variant]" forces
-  // them; otherwise every K split of 1, 2, 4, 8 whose K range fits the exact
-  // INT32 bins is timed with both variants, once per shape and process.
+  // K split (one problem only) and tile-loading variant: REFINE_SPLIT_KS=
+  // "ks[,variant]" forces them; otherwise the candidates (K splits 1, 2, 4, 8
+  // whose K range fits the exact INT32 bins; both variants) are timed once
+  // per shape and process.
   const int64_t kmax_range = max_k_range(s);
-  auto fits = [&](int ks) { return ((int64_t)nch + ks - 1) / ks * 32 <= kmax_range; };
+  int64_t nch_max = 0, nsum = 0;
+  for (const Prob& P : hp) {
+    nch_max = std::max<int64_t>(nch_max, P.nch);
+    nsum += P.n;
+  }
+  auto fits = [&](int ksp) { return (nch_max + ksp - 1) / ksp * 32 <= kmax_range; };
+  const int ks_cap = np == 1 ? SPLIT_KS_MAX : 1;
   int best_ks = 0, best_var = 0;
   if (const char* env = getenv("REFINE_SPLIT_KS")) {
-    int ks = 0, var = 0;
-    const int got = sscanf(env, "%d,%d", &ks, &var);
-    if (got >= 1 && ks >= 1 && ks <= SPLIT_KS_MAX && fits(ks) && var >= 0 && var <= 1) {
-      best_ks = ks;
+    int ksp = 0, var = 0;
+    const int got = sscanf(env, "%d,%d", &ksp, &var);
+    if (got >= 1 && ksp >= 1 && ksp <= ks_cap && fits(ksp) && var >= 0 && var <= 1) {
+      best_ks = ksp;
       best_var = got == 2 ? var : 0;
     }
   }
-  const SplitKey key{n, k, s};
+  const SplitKey key{np == 1 ? As[0].n : nsum, kmax, s, np};
   if (!best_ks) {
     auto hit = split_tune_cache().find(key);
     if (hit != split_tune_cache().end()) {
@@ -640,10 +712,12 @@ int split_init(SplitPlan& sp, const refine_matrix& A, int k, int slices, Prob& h
   }
   if (!best_ks) {
     // time on a zero X (the workspace copy of the update)
-    double* const saved_x = hp.x;
-    const int64_t saved_ldx = hp.ldx;
-    hp.x = hp.xn;
-    hp.ldx = k;
+    std::vector<std::pair<double*, int64_t>> saved;
+    for (Prob& P : hp) {
+      saved.push_back({P.x, P.ldx});
+      P.x = P.xn;
+      P.ldx = P.k;
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
       split_free(sp);
@@ -651,10 +725,10 @@ int split_init(SplitPlan& sp, const refine_matrix& A, int k, int slices, Prob& h
     }
     float best = 1e30f;
     for (int var = 0; var <= 1; ++var)
-      for (int ks = 1; ks <= SPLIT_KS_MAX; ks *= 2) {
-        if (!fits(ks)) continue;
+      for (int ksp = 1; ksp <= ks_cap; ksp *= 2) {
+        if (!fits(ksp)) continue;
         sp.variant = var;
-        int rc = install_items(sp, n, nch, ks, hp, dprob);
+        int rc = install_items(sp, ksp, hp, dprob);
         if (rc != REFINE_OK) {
           split_free(sp);
           return rc;
@@ -671,30 +745,32 @@ int split_init(SplitPlan& sp, const refine_matrix& A, int k, int slices, Prob& h
           return REFINE_EHIP;
         }
         if (getenv("REFINE_LOG") && atoi(getenv("REFINE_LOG")) >= 2)
-          fprintf(stderr, "refine: tune split n=%lld k=%d s=%d variant %d ks %d: %.1f us\n",
-                  (long long)n, k, s, var, ks, t * 1000.f / 3.f);
+          fprintf(stderr, "refine: tune split np=%d n=%lld k=%d s=%d variant %d ks %d: %.1f us\n",
+                  np, (long long)key.n, kmax, s, var, ksp, t * 1000.f / 3.f);
         if (t < best) {
           best = t;
-          best_ks = ks;
+          best_ks = ksp;
           best_var = var;
         }
       }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    hp.x = saved_x;
-    hp.ldx = saved_ldx;
+    for (size_t p = 0; p < hp.size(); ++p) {
+      hp[p].x = saved[p].first;
+      hp[p].ldx = saved[p].second;
+    }
     sp.ms = best / 3.f;
     split_tune_cache()[key] = {best_ks, best_var};
     if (getenv("REFINE_LOG"))
-      fprintf(stderr, "refine: split product n=%lld k=%d s=%d: variant %d, K split %d, %.1f us\n",
-              (long long)n, k, s, best_var, best_ks, best * 1000.f / 3.f);
+      fprintf(stderr, "refine: split product np=%d n=%lld k=%d s=%d: variant %d, K split %d, %.1f us\n",
+              np, (long long)key.n, kmax, s, best_var, best_ks, best * 1000.f / 3.f);
   }
   if (!best_ks) {
     split_free(sp);
     return REFINE_EINVAL;
   }
   sp.variant = best_var;
-  return install_items(sp, n, nch, best_ks, hp, dprob);
+  return install_items(sp, best_ks, hp, dprob);
 }
 
 void split_free(SplitPlan& sp) {
@@ -705,6 +781,8 @@ void split_free(SplitPlan& sp) {
   (void)hipFree(sp.xmaxp);
   (void)hipFree(sp.swp);
   (void)hipFree(sp.items);
+  (void)hipFree(sp.xmax_items);
+  (void)hipFree(sp.xsl_items);
   sp = SplitPlan();
 }
 

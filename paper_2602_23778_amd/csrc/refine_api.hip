@@ -691,7 +691,7 @@ int refine_init(refine_ctx** out, const refine_matrix* A, int32_t k, const refin
   std::vector<int> ks{k};
   rc = build_plan(c->plan, As, ks, opt, {c->mu}, {c->delta}, {c->norm_used});
   if (rc == REFINE_OK && c->plan.split) {
-    rc = split_init(c->plan.sp, *A, k, opt.slices > 0 ? opt.slices : SPLIT_S_DEFAULT, c->plan.hprob[0],
+    rc = split_init(c->plan.sp, {*A}, {k}, opt.slices > 0 ? opt.slices : SPLIT_S_DEFAULT, c->plan.hprob,
                     c->plan.dprob, c->stream);
   }
   if (rc == REFINE_OK) rc = capture_graph(c->plan, RUN_CHUNK);
@@ -831,7 +831,6 @@ int refine_batch_init(refine_batch** out, int32_t count, const refine_matrix* As
     opt = *optp;
   else
     refine_options_default(&opt);
-  if (opt.precision != REFINE_FP64) return REFINE_EINVAL;
   for (int p = 0; p < count; ++p) {
     if (As[p].kind != REFINE_DENSE) return REFINE_EINVAL;
     int rc = validate_matrix(&As[p], ks[p], opt);
@@ -857,6 +856,9 @@ int refine_batch_init(refine_batch** out, int32_t count, const refine_matrix* As
     deltas[p] = opt.delta_c * norms[p] * UNIT_ROUNDOFF;
   }
   int rc = build_plan(b->plan, b->As, b->ks, opt, mus, deltas, norms);
+  if (rc == REFINE_OK && b->plan.split)
+    rc = split_init(b->plan.sp, b->As, b->ks, opt.slices > 0 ? opt.slices : SPLIT_S_DEFAULT,
+                    b->plan.hprob, b->plan.dprob, b->stream);
   if (rc == REFINE_OK) rc = capture_graph(b->plan, BATCH_GRAPH_STEPS);
   if (rc == REFINE_OK && hipMalloc((void**)&b->d_xs, sizeof(double*) * 2 * count) != hipSuccess)
     rc = REFINE_ENOMEM;

@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "common.h"
 #include "refine.h"
 
@@ -26,31 +28,34 @@ constexpr int SPLIT_ROW_PAD = 256;
 
 struct SplitPlan {
   int s = 0;                  // slices per operand
-  int ks = 1;                 // K split
+  int ks = 1;                 // K split (one problem only)
   int variant = 0;            // 0: tiles staged through registers, 1: direct-to-LDS loads
   int bm = 0;                 // rows per block of the product
-  int64_t n = 0;
-  int k = 0;
-  int nch = 0;                // 32-wide contraction chunks
-  int kpad = 0;               // k rounded up to 32
-  int nbx = 0;                // blocks of the column-maximum pass
-  int xrows = 0;              // rows per such block
-  uint8_t* asl = nullptr;     // slices of A (s * rows_pad * nch * 32 bytes)
+  int kmax = 0;               // largest k of the problems
+  int kpad = 0;               // kmax rounded up to 32 (the column tile of every problem)
+  int np = 0;                 // problems
+  int64_t nk0 = 0;            // n k of problem 0 (K-split sum)
+  uint8_t* asl = nullptr;     // slices of every A (per problem s * rows_pad * nch * 32 bytes)
   int32_t* aexp = nullptr;    // per-row exponents
-  uint8_t* xsl = nullptr;     // slices of X^T (s * nch * kpad * 32 bytes)
-  int32_t* xexp = nullptr;
-  double* xmaxp = nullptr;    // column-maximum partials
-  double* swp = nullptr;      // K-split partials (hi, lo)
-  GemmItem* items = nullptr;
+  uint8_t* xsl = nullptr;     // slices of every X^T (per problem s * nch * kpad * 32 bytes)
+  int32_t* xexp = nullptr;    // per-column exponents, kpad per problem
+  double* xmaxp = nullptr;    // column maxima, kpad per problem
+  double* swp = nullptr;      // K-split partials (hi, lo), one problem only
+  GemmItem* items = nullptr;  // product work items
   int nitems = 0;
+  RowItem* xmax_items = nullptr;  // (problem, row block) of the column-maximum pass
+  int n_xmax = 0;
+  RowItem* xsl_items = nullptr;   // (problem, 256 units) of the X slicing pass
+  int n_xsl = 0;
   float ms = 0.f;             // product time measured by the tuner
 };
 
-// Slices A (read only here), chooses the K split, fills the split fields of
-// hp and uploads hp to dprob.  Returns a REFINE_* status.
-int split_init(SplitPlan& sp, const refine_matrix& A, int k, int slices, Prob& hp, Prob* dprob,
-               hipStream_t st);
-// Enqueues the whole split product for problem dprob[0]: column maxima and
+// Slices every A (read only here), chooses the K split (one problem) and the
+// tile-loading variant, fills the split fields of hp and uploads hp to dprob.
+// Returns a REFINE_* status.
+int split_init(SplitPlan& sp, const std::vector<refine_matrix>& As, const std::vector<int>& ks,
+               int slices, std::vector<Prob>& hp, Prob* dprob, hipStream_t st);
+// Enqueues the whole split product of every problem: column maxima and
 // slices of X, the INT8 products, and the K-split sum.
 hipError_t split_product(const SplitPlan& sp, const Prob* dprob, hipStream_t st);
 void split_free(SplitPlan& sp);
