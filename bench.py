@@ -1,18 +1,21 @@
-"""Benchmark of one refinement step (Algorithm 4 with Algorithm 1) on one MI355X.
+"""Benchmark of the refinement step (Algorithm 4 with Algorithm 1) on one MI355X.
 
-Workload (default): dense FP64, n = 8192, k = 64, A = Q diag(lam) Q^T with Q a
+Default workload: dense, n = 8192, k = 64, A = Q diag(lam) Q^T with Q a
 product of 8192 seeded Householder reflectors, lam log-spaced in [1e-3, 1]
 with the 64 targets separated by a factor 1.05 from the rest, X0 = true
 eigenvectors + N(0, 1e-7^2) noise, orthonormalised.  A step is the whole hot
 path: W = A X, Rayleigh quotients, residual, compact-WY factors, correction
-matrix, WY update and normalisation, replayed as one HIP graph.
+matrix, WY update and normalisation, replayed as one HIP graph.  `value` is
+the FP64 form's refined eigenvectors per second (k / seconds per step).  The
+split form (INT8 slices on the matrix cores, double-double W) runs on the
+same input and is reported in config.split with its speed ratio.
 
-`value` is the FP64 form's refined eigenvectors per second (k eigenvectors
-per step / seconds per step).  The split-precision form (INT8 slices on the
-matrix cores, double-double W) runs on the same workload and is reported in
-config.split with its speed ratio to the FP64 form and its error against the
-oracle.  --workload uniform_top selects the n = 16384, k = 128 uniform
-spectrum instead; --precision split makes the split form the timed one.
+Other workloads (--workload):
+  uniform_top  dense n = 16384, k = 128, targets 1e-3 apart;
+  laplacian    CSR 3-D Laplacian on a 128^3 grid (separable random diagonal),
+               k = 32 smallest through the Gershgorin shift;
+  batch        512 dense problems, n ~ U[128, 2048], k ~ U[4, 32], two target
+               clusters of gap 1e-6 each; 5 steps per graph; FP64 and split.
 
 Prints one JSON line.
 """
@@ -40,19 +43,19 @@ def _cores() -> int:
         return os.cpu_count() or 1
 
 
-def _problem(workload, n, k, dev):
-    import synth
-    if workload == "logspace":
-        P = synth.dense_logspace(n, k, device=dev, torch_out=True)
-        desc = ("dense, n=%d, k=%d, log-spaced spectrum in [1e-3, 1], separation ratio 1.05, "
-                "Householder Q" % (n, k))
-    elif workload == "uniform_top":
-        P = synth.dense_uniform_top(n, k, device=dev, torch_out=True)
-        desc = ("dense, n=%d, k=%d, rest U[0, 0.871), targets 0.872 + 1e-3 j, Householder Q"
-                % (n, k))
-    else:
-        raise SystemExit("unknown workload %s" % workload)
-    return P, desc
+def _aligned_err(g, o):
+    import numpy as np
+    s = np.sign(np.sum(g * o, 0))
+    s[s == 0] = 1.0
+    return float(np.max(np.abs(g * s - o)))
+
+
+def _orthogonality(X):
+    """max |X^T X - I| in extended precision on the host."""
+    import numpy as np
+    Xl = np.asarray(X, dtype=np.longdouble)
+    G = Xl.T @ Xl
+    return float(np.max(np.abs(G - np.eye(G.shape[0], dtype=np.longdouble))))
 
 
 def _time_steps(ctx, X, steps, warmup, torch):
@@ -70,45 +73,39 @@ def _time_steps(ctx, X, steps, warmup, torch):
     return sec, st1, st_last, X_first
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="logspace", choices=["logspace", "uniform_top"])
-    ap.add_argument("--n", type=int, default=0, help="default 8192 (logspace), 16384 (uniform_top)")
-    ap.add_argument("--k", type=int, default=0, help="default 64 (logspace), 128 (uniform_top)")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "split"])
-    ap.add_argument("--slices", type=int, default=9)
-    ap.add_argument("--no-split", action="store_true", help="skip the split-form comparison")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--product-reps", type=int, default=20)
-    ap.add_argument("--product-only", action="store_true",
-                    help="counter runs: one copy of A (a plain copy kernel of known size, "
-                         "for calibrating byte counters) then --product-reps launches of the "
-                         "product alone; prints their mean time")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
-        return 2
+def _traffic_for(n, k):
+    """HBM bytes per launch of the dense FP64 product from the committed
+    counter summary, when it was taken on this workload and kernel source."""
+    import hashlib
+    tpath = os.path.join(ROOT, "profiles", "traffic_gemm_f64_dense_n8192_k64.json")
+    if (n, k) != (8192, 64) or not os.path.exists(tpath):
+        return None
+    try:
+        with open(tpath) as f:
+            tj = json.load(f)
+        with open(os.path.join(ROOT, "paper_2602_23778_amd", "csrc", "k_gemm.hip"), "rb") as f:
+            h = hashlib.sha256(f.read()).hexdigest()
+        return tj.get("bytes_per_launch") if tj.get("kernel_source_sha256") == h else None
+    except Exception:
+        return None
 
-    import numpy as np
-    import torch
 
-    import paper_2602_23778_amd as rf
-
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    rf.load_library()
+def bench_dense(args, rf, torch, np):
+    import synth
     dev = "cuda:0"
-    n = args.n or (8192 if args.workload == "logspace" else 16384)
-    k = args.k or (64 if args.workload == "logspace" else 128)
-    t0 = time.time()
-    P, desc = _problem(args.workload, n, k, dev)
+    if args.workload == "logspace":
+        n, k = args.n or 8192, args.k or 64
+        P = synth.dense_logspace(n, k, device=dev, torch_out=True)
+        desc = ("dense, n=%d, k=%d, log-spaced spectrum in [1e-3, 1], separation ratio 1.05, "
+                "Householder Q" % (n, k))
+    else:
+        n, k = args.n or 16384, args.k or 128
+        P = synth.dense_uniform_top(n, k, device=dev, torch_out=True)
+        desc = ("dense, n=%d, k=%d, rest U[0, 0.871), targets 0.872 + 1e-3 j, Householder Q"
+                % (n, k))
     A = P.A
     X0 = P.X0.to(dev).contiguous()
     torch.cuda.synchronize()
-    print("input ready in %.1f s" % (time.time() - t0), file=sys.stderr, flush=True)
 
     main_prec = "split_int8" if args.precision == "split" else "fp64"
     slices = args.slices if main_prec == "split_int8" else 0
@@ -122,45 +119,25 @@ def main() -> int:
         print(json.dumps({"product_ms": ms, "n": n, "k": k, "precision": main_prec,
                           "slices": slices, "copy_bytes": 8 * n * n}), flush=True)
         ctx.close()
-        return 0
-
-    sec_per_step, st1, st_last, X_first = _time_steps(ctx, X, args.steps, args.warmup, torch)
-    value = k / sec_per_step
-
+        return None
+    sec, st1, st_last, X_first = _time_steps(ctx, X, args.steps, args.warmup, torch)
+    value = k / sec
     # dominant kernel: the product W = A X, timed with HIP events on the
     # context's stream, same launch configuration as inside the step
     ms_prod = ctx.time_product(X0.clone(), args.product_reps)
     ctx.close()
     flops = 2.0 * n * n * k
-    eff_tflops = flops / (ms_prod * 1e-3) / 1e12
+    eff = flops / (ms_prod * 1e-3) / 1e12
     if main_prec == "fp64":
-        roof = {"bound": "mfma", "achieved": eff_tflops, "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": eff_tflops / FP64_PEAK_TFLOPS}
+        roof = {"bound": "mfma", "achieved": eff, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": eff / FP64_PEAK_TFLOPS, "traffic": _traffic_for(n, k)}
     else:
-        # INT8 operations actually issued: s(s+1)/2 digit products of 2 n^2 k each
         tops = slices * (slices + 1) / 2 * flops / (ms_prod * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": tops, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
-                "frac": tops / INT8_PEAK_TOPS}
-    print("product %.1f us: %.1f eff TFLOP/s" % (ms_prod * 1e3, eff_tflops),
-          file=sys.stderr, flush=True)
+                "frac": tops / INT8_PEAK_TOPS, "traffic": None}
 
-    traffic = None
-    tpath = os.path.join(ROOT, "profiles", "traffic_gemm_f64_dense_n8192_k64.json")
-    if main_prec == "fp64" and os.path.exists(tpath) and (n, k) == (8192, 64):
-        try:
-            import hashlib
-            with open(tpath) as f:
-                tj = json.load(f)
-            with open(os.path.join(ROOT, "paper_2602_23778_amd", "csrc", "k_gemm.hip"), "rb") as f:
-                h = hashlib.sha256(f.read()).hexdigest()
-            if tj.get("kernel_source_sha256") == h:
-                traffic = tj.get("bytes_per_launch")
-        except Exception:
-            traffic = None
-    roof["traffic"] = traffic
-
-    # the other form on the same workload, for the split-vs-FP64 ratio
     other = None
+    Xo_first = None
     if not args.no_split:
         oprec = "fp64" if main_prec == "split_int8" else "split_int8"
         oslices = 0 if oprec == "fp64" else args.slices
@@ -172,12 +149,13 @@ def main() -> int:
         other = {"precision": oprec, "slices": oslices, "eigvecs_per_s": k / osec,
                  "ms_per_step": osec * 1e3, "product_us": oms * 1e3,
                  "product_eff_gflops": flops / (oms * 1e-3) / 1e9,
-                 "corr_fro_last": ost_last.corr_fro}
-        s1 = torch.sign((X_first * Xo_first).sum(0))
-        other["max_dx_first_step_vs_main"] = float((X_first - Xo_first * s1).abs().max())
+                 "corr_fro_last": ost_last.corr_fro,
+                 "orthogonality_last": _orthogonality(Xo.cpu().numpy())}
+        other["max_dx_first_step_vs_main"] = _aligned_err(X_first.cpu().numpy(),
+                                                          Xo_first.cpu().numpy())
 
     cpu = None
-    err = None
+    errs = {}
     if not args.no_cpu_baseline:
         import oracle
         A_h = A.cpu().numpy()
@@ -186,11 +164,15 @@ def main() -> int:
         r = oracle.refine_step(A_h, X0_h, norm_a=P.norm_a)
         t_cpu = time.perf_counter() - ts
         g = X_first.cpu().numpy()
-        s = np.sign(np.sum(g * r.X, 0))
-        err = float(np.max(np.abs(g * s - r.X)))
+        errs["err_vs_fp64_oracle_first_step"] = _aligned_err(g, r.X)
         cpu = {"value": k / t_cpu, "unit": "eigvecs/s", "cores": _cores(), "kind": "oracle",
                "sample": "one full FP64 oracle step of the same workload (n=%d, k=%d), %.1f s"
                          % (n, k, t_cpu)}
+        if args.dd_check:
+            rd = oracle.refine_step(A_h, X0_h, norm_a=P.norm_a, dd=True)
+            errs["err_vs_dd_oracle_first_step"] = _aligned_err(g, rd.X)
+            if Xo_first is not None:
+                other["err_vs_dd_oracle_first_step"] = _aligned_err(Xo_first.cpu().numpy(), rd.X)
 
     split_block = None
     if other is not None:
@@ -200,31 +182,196 @@ def main() -> int:
         else:
             split_block = {"fp64": other,
                            "speed_ratio_split_over_fp64": value / other["eigvecs_per_s"]}
+    cfg = {"workload": ("%s form, " % ("FP64 plain" if main_prec == "fp64" else
+                                       "split INT8 s=%d" % slices)) + desc,
+           "n": n, "k": k, "precision": main_prec,
+           "product_us": ms_prod * 1e3, "product_eff_gflops": eff * 1e3,
+           "corr_fro_first": st1.corr_fro, "corr_fro_last": st_last.corr_fro,
+           "resid_rel_last": st_last.resid_rel,
+           "orthogonality_last": _orthogonality(X.cpu().numpy()),
+           "split": split_block}
+    cfg.update(errs)
+    return {"value": value, "ms_per_step": sec * 1e3, "unit": "eigvecs/s",
+            "dtype": "f64" if main_prec == "fp64" else "i8", "config": cfg, "roofline": roof,
+            "cpu_baseline": cpu}
 
+
+def bench_laplacian(args, rf, torch, np):
+    import synth
+    N = args.n or 128
+    k = args.k or 32
+    L, lam, Xt, X0h = synth.laplacian3d_separable(N, k)
+    n, nnz = L.n, len(L.val)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a)).cuda()
+    C = rf.CsrMatrix(n, dev(L.row_ptr), dev(L.col_idx), dev(L.val))
+    ctx = rf.RefineContext(C, k, target="smallest", norm_a=L.sigma)
+    X0 = dev(X0h)
+    X = X0.clone()
+    sec, st1, st_last, X_first = _time_steps(ctx, X, args.steps, args.warmup, torch)
+    ms_prod = ctx.time_product(X0.clone(), args.product_reps)
+    ctx.close()
+    byts = 12.0 * nnz + 4.0 * (n + 1) + 16.0 * n * k
+    gbs = byts / (ms_prod * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "traffic": None}
+    Xg = X.cpu().numpy()
+    cfg = {"workload": "CSR FP64, 3-D 7-point Laplacian %d^3 (n=%d, nnz=%d), diagonal 6 + "
+                       "dx+dy+dz with d* iid U[0, 1/3), k=%d smallest via the Gershgorin shift"
+                       % (N, n, nnz, k),
+           "n": n, "k": k, "nnz": nnz, "precision": "fp64",
+           "product_us": ms_prod * 1e3,
+           "product_eff_gflops": 2.0 * nnz * k / (ms_prod * 1e-3) / 1e9,
+           "corr_fro_first": st1.corr_fro, "corr_fro_last": st_last.corr_fro,
+           "resid_rel_last": st_last.resid_rel,
+           "err_vs_exact_eigvecs_last": _aligned_err(Xg, Xt),
+           "err_vs_exact_eigvecs_start": _aligned_err(X0h, Xt)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        Co = oracle.Csr(n, L.row_ptr, L.col_idx, L.val)
+        ts = time.perf_counter()
+        # the library's shift for target="smallest" is the Gershgorin upper bound
+        r = oracle.refine_step(Co, X0h, mu=L.sigma, norm_a=L.sigma)
+        t_cpu = time.perf_counter() - ts
+        cfg["err_vs_fp64_oracle_first_step"] = _aligned_err(X_first.cpu().numpy(), r.X)
+        cpu = {"value": k / t_cpu, "unit": "eigvecs/s", "cores": _cores(), "kind": "oracle",
+               "sample": "one full FP64 oracle step of the same workload, %.1f s" % t_cpu}
+    return {"value": k / sec, "ms_per_step": sec * 1e3, "unit": "eigvecs/s", "dtype": "f64",
+            "config": cfg, "roofline": roof, "cpu_baseline": cpu}
+
+
+def bench_batch(args, rf, torch, np):
+    import synth
+    count = args.count
+    probs = synth.batch_problems(count, device="cuda", torch_out=True)
+    torch.cuda.synchronize()
+    As = [p.A for p in probs]
+    ks = [int(p.X0.shape[1]) for p in probs]
+    ns = [int(p.A.shape[0]) for p in probs]
+    X0s = [p.X0.cuda().contiguous() for p in probs]
+    ksum = sum(ks)
+    steps_per_graph = 5
+    reps = max(1, args.steps // steps_per_graph)
+    res = {}
+    for prec in ("fp64", "split_int8"):
+        b = rf.RefineBatch(As, ks, norm_a=1.0, precision=prec,
+                           slices=args.slices if prec == "split_int8" else 0)
+        Xs = [x.clone() for x in X0s]
+        rc, _ = b.run(Xs, steps_per_graph)
+        first = [x.clone() for x in Xs]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            b.run(Xs, steps_per_graph, sync=False)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / (reps * steps_per_graph)
+        ms_prod = b.time_product(args.product_reps)
+        b.close()
+        res[prec] = {"sec": sec, "first": first, "rc": rc, "ms_prod": ms_prod}
+    byts = sum(8.0 * n * n for n in ns)
+    main = res["fp64"]
+    gbs = byts / (main["ms_prod"] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "traffic": None}
+    sample = list(range(min(args.sample, count)))
+    cfg = {"workload": "batch of %d dense problems, n ~ U[128, 2048], k ~ U[4, 32], two target "
+                       "clusters of internal gap 1e-6, 5 steps per graph, FP64 form" % count,
+           "problems": count, "sum_k": ksum, "mean_n2": float(np.mean(np.array(ns, float) ** 2)),
+           "precision": "fp64", "product_us": main["ms_prod"] * 1e3,
+           "split": {"slices": args.slices, "eigvecs_per_s": ksum / res["split_int8"]["sec"],
+                     "ms_per_step": res["split_int8"]["sec"] * 1e3,
+                     "product_us": res["split_int8"]["ms_prod"] * 1e3,
+                     "speed_ratio_split_over_fp64": main["sec"] / res["split_int8"]["sec"]}}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        e64, esp = [], []
+        ts = time.perf_counter()
+        tcpu = 0.0
+        for p in sample:
+            A_h = probs[p].A.cpu().numpy()
+            X_h = probs[p].X0.cpu().numpy()
+            t1 = time.perf_counter()
+            Xd, _ = oracle.refine(A_h, X_h, steps_per_graph, norm_a=1.0, dd=True)
+            tcpu += time.perf_counter() - t1
+            e64.append(_aligned_err(res["fp64"]["first"][p].cpu().numpy(), Xd))
+            esp.append(_aligned_err(res["split_int8"]["first"][p].cpu().numpy(), Xd))
+        cfg["err_vs_dd_oracle_5_steps_fp64_max"] = max(e64)
+        cfg["split"]["err_vs_dd_oracle_5_steps_max"] = max(esp)
+        cfg["err_sample"] = "problems 0..%d, 5 steps each, double-double oracle" % (len(sample) - 1)
+        kk = sum(ks[p] for p in sample) * steps_per_graph
+        cpu = {"value": kk / tcpu, "unit": "eigvecs/s", "cores": _cores(), "kind": "oracle",
+               "sample": "double-double oracle, 5 steps of problems 0..%d (%.1f s)"
+                         % (len(sample) - 1, tcpu)}
+    return {"value": ksum / main["sec"], "ms_per_step": main["sec"] * 1e3, "unit": "eigvecs/s",
+            "dtype": "f64", "config": cfg, "roofline": roof, "cpu_baseline": cpu}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="logspace",
+                    choices=["logspace", "uniform_top", "laplacian", "batch"])
+    ap.add_argument("--n", type=int, default=0,
+                    help="dense n (default 8192 / 16384) or the Laplacian grid side (128)")
+    ap.add_argument("--k", type=int, default=0)
+    ap.add_argument("--count", type=int, default=512, help="batch: number of problems")
+    ap.add_argument("--sample", type=int, default=8, help="batch: problems checked on the CPU")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "split"])
+    ap.add_argument("--slices", type=int, default=0,
+                    help="split slices (default 9; 10 for the clustered batch)")
+    ap.add_argument("--no-split", action="store_true", help="skip the split-form comparison")
+    ap.add_argument("--dd-check", action="store_true",
+                    help="dense: also compare the first step with the double-double oracle")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--product-reps", type=int, default=20)
+    ap.add_argument("--product-only", action="store_true",
+                    help="counter runs (dense): one copy of A (a plain copy kernel of known "
+                         "size, for calibrating byte counters) then --product-reps launches of "
+                         "the product alone; prints their mean time")
+    args = ap.parse_args()
+    if args.slices == 0:
+        args.slices = 10 if args.workload == "batch" else 9
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2602_23778_amd as rf
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    rf.load_library()
+    t0 = time.time()
+    if args.workload in ("logspace", "uniform_top"):
+        r = bench_dense(args, rf, torch, np)
+        if r is None:
+            return 0
+    elif args.workload == "laplacian":
+        r = bench_laplacian(args, rf, torch, np)
+    else:
+        r = bench_batch(args, rf, torch, np)
+    print("bench done in %.1f s" % (time.time() - t0), file=sys.stderr, flush=True)
     out = {
         "metric": METRIC,
-        "value": value,
-        "unit": "eigvecs/s",
+        "value": r["value"],
+        "unit": r["unit"],
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": sec_per_step * 1e3,
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if main_prec == "fp64" else "i8",
+        "dtype": r["dtype"],
         "data": "synthetic",
-        "config": {"workload": ("%s form, " % ("FP64 plain" if main_prec == "fp64" else
-                                               "split INT8 s=%d" % slices)) + desc,
-                   "n": n, "k": k, "precision": main_prec,
-                   "product_us": ms_prod * 1e3,
-                   "product_eff_gflops": eff_tflops * 1e3,
-                   "err_vs_oracle_first_step": err,
-                   "corr_fro_first": st1.corr_fro, "corr_fro_last": st_last.corr_fro,
-                   "resid_rel_last": st_last.resid_rel,
-                   "split": split_block},
-        "roofline": roof,
-        "cpu_baseline": cpu,
+        "config": r["config"],
+        "roofline": r["roofline"],
+        "cpu_baseline": r["cpu_baseline"],
     }
     print(json.dumps(out), flush=True)
     return 0

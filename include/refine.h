@@ -184,6 +184,12 @@ int refine_batch_run(refine_batch* b, double* const* Xs, const int64_t* ldxs,
 
 int refine_batch_destroy(refine_batch* b);
 
+/* Measurement hook, as refine_time_product for a batch: `reps` launches of
+ * the grouped product of all problems (with the X pointers of the last
+ * refine_batch_run; in split mode with the slicing of every X), mean time of
+ * one launch in *ms.  Call it between runs. */
+int refine_batch_time_product(refine_batch* b, int32_t reps, float* ms);
+
 /* Static string for a status code. */
 const char* refine_status_string(int status);
 

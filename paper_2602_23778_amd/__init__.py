@@ -59,7 +59,8 @@ class refine_stats(ctypes.Structure):
 
 EXPORTS = ("refine_options_default", "refine_init", "refine_step", "refine_run",
            "refine_get_info", "refine_destroy", "refine_batch_init", "refine_batch_run",
-           "refine_batch_destroy", "refine_status_string", "refine_time_product")
+           "refine_batch_destroy", "refine_status_string", "refine_time_product",
+           "refine_batch_time_product")
 
 _lib = None
 
@@ -92,12 +93,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.refine_batch_run.argtypes = [vp, P(vp), P(i64), i32, P(refine_stats)]
     lib.refine_batch_destroy.argtypes = [vp]
     lib.refine_time_product.argtypes = [vp, vp, i64, i32, P(ctypes.c_float)]
+    lib.refine_batch_time_product.argtypes = [vp, i32, P(ctypes.c_float)]
     lib.refine_debug_workspace.argtypes = [vp, P(vp), i32]
     lib.refine_debug_workspace.restype = ctypes.c_int
     lib.refine_status_string.argtypes = [ctypes.c_int]
     lib.refine_status_string.restype = ctypes.c_char_p
     for name in ("refine_init", "refine_step", "refine_run", "refine_get_info", "refine_destroy",
                  "refine_batch_init", "refine_batch_run", "refine_batch_destroy",
+                 "refine_batch_time_product",
                  "refine_time_product"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -140,6 +143,12 @@ def refine_get_info(ctx):
 def refine_time_product(ctx, X_ptr: int, ldx: int, reps: int):
     ms = ctypes.c_float()
     rc = _l().refine_time_product(ctx, X_ptr, ldx, reps, ctypes.byref(ms))
+    return rc, ms.value
+
+
+def refine_batch_time_product(b, reps: int):
+    ms = ctypes.c_float()
+    rc = _l().refine_batch_time_product(b, reps, ctypes.byref(ms))
     return rc, ms.value
 
 
@@ -347,6 +356,13 @@ class RefineBatch:
         per = (refine_stats * n)()
         rc = refine_batch_run(self._b, ptrs, lds, iters, per)
         return rc, [Stats(p.corr_fro, p.resid_rel, p.iters, p.status) for p in per]
+
+    def time_product(self, reps: int) -> float:
+        """Mean milliseconds of one grouped product launch (X of the last run)."""
+        rc, ms = refine_batch_time_product(self._b, reps)
+        if rc != OK:
+            raise RefineError(rc, "refine_batch_time_product")
+        return ms
 
     def close(self):
         if self._b:

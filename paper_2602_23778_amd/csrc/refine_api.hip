@@ -922,6 +922,34 @@ int refine_batch_run(refine_batch* b, double* const* Xs, const int64_t* ldxs, in
   return worst;
 }
 
+int refine_batch_time_product(refine_batch* b, int32_t reps, float* ms) {
+  if (!b || reps <= 0 || !ms) return REFINE_EINVAL;
+  for (double* x : b->cur_x)
+    if (!x) return REFINE_EINVAL;  // no X bound yet
+  Plan& pl = b->plan;
+  const int np = (int)pl.hprob.size();
+  hipEvent_t e0, e1;
+  RF_CHECK(hipEventCreate(&e0));
+  RF_CHECK(hipEventCreate(&e1));
+  hipError_t e = hipSuccess;
+  if (launch_ctrl_reset(pl.dprob, np, 0, 0.0, b->stream) != hipSuccess) e = hipErrorUnknown;
+  if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+  for (int i = 0; i < reps && e == hipSuccess; ++i)
+    e = pl.split ? split_product(pl.sp, pl.dprob, b->stream)
+                 : launch_gemm_f64(pl.dprob, pl.gemm_items, pl.n_gemm, pl.kmax, pl.vec2, pl.gemm_cfg,
+                                   b->stream);
+  if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return REFINE_EHIP;
+  *ms = t / (float)reps;
+  if (launch_ctrl_reset(pl.dprob, np, 0, 0.0, b->stream) != hipSuccess) return REFINE_EHIP;
+  return REFINE_OK;
+}
+
 int refine_batch_destroy(refine_batch* b) {
   if (!b) return REFINE_EINVAL;
   (void)hipStreamSynchronize(b->stream);
