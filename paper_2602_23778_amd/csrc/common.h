@@ -70,8 +70,10 @@ struct Prob {
   int32_t beta_zero;
   int32_t normalize;
   // split form of the dense product (INT8 slices); unused otherwise
-  const uint8_t* asl;     // slices of A: row i, chunk c at asl + i*asl_rs + c*32*s
-  int64_t asl_rs;         // bytes per row of asl (nch chunks)
+  const uint8_t* asl;     // slices of A in tiles of bm rows x 32 columns: the row block
+                          // starting at row i0 at asl + i0*asl_rs, its chunk c, row r at
+                          // + (c*bm + r)*32*s
+  int64_t asl_rs;         // bytes of asl per row of A (nch chunks)
   const int32_t* aexp;    // per-row scale exponents of A (rows padded with 0)
   uint8_t* xsl;           // slices of X^T: chunk c, column j at xsl + (c*kpad + j)*32*s
   int32_t* xexp;          // per-column scale exponents of X (kpad entries)

@@ -19,9 +19,12 @@
 // the K-split lengths the host allows.
 //
 // Layouts (bytes).  A slice unit = 16 consecutive columns of one row in one
-// plane.  A row holds nch = ceil(n/32) chunks of 32 columns; a chunk holds its
-// two halves, each as s planes of 16 bytes: row i, chunk c, half h, plane p at
-//     asl + i*(nch*32*s) + c*32*s + h*16*s + p*16.
+// plane.  A row of a chunk of 32 columns holds the chunk's two halves, each as
+// s planes of 16 bytes; the rows of one row block (bm rows, the product's
+// block height) and one chunk are stored together, chunks of a row block one
+// after another, so that the product reads each A tile as one contiguous
+// run (nch = ceil(n/32); row i = bm*b + r, chunk c, half h, plane p at)
+//     asl + ((b*nch + c)*bm + r)*32*s + h*16*s + p*16.
 // X^T is stored the same way with the column j of X as the "row", the chunks
 // outermost so that one chunk of all kpad columns is contiguous:
 //     xsl + (c*kpad + j)*32*s + h*16*s + q*16.
@@ -105,11 +108,10 @@ __global__ __launch_bounds__(256) void split_aexp_kernel(const double* __restric
 template <int S>
 __global__ __launch_bounds__(256) void split_aslice_kernel(const double* __restrict__ a,
                                                            int64_t lda, int n, int nch,
-                                                           int rows_pad,
+                                                           int rows_pad, int bm,
                                                            const int32_t* __restrict__ aexp,
                                                            uint8_t* __restrict__ asl) {
   const int64_t units = (int64_t)rows_pad * nch * 2;
-  const int64_t rs = (int64_t)nch * 32 * S;
   for (int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x; u < units;
        u += (int64_t)gridDim.x * 256) {
     const int row = (int)(u / (2 * nch));
@@ -121,7 +123,9 @@ __global__ __launch_bounds__(256) void split_aslice_kernel(const double* __restr
       v[b] = (row < n && col0 + b < n) ? a[(int64_t)row * lda + col0 + b] : 0.0;
     u4v out[S];
     digits16<S>(v, aexp[row], out);
-    u4v* dst = reinterpret_cast<u4v*>(asl + row * rs + (int64_t)cu * 16 * S);
+    const int rb = row / bm, c = cu >> 1;
+    u4v* dst = reinterpret_cast<u4v*>(
+        asl + (((int64_t)rb * nch + c) * bm + (row - rb * bm)) * (32 * S) + (cu & 1) * 16 * S);
 #pragma unroll
     for (int p = 0; p < S; ++p) dst[p] = out[p];
   }
@@ -201,6 +205,79 @@ __global__ __launch_bounds__(256) void split_xslice_kernel(const Prob* __restric
 // The product
 // ---------------------------------------------------------------------------
 
+// Epilogue of one work item.  Register r of bin t holds B_t[j][i] for the
+// column j = 32 wj + mfma32_row(lane, r) of W and the row i = row0 + 32 wi +
+// l32.  Each (hi, lo) goes straight to the wavefront's two LDS transpose
+// tiles, so that 32 lanes then write 32 consecutive columns of a row.  The
+// LDS tiles must be idle on entry (every wave past the last barrier, no
+// direct-to-LDS load in flight).
+template <int S, int WM, int WN>
+__device__ __forceinline__ void split_epilogue(const Prob& P, const GemmItem& item, v16i (&acc)[S],
+                                               uint8_t* smem) {
+  constexpr int NW = WM * WN, BM = 32 * WM, BN = 32 * WN;
+  constexpr int TT = 32 * 33;  // transpose tile (doubles)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wi = wave / WN, wj = wave % WN;
+  const int l32 = lane & 31, hh = lane >> 5;
+  const int n = P.n, k = P.k, row0 = item.row0;
+  const int ea = *gld(P.aexp + row0 + wi * 32 + l32);
+  double* Th = reinterpret_cast<double*>(smem) + wave * 2 * TT;
+  double* Tl = Th + TT;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    double h = (double)acc[S - 1][r], l = 0.0;
+#pragma unroll
+    for (int t = S - 2; t >= 0; --t) {
+      double s, e;
+      two_sum((double)acc[t][r], h * 0x1p-7, s, e);
+      l = __builtin_fma(l, 0x1p-7, e);
+      two_sum(s, l, h, l);
+    }
+    const int jr = mfma32_row(lane, r);
+    const int sc = ea + *gld(P.xexp + wj * 32 + jr) - 12;
+    Th[l32 * 33 + jr] = ldexp(h, sc);
+    Tl[l32 * 33 + jr] = ldexp(l, sc);
+  }
+  __builtin_amdgcn_wave_barrier();
+  const bool part = P.ksplit > 1;
+  double* __restrict__ out_hi = part ? P.swp + (int64_t)item.split * 2 * n * k : P.w;
+  double* __restrict__ out_lo = part ? out_hi + (int64_t)n * k : P.wlo;
+  double* red = reinterpret_cast<double*>(smem) + NW * 2 * TT;  // [WM][2][BN]
+  const int col = wj * 32 + l32;
+  double sxw = 0.0, sxx = 0.0;
+#pragma unroll 4
+  for (int v = 0; v < 16; ++v) {
+    const int il = 2 * v + hh;
+    const int row = row0 + wi * 32 + il;
+    if (row < n && col < k) {
+      const double w = Th[il * 33 + l32];
+      *gst(out_hi + (int64_t)row * k + col) = w;
+      *gst(out_lo + (int64_t)row * k + col) = Tl[il * 33 + l32];
+      const double x = *gld(P.x + (int64_t)row * P.ldx + col);
+      sxw = __builtin_fma(x, w, sxw);
+      sxx = __builtin_fma(x, x, sxx);
+    }
+  }
+  // Rayleigh partials (x*w_hi over the block's rows; x*x for the first K range)
+  sxw += __shfl_xor(sxw, 32);
+  sxx += __shfl_xor(sxx, 32);
+  if (lane < 32) {
+    red[(wi * 2) * BN + col] = sxw;
+    red[(wi * 2 + 1) * BN + col] = sxx;
+  }
+  __syncthreads();
+  if (tid < k) {
+    double a = 0.0, b = 0.0;
+    for (int w = 0; w < WM; ++w) {
+      a += red[(w * 2) * BN + tid];
+      b += red[(w * 2 + 1) * BN + tid];
+    }
+    double* dst = P.dpart + (int64_t)(row0 / BM * P.ksplit + item.split) * 2 * k;
+    *gst(dst + tid) = a;
+    *gst(dst + k + tid) = item.split == 0 ? b : 0.0;
+  }
+}
+
 // Block = WM x WN wavefronts; wavefront (wi, wj) owns rows row0 + 32 wi ..
 // +31 of W and columns 32 wj .. +31 (BN = 32 WN = kpad).  Per 32-wide
 // contraction chunk the block stages the A tile (BM rows) and the X^T tile
@@ -259,7 +336,7 @@ __global__ __launch_bounds__(WM* WN * 64) void gemm_split_kernel(const Prob* __r
         if (e < UA) {
           const int row = e / (2 * S), part = e - row * (2 * S);
           stg[u] = __builtin_nontemporal_load(
-              gld(reinterpret_cast<const u4v*>(Ab + row * rs + (int64_t)c * UB + part * 16)));
+              gld(reinterpret_cast<const u4v*>(Ab + ((int64_t)c * BM + row) * UB + part * 16)));
         } else if (e < UA + UX) {
           stg[u] = *gld(reinterpret_cast<const u4v*>(Xb + (int64_t)c * BN * UB + (e - UA) * 16));
         }
@@ -291,7 +368,7 @@ __global__ __launch_bounds__(WM* WN * 64) void gemm_split_kernel(const Prob* __r
           const int f = ii * 64 + lane;
           const int row = f / SROW, part = f - row * SROW;
           if (f < TSLOTS && part < 2 * S) {
-            const uint8_t* src = row < BM ? Ab + row * rs + (int64_t)c * UB + part * 16
+            const uint8_t* src = row < BM ? Ab + ((int64_t)c * BM + row) * UB + part * 16
                                           : Xb + ((int64_t)c * BN + (row - BM)) * UB + part * 16;
             __builtin_amdgcn_global_load_lds(
                 (const RFK_GLOBAL void*)src,
@@ -337,66 +414,199 @@ __global__ __launch_bounds__(WM* WN * 64) void gemm_split_kernel(const Prob* __r
       __syncthreads();
     }
 
-    // Epilogue.  Register r of bin t holds B_t[j][i] for the column
-    // j = 32 wj + mfma32_row(lane, r) of W and the row i = row0 + 32 wi + l32.
-    // Each (hi, lo) goes straight to the wavefront's two LDS transpose tiles,
-    // so that 32 lanes then write 32 consecutive columns of a row.
-    const int ea = *gld(P.aexp + row0 + wi * 32 + l32);
-    double* Th = reinterpret_cast<double*>(smem) + wave * 2 * TT;
-    double* Tl = Th + TT;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      double h = (double)acc[S - 1][r], l = 0.0;
-#pragma unroll
-      for (int t = S - 2; t >= 0; --t) {
-        double s, e;
-        two_sum((double)acc[t][r], h * 0x1p-7, s, e);
-        l = __builtin_fma(l, 0x1p-7, e);
-        two_sum(s, l, h, l);
-      }
-      const int jr = mfma32_row(lane, r);
-      const int sc = ea + *gld(P.xexp + wj * 32 + jr) - 12;
-      Th[l32 * 33 + jr] = ldexp(h, sc);
-      Tl[l32 * 33 + jr] = ldexp(l, sc);
-    }
-    __builtin_amdgcn_wave_barrier();
-    const bool part = P.ksplit > 1;
-    double* __restrict__ out_hi = part ? P.swp + (int64_t)item.split * 2 * n * k : P.w;
-    double* __restrict__ out_lo = part ? out_hi + (int64_t)n * k : P.wlo;
-    double* red = reinterpret_cast<double*>(smem) + NW * 2 * TT;  // [WM][2][BN]
-    const int col = wj * 32 + l32;
-    double sxw = 0.0, sxx = 0.0;
-#pragma unroll 4
-    for (int v = 0; v < 16; ++v) {
-      const int il = 2 * v + hh;
-      const int row = row0 + wi * 32 + il;
-      if (row < n && col < k) {
-        const double w = Th[il * 33 + l32];
-        *gst(out_hi + (int64_t)row * k + col) = w;
-        *gst(out_lo + (int64_t)row * k + col) = Tl[il * 33 + l32];
-        const double x = *gld(P.x + (int64_t)row * P.ldx + col);
-        sxw = __builtin_fma(x, w, sxw);
-        sxx = __builtin_fma(x, x, sxx);
-      }
-    }
-    // Rayleigh partials (x*w_hi over the block's rows; x*x for the first K range)
-    sxw += __shfl_xor(sxw, 32);
-    sxx += __shfl_xor(sxx, 32);
-    if (lane < 32) {
-      red[(wi * 2) * BN + col] = sxw;
-      red[(wi * 2 + 1) * BN + col] = sxx;
-    }
+    split_epilogue<S, WM, WN>(P, item, acc, smem);
     __syncthreads();
-    if (tid < k) {
-      double a = 0.0, b = 0.0;
-      for (int w = 0; w < WM; ++w) {
-        a += red[(w * 2) * BN + tid];
-        b += red[(w * 2 + 1) * BN + tid];
-      }
-      double* dst = P.dpart + (int64_t)(row0 / BM * P.ksplit + item.split) * 2 * k;
-      *gst(dst + tid) = a;
-      *gst(dst + k + tid) = item.split == 0 ? b : 0.0;
+  }
+}
+
+// Word 3 of a raw buffer resource on gfx9 (32-bit data format, no swizzle).
+#define RFK_BUFFER_FLAGS 0x00020000
+
+// One 16-byte-per-lane buffer load straight into LDS: lane l's bytes at
+// rsrc base + voff + soff land at lds + 16 l.
+__device__ __forceinline__ void buffer_load_lds16(__amdgpu_buffer_rsrc_t r, uint8_t* lds,
+                                                  uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)lds, 16,
+                                           voff, soff, 0, 0);
+}
+
+// s_waitcnt on the vector-memory counter alone: wait until at most n of this
+// wavefront's vector memory operations are outstanding (n wave-uniform).
+__device__ __forceinline__ void wait_vmcnt(int n) {
+  // gfx9 encoding: vmcnt[3:0] in bits 3:0, expcnt 7 and lgkmcnt 15 (no wait)
+  switch (n) {
+    case 0: __builtin_amdgcn_s_waitcnt(0xF70); break;
+    case 1: __builtin_amdgcn_s_waitcnt(0xF71); break;
+    case 2: __builtin_amdgcn_s_waitcnt(0xF72); break;
+    case 3: __builtin_amdgcn_s_waitcnt(0xF73); break;
+    case 4: __builtin_amdgcn_s_waitcnt(0xF74); break;
+    case 5: __builtin_amdgcn_s_waitcnt(0xF75); break;
+    case 6: __builtin_amdgcn_s_waitcnt(0xF76); break;
+    case 7: __builtin_amdgcn_s_waitcnt(0xF77); break;
+    case 8: __builtin_amdgcn_s_waitcnt(0xF78); break;
+    case 9: __builtin_amdgcn_s_waitcnt(0xF79); break;
+    case 10: __builtin_amdgcn_s_waitcnt(0xF7A); break;
+    case 11: __builtin_amdgcn_s_waitcnt(0xF7B); break;
+    case 12: __builtin_amdgcn_s_waitcnt(0xF7C); break;
+    case 13: __builtin_amdgcn_s_waitcnt(0xF7D); break;
+    case 14: __builtin_amdgcn_s_waitcnt(0xF7E); break;
+    case 15: __builtin_amdgcn_s_waitcnt(0xF7F); break;
+    default: __builtin_amdgcn_s_waitcnt(0xF70); break;
+  }
+}
+
+// Ring-pipelined form of the product.  The tiles of one 32-wide contraction
+// chunk are split in two rings of direct-to-LDS stages: the X^T tile (read
+// by every block, so served from L2) one chunk ahead in two stages, and the A
+// tile (streamed once from HBM) DA - 1 chunks ahead in DA stages, as many
+// as fit in LDS beside the X stages.  Per chunk c a wavefront issues its share
+// of X(c + 1), then of A(c + DA - 1); loads complete in issue order, so
+// waiting until only the A(c + DA - 1) share is outstanding leaves X(c + 1)
+// and A(c + 1) (issued a chunk earlier) in LDS before the barrier that
+// publishes them.
+template <int S, int WM, int WN>
+struct SplitRing {
+  static constexpr int NW = WM * WN, BM = 32 * WM, BN = 32 * WN;
+  static constexpr int SROW = 2 * S + 1;  // 16-byte slots per tile row (one padding slot)
+  static constexpr int LS = 16 * SROW;     // bytes per tile row
+  // direct-to-LDS instructions per stage (64 slots each) and stage strides:
+  // a stage spans whole instructions, so the lanes of the last one that fall
+  // past the tile write into the stage's own tail
+  static constexpr int NIX = (BN * SROW + 63) / 64, NIA = (BM * SROW + 63) / 64;
+  static constexpr int XSTR = NIX * 1024, ASTR = NIA * 1024;
+  static constexpr int IPX = (NIX + NW - 1) / NW, IPA = (NIA + NW - 1) / NW;
+  static constexpr int LDS_BYTES = 160 * 1024;
+  static constexpr int DA0 = (LDS_BYTES - 2 * XSTR) / ASTR;
+  static constexpr int DA = DA0 > 4 ? 4 : DA0;
+  static constexpr int TT = 32 * 33;
+  static constexpr int EPI = (NW * 2 * TT + 2 * WM * BN) * 8;
+  static constexpr int RING = 2 * XSTR + DA * ASTR;
+  static constexpr int SMEM = RING > EPI ? RING : EPI;
+  static_assert(DA >= 2, "two A stages must fit");
+  static_assert(NIA >= NW, "every wavefront issues part of each A stage");
+  static_assert(IPA <= 15, "wait_vmcnt covers at most 15 outstanding loads");
+};
+
+template <int S, int WM, int WN>
+__global__ __launch_bounds__(WM* WN * 64) void gemm_split_ring_kernel(const Prob* __restrict__ probs,
+                                                                      const GemmItem* __restrict__ items,
+                                                                      int nitems) {
+  using R = SplitRing<S, WM, WN>;
+  constexpr int NW = R::NW, BN = R::BN, BM = R::BM, LS = R::LS, SROW = R::SROW, DA = R::DA;
+  constexpr int UB = 32 * S;  // bytes of one row (or column) of a chunk
+  __shared__ __attribute__((aligned(16))) uint8_t smem[R::SMEM];
+  uint8_t* ringX = smem;
+  uint8_t* ringA = smem + 2 * R::XSTR;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wi = wave / WN, wj = wave % WN;
+  const int l32 = lane & 31, hh = lane >> 5;
+  // this wavefront's A instructions per stage (all waves issue at least one)
+  const int wv = __builtin_amdgcn_readfirstlane(wave);  // wave index as a scalar
+  const int na_w = (R::NIA - wv + NW - 1) / NW;
+
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const GemmItem item = items[it];
+    const Prob& P = probs[item.prob];
+    // the column maxima of this step have been consumed by the slicing pass
+    if (item.row0 == 0 && item.split == 0 && tid < P.kpad)
+      reinterpret_cast<unsigned long long*>(P.xmaxp)[tid] = 0ull;
+    if (P.ctrl->stopped) continue;
+    const int row0 = item.row0;
+    const int c0 = item.k0 >> 5, c1 = item.k1 >> 5;
+    const int64_t rs = P.asl_rs;
+    const uint8_t* __restrict__ Ab = P.asl + (int64_t)row0 * rs;
+    const uint8_t* __restrict__ Xb = P.xsl;
+
+    // Per-lane source offsets within a chunk.  Every lane of an instruction
+    // loads: a padding slot takes a copy of its row's first unit and a slot
+    // past the tile the tile's first unit (both land where nothing reads),
+    // so the loads need no per-lane branches.
+    uint32_t offX[R::IPX], offA[R::IPA];
+#pragma unroll
+    for (int i = 0; i < R::IPX; ++i) {
+      const int f = (wv + i * NW) * 64 + lane, row = f / SROW, part = f - row * SROW;
+      offX[i] = f < BN * SROW ? (uint32_t)(row * UB + (part < 2 * S ? part : 0) * 16) : 0u;
     }
+#pragma unroll
+    for (int i = 0; i < R::IPA; ++i) {
+      const int f = (wv + i * NW) * 64 + lane, row = f / SROW, part = f - row * SROW;
+      offA[i] = f < BM * SROW ? (uint32_t)(row * UB + (part < 2 * S ? part : 0) * 16) : 0u;
+    }
+    // Buffer resources over this item's X slices and A row block: the loads
+    // take a fixed per-lane offset and a per-chunk scalar offset, so no
+    // per-lane 64-bit address lives across the loop.  Offsets past the
+    // resource's size read zeros instead of faulting.
+    const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)Xb, (short)0, (int)((int64_t)P.nch * BN * UB), RFK_BUFFER_FLAGS);
+    const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)Ab, (short)0, (int)((int64_t)P.nch * BM * UB), RFK_BUFFER_FLAGS);
+    auto dma_x = [&](int stage, int c) {
+      const uint32_t soff = (uint32_t)c * (BN * UB);
+      uint8_t* dst = ringX + stage * R::XSTR;
+#pragma unroll
+      for (int i = 0; i < R::IPX; ++i) {
+        const int ii = wv + i * NW;
+        if (ii < R::NIX)
+          buffer_load_lds16(rx, dst + ii * 1024, offX[i], soff);
+      }
+    };
+    auto dma_a = [&](int stage, int c) {
+      const uint32_t soff = (uint32_t)c * (BM * UB);
+      uint8_t* dst = ringA + stage * R::ASTR;
+#pragma unroll
+      for (int i = 0; i < R::IPA; ++i) {
+        const int ii = wv + i * NW;
+        if (ii < R::NIA)
+          buffer_load_lds16(ra, dst + ii * 1024, offA[i], soff);
+      }
+    };
+
+    v16i acc[S];
+#pragma unroll
+    for (int t = 0; t < S; ++t) acc[t] = v16i{};
+
+    dma_x(0, c0);
+#pragma unroll
+    for (int d = 0; d < DA - 1; ++d)
+      if (c0 + d < c1) dma_a(d, c0 + d);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+
+    const int xoff = (wj * 32 + l32) * LS + hh * 16 * S;
+    const int aoff = (wi * 32 + l32) * LS + hh * 16 * S;
+    int sx = 0, sa = 0;  // ring stages of chunk c
+    for (int c = c0; c < c1; ++c) {
+      const bool more_x = c + 1 < c1, more_a = c + DA - 1 < c1;
+      if (more_x) dma_x(sx ^ 1, c + 1);
+      if (more_a) dma_a(sa == 0 ? DA - 1 : sa - 1, c + DA - 1);
+      const uint8_t* xc = ringX + sx * R::XSTR;
+      const uint8_t* ac = ringA + sa * R::ASTR;
+      v4i xf[S];
+#pragma unroll
+      for (int q = 0; q < S; ++q) xf[q] = *reinterpret_cast<const v4i*>(xc + xoff + q * 16);
+#pragma unroll
+      for (int p = 0; p < S; ++p) {
+        const v4i af = *reinterpret_cast<const v4i*>(ac + aoff + p * 16);
+#pragma unroll
+        for (int q = 0; q < S - p; ++q) acc[p + q] = mfma_i8(xf[q], af, acc[p + q]);
+      }
+      if (DA > 2 && more_x && more_a)
+        wait_vmcnt(na_w);
+      else
+        __builtin_amdgcn_s_waitcnt(0);
+      // A bare barrier: the workgroup fence of __syncthreads would wait for
+      // every direct-to-LDS load in flight, the A stages ahead included.  The
+      // empty asm statements keep the compiler from moving LDS accesses
+      // across it; each wavefront's own wait above covers its loads.
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_s_barrier();
+      asm volatile("" ::: "memory");
+      sx ^= 1;
+      sa = sa + 1 == DA ? 0 : sa + 1;
+    }
+
+    split_epilogue<S, WM, WN>(P, item, acc, smem);
     __syncthreads();
   }
 }
@@ -442,7 +652,10 @@ hipError_t launch_product_s(const Layout& L, int variant, const Prob* probs, con
                             int nitems, hipStream_t st) {
 #define RFK_SPLIT(WM, WN)                                                                      \
   if (L.wm == WM && L.wn == WN) {                                                              \
-    if (variant == 1)                                                                          \
+    if (variant == 2)                                                                          \
+      hipLaunchKernelGGL((gemm_split_ring_kernel<S, WM, WN>), dim3(nitems), dim3(WM * WN * 64),  \
+                         0, st, probs, items, nitems);                                         \
+    else if (variant == 1)                                                                     \
       hipLaunchKernelGGL((gemm_split_kernel<S, WM, WN, true>), dim3(nitems), dim3(WM * WN * 64), \
                          0, st, probs, items, nitems);                                         \
     else                                                                                       \
@@ -470,22 +683,22 @@ hipError_t launch_product(int s, const Layout& L, int variant, const Prob* probs
 }
 
 template <int S>
-hipError_t launch_aslice_s(const double* a, int64_t lda, int n, int nch, int rows_pad,
+hipError_t launch_aslice_s(const double* a, int64_t lda, int n, int nch, int rows_pad, int bm,
                            const int32_t* aexp, uint8_t* asl, hipStream_t st) {
   const int64_t units = (int64_t)rows_pad * nch * 2;
   const int grid = (int)std::min<int64_t>((units + 255) / 256, 16384);
   hipLaunchKernelGGL((split_aslice_kernel<S>), dim3(grid), dim3(256), 0, st, a, lda, n, nch,
-                     rows_pad, aexp, asl);
+                     rows_pad, bm, aexp, asl);
   return hipGetLastError();
 }
 
-hipError_t launch_aslice(int s, const double* a, int64_t lda, int n, int nch, int rows_pad,
+hipError_t launch_aslice(int s, const double* a, int64_t lda, int n, int nch, int rows_pad, int bm,
                          const int32_t* aexp, uint8_t* asl, hipStream_t st) {
   switch (s) {
-    case 7: return launch_aslice_s<7>(a, lda, n, nch, rows_pad, aexp, asl, st);
-    case 8: return launch_aslice_s<8>(a, lda, n, nch, rows_pad, aexp, asl, st);
-    case 9: return launch_aslice_s<9>(a, lda, n, nch, rows_pad, aexp, asl, st);
-    case 10: return launch_aslice_s<10>(a, lda, n, nch, rows_pad, aexp, asl, st);
+    case 7: return launch_aslice_s<7>(a, lda, n, nch, rows_pad, bm, aexp, asl, st);
+    case 8: return launch_aslice_s<8>(a, lda, n, nch, rows_pad, bm, aexp, asl, st);
+    case 9: return launch_aslice_s<9>(a, lda, n, nch, rows_pad, bm, aexp, asl, st);
+    case 10: return launch_aslice_s<10>(a, lda, n, nch, rows_pad, bm, aexp, asl, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -653,7 +866,7 @@ int split_init(SplitPlan& sp, const std::vector<refine_matrix>& As, const std::v
                        A.a, A.lda, (int)n, (int)rows_pad, sp.aexp + o_aexp[p]);
     e = hipGetLastError();
     if (e == hipSuccess)
-      e = launch_aslice(s, A.a, A.lda, (int)n, nch, (int)rows_pad, sp.aexp + o_aexp[p],
+      e = launch_aslice(s, A.a, A.lda, (int)n, nch, (int)rows_pad, sp.bm, sp.aexp + o_aexp[p],
                         sp.asl + o_asl[p], st);
     Prob& P = hp[p];
     P.asl = sp.asl + o_asl[p];
@@ -683,8 +896,8 @@ int split_init(SplitPlan& sp, const std::vector<refine_matrix>& As, const std::v
 
   // K split (one problem only) and tile-loading variant: REFINE_SPLIT_KS=
   // "ks[,variant]" forces them; otherwise the candidates (K splits 1, 2, 4, 8
-  // whose K range fits the exact INT32 bins; both variants) are timed once
-  // per shape and process.
+  // whose K range fits the exact INT32 bins; the three variants) are timed
+  // once per shape and process.
   const int64_t kmax_range = max_k_range(s);
   int64_t nch_max = 0, nsum = 0;
   for (const Prob& P : hp) {
@@ -697,7 +910,7 @@ int split_init(SplitPlan& sp, const std::vector<refine_matrix>& As, const std::v
   if (const char* env = getenv("REFINE_SPLIT_KS")) {
     int ksp = 0, var = 0;
     const int got = sscanf(env, "%d,%d", &ksp, &var);
-    if (got >= 1 && ksp >= 1 && ksp <= ks_cap && fits(ksp) && var >= 0 && var <= 1) {
+    if (got >= 1 && ksp >= 1 && ksp <= ks_cap && fits(ksp) && var >= 0 && var <= 2) {
       best_ks = ksp;
       best_var = got == 2 ? var : 0;
     }
@@ -724,7 +937,7 @@ int split_init(SplitPlan& sp, const std::vector<refine_matrix>& As, const std::v
       return REFINE_EHIP;
     }
     float best = 1e30f;
-    for (int var = 0; var <= 1; ++var)
+    for (int var = 0; var <= 2; ++var)
       for (int ksp = 1; ksp <= ks_cap; ksp *= 2) {
         if (!fits(ksp)) continue;
         sp.variant = var;

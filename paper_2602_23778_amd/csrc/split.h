@@ -29,7 +29,8 @@ constexpr int SPLIT_ROW_PAD = 256;
 struct SplitPlan {
   int s = 0;                  // slices per operand
   int ks = 1;                 // K split (one problem only)
-  int variant = 0;            // 0: tiles staged through registers, 1: direct-to-LDS loads
+  int variant = 0;            // 0: tiles staged through registers, 1: direct-to-LDS loads,
+                              // 2: direct-to-LDS rings (X two stages, A deeper)
   int bm = 0;                 // rows per block of the product
   int kmax = 0;               // largest k of the problems
   int kpad = 0;               // kmax rounded up to 32 (the column tile of every problem)

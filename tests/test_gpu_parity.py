@@ -223,7 +223,7 @@ def _split_product_check(P, n, k, slices, ks, monkeypatch, variant=0):
     back as (W_hi, W_lo), equals the oracle's split product (exact binned
     digit products) up to the double-double rounding of the recombination.
     variant 0 stages the tiles through registers, 1 loads them straight
-    into LDS."""
+    into LDS, 2 through direct-to-LDS rings (A several chunks ahead)."""
     rf = _lib()
     monkeypatch.setenv("REFINE_SPLIT_KS", "%d,%d" % (ks, variant))
     ctx = rf.RefineContext(_dev(P.A), k, norm_a=1.0, precision="split_int8", slices=slices)
@@ -240,18 +240,19 @@ def _split_product_check(P, n, k, slices, ks, monkeypatch, variant=0):
         n, k, slices, ks, err, scale)
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 @pytest.mark.parametrize("n,k,ks", [(777, 13, 1), (1000, 64, 2), (1280, 33, 4), (640, 128, 1),
-                                    (300, 1, 1), (513, 96, 8)])
+                                    (300, 1, 1), (513, 96, 8), (150, 128, 1), (30, 5, 1)])
 def test_split_product_matches_oracle(n, k, ks, variant, monkeypatch):
     """Ragged n (not a multiple of the 32-wide chunks or of the row blocks),
-    every column-tile layout (k <= 32, 64, 96, 128), K splits 1-8, both
+    every column-tile layout (k <= 32, 64, 96, 128), K splits 1-8 (K ranges
+    down to two chunks, fewer than the ring's prefetch depth), the three
     tile-loading variants."""
     P = synth.dense_spectrum(n, k, 5000 + n)
     _split_product_check(P, n, k, 9, ks, monkeypatch, variant)
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 @pytest.mark.parametrize("slices", [7, 8, 10])
 def test_split_product_other_slice_counts(slices, variant, monkeypatch):
     P = synth.dense_spectrum(700, 40, 5100 + slices)
@@ -335,10 +336,14 @@ def test_kxk_panel_pipeline_steps(n, k):
     assert flags[0] == 1 and flags[-1] == 0, flags
 
 
-def test_split_batched_matches_oracle_per_problem():
+@pytest.mark.parametrize("variant", [None, 2])
+def test_split_batched_matches_oracle_per_problem(variant, monkeypatch):
     """Batched split-mode steps (uneven n and k, one grouped launch per
-    kernel): every problem matches the oracle's split-mode steps."""
+    kernel): every problem matches the oracle's split-mode steps (the tuned
+    tile-loading variant, and the ring variant forced)."""
     rf = _lib()
+    if variant is not None:
+        monkeypatch.setenv("REFINE_SPLIT_KS", "1,%d" % variant)
     shapes = [(130, 4), (257, 9), (511, 32), (200, 17), (129, 31)]
     probs = [synth.dense_spectrum(n, k, 970 + i) for i, (n, k) in enumerate(shapes)]
     b = rf.RefineBatch([_dev(p.A) for p in probs], [k for _, k in shapes], norm_a=1.0,
