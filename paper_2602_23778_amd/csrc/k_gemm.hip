@@ -75,67 +75,68 @@ __global__ __launch_bounds__(WAVES * 64) void gemm_f64_t_kernel(const Prob* __re
 #pragma unroll
       for (int c = 0; c < CT; ++c) acc[rt][c] = v4d{0.0, 0.0, 0.0, 0.0};
 
-    double a_cur[KS][RT], a_nxt[KS][RT];
+    double a_s0[KS][RT], a_s1[KS][RT], a_s2[KS][RT];
     double bst[BPT];
 
+    // Loads never branch and never write a register before the load itself:
+    // rows past the K range are clamped to its last row (their X rows are
+    // zero in LDS, so they add nothing) and columns past n to column n - 1
+    // (their W rows are never stored).
     auto load_a = [&](double (*dst)[RT], int kb) {
-      const bool full = (kb + KC <= k1) && (jl + RT <= n);
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
-        const int kk = kb + 4 * s + g;
-        if (full) {
-          const double* p = A + (int64_t)kk * lda + jl;
-          if (VECA && RT == 2) {
-            typedef double v2d __attribute__((ext_vector_type(2)));
-            const v2d v = __builtin_nontemporal_load(gld(reinterpret_cast<const v2d*>(p)));
-            dst[s][0] = v.x;
-            dst[s][RT - 1] = v.y;
-          } else {
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt) dst[s][rt] = __builtin_nontemporal_load(gld(p + rt));
-          }
+        const int kk = min(kb + 4 * s + g, k1 - 1);
+        const double* p = A + (int64_t)kk * lda;
+        if (VECA && RT == 2) {
+          typedef double v2d __attribute__((ext_vector_type(2)));
+          // (even n here: jl <= n - 2 for every valid pair)
+          const v2d v = __builtin_nontemporal_load(gld(reinterpret_cast<const v2d*>(p + min(jl, n - 2))));
+          dst[s][0] = v.x;
+          dst[s][RT - 1] = v.y;
         } else {
-          const bool kok = kk < k1;
-          const double* p = A + (int64_t)(kok ? kk : k0) * lda;
 #pragma unroll
-          for (int rt = 0; rt < RT; ++rt) dst[s][rt] = (kok && jl + rt < n) ? *gld(p + jl + rt) : 0.0;
+          for (int rt = 0; rt < RT; ++rt) dst[s][rt] = __builtin_nontemporal_load(gld(p + min(jl + rt, n - 1)));
         }
       }
     };
     auto load_b = [&](int kb) {
 #pragma unroll
       for (int s = 0; s < BPT; ++s) {
-        const int e = tid + s * NT;
+        const int e = min(tid + s * NT, KC * BN - 1);
         const int kr = e / BN, col = e - kr * BN;
-        double v = 0.0;
-        if (e < KC * BN && kb + kr < k1 && col < k) v = *gld(X + (int64_t)(kb + kr) * ldx + col);
-        bst[s] = v;
+        bst[s] = *gld(X + (int64_t)min(kb + kr, k1 - 1) * ldx + min(col, k - 1));
       }
     };
-    auto store_b = [&](double* dst) {
+    auto store_b = [&](double* dst, int kb) {
 #pragma unroll
       for (int s = 0; s < BPT; ++s) {
         const int e = tid + s * NT;
         if (e < KC * BN) {
           const int kr = e / BN, col = e - kr * BN;
-          dst[kr * LDB + col] = bst[s];
+          dst[kr * LDB + col] = (kb + kr < k1 && col < k) ? bst[s] : 0.0;
         }
       }
     };
 
+    // A is prefetched two chunks ahead through three register stages (the
+    // chunk loop is unrolled by three so that every stage keeps its
+    // registers).  Per chunk the X chunk of the next step is requested
+    // before the A chunk two steps ahead, so the wait that precedes its LDS
+    // store leaves the A requests in flight.  The loads and the store are
+    // unconditional (past the K range they read the clamped last row and
+    // store zeros), which keeps the compiler's wait counts exact across the
+    // loop.
     const int nchunks = (k1 - k0 + KC - 1) / KC;
-    load_a(a_cur, k0);
     load_b(k0);
-    store_b(Bs0);
+    load_a(a_s0, k0);
+    store_b(Bs0, k0);
+    load_a(a_s1, k0 + KC);
     __syncthreads();
-    for (int c = 0; c < nchunks; ++c) {
-      const bool more = c + 1 < nchunks;
+    auto chunk = [&](int c, double (*cur)[RT], double (*ahead)[RT]) {
       const int kb = k0 + c * KC;
       const double* bs = (c & 1) ? Bs1 : Bs0;
-      if (more) {
-        load_a(a_nxt, kb + KC);
-        load_b(kb + KC);
-      }
+      load_b(kb + KC);
+      load_a(ahead, kb + 2 * KC);
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
         const double* xr = bs + (4 * s + g) * LDB + r16;
@@ -143,15 +144,16 @@ __global__ __launch_bounds__(WAVES * 64) void gemm_f64_t_kernel(const Prob* __re
         for (int ct = 0; ct < CT; ++ct) {
           const double xv = xr[ct * 16];
 #pragma unroll
-          for (int rt = 0; rt < RT; ++rt) acc[rt][ct] = mfma_f64(xv, a_cur[s][rt], acc[rt][ct]);
+          for (int rt = 0; rt < RT; ++rt) acc[rt][ct] = mfma_f64(xv, cur[s][rt], acc[rt][ct]);
         }
       }
-      if (more) store_b((c & 1) ? Bs0 : Bs1);
+      store_b((c & 1) ? Bs0 : Bs1, kb + KC);
       __syncthreads();
-#pragma unroll
-      for (int s = 0; s < KS; ++s)
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) a_cur[s][rt] = a_nxt[s][rt];
+    };
+    for (int c = 0; c < nchunks; c += 3) {
+      chunk(c, a_s0, a_s2);
+      if (c + 1 < nchunks) chunk(c + 1, a_s1, a_s0);
+      if (c + 2 < nchunks) chunk(c + 2, a_s2, a_s1);
     }
 
     // Epilogue: register r of tile (rt, ct) holds W^T[ct*16 + mfma_row(g, r)][column

@@ -353,7 +353,8 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
     b += align_up((size_t)VEC_COUNT * k * sizeof(double));
     bytes += b;
     if (As[p].kind == REFINE_DENSE) {
-      if ((As[p].lda & 1) || ((uintptr_t)As[p].a & 15)) pl.vec2 = false;
+      // pairs of columns per lane: aligned rows, and no pair straddling n
+      if ((As[p].lda & 1) || (As[p].n & 1) || ((uintptr_t)As[p].a & 15)) pl.vec2 = false;
     }
   }
   const size_t ctrl_off = bytes;
