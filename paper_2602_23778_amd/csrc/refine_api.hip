@@ -39,7 +39,7 @@ hipError_t launch_fin_d(const Prob*, int, hipStream_t);
 hipError_t launch_fin_stats(const Prob*, int, hipStream_t);
 hipError_t launch_ctrl_reset(const Prob*, int, int, double, hipStream_t);
 hipError_t launch_set_x(Prob*, int, double*, int64_t, hipStream_t);
-hipError_t launch_spmm(const Prob*, const RowItem*, int, hipStream_t);
+hipError_t launch_spmm(const Prob*, const RowItem*, int, int, hipStream_t);
 int spmm_chunk_rows();
 int spmm_grid(int nitems);
 hipError_t launch_rowstats(int, int, const double*, int64_t, const int32_t*, const int32_t*,
@@ -460,7 +460,7 @@ hipError_t enqueue_step(Plan& pl, hipStream_t st) {
   hipError_t e;
   const int np = (int)pl.hprob.size();
   if (pl.csr) {
-    if ((e = launch_spmm(pl.dprob, pl.spmm_items, pl.n_spmm, st)) != hipSuccess) return e;
+    if ((e = launch_spmm(pl.dprob, pl.spmm_items, pl.n_spmm, pl.hprob[0].k, st)) != hipSuccess) return e;
   } else {
     if (pl.split) {
       if ((e = split_product(pl.sp, pl.dprob, st)) != hipSuccess) return e;
@@ -786,7 +786,7 @@ int refine_time_product(refine_ctx* c, double* X, int64_t ldx, int32_t reps, flo
   hipError_t e = hipEventRecord(e0, c->stream);
   for (int i = 0; i < reps && e == hipSuccess; ++i) {
     if (pl.csr)
-      e = launch_spmm(pl.dprob, pl.spmm_items, pl.n_spmm, c->stream);
+      e = launch_spmm(pl.dprob, pl.spmm_items, pl.n_spmm, pl.hprob[0].k, c->stream);
     else if (pl.split)
       e = split_product(pl.sp, pl.dprob, c->stream);
     else

@@ -108,6 +108,51 @@ def test_csr_laplacian_16():
     _compare_steps(None, X0, 3, norm_a=L.sigma, mu=L.sigma, target="smallest", csr=L)
 
 
+@pytest.mark.parametrize("k", [1, 3, 5, 13, 32, 64, 100, 128])
+def test_csr_every_row_width(k):
+    """CSR product widths: k picks the lanes per row (1 to 32) and, for k not
+    a multiple of four or odd, the per-column loads of the last lane group.
+    Separable Laplacian on a 12^3 grid (exact eigenvectors + 1e-6 noise)."""
+    L, lam, Xt, X0 = synth.laplacian3d_separable(12, k)
+    _compare_steps(None, X0, 2, norm_a=L.sigma, mu=L.sigma, target="smallest", csr=L)
+
+
+def test_csr_irregular_rows():
+    """Rows of 0 to ~2000 nonzeros: empty rows, rows longer than one gather
+    round, and a chunk whose nonzeros exceed the block's LDS copy (read from
+    memory instead).  The 12 largest |lambda| of a random sparse symmetric
+    matrix, X0 = fl32 of its eigenvectors."""
+    n, k = 1500, 12
+    rng = np.random.default_rng(4242)
+    M = np.zeros((n, n))
+    for i in range(n):
+        cols = rng.choice(n, size=int(rng.integers(0, 4)), replace=False)
+        M[i, cols] = rng.standard_normal(len(cols))
+    M[5, :] = 0.05 * rng.standard_normal(n)
+    M = M + M.T
+    M[np.arange(n), np.arange(n)] += np.linspace(0.0, 3.0, n)
+    for e in (17, 300, 301):
+        M[e, :] = 0.0
+        M[:, e] = 0.0
+    lam, V = np.linalg.eigh(M)
+    order = np.argsort(-np.abs(lam))[:k]
+    X0 = synth.fp32_round(V[:, order])
+    rp = np.zeros(n + 1, dtype=np.int32)
+    nz = M != 0.0
+    rp[1:] = np.cumsum(nz.sum(1))
+    ci = np.nonzero(nz)[1].astype(np.int32)
+    val = M[nz]
+    assert rp[256] - rp[0] > 2048 and rp[1] - rp[0] > 0 and rp[18] == rp[17]
+
+    class Csr:
+        pass
+
+    C = Csr()
+    C.n, C.row_ptr, C.col_idx, C.val = n, rp, ci, val
+    norm = float(np.max(np.abs(M).sum(1)))
+    _compare_steps(None, X0, 2, norm_a=norm, csr=C)
+
+
 def test_refine_run_converges_and_counts():
     """refine_run with the correction-size stopping rule (Sec. 3.3)."""
     rf = _lib()
