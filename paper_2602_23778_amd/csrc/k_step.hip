@@ -192,6 +192,175 @@ __global__ __launch_bounds__(CT * RG * 64) void gram_kernel(const Prob* __restri
   }
 }
 
+// The same pass for k <= 32 (CT <= 2): every wavefront accumulates all
+// tiles, so each X and W value is loaded once, and U 4-row steps are
+// requested before their products.  Loads never branch (clamped addresses,
+// masked values), which keeps the compiler's wait counts exact.  The RG
+// wavefronts of a block take interleaved runs of 4U rows; their tiles and
+// column sums are added in LDS in a fixed order.
+template <int CT, int RG, int U>
+__global__ __launch_bounds__(RG * 64) void gram_all_kernel(const Prob* __restrict__ probs,
+                                                          const RowItem* __restrict__ items,
+                                                          int nitems) {
+  static_assert(CT <= 2, "tile bookkeeping below covers CT <= 2");
+  constexpr int NTP = CT * CT, NTG = CT * (CT + 1) / 2;
+  __shared__ double xch[RG][256];
+  __shared__ double rsq_x[RG][CT * 64];
+  const int lane = threadIdx.x & 63, rg = threadIdx.x >> 6;
+  const int g = lane >> 4, r16 = lane & 15;
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const RowItem item = items[it];
+    const Prob& P = probs[item.prob];
+    if (P.ctrl->stopped) continue;
+    const int n = P.n, k = P.k;
+    const int ct_used = (k + 15) / 16;
+    const bool has_lo = P.wlo != nullptr;
+    const double* __restrict__ X = P.x;
+    const double* __restrict__ Wh = P.w;
+    const double* __restrict__ Wl = has_lo ? P.wlo : P.w;
+    const int64_t ldx = P.ldx;
+    const int r0 = item.blk * P.gbrows, r1 = min(n, r0 + P.gbrows);
+    const int kk2 = k * k;
+    double dv[CT];
+    bool cok[CT];
+    int cc[CT];
+#pragma unroll
+    for (int t = 0; t < CT; ++t) {
+      const int c = t * 16 + r16;
+      cok[t] = c < k;
+      cc[t] = cok[t] ? c : 0;
+      dv[t] = *gld(P.vec + VEC_D * k + cc[t]);
+    }
+    double rsq[CT];
+#pragma unroll
+    for (int t = 0; t < CT; ++t) rsq[t] = 0.0;
+
+    // phase 0: rows < k (only block 0 has them); phase 1: rows >= k
+    for (int phase = 0; phase < 2; ++phase) {
+      const int lo = phase == 0 ? r0 : max(r0, k);
+      const int hi = phase == 0 ? min(r1, k) : r1;
+      if (lo >= hi) continue;
+      v4d accP[NTP], accG[NTG];
+#pragma unroll
+      for (int t = 0; t < NTP; ++t) accP[t] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int t = 0; t < NTG; ++t) accG[t] = v4d{0.0, 0.0, 0.0, 0.0};
+      for (int base = lo + rg * 4 * U; base < hi; base += RG * 4 * U) {
+        double xv[U][CT], wv[U][CT], lv[U][CT];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int row = base + 4 * u + g;
+          const int rr = row < hi ? row : lo;
+#pragma unroll
+          for (int t = 0; t < CT; ++t) {
+            xv[u][t] = *gld(X + (int64_t)rr * ldx + cc[t]);
+            wv[u][t] = *gld(Wh + (int64_t)rr * k + cc[t]);
+            if (has_lo) lv[u][t] = *gld(Wl + (int64_t)rr * k + cc[t]);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int row = base + 4 * u + g;
+          const bool rok = row < hi;
+          double xm[CT], rv[CT];
+#pragma unroll
+          for (int t = 0; t < CT; ++t) {
+            const bool ok = rok && cok[t];
+            xm[t] = ok ? xv[u][t] : 0.0;
+            rv[t] = ok ? residual(wv[u][t], has_lo ? lv[u][t] : 0.0, xv[u][t], dv[t], has_lo) : 0.0;
+            rsq[t] = __builtin_fma(rv[t], rv[t], rsq[t]);
+          }
+#pragma unroll
+          for (int ti = 0; ti < CT; ++ti) {
+            if (ti < ct_used) {
+#pragma unroll
+              for (int t = 0; t < CT; ++t) {
+                if (t < ct_used) {
+                  accP[ti * CT + t] = mfma_f64(xm[ti], rv[t], accP[ti * CT + t]);
+                  if (t >= ti) {
+                    const int gi = ti * CT - ti * (ti - 1) / 2 + (t - ti);
+                    accG[gi] = mfma_f64(xm[ti], xm[t], accG[gi]);
+                  }
+                }
+              }
+            }
+          }
+          if (phase == 0 && rok) {
+#pragma unroll
+            for (int t = 0; t < CT; ++t)
+              if (cok[t]) *gst(P.kk + KK_R1 * kk2 + row * k + t * 16 + r16) = rv[t];
+          }
+        }
+      }
+      // sum the wavefronts' tiles into wavefront 0, one tile at a time
+      double* dstP;
+      double* dstG;
+      if (phase == 0) {
+        dstP = P.kk + KK_PT * kk2;
+        dstG = P.kk + KK_GT * kk2;
+      } else {
+        dstP = P.gpart + (int64_t)item.blk * (2 * kk2 + k);
+        dstG = dstP + kk2;
+      }
+#pragma unroll
+      for (int q = 0; q < NTP + NTG; ++q) {
+        v4d& v = q < NTP ? accP[q] : accG[q - NTP];
+        // tile indices of q
+        int ti, t;
+        if (q < NTP) {
+          ti = q / CT;
+          t = q % CT;
+        } else {
+          const int gi = q - NTP;
+          ti = gi < CT ? 0 : 1;
+          t = ti + (gi - (ti == 0 ? 0 : CT));
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) xch[rg][lane * 4 + r] = v[r];
+        __syncthreads();
+        if (rg == 0 && ti < ct_used && t < ct_used) {
+          double sum[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            double a = xch[0][lane * 4 + r];
+            for (int w = 1; w < RG; ++w) a += xch[w][lane * 4 + r];
+            sum[r] = a;
+          }
+          const int c = t * 16 + r16;
+          if (c < k) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int i = ti * 16 + mfma_row(g, r);
+              if (i < k) *gst((q < NTP ? dstP : dstG) + i * k + c) = sum[r];
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    // blocks without rows >= k still publish zero partials
+    if (max(r0, k) >= r1) {
+      double* dst = P.gpart + (int64_t)item.blk * (2 * kk2 + k);
+      for (int e = threadIdx.x; e < 2 * kk2; e += blockDim.x) *gst(dst + e) = 0.0;
+    }
+    // column sums of r^2 over the block's rows
+#pragma unroll
+    for (int t = 0; t < CT; ++t) rsq_x[rg][t * 64 + lane] = rsq[t];
+    __syncthreads();
+    if (threadIdx.x < CT * 16) {
+      const int t = threadIdx.x / 16, c16 = threadIdx.x % 16, c = t * 16 + c16;
+      if (c < k) {
+        double s = 0.0;
+        for (int q = 0; q < RG; ++q)
+          s += (rsq_x[q][t * 64 + c16] + rsq_x[q][t * 64 + 16 + c16]) +
+               (rsq_x[q][t * 64 + 32 + c16] + rsq_x[q][t * 64 + 48 + c16]);
+        *gst(P.gpart + (int64_t)item.blk * (2 * kk2 + k) + 2 * kk2 + c) = s;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Sums the Gram partials of every problem in a fixed order over blocks:
 // 64 slots per workgroup, 16 block groups per slot, then an LDS tree.  Slots
 // [0, k^2) are X2^T R2, [k^2, 2k^2) X2^T X2 (lower tiles mirrored from the
@@ -437,6 +606,170 @@ __global__ __launch_bounds__(256) void update_kernel(const Prob* __restrict__ pr
   }
 }
 
+// The same pass for k <= 32 (CT <= 2), for long problems: the block's X rows
+// come in 64-row tiles read with coalesced 16-byte loads (one tile ahead, in
+// registers) into LDS, where the wavefronts take both the MFMA A operand
+// (16 rows x 4 columns per step) and the epilogue's x from them, so X is read
+// from memory once and in whole rows.  W (and W_lo) are read in the
+// epilogue's layout before the products.  [M | N] is staged once per block.
+template <int CT>
+__global__ __launch_bounds__(256) void update_small_kernel(const Prob* __restrict__ probs,
+                                                          const RowItem* __restrict__ items,
+                                                          int nitems) {
+  typedef double v2d __attribute__((ext_vector_type(2)));
+  static_assert(CT <= 2, "tall-skinny form");
+  constexpr int NT = 256, WAVES = 4, TR = 64, KP = CT * 16, LDXS = KP + 1;
+  constexpr int BW = 2 * KP, LDC = BW + 2;
+  constexpr int UNITS = TR * KP / 2, UPT = (UNITS + NT - 1) / NT;  // 2-double units per tile
+  __shared__ double Cs[KP * LDC];
+  __shared__ double Xs[TR * LDXS];
+  __shared__ double colred[2][WAVES][KP];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, r16 = lane & 15;
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const RowItem item = items[it];
+    const Prob& P = probs[item.prob];
+    if (P.ctrl->stopped) continue;
+    const int n = P.n, k = P.k, kk2 = k * k, k2 = 2 * k;
+    const bool has_lo = P.wlo != nullptr;
+    const double* __restrict__ X = P.x;
+    const int64_t ldx = P.ldx;
+    const double* __restrict__ Cm = P.kk + KK_CM * kk2;
+    const double* __restrict__ X1n = P.kk + KK_X1N * kk2;
+    const int r0 = item.blk * P.rbrows, r1 = min(n, r0 + P.rbrows);
+    const bool vec = (ldx & 1) == 0 && (((uintptr_t)X) & 15) == 0 && (k & 1) == 0;
+    double dv[CT], di[CT], xsq[CT], esq[CT];
+    bool cok[CT];
+#pragma unroll
+    for (int t = 0; t < CT; ++t) {
+      const int c = t * 16 + r16;
+      cok[t] = c < k;
+      const int cc = cok[t] ? c : 0;
+      dv[t] = *gld(P.vec + VEC_D * k + cc);
+      di[t] = cok[t] ? *gld(P.vec + VEC_DINV * k + cc) : 0.0;
+      xsq[t] = 0.0;
+      esq[t] = 0.0;
+    }
+    // [M | N] rows < KP (zero past k)
+    for (int e = tid; e < KP * BW; e += NT) {
+      const int rr = e / BW, cc = e - rr * BW;
+      const int half = cc / KP, cj = cc - half * KP;
+      Cs[rr * LDC + cc] = (rr < k && cj < k) ? *gld(Cm + rr * k2 + half * k + cj) : 0.0;
+    }
+    // one 64-row tile of X as UPT pairs of doubles per thread (zero past n or k)
+    auto load_tile = [&](int rc, v2d (&buf)[UPT]) {
+#pragma unroll
+      for (int u = 0; u < UPT; ++u) {
+        const int e = min(tid + u * NT, UNITS - 1);
+        const int rr = e / (KP / 2), c = 2 * (e - rr * (KP / 2));
+        const int row = min(rc + rr, r1 - 1);
+        const double* p = X + (int64_t)row * ldx;
+        if (vec && c + 1 < k) {
+          buf[u] = *gld(reinterpret_cast<const v2d*>(p + c));
+        } else {
+          buf[u].x = *gld(p + min(c, k - 1));
+          buf[u].y = *gld(p + min(c + 1, k - 1));
+        }
+      }
+    };
+    v2d nxt[UPT];
+    load_tile(r0, nxt);
+    for (int rc = r0; rc < r1; rc += TR) {
+      __syncthreads();  // previous tile's LDS reads (and the [M | N] stores) are done
+#pragma unroll
+      for (int u = 0; u < UPT; ++u) {
+        const int e = tid + u * NT;
+        if (e < UNITS) {
+          const int rr = e / (KP / 2), c = 2 * (e - rr * (KP / 2));
+          const bool rok = rc + rr < r1;
+          Xs[rr * LDXS + c] = (rok && c < k) ? nxt[u].x : 0.0;
+          Xs[rr * LDXS + c + 1] = (rok && c + 1 < k) ? nxt[u].y : 0.0;
+        }
+      }
+      if (rc + TR < r1) load_tile(rc + TR, nxt);
+      // the epilogue's W values of this wavefront's 16 rows
+      double ew[CT][4], el[CT][4];
+#pragma unroll
+      for (int t = 0; t < CT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = min(rc + wave * 16 + mfma_row(g, r), r1 - 1);
+          const int64_t o = (int64_t)row * k + (cok[t] ? t * 16 + r16 : 0);
+          ew[t][r] = *gld(P.w + o);
+          el[t][r] = has_lo ? *gld(P.wlo + o) : 0.0;
+        }
+      __syncthreads();
+      v4d accM[CT], accN[CT];
+#pragma unroll
+      for (int t = 0; t < CT; ++t) {
+        accM[t] = v4d{0.0, 0.0, 0.0, 0.0};
+        accN[t] = v4d{0.0, 0.0, 0.0, 0.0};
+      }
+      const double* xa = Xs + (wave * 16 + r16) * LDXS + g;
+#pragma unroll
+      for (int s = 0; s < KP / 4; ++s) {
+        const double av = xa[4 * s];
+        const double* brow = Cs + (4 * s + g) * LDC + r16;
+#pragma unroll
+        for (int t = 0; t < CT; ++t) {
+          accM[t] = mfma_f64(av, brow[t * 16], accM[t]);
+          accN[t] = mfma_f64(av, brow[KP + t * 16], accN[t]);
+        }
+      }
+      // epilogue: register r holds row rc + wave*16 + mfma_row(g, r), column t*16 + r16
+#pragma unroll
+      for (int t = 0; t < CT; ++t) {
+        const int c = t * 16 + r16;
+        if (cok[t]) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int lr = wave * 16 + mfma_row(g, r), row = rc + lr;
+            if (row < r1) {
+              double xt;
+              if (row < k) {
+                xt = *gld(X1n + row * k + c);
+              } else {
+                const double x = Xs[lr * LDXS + c];
+                const double rr = residual(ew[t][r], el[t][r], x, dv[t], has_lo);
+                const double e = (rr - accM[t][r]) * di[t];
+                xt = (x + e) - accN[t][r];
+                esq[t] = __builtin_fma(e, e, esq[t]);
+              }
+              *gst(P.xn + (int64_t)row * k + c) = xt;
+              xsq[t] = __builtin_fma(xt, xt, xsq[t]);
+            }
+          }
+        }
+      }
+    }
+    // block partials of sum x~^2 and sum e^2 per column
+#pragma unroll
+    for (int t = 0; t < CT; ++t) {
+      double a = xsq[t], b = esq[t];
+      a += __shfl_xor(a, 16);
+      a += __shfl_xor(a, 32);
+      b += __shfl_xor(b, 16);
+      b += __shfl_xor(b, 32);
+      if (g == 0) {
+        colred[0][wave][t * 16 + r16] = a;
+        colred[1][wave][t * 16 + r16] = b;
+      }
+    }
+    __syncthreads();
+    const int stride = 5 * k;
+    if (tid < k) {
+      double a = 0.0, b = 0.0;
+      for (int w = 0; w < WAVES; ++w) {
+        a += colred[0][w][tid];
+        b += colred[1][w][tid];
+      }
+      *gst(P.part + (int64_t)item.blk * stride + 2 * k + tid) = a;
+      *gst(P.part + (int64_t)item.blk * stride + 3 * k + tid) = b;
+    }
+    __syncthreads();
+  }
+}
+
 // Statistics and the accept/reject decision of the step, one workgroup per
 // problem: sums the update partials (fixed order), forms the normalisation
 // factors 1/||x~_j||, ||E_L||_F = sqrt(||E11||_F^2 + sum e^2) and
@@ -624,8 +957,17 @@ hipError_t launch_gram(const Prob* probs, const RowItem* items, int nitems, int 
     hipLaunchKernelGGL((gram_kernel<CTV, RGV>), dim3(nitems), dim3(CTV * RGV * 64), 0, st,   \
                        probs, items, nitems);                                                \
     break;
+  if (ct <= 2) {
+    if (ct == 1)
+      hipLaunchKernelGGL((gram_all_kernel<1, 8, 4>), dim3(nitems), dim3(512), 0, st, probs, items,
+                         nitems);
+    else
+      hipLaunchKernelGGL((gram_all_kernel<2, 8, 4>), dim3(nitems), dim3(512), 0, st, probs, items,
+                         nitems);
+    return hipGetLastError();
+  }
   switch (ct) {
-    RFK_CASE(1, 16) RFK_CASE(2, 8) RFK_CASE(3, 2) RFK_CASE(4, 2)
+    RFK_CASE(3, 2) RFK_CASE(4, 2)
     RFK_CASE(5, 1) RFK_CASE(6, 1) RFK_CASE(7, 1) RFK_CASE(8, 1)
     default:
       return hipErrorInvalidValue;
@@ -643,6 +985,15 @@ hipError_t launch_gram_reduce(const Prob* probs, const GramRedItem* items, int n
 hipError_t launch_update(const Prob* probs, const RowItem* items, int nitems, int kmax,
                          hipStream_t st) {
   const int ct = (kmax + 15) / 16;
+  if (ct <= 2) {
+    if (ct == 1)
+      hipLaunchKernelGGL((update_small_kernel<1>), dim3(nitems), dim3(256), 0, st, probs, items,
+                         nitems);
+    else
+      hipLaunchKernelGGL((update_small_kernel<2>), dim3(nitems), dim3(256), 0, st, probs, items,
+                         nitems);
+    return hipGetLastError();
+  }
 #define RFK_CASE(CTV)                                                                   \
   case CTV:                                                                             \
     hipLaunchKernelGGL((update_kernel<CTV>), dim3(nitems), dim3(256), 0, st, probs, items, \
