@@ -57,7 +57,7 @@ class _Opts(ctypes.Structure):
                 ("normalize", ctypes.c_int32), ("dd", ctypes.c_int32),
                 ("shift_in_denominators", ctypes.c_int32),
                 ("plant_printed_sign", ctypes.c_int32),
-                ("split_slices", ctypes.c_int32)]
+                ("split_slices", ctypes.c_int32), ("rr_zero_top", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -215,13 +215,16 @@ def refine_step(A, X, *, mu: float = 0.0, norm_a: float | None = None,
                 delta_c: float = 10.0, beta_zero: bool = False,
                 normalize: bool = True, dd: bool = False,
                 shift_in_denominators: bool = False,
-                plant_printed_sign: bool = False, split: int = 0) -> StepResult:
+                plant_printed_sign: bool = False, split: int = 0,
+                rr_top: bool = False) -> StepResult:
     """One step of Algorithm 4 (with Algorithm 1) on A (dense or Csr).
 
     mu: the method runs on A - mu I (Sec. 5.1); norm_a: ||A|| in delta and in
     the residual statistic (default ||A||_inf); dd: line 1 in double-double;
     split: line 1 by the split form with that many slices (dense A), its
     pair (W_hi, W_lo) then used like the double-double one.
+    rr_top: X is a Rayleigh-Ritz basis (the output of rayleigh_ritz); the
+    leading k x k block of E_L is then zero (Sec. 4, clustered eigenvalues).
     plant_printed_sign exists only so that a test can show that the sign
     printed in eq. (V-def) makes the iteration diverge."""
     lib = _load()
@@ -242,7 +245,7 @@ def refine_step(A, X, *, mu: float = 0.0, norm_a: float | None = None,
         m.kind = 0
         m.a, m.lda = _p(A), A.shape[1]
     o = _Opts(mu, delta_c, norm_a, int(beta_zero), int(normalize), int(dd),
-              int(shift_in_denominators), int(plant_printed_sign), int(split))
+              int(shift_in_denominators), int(plant_printed_sign), int(split), int(rr_top))
     st = _Stats()
     Xout = np.zeros((n, k))
     d = np.zeros(k)
@@ -250,6 +253,34 @@ def refine_step(A, X, *, mu: float = 0.0, norm_a: float | None = None,
     rc = lib.orc_refine_step(ctypes.byref(m), k, _p(X), k, _p(Xout), k, ctypes.byref(o),
                              ctypes.byref(st), _p(d), _p(E))
     return StepResult(rc, Xout, st.corr_fro, st.resid_rel, st.cond_y1, d, E)
+
+
+def rayleigh_ritz(A, X, mu: float = 0.0):
+    """Rayleigh-Ritz preprocessing on span(X) (Sec. 4, clustered eigenvalues):
+    the symmetric-definite k x k problem (X^T A X) S = (X^T X) S Theta is
+    solved by a library eigensolver (the step's one library primitive; A X is
+    the oracle's own product), and Z = X S has Z^T Z = I and Z^T A Z = Theta.
+
+    Conventions shared with the GPU path (the paper fixes neither): the
+    columns are ordered by |theta - mu| descending (the refinement's targets
+    first, ties in ascending theta), and each column's sign makes z_jj <= 0,
+    so that the leading block Z1 - I of the compact-WY factor keeps its
+    diagonal at or below -1.  Returns (Z, theta)."""
+    import scipy.linalg
+    X = _f64(X)
+    n, k = X.shape
+    W = matmul(A, X)
+    H = X.T @ W
+    H = 0.5 * (H + H.T)
+    G = X.T @ X
+    theta, S = scipy.linalg.eigh(H, G)
+    order = np.lexsort((theta, -np.abs(theta - mu)))
+    theta, S = theta[order], S[:, order]
+    Z = X @ S
+    for j in range(k):
+        if Z[j, j] > 0.0:
+            Z[:, j] = -Z[:, j]
+    return Z, theta
 
 
 def refine(A, X, steps: int, **kw):

@@ -401,6 +401,9 @@ typedef struct {
   int32_t plant_printed_sign;    /* 1: use the sign printed in eq. (V-def) */
   int32_t split_slices;  /* > 0: W by the split form with that many slices
                             (dense only), kept as a pair like dd */
+  int32_t rr_zero_top;   /* 1: X is a Rayleigh-Ritz basis (Sec. 4, clustered
+                            eigenvalues): the leading k x k block of E_L is
+                            zero, so no d_j - d_i denominator is formed */
 } orc_opts;
 
 typedef struct {
@@ -512,7 +515,9 @@ int orc_refine_step(const orc_matrix* M, int64_t k, const double* X,
     for (int64_t i = 0; i < k; ++i)
       for (int64_t j = 0; j < k; ++j) {
         double e;
-        if (i == j) {
+        if (o->rr_zero_top) {
+          e = 0.0;                                            /* Sec. 4 (clusters) */
+        } else if (i == j) {
           e = (1.0 - alpha[i]) / 2.0;                         /* eq. Ediag */
         } else if (fabs(d[j] - d[i]) <= delta) {
           if (o->beta_zero) {

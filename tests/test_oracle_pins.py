@@ -493,3 +493,65 @@ def test_separable_laplacian_generator_eigenpairs():
     # the same pattern as laplacian3d
     L = synth.laplacian3d(6)
     assert np.array_equal(L.row_ptr, P.row_ptr) and np.array_equal(L.col_idx, P.col_idx)
+
+
+# --------------------------------------------------------------------------
+# Rayleigh-Ritz preprocessing (Sec. 4, clustered eigenvalues)
+# --------------------------------------------------------------------------
+def test_rayleigh_ritz_on_an_invariant_subspace_returns_its_eigenpairs():
+    """X spans an exact invariant subspace (6 eigenvectors mixed by a random
+    nonsingular R): the Ritz pairs are those eigenpairs, ordered by |lambda|
+    descending, with the sign convention z_jj <= 0."""
+    n, k = 80, 6
+    rng = np.random.default_rng(31)
+    lam = np.concatenate([rng.uniform(-0.5, 0.5, n - k), [0.9, -0.85, 0.8, 0.75, -0.7, 0.65]])
+    A, Q = _sym_problem(n, lam, 32)
+    idx = np.arange(n - k, n)
+    R = rng.standard_normal((k, k)) + 3.0 * np.eye(k)
+    X = Q[:, idx] @ R
+    Z, theta = oracle.rayleigh_ritz(A, X)
+    want = lam[idx][np.argsort(-np.abs(lam[idx]))]
+    assert np.allclose(theta, want, atol=1e-13)
+    Qs = Q[:, idx][:, np.argsort(-np.abs(lam[idx]))]
+    assert max_abs_diff_aligned(Z, Qs) < 1e-12
+    assert np.all(np.diag(Z[:k]) <= 0.0)
+
+
+def test_rayleigh_ritz_basis_properties_and_separation_theorem():
+    """On a clustered problem from an fp32-accurate start: Z^T Z = I and
+    Z^T A Z = diag(theta) to rounding, and the Ritz values obey the
+    Poincare separation theorem lam_{n-k+i} <= theta_i <= lam_i (both sorted
+    descending).  Shifted ordering: with mu above the spectrum the columns
+    come in ascending theta."""
+    P = synth.dense_clustered(300, 8, 71)
+    A, X = P.A, P.X0
+    Z, theta = oracle.rayleigh_ritz(A, X)
+    k = X.shape[1]
+    assert np.max(np.abs(Z.T @ Z - np.eye(k))) < 1e-13
+    H = Z.T @ (A @ Z)
+    assert np.max(np.abs(H - np.diag(theta))) < 1e-13
+    lam = np.sort(np.linalg.eigvalsh(A))[::-1]
+    th = np.sort(theta)[::-1]
+    n = A.shape[0]
+    assert np.all(th <= lam[:k] + 1e-13) and np.all(th >= lam[n - k:] - 1e-13)
+    assert np.all(np.diff(np.abs(theta)) <= 0.0)
+    Zs, ths = oracle.rayleigh_ritz(A, X, mu=2.0)
+    assert np.all(np.diff(ths) >= 0.0)
+
+
+def test_rr_zero_top_step_keeps_the_bottom_block():
+    """The step after Rayleigh-Ritz with the leading k x k block of E_L set to
+    zero: that block is exactly zero, the bottom rows equal those of the
+    plain step on the same input (they do not depend on the option), and the
+    plain step's leading block on a Ritz basis is only rounding-sized
+    off the clusters."""
+    P = synth.dense_clustered(200, 6, 91)
+    Z, theta = oracle.rayleigh_ritz(P.A, P.X0)
+    k = Z.shape[1]
+    a = oracle.refine_step(P.A, Z, norm_a=1.0, rr_top=True, normalize=False)
+    b = oracle.refine_step(P.A, Z, norm_a=1.0, normalize=False)
+    assert a.status == 0 and b.status == 0
+    assert np.all(a.E[:k] == 0.0)
+    assert np.array_equal(a.E[k:], b.E[k:])
+    assert np.max(np.abs(np.diag(b.E[:k]))) < 1e-14
+    assert a.corr_fro <= b.corr_fro
