@@ -53,6 +53,8 @@ extern "C" {
                                     eq. Neumann needs ||E|| < 1), or ||E_L||_F grew
                                     tenfold over three steps (Sec. 4.3 guidance) */
 #define REFINE_ENONFINITE (-6)   /* NaN or Inf in X or in the step's reductions */
+#define REFINE_ERANK (-7)        /* refine_rayleigh_ritz: X^T X is not numerically
+                                    positive definite (dependent columns) */
 
 typedef struct refine_ctx refine_ctx;
 typedef struct refine_batch refine_batch;
@@ -155,6 +157,20 @@ int refine_run(refine_ctx* ctx, double* X, int64_t ldx, int32_t max_iters,
  * for delta and the residual, and delta itself. */
 int refine_get_info(const refine_ctx* ctx, double* mu, double* norm_inf,
                     double* norm_used, double* delta);
+
+/* Rayleigh-Ritz preprocessing for clustered targets (Sec. 4, handling
+ * clustered eigenvalues): solves the k x k symmetric-definite problem
+ * (X^T A X) S = (X^T X) S Theta and overwrites X (device, n x k, ld ldx >= k,
+ * the caller's) with X S, so that X^T X = I and X^T A X = Theta to rounding.
+ * Columns come ordered by |theta - mu| descending (ties in ascending theta),
+ * each signed so that X(j, j) <= 0.  The next applied step of this context
+ * (refine_step or the first of refine_run) then takes the leading k x k block
+ * of E_L as zero, so it forms no d_j - d_i denominator; later steps are
+ * plain.  A X is formed by the context's product (FP64, split or CSR), the
+ * k x k problem on one workgroup (Cholesky, then cyclic Jacobi).  Returns
+ * REFINE_OK, REFINE_ERANK when X^T X is not positive definite (X unchanged),
+ * or an argument or HIP error.  Synchronises with the host once. */
+int refine_rayleigh_ritz(refine_ctx* ctx, double* X, int64_t ldx);
 
 int refine_destroy(refine_ctx* ctx);
 

@@ -32,6 +32,7 @@ EHIP = -3
 EWY_SINGULAR = -4
 EDIVERGED = -5
 ENONFINITE = -6
+ERANK = -7
 
 DENSE, CSR = 0, 1
 FP64, SPLIT_INT8 = 0, 1
@@ -60,7 +61,7 @@ class refine_stats(ctypes.Structure):
 EXPORTS = ("refine_options_default", "refine_init", "refine_step", "refine_run",
            "refine_get_info", "refine_destroy", "refine_batch_init", "refine_batch_run",
            "refine_batch_destroy", "refine_status_string", "refine_time_product",
-           "refine_batch_time_product")
+           "refine_batch_time_product", "refine_rayleigh_ritz")
 
 _lib = None
 
@@ -93,6 +94,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.refine_batch_run.argtypes = [vp, P(vp), P(i64), i32, P(refine_stats)]
     lib.refine_batch_destroy.argtypes = [vp]
     lib.refine_time_product.argtypes = [vp, vp, i64, i32, P(ctypes.c_float)]
+    lib.refine_rayleigh_ritz.argtypes = [vp, vp, i64]
     lib.refine_batch_time_product.argtypes = [vp, i32, P(ctypes.c_float)]
     lib.refine_debug_workspace.argtypes = [vp, P(vp), i32]
     lib.refine_debug_workspace.restype = ctypes.c_int
@@ -100,7 +102,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.refine_status_string.restype = ctypes.c_char_p
     for name in ("refine_init", "refine_step", "refine_run", "refine_get_info", "refine_destroy",
                  "refine_batch_init", "refine_batch_run", "refine_batch_destroy",
-                 "refine_batch_time_product",
+                 "refine_batch_time_product", "refine_rayleigh_ritz",
                  "refine_time_product"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -132,6 +134,10 @@ def refine_run(ctx, X_ptr: int, ldx: int, max_iters: int, stop: int, tol: float,
                stats: refine_stats | None) -> int:
     return _l().refine_run(ctx, X_ptr, ldx, max_iters, stop, tol,
                            ctypes.byref(stats) if stats is not None else None)
+
+
+def refine_rayleigh_ritz(ctx, X_ptr: int, ldx: int) -> int:
+    return _l().refine_rayleigh_ritz(ctx, X_ptr, ldx)
 
 
 def refine_get_info(ctx):
@@ -279,6 +285,15 @@ class RefineContext:
         st = refine_stats()
         rc = refine_run(self._ctx, X.data_ptr(), X.stride(0), max_iters, STOPS[stop], tol, st)
         return Stats(st.corr_fro, st.resid_rel, st.iters, rc)
+
+    def rayleigh_ritz(self, X: torch.Tensor) -> None:
+        """Rayleigh-Ritz preprocessing of X in place (Sec. 4, clustered
+        eigenvalues); the next applied step takes the leading block of E_L as
+        zero.  Raises RefineError (ERANK when X^T X is not positive definite)."""
+        self._check_x(X)
+        rc = refine_rayleigh_ritz(self._ctx, X.data_ptr(), X.stride(0))
+        if rc != OK:
+            raise RefineError(rc, "refine_rayleigh_ritz")
 
     def time_product(self, X: torch.Tensor, reps: int) -> float:
         """Mean milliseconds of one launch of the product W = A X alone."""

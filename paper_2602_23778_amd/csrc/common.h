@@ -30,7 +30,7 @@ struct Ctrl {
   double resid_rel;
   double hist[4];     // ||E_L||_F of the last applied steps (ring)
   int32_t kxk_fb;     // this step's k-by-k work falls back to the one-workgroup solver
-  int32_t pad0;
+  int32_t rr_top;     // X is a Rayleigh-Ritz basis: the next applied step takes E11 = 0
 };
 
 // One problem: a symmetric matrix, its iterate and its workspace slices.

@@ -305,10 +305,13 @@ __global__ __launch_bounds__(KXK_NT) void kxk_kernel(const Prob* __restrict__ pr
     double* Fm = (Z == Fb) ? Zb : Fb;
     double e1sq = 0.0;
     const double delta = P.delta;
+    const bool rr_top = ctrl->rr_top != 0;
     for (int e = tid; e < kk2; e += KXK_NT) {
       const int i = e / k, j = e - i * k;
       double v;
-      if (i == j) {
+      if (rr_top) {
+        v = 0.0;  // X is a Rayleigh-Ritz basis (Sec. 4, clustered eigenvalues)
+      } else if (i == j) {
         v = (1.0 - alpha[i]) * 0.5;
       } else if (fabs(d[j] - d[i]) <= delta) {
         v = P.beta_zero ? 0.0 : -(GT[e] + G2[e]) * 0.5;
@@ -639,7 +642,9 @@ __global__ __launch_bounds__(KS_NT) void kxk_small_kernel(const Prob* __restrict
         if (e < kk2) {
           const int i = e / k, j = e - i * k;
           double v;
-          if (i == j)
+          if (ctrl->rr_top)
+            v = 0.0;  // X is a Rayleigh-Ritz basis (Sec. 4, clustered eigenvalues)
+          else if (i == j)
             v = (1.0 - alpha[i]) * 0.5;
           else if (fabs(d[j] - d[i]) <= delta)
             v = P.beta_zero ? 0.0 : -gv[q] * 0.5;
@@ -841,7 +846,9 @@ __global__ __launch_bounds__(512) void pp_res_kernel(const Prob* __restrict__ pr
       const double v1 = vpt[r] + vp2[r];
       *gst(Cb + e) = v1 - vr1[r];
       double ev;
-      if (i == j)
+      if (ctrl->rr_top)
+        ev = 0.0;  // X is a Rayleigh-Ritz basis (Sec. 4, clustered eigenvalues)
+      else if (i == j)
         ev = (1.0 - ai[r]) * 0.5;
       else if (fabs(dj - di[r]) <= P.delta)
         ev = P.beta_zero ? 0.0 : -vg[r] * 0.5;

@@ -826,6 +826,7 @@ __global__ __launch_bounds__(1024) void fin_stats_kernel(const Prob* __restrict_
         C->stopped = 1;
       } else {
         C->apply = 1;
+        C->rr_top = 0;  // a Rayleigh-Ritz basis serves one step
         C->hist[h & 3] = corr;
         C->iters = h + 1;
         if ((C->stop_mode == 1 && corr <= C->tol) || (C->stop_mode == 2 && resid <= C->tol)) {

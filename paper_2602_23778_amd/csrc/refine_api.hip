@@ -40,6 +40,9 @@ hipError_t launch_fin_stats(const Prob*, int, hipStream_t);
 hipError_t launch_ctrl_reset(const Prob*, int, int, double, hipStream_t);
 hipError_t launch_set_x(Prob*, int, double*, int64_t, hipStream_t);
 hipError_t launch_spmm(const Prob*, const RowItem*, int, int, hipStream_t);
+hipError_t launch_rr_prep(const Prob*, int, hipStream_t);
+hipError_t launch_rr_solve(const Prob*, int, hipStream_t);
+hipError_t launch_rr_apply(const Prob*, const RowItem*, int, hipStream_t);
 int spmm_chunk_rows();
 int spmm_grid(int nitems);
 hipError_t launch_rowstats(int, int, const double*, int64_t, const int32_t*, const int32_t*,
@@ -456,7 +459,8 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
   return REFINE_OK;
 }
 
-hipError_t enqueue_step(Plan& pl, hipStream_t st) {
+// Line 1 of Algorithm 4 for every problem: W = A X (and the K-split sum).
+hipError_t enqueue_product(Plan& pl, hipStream_t st) {
   hipError_t e;
   const int np = (int)pl.hprob.size();
   if (pl.csr) {
@@ -474,6 +478,13 @@ hipError_t enqueue_step(Plan& pl, hipStream_t st) {
           (e = launch_wsum(pl.dprob, p, pl.hprob[p].n, pl.hprob[p].k, st)) != hipSuccess)
         return e;
   }
+  return hipSuccess;
+}
+
+hipError_t enqueue_step(Plan& pl, hipStream_t st) {
+  hipError_t e;
+  const int np = (int)pl.hprob.size();
+  if ((e = enqueue_product(pl, st)) != hipSuccess) return e;
   if ((e = launch_fin_d(pl.dprob, np, st)) != hipSuccess) return e;
   if ((e = launch_gram(pl.dprob, pl.gram_items, pl.n_gram, pl.kmax, st)) != hipSuccess) return e;
   if ((e = launch_gram_reduce(pl.dprob, pl.gred_items, pl.n_gred, st)) != hipSuccess) return e;
@@ -656,6 +667,8 @@ const char* refine_status_string(int s) {
       return "refinement diverged (||E_L||_F >= 1 or growing)";
     case REFINE_ENONFINITE:
       return "non-finite values";
+    case REFINE_ERANK:
+      return "X^T X is not positive definite (dependent columns)";
     default:
       return "unknown status";
   }
@@ -737,6 +750,31 @@ int refine_step(refine_ctx* c, double* X, int64_t ldx, refine_stats* stats) {
     if (launch_ctrl_reset(c->plan.dprob, 1, 0, 0.0, c->stream) != hipSuccess) return REFINE_EHIP;
   }
   return st;
+}
+
+int refine_rayleigh_ritz(refine_ctx* c, double* X, int64_t ldx) {
+  if (!c) return REFINE_EINVAL;
+  int rc = set_x(c, X, ldx);
+  if (rc != REFINE_OK) return rc;
+  Plan& pl = c->plan;
+  hipStream_t st = c->stream;
+  hipError_t e = launch_ctrl_reset(pl.dprob, 1, 0, 0.0, st);
+  if (e == hipSuccess) e = enqueue_product(pl, st);
+  if (e == hipSuccess) e = launch_rr_prep(pl.dprob, 1, st);
+  if (e == hipSuccess) e = launch_gram(pl.dprob, pl.gram_items, pl.n_gram, pl.kmax, st);
+  if (e == hipSuccess) e = launch_gram_reduce(pl.dprob, pl.gred_items, pl.n_gred, st);
+  if (e == hipSuccess) e = launch_rr_solve(pl.dprob, 1, st);
+  if (e == hipSuccess) e = launch_rr_apply(pl.dprob, pl.row_items, pl.n_row, st);
+  if (e != hipSuccess) return REFINE_EHIP;
+  std::vector<Ctrl> cs;
+  rc = read_ctrl(pl, st, cs);
+  if (rc != REFINE_OK) return rc;
+  const int status = cs[0].status;
+  if (status != 0) {
+    if (launch_ctrl_reset(pl.dprob, 1, 0, 0.0, st) != hipSuccess) return REFINE_EHIP;
+    return status;
+  }
+  return REFINE_OK;
 }
 
 int refine_run(refine_ctx* c, double* X, int64_t ldx, int32_t max_iters, refine_stop stop,
