@@ -90,6 +90,21 @@ def _traffic_for(n, k):
         return None
 
 
+def _time_rayleigh_ritz(ctx, X0, torch, reps=3):
+    """Milliseconds of one Rayleigh-Ritz preprocessing call (Sec. 4) on a copy
+    of the start block, host-synchronised (the call reads its status back)."""
+    best = None
+    for _ in range(reps):
+        Xr = X0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.rayleigh_ritz(Xr)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) * 1e3
+        best = t if best is None else min(best, t)
+    return best
+
+
 def bench_dense(args, rf, torch, np):
     import synth
     dev = "cuda:0"
@@ -125,6 +140,7 @@ def bench_dense(args, rf, torch, np):
     # dominant kernel: the product W = A X, timed with HIP events on the
     # context's stream, same launch configuration as inside the step
     ms_prod = ctx.time_product(X0.clone(), args.product_reps)
+    rr_ms = _time_rayleigh_ritz(ctx, X0, torch)
     ctx.close()
     flops = 2.0 * n * n * k
     eff = flops / (ms_prod * 1e-3) / 1e12
@@ -189,6 +205,7 @@ def bench_dense(args, rf, torch, np):
            "corr_fro_first": st1.corr_fro, "corr_fro_last": st_last.corr_fro,
            "resid_rel_last": st_last.resid_rel,
            "orthogonality_last": _orthogonality(X.cpu().numpy()),
+           "rayleigh_ritz_ms": rr_ms,
            "split": split_block}
     cfg.update(errs)
     return {"value": value, "ms_per_step": sec * 1e3, "unit": "eigvecs/s",
@@ -209,6 +226,7 @@ def bench_laplacian(args, rf, torch, np):
     X = X0.clone()
     sec, st1, st_last, X_first = _time_steps(ctx, X, args.steps, args.warmup, torch)
     ms_prod = ctx.time_product(X0.clone(), args.product_reps)
+    rr_ms = _time_rayleigh_ritz(ctx, X0, torch)
     ctx.close()
     byts = 12.0 * nnz + 4.0 * (n + 1) + 16.0 * n * k
     gbs = byts / (ms_prod * 1e-3) / 1e9
@@ -224,7 +242,8 @@ def bench_laplacian(args, rf, torch, np):
            "corr_fro_first": st1.corr_fro, "corr_fro_last": st_last.corr_fro,
            "resid_rel_last": st_last.resid_rel,
            "err_vs_exact_eigvecs_last": _aligned_err(Xg, Xt),
-           "err_vs_exact_eigvecs_start": _aligned_err(X0h, Xt)}
+           "err_vs_exact_eigvecs_start": _aligned_err(X0h, Xt),
+           "rayleigh_ritz_ms": rr_ms}
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -266,8 +285,14 @@ def bench_batch(args, rf, torch, np):
         torch.cuda.synchronize()
         sec = (time.perf_counter() - t0) / (reps * steps_per_graph)
         ms_prod = b.time_product(args.product_reps)
+        Xr = [x.clone() for x in X0s]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.rayleigh_ritz(Xr)
+        torch.cuda.synchronize()
+        rr_ms = (time.perf_counter() - t0) * 1e3
         b.close()
-        res[prec] = {"sec": sec, "first": first, "rc": rc, "ms_prod": ms_prod}
+        res[prec] = {"sec": sec, "first": first, "rc": rc, "ms_prod": ms_prod, "rr_ms": rr_ms}
     byts = sum(8.0 * n * n for n in ns)
     main = res["fp64"]
     gbs = byts / (main["ms_prod"] * 1e-3) / 1e9
@@ -278,6 +303,7 @@ def bench_batch(args, rf, torch, np):
                        "clusters of internal gap 1e-6, 5 steps per graph, FP64 form" % count,
            "problems": count, "sum_k": ksum, "mean_n2": float(np.mean(np.array(ns, float) ** 2)),
            "precision": "fp64", "product_us": main["ms_prod"] * 1e3,
+           "rayleigh_ritz_ms": main["rr_ms"],
            "split": {"slices": args.slices, "eigvecs_per_s": ksum / res["split_int8"]["sec"],
                      "ms_per_step": res["split_int8"]["sec"] * 1e3,
                      "product_us": res["split_int8"]["ms_prod"] * 1e3,

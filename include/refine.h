@@ -198,6 +198,17 @@ int refine_batch_init(refine_batch** b, int32_t count, const refine_matrix* As,
 int refine_batch_run(refine_batch* b, double* const* Xs, const int64_t* ldxs,
                      int32_t iters, refine_stats* per_problem);
 
+/* Rayleigh-Ritz preprocessing of every problem of a batch, as
+ * refine_rayleigh_ritz (Sec. 4, clustered eigenvalues): Xs[p] (device,
+ * n_p x k_p, ld ldxs[p], NULL ldxs meaning ld = k_p) is overwritten with its
+ * Ritz basis and the next applied step of that problem takes the leading
+ * block of E_L as zero.  status (count entries) may be NULL; it receives each
+ * problem's result (REFINE_OK or REFINE_ERANK, whose X is left unchanged).
+ * Returns REFINE_OK, the first failing problem's status, or an argument or
+ * HIP error.  Synchronises with the host once. */
+int refine_batch_rayleigh_ritz(refine_batch* b, double* const* Xs, const int64_t* ldxs,
+                               int32_t* status);
+
 int refine_batch_destroy(refine_batch* b);
 
 /* Measurement hook, as refine_time_product for a batch: `reps` launches of

@@ -61,7 +61,7 @@ class refine_stats(ctypes.Structure):
 EXPORTS = ("refine_options_default", "refine_init", "refine_step", "refine_run",
            "refine_get_info", "refine_destroy", "refine_batch_init", "refine_batch_run",
            "refine_batch_destroy", "refine_status_string", "refine_time_product",
-           "refine_batch_time_product", "refine_rayleigh_ritz")
+           "refine_batch_time_product", "refine_rayleigh_ritz", "refine_batch_rayleigh_ritz")
 
 _lib = None
 
@@ -95,6 +95,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.refine_batch_destroy.argtypes = [vp]
     lib.refine_time_product.argtypes = [vp, vp, i64, i32, P(ctypes.c_float)]
     lib.refine_rayleigh_ritz.argtypes = [vp, vp, i64]
+    lib.refine_batch_rayleigh_ritz.argtypes = [vp, P(vp), P(i64), P(i32)]
     lib.refine_batch_time_product.argtypes = [vp, i32, P(ctypes.c_float)]
     lib.refine_debug_workspace.argtypes = [vp, P(vp), i32]
     lib.refine_debug_workspace.restype = ctypes.c_int
@@ -103,7 +104,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     for name in ("refine_init", "refine_step", "refine_run", "refine_get_info", "refine_destroy",
                  "refine_batch_init", "refine_batch_run", "refine_batch_destroy",
                  "refine_batch_time_product", "refine_rayleigh_ritz",
-                 "refine_time_product"):
+                 "refine_batch_rayleigh_ritz", "refine_time_product"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -169,6 +170,10 @@ def refine_batch_init(b: ctypes.c_void_p, count: int, As, ks, opt, hip_stream) -
 
 def refine_batch_run(b, Xs, ldxs, iters: int, per_problem) -> int:
     return _l().refine_batch_run(b, Xs, ldxs, iters, per_problem)
+
+
+def refine_batch_rayleigh_ritz(b, Xs, ldxs, status) -> int:
+    return _l().refine_batch_rayleigh_ritz(b, Xs, ldxs, status)
 
 
 def refine_batch_destroy(b) -> int:
@@ -371,6 +376,16 @@ class RefineBatch:
         per = (refine_stats * n)()
         rc = refine_batch_run(self._b, ptrs, lds, iters, per)
         return rc, [Stats(p.corr_fro, p.resid_rel, p.iters, p.status) for p in per]
+
+    def rayleigh_ritz(self, Xs):
+        """Rayleigh-Ritz preprocessing of every problem in place (Sec. 4);
+        returns (status, per-problem statuses)."""
+        n = len(self._As)
+        ptrs = (ctypes.c_void_p * n)(*[X.data_ptr() for X in Xs])
+        lds = (ctypes.c_int64 * n)(*[X.stride(0) for X in Xs])
+        st = (ctypes.c_int32 * n)()
+        rc = refine_batch_rayleigh_ritz(self._b, ptrs, lds, st)
+        return rc, list(st)
 
     def time_product(self, reps: int) -> float:
         """Mean milliseconds of one grouped product launch (X of the last run)."""

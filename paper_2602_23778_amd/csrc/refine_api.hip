@@ -916,9 +916,8 @@ int refine_batch_init(refine_batch** out, int32_t count, const refine_matrix* As
   return REFINE_OK;
 }
 
-int refine_batch_run(refine_batch* b, double* const* Xs, const int64_t* ldxs, int32_t iters,
-                     refine_stats* per) {
-  if (!b || !Xs || iters < 0) return REFINE_EINVAL;
+// Binds the problems' iterates (device descriptors rewritten only on change).
+static int bind_batch_x(refine_batch* b, double* const* Xs, const int64_t* ldxs) {
   const int np = (int)b->As.size();
   bool changed = false;
   for (int p = 0; p < np; ++p) {
@@ -939,6 +938,15 @@ int refine_batch_run(refine_batch* b, double* const* Xs, const int64_t* ldxs, in
         hipSuccess)
       return REFINE_EHIP;
   }
+  return REFINE_OK;
+}
+
+int refine_batch_run(refine_batch* b, double* const* Xs, const int64_t* ldxs, int32_t iters,
+                     refine_stats* per) {
+  if (!b || !Xs || iters < 0) return REFINE_EINVAL;
+  const int np = (int)b->As.size();
+  int brc = bind_batch_x(b, Xs, ldxs);
+  if (brc != REFINE_OK) return brc;
   if (launch_steps(b->plan, iters, b->stream) != hipSuccess) return REFINE_EHIP;
   if (!per) return REFINE_OK;
   std::vector<Ctrl> cs;
@@ -957,6 +965,35 @@ int refine_batch_run(refine_batch* b, double* const* Xs, const int64_t* ldxs, in
     }
   }
   if (any_bad && launch_ctrl_reset(b->plan.dprob, np, 0, 0.0, b->stream) != hipSuccess)
+    return REFINE_EHIP;
+  return worst;
+}
+
+int refine_batch_rayleigh_ritz(refine_batch* b, double* const* Xs, const int64_t* ldxs,
+                               int32_t* status) {
+  if (!b || !Xs) return REFINE_EINVAL;
+  const int np = (int)b->As.size();
+  int rc = bind_batch_x(b, Xs, ldxs);
+  if (rc != REFINE_OK) return rc;
+  Plan& pl = b->plan;
+  hipStream_t st = b->stream;
+  hipError_t e = launch_ctrl_reset(pl.dprob, np, 0, 0.0, st);
+  if (e == hipSuccess) e = enqueue_product(pl, st);
+  if (e == hipSuccess) e = launch_rr_prep(pl.dprob, np, st);
+  if (e == hipSuccess) e = launch_gram(pl.dprob, pl.gram_items, pl.n_gram, pl.kmax, st);
+  if (e == hipSuccess) e = launch_gram_reduce(pl.dprob, pl.gred_items, pl.n_gred, st);
+  if (e == hipSuccess) e = launch_rr_solve(pl.dprob, np, st);
+  if (e == hipSuccess) e = launch_rr_apply(pl.dprob, pl.row_items, pl.n_row, st);
+  if (e != hipSuccess) return REFINE_EHIP;
+  std::vector<Ctrl> cs;
+  rc = read_ctrl(pl, st, cs);
+  if (rc != REFINE_OK) return rc;
+  int worst = REFINE_OK;
+  for (int p = 0; p < np; ++p) {
+    if (status) status[p] = cs[p].status;
+    if (cs[p].status != 0 && worst == REFINE_OK) worst = cs[p].status;
+  }
+  if (worst != REFINE_OK && launch_ctrl_reset(pl.dprob, np, 0, 0.0, st) != hipSuccess)
     return REFINE_EHIP;
   return worst;
 }

@@ -138,3 +138,28 @@ def test_rayleigh_ritz_rejects_dependent_columns():
     X2 = _dev(P.X0).clone()
     assert ctx.step(X2).status == rf.OK
     ctx.close()
+
+
+def test_batched_rayleigh_ritz_matches_oracle_per_problem():
+    """Grouped launches over uneven problems (one of them with dependent
+    columns, which alone reports REFINE_ERANK and keeps its X), then a step
+    with the zero leading block, against the oracle problem by problem."""
+    rf = _lib()
+    shapes = [(130, 4), (257, 9), (511, 32), (200, 17), (129, 31)]
+    probs = [synth.dense_spectrum(n, k, 6500 + i) for i, (n, k) in enumerate(shapes)]
+    X0s = [np.array(p.X0) for p in probs]
+    X0s[3][:, 5] = X0s[3][:, 4]
+    b = rf.RefineBatch([_dev(p.A) for p in probs], [k for _, k in shapes], norm_a=1.0)
+    Xs = [_dev(x).clone() for x in X0s]
+    rc, st = b.rayleigh_ritz(Xs)
+    assert rc == rf.ERANK and st == [0, 0, 0, rf.ERANK, 0]
+    assert np.array_equal(Xs[3].cpu().numpy(), X0s[3])
+    rc, per = b.run(Xs, 1)
+    for i, ((n, k), p) in enumerate(zip(shapes, probs)):
+        if i == 3:
+            continue
+        Zo, _ = oracle.rayleigh_ritz(p.A, X0s[i])
+        r = oracle.refine_step(p.A, Zo, norm_a=1.0, rr_top=True)
+        err = float(np.max(np.abs(align_signs(Xs[i].cpu().numpy(), r.X) - r.X)))
+        assert err <= TOL, "problem %d: %.3e" % (i, err)
+    b.close()
