@@ -181,6 +181,44 @@ def compact_wy(X):
     return rc, Y, T, c.value
 
 
+def modified_lu(Q):
+    """Algorithm 2 (Ballard's modified LU): for each column j the sign
+    sigma_j = -sign(q_jj) of the current diagonal entry is subtracted from it
+    before the elimination, so the pivot is at least 1 in magnitude for
+    orthonormal columns.  Returns (Y, U, sigma) with Q - Sigma = Y U, Y n x k
+    unit lower trapezoidal and U k x k upper triangular (sign(0) = +1)."""
+    Qw = np.array(_f64(Q), dtype=np.float64, copy=True)
+    n, k = Qw.shape
+    sigma = np.zeros(k)
+    for j in range(k):
+        sigma[j] = -1.0 if Qw[j, j] >= 0.0 else 1.0
+        Qw[j, j] -= sigma[j]
+        Qw[j + 1:, j] /= Qw[j, j]
+        Qw[j + 1:, j + 1:] -= np.outer(Qw[j + 1:, j], Qw[j, j + 1:])
+    U = np.triu(Qw[:k, :])
+    Y = np.tril(Qw, -1)
+    Y[np.arange(k), np.arange(k)] = 1.0
+    return Y, U, sigma
+
+
+def compact_wy_lu(Q):
+    """Algorithm 3: [Y, U, Sigma] = modified_LU(Q), T = -U Sigma Y1^{-T};
+    for orthonormal Q, H = I - Y T Y^T is orthogonal and its first k columns
+    are Q Sigma (the stated identity holds up to these column signs, since
+    I_{n,k} + Y U Sigma = I_{n,k} + (Q - Sigma) Sigma).  Returns (Y, T, sigma)."""
+    Y, U, sigma = modified_lu(Q)
+    k = U.shape[0]
+    T = -(U * sigma) @ np.linalg.inv(Y[:k].T)
+    return Y, T, sigma
+
+
+def sign_flip(X):
+    """The one-time transformation X <- X Sigma of Sec. 3.1 (Sigma from the
+    modified LU), after which Algorithm 1 applies.  Returns (X Sigma, sigma)."""
+    _, _, sigma = modified_lu(X)
+    return _f64(X) * sigma, sigma
+
+
 def apply_h(Y, T, B, trans: bool = False):
     """H B or H^T B with H = I - Y T Y^T, without forming H (after Table 1)."""
     lib = _load()

@@ -555,3 +555,60 @@ def test_rr_zero_top_step_keeps_the_bottom_block():
     assert np.array_equal(a.E[k:], b.E[k:])
     assert np.max(np.abs(np.diag(b.E[:k]))) < 1e-14
     assert a.corr_fro <= b.corr_fro
+
+
+# --------------------------------------------------------------------------
+# Modified LU, compact WY from it, and the one-time sign flip (Sec. 3.1)
+# --------------------------------------------------------------------------
+def _x_with_singular_y1(n, k, seed):
+    """Orthonormal columns whose first one is e_1 (so Y1 = X1 - I has a zero
+    column and Algorithm 1 cannot run)."""
+    Xo = _orthonormal(n - 1, k - 1, seed)
+    X = np.zeros((n, k))
+    X[0, 0] = 1.0
+    X[1:, 1:] = Xo
+    return X
+
+
+@pytest.mark.parametrize("case", ["random", "singular_y1"])
+def test_modified_lu_factorises_q_minus_sigma(case):
+    n, k = 40, 6
+    X = _orthonormal(n, k, 77) if case == "random" else _x_with_singular_y1(n, k, 78)
+    Y, U, sigma = oracle.modified_lu(X)
+    S = np.zeros((n, k))
+    S[np.arange(k), np.arange(k)] = sigma
+    assert np.max(np.abs(X - S - Y @ U)) < 1e-14
+    assert np.all(np.abs(np.diag(U)) >= 1.0 - 1e-14)
+    assert np.array_equal(np.abs(sigma), np.ones(k))
+    assert np.allclose(np.tril(U, -1), 0.0) and np.allclose(np.diag(Y[:k]), 1.0)
+
+
+@pytest.mark.parametrize("case", ["random", "singular_y1"])
+def test_compact_wy_lu_is_orthogonal_and_maps_the_first_columns(case):
+    """Algorithm 3 for any orthonormal Q, including one whose Y1 is singular
+    for Algorithm 1: H = I - Y T Y^T is orthogonal and its first k columns are
+    Q Sigma (I_{n,k} + Y U Sigma = I_{n,k} + (Q - Sigma) Sigma), i.e. Q up to
+    the column signs that the one-time flip absorbs."""
+    n, k = 30, 5
+    X = _orthonormal(n, k, 81) if case == "random" else _x_with_singular_y1(n, k, 82)
+    Y, T, sigma = oracle.compact_wy_lu(X)
+    H = np.eye(n) - Y @ T @ Y.T
+    assert np.max(np.abs(H.T @ H - np.eye(n))) < 1e-13
+    assert np.max(np.abs(H[:, :k] - X * sigma)) < 1e-13
+    # T is upper triangular, as a compact WY T factor is
+    assert np.max(np.abs(np.tril(T, -1))) < 1e-13
+
+
+def test_sign_flip_makes_compact_wy_applicable():
+    """Algorithm 1 fails on X (Y1 singular) and succeeds on X Sigma, whose
+    columns span the same space; the flip changes signs only."""
+    n, k = 50, 5
+    X = _x_with_singular_y1(n, k, 83)
+    rc, _, _, _ = oracle.compact_wy(X)
+    assert rc == oracle.SINGULAR
+    Xf, sigma = oracle.sign_flip(X)
+    assert np.array_equal(np.abs(Xf), np.abs(X))
+    rc, Y, T, cond = oracle.compact_wy(Xf)
+    assert rc == oracle.OK and cond < 1e3
+    H = np.eye(n) - Y @ T @ Y.T
+    assert np.max(np.abs(H[:, :k] - Xf)) < 1e-13
