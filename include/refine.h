@@ -47,8 +47,7 @@ extern "C" {
 #define REFINE_EHIP (-3)         /* a HIP runtime call failed */
 #define REFINE_EWY_SINGULAR (-4) /* Y1 = X(1:k,:) - I_k singular or cond_1 > 1/(n u)
                                     (Algorithm 1 needs Y1 nonsingular, Sec. 3.1);
-                                    the one-time sign flip X <- X Sigma of Sec. 3.1
-                                    is left to the caller */
+                                    X is unchanged: refine_sign_flip, then step again */
 #define REFINE_EDIVERGED (-5)    /* ||E_L||_F >= 1 (the Neumann expansion of
                                     eq. Neumann needs ||E|| < 1), or ||E_L||_F grew
                                     tenfold over three steps (Sec. 4.3 guidance) */
@@ -172,6 +171,22 @@ int refine_get_info(const refine_ctx* ctx, double* mu, double* norm_inf,
  * or an argument or HIP error.  Synchronises with the host once. */
 int refine_rayleigh_ritz(refine_ctx* ctx, double* X, int64_t ldx);
 
+/* One-time column sign flip X <- X Sigma (Sec. 3.1), for an X on which the
+ * step reports REFINE_EWY_SINGULAR.  Sigma = diag(sigma) is the sign matrix
+ * of the modified LU factorisation of X (Algorithm 2: sigma_j = -sign(q_jj)
+ * of the diagonal entry at elimination step j, sign(0) = +1), which depends
+ * on the leading k x k block of X alone; after the flip, X Sigma - I_{n,k} =
+ * Y U Sigma with Y unit lower trapezoidal and |u_jj| >= 1 (Algorithm 3), so
+ * the leading block of the compact WY factor is nonsingular and the steps of
+ * Algorithm 1 apply.  The flip spans the same space and keeps a Rayleigh-Ritz
+ * basis one (the zero leading block of E_L stays armed).
+ * X: device, n x k row-major, leading dimension ldx, updated in place.
+ * sigma: HOST array of k entries receiving +1 or -1, or NULL.
+ * Returns REFINE_OK, REFINE_ENONFINITE for a NaN or Inf in the leading block
+ * or a pivot (X unchanged), or an argument or HIP error.  Synchronises with
+ * the host once. */
+int refine_sign_flip(refine_ctx* ctx, double* X, int64_t ldx, int32_t* sigma);
+
 int refine_destroy(refine_ctx* ctx);
 
 /* Measurement hook for the roofline figures: enqueues `reps` launches of the
@@ -208,6 +223,16 @@ int refine_batch_run(refine_batch* b, double* const* Xs, const int64_t* ldxs,
  * HIP error.  Synchronises with the host once. */
 int refine_batch_rayleigh_ritz(refine_batch* b, double* const* Xs, const int64_t* ldxs,
                                int32_t* status);
+
+/* The sign flip of refine_sign_flip on every problem of a batch, in one
+ * grouped launch (one workgroup per problem for the k_p x k_p elimination,
+ * then (problem, row block) items for the column scaling).  status (count
+ * entries) may be NULL; it receives each problem's result (REFINE_OK or
+ * REFINE_ENONFINITE, whose X is left unchanged).  Returns REFINE_OK, the
+ * first failing problem's status, or an argument or HIP error.  Synchronises
+ * with the host once. */
+int refine_batch_sign_flip(refine_batch* b, double* const* Xs, const int64_t* ldxs,
+                           int32_t* status);
 
 int refine_batch_destroy(refine_batch* b);
 

@@ -61,7 +61,8 @@ class refine_stats(ctypes.Structure):
 EXPORTS = ("refine_options_default", "refine_init", "refine_step", "refine_run",
            "refine_get_info", "refine_destroy", "refine_batch_init", "refine_batch_run",
            "refine_batch_destroy", "refine_status_string", "refine_time_product",
-           "refine_batch_time_product", "refine_rayleigh_ritz", "refine_batch_rayleigh_ritz")
+           "refine_batch_time_product", "refine_rayleigh_ritz", "refine_batch_rayleigh_ritz",
+           "refine_sign_flip", "refine_batch_sign_flip")
 
 _lib = None
 
@@ -96,6 +97,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.refine_time_product.argtypes = [vp, vp, i64, i32, P(ctypes.c_float)]
     lib.refine_rayleigh_ritz.argtypes = [vp, vp, i64]
     lib.refine_batch_rayleigh_ritz.argtypes = [vp, P(vp), P(i64), P(i32)]
+    lib.refine_sign_flip.argtypes = [vp, vp, i64, P(i32)]
+    lib.refine_batch_sign_flip.argtypes = [vp, P(vp), P(i64), P(i32)]
     lib.refine_batch_time_product.argtypes = [vp, i32, P(ctypes.c_float)]
     lib.refine_debug_workspace.argtypes = [vp, P(vp), i32]
     lib.refine_debug_workspace.restype = ctypes.c_int
@@ -104,7 +107,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     for name in ("refine_init", "refine_step", "refine_run", "refine_get_info", "refine_destroy",
                  "refine_batch_init", "refine_batch_run", "refine_batch_destroy",
                  "refine_batch_time_product", "refine_rayleigh_ritz",
-                 "refine_batch_rayleigh_ritz", "refine_time_product"):
+                 "refine_batch_rayleigh_ritz", "refine_time_product", "refine_sign_flip",
+                 "refine_batch_sign_flip"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -141,6 +145,10 @@ def refine_rayleigh_ritz(ctx, X_ptr: int, ldx: int) -> int:
     return _l().refine_rayleigh_ritz(ctx, X_ptr, ldx)
 
 
+def refine_sign_flip(ctx, X_ptr: int, ldx: int, sigma) -> int:
+    return _l().refine_sign_flip(ctx, X_ptr, ldx, sigma)
+
+
 def refine_get_info(ctx):
     v = [ctypes.c_double() for _ in range(4)]
     rc = _l().refine_get_info(ctx, *[ctypes.byref(x) for x in v])
@@ -174,6 +182,10 @@ def refine_batch_run(b, Xs, ldxs, iters: int, per_problem) -> int:
 
 def refine_batch_rayleigh_ritz(b, Xs, ldxs, status) -> int:
     return _l().refine_batch_rayleigh_ritz(b, Xs, ldxs, status)
+
+
+def refine_batch_sign_flip(b, Xs, ldxs, status) -> int:
+    return _l().refine_batch_sign_flip(b, Xs, ldxs, status)
 
 
 def refine_batch_destroy(b) -> int:
@@ -300,6 +312,18 @@ class RefineContext:
         if rc != OK:
             raise RefineError(rc, "refine_rayleigh_ritz")
 
+    def sign_flip(self, X: torch.Tensor) -> list:
+        """One-time column sign flip X <- X Sigma in place (Sec. 3.1, Sigma of
+        the modified LU, Algorithm 2), for an X whose compact WY factor is
+        singular; returns sigma as a list of +1 / -1."""
+        self._check_x(X)
+        k = X.shape[1]
+        sg = (ctypes.c_int32 * k)()
+        rc = refine_sign_flip(self._ctx, X.data_ptr(), X.stride(0), sg)
+        if rc != OK:
+            raise RefineError(rc, "refine_sign_flip")
+        return list(sg)
+
     def time_product(self, X: torch.Tensor, reps: int) -> float:
         """Mean milliseconds of one launch of the product W = A X alone."""
         self._check_x(X)
@@ -385,6 +409,16 @@ class RefineBatch:
         lds = (ctypes.c_int64 * n)(*[X.stride(0) for X in Xs])
         st = (ctypes.c_int32 * n)()
         rc = refine_batch_rayleigh_ritz(self._b, ptrs, lds, st)
+        return rc, list(st)
+
+    def sign_flip(self, Xs):
+        """Column sign flip X <- X Sigma of every problem in place (Sec. 3.1);
+        returns (status, per-problem statuses)."""
+        n = len(self._As)
+        ptrs = (ctypes.c_void_p * n)(*[X.data_ptr() for X in Xs])
+        lds = (ctypes.c_int64 * n)(*[X.stride(0) for X in Xs])
+        st = (ctypes.c_int32 * n)()
+        rc = refine_batch_sign_flip(self._b, ptrs, lds, st)
         return rc, list(st)
 
     def time_product(self, reps: int) -> float:

@@ -43,6 +43,8 @@ hipError_t launch_spmm(const Prob*, const RowItem*, int, int, hipStream_t);
 hipError_t launch_rr_prep(const Prob*, int, hipStream_t);
 hipError_t launch_rr_solve(const Prob*, int, hipStream_t);
 hipError_t launch_rr_apply(const Prob*, const RowItem*, int, hipStream_t);
+hipError_t launch_flip_sigma(const Prob*, int, hipStream_t);
+hipError_t launch_flip_apply(const Prob*, const RowItem*, int, hipStream_t);
 int spmm_chunk_rows();
 int spmm_grid(int nitems);
 hipError_t launch_rowstats(int, int, const double*, int64_t, const int32_t*, const int32_t*,
@@ -662,7 +664,7 @@ const char* refine_status_string(int s) {
     case REFINE_EHIP:
       return "HIP runtime error";
     case REFINE_EWY_SINGULAR:
-      return "Y1 = X(1:k,:) - I singular or ill-conditioned (compact WY needs it nonsingular)";
+      return "Y1 = X(1:k,:) - I singular or ill-conditioned (compact WY needs it nonsingular; refine_sign_flip)";
     case REFINE_EDIVERGED:
       return "refinement diverged (||E_L||_F >= 1 or growing)";
     case REFINE_ENONFINITE:
@@ -774,6 +776,34 @@ int refine_rayleigh_ritz(refine_ctx* c, double* X, int64_t ldx) {
     if (launch_ctrl_reset(pl.dprob, 1, 0, 0.0, st) != hipSuccess) return REFINE_EHIP;
     return status;
   }
+  return REFINE_OK;
+}
+
+int refine_sign_flip(refine_ctx* c, double* X, int64_t ldx, int32_t* sigma) {
+  if (!c) return REFINE_EINVAL;
+  int rc = set_x(c, X, ldx);
+  if (rc != REFINE_OK) return rc;
+  Plan& pl = c->plan;
+  hipStream_t st = c->stream;
+  hipError_t e = launch_ctrl_reset(pl.dprob, 1, 0, 0.0, st);
+  if (e == hipSuccess) e = launch_flip_sigma(pl.dprob, 1, st);
+  if (e == hipSuccess) e = launch_flip_apply(pl.dprob, pl.row_items, pl.n_row, st);
+  if (e != hipSuccess) return REFINE_EHIP;
+  std::vector<double> sg;
+  if (sigma) {
+    sg.resize(c->k);
+    RF_CHECK(hipMemcpyAsync(sg.data(), pl.hprob[0].vec + VEC_SCALE * c->k, sizeof(double) * c->k,
+                            hipMemcpyDeviceToHost, st));
+  }
+  std::vector<Ctrl> cs;
+  rc = read_ctrl(pl, st, cs);
+  if (rc != REFINE_OK) return rc;
+  const int status = cs[0].status;
+  if (status != 0) {
+    if (launch_ctrl_reset(pl.dprob, 1, 0, 0.0, st) != hipSuccess) return REFINE_EHIP;
+    return status;
+  }
+  for (int j = 0; sigma && j < c->k; ++j) sigma[j] = sg[j] < 0.0 ? -1 : 1;
   return REFINE_OK;
 }
 
@@ -984,6 +1014,30 @@ int refine_batch_rayleigh_ritz(refine_batch* b, double* const* Xs, const int64_t
   if (e == hipSuccess) e = launch_gram_reduce(pl.dprob, pl.gred_items, pl.n_gred, st);
   if (e == hipSuccess) e = launch_rr_solve(pl.dprob, np, st);
   if (e == hipSuccess) e = launch_rr_apply(pl.dprob, pl.row_items, pl.n_row, st);
+  if (e != hipSuccess) return REFINE_EHIP;
+  std::vector<Ctrl> cs;
+  rc = read_ctrl(pl, st, cs);
+  if (rc != REFINE_OK) return rc;
+  int worst = REFINE_OK;
+  for (int p = 0; p < np; ++p) {
+    if (status) status[p] = cs[p].status;
+    if (cs[p].status != 0 && worst == REFINE_OK) worst = cs[p].status;
+  }
+  if (worst != REFINE_OK && launch_ctrl_reset(pl.dprob, np, 0, 0.0, st) != hipSuccess)
+    return REFINE_EHIP;
+  return worst;
+}
+
+int refine_batch_sign_flip(refine_batch* b, double* const* Xs, const int64_t* ldxs, int32_t* status) {
+  if (!b || !Xs) return REFINE_EINVAL;
+  const int np = (int)b->As.size();
+  int rc = bind_batch_x(b, Xs, ldxs);
+  if (rc != REFINE_OK) return rc;
+  Plan& pl = b->plan;
+  hipStream_t st = b->stream;
+  hipError_t e = launch_ctrl_reset(pl.dprob, np, 0, 0.0, st);
+  if (e == hipSuccess) e = launch_flip_sigma(pl.dprob, np, st);
+  if (e == hipSuccess) e = launch_flip_apply(pl.dprob, pl.row_items, pl.n_row, st);
   if (e != hipSuccess) return REFINE_EHIP;
   std::vector<Ctrl> cs;
   rc = read_ctrl(pl, st, cs);

@@ -167,6 +167,25 @@ def dense_spectrum(n, k, seed, top_lo=0.9, top_hi=1.0, rest_hi=0.8, device="cpu"
                         {"workload": "dense_spectrum", "n": n, "k": k, "seed": seed})
 
 
+def dense_exact_first(n, k, seed, device="cpu", torch_out=False):
+    """As dense_spectrum, except that the largest target's eigenvector is e_1
+    exactly: Q = diag(1, Q') with Q' seeded Householder of order n - 1.  X0 =
+    fl32(Q_top) then has e_1 as its first column, so X0(1:k,:) - I_k has a zero
+    first column (the singular case of the compact WY form)."""
+    torch = _torch()
+    rng = np.random.default_rng(seed)
+    rest = rng.uniform(0.0, 0.8, n - k)
+    top = np.linspace(0.9, 1.0, k) if k > 1 else np.array([1.0])
+    lam = np.concatenate([[top[-1]], rest, top[:-1]])
+    targets = np.concatenate([[0], np.arange(n - 1, n - k, -1)]).astype(np.int64)
+    Q = torch.zeros((n, n), dtype=torch.float64, device=device)
+    Q[0, 0] = 1.0
+    Q[1:, 1:] = householder_q(n - 1, n - 1, seed + 1, device)
+    A, Xt = _assemble(Q, lam, targets, torch_out)
+    return DenseProblem(A, lam, targets, Xt, fp32_round(Xt), 0.0, float(lam.max()),
+                        {"workload": "dense_exact_first", "n": n, "k": k, "seed": seed})
+
+
 def batch_shapes(count=512, seed=SEED_BASE + 5, n_lo=128, n_hi=2048, k_lo=4, k_hi=32):
     """Sizes of the batched workload: n ~ U_int[n_lo, n_hi], k ~ U_int[k_lo, k_hi]."""
     rng = np.random.default_rng(seed)
