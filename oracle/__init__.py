@@ -57,7 +57,8 @@ class _Opts(ctypes.Structure):
                 ("normalize", ctypes.c_int32), ("dd", ctypes.c_int32),
                 ("shift_in_denominators", ctypes.c_int32),
                 ("plant_printed_sign", ctypes.c_int32),
-                ("split_slices", ctypes.c_int32), ("rr_zero_top", ctypes.c_int32)]
+                ("split_slices", ctypes.c_int32), ("rr_zero_top", ctypes.c_int32),
+                ("square", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -254,7 +255,7 @@ def refine_step(A, X, *, mu: float = 0.0, norm_a: float | None = None,
                 normalize: bool = True, dd: bool = False,
                 shift_in_denominators: bool = False,
                 plant_printed_sign: bool = False, split: int = 0,
-                rr_top: bool = False) -> StepResult:
+                rr_top: bool = False, square: bool = False) -> StepResult:
     """One step of Algorithm 4 (with Algorithm 1) on A (dense or Csr).
 
     mu: the method runs on A - mu I (Sec. 5.1); norm_a: ||A|| in delta and in
@@ -263,6 +264,8 @@ def refine_step(A, X, *, mu: float = 0.0, norm_a: float | None = None,
     pair (W_hi, W_lo) then used like the double-double one.
     rr_top: X is a Rayleigh-Ritz basis (the output of rayleigh_ritz); the
     leading k x k block of E_L is then zero (Sec. 4, clustered eigenvalues).
+    square: the method runs on B = A^2 - mu I (Sec. 5.2, eigenvectors of the
+    smallest |lambda|), line 1 as A (A X); norm_a then stands for ||B||.
     plant_printed_sign exists only so that a test can show that the sign
     printed in eq. (V-def) makes the iteration diverge."""
     lib = _load()
@@ -283,7 +286,8 @@ def refine_step(A, X, *, mu: float = 0.0, norm_a: float | None = None,
         m.kind = 0
         m.a, m.lda = _p(A), A.shape[1]
     o = _Opts(mu, delta_c, norm_a, int(beta_zero), int(normalize), int(dd),
-              int(shift_in_denominators), int(plant_printed_sign), int(split), int(rr_top))
+              int(shift_in_denominators), int(plant_printed_sign), int(split), int(rr_top),
+              int(square))
     st = _Stats()
     Xout = np.zeros((n, k))
     d = np.zeros(k)
@@ -293,7 +297,7 @@ def refine_step(A, X, *, mu: float = 0.0, norm_a: float | None = None,
     return StepResult(rc, Xout, st.corr_fro, st.resid_rel, st.cond_y1, d, E)
 
 
-def rayleigh_ritz(A, X, mu: float = 0.0):
+def rayleigh_ritz(A, X, mu: float = 0.0, square: bool = False):
     """Rayleigh-Ritz preprocessing on span(X) (Sec. 4, clustered eigenvalues):
     the symmetric-definite k x k problem (X^T A X) S = (X^T X) S Theta is
     solved by a library eigensolver (the step's one library primitive; A X is
@@ -303,11 +307,15 @@ def rayleigh_ritz(A, X, mu: float = 0.0):
     columns are ordered by |theta - mu| descending (the refinement's targets
     first, ties in ascending theta), and each column's sign makes z_jj <= 0,
     so that the leading block Z1 - I of the compact-WY factor keeps its
-    diagonal at or below -1.  Returns (Z, theta)."""
+    diagonal at or below -1.  square: the pencil of B = A^2 - mu I (Sec. 5.2),
+    with A X replaced by A (A X); theta are then eigenvalues of A^2.
+    Returns (Z, theta)."""
     import scipy.linalg
     X = _f64(X)
     n, k = X.shape
     W = matmul(A, X)
+    if square:
+        W = matmul(A, W)
     H = X.T @ W
     H = 0.5 * (H + H.T)
     G = X.T @ X

@@ -404,6 +404,9 @@ typedef struct {
   int32_t rr_zero_top;   /* 1: X is a Rayleigh-Ritz basis (Sec. 4, clustered
                             eigenvalues): the leading k x k block of E_L is
                             zero, so no d_j - d_i denominator is formed */
+  int32_t square;        /* 1: the method runs on B = A^2 - mu I (Sec. 5.2, the
+                            smallest |lambda|): line 1 forms A (A X), so A^2 is
+                            never formed (plain FP64 only) */
 } orc_opts;
 
 typedef struct {
@@ -452,6 +455,18 @@ int orc_refine_step(const orc_matrix* M, int64_t k, const double* X,
     else orc_gemm_csr(n, k, M->row_ptr, M->col_idx, M->val, X, ldx, W, k);
   }
   if (!pair) memset(Wlo, 0, sizeof(double) * nk);
+
+  /* Squared variant: W <- A W, so that W = A^2 X; the shift below then gives
+   * W_B = A^2 X - mu X. */
+  if (o->square) {
+    if (pair) { rc = ORC_EINVAL; goto done; }
+    double* W2 = (double*)malloc(sizeof(double) * nk);
+    if (!W2) { rc = ORC_ENOMEM; goto done; }
+    if (M->kind == 0) orc_gemm_dense(n, k, M->a, M->lda, W, k, W2, k);
+    else orc_gemm_csr(n, k, M->row_ptr, M->col_idx, M->val, W, k, W2, k);
+    memcpy(W, W2, sizeof(double) * nk);
+    free(W2);
+  }
 
   /* Shift, as the paper's variant does it: the method runs on B = A - mu I,
    * so W_B = W - mu X.  The derived form keeps W and puts mu only into the

@@ -186,6 +186,23 @@ def dense_exact_first(n, k, seed, device="cpu", torch_out=False):
                         {"workload": "dense_exact_first", "n": n, "k": k, "seed": seed})
 
 
+def dense_smallest_abs(n, k, seed, device="cpu", torch_out=False, top=0.3, rest_lo=0.7):
+    """Targets of small magnitude and both signs, +-top * (j + 1) / k with
+    alternating signs (distinct |lambda|); the rest have |lambda| iid
+    U[rest_lo, 1] with random signs.  The targets are the k smallest |lambda|
+    (the squared-shift variant).  X0 = fl32(Q_top), in ascending |lambda|."""
+    rng = np.random.default_rng(seed)
+    mag = rng.uniform(rest_lo, 1.0, n - k)
+    rest = mag * np.where(rng.uniform(size=n - k) < 0.5, -1.0, 1.0)
+    tgt = top * np.arange(1, k + 1) / k * np.where(np.arange(k) % 2 == 0, 1.0, -1.0)
+    lam = np.concatenate([rest, tgt])
+    targets = np.arange(n - k, n)
+    Q = householder_q(n, n, seed + 1, device)
+    A, Xt = _assemble(Q, lam, targets, torch_out)
+    return DenseProblem(A, lam, targets, Xt, fp32_round(Xt), 0.0, 1.0,
+                        {"workload": "dense_smallest_abs", "n": n, "k": k, "seed": seed})
+
+
 def batch_shapes(count=512, seed=SEED_BASE + 5, n_lo=128, n_hi=2048, k_lo=4, k_hi=32):
     """Sizes of the batched workload: n ~ U_int[n_lo, n_hi], k ~ U_int[k_lo, k_hi]."""
     rng = np.random.default_rng(seed)

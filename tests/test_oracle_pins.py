@@ -612,3 +612,74 @@ def test_sign_flip_makes_compact_wy_applicable():
     assert rc == oracle.OK and cond < 1e3
     H = np.eye(n) - Y @ T @ Y.T
     assert np.max(np.abs(H[:, :k] - Xf)) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# Squared shift for the smallest |lambda| (Sec. 5.2): B = A^2 - alpha I, with
+# A^2 X formed as A (A X)
+# --------------------------------------------------------------------------
+def test_square_equals_the_step_on_an_explicit_square():
+    """The step on B = A^2 - alpha I through two products equals the plain
+    shifted step on the explicitly formed (and symmetrised) A^2."""
+    n, k = 60, 4
+    P = synth.dense_smallest_abs(n, k, 91)
+    A = P.A
+    alpha = 0.6
+    r1 = oracle.refine_step(A, P.X0, mu=alpha, norm_a=1.0, square=True)
+    A2 = A @ A
+    A2 = 0.5 * (A2 + A2.T)
+    r2 = oracle.refine_step(A2, P.X0, mu=alpha, norm_a=1.0)
+    assert r1.status == 0 and r2.status == 0
+    assert np.max(np.abs(r1.X - r2.X)) < 1e-14
+    assert np.max(np.abs(r1.d - r2.d)) < 1e-14
+
+
+def test_square_k1_is_the_power_method_on_b():
+    """k = 1: one step is one power iteration x <- B x / ||B x|| on
+    B = A^2 - alpha I."""
+    n = 41
+    A, Q = _sym_problem(n, np.linspace(-1.0, 0.9, n), 17)
+    rng = np.random.default_rng(17)
+    x = Q[:, 20:21] + 0.05 * rng.standard_normal((n, 1))
+    x /= np.linalg.norm(x)
+    alpha = 0.7
+    r = oracle.refine_step(A, x, mu=alpha, norm_a=1.0, square=True)
+    y = A @ (A @ x) - alpha * x
+    y /= np.linalg.norm(y)
+    assert max_abs_diff_aligned(r.X, y) < 1e-15
+
+
+def test_square_converges_to_the_smallest_abs_eigenvectors():
+    """With alpha = (||A||^2 + lambda_{k+1}^2) / 2 the targets of smallest
+    |lambda| (both signs) satisfy the separation condition for B; the
+    iterates converge to them and d~ to lambda^2.  The same step without the
+    square (mu = 0) drifts away from them, as eq. (condition) predicts."""
+    n, k = 80, 5
+    P = synth.dense_smallest_abs(n, k, 93)
+    lam_t = P.lam[P.targets]
+    rest = np.delete(P.lam, P.targets)
+    alpha = (1.0 + np.min(np.abs(rest)) ** 2) / 2
+    X = P.X0
+    for _ in range(20):
+        r = oracle.refine_step(P.A, X, mu=alpha, norm_a=1.0, square=True)
+        assert r.status == 0
+        X = r.X
+    assert max_abs_diff_aligned(X, P.X_true) < 1e-13
+    assert np.max(np.abs(r.d - lam_t ** 2)) < 1e-14
+    Xp = P.X0
+    for _ in range(12):
+        rp = oracle.refine_step(P.A, Xp, norm_a=1.0)
+        if rp.status != 0:
+            break
+        Xp = rp.X
+    assert rp.status != 0 or max_abs_diff_aligned(Xp, P.X_true) > 1e-3
+
+
+def test_square_rayleigh_ritz_orders_by_distance_from_alpha():
+    """Rayleigh-Ritz on the squared pencil: theta are lambda^2 of the
+    targets, ascending (largest |theta - alpha| first)."""
+    n, k = 70, 4
+    P = synth.dense_smallest_abs(n, k, 95)
+    Z, theta = oracle.rayleigh_ritz(P.A, P.X0, mu=0.6, square=True)
+    assert np.all(np.diff(theta) >= 0.0)
+    assert np.max(np.abs(theta - np.sort(P.lam[P.targets] ** 2))) < 1e-12
