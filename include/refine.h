@@ -73,12 +73,23 @@ typedef enum { REFINE_FP64 = 0, REFINE_SPLIT_INT8 = 1 } refine_precision;
  *   LARGEST_ABS: mu = 0, the k eigenvalues of largest |lambda|;
  *   SMALLEST:    mu = max_i (a_ii + sum_{j!=i} |a_ij|) (Gershgorin upper bound);
  *   LARGEST:     mu = min_i (a_ii - sum_{j!=i} |a_ij|) (Gershgorin lower bound);
- *   SHIFT:       mu = options.shift, e.g. (||A||_inf + lambda_{k+1})/2 (Sec. 5.1). */
+ *   SHIFT:       mu = options.shift, e.g. (||A||_inf + lambda_{k+1})/2 (Sec. 5.1);
+ *   SMALLEST_ABS: the k eigenvalues of smallest |lambda| (Sec. 5.2): the method
+ *     runs on B = A^2 - alpha I, line 1 of Algorithm 4 as A (A X) by two
+ *     products (A^2 is never formed), with alpha = (||A||^2 + lhat^2)/2, lhat =
+ *     options.shift the caller's estimate of the (k+1)-th smallest |lambda|
+ *     (alpha = ||A||^2 when options.shift <= 0, which separates the targets
+ *     too, at a slower rate); ||A|| is options.norm_a, else ||A||_inf.  delta
+ *     and the residual statistic then use ||A||^2, a bound of ||B||, and the
+ *     Rayleigh quotients are those of A^2 (lambda^2).  FP64 only, dense or
+ *     CSR.  The paper prints |lhat| where the separation condition asks for
+ *     lhat^2 (alpha must exceed (||A||^2 + lambda_k^2)/2). */
 typedef enum {
   REFINE_TARGET_LARGEST_ABS = 0,
   REFINE_TARGET_SMALLEST = 1,
   REFINE_TARGET_LARGEST = 2,
-  REFINE_TARGET_SHIFT = 3
+  REFINE_TARGET_SHIFT = 3,
+  REFINE_TARGET_SMALLEST_ABS = 4
 } refine_target;
 
 /* beta_ij for (near-)equal Rayleigh quotients (line 6 of Algorithm 4):
@@ -108,7 +119,8 @@ typedef struct {
 typedef struct {
   refine_precision precision;
   refine_target target;
-  double shift;            /* mu for REFINE_TARGET_SHIFT */
+  double shift;            /* mu for REFINE_TARGET_SHIFT; the estimate lhat for
+                              REFINE_TARGET_SMALLEST_ABS */
   double delta_c;          /* delta = delta_c * ||A|| * 2^-53; the paper uses 10 (Sec. 3.3) */
   double norm_a;           /* ||A|| for delta and the residual statistic; <= 0: ||A||_inf */
   refine_beta beta;

@@ -69,6 +69,12 @@ struct Prob {
   double norm_a;          // ||A|| used in the residual statistic
   int32_t beta_zero;
   int32_t normalize;
+  // squared variant (B = A^2 - mu I): W = A W1 with W1 = A X; the products run
+  // from two derived descriptors, the first writing its Rayleigh partials
+  // (x*w1, x*x) to dpx, the second (w1*w, w1*w1) to dpart
+  int32_t square;
+  double* w1;             // A X, n x k (ld k), or nullptr
+  double* dpx;            // partials of the first product, ndp x (2 k), or nullptr
   // split form of the dense product (INT8 slices); unused otherwise
   const uint8_t* asl;     // slices of A in tiles of bm rows x 32 columns: the row block
                           // starting at row i0 at asl + i0*asl_rs, its chunk c, row r at

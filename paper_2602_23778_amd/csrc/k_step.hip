@@ -844,6 +844,7 @@ __global__ __launch_bounds__(1024) void fin_stats_kernel(const Prob* __restrict_
 __global__ __launch_bounds__(1024) void fin_d_kernel(const Prob* __restrict__ probs, int nprob) {
   constexpr int NT = 1024;
   __shared__ double tot[2 * KMAX];
+  __shared__ double totx[2 * KMAX];
   __shared__ double scr[NT];
   const int tid = threadIdx.x;
   for (int p = blockIdx.x; p < nprob; p += gridDim.x) {
@@ -852,10 +853,13 @@ __global__ __launch_bounds__(1024) void fin_d_kernel(const Prob* __restrict__ pr
     if (P.ctrl->stopped) continue;
     const int k = P.k;
     team_reduce(P.dpart, 2 * k, 2 * k, P.ndp, scr, tot);
+    // squared variant: x^T A^2 x = ||A x||^2 (A symmetric) is the second
+    // product's input norm, x^T x the first product's
+    if (P.square) team_reduce(P.dpx, 2 * k, 2 * k, P.ndp, scr, totx);
     int bad = 0;
     for (int j = tid; j < k; j += NT) {
-      const double a = tot[k + j];
-      const double d = tot[j] / a;
+      const double a = P.square ? totx[k + j] : tot[k + j];
+      const double d = (P.square ? tot[k + j] : tot[j]) / a;
       P.vec[VEC_D * k + j] = d;
       P.vec[VEC_ALPHA * k + j] = a;
       P.vec[VEC_DINV * k + j] = 1.0 / (d - P.mu);

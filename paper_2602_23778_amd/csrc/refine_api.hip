@@ -82,6 +82,9 @@ struct Plan {
   bool vec2 = true;
   bool csr = false;
   bool split = false;
+  bool square = false;            // B = A^2 - mu I: two products per step
+  Prob* dprob1 = nullptr;         // descriptors of the first product (X -> W1)
+  Prob* dprob2 = nullptr;         // and of the second (W1 -> W)
   SplitPlan sp;
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -161,6 +164,8 @@ void free_plan(Plan& p) {
   if (p.graph) (void)hipGraphDestroy(p.graph);
   if (p.cap_stream) (void)hipStreamDestroy(p.cap_stream);
   (void)hipFree(p.dprob);
+  (void)hipFree(p.dprob1);
+  (void)hipFree(p.dprob2);
   (void)hipFree(p.gemm_items);
   (void)hipFree(p.row_items);
   (void)hipFree(p.gram_items);
@@ -209,6 +214,28 @@ std::vector<GemmItem> gemm_items(const std::vector<refine_matrix>& As, int cfg, 
   return gi;
 }
 
+// Squared variant: the descriptors of the two products, derived from the
+// problem's own (first: X -> W1 with its Rayleigh partials in dpx; second:
+// W1 -> W).  Rewritten whenever the problem descriptors are.
+int upload_square_descs(Plan& pl) {
+  if (!pl.square) return REFINE_OK;
+  std::vector<Prob> d1(pl.hprob), d2(pl.hprob);
+  for (size_t p = 0; p < pl.hprob.size(); ++p) {
+    d1[p].square = 0;
+    d1[p].w = pl.hprob[p].w1;
+    d1[p].dpart = pl.hprob[p].dpx;
+    d2[p].square = 0;
+    d2[p].x = pl.hprob[p].w1;
+    d2[p].ldx = pl.hprob[p].k;
+  }
+  const size_t bytes = sizeof(Prob) * pl.hprob.size();
+  if (!pl.dprob1) RF_CHECK(hipMalloc((void**)&pl.dprob1, bytes));
+  if (!pl.dprob2) RF_CHECK(hipMalloc((void**)&pl.dprob2, bytes));
+  RF_CHECK(hipMemcpy(pl.dprob1, d1.data(), bytes, hipMemcpyHostToDevice));
+  RF_CHECK(hipMemcpy(pl.dprob2, d2.data(), bytes, hipMemcpyHostToDevice));
+  return REFINE_OK;
+}
+
 int install_gemm(Plan& pl, const std::vector<refine_matrix>& As, int cfg, int ks) {
   std::vector<int> nks;
   std::vector<GemmItem> gi = gemm_items(As, cfg, ks, &nks);
@@ -223,7 +250,7 @@ int install_gemm(Plan& pl, const std::vector<refine_matrix>& As, int cfg, int ks
     pl.hprob[p].ndp = iceil(As[p].n, gemm_rows_per_block(cfg)) * nks[p];
   }
   RF_CHECK(hipMemcpy(pl.dprob, pl.hprob.data(), sizeof(Prob) * pl.hprob.size(), hipMemcpyHostToDevice));
-  return REFINE_OK;
+  return upload_square_descs(pl);
 }
 
 // Tuning cache: (n, k, vector width) -> (launch configuration, K split).
@@ -329,6 +356,7 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
   const bool single = np == 1;
   pl.csr = As[0].kind == REFINE_CSR;
   pl.split = opt.precision == REFINE_SPLIT_INT8;
+  pl.square = opt.target == REFINE_TARGET_SMALLEST_ABS;
   pl.hprob.resize(np);
   std::vector<Shape> shapes(np);
   size_t bytes = 0;
@@ -356,6 +384,10 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
     b += align_up((size_t)KK_COUNT * k * k * sizeof(double));
     b += align_up((size_t)(16 + 16 * k) * sizeof(double));  // kpp
     b += align_up((size_t)VEC_COUNT * k * sizeof(double));
+    if (pl.square) {
+      b += align_up(nk);                                                          // w1
+      b += align_up((size_t)dpart_entries(n, s, pl.split) * 2 * k * sizeof(double));  // dpx
+    }
     bytes += b;
     if (As[p].kind == REFINE_DENSE) {
       // pairs of columns per lane: aligned rows, and no pair straddling n
@@ -420,6 +452,13 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
     P.kpp = (double*)base;
     base += align_up((size_t)(16 + 16 * k) * sizeof(double));
     P.vec = (double*)base;
+    base += align_up((size_t)VEC_COUNT * k * sizeof(double));
+    if (pl.square) {
+      P.square = 1;
+      P.w1 = (double*)base;
+      base += align_up((size_t)n * k * sizeof(double));
+      P.dpx = (double*)base;
+    }
     P.ctrl = pl.ctrl + p;
     P.mu = mus[p];
     P.delta = deltas[p];
@@ -442,6 +481,7 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
     sort_items(gri);
   }
   RF_CHECK(upload(&pl.dprob, pl.hprob));
+  if (upload_square_descs(pl) != REFINE_OK) return REFINE_EHIP;
   RF_CHECK(upload(&pl.row_items, ri));
   RF_CHECK(upload(&pl.gram_items, gri));
   RF_CHECK(upload(&pl.gred_items, rr));
@@ -461,26 +501,35 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
   return REFINE_OK;
 }
 
-// Line 1 of Algorithm 4 for every problem: W = A X (and the K-split sum).
-hipError_t enqueue_product(Plan& pl, hipStream_t st) {
+// One product W = A X over the descriptors `probs` (and the K-split sum).
+hipError_t enqueue_product_on(Plan& pl, const Prob* probs, hipStream_t st) {
   hipError_t e;
   const int np = (int)pl.hprob.size();
   if (pl.csr) {
-    if ((e = launch_spmm(pl.dprob, pl.spmm_items, pl.n_spmm, pl.hprob[0].k, st)) != hipSuccess) return e;
+    if ((e = launch_spmm(probs, pl.spmm_items, pl.n_spmm, pl.hprob[0].k, st)) != hipSuccess) return e;
   } else {
     if (pl.split) {
-      if ((e = split_product(pl.sp, pl.dprob, st)) != hipSuccess) return e;
+      if ((e = split_product(pl.sp, probs, st)) != hipSuccess) return e;
     } else {
-      if ((e = launch_gemm_f64(pl.dprob, pl.gemm_items, pl.n_gemm, pl.kmax, pl.vec2, pl.gemm_cfg,
-                               st)) != hipSuccess)
+      if ((e = launch_gemm_f64(probs, pl.gemm_items, pl.n_gemm, pl.kmax, pl.vec2, pl.gemm_cfg, st)) !=
+          hipSuccess)
         return e;
     }
     for (int p = 0; p < np; ++p)
       if (!pl.split && pl.hprob[p].ksplit > 1 &&
-          (e = launch_wsum(pl.dprob, p, pl.hprob[p].n, pl.hprob[p].k, st)) != hipSuccess)
+          (e = launch_wsum(probs, p, pl.hprob[p].n, pl.hprob[p].k, st)) != hipSuccess)
         return e;
   }
   return hipSuccess;
+}
+
+// Line 1 of Algorithm 4 for every problem: W = A X, or for the squared
+// variant (Sec. 5.2) W = A (A X) through W1 = A X, with no A^2 formed.
+hipError_t enqueue_product(Plan& pl, hipStream_t st) {
+  if (!pl.square) return enqueue_product_on(pl, pl.dprob, st);
+  hipError_t e = enqueue_product_on(pl, pl.dprob1, st);
+  if (e == hipSuccess) e = enqueue_product_on(pl, pl.dprob2, st);
+  return e;
 }
 
 hipError_t enqueue_step(Plan& pl, hipStream_t st) {
@@ -586,6 +635,10 @@ int validate_matrix(const refine_matrix* A, int32_t k, const refine_options& opt
       (A->n > SPLIT_NMAX || (opt.slices != 0 && (opt.slices < SPLIT_S_MIN || opt.slices > SPLIT_S_MAX))))
     return REFINE_EINVAL;
   if (!(opt.delta_c >= 0.0)) return REFINE_EINVAL;
+  if (opt.target < REFINE_TARGET_LARGEST_ABS || opt.target > REFINE_TARGET_SMALLEST_ABS)
+    return REFINE_EINVAL;
+  // the squared variant feeds W1 = A X into a second product: FP64 only
+  if (opt.target == REFINE_TARGET_SMALLEST_ABS && opt.precision != REFINE_FP64) return REFINE_EINVAL;
   return REFINE_OK;
 }
 
@@ -625,6 +678,16 @@ double shift_for(const refine_options& opt, double lo, double hi) {
     default:
       return 0.0;
   }
+}
+
+// Squared variant (Sec. 5.2): B = A^2 - alpha I with alpha = (||A||^2 +
+// lam^2) / 2, lam = opt.shift the caller's estimate of the (k+1)-th smallest
+// |lambda|; without an estimate alpha = ||A||^2, which also separates the
+// targets (more slowly).  Returns alpha; *norm_b receives ||A||^2, the bound
+// of ||B|| used for delta and the residual statistic.
+double square_alpha(const refine_options& opt, double norm, double* norm_b) {
+  *norm_b = norm * norm;
+  return opt.shift > 0.0 ? 0.5 * (norm * norm + opt.shift * opt.shift) : norm * norm;
 }
 
 int read_ctrl(Plan& pl, hipStream_t st, std::vector<Ctrl>& out) {
@@ -700,8 +763,11 @@ int refine_init(refine_ctx** out, const refine_matrix* A, int32_t k, const refin
     delete c;
     return rc;
   }
-  c->mu = shift_for(opt, c->g_lo, c->g_hi);
   c->norm_used = opt.norm_a > 0.0 ? opt.norm_a : c->norm_inf;
+  if (opt.target == REFINE_TARGET_SMALLEST_ABS)
+    c->mu = square_alpha(opt, c->norm_used, &c->norm_used);
+  else
+    c->mu = shift_for(opt, c->g_lo, c->g_hi);
   c->delta = opt.delta_c * c->norm_used * UNIT_ROUNDOFF;
   std::vector<refine_matrix> As{*A};
   std::vector<int> ks{k};
@@ -727,6 +793,8 @@ static int set_x(refine_ctx* c, double* X, int64_t ldx) {
   if (!X || ldx < c->k) return REFINE_EINVAL;
   if (X != c->cur_x || ldx != c->cur_ldx) {
     if (launch_set_x(c->plan.dprob, 0, X, ldx, c->stream) != hipSuccess) return REFINE_EHIP;
+    if (c->plan.square && launch_set_x(c->plan.dprob1, 0, X, ldx, c->stream) != hipSuccess)
+      return REFINE_EHIP;
     c->cur_x = X;
     c->cur_ldx = ldx;
   }
@@ -920,8 +988,11 @@ int refine_batch_init(refine_batch** out, int32_t count, const refine_matrix* As
       delete b;
       return rc;
     }
-    mus[p] = shift_for(opt, lo, hi);
     norms[p] = opt.norm_a > 0.0 ? opt.norm_a : ninf;
+    if (opt.target == REFINE_TARGET_SMALLEST_ABS)
+      mus[p] = square_alpha(opt, norms[p], &norms[p]);
+    else
+      mus[p] = shift_for(opt, lo, hi);
     deltas[p] = opt.delta_c * norms[p] * UNIT_ROUNDOFF;
   }
   int rc = build_plan(b->plan, b->As, b->ks, opt, mus, deltas, norms);
@@ -967,6 +1038,7 @@ static int bind_batch_x(refine_batch* b, double* const* Xs, const int64_t* ldxs)
     if (hipMemcpy(b->plan.dprob, b->plan.hprob.data(), sizeof(Prob) * np, hipMemcpyHostToDevice) !=
         hipSuccess)
       return REFINE_EHIP;
+    if (upload_square_descs(b->plan) != REFINE_OK) return REFINE_EHIP;
   }
   return REFINE_OK;
 }
