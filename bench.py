@@ -15,7 +15,12 @@ Other workloads (--workload):
   laplacian    CSR 3-D Laplacian on a 128^3 grid (separable random diagonal),
                k = 32 smallest through the Gershgorin shift;
   batch        512 dense problems, n ~ U[128, 2048], k ~ U[4, 32], two target
-               clusters of gap 1e-6 each; 5 steps per graph; FP64 and split.
+               clusters of gap 1e-6 each; 5 steps per graph; FP64 and split;
+  kron         CSR Kronecker product of three banded 53 x 53 factors (148,877
+               rows, 70.7 nonzeros per row, the size and density of the
+               paper's larger sparse cases), k = 5 largest |lambda|;
+  smallest_abs dense n = 8192, k = 64, targets the smallest |lambda| of both
+               signs through B = A^2 - alpha I (Sec. 5.2), two products per step.
 
 Prints one JSON line.
 """
@@ -37,10 +42,17 @@ HBM_PEAK_GBS = 8000.0
 
 
 def _cores() -> int:
+    """Threads the oracle's OpenMP products run on: OMP_NUM_THREADS when set,
+    bounded by the CPUs this process may use."""
     try:
-        return len(os.sched_getaffinity(0))
+        avail = len(os.sched_getaffinity(0))
     except Exception:
-        return os.cpu_count() or 1
+        avail = os.cpu_count() or 1
+    try:
+        omp = int(os.environ.get("OMP_NUM_THREADS", "0"))
+    except ValueError:
+        omp = 0
+    return min(avail, omp) if omp > 0 else avail
 
 
 def _aligned_err(g, o):
@@ -259,6 +271,96 @@ def bench_laplacian(args, rf, torch, np):
             "config": cfg, "roofline": roof, "cpu_baseline": cpu}
 
 
+def bench_kron(args, rf, torch, np):
+    import synth
+    m = args.n or 53
+    k = args.k or 5
+    K, lam, Xt, X0h = synth.kron_banded(m=m, k=k)
+    n, nnz = K.n, len(K.val)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a)).cuda()
+    C = rf.CsrMatrix(n, dev(K.row_ptr), dev(K.col_idx), dev(K.val))
+    ctx = rf.RefineContext(C, k, norm_a=K.sigma)
+    X0 = dev(X0h)
+    X = X0.clone()
+    sec, st1, st_last, X_first = _time_steps(ctx, X, args.steps, args.warmup, torch)
+    ms_prod = ctx.time_product(X0.clone(), args.product_reps)
+    rr_ms = _time_rayleigh_ritz(ctx, X0, torch)
+    ctx.close()
+    byts = 12.0 * nnz + 4.0 * (n + 1) + 16.0 * n * k
+    gbs = byts / (ms_prod * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "traffic": None}
+    Xg = X.cpu().numpy()
+    cfg = {"workload": "CSR FP64, Kronecker product of three banded %d x %d factors "
+                       "(half-bandwidths 2, 2, 1; n=%d, nnz=%d, %.1f per row), k=%d largest |lambda|"
+                       % (m, m, n, nnz, nnz / n, k),
+           "n": n, "k": k, "nnz": nnz, "precision": "fp64",
+           "product_us": ms_prod * 1e3,
+           "product_eff_gflops": 2.0 * nnz * k / (ms_prod * 1e-3) / 1e9,
+           "corr_fro_first": st1.corr_fro, "corr_fro_last": st_last.corr_fro,
+           "resid_rel_last": st_last.resid_rel,
+           "err_vs_exact_eigvecs_last": _aligned_err(Xg, Xt),
+           "err_vs_exact_eigvecs_start": _aligned_err(X0h, Xt),
+           "rayleigh_ritz_ms": rr_ms}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        Co = oracle.Csr(n, K.row_ptr, K.col_idx, K.val)
+        ts = time.perf_counter()
+        reps = 0
+        while reps == 0 or time.perf_counter() - ts < 10.0:
+            r = oracle.refine_step(Co, X0h, norm_a=K.sigma)
+            reps += 1
+        t_cpu = (time.perf_counter() - ts) / reps
+        cfg["err_vs_fp64_oracle_first_step"] = _aligned_err(X_first.cpu().numpy(), r.X)
+        cpu = {"value": k / t_cpu, "unit": "eigvecs/s", "cores": _cores(), "kind": "oracle",
+               "sample": "%d FP64 oracle steps of the same workload, %.3f s each" % (reps, t_cpu)}
+    return {"value": k / sec, "ms_per_step": sec * 1e3, "unit": "eigvecs/s", "dtype": "f64",
+            "config": cfg, "roofline": roof, "cpu_baseline": cpu}
+
+
+def bench_smallest_abs(args, rf, torch, np):
+    import synth
+    n = args.n or 8192
+    k = args.k or 64
+    P = synth.dense_smallest_abs(n, k, synth.SEED_BASE + 12, device="cuda", torch_out=True)
+    torch.cuda.synchronize()
+    lhat = 0.7  # the rest of the spectrum has |lambda| >= 0.7
+    ctx = rf.RefineContext(P.A, k, norm_a=1.0, target="smallest_abs", shift=lhat)
+    alpha = ctx.info()["mu"]
+    X0 = P.X0.cuda().contiguous()
+    X = X0.clone()
+    sec, st1, st_last, X_first = _time_steps(ctx, X, args.steps, args.warmup, torch)
+    ms_prod = ctx.time_product(X0.clone(), args.product_reps)
+    ctx.close()
+    flops = 2.0 * n * n * k
+    tf = flops / (ms_prod * 1e-3) / 1e12
+    roof = {"bound": "mfma", "achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": tf / FP64_PEAK_TFLOPS, "traffic": None}
+    Xt = P.X_true.cpu().numpy()
+    cfg = {"workload": "dense FP64 n=%d, k=%d smallest |lambda| (targets +-0.3(j+1)/k, rest "
+                       "|lambda| in [0.7, 1]) through B = A^2 - alpha I, alpha=%.4f, two products "
+                       "per step" % (n, k, alpha),
+           "n": n, "k": k, "precision": "fp64", "alpha": alpha,
+           "product_us_one_of_two": ms_prod * 1e3,
+           "corr_fro_first": st1.corr_fro, "corr_fro_last": st_last.corr_fro,
+           "err_vs_exact_eigvecs_last": _aligned_err(X.cpu().numpy(), Xt),
+           "err_vs_exact_eigvecs_start": _aligned_err(X0.cpu().numpy(), Xt)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        A_h = P.A.cpu().numpy()
+        X0h = X0.cpu().numpy()
+        ts = time.perf_counter()
+        r = oracle.refine_step(A_h, X0h, mu=alpha, norm_a=1.0, square=True)
+        t_cpu = time.perf_counter() - ts
+        cfg["err_vs_fp64_oracle_first_step"] = _aligned_err(X_first.cpu().numpy(), r.X)
+        cpu = {"value": k / t_cpu, "unit": "eigvecs/s", "cores": _cores(), "kind": "oracle",
+               "sample": "one full FP64 oracle step of the same workload, %.1f s" % t_cpu}
+    return {"value": k / sec, "ms_per_step": sec * 1e3, "unit": "eigvecs/s", "dtype": "f64",
+            "config": cfg, "roofline": roof, "cpu_baseline": cpu}
+
+
 def bench_batch(args, rf, torch, np):
     import synth
     count = args.count
@@ -339,7 +441,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="logspace",
-                    choices=["logspace", "uniform_top", "laplacian", "batch"])
+                    choices=["logspace", "uniform_top", "laplacian", "batch", "kron",
+                             "smallest_abs"])
     ap.add_argument("--n", type=int, default=0,
                     help="dense n (default 8192 / 16384) or the Laplacian grid side (128)")
     ap.add_argument("--k", type=int, default=0)
@@ -379,6 +482,10 @@ def main() -> int:
             return 0
     elif args.workload == "laplacian":
         r = bench_laplacian(args, rf, torch, np)
+    elif args.workload == "kron":
+        r = bench_kron(args, rf, torch, np)
+    elif args.workload == "smallest_abs":
+        r = bench_smallest_abs(args, rf, torch, np)
     else:
         r = bench_batch(args, rf, torch, np)
     print("bench done in %.1f s" % (time.time() - t0), file=sys.stderr, flush=True)

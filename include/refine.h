@@ -151,7 +151,11 @@ int refine_init(refine_ctx** ctx, const refine_matrix* A, int32_t k,
                 const refine_options* opt, void* hip_stream);
 
 /* One refinement step on X (device, n x k row-major, leading dimension ldx),
- * in place.  stats == NULL: the step is only enqueued (no host
+ * in place.  The divergence test (REFINE_EDIVERGED) compares ||E_L||_F with
+ * the steps since the context last saw a different X pointer or ldx, an
+ * error status or a refine_run: a caller that restarts from new values in
+ * the same buffer calls refine_run (or passes another buffer) to start a
+ * new history.  stats == NULL: the step is only enqueued (no host
  * synchronisation) and errors surface at the next call that reports them;
  * otherwise the stream is synchronised and *stats filled. */
 int refine_step(refine_ctx* ctx, double* X, int64_t ldx, refine_stats* stats);

@@ -9,6 +9,7 @@
 // whole GPU works on one contiguous window of rows and the far stencil
 // neighbours (N^2 rows away on a 3-D grid) are still in the caches.
 #include <algorithm>
+#include <cstdlib>
 
 #include "common.h"
 #include "dev_util.h"
@@ -152,15 +153,166 @@ __global__ __launch_bounds__(NT) void spmm_vec_kernel(const Prob* __restrict__ p
   }
 }
 
+// Row form for narrow X (k <= KC <= 8) and wide rows: L lanes share a row
+// and stride over its nonzeros, two at a time per lane, so a row's column
+// indices and values are read by coalesced loads and a row of tens of
+// nonzeros spreads over the lanes.  The next pair's index and value are
+// requested before the current pair's X gathers are used, so a round waits
+// on one memory trip, not two.  Each lane accumulates all k columns of its
+// nonzeros (lanes past the row's end use a = 0 and the row's own X row,
+// adding exact zeros); the row's sum is then a butterfly over its L lanes
+// (the terms are associated differently from CSR order, within the rounding
+// of any FP64 order).  Lane j < k of the row owns column j: it writes w_rj
+// and keeps column j's Rayleigh terms.  Chunks of ROW_CHUNK rows, taken
+// block-strided as in the vector form, over a grid sized to the occupancy.
+constexpr int ROW_CHUNK = 64;
+constexpr int ROW_GRID = 2048;
+
+template <int NT, int L, int KC>
+__global__ __launch_bounds__(NT) void spmm_row_kernel(const Prob* __restrict__ probs,
+                                                     const RowItem* __restrict__ items, int nitems,
+                                                     int chunk_rows) {
+  static_assert(64 % L == 0 && KC <= L, "row groups must tile a wavefront");
+  constexpr int NW = NT / 64, RPB = NT / L;
+  __shared__ double red[2][NW][KC];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int j = lane % L;
+  const Prob& P = probs[0];
+  if (P.ctrl->stopped) return;
+  const int n = P.n, k = P.k;
+  const int32_t* __restrict__ rp = P.rp;
+  const int32_t* __restrict__ ci = P.ci;
+  const double* __restrict__ av = P.av;
+  const double* __restrict__ X = P.x;
+  const int64_t ldx = P.ldx;
+  double* __restrict__ W = P.w;
+  double sxw = 0.0, sxx = 0.0;
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const RowItem item = items[it];
+    const int r0 = item.blk * chunk_rows, r1 = min(n, r0 + chunk_rows);
+    for (int rb = r0; rb < r1; rb += RPB) {
+      const int row = rb + tid / L;
+      const bool rok = row < r1;
+      const int rr = rok ? row : r0;
+      const int e0 = *gld(rp + rr), e1 = rok ? *gld(rp + rr + 1) : e0;
+      auto fetch = [&](int e, int& c0, double& a0, int& c1, double& a1) {
+        const bool ok0 = e < e1, ok1 = e + L < e1;
+        c0 = ok0 ? *gld(ci + e) : rr;
+        a0 = ok0 ? *gld(av + e) : 0.0;
+        c1 = ok1 ? *gld(ci + e + L) : rr;
+        a1 = ok1 ? *gld(av + e + L) : 0.0;
+      };
+      double acc[KC];
+#pragma unroll
+      for (int q = 0; q < KC; ++q) acc[q] = 0.0;
+      int ca, cb;
+      double aa, ab;
+      fetch(e0 + j, ca, aa, cb, ab);
+      for (int e = e0 + j; e < e1; e += 2 * L) {
+        double xa[KC], xb[KC];
+#pragma unroll
+        for (int q = 0; q < KC; ++q) {
+          xa[q] = q < k ? *gld(X + (int64_t)ca * ldx + q) : 0.0;
+          xb[q] = q < k ? *gld(X + (int64_t)cb * ldx + q) : 0.0;
+        }
+        int nca, ncb;
+        double naa, nab;
+        fetch(e + 2 * L, nca, naa, ncb, nab);
+#pragma unroll
+        for (int q = 0; q < KC; ++q) acc[q] = __builtin_fma(ab, xb[q], __builtin_fma(aa, xa[q], acc[q]));
+        ca = nca;
+        cb = ncb;
+        aa = naa;
+        ab = nab;
+      }
+#pragma unroll
+      for (int q = 0; q < KC; ++q)
+#pragma unroll
+        for (int o = L / 2; o >= 1; o /= 2) acc[q] += __shfl_xor(acc[q], o);
+      if (rok && j < k) {
+        double wv = 0.0;
+#pragma unroll
+        for (int q = 0; q < KC; ++q)
+          if (q == j) wv = acc[q];
+        *gst(W + (int64_t)row * k + j) = wv;
+        const double xv = *gld(X + (int64_t)row * ldx + j);
+        sxw = __builtin_fma(xv, wv, sxw);
+        sxx = __builtin_fma(xv, xv, sxx);
+      }
+    }
+  }
+  // column j's partial over the wavefront's row groups, then over waves
+#pragma unroll
+  for (int o = L; o < 64; o *= 2) {
+    sxw += __shfl_xor(sxw, o);
+    sxx += __shfl_xor(sxx, o);
+  }
+  if (lane < KC) {
+    red[0][wave][lane] = sxw;
+    red[1][wave][lane] = sxx;
+  }
+  __syncthreads();
+  if (tid < k) {
+    double a = 0.0, b = 0.0;
+    for (int w = 0; w < NW; ++w) {
+      a += red[0][w][tid];
+      b += red[1][w][tid];
+    }
+    *gst(P.dpart + (int64_t)blockIdx.x * 2 * k + tid) = a;
+    *gst(P.dpart + (int64_t)blockIdx.x * 2 * k + k + tid) = b;
+  }
+}
+
 // Grid: three resident 256-thread blocks on each of the 256 CUs.
 constexpr int SPMM_GRID = 768;
 
-int spmm_chunk_rows() { return SPMM_ROWS; }
-int spmm_grid(int nitems) { return nitems < SPMM_GRID ? nitems : SPMM_GRID; }
+int spmm_chunk_rows(int lanes) { return lanes ? ROW_CHUNK : SPMM_ROWS; }
+int spmm_grid(int nitems, int lanes) {
+  const int g = lanes ? ROW_GRID : SPMM_GRID;
+  return nitems < g ? nitems : g;
+}
 
 // k picks the lanes per row: G = pow2ceil(k) / 4, at least 1.
-hipError_t launch_spmm(const Prob* probs, const RowItem* items, int nitems, int k, hipStream_t st) {
-  const int grid = spmm_grid(nitems);
+// Lanes per row of the row form for k <= 8 (0: the vector form): rows of 16
+// or more nonzeros on average take the row form, with 8 lanes (two nonzeros
+// per lane and round) up to 160 and 16 beyond.  REFINE_SPMM_L overrides it
+// (0, 8, 16 or 32; a tuning hook).
+int spmm_row_lanes(int k, int64_t n, int64_t nnz) {
+  if (const char* env = getenv("REFINE_SPMM_L")) {
+    const int l = atoi(env);
+    if (l == 0) return 0;
+    if ((l == 8 || l == 16 || l == 32) && k <= 8) return l;
+  }
+  if (k > 8 || n <= 0) return 0;
+  const double mean = (double)nnz / (double)n;
+  return mean < 16.0 ? 0 : mean < 160.0 ? 8 : 16;
+}
+
+template <int L>
+hipError_t launch_spmm_row(const Prob* probs, const RowItem* items, int nitems, int k, int grid,
+                           hipStream_t st) {
+  switch (k) {
+#define RFK_SPMM_ROW(KV)                                                                         \
+  case KV:                                                                                       \
+    hipLaunchKernelGGL((spmm_row_kernel<256, L, KV>), dim3(grid), dim3(256), 0, st, probs, items, \
+                       nitems, ROW_CHUNK);                                                       \
+    break;
+    RFK_SPMM_ROW(1) RFK_SPMM_ROW(2) RFK_SPMM_ROW(3) RFK_SPMM_ROW(4)
+    RFK_SPMM_ROW(5) RFK_SPMM_ROW(6) RFK_SPMM_ROW(7) RFK_SPMM_ROW(8)
+#undef RFK_SPMM_ROW
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_spmm(const Prob* probs, const RowItem* items, int nitems, int k, int lanes,
+                       hipStream_t st) {
+  const int grid = spmm_grid(nitems, lanes);
+  if (lanes == 8) return launch_spmm_row<8>(probs, items, nitems, k, grid, st);
+  if (lanes == 16) return launch_spmm_row<16>(probs, items, nitems, k, grid, st);
+  if (lanes == 32) return launch_spmm_row<32>(probs, items, nitems, k, grid, st);
+  if (lanes) return hipErrorInvalidValue;
   int kp = 1;
   while (kp < k) kp *= 2;
   const int g = std::max(1, kp / 4);

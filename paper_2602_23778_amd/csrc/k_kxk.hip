@@ -1067,8 +1067,11 @@ int kxk_lds_doubles(int kmax) { return 0; }
 // One problem: the panel pipeline with the one-workgroup solver as its
 // fallback (which runs only when the warm start is not close enough).
 // Batches: the one-workgroup solver per problem.
-hipError_t launch_kxk(const Prob* probs, int nprob, int kmax, hipStream_t st) {
-  if (nprob == 1) {
+// pipeline: one problem through the four-launch panel pipeline (the
+// one-workgroup kernel only as its fallback); otherwise the whole stage runs
+// in one workgroup per problem.
+hipError_t launch_kxk(const Prob* probs, int nprob, int kmax, bool pipeline, hipStream_t st) {
+  if (nprob == 1 && pipeline) {
     const int np = (kmax + 15) / 16;
     const dim3 grid(np), block(64 * np);
     hipLaunchKernelGGL(pp_res_kernel, grid, block, 0, st, probs);

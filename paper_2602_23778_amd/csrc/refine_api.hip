@@ -31,7 +31,7 @@ struct GramRedItem {
 };
 hipError_t launch_gram_reduce(const Prob*, const GramRedItem*, int, hipStream_t);
 int kxk_lds_doubles(int);
-hipError_t launch_kxk(const Prob*, int, int, hipStream_t);
+hipError_t launch_kxk(const Prob*, int, int, bool, hipStream_t);
 hipError_t launch_update(const Prob*, const RowItem*, int, int, hipStream_t);
 hipError_t launch_normalize(const Prob*, const RowItem*, int, hipStream_t);
 hipError_t launch_wsum(const Prob*, int, int64_t, int, hipStream_t);
@@ -39,14 +39,15 @@ hipError_t launch_fin_d(const Prob*, int, hipStream_t);
 hipError_t launch_fin_stats(const Prob*, int, hipStream_t);
 hipError_t launch_ctrl_reset(const Prob*, int, int, double, hipStream_t);
 hipError_t launch_set_x(Prob*, int, double*, int64_t, hipStream_t);
-hipError_t launch_spmm(const Prob*, const RowItem*, int, int, hipStream_t);
+hipError_t launch_spmm(const Prob*, const RowItem*, int, int, int, hipStream_t);
+int spmm_row_lanes(int k, int64_t n, int64_t nnz);
 hipError_t launch_rr_prep(const Prob*, int, hipStream_t);
 hipError_t launch_rr_solve(const Prob*, int, hipStream_t);
 hipError_t launch_rr_apply(const Prob*, const RowItem*, int, hipStream_t);
 hipError_t launch_flip_sigma(const Prob*, int, hipStream_t);
 hipError_t launch_flip_apply(const Prob*, const RowItem*, int, hipStream_t);
-int spmm_chunk_rows();
-int spmm_grid(int nitems);
+int spmm_chunk_rows(int lanes);
+int spmm_grid(int nitems, int lanes);
 hipError_t launch_rowstats(int, int, const double*, int64_t, const int32_t*, const int32_t*,
                            const double*, double*, int, hipStream_t);
 hipError_t kxk_set_attributes();
@@ -71,8 +72,10 @@ struct Plan {
   int n_row = 0;
   RowItem* gram_items = nullptr;
   int n_gram = 0;
-  RowItem* spmm_items = nullptr;  // CSR product: chunks of spmm_chunk_rows() rows
+  RowItem* spmm_items = nullptr;  // CSR product: chunks of spmm_chunk_rows(lanes) rows
   int n_spmm = 0;
+  int spmm_lanes = 0;             // lanes per row of the row form (0: vector form)
+  bool kxk_pipeline = false;      // one problem: k x k stage by the panel pipeline
   GramRedItem* gred_items = nullptr;
   int n_gred = 0;
   int kmax = 0;
@@ -144,6 +147,18 @@ constexpr int BATCH_GRAPH_STEPS = 5;
 int64_t dpart_entries(int64_t n, const Shape& s, bool split) {
   const int ks = split ? SPLIT_KS_MAX : std::max(1, s.ksplit);
   return std::max<int64_t>((int64_t)iceil(n, 64) * ks, s.nrb);
+}
+
+// Largest k whose single-problem k x k stage runs in one workgroup rather
+// than the panel pipeline (a tuning constant; REFINE_KXK_PIPE=0/1 forces
+// either form).
+constexpr int KXK_ONE_WG_MAX = 48;
+
+// Rayleigh partial slots of one problem: the dense and split products' row
+// blocks and K splits, or the CSR product's grid.
+int64_t dpart_count(int64_t n, const Shape& s, const Plan& pl) {
+  const int64_t d = dpart_entries(n, s, pl.split);
+  return pl.csr ? std::max<int64_t>(d, spmm_grid(iceil(n, spmm_chunk_rows(pl.spmm_lanes)), pl.spmm_lanes)) : d;
 }
 
 template <class T>
@@ -357,6 +372,9 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
   pl.csr = As[0].kind == REFINE_CSR;
   pl.split = opt.precision == REFINE_SPLIT_INT8;
   pl.square = opt.target == REFINE_TARGET_SMALLEST_ABS;
+  pl.spmm_lanes = pl.csr ? spmm_row_lanes(ks[0], As[0].n, As[0].nnz) : 0;
+  pl.kxk_pipeline = single && ks[0] > KXK_ONE_WG_MAX;
+  if (const char* env = getenv("REFINE_KXK_PIPE")) pl.kxk_pipeline = single && atoi(env) != 0;
   pl.hprob.resize(np);
   std::vector<Shape> shapes(np);
   size_t bytes = 0;
@@ -379,14 +397,14 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
     if (pl.split) b += align_up(nk);                     // wlo
     b += align_up(nk);                                   // xn
     b += align_up((size_t)s.nrb * 5 * k * sizeof(double));
-    b += align_up((size_t)dpart_entries(n, s, pl.split) * 2 * k * sizeof(double));
+    b += align_up((size_t)dpart_count(n, s, pl) * 2 * k * sizeof(double));
     b += align_up((size_t)s.ngb * (2 * k * k + k) * sizeof(double));
     b += align_up((size_t)KK_COUNT * k * k * sizeof(double));
     b += align_up((size_t)(16 + 16 * k) * sizeof(double));  // kpp
     b += align_up((size_t)VEC_COUNT * k * sizeof(double));
     if (pl.square) {
       b += align_up(nk);                                                          // w1
-      b += align_up((size_t)dpart_entries(n, s, pl.split) * 2 * k * sizeof(double));  // dpx
+      b += align_up((size_t)dpart_count(n, s, pl) * 2 * k * sizeof(double));  // dpx
     }
     bytes += b;
     if (As[p].kind == REFINE_DENSE) {
@@ -443,8 +461,8 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
     base += align_up((size_t)s.nrb * 5 * k * sizeof(double));
     P.dpart = (double*)base;
     // CSR: one partial per product block; dense: set with the product's items
-    P.ndp = pl.csr ? spmm_grid(iceil(n, spmm_chunk_rows())) : s.nrb;
-    base += align_up((size_t)dpart_entries(n, s, pl.split) * 2 * k * sizeof(double));
+    P.ndp = pl.csr ? spmm_grid(iceil(n, spmm_chunk_rows(pl.spmm_lanes)), pl.spmm_lanes) : s.nrb;
+    base += align_up((size_t)dpart_count(n, s, pl) * 2 * k * sizeof(double));
     P.gpart = (double*)base;
     base += align_up((size_t)s.ngb * (2 * k * k + k) * sizeof(double));
     P.kk = (double*)base;
@@ -487,7 +505,7 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
   RF_CHECK(upload(&pl.gred_items, rr));
   if (pl.csr) {
     std::vector<RowItem> si;
-    for (int b = 0; b < iceil(As[0].n, spmm_chunk_rows()); ++b) si.push_back(RowItem{0, b});
+    for (int b = 0; b < iceil(As[0].n, spmm_chunk_rows(pl.spmm_lanes)); ++b) si.push_back(RowItem{0, b});
     RF_CHECK(upload(&pl.spmm_items, si));
     pl.n_spmm = (int)si.size();
   }
@@ -506,7 +524,9 @@ hipError_t enqueue_product_on(Plan& pl, const Prob* probs, hipStream_t st) {
   hipError_t e;
   const int np = (int)pl.hprob.size();
   if (pl.csr) {
-    if ((e = launch_spmm(probs, pl.spmm_items, pl.n_spmm, pl.hprob[0].k, st)) != hipSuccess) return e;
+    if ((e = launch_spmm(probs, pl.spmm_items, pl.n_spmm, pl.hprob[0].k, pl.spmm_lanes, st)) !=
+        hipSuccess)
+      return e;
   } else {
     if (pl.split) {
       if ((e = split_product(pl.sp, probs, st)) != hipSuccess) return e;
@@ -539,7 +559,7 @@ hipError_t enqueue_step(Plan& pl, hipStream_t st) {
   if ((e = launch_fin_d(pl.dprob, np, st)) != hipSuccess) return e;
   if ((e = launch_gram(pl.dprob, pl.gram_items, pl.n_gram, pl.kmax, st)) != hipSuccess) return e;
   if ((e = launch_gram_reduce(pl.dprob, pl.gred_items, pl.n_gred, st)) != hipSuccess) return e;
-  if ((e = launch_kxk(pl.dprob, np, pl.kmax, st)) != hipSuccess) return e;
+  if ((e = launch_kxk(pl.dprob, np, pl.kmax, pl.kxk_pipeline, st)) != hipSuccess) return e;
   if ((e = launch_update(pl.dprob, pl.row_items, pl.n_row, pl.kmax, st)) != hipSuccess) return e;
   if ((e = launch_fin_stats(pl.dprob, np, st)) != hipSuccess) return e;
   if ((e = launch_normalize(pl.dprob, pl.row_items, pl.n_row, st)) != hipSuccess) return e;
@@ -795,6 +815,8 @@ static int set_x(refine_ctx* c, double* X, int64_t ldx) {
     if (launch_set_x(c->plan.dprob, 0, X, ldx, c->stream) != hipSuccess) return REFINE_EHIP;
     if (c->plan.square && launch_set_x(c->plan.dprob1, 0, X, ldx, c->stream) != hipSuccess)
       return REFINE_EHIP;
+    // a new iterate starts a new history for the divergence test
+    if (launch_ctrl_reset(c->plan.dprob, 1, 0, 0.0, c->stream) != hipSuccess) return REFINE_EHIP;
     c->cur_x = X;
     c->cur_ldx = ldx;
   }
@@ -922,7 +944,7 @@ int refine_time_product(refine_ctx* c, double* X, int64_t ldx, int32_t reps, flo
   hipError_t e = hipEventRecord(e0, c->stream);
   for (int i = 0; i < reps && e == hipSuccess; ++i) {
     if (pl.csr)
-      e = launch_spmm(pl.dprob, pl.spmm_items, pl.n_spmm, pl.hprob[0].k, c->stream);
+      e = launch_spmm(pl.dprob, pl.spmm_items, pl.n_spmm, pl.hprob[0].k, pl.spmm_lanes, c->stream);
     else if (pl.split)
       e = split_product(pl.sp, pl.dprob, c->stream);
     else
@@ -1039,6 +1061,8 @@ static int bind_batch_x(refine_batch* b, double* const* Xs, const int64_t* ldxs)
         hipSuccess)
       return REFINE_EHIP;
     if (upload_square_descs(b->plan) != REFINE_OK) return REFINE_EHIP;
+    // new iterates start a new history for the divergence test
+    if (launch_ctrl_reset(b->plan.dprob, np, 0, 0.0, b->stream) != hipSuccess) return REFINE_EHIP;
   }
   return REFINE_OK;
 }

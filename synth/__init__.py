@@ -362,3 +362,56 @@ def laplacian3d_separable(N: int, k: int, seed: int = SEED_BASE + 4, noise: floa
     X0 = q * np.sign(np.diag(rr))
     P.meta["lam_next"] = float(top[k][0])
     return P, lam, Xt, X0
+
+
+def _banded_symmetric(m: int, b: int, rng) -> np.ndarray:
+    """m x m symmetric with iid N(0, 1) entries on the 2b + 1 central diagonals."""
+    T = np.zeros((m, m))
+    for o in range(b + 1):
+        v = rng.standard_normal(m - o)
+        T += np.diag(v, o)
+        if o:
+            T += np.diag(v, -o)
+    return T
+
+
+def kron_banded(m=53, bands=(2, 2, 1), k=5, seed=SEED_BASE + 265, noise=1e-6, start_seed=11):
+    """Sparse symmetric A = T1 (x) T2 (x) T3 of three banded m x m factors with
+    iid N(0, 1) entries (half-bandwidths `bands`): a 3-D stencil of
+    prod(2 b + 1) points (75 for (2, 2, 1); about 70.7 nonzeros per row with
+    the boundary rows), indefinite, with eigenpairs known exactly from the
+    factors: lambda = t1[a] t2[b] t3[c], v = u1[:, a] (x) u2[:, b] (x) u3[:, c].
+    At m = 53 it has the size and density of the paper's larger SuiteSparse
+    cases (148,877 rows, 10.5M nonzeros).  The targets are the k largest
+    |lambda| (the paper's sparse runs: k = 5, largest magnitude); the default
+    seed gives relative gaps >= 2.4e-2 among them and 4e-2 to the next.
+    Returns (CsrProblem, lam_k, X_true, X0) with X0 = X_true + N(0, noise^2)
+    orthonormalised; CsrProblem.sigma is max |lambda| (= ||A||_2)."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    facs = [_banded_symmetric(m, b, rng) for b in bands]
+    eig = [np.linalg.eigh(T) for T in facs]
+    A = sp.kron(sp.kron(sp.csr_matrix(facs[0]), sp.csr_matrix(facs[1]), format="csr"),
+                sp.csr_matrix(facs[2]), format="csr")
+    A.eliminate_zeros()
+    A.sort_indices()
+    n = A.shape[0]
+    t = [e[0] for e in eig]
+    lam_all = (t[0][:, None, None] * t[1][None, :, None] * t[2][None, None, :]).reshape(-1)
+    order = np.argsort(-np.abs(lam_all), kind="stable")[:k + 1]
+    Xt = np.empty((n, k))
+    for j, flat in enumerate(order[:k]):
+        a, b, c = np.unravel_index(flat, (m, m, m))
+        u1, u2, u3 = eig[0][1][:, a], eig[1][1][:, b], eig[2][1][:, c]
+        Xt[:, j] = (u1[:, None, None] * u2[None, :, None] * u3[None, None, :]).reshape(-1)
+    lam = lam_all[order[:k]]
+    P = CsrProblem(n, A.indptr.astype(np.int32), A.indices.astype(np.int32),
+                   A.data.astype(np.float64), float(np.abs(lam_all).max()),
+                   {"workload": "kron_banded", "m": m, "bands": list(bands), "seed": seed})
+    P.meta["lam_next"] = float(lam_all[order[k]])
+    r = np.random.default_rng(start_seed)
+    X = Xt + noise * r.standard_normal(Xt.shape)
+    q, rr = np.linalg.qr(X)
+    X0 = q * np.sign(np.diag(rr))
+    return P, lam, Xt, X0
+

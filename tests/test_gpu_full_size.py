@@ -9,6 +9,8 @@ the C ABI and compares with the CPU oracle:
   oracle step (the split product is at least as accurate as FP64, and the
   two forms agree to a few ulps on these well-separated spectra);
 * CSR 3-D Laplacian on a 128^3 grid, k = 32: one step, every entry;
+* CSR Kronecker-banded 53^3 (148,877 rows, 70.7 nonzeros per row), k = 5:
+  one step, every entry;
 * 512 clustered problems: every problem ends with a normal status and
   orthonormal columns; problems 0..7 after five steps against the
   double-double oracle (split form, 10 slices).  The FP64 form is held to
@@ -94,6 +96,27 @@ def test_full_csr_laplacian_128cubed_k32():
     t0 = time.perf_counter()
     r = oracle.refine_step(oracle.Csr(n, L.row_ptr, L.col_idx, L.val), X0h, mu=L.sigma,
                            norm_a=L.sigma)
+    _say("oracle step %.1f s" % (time.perf_counter() - t0))
+    err = _err(X.cpu().numpy(), r.X)
+    _say("max |dX| = %.3e" % err)
+    assert err <= TOL
+    assert st.corr_fro == pytest.approx(r.corr_fro, rel=1e-6)
+
+
+def test_full_csr_kron_banded_m53_k5():
+    _say("case: CSR Kronecker-banded 53^3 (75-point), k=5, one step")
+    rf = _lib()
+    K, lam, Xt, X0h = synth.kron_banded()
+    n = K.n
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a)).cuda()
+    C = rf.CsrMatrix(n, dev(K.row_ptr), dev(K.col_idx), dev(K.val))
+    ctx = rf.RefineContext(C, 5, norm_a=K.sigma)
+    X = dev(X0h)
+    st = ctx.step(X)
+    ctx.close()
+    assert st.status == rf.OK, rf.status_string(st.status)
+    t0 = time.perf_counter()
+    r = oracle.refine_step(oracle.Csr(n, K.row_ptr, K.col_idx, K.val), X0h, norm_a=K.sigma)
     _say("oracle step %.1f s" % (time.perf_counter() - t0))
     err = _err(X.cpu().numpy(), r.X)
     _say("max |dX| = %.3e" % err)

@@ -117,12 +117,16 @@ def test_csr_every_row_width(k):
     _compare_steps(None, X0, 2, norm_a=L.sigma, mu=L.sigma, target="smallest", csr=L)
 
 
-def test_csr_irregular_rows():
+@pytest.mark.parametrize("k,lanes", [(12, None), (5, "8"), (5, "32"), (8, "16")])
+def test_csr_irregular_rows(k, lanes, monkeypatch):
     """Rows of 0 to ~2000 nonzeros: empty rows, rows longer than one gather
     round, and a chunk whose nonzeros exceed the block's LDS copy (read from
-    memory instead).  The 12 largest |lambda| of a random sparse symmetric
-    matrix, X0 = fl32 of its eigenvectors."""
-    n, k = 1500, 12
+    memory instead).  The k largest |lambda| of a random sparse symmetric
+    matrix, X0 = fl32 of its eigenvectors.  k <= 8 runs the row form (lanes
+    over a row's nonzeros) with the lane count forced."""
+    if lanes is not None:
+        monkeypatch.setenv("REFINE_SPMM_L", lanes)
+    n = 1500
     rng = np.random.default_rng(4242)
     M = np.zeros((n, n))
     for i in range(n):
@@ -151,6 +155,47 @@ def test_csr_irregular_rows():
     C.n, C.row_ptr, C.col_idx, C.val = n, rp, ci, val
     norm = float(np.max(np.abs(M).sum(1)))
     _compare_steps(None, X0, 2, norm_a=norm, csr=C)
+
+
+@pytest.mark.parametrize("m,bands,k,lanes", [
+    (14, (2, 2, 1), 5, None), (14, (2, 2, 1), 5, "8"), (14, (2, 2, 1), 5, "32"),
+    (13, (1, 1, 1), 3, None), (12, (3, 3, 3), 5, None), (12, (3, 3, 3), 8, "32"),
+    (15, (2, 2, 1), 1, None), (14, (2, 2, 1), 6, "16")])
+def test_csr_kron_banded(m, bands, k, lanes, monkeypatch):
+    """The Kronecker-banded sparse workload (27 to 343-point stencils, the
+    paper's 25-364 nonzeros per row), k largest |lambda| of an indefinite
+    spectrum, through the row form of the CSR product (k <= 8) with its lane
+    count chosen from the mean row length or forced."""
+    if lanes is not None:
+        monkeypatch.setenv("REFINE_SPMM_L", lanes)
+    K, lam, Xt, X0 = synth.kron_banded(m=m, bands=bands, k=k)
+    _compare_steps(None, X0, 3, norm_a=K.sigma, csr=K)
+
+
+def test_new_iterate_starts_a_new_divergence_history():
+    """Steps on one X, then a restart from the start block in another buffer:
+    the first step of the restart has a larger correction than the last steps
+    before it, which is no divergence (the history begins anew)."""
+    rf = _lib()
+    P = synth.dense_logspace(1024, 16)
+    ctx = rf.RefineContext(_dev(P.A), 16, norm_a=P.norm_a)
+    X = _dev(P.X0).clone()
+    for _ in range(6):
+        assert ctx.step(X).status == rf.OK
+    X2 = _dev(P.X0).clone()
+    for _ in range(3):
+        st = ctx.step(X2)
+        assert st.status == rf.OK, rf.status_string(st.status)
+    ctx.close()
+
+
+@pytest.mark.parametrize("k,pipe", [(5, "1"), (64, "0")])
+def test_kxk_forms_single_problem(k, pipe, monkeypatch):
+    """Both forms of the k x k stage for one problem: the panel pipeline
+    forced at small k and the one-workgroup kernel forced at k = 64."""
+    monkeypatch.setenv("REFINE_KXK_PIPE", pipe)
+    P = synth.dense_logspace(1024, k)
+    _compare_steps(P.A, P.X0, 3, norm_a=P.norm_a)
 
 
 def test_refine_run_converges_and_counts():
@@ -358,10 +403,12 @@ def _ctrl_fallback_flag(ctx):
 
 
 @pytest.mark.parametrize("n,k", [(1500, 128), (1100, 100), (900, 48)])
-def test_kxk_panel_pipeline_steps(n, k):
-    """Several FP64 steps at k up to 128: the first step has no warm start
-    and takes the one-workgroup solver, the later ones the panel pipeline;
-    every step matches the oracle."""
+def test_kxk_panel_pipeline_steps(n, k, monkeypatch):
+    """Several FP64 steps at k up to 128 through the panel pipeline (forced
+    for k <= 48, where one workgroup is the default): the first step has no
+    warm start and takes the one-workgroup solver, the later ones the
+    pipeline; every step matches the oracle."""
+    monkeypatch.setenv("REFINE_KXK_PIPE", "1")
     P = synth.dense_spectrum(n, k, 6000 + n)
     rf = _lib()
     ctx = rf.RefineContext(_dev(P.A), k, norm_a=1.0)
