@@ -114,22 +114,34 @@ Shape choose_shape(int64_t n, int k, bool single, bool csr) {
   s.ksplit = 1;
   s.kchunk = (int)n;
   // Row blocks of the streaming passes (split-K sum, update, normalisation):
-  // 64 rows for one dense problem; about 2048 blocks for a long one (every
-  // CU then has several blocks to overlap their latencies); a few blocks per
-  // problem in a batch (thousands of tiny blocks would each pay the fixed
-  // latency of staging [M | N] and of the partial writes).
+  // at least 64 rows for one problem and about 1024 blocks for a long one
+  // (four per CU to overlap their latencies; twice as many, smaller blocks
+  // each pay the fixed latency of staging [M | N] and of the partial writes,
+  // which measured slower at n = 150k and 2M); 256 rows per block in a batch.
   if (single) {
-    s.rbrows = (int)std::max<int64_t>(64, (n + 2047) / 2048 + 63) / 64 * 64;
+    s.rbrows = (int)std::max<int64_t>(64, (n + 1023) / 1024 + 63) / 64 * 64;
   } else {
     s.rbrows = 256;
   }
   // Gram blocks: at least k rows (the leading k rows must sit in block 0);
-  // about 1024 blocks for one long problem (the k-by-k partials stay a few
-  // percent of the pass's traffic), 256 rows in a batch.
+  // about 512 blocks for one long problem (fewer k-by-k partials to reduce),
+  // 256 rows in a batch.
   {
     const int64_t kr = (k + 3) / 4 * 4;
-    const int64_t per = single ? std::max<int64_t>(64, ((n + 1023) / 1024 + 3) / 4 * 4) : 256;
+    const int64_t per = single ? std::max<int64_t>(64, ((n + 511) / 512 + 3) / 4 * 4) : 256;
     s.gbrows = (int)std::max<int64_t>(std::max<int64_t>(kr, per), 16);
+  }
+  // tuning hooks for one problem: REFINE_RBROWS, REFINE_GBROWS (rows per
+  // streaming / Gram block; a Gram block keeps at least k rows)
+  if (single) {
+    if (const char* env = getenv("REFINE_RBROWS")) {
+      const int v = atoi(env);
+      if (v >= 16 && v % 16 == 0) s.rbrows = v;
+    }
+    if (const char* env = getenv("REFINE_GBROWS")) {
+      const int v = atoi(env);
+      if (v >= 16 && v % 4 == 0) s.gbrows = std::max(v, (k + 3) / 4 * 4);
+    }
   }
   s.nrb = iceil(n, s.rbrows);
   s.ngb = iceil(n, s.gbrows);
