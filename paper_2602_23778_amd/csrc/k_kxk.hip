@@ -721,12 +721,47 @@ __global__ __launch_bounds__(KS_NT) void kxk_small_kernel(const Prob* __restrict
 // ---------------------------------------------------------------------------
 constexpr int PP_LDA = KMAX + 4;  // LDS panel row stride (doubles)
 
-// Loads the 16 x k panel a(r, l) (rows r < 16 of the panel, zero-padded to
-// a multiple of 4 columns and beyond k rows) into LDS.  Ends with a barrier.
+// The right operand b (k x k, read from global memory) of a panel product,
+// fetched into registers for the 16x16 result tile tj: lane l holds
+// b(4q + l/16, tj*16 + l%16) for q < KQ (KQ >= ceil(k/4)), zero past k, so
+// that a kernel can issue every fetch it needs in one round before any of
+// them is consumed.
+template <int KQ, class FB>
+__device__ __forceinline__ void pp_fetch(int k, FB b, int tj, double (&bv)[KQ]) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, r16 = lane & 15;
+  const int j = tj * 16 + r16;
+  const bool jok = j < k;
+  const int kq = (k + 3) / 4;
+#pragma unroll
+  for (int q = 0; q < KQ; ++q) {
+    const int l = 4 * q + g;
+    bv[q] = (q < kq && l < k && jok) ? b(l, j) : 0.0;
+  }
+}
+
+// (16 x k panel in LDS, row stride PP_LDA) x (fetched right operand): the
+// 16x16 result tile tj; register r of lane l holds row pi*16 + l/16 + 4r and
+// column tj*16 + l%16.
+template <int KQ>
+__device__ __forceinline__ v4d pp_mul(int k, const double* As, const double (&bv)[KQ]) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, r16 = lane & 15;
+  const int kq = (k + 3) / 4;
+  v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < KQ; q += 2) {
+    if (q < kq) acc0 = mfma_f64(As[r16 * PP_LDA + 4 * q + g], bv[q], acc0);
+    if (q + 1 < kq) acc1 = mfma_f64(As[r16 * PP_LDA + 4 * q + 4 + g], bv[q + 1], acc1);
+  }
+  return acc0 + acc1;
+}
+
+// Loads the 16 x k panel a(i, l) (rows i = pi*16 + r, zero-padded to a
+// multiple of 4 columns and beyond k rows) into LDS, four loads per thread at
+// most (16 * kp <= 4 * blockDim for kp <= 16 np, blockDim = 64 np), all
+// issued before the first LDS store.  No closing barrier: several panels can
+// be requested together, and the caller synchronises.
 template <class FA>
-__device__ __forceinline__ void pp_load(int k, int pi, double* As, FA a) {
-  // 16 * kp <= 4 * blockDim (kp <= 16 np, blockDim = 64 np): four loads per
-  // thread at most, all issued before the first LDS store
+__device__ __forceinline__ void pp_load_nb(int k, int pi, double* As, FA a) {
   const int kp = (k + 3) / 4 * 4;
   double v[4];
 #pragma unroll
@@ -741,30 +776,6 @@ __device__ __forceinline__ void pp_load(int k, int pi, double* As, FA a) {
     const int e = threadIdx.x + u * blockDim.x;
     if (e < 16 * kp) As[(e / kp) * PP_LDA + e % kp] = v[u];
   }
-  __syncthreads();
-}
-
-// 16x16 tile tj of (panel in LDS) x b: register r of the result holds row
-// pi*16 + g + 4r and column tj*16 + (lane % 16).
-template <class FB>
-__device__ __forceinline__ v4d pp_tile(int k, const double* As, FB b, int tj) {
-  const int lane = threadIdx.x & 63, g = lane >> 4, r16 = lane & 15;
-  const int j = tj * 16 + r16;
-  const bool jok = j < k;
-  const int kq = (k + 3) / 4;
-  double bv[KMAX / 4];
-#pragma unroll
-  for (int q = 0; q < KMAX / 4; ++q) {
-    const int l = 4 * q + g;
-    bv[q] = (q < kq && l < k && jok) ? b(l, j) : 0.0;
-  }
-  v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int q = 0; q < KMAX / 4; q += 2) {
-    if (q < kq) acc0 = mfma_f64(As[r16 * PP_LDA + 4 * q + g], bv[q], acc0);
-    if (q + 1 < kq) acc1 = mfma_f64(As[r16 * PP_LDA + 4 * q + 4 + g], bv[q + 1], acc1);
-  }
-  return acc0 + acc1;
 }
 
 // Calls f(i, j, v) for the valid entries of a tile result.
@@ -794,6 +805,10 @@ __device__ __forceinline__ double pp_y1(const Prob& P, int i, int l) {
   return *gld(P.x + (int64_t)i * P.ldx + l) - (i == l ? 1.0 : 0.0);
 }
 
+// Every kernel of the pipeline requests all it needs (panels, right
+// operands, partial sums) in one round at its start, so that it waits on
+// memory once rather than once per product.
+template <int KQ>
 __global__ __launch_bounds__(512) void pp_res_kernel(const Prob* __restrict__ probs) {
   __shared__ double As[16 * PP_LDA];
   __shared__ double red[8];
@@ -814,9 +829,11 @@ __global__ __launch_bounds__(512) void pp_res_kernel(const Prob* __restrict__ pr
   const double* R1 = P.kk + KK_R1 * kk2;
   const double* d = P.vec + VEC_D * k;
   const double* alpha = P.vec + VEC_ALPHA * k;
-  // this lane's four entries (rows pi*16 + g + 4r, column tj*16 + r16): every
-  // load of the elementwise part is issued before the product
+  // this lane's four entries (rows pi*16 + g + 4r, column tj*16 + r16), the
+  // right operand Y1 and the panel of Z0
   const int j = tj * 16 + r16;
+  double by[KQ];
+  pp_fetch<KQ>(k, [&](int l, int jj) { return pp_y1(P, l, jj); }, tj, by);
   double vpt[4], vp2[4], vr1[4], vg[4], di[4], ai[4];
   const double dj = j < k ? *gld(d + j) : 0.0;
 #pragma unroll
@@ -831,9 +848,10 @@ __global__ __launch_bounds__(512) void pp_res_kernel(const Prob* __restrict__ pr
     di[r] = i < k ? *gld(d + i) : 0.0;
     ai[r] = i < k ? *gld(alpha + i) : 0.0;
   }
+  pp_load_nb(k, pi, As, [&](int i, int l) { return *gld(Zg + i * k + l); });
+  __syncthreads();
   // F0 = I - Z0 Y1
-  pp_load(k, pi, As, [&](int i, int l) { return *gld(Zg + i * k + l); });
-  const v4d acc = pp_tile(k, As, [&](int l, int jj) { return pp_y1(P, l, jj); }, tj);
+  const v4d acc = pp_mul<KQ>(k, As, by);
   double f2 = 0.0, e2 = 0.0;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
@@ -866,6 +884,7 @@ __global__ __launch_bounds__(512) void pp_res_kernel(const Prob* __restrict__ pr
   }
 }
 
+template <int KQ>
 __global__ __launch_bounds__(512) void pp_ns_kernel(const Prob* __restrict__ probs) {
   __shared__ double As[16 * PP_LDA];
   __shared__ double Bs[16 * PP_LDA];
@@ -874,20 +893,28 @@ __global__ __launch_bounds__(512) void pp_ns_kernel(const Prob* __restrict__ pro
   if (ctrl->stopped) return;
   const int k = P.k, kk2 = k * k, pi = blockIdx.x, tj = threadIdx.x >> 6;
   const int np = (k + 15) / 16;
+  const double* Zg = P.kk + KK_Z * kk2;
+  const double* F0 = P.kk + KK_S0 * kk2;
+  const double* Cb = P.kk + (KK_S0 + 1) * kk2;
+  double* Zn = P.kk + (KK_S0 + 3) * kk2;
+  double* Cm = P.kk + KK_CM * kk2;
+  // one round: F0, Z0 and C as right operands, the panel of F0 and the
+  // partial norms of F0 (fetched before the acceptance test; unused if the
+  // warm start is rejected)
+  double bF[KQ], bZ[KQ], bC[KQ];
+  pp_fetch<KQ>(k, [&](int l, int j) { return *gld(F0 + l * k + j); }, tj, bF);
+  pp_fetch<KQ>(k, [&](int l, int j) { return *gld(Zg + l * k + j); }, tj, bZ);
+  pp_fetch<KQ>(k, [&](int l, int j) { return *gld(Cb + l * k + j); }, tj, bC);
+  pp_load_nb(k, pi, As, [&](int i, int l) { return *gld(F0 + i * k + l); });  // As = F0 panel
   double f2 = 0.0;
   for (int p = 0; p < np; ++p) f2 += P.kpp[p];
   const double eres = sqrt(f2);
   const double tol = 16.0 * k * UNIT_ROUNDOFF;
   const bool accept = (eres * eres) * (eres * eres) <= tol;
   if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->kxk_fb = accept ? 0 : 1;
-  if (!accept) return;
-  const double* Zg = P.kk + KK_Z * kk2;
-  const double* F0 = P.kk + KK_S0 * kk2;
-  const double* Cb = P.kk + (KK_S0 + 1) * kk2;
-  double* Zn = P.kk + (KK_S0 + 3) * kk2;
-  double* Cm = P.kk + KK_CM * kk2;
+  if (!accept) return;  // the same decision in every thread
+  __syncthreads();
   // T = I + F0 + F0^2 + F0^3 on this panel, accumulated in Bs
-  pp_load(k, pi, As, [&](int i, int l) { return *gld(F0 + i * k + l); });  // As = F0 panel
   {
     const int kp = (k + 3) / 4 * 4;
     for (int e = threadIdx.x; e < 16 * kp; e += blockDim.x) {
@@ -898,7 +925,7 @@ __global__ __launch_bounds__(512) void pp_ns_kernel(const Prob* __restrict__ pro
   }
   for (int pw = 2; pw <= 3; ++pw) {
     // As <- As F0 (F0^pw on the panel); Bs += As
-    const v4d acc = pp_tile(k, As, [&](int l, int j) { return *gld(F0 + l * k + j); }, tj);
+    const v4d acc = pp_mul<KQ>(k, As, bF);
     __syncthreads();
     pp_each(k, pi, tj, acc, [&](int i, int j, double v) {
       const int r = i - pi * 16;
@@ -909,7 +936,7 @@ __global__ __launch_bounds__(512) void pp_ns_kernel(const Prob* __restrict__ pro
   }
   // Z = T Z0 on this panel -> As and Zn
   {
-    const v4d acc = pp_tile(k, Bs, [&](int l, int j) { return *gld(Zg + l * k + j); }, tj);
+    const v4d acc = pp_mul<KQ>(k, Bs, bZ);
     __syncthreads();
     pp_each(k, pi, tj, acc, [&](int i, int j, double v) {
       As[(i - pi * 16) * PP_LDA + j] = v;
@@ -919,7 +946,7 @@ __global__ __launch_bounds__(512) void pp_ns_kernel(const Prob* __restrict__ pro
   }
   // M = -Z C
   {
-    const v4d acc = pp_tile(k, As, [&](int l, int j) { return *gld(Cb + l * k + j); }, tj);
+    const v4d acc = pp_mul<KQ>(k, As, bC);
     pp_each(k, pi, tj, acc, [&](int i, int j, double v) { *gst(Cm + i * 2 * k + j) = -v; });
   }
   // column sums of |Z| over the panel's rows
@@ -930,8 +957,9 @@ __global__ __launch_bounds__(512) void pp_ns_kernel(const Prob* __restrict__ pro
   }
 }
 
+template <int KQ>
 __global__ __launch_bounds__(512) void pp_f_kernel(const Prob* __restrict__ probs) {
-  __shared__ double As[16 * PP_LDA];
+  __shared__ double As[3][16 * PP_LDA];
   const Prob& P = probs[0];
   Ctrl* ctrl = P.ctrl;
   if (ctrl->stopped || ctrl->kxk_fb) return;
@@ -946,7 +974,15 @@ __global__ __launch_bounds__(512) void pp_f_kernel(const Prob* __restrict__ prob
   const double* Cm = P.kk + KK_CM * kk2;
   double* Q = P.kk + KK_Q * kk2;
   const int j = tj * 16 + r16;
-  // loads of the elementwise parts first
+  // one round: E11, M and Z^T as right operands, the panels of X1^T, G2 and
+  // Y1, and the elementwise parts
+  // (past k = 64 the third operand is fetched once the first two are used,
+  // which keeps the three within the register file)
+  double bE[KQ], bM[KQ], bZt[KQ];
+  auto fetch_zt = [&]() { pp_fetch<KQ>(k, [&](int l, int jj) { return *gld(Zn + jj * k + l); }, tj, bZt); };
+  pp_fetch<KQ>(k, [&](int l, int jj) { return *gld(E1 + l * k + jj); }, tj, bE);
+  pp_fetch<KQ>(k, [&](int l, int jj) { return *gld(Cm + l * 2 * k + jj); }, tj, bM);
+  if constexpr (KQ <= 16) fetch_zt();
   double vp2[4], ve1[4], zc[4];
   const double dj = j < k ? *gld(P.vec + VEC_DINV * k + j) : 0.0;
 #pragma unroll
@@ -958,12 +994,13 @@ __global__ __launch_bounds__(512) void pp_f_kernel(const Prob* __restrict__ prob
     ve1[r] = ok ? *gld(E1 + e) : 0.0;
     zc[r] = ok ? *gld(Zn + e) : 0.0;
   }
-  // F = X1^T E11 + (P2 - G2 M) diag(dinv) - E11
-  pp_load(k, pi, As, [&](int i, int l) { return *gld(P.x + (int64_t)l * P.ldx + i); });
-  const v4d fa = pp_tile(k, As, [&](int l, int jj) { return *gld(E1 + l * k + jj); }, tj);
+  pp_load_nb(k, pi, As[0], [&](int i, int l) { return *gld(P.x + (int64_t)l * P.ldx + i); });
+  pp_load_nb(k, pi, As[1], [&](int i, int l) { return *gld(G2 + i * k + l); });
+  pp_load_nb(k, pi, As[2], [&](int i, int l) { return pp_y1(P, i, l); });
   __syncthreads();
-  pp_load(k, pi, As, [&](int i, int l) { return *gld(G2 + i * k + l); });
-  const v4d fb = pp_tile(k, As, [&](int l, int jj) { return *gld(Cm + l * 2 * k + jj); }, tj);
+  // F = X1^T E11 + (P2 - G2 M) diag(dinv) - E11
+  const v4d fa = pp_mul<KQ>(k, As[0], bE);
+  const v4d fb = pp_mul<KQ>(k, As[1], bM);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int i = pi * 16 + mfma_row(g, r);
@@ -973,20 +1010,20 @@ __global__ __launch_bounds__(512) void pp_f_kernel(const Prob* __restrict__ prob
       *gst(Zg + e) = zc[r];  // the next step's warm start
     }
   }
-  __syncthreads();
   // Q = Y1 Z^T, and the column sums of |Y1| over this panel's rows
-  pp_load(k, pi, As, [&](int i, int l) { return pp_y1(P, i, l); });
-  const v4d qa = pp_tile(k, As, [&](int l, int jj) { return *gld(Zn + jj * k + l); }, tj);
+  if constexpr (KQ > 16) fetch_zt();
+  const v4d qa = pp_mul<KQ>(k, As[2], bZt);
   pp_each(k, pi, tj, qa, [&](int i, int jj, double v) { *gst(Q + i * k + jj) = v; });
   for (int c = threadIdx.x; c < k; c += blockDim.x) {
     double a = 0.0;
-    for (int r = 0; r < 16; ++r) a += fabs(As[r * PP_LDA + c]);  // zero rows beyond k
+    for (int r = 0; r < 16; ++r) a += fabs(As[2][r * PP_LDA + c]);  // zero rows beyond k
     P.kpp[16 + pi * k + c] = a;
   }
 }
 
+template <int KQ>
 __global__ __launch_bounds__(512) void pp_n_kernel(const Prob* __restrict__ probs) {
-  __shared__ double As[16 * PP_LDA];
+  __shared__ double As[2][16 * PP_LDA];
   __shared__ double red[2][8];
   const Prob& P = probs[0];
   Ctrl* ctrl = P.ctrl;
@@ -1001,6 +1038,10 @@ __global__ __launch_bounds__(512) void pp_n_kernel(const Prob* __restrict__ prob
   double* Cm = P.kk + KK_CM * kk2;
   double* X1n = P.kk + KK_X1N * kk2;
   const int j = tj * 16 + r16;
+  // one round: F as the right operand of both products, the panels of Z^T
+  // and Q, the elementwise parts and the column sums for cond_1
+  double bF[KQ];
+  pp_fetch<KQ>(k, [&](int l, int jj) { return *gld(Fm + l * k + jj); }, tj, bF);
   double vx[4], ve1[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
@@ -1009,6 +1050,8 @@ __global__ __launch_bounds__(512) void pp_n_kernel(const Prob* __restrict__ prob
     vx[r] = ok ? *gld(P.x + (int64_t)i * P.ldx + j) : 0.0;
     ve1[r] = ok ? *gld(E1 + i * k + j) : 0.0;
   }
+  pp_load_nb(k, pi, As[0], [&](int i, int l) { return *gld(Zn + l * k + i); });
+  pp_load_nb(k, pi, As[1], [&](int i, int l) { return *gld(Q + i * k + l); });
   // cond_1(Y1) = ||Y1||_1 ||Z||_1 from the panel column sums (the same in
   // every block); a failure stops the step before the update applies it
   double cy = 0.0, cz = 0.0;
@@ -1029,7 +1072,7 @@ __global__ __launch_bounds__(512) void pp_n_kernel(const Prob* __restrict__ prob
     red[0][tj] = cy;
     red[1][tj] = cz;
   }
-  __syncthreads();
+  __syncthreads();  // also completes the panels in LDS
   double ny = 0.0, nz = 0.0;
   for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
     ny = fmax(ny, red[0][w]);
@@ -1043,13 +1086,10 @@ __global__ __launch_bounds__(512) void pp_n_kernel(const Prob* __restrict__ prob
     return;
   }
   // N = -Z^T F
-  pp_load(k, pi, As, [&](int i, int l) { return *gld(Zn + l * k + i); });
-  const v4d na = pp_tile(k, As, [&](int l, int jj) { return *gld(Fm + l * k + jj); }, tj);
+  const v4d na = pp_mul<KQ>(k, As[0], bF);
   pp_each(k, pi, tj, na, [&](int i, int jj, double v) { *gst(Cm + i * 2 * k + k + jj) = -v; });
-  __syncthreads();
   // X1 + E11 + Q F
-  pp_load(k, pi, As, [&](int i, int l) { return *gld(Q + i * k + l); });
-  const v4d xa = pp_tile(k, As, [&](int l, int jj) { return *gld(Fm + l * k + jj); }, tj);
+  const v4d xa = pp_mul<KQ>(k, As[1], bF);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int i = pi * 16 + mfma_row(g, r);
@@ -1074,14 +1114,25 @@ hipError_t launch_kxk(const Prob* probs, int nprob, int kmax, bool pipeline, hip
   if (nprob == 1 && pipeline) {
     const int np = (kmax + 15) / 16;
     const dim3 grid(np), block(64 * np);
-    hipLaunchKernelGGL(pp_res_kernel, grid, block, 0, st, probs);
-    hipLaunchKernelGGL(pp_ns_kernel, grid, block, 0, st, probs);
+    const bool q16 = kmax <= 64;  // contraction in groups of four: 16 or 32 groups
+    if (q16) {
+      hipLaunchKernelGGL(pp_res_kernel<16>, grid, block, 0, st, probs);
+      hipLaunchKernelGGL(pp_ns_kernel<16>, grid, block, 0, st, probs);
+    } else {
+      hipLaunchKernelGGL(pp_res_kernel<32>, grid, block, 0, st, probs);
+      hipLaunchKernelGGL(pp_ns_kernel<32>, grid, block, 0, st, probs);
+    }
     if (kmax <= KS_K)
       hipLaunchKernelGGL(kxk_small_kernel, dim3(1), dim3(KS_NT), 0, st, probs, 1, 1);
     else
       hipLaunchKernelGGL(kxk_kernel<false>, dim3(1), dim3(KXK_NT), 0, st, probs, 1, 1);
-    hipLaunchKernelGGL(pp_f_kernel, grid, block, 0, st, probs);
-    hipLaunchKernelGGL(pp_n_kernel, grid, block, 0, st, probs);
+    if (q16) {
+      hipLaunchKernelGGL(pp_f_kernel<16>, grid, block, 0, st, probs);
+      hipLaunchKernelGGL(pp_n_kernel<16>, grid, block, 0, st, probs);
+    } else {
+      hipLaunchKernelGGL(pp_f_kernel<32>, grid, block, 0, st, probs);
+      hipLaunchKernelGGL(pp_n_kernel<32>, grid, block, 0, st, probs);
+    }
     return hipGetLastError();
   }
   if (kmax <= KS_K)
