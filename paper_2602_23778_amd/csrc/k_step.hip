@@ -26,21 +26,28 @@
 namespace rfk {
 
 // ---------------------------------------------------------------------------
-// pass 2: Gram partials on the matrix cores.  Wavefront (ti, rg) owns the
-// 16-column tile ti of the left factor for row group rg: it accumulates the
-// tiles (ti, tj) of X^T R for all tj and of X^T X for tj >= ti (X^T X is
-// symmetric; the reduction mirrors the rest) over every RG-th 4-row step of
-// the block.  Lane l reads row (r + l/16) at column (t*16 + l%16), so both
-// MFMA operands are plain row-major reads.  The RG row groups are summed in
-// LDS in a fixed order before the block writes its partial.
+// pass 2: Gram partials on the matrix cores.  A work item is one row block
+// and one of CH groups of TH column tiles (CH = 2 from k > 48 on: twice the
+// workgroups, each with half the accumulators and operand loads; the groups
+// write disjoint entries of the block's partial).  Wavefront (ti, rg) owns
+// the 16-column tile ti of the left factor for row group rg: it accumulates
+// the tiles (ti, tj) of X^T R for the item's tj and of X^T X for those
+// tj >= ti (X^T X is symmetric; the reduction mirrors the rest) over every
+// RG-th 4-row step of the block.  Lane l reads row (r + l/16) at column
+// (t*16 + l%16), so both MFMA operands are plain row-major reads.  The RG row
+// groups are summed in LDS in a fixed order before the item writes its part
+// of the partial.
 // ---------------------------------------------------------------------------
-template <int CT, int RG>
+int gram_halves(int kmax) { return (kmax + 15) / 16 >= 4 ? 2 : 1; }
+
+template <int CT, int RG, int CH>
 __global__ __launch_bounds__(CT * RG * 64) void gram_kernel(const Prob* __restrict__ probs,
                                                            const RowItem* __restrict__ items,
                                                            int nitems) {
+  constexpr int TH = (CT + CH - 1) / CH;
   constexpr int XR = RG > 1 ? RG - 1 : 1;
   __shared__ double xch[XR][CT][256];
-  __shared__ double rsq_x[RG][CT * 64];
+  __shared__ double rsq_x[RG][TH * 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int ti = wave % CT, rg = wave / CT;
   const int g = lane >> 4, r16 = lane & 15;
@@ -48,38 +55,39 @@ __global__ __launch_bounds__(CT * RG * 64) void gram_kernel(const Prob* __restri
     const RowItem item = items[it];
     const Prob& P = probs[item.prob];
     if (P.ctrl->stopped) continue;
+    const int blk = item.blk / CH, t0 = (item.blk % CH) * TH;
     const int n = P.n, k = P.k;
     const int ct_used = (k + 15) / 16;
     const bool has_lo = P.wlo != nullptr;
     const double* __restrict__ X = P.x;
     const int64_t ldx = P.ldx;
-    const int r0 = item.blk * P.gbrows, r1 = min(n, r0 + P.gbrows);
+    const int r0 = blk * P.gbrows, r1 = min(n, r0 + P.gbrows);
     const int kk2 = k * k;
     const bool active = ti < ct_used;
-    double dv[CT];
-    bool cok[CT];
+    double dv[TH];
+    bool cok[TH];
 #pragma unroll
-    for (int t = 0; t < CT; ++t) {
-      const int c = t * 16 + r16;
-      cok[t] = c < k;
-      dv[t] = cok[t] ? *gld(P.vec + VEC_D * k + c) : 0.0;
+    for (int u = 0; u < TH; ++u) {
+      const int c = (t0 + u) * 16 + r16;
+      cok[u] = t0 + u < CT && c < k;
+      dv[u] = cok[u] ? *gld(P.vec + VEC_D * k + c) : 0.0;
     }
     const int ca = ti * 16 + r16;
     const bool aok = ca < k;
-    double rsq[CT];
+    double rsq[TH];
 #pragma unroll
-    for (int t = 0; t < CT; ++t) rsq[t] = 0.0;
+    for (int u = 0; u < TH; ++u) rsq[u] = 0.0;
 
     // phase 0: rows < k (only block 0 has them); phase 1: rows >= k
     for (int phase = 0; phase < 2; ++phase) {
       const int lo = phase == 0 ? r0 : max(r0, k);
       const int hi = phase == 0 ? min(r1, k) : r1;
       if (lo >= hi) continue;
-      v4d accP[CT], accG[CT];
+      v4d accP[TH], accG[TH];
 #pragma unroll
-      for (int t = 0; t < CT; ++t) {
-        accP[t] = v4d{0.0, 0.0, 0.0, 0.0};
-        accG[t] = v4d{0.0, 0.0, 0.0, 0.0};
+      for (int u = 0; u < TH; ++u) {
+        accP[u] = v4d{0.0, 0.0, 0.0, 0.0};
+        accG[u] = v4d{0.0, 0.0, 0.0, 0.0};
       }
       if (active) {
 #pragma unroll 2
@@ -90,33 +98,34 @@ __global__ __launch_bounds__(CT * RG * 64) void gram_kernel(const Prob* __restri
           const double* wr = P.w + (int64_t)(rok ? row : lo) * k;
           const double* wl = has_lo ? P.wlo + (int64_t)(rok ? row : lo) * k : nullptr;
           const double xa = (rok && aok) ? *gld(xr + ca) : 0.0;
-          double xv[CT], rv[CT];
+          double xv[TH], rv[TH];
 #pragma unroll
-          for (int t = 0; t < CT; ++t) {
-            const int c = t * 16 + r16;
-            if (rok && cok[t]) {
+          for (int u = 0; u < TH; ++u) {
+            const int c = (t0 + u) * 16 + r16;
+            if (rok && cok[u]) {
               const double x = *gld(xr + c);
-              xv[t] = x;
-              rv[t] = residual(*gld(wr + c), has_lo ? *gld(wl + c) : 0.0, x, dv[t], has_lo);
+              xv[u] = x;
+              rv[u] = residual(*gld(wr + c), has_lo ? *gld(wl + c) : 0.0, x, dv[u], has_lo);
             } else {
-              xv[t] = 0.0;
-              rv[t] = 0.0;
+              xv[u] = 0.0;
+              rv[u] = 0.0;
             }
           }
 #pragma unroll
-          for (int t = 0; t < CT; ++t) {
+          for (int u = 0; u < TH; ++u) {
+            const int t = t0 + u;
             if (t < ct_used) {
-              accP[t] = mfma_f64(xa, rv[t], accP[t]);
-              if (t >= ti) accG[t] = mfma_f64(xa, xv[t], accG[t]);
+              accP[u] = mfma_f64(xa, rv[u], accP[u]);
+              if (t >= ti) accG[u] = mfma_f64(xa, xv[u], accG[u]);
             }
           }
           if (ti == 0) {
 #pragma unroll
-            for (int t = 0; t < CT; ++t) rsq[t] = __builtin_fma(rv[t], rv[t], rsq[t]);
+            for (int u = 0; u < TH; ++u) rsq[u] = __builtin_fma(rv[u], rv[u], rsq[u]);
             if (phase == 0 && rok) {
 #pragma unroll
-              for (int t = 0; t < CT; ++t)
-                if (cok[t]) *gst(P.kk + KK_R1 * kk2 + row * k + t * 16 + r16) = rv[t];
+              for (int u = 0; u < TH; ++u)
+                if (cok[u]) *gst(P.kk + KK_R1 * kk2 + row * k + (t0 + u) * 16 + r16) = rv[u];
             }
           }
         }
@@ -124,8 +133,8 @@ __global__ __launch_bounds__(CT * RG * 64) void gram_kernel(const Prob* __restri
       // sum the row groups into row group 0, one tile at a time
       if (RG > 1) {
 #pragma unroll
-        for (int t = 0; t < 2 * CT; ++t) {
-          v4d& v = t < CT ? accP[t] : accG[t - CT];
+        for (int t = 0; t < 2 * TH; ++t) {
+          v4d& v = t < TH ? accP[t] : accG[t - TH];
           if (rg > 0) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) xch[rg - 1][ti][lane * 4 + r] = v[r];
@@ -148,44 +157,46 @@ __global__ __launch_bounds__(CT * RG * 64) void gram_kernel(const Prob* __restri
           dstP = P.kk + KK_PT * kk2;
           dstG = P.kk + KK_GT * kk2;
         } else {
-          dstP = P.gpart + (int64_t)item.blk * (2 * kk2 + k);
+          dstP = P.gpart + (int64_t)blk * (2 * kk2 + k);
           dstG = dstP + kk2;
         }
 #pragma unroll
-        for (int t = 0; t < CT; ++t) {
+        for (int u = 0; u < TH; ++u) {
+          const int t = t0 + u;
           const int c = t * 16 + r16;
           if (t < ct_used && c < k) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               const int i = ti * 16 + mfma_row(g, r);
               if (i < k) {
-                *gst(dstP + i * k + c) = accP[t][r];
-                if (t >= ti) *gst(dstG + i * k + c) = accG[t][r];
+                *gst(dstP + i * k + c) = accP[u][r];
+                if (t >= ti) *gst(dstG + i * k + c) = accG[u][r];
               }
             }
           }
         }
       }
     }
-    // blocks without rows >= k still publish zero partials
-    if (max(r0, k) >= r1) {
-      double* dst = P.gpart + (int64_t)item.blk * (2 * kk2 + k);
+    // blocks without rows >= k still publish zero partials (the first column
+    // group writes them all)
+    if (max(r0, k) >= r1 && t0 == 0) {
+      double* dst = P.gpart + (int64_t)blk * (2 * kk2 + k);
       for (int e = threadIdx.x; e < 2 * kk2; e += blockDim.x) *gst(dst + e) = 0.0;
     }
-    // column sums of r^2 over the block's rows
+    // column sums of r^2 over the block's rows, for this item's columns
     if (ti == 0) {
 #pragma unroll
-      for (int t = 0; t < CT; ++t) rsq_x[rg][t * 64 + lane] = rsq[t];
+      for (int u = 0; u < TH; ++u) rsq_x[rg][u * 64 + lane] = rsq[u];
     }
     __syncthreads();
-    if (threadIdx.x < CT * 16) {
-      const int t = threadIdx.x / 16, c16 = threadIdx.x % 16, c = t * 16 + c16;
-      if (c < k) {
+    if (threadIdx.x < TH * 16) {
+      const int u = threadIdx.x / 16, c16 = threadIdx.x % 16, c = (t0 + u) * 16 + c16;
+      if (t0 + u < CT && c < k) {
         double s = 0.0;
         for (int q = 0; q < RG; ++q)
-          s += (rsq_x[q][t * 64 + c16] + rsq_x[q][t * 64 + 16 + c16]) +
-               (rsq_x[q][t * 64 + 32 + c16] + rsq_x[q][t * 64 + 48 + c16]);
-        *gst(P.gpart + (int64_t)item.blk * (2 * kk2 + k) + 2 * kk2 + c) = s;
+          s += (rsq_x[q][u * 64 + c16] + rsq_x[q][u * 64 + 16 + c16]) +
+               (rsq_x[q][u * 64 + 32 + c16] + rsq_x[q][u * 64 + 48 + c16]);
+        *gst(P.gpart + (int64_t)blk * (2 * kk2 + k) + 2 * kk2 + c) = s;
       }
     }
     __syncthreads();
@@ -959,8 +970,12 @@ hipError_t launch_gram(const Prob* probs, const RowItem* items, int nitems, int 
   const int ct = (kmax + 15) / 16;
 #define RFK_CASE(CTV, RGV)                                                                   \
   case CTV:                                                                                  \
-    hipLaunchKernelGGL((gram_kernel<CTV, RGV>), dim3(nitems), dim3(CTV * RGV * 64), 0, st,   \
-                       probs, items, nitems);                                                \
+    if (gram_halves(kmax) == 2)                                                              \
+      hipLaunchKernelGGL((gram_kernel<CTV, RGV, 2>), dim3(nitems), dim3(CTV * RGV * 64), 0, st, \
+                         probs, items, nitems);                                              \
+    else                                                                                     \
+      hipLaunchKernelGGL((gram_kernel<CTV, RGV, 1>), dim3(nitems), dim3(CTV * RGV * 64), 0, st, \
+                         probs, items, nitems);                                              \
     break;
   if (ct <= 2) {
     if (ct == 1)

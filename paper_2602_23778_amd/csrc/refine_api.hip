@@ -41,6 +41,7 @@ hipError_t launch_ctrl_reset(const Prob*, int, int, double, hipStream_t);
 hipError_t launch_set_x(Prob*, int, double*, int64_t, hipStream_t);
 hipError_t launch_spmm(const Prob*, const RowItem*, int, int, int, hipStream_t);
 int spmm_row_lanes(int k, int64_t n, int64_t nnz);
+int gram_halves(int kmax);
 hipError_t launch_rr_prep(const Prob*, int, hipStream_t);
 hipError_t launch_rr_solve(const Prob*, int, hipStream_t);
 hipError_t launch_rr_apply(const Prob*, const RowItem*, int, hipStream_t);
@@ -432,6 +433,7 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
   pl.ctrl = (Ctrl*)(pl.ws + ctrl_off);
 
   std::vector<RowItem> ri, gri;
+  const int gh = gram_halves(pl.kmax);
   std::vector<GramRedItem> rr;
   for (int p = 0; p < np; ++p) {
     const refine_matrix& A = As[p];
@@ -497,7 +499,7 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
     P.normalize = opt.normalize != 0;
 
     for (int b = 0; b < s.nrb; ++b) ri.push_back(RowItem{p, b});
-    for (int b = 0; b < s.ngb; ++b) gri.push_back(RowItem{p, b});
+    for (int b = 0; b < s.ngb * gh; ++b) gri.push_back(RowItem{p, b});  // (row block, column group)
     const int S = 2 * k * k + k;
     for (int s0 = 0; s0 < S; s0 += 64) rr.push_back(GramRedItem{p, s0});
   }
