@@ -83,7 +83,7 @@ struct Prob {
   const int32_t* aexp;    // per-row scale exponents of A (rows padded with 0)
   uint8_t* xsl;           // slices of X^T: chunk c, column j at xsl + (c*kpad + j)*32*s
   int32_t* xexp;          // per-column scale exponents of X (kpad entries)
-  double* xmaxp;          // per-row-block column maxima of |X|, nbx x kpad
+  double* xmaxp;          // column maxima of |X| (kpad entries), merged by atomic maximum
   double* swp;            // K-split partials of the split product: ksplit x (hi, lo) x n x k
   int32_t nch;            // 32-wide contraction chunks (ceil(n / 32))
   int32_t kpad;           // k rounded up to 32

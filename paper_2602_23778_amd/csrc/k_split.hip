@@ -152,8 +152,11 @@ __global__ __launch_bounds__(256) void split_xmax_kernel(const Prob* __restrict_
     const int tid = threadIdx.x, j = tid % kp, r = tid / kp;
     const int r0 = item.blk * P.xrows, r1 = min(P.n, r0 + P.xrows);
     double m = 0.0;
-    if (j < k)
+    if (j < k) {
+      // eight independent loads in flight per thread
+#pragma unroll 8
       for (int i = r0 + r; i < r1; i += rl) m = fmax(m, fabs(*gld(P.x + (int64_t)i * P.ldx + j)));
+    }
     red[tid] = m;
     __syncthreads();
     for (int s = rl / 2; s > 0; s >>= 1) {
@@ -830,7 +833,10 @@ int split_init(SplitPlan& sp, const std::vector<refine_matrix>& As, const std::v
   sp.bm = 32 * L.wm;
   sp.np = np;
   sp.nk0 = As[0].n * ks[0];
-  constexpr int XROWS = 256;
+  // rows per column-maximum item: 64 gives a few hundred items at n = 8k-16k
+  // (256-row items left most CUs idle and each thread a long chain of loads)
+  // at a few hundred atomic merges per column
+  constexpr int XROWS = 64;
   // one allocation per array for all problems
   std::vector<size_t> o_asl(np), o_aexp(np), o_xsl(np);
   size_t t_asl = 0, t_aexp = 0, t_xsl = 0;
