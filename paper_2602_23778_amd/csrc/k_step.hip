@@ -623,7 +623,13 @@ __global__ __launch_bounds__(256) void update_kernel(const Prob* __restrict__ pr
 // (16 rows x 4 columns per step) and the epilogue's x from them, so X is read
 // from memory once and in whole rows.  W (and W_lo) are read in the
 // epilogue's layout before the products.  [M | N] is staged once per block.
-template <int CT>
+//
+// FUSED (with fin_pre_kernel before it): the step's statistics, scale factors
+// and acceptance are already known, so an accepted step writes the
+// normalised iterate straight into X (each block reads its rows before it
+// overwrites them, and no other block reads them), with no partial sums and
+// no normalisation pass afterwards.
+template <int CT, bool FUSED>
 __global__ __launch_bounds__(256) void update_small_kernel(const Prob* __restrict__ probs,
                                                           const RowItem* __restrict__ items,
                                                           int nitems) {
@@ -640,16 +646,16 @@ __global__ __launch_bounds__(256) void update_small_kernel(const Prob* __restric
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const RowItem item = items[it];
     const Prob& P = probs[item.prob];
-    if (P.ctrl->stopped) continue;
+    if (FUSED ? !P.ctrl->apply : P.ctrl->stopped) continue;
     const int n = P.n, k = P.k, kk2 = k * k, k2 = 2 * k;
     const bool has_lo = P.wlo != nullptr;
-    const double* __restrict__ X = P.x;
+    const double* X = P.x;  // written in place in the fused form
     const int64_t ldx = P.ldx;
     const double* __restrict__ Cm = P.kk + KK_CM * kk2;
     const double* __restrict__ X1n = P.kk + KK_X1N * kk2;
     const int r0 = item.blk * P.rbrows, r1 = min(n, r0 + P.rbrows);
     const bool vec = (ldx & 1) == 0 && (((uintptr_t)X) & 15) == 0 && (k & 1) == 0;
-    double dv[CT], di[CT], xsq[CT], esq[CT];
+    double dv[CT], di[CT], xsq[CT], esq[CT], sc[CT];
     bool cok[CT];
 #pragma unroll
     for (int t = 0; t < CT; ++t) {
@@ -658,6 +664,7 @@ __global__ __launch_bounds__(256) void update_small_kernel(const Prob* __restric
       const int cc = cok[t] ? c : 0;
       dv[t] = *gld(P.vec + VEC_D * k + cc);
       di[t] = cok[t] ? *gld(P.vec + VEC_DINV * k + cc) : 0.0;
+      sc[t] = FUSED ? *gld(P.vec + VEC_SCALE * k + cc) : 1.0;
       xsq[t] = 0.0;
       esq[t] = 0.0;
     }
@@ -746,13 +753,18 @@ __global__ __launch_bounds__(256) void update_small_kernel(const Prob* __restric
                 xt = (x + e) - accN[t][r];
                 esq[t] = __builtin_fma(e, e, esq[t]);
               }
-              *gst(P.xn + (int64_t)row * k + c) = xt;
-              xsq[t] = __builtin_fma(xt, xt, xsq[t]);
+              if (FUSED) {
+                *gst(P.x + (int64_t)row * ldx + c) = xt * sc[t];
+              } else {
+                *gst(P.xn + (int64_t)row * k + c) = xt;
+                xsq[t] = __builtin_fma(xt, xt, xsq[t]);
+              }
             }
           }
         }
       }
     }
+    if (FUSED) continue;
     // block partials of sum x~^2 and sum e^2 per column
 #pragma unroll
     for (int t = 0; t < CT; ++t) {
@@ -817,6 +829,138 @@ __global__ __launch_bounds__(1024) void fin_stats_kernel(const Prob* __restrict_
     bad = __syncthreads_or(bad);
     if (tid == 0) {
       Ctrl* C = P.ctrl;
+      double se = P.vec[VEC_E1SQ * k], sr = 0.0;
+      for (int w = 0; w < NW; ++w) {
+        se += fin[0][w];
+        sr += fin[1][w];
+      }
+      const double corr = sqrt(se);
+      const double resid = sqrt(sr) / P.norm_a;
+      C->corr_fro = corr;
+      C->resid_rel = resid;
+      const bool finite = !bad && __builtin_isfinite(corr) && __builtin_isfinite(resid);
+      const int h = C->iters;
+      const bool grew = h >= 3 && corr > 10.0 * C->hist[(h - 3) & 3];
+      if (!finite) {
+        C->status = -6;
+        C->stopped = 1;
+      } else if (corr >= 1.0 || grew) {
+        C->status = -5;
+        C->stopped = 1;
+      } else {
+        C->apply = 1;
+        C->rr_top = 0;  // a Rayleigh-Ritz basis serves one step
+        C->hist[h & 3] = corr;
+        C->iters = h + 1;
+        if ((C->stop_mode == 1 && corr <= C->tol) || (C->stop_mode == 2 && resid <= C->tol)) {
+          C->converged = 1;
+          C->stopped = 1;
+        }
+      }
+    }
+  }
+}
+
+// Statistics, normalisation factors and the accept/reject decision before
+// the update, for k <= 32, one workgroup per problem.  The bottom rows update
+// as X~2 = X2 A + R2 Delta with A = I - N - M Delta and Delta =
+// diag(1/(d - mu)), so every column norm the step needs is a quadratic form
+// in k x k quantities it already has:
+//   ||x~_j||^2  = ||x~1_j||^2 + a_j^T G2 a_j + 2 Delta_j a_j^T p_j + Delta_j^2 s_j,
+//   ||e21_j||^2 = Delta_j^2 (s_j - 2 m_j^T p_j + m_j^T G2 m_j),
+// with G2 = X2^T X2, p_j and m_j the columns j of X2^T R2 and of M, and
+// s_j = ||r2_j||^2 (the column sum of r^2 less the leading rows).  The terms
+// are small corrections to a_j^T G2 a_j ~ 1 or sums of squares, so the
+// factors are accurate to a few rounding errors.  The rules applied are those
+// of fin_stats_kernel; the fused update then writes the normalised iterate.
+constexpr int FP_K = 32;
+__global__ __launch_bounds__(256) void fin_pre_kernel(const Prob* __restrict__ probs, int nprob) {
+  constexpr int NT = 256, NW = NT / 64, LD = FP_K + 1;
+  __shared__ double Gs[FP_K * LD], Ps[FP_K * LD], As[FP_K * LD], Ms[FP_K * LD];
+  __shared__ double colv[2][FP_K];
+  __shared__ double fin[2][NW];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int p = blockIdx.x; p < nprob; p += gridDim.x) {
+    const Prob& P = probs[p];
+    Ctrl* C = P.ctrl;
+    __syncthreads();
+    if (tid == 0) C->apply = 0;
+    if (C->stopped) continue;
+    const int k = P.k, kk2 = k * k, k2 = 2 * k;
+    const double* G2 = P.kk + KK_G2 * kk2;
+    const double* P2 = P.kk + KK_P2 * kk2;
+    const double* Cm = P.kk + KK_CM * kk2;
+    const double* X1n = P.kk + KK_X1N * kk2;
+    const double* R1 = P.kk + KK_R1 * kk2;
+    const double* dinv = P.vec + VEC_DINV * k;
+    const double* rsq = P.vec + VEC_RSQ * k;
+    for (int e = tid; e < kk2; e += NT) {
+      const int i = e / k, j = e - i * k;
+      const double m = *gld(Cm + i * k2 + j), nn = *gld(Cm + i * k2 + k + j);
+      Gs[i * LD + j] = *gld(G2 + e);
+      Ps[i * LD + j] = *gld(P2 + e);
+      Ms[i * LD + j] = m;
+      As[i * LD + j] = (i == j ? 1.0 : 0.0) - nn - m * *gld(dinv + j);
+    }
+    __syncthreads();
+    // eight threads per column j, each over the rows l = part, part + 8, ...
+    {
+      const int j = tid / 8, part = tid % 8;
+      double sA = 0.0, sM = 0.0, pA = 0.0, pM = 0.0, top = 0.0, r1 = 0.0;
+      if (j < k) {
+        for (int l = part; l < k; l += 8) {
+          double qa = 0.0, qm = 0.0;
+          for (int m = 0; m < k; ++m) {
+            const double gv = Gs[l * LD + m];
+            qa = __builtin_fma(gv, As[m * LD + j], qa);
+            qm = __builtin_fma(gv, Ms[m * LD + j], qm);
+          }
+          const double al = As[l * LD + j], ml = Ms[l * LD + j], pl = Ps[l * LD + j];
+          sA = __builtin_fma(al, qa, sA);
+          sM = __builtin_fma(ml, qm, sM);
+          pA = __builtin_fma(al, pl, pA);
+          pM = __builtin_fma(ml, pl, pM);
+          const double xt = *gld(X1n + l * k + j), rt = *gld(R1 + l * k + j);
+          top = __builtin_fma(xt, xt, top);
+          r1 = __builtin_fma(rt, rt, r1);
+        }
+      }
+#pragma unroll
+      for (int o = 1; o < 8; o *= 2) {
+        sA += __shfl_xor(sA, o);
+        sM += __shfl_xor(sM, o);
+        pA += __shfl_xor(pA, o);
+        pM += __shfl_xor(pM, o);
+        top += __shfl_xor(top, o);
+        r1 += __shfl_xor(r1, o);
+      }
+      if (j < k && part == 0) {
+        const double D = *gld(dinv + j);
+        const double s2 = fmax(*gld(rsq + j) - r1, 0.0);
+        colv[0][j] = top + sA + 2.0 * D * pA + D * D * s2;
+        colv[1][j] = fmax(D * D * (s2 - 2.0 * pM + sM), 0.0);
+      }
+    }
+    __syncthreads();
+    double e2 = 0.0, r2 = 0.0;
+    int bad = 0;
+    for (int j = tid; j < k; j += NT) {
+      const double xs = colv[0][j];
+      P.vec[VEC_SCALE * k + j] = P.normalize ? 1.0 / sqrt(xs) : 1.0;
+      if (!__builtin_isfinite(xs) || !(xs > 0.0)) bad = 1;
+      e2 += colv[1][j];
+      r2 += *gld(rsq + j);
+    }
+    for (int o = 32; o >= 1; o /= 2) {
+      e2 += __shfl_xor(e2, o);
+      r2 += __shfl_xor(r2, o);
+    }
+    if (lane == 0) {
+      fin[0][wave] = e2;
+      fin[1][wave] = r2;
+    }
+    bad = __syncthreads_or(bad);
+    if (tid == 0) {
       double se = P.vec[VEC_E1SQ * k], sr = 0.0;
       for (int w = 0; w < NW; ++w) {
         se += fin[0][w];
@@ -1002,16 +1146,21 @@ hipError_t launch_gram_reduce(const Prob* probs, const GramRedItem* items, int n
   return hipGetLastError();
 }
 
-hipError_t launch_update(const Prob* probs, const RowItem* items, int nitems, int kmax,
+// fused: k <= 32 only (fin_pre_kernel has run; X written in place).
+hipError_t launch_update(const Prob* probs, const RowItem* items, int nitems, int kmax, bool fused,
                          hipStream_t st) {
   const int ct = (kmax + 15) / 16;
+  if (fused && ct > 2) return hipErrorInvalidValue;
   if (ct <= 2) {
-    if (ct == 1)
-      hipLaunchKernelGGL((update_small_kernel<1>), dim3(nitems), dim3(256), 0, st, probs, items,
-                         nitems);
+    const dim3 grid(nitems), block(256);
+    if (ct == 1 && fused)
+      hipLaunchKernelGGL((update_small_kernel<1, true>), grid, block, 0, st, probs, items, nitems);
+    else if (ct == 1)
+      hipLaunchKernelGGL((update_small_kernel<1, false>), grid, block, 0, st, probs, items, nitems);
+    else if (fused)
+      hipLaunchKernelGGL((update_small_kernel<2, true>), grid, block, 0, st, probs, items, nitems);
     else
-      hipLaunchKernelGGL((update_small_kernel<2>), dim3(nitems), dim3(256), 0, st, probs, items,
-                         nitems);
+      hipLaunchKernelGGL((update_small_kernel<2, false>), grid, block, 0, st, probs, items, nitems);
     return hipGetLastError();
   }
 #define RFK_CASE(CTV)                                                                   \
@@ -1036,6 +1185,11 @@ hipError_t launch_wsum(const Prob* probs, int p, int64_t n, int k, hipStream_t s
 
 hipError_t launch_fin_d(const Prob* probs, int nprob, hipStream_t st) {
   hipLaunchKernelGGL(fin_d_kernel, dim3(nprob), dim3(1024), 0, st, probs, nprob);
+  return hipGetLastError();
+}
+
+hipError_t launch_fin_pre(const Prob* probs, int nprob, hipStream_t st) {
+  hipLaunchKernelGGL(fin_pre_kernel, dim3(nprob), dim3(256), 0, st, probs, nprob);
   return hipGetLastError();
 }
 

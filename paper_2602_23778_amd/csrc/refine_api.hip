@@ -32,7 +32,8 @@ struct GramRedItem {
 hipError_t launch_gram_reduce(const Prob*, const GramRedItem*, int, hipStream_t);
 int kxk_lds_doubles(int);
 hipError_t launch_kxk(const Prob*, int, int, bool, hipStream_t);
-hipError_t launch_update(const Prob*, const RowItem*, int, int, hipStream_t);
+hipError_t launch_update(const Prob*, const RowItem*, int, int, bool, hipStream_t);
+hipError_t launch_fin_pre(const Prob*, int, hipStream_t);
 hipError_t launch_normalize(const Prob*, const RowItem*, int, hipStream_t);
 hipError_t launch_wsum(const Prob*, int, int64_t, int, hipStream_t);
 hipError_t launch_fin_d(const Prob*, int, hipStream_t);
@@ -77,6 +78,7 @@ struct Plan {
   int n_spmm = 0;
   int spmm_lanes = 0;             // lanes per row of the row form (0: vector form)
   bool kxk_pipeline = false;      // one problem: k x k stage by the panel pipeline
+  bool fused = false;             // k <= 32: statistics before the update, X written in place
   GramRedItem* gred_items = nullptr;
   int n_gred = 0;
   int kmax = 0;
@@ -434,6 +436,7 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
 
   std::vector<RowItem> ri, gri;
   const int gh = gram_halves(pl.kmax);
+  pl.fused = pl.kmax <= 32;
   std::vector<GramRedItem> rr;
   for (int p = 0; p < np; ++p) {
     const refine_matrix& A = As[p];
@@ -574,7 +577,14 @@ hipError_t enqueue_step(Plan& pl, hipStream_t st) {
   if ((e = launch_gram(pl.dprob, pl.gram_items, pl.n_gram, pl.kmax, st)) != hipSuccess) return e;
   if ((e = launch_gram_reduce(pl.dprob, pl.gred_items, pl.n_gred, st)) != hipSuccess) return e;
   if ((e = launch_kxk(pl.dprob, np, pl.kmax, pl.kxk_pipeline, st)) != hipSuccess) return e;
-  if ((e = launch_update(pl.dprob, pl.row_items, pl.n_row, pl.kmax, st)) != hipSuccess) return e;
+  if (pl.fused) {
+    // k <= 32: statistics and scale factors from k x k quantities, then the
+    // update writes the normalised iterate in place
+    if ((e = launch_fin_pre(pl.dprob, np, st)) != hipSuccess) return e;
+    if ((e = launch_update(pl.dprob, pl.row_items, pl.n_row, pl.kmax, true, st)) != hipSuccess) return e;
+    return hipSuccess;
+  }
+  if ((e = launch_update(pl.dprob, pl.row_items, pl.n_row, pl.kmax, false, st)) != hipSuccess) return e;
   if ((e = launch_fin_stats(pl.dprob, np, st)) != hipSuccess) return e;
   if ((e = launch_normalize(pl.dprob, pl.row_items, pl.n_row, st)) != hipSuccess) return e;
   return hipSuccess;
