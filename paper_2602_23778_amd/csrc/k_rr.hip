@@ -243,36 +243,87 @@ __global__ __launch_bounds__(RR_NT) void rr_solve_kernel(const Prob* __restrict_
   }
 }
 
-// X <- X S in place, 16 rows at a time: the rows are copied to LDS before any
-// of them is overwritten.
+// X <- X S in place, 16 rows at a time: a chunk's rows are copied to LDS
+// before any of them is overwritten, and the next chunk's rows are requested
+// (into registers) before the current chunk is multiplied, so the block waits
+// on memory once per chunk rather than twice.  S sits in LDS for k <= 64
+// (read from L2 otherwise); for k <= 32 each thread keeps its column of S in
+// registers, so the product reads LDS once per multiply-add, by broadcast.
+constexpr int RA_ROWS = 16;
+constexpr int RA_SMAX = 64;
 __global__ __launch_bounds__(256) void rr_apply_kernel(const Prob* __restrict__ probs,
                                                       const RowItem* __restrict__ items, int nitems) {
-  __shared__ double xs[16 * KMAX];
+  constexpr int NT = 256, PF = RA_ROWS * KMAX / NT;
+  __shared__ double xs[2][RA_ROWS * KMAX];
+  __shared__ double ss[RA_SMAX * RA_SMAX];
+  const int tid = threadIdx.x;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const RowItem item = items[it];
     const Prob& P = probs[item.prob];
-    __syncthreads();
+    __syncthreads();  // the previous item's reads of xs and ss are done
     if (P.ctrl->stopped) continue;
-    const int n = P.n, k = P.k, kk2 = k * k;
+    const int n = P.n, k = P.k, kk2 = k * k, rk = RA_ROWS * k;
     const double* S = P.kk + (KK_S0 + 2) * kk2;
+    const bool s_lds = k <= RA_SMAX;
+    if (s_lds)
+      for (int e = tid; e < kk2; e += NT) ss[e] = *gld(S + e);
+    const double* Sv = s_lds ? ss : S;
+    // k <= 32: this thread's column of S (tid % 32) in registers
+    double scol[32];
+    {
+      const int c = tid % 32;
+#pragma unroll
+      for (int l = 0; l < 32; ++l) scol[l] = (l < k && c < k) ? *gld(S + l * k + c) : 0.0;
+    }
     double* X = P.x;
     const int64_t ldx = P.ldx;
     const int r0 = item.blk * P.rbrows, r1 = min(n, r0 + P.rbrows);
-    for (int rb = r0; rb < r1; rb += 16) {
-      __syncthreads();
-      for (int e = threadIdx.x; e < 16 * k; e += 256) {
+    double pf[PF];
+    auto fetch = [&](int rb) {
+#pragma unroll
+      for (int u = 0; u < PF; ++u) {
+        const int e = tid + u * NT;
         const int r = e / k, j = e - r * k;
-        xs[e] = rb + r < r1 ? X[(int64_t)(rb + r) * ldx + j] : 0.0;
+        pf[u] = (e < rk && rb + r < r1) ? *gld(X + (int64_t)(rb + r) * ldx + j) : 0.0;
+      }
+    };
+    fetch(r0);
+    int b = 0;
+    for (int rb = r0; rb < r1; rb += RA_ROWS) {
+#pragma unroll
+      for (int u = 0; u < PF; ++u) {
+        const int e = tid + u * NT;
+        if (e < rk) xs[b][e] = pf[u];
       }
       __syncthreads();
-      for (int e = threadIdx.x; e < 16 * k; e += 256) {
-        const int r = e / k, c = e - r * k;
-        if (rb + r < r1) {
-          double v = 0.0;
-          for (int l = 0; l < k; ++l) v = __builtin_fma(xs[r * k + l], S[l * k + c], v);
-          X[(int64_t)(rb + r) * ldx + c] = v;
+      if (rb + RA_ROWS < r1) fetch(rb + RA_ROWS);
+      if (k <= 32) {
+        // lane c of a 32-lane row slot owns column c with S(:, c) in
+        // registers; the slot's rows r and r + 8 come from LDS by broadcast
+        const int c = tid % 32, r = tid / 32;
+        if (c < k) {
+          double v0 = 0.0, v1 = 0.0;
+#pragma unroll
+          for (int l = 0; l < 32; ++l) {
+            if (l < k) {
+              v0 = __builtin_fma(xs[b][r * k + l], scol[l], v0);
+              v1 = __builtin_fma(xs[b][(r + 8) * k + l], scol[l], v1);
+            }
+          }
+          if (rb + r < r1) X[(int64_t)(rb + r) * ldx + c] = v0;
+          if (rb + r + 8 < r1) X[(int64_t)(rb + r + 8) * ldx + c] = v1;
+        }
+      } else {
+        for (int e = tid; e < rk; e += NT) {
+          const int r = e / k, c = e - r * k;
+          if (rb + r < r1) {
+            double v = 0.0;
+            for (int l = 0; l < k; ++l) v = __builtin_fma(xs[b][r * k + l], Sv[l * k + c], v);
+            X[(int64_t)(rb + r) * ldx + c] = v;
+          }
         }
       }
+      b ^= 1;
     }
   }
 }
