@@ -47,7 +47,8 @@ def _compare_steps(A_np, X0, steps, *, norm_a, mu=0.0, target="largest_abs", shi
     for s in range(steps):
         st = ctx.step(Xg)
         assert st.status == rf.OK, rf.status_string(st.status)
-        r = oracle.refine_step(A_host, Xo, mu=info["mu"], norm_a=norm_a, dd=dd, split=split)
+        r = oracle.refine_step(A_host, Xo, mu=info["mu"], norm_a=norm_a, dd=dd, split=split,
+                               normalize=opts.get("normalize", True))
         assert r.status == 0
         Xo = r.X
         got = Xg.cpu().numpy()
@@ -231,6 +232,37 @@ def test_singular_y1_and_nonfinite_are_reported():
     st = ctx.step(Xn)
     assert st.status == rf.ENONFINITE
     ctx.close()
+
+
+@pytest.mark.parametrize("k", [8, 40])
+def test_diverged_step_is_rejected_and_x_unchanged(k):
+    """||E_L||_F >= 1 (a random orthonormal start) is reported as divergence
+    and the rejected step leaves X unchanged, both where the statistics are
+    formed before the update (k <= 32) and after it (k > 32)."""
+    rf = _lib()
+    P = synth.dense_spectrum(300, k, 9100 + k)
+    rng = np.random.default_rng(5)
+    q, r = np.linalg.qr(rng.standard_normal((300, k)))
+    X0 = q * np.sign(np.diag(r))
+    assert oracle.refine_step(P.A, X0, norm_a=1.0).corr_fro > 1.0
+    ctx = rf.RefineContext(_dev(P.A), k, norm_a=1.0)
+    X = _dev(X0).clone()
+    st = ctx.step(X)
+    assert st.status == rf.EDIVERGED
+    assert np.array_equal(X.cpu().numpy(), X0)
+    # the context recovers with a good start
+    Xg = _dev(P.X0).clone()
+    assert ctx.step(Xg).status == rf.OK
+    ctx.close()
+
+
+@pytest.mark.parametrize("k", [8, 40])
+def test_normalization_off_matches_oracle(k):
+    """normalize = 0 (Sec. 3.3 makes normalisation a choice): columns 0.1 %
+    longer than unit length stay unnormalised, as in the oracle."""
+    P = synth.dense_spectrum(300, k, 9200 + k)
+    X0 = P.X0 * 1.001
+    _compare_steps(P.A, X0, 3, norm_a=1.0, normalize=False)
 
 
 def test_invalid_arguments():
