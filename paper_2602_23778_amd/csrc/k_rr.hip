@@ -33,7 +33,7 @@ constexpr int RR_LD = KMAX + 1;
 constexpr int RR_SWEEPS = 40;
 
 __global__ __launch_bounds__(RR_NT) void rr_solve_kernel(const Prob* __restrict__ probs, int nprob) {
-  __shared__ double C[KMAX * RR_LD];
+  __shared__ double C[KMAX * RR_LD];  // C (stride k + 1), then Q when it fits
   __shared__ double rc[KMAX / 2 + 1], rs[KMAX / 2 + 1];
   __shared__ int ra[KMAX / 2 + 1], rb[KMAX / 2 + 1];
   __shared__ double red[2][RR_NT];
@@ -47,8 +47,15 @@ __global__ __launch_bounds__(RR_NT) void rr_solve_kernel(const Prob* __restrict_
     __syncthreads();
     if (ctrl->stopped) continue;
     const int k = P.k, kk2 = k * k;
-    double* L = P.kk + KK_S0 * kk2;        // Cholesky factor, row-major, lower
-    double* Q = P.kk + (KK_S0 + 1) * kk2;  // Jacobi eigenvectors
+    // C at stride k + 1; the Jacobi eigenvectors Q and the Cholesky factor L
+    // (row-major, lower) follow it in LDS while they fit (Q for k <= 90, L for
+    // k <= 74): the triangular solves read L once per multiply-add, and from
+    // memory each read would be a round trip
+    const int ld = k + 1;
+    const bool q_lds = 2 * k * ld <= KMAX * RR_LD, l_lds = 2 * k * ld + kk2 <= KMAX * RR_LD;
+    const int qd = q_lds ? ld : k;  // Q's row stride (padded in LDS: no bank conflicts by column)
+    double* Q = q_lds ? C + k * ld : P.kk + (KK_S0 + 1) * kk2;
+    double* L = l_lds ? C + 2 * k * ld : P.kk + KK_S0 * kk2;
     double* S = P.kk + (KK_S0 + 2) * kk2;  // result
     const double* PT = P.kk + KK_PT * kk2;
     const double* P2 = P.kk + KK_P2 * kk2;
@@ -60,7 +67,7 @@ __global__ __launch_bounds__(RR_NT) void rr_solve_kernel(const Prob* __restrict_
     for (int e = tid; e < kk2; e += RR_NT) {
       const int i = e / k, j = e - i * k;
       const double gt = (i / 16 <= j / 16) ? GT[i * k + j] : GT[j * k + i];
-      C[i * RR_LD + j] = gt + G2[i * k + j];
+      C[i * ld + j] = gt + G2[i * k + j];
       if (i == j) gdiag[i] = gt + G2[i * k + j];
     }
     __syncthreads();
@@ -68,19 +75,21 @@ __global__ __launch_bounds__(RR_NT) void rr_solve_kernel(const Prob* __restrict_
     // column's norm means numerically dependent columns
     for (int c = 0; c < k; ++c) {
       if (tid == 0) {
-        const double v = C[c * RR_LD + c];
+        const double v = C[c * ld + c];
         if (!(v > 64.0 * k * UNIT_ROUNDOFF * gdiag[c]) || !__builtin_isfinite(v)) fail = 1;
-        C[c * RR_LD + c] = sqrt(fmax(v, 0.0));
+        C[c * ld + c] = sqrt(fmax(v, 0.0));
       }
       __syncthreads();
       if (fail) break;
-      const double piv = C[c * RR_LD + c];
-      for (int r = c + 1 + tid; r < k; r += RR_NT) C[r * RR_LD + c] /= piv;
+      const double piv = C[c * ld + c];
+      for (int r = c + 1 + tid; r < k; r += RR_NT) C[r * ld + c] /= piv;
       __syncthreads();
       const int m = k - c - 1;
+      const float invm = 1.0f / (float)max(m, 1);
       for (int e = tid; e < m * m; e += RR_NT) {
-        const int r = c + 1 + e / m, j = c + 1 + e % m;
-        if (j <= r) C[r * RR_LD + j] -= C[r * RR_LD + c] * C[j * RR_LD + c];
+        const int qe = __float2int_rz((e + 0.5f) * invm);
+        const int r = c + 1 + qe, j = c + 1 + (e - qe * m);
+        if (j <= r) C[r * ld + j] -= C[r * ld + c] * C[j * ld + c];
       }
       __syncthreads();
     }
@@ -93,51 +102,53 @@ __global__ __launch_bounds__(RR_NT) void rr_solve_kernel(const Prob* __restrict_
     }
     for (int e = tid; e < kk2; e += RR_NT) {
       const int i = e / k, j = e - i * k;
-      L[e] = j <= i ? C[i * RR_LD + j] : 0.0;
+      L[e] = j <= i ? C[i * ld + j] : 0.0;
     }
     __syncthreads();
     // H = sym(X^T W) into C
     for (int e = tid; e < kk2; e += RR_NT) {
       const int i = e / k, j = e - i * k;
       const double hij = PT[i * k + j] + P2[i * k + j], hji = PT[j * k + i] + P2[j * k + i];
-      C[i * RR_LD + j] = 0.5 * (hij + hji);
+      C[i * ld + j] = 0.5 * (hij + hji);
     }
     __syncthreads();
     // B = L^{-1} H, one column per thread (forward substitution)
     for (int c = tid; c < k; c += RR_NT) {
       for (int r = 0; r < k; ++r) {
-        double b = C[r * RR_LD + c];
-        for (int l = 0; l < r; ++l) b -= L[r * k + l] * C[l * RR_LD + c];
-        C[r * RR_LD + c] = b / L[r * k + r];
+        double b = C[r * ld + c];
+        for (int l = 0; l < r; ++l) b -= L[r * k + l] * C[l * ld + c];
+        C[r * ld + c] = b / L[r * k + r];
       }
     }
     __syncthreads();
     // C = B L^{-T}, one row per thread
     for (int r = tid; r < k; r += RR_NT) {
       for (int j = 0; j < k; ++j) {
-        double v = C[r * RR_LD + j];
-        for (int l = 0; l < j; ++l) v -= C[r * RR_LD + l] * L[j * k + l];
-        C[r * RR_LD + j] = v / L[j * k + j];
+        double v = C[r * ld + j];
+        for (int l = 0; l < j; ++l) v -= C[r * ld + l] * L[j * k + l];
+        C[r * ld + j] = v / L[j * k + j];
       }
     }
     __syncthreads();
     for (int e = tid; e < kk2; e += RR_NT) {
       const int i = e / k, j = e - i * k;
       if (i < j) {
-        const double v = 0.5 * (C[i * RR_LD + j] + C[j * RR_LD + i]);
-        C[i * RR_LD + j] = v;
-        C[j * RR_LD + i] = v;
+        const double v = 0.5 * (C[i * ld + j] + C[j * ld + i]);
+        C[i * ld + j] = v;
+        C[j * ld + i] = v;
       }
-      Q[e] = i == j ? 1.0 : 0.0;
+      Q[i * qd + j] = i == j ? 1.0 : 0.0;
     }
     __syncthreads();
-    // cyclic Jacobi in parallel rounds
+    // cyclic Jacobi in parallel rounds (element index / k by a float
+    // reciprocal: exact for indices below 2^13)
+    const float invk = 1.0f / (float)k;
     const int m = k + (k & 1), npair = m / 2;
     for (int sweep = 0; sweep < RR_SWEEPS; ++sweep) {
       double off = 0.0, dia = 0.0;
       for (int e = tid; e < kk2; e += RR_NT) {
         const int i = e / k, j = e - i * k;
-        const double v = C[i * RR_LD + j];
+        const double v = C[i * ld + j];
         if (i == j)
           dia += v * v;
         else
@@ -153,7 +164,11 @@ __global__ __launch_bounds__(RR_NT) void rr_solve_kernel(const Prob* __restrict_
         }
         __syncthreads();
       }
-      const bool done = !(red[0][0] > 1e-32 * red[1][0]);
+      // converged once the off-diagonal mass is at the rounding floor: every
+      // rotation leaves entries of about u ||C||, so off^2 settles near
+      // k u^2 dia^2 and further sweeps change nothing (a fixed 1e-32 sat below
+      // that floor and always ran every sweep)
+      const bool done = !(red[0][0] > 16.0 * k * UNIT_ROUNDOFF * UNIT_ROUNDOFF * red[1][0]);
       __syncthreads();
       if (done) break;
       for (int r = 0; r < m - 1; ++r) {
@@ -168,9 +183,9 @@ __global__ __launch_bounds__(RR_NT) void rr_solve_kernel(const Prob* __restrict_
           double c = 1.0, s = 0.0;
           const bool valid = b < k;
           if (valid) {
-            const double apq = C[a * RR_LD + b];
+            const double apq = C[a * ld + b];
             if (apq != 0.0) {
-              const double th = (C[b * RR_LD + b] - C[a * RR_LD + a]) / (2.0 * apq);
+              const double th = (C[b * ld + b] - C[a * ld + a]) / (2.0 * apq);
               const double t = fabs(th) > 1e150 ? 0.5 / th
                                                 : (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
               c = 1.0 / sqrt(1.0 + t * t);
@@ -185,28 +200,28 @@ __global__ __launch_bounds__(RR_NT) void rr_solve_kernel(const Prob* __restrict_
         __syncthreads();
         // rows a, b of C: C <- J^T C
         for (int e = tid; e < npair * k; e += RR_NT) {
-          const int q = e / k, j = e - q * k, a = ra[q];
+          const int q = __float2int_rz((e + 0.5f) * invk), j = e - q * k, a = ra[q];
           if (a >= 0) {
             const int b = rb[q];
             const double c = rc[q], s = rs[q];
-            const double x = C[a * RR_LD + j], y = C[b * RR_LD + j];
-            C[a * RR_LD + j] = c * x - s * y;
-            C[b * RR_LD + j] = s * x + c * y;
+            const double x = C[a * ld + j], y = C[b * ld + j];
+            C[a * ld + j] = c * x - s * y;
+            C[b * ld + j] = s * x + c * y;
           }
         }
         __syncthreads();
         // columns a, b of C and of Q: C <- C J, Q <- Q J
         for (int e = tid; e < npair * k; e += RR_NT) {
-          const int q = e / k, j = e - q * k, a = ra[q];
+          const int q = __float2int_rz((e + 0.5f) * invk), j = e - q * k, a = ra[q];
           if (a >= 0) {
             const int b = rb[q];
             const double c = rc[q], s = rs[q];
-            const double x = C[j * RR_LD + a], y = C[j * RR_LD + b];
-            C[j * RR_LD + a] = c * x - s * y;
-            C[j * RR_LD + b] = s * x + c * y;
-            const double u = Q[j * k + a], v = Q[j * k + b];
-            Q[j * k + a] = c * u - s * v;
-            Q[j * k + b] = s * u + c * v;
+            const double x = C[j * ld + a], y = C[j * ld + b];
+            C[j * ld + a] = c * x - s * y;
+            C[j * ld + b] = s * x + c * y;
+            const double u = Q[j * qd + a], v = Q[j * qd + b];
+            Q[j * qd + a] = c * u - s * v;
+            Q[j * qd + b] = s * u + c * v;
           }
         }
         __syncthreads();
@@ -214,30 +229,37 @@ __global__ __launch_bounds__(RR_NT) void rr_solve_kernel(const Prob* __restrict_
     }
     // order: |theta - mu| descending, ties in ascending theta, then index
     for (int j = tid; j < k; j += RR_NT) {
-      const double tj = C[j * RR_LD + j], kj = fabs(tj - P.mu);
+      const double tj = C[j * ld + j], kj = fabs(tj - P.mu);
       int rank = 0;
       for (int i = 0; i < k; ++i) {
-        const double ti = C[i * RR_LD + i], ki = fabs(ti - P.mu);
+        const double ti = C[i * ld + i], ki = fabs(ti - P.mu);
         if (ki > kj || (ki == kj && (ti < tj || (ti == tj && i < j)))) ++rank;
       }
       perm[rank] = j;
     }
     __syncthreads();
+    // the Ritz values, before C's storage takes S (when L is in LDS)
+    for (int j = tid; j < k; j += RR_NT) gdiag[j] = C[j * ld + j];
+    __syncthreads();
+    double* Sw = l_lds ? C : S;  // S is formed in LDS and written out once
     // S = L^{-T} Q(:, perm), one column per thread (back substitution), then
     // the sign that makes z_cc = (X S)_cc <= 0; the Ritz values go to d
     for (int c = tid; c < k; c += RR_NT) {
       const int src = perm[c];
       for (int r = k - 1; r >= 0; --r) {
-        double v = Q[r * k + src];
-        for (int l = r + 1; l < k; ++l) v -= L[l * k + r] * S[l * k + c];
-        S[r * k + c] = v / L[r * k + r];
+        double v = Q[r * qd + src];
+        for (int l = r + 1; l < k; ++l) v -= L[l * k + r] * Sw[l * k + c];
+        Sw[r * k + c] = v / L[r * k + r];
       }
       double z = 0.0;
-      for (int l = 0; l < k; ++l) z += P.x[(int64_t)c * P.ldx + l] * S[l * k + c];
+      for (int l = 0; l < k; ++l) z += P.x[(int64_t)c * P.ldx + l] * Sw[l * k + c];
       if (z > 0.0)
-        for (int l = 0; l < k; ++l) S[l * k + c] = -S[l * k + c];
-      P.vec[VEC_D * k + c] = C[src * RR_LD + src];
+        for (int l = 0; l < k; ++l) Sw[l * k + c] = -Sw[l * k + c];
+      P.vec[VEC_D * k + c] = gdiag[src];
     }
+    __syncthreads();
+    if (l_lds)
+      for (int e = tid; e < kk2; e += RR_NT) S[e] = Sw[e];
     __syncthreads();
     if (tid == 0) ctrl->rr_top = 1;
   }
