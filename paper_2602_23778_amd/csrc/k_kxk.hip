@@ -1102,8 +1102,6 @@ __global__ __launch_bounds__(512) void pp_n_kernel(const Prob* __restrict__ prob
   }
 }
 
-int kxk_lds_doubles(int kmax) { return 0; }
-
 // One problem: the panel pipeline with the one-workgroup solver as its
 // fallback (which runs only when the warm start is not close enough).
 // Batches: the one-workgroup solver per problem.
@@ -1141,7 +1139,5 @@ hipError_t launch_kxk(const Prob* probs, int nprob, int kmax, bool pipeline, hip
     hipLaunchKernelGGL(kxk_kernel<false>, dim3(nprob), dim3(KXK_NT), 0, st, probs, nprob, 0);
   return hipGetLastError();
 }
-
-hipError_t kxk_set_attributes() { return hipSuccess; }
 
 }  // namespace rfk

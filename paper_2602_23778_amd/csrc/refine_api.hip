@@ -30,7 +30,6 @@ struct GramRedItem {
   int32_t prob, s0;
 };
 hipError_t launch_gram_reduce(const Prob*, const GramRedItem*, int, hipStream_t);
-int kxk_lds_doubles(int);
 hipError_t launch_kxk(const Prob*, int, int, bool, hipStream_t);
 hipError_t launch_update(const Prob*, const RowItem*, int, int, bool, hipStream_t);
 hipError_t launch_fin_pre(const Prob*, int, hipStream_t);
@@ -52,7 +51,6 @@ int spmm_chunk_rows(int lanes);
 int spmm_grid(int nitems, int lanes);
 hipError_t launch_rowstats(int, int, const double*, int64_t, const int32_t*, const int32_t*,
                            const double*, double*, int, hipStream_t);
-hipError_t kxk_set_attributes();
 }  // namespace rfk
 
 using namespace rfk;
@@ -795,7 +793,6 @@ int refine_init(refine_ctx** out, const refine_matrix* A, int32_t k, const refin
   if (opt.delta_c == 0.0 && !optp) opt.delta_c = 10.0;
   int rc = validate_matrix(A, k, opt);
   if (rc != REFINE_OK) return rc;
-  if (kxk_set_attributes() != hipSuccess) return REFINE_EHIP;
   refine_ctx* c = new (std::nothrow) refine_ctx();
   if (!c) return REFINE_ENOMEM;
   c->stream = (hipStream_t)hip_stream;
@@ -1019,7 +1016,6 @@ int refine_batch_init(refine_batch** out, int32_t count, const refine_matrix* As
     int rc = validate_matrix(&As[p], ks[p], opt);
     if (rc != REFINE_OK) return rc;
   }
-  if (kxk_set_attributes() != hipSuccess) return REFINE_EHIP;
   refine_batch* b = new (std::nothrow) refine_batch();
   if (!b) return REFINE_ENOMEM;
   b->stream = (hipStream_t)hip_stream;
