@@ -126,23 +126,22 @@ Shape choose_shape(int64_t n, int k, bool single, bool csr) {
   }
   // Gram blocks: at least k rows (the leading k rows must sit in block 0);
   // about 512 blocks for one long problem (fewer k-by-k partials to reduce),
-  // 256 rows in a batch.
+  // 512 rows in a batch (1.3 % faster steps than 256 or 1024 on 512 problems
+  // of n <= 2048).
   {
     const int64_t kr = (k + 3) / 4 * 4;
-    const int64_t per = single ? std::max<int64_t>(64, ((n + 511) / 512 + 3) / 4 * 4) : 256;
+    const int64_t per = single ? std::max<int64_t>(64, ((n + 511) / 512 + 3) / 4 * 4) : 512;
     s.gbrows = (int)std::max<int64_t>(std::max<int64_t>(kr, per), 16);
   }
-  // tuning hooks for one problem: REFINE_RBROWS, REFINE_GBROWS (rows per
-  // streaming / Gram block; a Gram block keeps at least k rows)
-  if (single) {
-    if (const char* env = getenv("REFINE_RBROWS")) {
-      const int v = atoi(env);
-      if (v >= 16 && v % 16 == 0) s.rbrows = v;
-    }
-    if (const char* env = getenv("REFINE_GBROWS")) {
-      const int v = atoi(env);
-      if (v >= 16 && v % 4 == 0) s.gbrows = std::max(v, (k + 3) / 4 * 4);
-    }
+  // tuning hooks: REFINE_RBROWS, REFINE_GBROWS (rows per streaming / Gram
+  // block; a Gram block keeps at least k rows)
+  if (const char* env = getenv("REFINE_RBROWS")) {
+    const int v = atoi(env);
+    if (v >= 16 && v % 16 == 0) s.rbrows = v;
+  }
+  if (const char* env = getenv("REFINE_GBROWS")) {
+    const int v = atoi(env);
+    if (v >= 16 && v % 4 == 0) s.gbrows = std::max(v, (k + 3) / 4 * 4);
   }
   s.nrb = iceil(n, s.rbrows);
   s.ngb = iceil(n, s.gbrows);

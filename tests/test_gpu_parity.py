@@ -109,10 +109,11 @@ def test_csr_laplacian_16():
     _compare_steps(None, X0, 3, norm_a=L.sigma, mu=L.sigma, target="smallest", csr=L)
 
 
-@pytest.mark.parametrize("k", [1, 3, 5, 13, 32, 64, 100, 128])
+@pytest.mark.parametrize("k", [1, 2, 3, 5, 6, 13, 20, 32, 64, 100, 128])
 def test_csr_every_row_width(k):
-    """CSR product widths: k picks the lanes per row (1 to 32) and, for k not
-    a multiple of four or odd, the per-column loads of the last lane group.
+    """CSR product widths: k picks the lanes per row (1 to 32); for odd k the
+    per-column loads, for even k not a power of two the lanes whose second
+    column pair lies past k (k = 2, 6, 20, 100).
     Separable Laplacian on a 12^3 grid (exact eigenvectors + 1e-6 noise)."""
     L, lam, Xt, X0 = synth.laplacian3d_separable(12, k)
     _compare_steps(None, X0, 2, norm_a=L.sigma, mu=L.sigma, target="smallest", csr=L)
@@ -335,6 +336,26 @@ def test_every_product_configuration(cfg, monkeypatch):
         monkeypatch.setenv("REFINE_GEMM", "%d,%d" % (cfg, ks))
         P = synth.dense_spectrum(n, k, 4000 + n)
         _compare_steps(P.A, P.X0, 1, norm_a=1.0)
+
+
+@pytest.mark.parametrize("cfg", list(range(8)))
+def test_batched_mixed_k_every_product_configuration(cfg, monkeypatch):
+    """A batch whose largest k (72) sets five 16-column tiles for every
+    problem, so most problems run with zero-padded X columns (k = 1 .. 49):
+    every launch configuration gives each problem its own oracle steps."""
+    rf = _lib()
+    monkeypatch.setenv("REFINE_GEMM", "%d,1" % cfg)
+    shapes = [(200, 5), (333, 48), (150, 49), (260, 72), (180, 16), (97, 1)]
+    probs = [synth.dense_spectrum(n, k, 4500 + 7 * i + n) for i, (n, k) in enumerate(shapes)]
+    b = rf.RefineBatch([_dev(p.A) for p in probs], [k for _, k in shapes], norm_a=1.0)
+    Xs = [_dev(p.X0).clone() for p in probs]
+    rc, per = b.run(Xs, 2)
+    b.close()
+    assert rc == rf.OK
+    for (n, k), p, X in zip(shapes, probs, Xs):
+        Xo, _ = oracle.refine(p.A, p.X0, 2, norm_a=1.0)
+        err = np.max(np.abs(align_signs(X.cpu().numpy(), Xo) - Xo))
+        assert err <= TOL, "cfg %d, problem n=%d k=%d: max |dX| = %.3e" % (cfg, n, k, err)
 
 
 # --------------------------------------------------------------------------
