@@ -40,7 +40,8 @@ def _spectral(lam, seed):
     return 0.5 * (A + A.T), Q
 
 
-def _steps(rf, A_dev, A_host, X0, steps, *, norm_a, mu_expect=None, X_dev=None, **opts):
+def _steps(rf, A_dev, A_host, X0, steps, *, norm_a, mu_expect=None, X_dev=None, corr_abs=1e-15,
+           **opts):
     ctx = rf.RefineContext(A_dev, X0.shape[1], norm_a=norm_a, **opts)
     mu = ctx.info()["mu"]
     if mu_expect is not None:
@@ -56,7 +57,7 @@ def _steps(rf, A_dev, A_host, X0, steps, *, norm_a, mu_expect=None, X_dev=None, 
         Xo = r.X
         err = _err(X.cpu().numpy(), Xo)
         assert err <= TOL, "step %d: %.3e" % (s, err)
-        assert st.corr_fro == pytest.approx(r.corr_fro, rel=1e-6, abs=1e-15)
+        assert st.corr_fro == pytest.approx(r.corr_fro, rel=1e-6, abs=corr_abs)
     ctx.close()
     return X
 
@@ -161,3 +162,31 @@ def test_a_and_x_inside_wider_buffers(k):
     _steps(rf, A, P.A, P.X0, 3, norm_a=1.0, X_dev=X)
     assert bool(torch.all(Xbuf[:, k:] == 7.0))
     assert bool(torch.all(Abuf[:, n:] == 3.0))
+
+
+@pytest.mark.parametrize("k", [8, 16, 40, 64, 128])
+def test_one_bottom_row(k):
+    """n = k + 1: a single row below the leading k x k block, for the k x k
+    stage in one workgroup (k <= 48) and in the panel pipeline (k = 64, 128),
+    with the statistics before (k <= 32) or after the update."""
+    rf = _lib()
+    n = k + 1
+    P = synth.dense_spectrum(n, k, 400 + k)
+    _steps(rf, _dev(P.A), P.A, P.X0, 2, norm_a=1.0)
+
+
+@pytest.mark.parametrize("k", [8, 40])
+def test_exact_start_is_a_fixed_point(k):
+    """X = Q's columns for the targets: R is rounding noise and the steps
+    move X only by the distance between Q and the eigenvectors of the
+    rounded A (about u / gap), where the oracle moves it.  ||E_L||_F is then
+    rounding noise itself (1e-14 to 1e-12 here), so the two sides' values
+    are held to that level rather than to each other's digits."""
+    rf = _lib()
+    n = 300
+    lam = np.concatenate([np.linspace(0.9, 1.0, k)[::-1], np.linspace(0.0, 0.8, n - k)])
+    A, Q = _spectral(lam, 410 + k)
+    X0 = np.ascontiguousarray(Q[:, :k])
+    X = _steps(rf, _dev(A), A, X0, 2, norm_a=1.0, corr_abs=1e-11)
+    gap = 0.1 / (k - 1)
+    assert float(np.max(np.abs(X.cpu().numpy() - X0))) < 16 * 2.0 ** -53 / gap
