@@ -190,3 +190,36 @@ def test_exact_start_is_a_fixed_point(k):
     X = _steps(rf, _dev(A), A, X0, 2, norm_a=1.0, corr_abs=1e-11)
     gap = 0.1 / (k - 1)
     assert float(np.max(np.abs(X.cpu().numpy() - X0))) < 16 * 2.0 ** -53 / gap
+
+
+@pytest.mark.parametrize("n,k", [(9, 8), (65, 64), (500, 20)])
+def test_split_form_shifted_in_wider_buffers(n, k):
+    """The split form (INT8 slices of A and X, nine each) on the smallest
+    eigenvalues through mu = the Gershgorin upper bound, with A and X inside
+    wider buffers (lda = n + 37, ldx = k + 5) and down to one bottom row,
+    against the oracle's split-mode steps (the same product definition)."""
+    rf = _lib()
+    lam = np.concatenate([np.linspace(0.0, 0.1, k), np.linspace(0.2, 1.0, n - k)])
+    A, Q = _spectral(lam, 420 + n)
+    hi = float(np.max(np.diag(A) + (np.abs(A).sum(1) - np.abs(np.diag(A)))))
+    X0 = synth.fp32_round(Q[:, :k])
+    Abuf = torch.full((n, n + 37), 3.0, dtype=torch.float64, device="cuda")
+    Abuf[:, :n] = _dev(A)
+    Xbuf = torch.full((n, k + 5), 7.0, dtype=torch.float64, device="cuda")
+    Xbuf[:, :k] = _dev(X0)
+    X = Xbuf[:, :k]
+    ctx = rf.RefineContext(Abuf[:, :n], k, norm_a=1.0, target="smallest", precision="split_int8",
+                           slices=9)
+    mu = ctx.info()["mu"]
+    assert mu == pytest.approx(hi, rel=1e-13)
+    Xo = X0
+    for s in range(2):
+        st = ctx.step(X)
+        assert st.status == rf.OK, rf.status_string(st.status)
+        r = oracle.refine_step(A, Xo, mu=mu, norm_a=1.0, split=9)
+        assert r.status == oracle.OK
+        Xo = r.X
+        err = _err(X.cpu().numpy(), Xo)
+        assert err <= TOL, "step %d: %.3e" % (s, err)
+    ctx.close()
+    assert bool(torch.all(Xbuf[:, k:] == 7.0))
