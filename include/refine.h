@@ -9,7 +9,7 @@
  * refinement step (Algorithm 4 with Algorithm 1) computes
  *     W = A X,  d_j = x_j^T w_j / x_j^T x_j,  R = W - X diag(d),
  *     the compact WY factors Y = X - I_{n,k}, T = -Y1^{-T},
- *     V = H^T R,  the correction matrix E_L (line 6 of Algorithm 4),
+ *     V = H^T R,  the correction matrix E_L (correction step of Algorithm 4),
  *     X <- X + H E_L,  and normalises the columns of X.
  * The targets are the k eigenvalues of largest |lambda - mu| (eq. condition,
  * Sec. 5.1 for the shifted variants); mu = 0 is the paper's default.
@@ -60,7 +60,7 @@ typedef struct refine_batch refine_batch;
 
 typedef enum { REFINE_DENSE = 0, REFINE_CSR = 1 } refine_kind;
 
-/* Arithmetic of the product W = A X (line 1 of Algorithm 4).
+/* Arithmetic of the product W = A X (product step of Algorithm 4).
  *   REFINE_FP64: every step in IEEE double (the paper's experiments, Sec. 3.3).
  *   REFINE_SPLIT_INT8: A X by error-free splitting of A and X into INT8
  *     slices with exact INT32 accumulation on the matrix cores, recombined
@@ -75,7 +75,7 @@ typedef enum { REFINE_FP64 = 0, REFINE_SPLIT_INT8 = 1 } refine_precision;
  *   LARGEST:     mu = min_i (a_ii - sum_{j!=i} |a_ij|) (Gershgorin lower bound);
  *   SHIFT:       mu = options.shift, e.g. (||A||_inf + lambda_{k+1})/2 (Sec. 5.1);
  *   SMALLEST_ABS: the k eigenvalues of smallest |lambda| (Sec. 5.2): the method
- *     runs on B = A^2 - alpha I, line 1 of Algorithm 4 as A (A X) by two
+ *     runs on B = A^2 - alpha I, the product step of Algorithm 4 as A (A X) by two
  *     products (A^2 is never formed), with alpha = (||A||^2 + lhat^2)/2, lhat =
  *     options.shift the caller's estimate of the (k+1)-th smallest |lambda|
  *     (alpha = ||A||^2 when options.shift <= 0, which separates the targets
@@ -92,7 +92,7 @@ typedef enum {
   REFINE_TARGET_SMALLEST_ABS = 4
 } refine_target;
 
-/* beta_ij for (near-)equal Rayleigh quotients (line 6 of Algorithm 4):
+/* beta_ij for (near-)equal Rayleigh quotients (correction step of Algorithm 4):
  * -x_i^T x_j / 2, or 0 after Rayleigh-Ritz preprocessing (Sec. 3.4). */
 typedef enum { REFINE_BETA_HALF_GRAM = 0, REFINE_BETA_ZERO = 1 } refine_beta;
 
@@ -206,7 +206,7 @@ int refine_sign_flip(refine_ctx* ctx, double* X, int64_t ldx, int32_t* sigma);
 int refine_destroy(refine_ctx* ctx);
 
 /* Measurement hook for the roofline figures: enqueues `reps` launches of the
- * product W = A X alone (line 1 of Algorithm 4; its cost is the O(nnz(A) k)
+ * product W = A X alone (product step of Algorithm 4; its cost is the O(nnz(A) k)
  * row of Table 1; in split mode the slicing of X, the INT8 products and the
  * K-split sum), in the context's precision and launch configuration, on
  * the context's stream between two HIP events, waits for them and stores the

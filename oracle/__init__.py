@@ -118,7 +118,7 @@ class Csr:
 
 
 def matmul(A, X, dd: bool = False):
-    """Line 1 of Algorithm 4, W = A X (dense ndarray or Csr).  With dd=True
+    """The product step of Algorithm 4, W = A X (dense ndarray or Csr).  With dd=True
     returns (W_hi, W_lo) from the compensated dot product Dot2."""
     lib = _load()
     X = _f64(X)
@@ -155,7 +155,7 @@ def split_digits(M, s: int, by_row: bool):
 
 
 def matmul_split(A, X, s: int):
-    """Line 1 of Algorithm 4 by the split form with s slices per operand: the
+    """The product step of Algorithm 4 by the split form with s slices per operand: the
     products of digit matrices with p + q <= s + 1, combined exactly; returns
     (W_hi, W_lo) with W_hi + W_lo equal to that sum.  A need not be
     symmetric (rows of A are scaled, columns of X)."""

@@ -18,7 +18,7 @@
  * Readings of the paper that this file takes (each is also listed with its
  * reason in the design notes):
  *   - the off-diagonal top block of the correction uses v_ij / (d_j - d_i),
- *     as in eq. (Eoffdiag) and line 6 of Algorithm 4; the sign printed in
+ *     as in eq. (Eoffdiag) and the correction step of Algorithm 4; the sign printed in
  *     eq. (V-def) is inconsistent with eqs. (R) and (S) (a test plants that
  *     sign here, on purpose, to show it diverges);
  *   - a spectral shift mu is applied as the paper's variant does: the method
@@ -58,7 +58,7 @@ static void two_prod(double a, double b, double* p, double* e) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* Line 1 of Algorithm 4: W = A * X.                                         */
+/* The product step of Algorithm 4: W = A * X.                              */
 /* Dense A is row-major n x n with leading dimension lda; X and W are        */
 /* row-major n x k.  For each output entry the products are summed in        */
 /* ascending l; looping l outside j keeps that order while reading rows.     */
@@ -113,8 +113,8 @@ void orc_gemm_dense_dd(int64_t n, int64_t k, const double* A, int64_t lda,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Split form of line 1 of Algorithm 4 (the accelerator direction of        */
-/* Sec. 3.3): the error-free splitting of Ozaki, Ogita, Oishi and Rump      */
+/* Split form of the product step of Algorithm 4 (as Sec. 3.3 suggests for  */
+/* accelerators): the error-free splitting of Ozaki, Ogita, Oishi and Rump  */
 /* (2012) with integer slices, as Ootomo, Ozaki and Yokota (2024) run it on  */
 /* integer matrix units.                                                     */
 /*                                                                           */
@@ -441,7 +441,7 @@ int orc_refine_step(const orc_matrix* M, int64_t k, const double* X,
     goto done;
   }
 
-  /* Line 1: W = A X  (double-double pair when o->dd or split). */
+  /* Product: W = A X  (double-double pair when o->dd or split). */
   const int pair = o->dd || o->split_slices > 0;
   if (o->split_slices > 0) {
     if (M->kind != 0) { rc = ORC_EINVAL; goto done; }
@@ -488,13 +488,13 @@ int orc_refine_step(const orc_matrix* M, int64_t k, const double* X,
       }
   }
 
-  /* Line 2: compact WY factors of X (Algorithm 1). */
+  /* Compact WY factors of X (Algorithm 1). */
   double cond1 = 0.0;
   rc = orc_compact_wy(n, k, X, ldx, Y, T, &cond1);
   if (st) st->cond_y1 = cond1;
   if (rc != ORC_OK) goto done;
 
-  /* Lines 3-4: alpha_j = x_j^T x_j, d_j = x_j^T w_j / alpha_j (eq. Rayleigh). */
+  /* Rayleigh quotients: alpha_j = x_j^T x_j, d_j = x_j^T w_j / alpha_j (eq. Rayleigh). */
   for (int64_t j = 0; j < k; ++j) {
     double sa = 0.0, sd = 0.0;
     for (int64_t i = 0; i < n; ++i) {
@@ -524,7 +524,7 @@ int orc_refine_step(const orc_matrix* M, int64_t k, const double* X,
   /* Line 5, second half: V = H^T R through the WY factors. */
   orc_apply_h(n, k, Y, T, 1, R, k, V);
 
-  /* Line 6: the correction matrix E_L (n x k). */
+  /* Correction step: the correction matrix E_L (n x k). */
   {
     const double delta = o->delta_c * o->norm_a * ORC_U;
     for (int64_t i = 0; i < k; ++i)
@@ -556,7 +556,7 @@ int orc_refine_step(const orc_matrix* M, int64_t k, const double* X,
       }
   }
 
-  /* Line 7: X~ = X + H E_L. */
+  /* Update step: X~ = X + H E_L. */
   orc_apply_h(n, k, Y, T, 0, E, k, HE);
   for (int64_t i = 0; i < n; ++i)
     for (int64_t j = 0; j < k; ++j)

@@ -1,4 +1,4 @@
-// Line 1 of Algorithm 4 for sparse A in CSR form, fused with the first
+// The product step of Algorithm 4 for sparse A in CSR form, fused with the first
 // reduction of the step (eq. Rayleigh): W = A X, and per block the column
 // sums of x_j * w_j and x_j * x_j.
 //

@@ -1,4 +1,4 @@
-// Line 1 of Algorithm 4 for dense A: W = A X on the FP64 matrix cores.
+// The product step of Algorithm 4 for dense A: W = A X on the FP64 matrix cores.
 //
 // Shape: A is n x n (streamed once from HBM), X is n x k with k <= 128, so
 // the product is a tall-skinny GEMM whose work per byte of A is k/4 flop/B

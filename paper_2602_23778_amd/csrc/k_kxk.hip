@@ -11,13 +11,13 @@
 //     computes Z instead.  Both yield Y1^{-1} up to rounding; the 1-norm
 //     condition number of Y1 decides singularity (cond > 1/(n u)).
 //   * C = Y^T R = X^T R - R1 and M = T^T C = -Z C, so that the bottom rows of
-//     V = H^T R are V2 = R2 - X2 M (line 5 of Algorithm 4; the top rows of V
+//     V = H^T R are V2 = R2 - X2 M (the application of H^T in Algorithm 4; the top rows of V
 //     are X^T R).
-//   * E11 per line 6 of Algorithm 4 (eqs. Ediag, Eoffdiag; beta for
+//   * E11 per the correction step of Algorithm 4 (eqs. Ediag, Eoffdiag; beta for
 //     |d_j - d_i| <= delta).
 //   * F = Y^T E_L = X1^T E11 + (X2^T R2 - X2^T X2 M) diag(1/(d - mu)) - E11,
 //     using E21 = V2 diag(1/(d - mu)) without forming it, and N = T F = -Z^T F.
-//   * The new leading rows X1 + E11 - Y1 N (line 7).
+//   * The new leading rows X1 + E11 - Y1 N (the update step).
 // [M | N] and the new leading rows go to the workspace for the update pass.
 //
 // All k-by-k products run on the FP64 matrix cores, 16x16 tiles dealt to the
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(KXK_NT) void kxk_kernel(const Prob* __restrict__ pr
         k, [&](int i, int l) { return Z[i * k + l]; },
         [&](int l, int j) { return (PT[l * k + j] + P2[l * k + j]) - R1[l * k + j]; },
         [&](int i, int j, double v) { Cm[i * 2 * k + j] = -v; });
-    // ---- E11 (line 6 of Algorithm 4) into the E buffer ----
+    // ---- E11 (correction step of Algorithm 4) into the E buffer ----
     // free buffers: Eb, and whichever of Zb / Fb does not hold Z
     double* E1 = Eb;
     double* Fm = (Z == Fb) ? Zb : Fb;
@@ -625,7 +625,7 @@ __global__ __launch_bounds__(KS_NT) void kxk_small_kernel(const Prob* __restrict
       Cm[i * 2 * k + j] = -v;
     });
     __syncthreads();
-    // E11 (line 6 of Algorithm 4) -> B2
+    // E11 (correction step of Algorithm 4) -> B2
     double e1sq = 0.0;
     {
       double pv[KS_EPT], gv[KS_EPT];
@@ -704,7 +704,7 @@ __global__ __launch_bounds__(KS_NT) void kxk_small_kernel(const Prob* __restrict
 // over np = ceil(k/16) workgroups, one per 16-row panel, one wavefront per
 // 16x16 tile of the panel, in four launches:
 //   1. F0 = I - Z0 Y1 with Z0 the previous step's Y1^{-1} (left residual);
-//      C = X^T R - R1; E11 (line 6 of Algorithm 4).
+//      C = X^T R - R1; E11 (correction step of Algorithm 4).
 //   2. Z = (I + F0 + F0^2 + F0^3) Z0, whose left residual is F0^4, so Z is
 //      accepted when ||F0||_F^4 <= 16 k u; M = -Z C; column sums of |Z|.
 //      Otherwise the step's k-by-k work falls back to the one-workgroup

@@ -1,4 +1,4 @@
-// Split form of line 1 of Algorithm 4: W = A X by error-free splitting into
+// Split form of the product step of Algorithm 4: W = A X by error-free splitting into
 // INT8 digit slices with exact INT32 products on the matrix cores (the
 // accelerator direction of Sec. 3.3; Ozaki, Ogita, Oishi and Rump 2012, with
 // integer slices as in Ootomo, Ozaki and Yokota 2024).

@@ -1,4 +1,4 @@
-// Lines 3-7 of Algorithm 4 (and the column normalisation of Sec. 3.3) for one
+// The steps of Algorithm 4 after the product (and the column normalisation of Sec. 3.3) for one
 // or many problems.  The step is written so that no n x n matrix and no
 // explicit H is formed (Sec. 3.2, after Table 1) and so that every pass over
 // the n x k arrays streams them once:

@@ -557,7 +557,7 @@ hipError_t enqueue_product_on(Plan& pl, const Prob* probs, hipStream_t st) {
   return hipSuccess;
 }
 
-// Line 1 of Algorithm 4 for every problem: W = A X, or for the squared
+// The product step of Algorithm 4 for every problem: W = A X, or for the squared
 // variant (Sec. 5.2) W = A (A X) through W1 = A X, with no A^2 formed.
 hipError_t enqueue_product(Plan& pl, hipStream_t st) {
   if (!pl.square) return enqueue_product_on(pl, pl.dprob, st);

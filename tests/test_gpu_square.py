@@ -1,7 +1,7 @@
 """Squared-shift variant for the eigenvectors of smallest |lambda| (Sec. 5.2)
 on the GPU against the oracle, through the C ABI.
 
-The method runs on B = A^2 - alpha I with line 1 of Algorithm 4 as A (A X)
+The method runs on B = A^2 - alpha I with the product step of Algorithm 4 as A (A X)
 (two products; A^2 is never formed) and alpha = (||A||^2 + lhat^2) / 2.  The
 GPU takes the Rayleigh quotient of A^2 as ||A x||^2 / x^T x (the second
 product's input norm), the oracle as x^T (A (A x)) / x^T x; for symmetric A

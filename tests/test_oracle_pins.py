@@ -79,7 +79,7 @@ def test_wy_singular_leading_block_is_reported():
 
 
 # --------------------------------------------------------------------------
-# Line 1: W = A X, plain and double-double
+# The product step: W = A X, plain and double-double
 # --------------------------------------------------------------------------
 def _exact_product(A, X):
     n, k = X.shape
@@ -130,7 +130,7 @@ def test_csr_matmul_matches_dense_library_product():
 
 
 # --------------------------------------------------------------------------
-# Lines 3-7 of Algorithm 4
+# The steps of Algorithm 4 after the product
 # --------------------------------------------------------------------------
 def test_top_block_of_v_is_xt_r():
     """From eqs. (HhatX-block)-(HhatAX-block): the leading k rows of
@@ -147,9 +147,9 @@ def test_top_block_of_v_is_xt_r():
 
 
 def test_correction_structure_and_update():
-    """Line 6 of Alg. 4: e_jj = (1 - x_j^T x_j)/2; for i != j in the top block
+    """Correction step of Alg. 4: e_jj = (1 - x_j^T x_j)/2; for i != j in the top block
     e_ij + e_ji = -x_i^T x_j (the two branches v_ij/(d_j - d_i) and
-    v_ji/(d_i - d_j) combine to that); line 7: X~ - X = H E_L."""
+    v_ji/(d_i - d_j) combine to that); update step: X~ - X = H E_L."""
     n, k = 48, 7
     A, Q = _sym_problem(n, np.linspace(0.05, 1.0, n), 7)
     rng = np.random.default_rng(7)
@@ -333,7 +333,7 @@ def test_forced_failures():
 
 
 def test_beta_branch_for_exact_ties():
-    """Line 6 of Alg. 4: equal Rayleigh quotients take beta_ij = -x_i^T x_j/2
+    """Correction step of Alg. 4: equal Rayleigh quotients take beta_ij = -x_i^T x_j/2
     (or 0 after preprocessing) instead of dividing by d_j - d_i."""
     n, k = 30, 2
     lam = np.concatenate([np.linspace(0.1, 0.5, n - 2), [1.0, 1.0]])
@@ -365,7 +365,7 @@ def test_golden_k1_power_iteration_values():
 
 
 # --------------------------------------------------------------------------
-# Split form of line 1 (Sec. 3.3; Ozaki, Ogita, Oishi and Rump 2012)
+# Split form of the product step (Sec. 3.3; Ozaki, Ogita, Oishi and Rump 2012)
 # --------------------------------------------------------------------------
 def _wide_range_matrix(rows, cols, seed):
     """Entries spanning many binades within each row and column."""
