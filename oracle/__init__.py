@@ -330,7 +330,7 @@ def rayleigh_ritz(A, X, mu: float = 0.0, square: bool = False):
 
 
 def refine(A, X, steps: int, **kw):
-    """Repeated steps (the paper's driver loop); returns (X, [StepResult])."""
+    """Repeated steps (the paper's outer loop); returns (X, [StepResult])."""
     hist = []
     for _ in range(steps):
         r = refine_step(A, X, **kw)

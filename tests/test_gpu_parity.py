@@ -3,7 +3,7 @@
 Every case feeds the same seeded inputs to librefine.so and to the oracle and
 compares the iterates element by element after per-column sign alignment
 (eigenvectors are defined up to sign), together with the step statistics.
-Tolerance: max |X_gpu - X_oracle| <= 1e-13 (the target stated for this work),
+Tolerance: max |X_gpu - X_oracle| <= 1e-13 (the accuracy target of the refined vectors),
 for well-separated spectra where two correct FP64 implementations agree to a
 few ulps of the vector entries (about u / (gap * sqrt(n))).
 """
