@@ -269,28 +269,28 @@ __global__ __launch_bounds__(NT) void spmm_row_kernel(const Prob* __restrict__ p
 // Grid: three resident 256-thread blocks on each of the 256 CUs.
 constexpr int SPMM_GRID = 768;
 
-// Row form's rows per chunk and grid; REFINE_SPMM_CHUNK and REFINE_SPMM_GRID
-// override them (tuning hooks, read once per process).
-static int row_chunk() {
-  static const int v = [] {
-    const char* env = getenv("REFINE_SPMM_CHUNK");
-    const int c = env ? atoi(env) : 0;
-    return (c >= 8 && c <= 1024) ? c : ROW_CHUNK;
-  }();
-  return v;
+// Rows per chunk and grid of either form; REFINE_SPMM_CHUNK and
+// REFINE_SPMM_GRID override them (tuning hooks, read once per process; the
+// vector form's chunk stays within its LDS copy of SPMM_ROWS + 1 row
+// pointers).
+static int env_int(const char* name) {
+  const char* env = getenv(name);
+  return env ? atoi(env) : 0;
 }
-static int row_grid() {
-  static const int v = [] {
-    const char* env = getenv("REFINE_SPMM_GRID");
-    const int g = env ? atoi(env) : 0;
-    return (g >= 64 && g <= 65536) ? g : ROW_GRID;
-  }();
-  return v;
+static int chunk_rows_for(bool row_form) {
+  static const int c = env_int("REFINE_SPMM_CHUNK");
+  if (row_form) return (c >= 8 && c <= 1024) ? c : ROW_CHUNK;
+  return (c >= 8 && c <= SPMM_ROWS) ? c : SPMM_ROWS;
+}
+static int grid_for(bool row_form) {
+  static const int g = env_int("REFINE_SPMM_GRID");
+  if (g >= 64 && g <= 65536) return g;
+  return row_form ? ROW_GRID : SPMM_GRID;
 }
 
-int spmm_chunk_rows(int lanes) { return lanes ? row_chunk() : SPMM_ROWS; }
+int spmm_chunk_rows(int lanes) { return chunk_rows_for(lanes != 0); }
 int spmm_grid(int nitems, int lanes) {
-  const int g = lanes ? row_grid() : SPMM_GRID;
+  const int g = grid_for(lanes != 0);
   return nitems < g ? nitems : g;
 }
 
@@ -317,7 +317,7 @@ hipError_t launch_spmm_row(const Prob* probs, const RowItem* items, int nitems, 
 #define RFK_SPMM_ROW(KV)                                                                         \
   case KV:                                                                                       \
     hipLaunchKernelGGL((spmm_row_kernel<256, L, KV>), dim3(grid), dim3(256), 0, st, probs, items, \
-                       nitems, row_chunk());                                                     \
+                       nitems, chunk_rows_for(true));                                            \
     break;
     RFK_SPMM_ROW(1) RFK_SPMM_ROW(2) RFK_SPMM_ROW(3) RFK_SPMM_ROW(4)
     RFK_SPMM_ROW(5) RFK_SPMM_ROW(6) RFK_SPMM_ROW(7) RFK_SPMM_ROW(8)
@@ -342,7 +342,7 @@ hipError_t launch_spmm(const Prob* probs, const RowItem* items, int nitems, int 
 #define RFK_SPMM(GV)                                                                            \
   case GV:                                                                                      \
     hipLaunchKernelGGL((spmm_vec_kernel<256, GV>), dim3(grid), dim3(256), 0, st, probs, items, \
-                       nitems, SPMM_ROWS);                                                      \
+                       nitems, chunk_rows_for(false));                                          \
     break;
     RFK_SPMM(1) RFK_SPMM(2) RFK_SPMM(4) RFK_SPMM(8) RFK_SPMM(16) RFK_SPMM(32)
 #undef RFK_SPMM
