@@ -103,7 +103,7 @@ def _traffic_for(n, k):
 
 
 def _time_rayleigh_ritz(ctx, X0, torch, reps=3):
-    """Milliseconds of one Rayleigh-Ritz preprocessing call (Sec. 4) on a copy
+    """Milliseconds of one Rayleigh-Ritz preprocessing call (Sec. 3.4) on a copy
     of the start block, host-synchronised (the call reads its status back)."""
     best = None
     for _ in range(reps):

@@ -46,7 +46,7 @@ extern "C" {
 #define REFINE_ENOMEM (-2)       /* device or host allocation failed */
 #define REFINE_EHIP (-3)         /* a HIP runtime call failed */
 #define REFINE_EWY_SINGULAR (-4) /* Y1 = X(1:k,:) - I_k singular or cond_1 > 1/(n u)
-                                    (Algorithm 1 needs Y1 nonsingular, Sec. 3.1);
+                                    (Algorithm 1 needs Y1 nonsingular, Sec. 3.1.1);
                                     X is unchanged: refine_sign_flip, then step again */
 #define REFINE_EDIVERGED (-5)    /* ||E_L||_F >= 1 (the Neumann expansion of
                                     eq. Neumann needs ||E|| < 1), or ||E_L||_F grew
@@ -61,12 +61,12 @@ typedef struct refine_batch refine_batch;
 typedef enum { REFINE_DENSE = 0, REFINE_CSR = 1 } refine_kind;
 
 /* Arithmetic of the product W = A X (product step of Algorithm 4).
- *   REFINE_FP64: every step in IEEE double (the paper's experiments, Sec. 3.3).
+ *   REFINE_FP64: every step in IEEE double (the paper's experiments, Sec. 3.1.3).
  *   REFINE_SPLIT_INT8: A X by error-free splitting of A and X into INT8
  *     slices with exact INT32 accumulation on the matrix cores, recombined
  *     into a double-double W; the residual R = W - X diag(d) is then formed
  *     with an exact product, the rest of the step in double (the
- *     mixed-precision direction of Sec. 3.3).  Dense only. */
+ *     mixed-precision direction of Sec. 3.1.3).  Dense only. */
 typedef enum { REFINE_FP64 = 0, REFINE_SPLIT_INT8 = 1 } refine_precision;
 
 /* Which eigenpairs are targeted (eq. condition and Sec. 5.1):
@@ -96,7 +96,7 @@ typedef enum {
  * -x_i^T x_j / 2, or 0 after Rayleigh-Ritz preprocessing (Sec. 3.4). */
 typedef enum { REFINE_BETA_HALF_GRAM = 0, REFINE_BETA_ZERO = 1 } refine_beta;
 
-/* Stopping rules of Sec. 3.3: a fixed number of steps, ||E_L||_F <= tol,
+/* Stopping rules of Sec. 3.1.3: a fixed number of steps, ||E_L||_F <= tol,
  * or ||A X - X D||_F / ||A|| <= tol.  The test is made after each step; the
  * statistics describe the iterate that entered that step. */
 typedef enum {
@@ -121,10 +121,10 @@ typedef struct {
   refine_target target;
   double shift;            /* mu for REFINE_TARGET_SHIFT; the estimate lhat for
                               REFINE_TARGET_SMALLEST_ABS */
-  double delta_c;          /* delta = delta_c * ||A|| * 2^-53; the paper uses 10 (Sec. 3.3) */
+  double delta_c;          /* delta = delta_c * ||A|| * 2^-53; the paper uses 10 (Sec. 3.1.3) */
   double norm_a;           /* ||A|| for delta and the residual statistic; <= 0: ||A||_inf */
   refine_beta beta;
-  int32_t normalize;       /* 1: normalise columns after each update (Sec. 3.3) */
+  int32_t normalize;       /* 1: normalise columns after each update (Sec. 3.1.3) */
   int32_t slices;          /* split mode: INT8 digit slices per operand, 7..10;
                               0 = 9 (45 slice products; W then carries about
                               2^-60 of the row and column scales, below the
@@ -173,7 +173,7 @@ int refine_run(refine_ctx* ctx, double* X, int64_t ldx, int32_t max_iters,
 int refine_get_info(const refine_ctx* ctx, double* mu, double* norm_inf,
                     double* norm_used, double* delta);
 
-/* Rayleigh-Ritz preprocessing for clustered targets (Sec. 4, handling
+/* Rayleigh-Ritz preprocessing for clustered targets (Sec. 3.4, handling
  * clustered eigenvalues): solves the k x k symmetric-definite problem
  * (X^T A X) S = (X^T X) S Theta and overwrites X (device, n x k, ld ldx >= k,
  * the caller's) with X S, so that X^T X = I and X^T A X = Theta to rounding.
@@ -187,7 +187,7 @@ int refine_get_info(const refine_ctx* ctx, double* mu, double* norm_inf,
  * or an argument or HIP error.  Synchronises with the host once. */
 int refine_rayleigh_ritz(refine_ctx* ctx, double* X, int64_t ldx);
 
-/* One-time column sign flip X <- X Sigma (Sec. 3.1), for an X on which the
+/* One-time column sign flip X <- X Sigma (Sec. 3.1.1), for an X on which the
  * step reports REFINE_EWY_SINGULAR.  Sigma = diag(sigma) is the sign matrix
  * of the modified LU factorisation of X (Algorithm 2: sigma_j = -sign(q_jj)
  * of the diagonal entry at elimination step j, sign(0) = +1), which depends
@@ -230,7 +230,7 @@ int refine_batch_run(refine_batch* b, double* const* Xs, const int64_t* ldxs,
                      int32_t iters, refine_stats* per_problem);
 
 /* Rayleigh-Ritz preprocessing of every problem of a batch, as
- * refine_rayleigh_ritz (Sec. 4, clustered eigenvalues): Xs[p] (device,
+ * refine_rayleigh_ritz (Sec. 3.4, clustered eigenvalues): Xs[p] (device,
  * n_p x k_p, ld ldxs[p], NULL ldxs meaning ld = k_p) is overwritten with its
  * Ritz basis and the next applied step of that problem takes the leading
  * block of E_L as zero.  status (count entries) may be NULL; it receives each

@@ -141,7 +141,7 @@ def matmul(A, X, dd: bool = False):
 
 
 def split_digits(M, s: int, by_row: bool):
-    """Slicing of the split form (Sec. 3.3; Ozaki et al. 2012): returns
+    """Slicing of the split form (Sec. 3.1.3; Ozaki et al. 2012): returns
     (D, E) with D of shape (s, rows, cols), int8 digits in [-64, 64], and E
     the per-row (by_row) or per-column power-of-two exponents, such that
     M = 2^(E-6) sum_p D_p 2^(-7(p-1)) + r with |r| <= 2^(E-7s)."""
@@ -214,7 +214,7 @@ def compact_wy_lu(Q):
 
 
 def sign_flip(X):
-    """The one-time transformation X <- X Sigma of Sec. 3.1 (Sigma from the
+    """The one-time transformation X <- X Sigma of Sec. 3.1.1 (Sigma from the
     modified LU), after which Algorithm 1 applies.  Returns (X Sigma, sigma)."""
     _, _, sigma = modified_lu(X)
     return _f64(X) * sigma, sigma
@@ -263,7 +263,7 @@ def refine_step(A, X, *, mu: float = 0.0, norm_a: float | None = None,
     split: line 1 by the split form with that many slices (dense A), its
     pair (W_hi, W_lo) then used like the double-double one.
     rr_top: X is a Rayleigh-Ritz basis (the output of rayleigh_ritz); the
-    leading k x k block of E_L is then zero (Sec. 4, clustered eigenvalues).
+    leading k x k block of E_L is then zero (Sec. 3.4, clustered eigenvalues).
     square: the method runs on B = A^2 - mu I (Sec. 5.2, eigenvectors of the
     smallest |lambda|), line 1 as A (A X); norm_a then stands for ||B||.
     plant_printed_sign exists only so that a test can show that the sign
@@ -298,7 +298,7 @@ def refine_step(A, X, *, mu: float = 0.0, norm_a: float | None = None,
 
 
 def rayleigh_ritz(A, X, mu: float = 0.0, square: bool = False):
-    """Rayleigh-Ritz preprocessing on span(X) (Sec. 4, clustered eigenvalues):
+    """Rayleigh-Ritz preprocessing on span(X) (Sec. 3.4, clustered eigenvalues):
     the symmetric-definite k x k problem (X^T A X) S = (X^T X) S Theta is
     solved by a library eigensolver (the step's one library primitive; A X is
     the oracle's own product), and Z = X S has Z^T Z = I and Z^T A Z = Theta.

@@ -113,7 +113,7 @@ void orc_gemm_dense_dd(int64_t n, int64_t k, const double* A, int64_t lda,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Split form of the product step of Algorithm 4 (as Sec. 3.3 suggests for  */
+/* Split form of the product step of Algorithm 4 (as Sec. 3.1.3 suggests for  */
 /* accelerators): the error-free splitting of Ozaki, Ogita, Oishi and Rump  */
 /* (2012) with integer slices, as Ootomo, Ozaki and Yokota (2024) run it on  */
 /* integer matrix units.                                                     */
@@ -344,7 +344,7 @@ int orc_compact_wy(int64_t n, int64_t k, const double* X, int64_t ldx,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Application of H = I - Y T Y^T without forming it (Sec. 3, after Table 1):*/
+/* Application of H = I - Y T Y^T without forming it (Sec. 3.1.2, after Table 1):*/
 /*   H B   = B - Y (T   (Y^T B)),                                            */
 /*   H^T B = B - Y (T^T (Y^T B)).                                            */
 /* B and out are n x m row-major (ld m); trans != 0 selects H^T.             */
@@ -401,7 +401,7 @@ typedef struct {
   int32_t plant_printed_sign;    /* 1: use the sign printed in eq. (V-def) */
   int32_t split_slices;  /* > 0: W by the split form with that many slices
                             (dense only), kept as a pair like dd */
-  int32_t rr_zero_top;   /* 1: X is a Rayleigh-Ritz basis (Sec. 4, clustered
+  int32_t rr_zero_top;   /* 1: X is a Rayleigh-Ritz basis (Sec. 3.4, clustered
                             eigenvalues): the leading k x k block of E_L is
                             zero, so no d_j - d_i denominator is formed */
   int32_t square;        /* 1: the method runs on B = A^2 - mu I (Sec. 5.2, the
@@ -531,7 +531,7 @@ int orc_refine_step(const orc_matrix* M, int64_t k, const double* X,
       for (int64_t j = 0; j < k; ++j) {
         double e;
         if (o->rr_zero_top) {
-          e = 0.0;                                            /* Sec. 4 (clusters) */
+          e = 0.0;                                            /* Sec. 3.4 (clusters) */
         } else if (i == j) {
           e = (1.0 - alpha[i]) / 2.0;                         /* eq. Ediag */
         } else if (fabs(d[j] - d[i]) <= delta) {

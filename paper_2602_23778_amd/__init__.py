@@ -304,7 +304,7 @@ class RefineContext:
         return Stats(st.corr_fro, st.resid_rel, st.iters, rc)
 
     def rayleigh_ritz(self, X: torch.Tensor) -> None:
-        """Rayleigh-Ritz preprocessing of X in place (Sec. 4, clustered
+        """Rayleigh-Ritz preprocessing of X in place (Sec. 3.4, clustered
         eigenvalues); the next applied step takes the leading block of E_L as
         zero.  Raises RefineError (ERANK when X^T X is not positive definite)."""
         self._check_x(X)
@@ -313,7 +313,7 @@ class RefineContext:
             raise RefineError(rc, "refine_rayleigh_ritz")
 
     def sign_flip(self, X: torch.Tensor) -> list:
-        """One-time column sign flip X <- X Sigma in place (Sec. 3.1, Sigma of
+        """One-time column sign flip X <- X Sigma in place (Sec. 3.1.1, Sigma of
         the modified LU, Algorithm 2), for an X whose compact WY factor is
         singular; returns sigma as a list of +1 / -1."""
         self._check_x(X)
@@ -402,7 +402,7 @@ class RefineBatch:
         return rc, [Stats(p.corr_fro, p.resid_rel, p.iters, p.status) for p in per]
 
     def rayleigh_ritz(self, Xs):
-        """Rayleigh-Ritz preprocessing of every problem in place (Sec. 4);
+        """Rayleigh-Ritz preprocessing of every problem in place (Sec. 3.4);
         returns (status, per-problem statuses)."""
         n = len(self._As)
         ptrs = (ctypes.c_void_p * n)(*[X.data_ptr() for X in Xs])
@@ -412,7 +412,7 @@ class RefineBatch:
         return rc, list(st)
 
     def sign_flip(self, Xs):
-        """Column sign flip X <- X Sigma of every problem in place (Sec. 3.1);
+        """Column sign flip X <- X Sigma of every problem in place (Sec. 3.1.1);
         returns (status, per-problem statuses)."""
         n = len(self._As)
         ptrs = (ctypes.c_void_p * n)(*[X.data_ptr() for X in Xs])

@@ -1,4 +1,4 @@
-// One-time column sign flip X <- X Sigma of Sec. 3.1, for an X whose leading
+// One-time column sign flip X <- X Sigma of Sec. 3.1.1, for an X whose leading
 // block X1 - I is singular (or too ill-conditioned) for the compact WY form of
 // Algorithm 1.  Sigma = diag(sigma) comes from the modified LU factorisation of
 // Algorithm 2: at column j the sign sigma_j = -sign(q_jj) of the current

@@ -310,7 +310,7 @@ __global__ __launch_bounds__(KXK_NT) void kxk_kernel(const Prob* __restrict__ pr
       const int i = e / k, j = e - i * k;
       double v;
       if (rr_top) {
-        v = 0.0;  // X is a Rayleigh-Ritz basis (Sec. 4, clustered eigenvalues)
+        v = 0.0;  // X is a Rayleigh-Ritz basis (Sec. 3.4, clustered eigenvalues)
       } else if (i == j) {
         v = (1.0 - alpha[i]) * 0.5;
       } else if (fabs(d[j] - d[i]) <= delta) {
@@ -643,7 +643,7 @@ __global__ __launch_bounds__(KS_NT) void kxk_small_kernel(const Prob* __restrict
           const int i = e / k, j = e - i * k;
           double v;
           if (ctrl->rr_top)
-            v = 0.0;  // X is a Rayleigh-Ritz basis (Sec. 4, clustered eigenvalues)
+            v = 0.0;  // X is a Rayleigh-Ritz basis (Sec. 3.4, clustered eigenvalues)
           else if (i == j)
             v = (1.0 - alpha[i]) * 0.5;
           else if (fabs(d[j] - d[i]) <= delta)
@@ -865,7 +865,7 @@ __global__ __launch_bounds__(512) void pp_res_kernel(const Prob* __restrict__ pr
       *gst(Cb + e) = v1 - vr1[r];
       double ev;
       if (ctrl->rr_top)
-        ev = 0.0;  // X is a Rayleigh-Ritz basis (Sec. 4, clustered eigenvalues)
+        ev = 0.0;  // X is a Rayleigh-Ritz basis (Sec. 3.4, clustered eigenvalues)
       else if (i == j)
         ev = (1.0 - ai[r]) * 0.5;
       else if (fabs(dj - di[r]) <= P.delta)

@@ -1,4 +1,4 @@
-// Rayleigh-Ritz preprocessing for clustered targets (Sec. 4, handling
+// Rayleigh-Ritz preprocessing for clustered targets (Sec. 3.4, handling
 // clustered eigenvalues): on span(X) solve (X^T A X) S = (X^T X) S Theta, set
 // X <- X S (then X^T X = I and X^T A X = Theta), and arm the next step to take
 // the leading k x k block of E_L as zero, so that no d_j - d_i denominator

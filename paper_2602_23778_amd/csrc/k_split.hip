@@ -1,6 +1,6 @@
 // Split form of the product step of Algorithm 4: W = A X by error-free splitting into
 // INT8 digit slices with exact INT32 products on the matrix cores (the
-// accelerator direction of Sec. 3.3; Ozaki, Ogita, Oishi and Rump 2012, with
+// accelerator direction of Sec. 3.1.3; Ozaki, Ogita, Oishi and Rump 2012, with
 // integer slices as in Ootomo, Ozaki and Yokota 2024).
 //
 // Slicing.  Row i of A gets the scale 2^E_i, column j of X the scale 2^F_j,

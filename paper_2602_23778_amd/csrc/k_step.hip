@@ -1,6 +1,6 @@
-// The steps of Algorithm 4 after the product (and the column normalisation of Sec. 3.3) for one
+// The steps of Algorithm 4 after the product (and the column normalisation of Sec. 3.1.3) for one
 // or many problems.  The step is written so that no n x n matrix and no
-// explicit H is formed (Sec. 3.2, after Table 1) and so that every pass over
+// explicit H is formed (Sec. 3.1.2, after Table 1) and so that every pass over
 // the n x k arrays streams them once:
 //
 //   pass 1  (products) the product kernels write the column sums of x_j * w_j

@@ -1,5 +1,5 @@
 // Split form of the dense product W = A X (product step of Algorithm 4, computed
-// the accelerator way that Sec. 3.3 points to): error-free splitting of A and
+// the accelerator way that Sec. 3.1.3 points to): error-free splitting of A and
 // X into INT8 digit slices (Ozaki, Ogita, Oishi and Rump 2012, with integer
 // slices as in Ootomo, Ozaki and Yokota 2024), exact INT32 products on the
 // matrix cores, and a double-double result (Prob::w, Prob::wlo).

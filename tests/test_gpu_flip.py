@@ -1,4 +1,4 @@
-"""One-time column sign flip X <- X Sigma (Sec. 3.1; Sigma of the modified LU,
+"""One-time column sign flip X <- X Sigma (Sec. 3.1.1; Sigma of the modified LU,
 Algorithm 2) on the GPU against the oracle, through the C ABI.
 
 Sigma is a sign decision taken in FP64 on both sides with the same operations

@@ -201,7 +201,7 @@ def test_kxk_forms_single_problem(k, pipe, monkeypatch):
 
 
 def test_refine_run_converges_and_counts():
-    """refine_run with the correction-size stopping rule (Sec. 3.3)."""
+    """refine_run with the correction-size stopping rule (Sec. 3.1.3)."""
     rf = _lib()
     P = synth.dense_well_separated(256, 8)
     ctx = rf.RefineContext(_dev(P.A), 8, norm_a=P.norm_a)
@@ -259,7 +259,7 @@ def test_diverged_step_is_rejected_and_x_unchanged(k):
 
 @pytest.mark.parametrize("k", [8, 40])
 def test_normalization_off_matches_oracle(k):
-    """normalize = 0 (Sec. 3.3 makes normalisation a choice): columns 0.1 %
+    """normalize = 0 (Sec. 3.1.3 makes normalisation a choice): columns 0.1 %
     longer than unit length stay unnormalised, as in the oracle."""
     P = synth.dense_spectrum(300, k, 9200 + k)
     X0 = P.X0 * 1.001

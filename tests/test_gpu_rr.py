@@ -1,4 +1,4 @@
-"""Rayleigh-Ritz preprocessing (Sec. 4, clustered eigenvalues) on the GPU
+"""Rayleigh-Ritz preprocessing (Sec. 3.4, clustered eigenvalues) on the GPU
 against the oracle, through the C ABI.
 
 On well-separated spectra the Ritz vectors are unique up to sign, and both

@@ -66,7 +66,7 @@ def test_wy_is_orthogonal_for_orthonormal_x():
 
 
 def test_wy_singular_leading_block_is_reported():
-    """Sec. 3.1: Alg. 1 needs a nonsingular Y1; X = I_{n,k} gives Y1 = 0."""
+    """Sec. 3.1.1: Alg. 1 needs a nonsingular Y1; X = I_{n,k} gives Y1 = 0."""
     n, k = 12, 3
     rc, *_ = oracle.compact_wy(np.eye(n)[:, :k])
     assert rc == oracle.SINGULAR
@@ -127,6 +127,52 @@ def test_csr_matmul_matches_dense_library_product():
     Whi, Wlo = oracle.matmul(C, X, dd=True)
     assert np.max(np.abs(Whi - D @ X)) < 1e-13
     assert oracle.norm_inf(C) == pytest.approx(np.max(np.abs(D).sum(1)), rel=1e-15)
+
+
+def _cancelling_csr(n, per_row, k, seed):
+    """A CSR matrix and an X whose row products cancel: each row's last
+    nonzero is chosen so that its products with column 0 of X sum to about
+    the rounding error of the others (magnitudes spread over 2^-12..2^12)."""
+    rng = np.random.default_rng(seed)
+    rp, ci, va = [0], [], []
+    X = rng.standard_normal((n, k)) * np.exp2(rng.integers(-6, 7, (n, k)))
+    for i in range(n):
+        cols = np.sort(rng.choice(n, per_row, replace=False))
+        v = rng.standard_normal(per_row) * np.exp2(rng.integers(-12, 13, per_row))
+        last = cols[-1]
+        v[-1] = -float(np.dot(v[:-1], X[cols[:-1], 0])) / X[last, 0]
+        ci.extend(cols.tolist())
+        va.extend(v.tolist())
+        rp.append(len(ci))
+    return oracle.Csr(n, np.array(rp), np.array(ci), np.array(va)), X
+
+
+def test_csr_dot2_pair_against_exact_rationals():
+    """The CSR double-double product is Dot2 per row (Ogita, Rump and Oishi
+    2005): hi + lo is the compensated sum itself, within (m u)^2 |A||X| of
+    the exact value for a row of m nonzeros, on rows whose products cancel
+    (where the plain sum is off by about u |A||X|, many times more)."""
+    n, m, k = 30, 9, 3
+    C, X = _cancelling_csr(n, m, k, 42)
+    Whi, Wlo = oracle.matmul(C, X, dd=True)
+    W = oracle.matmul(C, X)
+    worst_plain = 0.0
+    for i in range(n):
+        cols = C.col_idx[C.row_ptr[i]:C.row_ptr[i + 1]]
+        vals = C.val[C.row_ptr[i]:C.row_ptr[i + 1]]
+        for j in range(k):
+            e = sum(Fraction(float(a)) * Fraction(float(X[c, j])) for a, c in zip(vals, cols))
+            absax = float(np.sum(np.abs(vals) * np.abs(X[cols, j])))
+            err_dd = abs(Fraction(Whi[i, j]) + Fraction(Wlo[i, j]) - e)
+            assert err_dd <= Fraction((m * U) ** 2 * absax) * Fraction(11, 10), (i, j)
+            # hi is the pair's rounded sum
+            assert Whi[i, j] + Wlo[i, j] == Whi[i, j]
+            err_plain = abs(Fraction(W[i, j]) - e)
+            assert err_plain <= Fraction(m * U * absax)
+            if j == 0:
+                worst_plain = max(worst_plain, float(err_plain) / absax)
+    # the cancelling column really exercises the compensation
+    assert worst_plain > 1e3 * (m * U) ** 2
 
 
 # --------------------------------------------------------------------------
@@ -320,8 +366,37 @@ def test_clustered_pair_needs_accurate_residual():
     assert ed < ef
 
 
+def test_clustered_pair_with_a_literal_shift():
+    """The double-double product with the shift applied literally, W_B =
+    (W_hi + W_lo) - mu X kept as a pair (Sec. 5.1): two clusters of gap 1e-6
+    at the top of the spectrum, targeted through mu = -0.55 below it, so that
+    both the low part of A X (|A x| about 1) and the exact product mu x
+    (|mu x| about 0.55; not a power of two, so fl(mu x) is inexact) decide
+    the residual.  The pair reaches the exact eigenvectors (Jacobi, 40
+    digits) as closely as it does with the shift in the denominators, and far
+    more closely than plain FP64 with the literal shift."""
+    from tests.mp_jacobi import jacobi_eigh
+    n, k = 24, 4
+    lam = np.concatenate([np.linspace(0.05, 0.6, n - k), [0.98, 0.98 + 1e-6, 0.99, 0.99 + 1e-6]])
+    A, Q = _sym_problem(n, lam, 16)
+    mu = -0.55
+    lam_mp, V = jacobi_eigh(A.tolist(), dps=40)
+    order = sorted(range(n), key=lambda i: -float(lam_mp[i]))[:k]
+    Xex = np.array([[float(V[r][c]) for c in order] for r in range(n)])
+    X = synth.fp32_round(Q[:, ::-1][:, :k])
+    Xl, _ = oracle.refine(A, X, 60, mu=mu, norm_a=1.0, dd=True)
+    Xd, _ = oracle.refine(A, X, 60, mu=mu, norm_a=1.0, dd=True, shift_in_denominators=True)
+    Xf, _ = oracle.refine(A, X, 60, mu=mu, norm_a=1.0)
+    el = max_abs_diff_aligned(Xl, Xex)
+    ed = max_abs_diff_aligned(Xd, Xex)
+    ef = max_abs_diff_aligned(Xf, Xex)
+    assert el < 1e-14 and ed < 1e-14
+    assert max_abs_diff_aligned(Xl, Xd) < 1e-14
+    assert ef > 100 * el
+
+
 def test_forced_failures():
-    """Status codes: singular Y1 (Sec. 3.1), non-finite input, invalid sizes."""
+    """Status codes: singular Y1 (Sec. 3.1.1), non-finite input, invalid sizes."""
     n, k = 16, 3
     A, Q = _sym_problem(n, np.linspace(0.1, 1, n), 15)
     r = oracle.refine_step(A, np.eye(n)[:, :k], norm_a=1.0)
@@ -365,7 +440,7 @@ def test_golden_k1_power_iteration_values():
 
 
 # --------------------------------------------------------------------------
-# Split form of the product step (Sec. 3.3; Ozaki, Ogita, Oishi and Rump 2012)
+# Split form of the product step (Sec. 3.1.3; Ozaki, Ogita, Oishi and Rump 2012)
 # --------------------------------------------------------------------------
 def _wide_range_matrix(rows, cols, seed):
     """Entries spanning many binades within each row and column."""
@@ -496,7 +571,7 @@ def test_separable_laplacian_generator_eigenpairs():
 
 
 # --------------------------------------------------------------------------
-# Rayleigh-Ritz preprocessing (Sec. 4, clustered eigenvalues)
+# Rayleigh-Ritz preprocessing (Sec. 3.4, clustered eigenvalues)
 # --------------------------------------------------------------------------
 def test_rayleigh_ritz_on_an_invariant_subspace_returns_its_eigenpairs():
     """X spans an exact invariant subspace (6 eigenvectors mixed by a random
@@ -558,7 +633,7 @@ def test_rr_zero_top_step_keeps_the_bottom_block():
 
 
 # --------------------------------------------------------------------------
-# Modified LU, compact WY from it, and the one-time sign flip (Sec. 3.1)
+# Modified LU, compact WY from it, and the one-time sign flip (Sec. 3.1.1)
 # --------------------------------------------------------------------------
 def _x_with_singular_y1(n, k, seed):
     """Orthonormal columns whose first one is e_1 (so Y1 = X1 - I has a zero
