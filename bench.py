@@ -1,17 +1,19 @@
 """Benchmark of the refinement step (Algorithm 4 with Algorithm 1) on one MI355X.
 
-Default workload: dense, n = 8192, k = 64, A = Q diag(lam) Q^T with Q a
-product of 8192 seeded Householder reflectors, lam log-spaced in [1e-3, 1]
-with the 64 targets separated by a factor 1.05 from the rest, X0 = true
-eigenvectors + N(0, 1e-7^2) noise, orthonormalised.  A step is the whole hot
-path: W = A X, Rayleigh quotients, residual, compact-WY factors, correction
-matrix, WY update and normalisation, replayed as one HIP graph.  `value` is
-the FP64 form's refined eigenvectors per second (k / seconds per step).  The
-split form (INT8 slices on the matrix cores, double-double W) runs on the
-same input and is reported in config.split with its speed ratio.
+Default workload (uniform_top): dense, n = 16384, k = 128, A = Q diag(lam)
+Q^T with Q a product of 16384 seeded Householder reflectors, lam iid U[0,
+0.871) for the rest and 0.872 + 1e-3 j (j = 0..127) for the targets, X0 =
+the true eigenvectors rounded to FP32.  A step is the whole hot path: W = A X,
+Rayleigh quotients, residual, compact-WY factors, correction matrix, WY
+update and normalisation, replayed as one HIP graph.  `value` is the main
+form's refined eigenvectors per second (k / seconds per step); the other form
+(FP64 or split: INT8 slices on the matrix cores, double-double W) runs on the
+same input and is reported in config.split with the speed ratio.  The first
+step of both forms is compared with the double-double oracle step and the
+FP64 oracle step; orthogonality is measured in extended precision.
 
 Other workloads (--workload):
-  uniform_top  dense n = 16384, k = 128, targets 1e-3 apart;
+  logspace     dense n = 8192, k = 64, log-spaced spectrum, gap ratio 1.05;
   laplacian    CSR 3-D Laplacian on a 128^3 grid (separable random diagonal),
                k = 32 smallest through the Gershgorin shift;
   batch        512 dense problems, n ~ U[128, 2048], k ~ U[4, 32], two target
@@ -82,22 +84,72 @@ def _time_steps(ctx, X, steps, warmup, torch):
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / steps
     st_last = ctx.step(X)
+    # every timed step was applied: a step that failed would have stopped the
+    # context, and the later ones would have been no-ops
+    _check_applied(st1.status, 1, st1.iters, "first step")
+    _check_applied(st_last.status, warmup + steps + 2, st_last.iters, "timed steps")
     return sec, st1, st_last, X_first
 
 
-def _traffic_for(n, k):
-    """HBM bytes per launch of the dense FP64 product from the committed
-    counter summary, when it was taken on this workload and kernel source."""
+def _meets(d):
+    """Both accuracy targets met (None when the double-double check did not run)."""
+    e = d.get("err_vs_dd_oracle_first_step")
+    if e is None:
+        return None
+    return bool(e <= 1e-13 and d["orthogonality_last"] <= 1e-14)
+
+
+def _progress(msg):
+    print("bench: %s" % msg, file=sys.stderr, flush=True)
+
+
+def _check_applied(status, want_iters, iters, what):
+    if status != 0 or iters != want_iters:
+        raise RuntimeError("%s: status %d, %d steps applied (expected %d): the timing is void"
+                           % (what, status, iters, want_iters))
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def kernel_source_key(files):
+    """SHA-256 of the named sources under paper_2602_23778_amd/csrc with their
+    comments and blank space removed: it changes when the code of a kernel
+    changes, not when its comments do."""
     import hashlib
-    tpath = os.path.join(ROOT, "profiles", "traffic_gemm_f64_dense_n8192_k64.json")
-    if (n, k) != (8192, 64) or not os.path.exists(tpath):
+    import re
+    h = hashlib.sha256()
+    for name in files:
+        with open(os.path.join(ROOT, "paper_2602_23778_amd", "csrc", name)) as f:
+            src = f.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(("%s\n%s\n" % (name, " ".join(src.split()))).encode())
+    return h.hexdigest()
+
+
+def _traffic_for(kernel_file, n, k):
+    """HBM bytes per launch of the product from the committed counter summary
+    profiles/traffic_<kernel>_n<n>_k<k>.json, when it was taken on this
+    workload and on the present code of the kernel (else None)."""
+    tpath = os.path.join(ROOT, "profiles", "traffic_%s_n%d_k%d.json" % (kernel_file, n, k))
+    if not os.path.exists(tpath):
         return None
     try:
         with open(tpath) as f:
             tj = json.load(f)
-        with open(os.path.join(ROOT, "paper_2602_23778_amd", "csrc", "k_gemm.hip"), "rb") as f:
-            h = hashlib.sha256(f.read()).hexdigest()
-        return tj.get("bytes_per_launch") if tj.get("kernel_source_sha256") == h else None
+        if tj.get("kernel_source_key") != kernel_source_key(tj["sources"]):
+            return None
+        return tj.get("bytes_per_launch")
     except Exception:
         return None
 
@@ -149,6 +201,7 @@ def bench_dense(args, rf, torch, np):
         return None
     sec, st1, st_last, X_first = _time_steps(ctx, X, args.steps, args.warmup, torch)
     value = k / sec
+    _progress("%s form timed: %.4f ms per step" % (main_prec, sec * 1e3))
     # dominant kernel: the product W = A X, timed with HIP events on the
     # context's stream, same launch configuration as inside the step
     ms_prod = ctx.time_product(X0.clone(), args.product_reps)
@@ -158,7 +211,7 @@ def bench_dense(args, rf, torch, np):
     eff = flops / (ms_prod * 1e-3) / 1e12
     if main_prec == "fp64":
         roof = {"bound": "mfma", "achieved": eff, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": eff / FP64_PEAK_TFLOPS, "traffic": _traffic_for(n, k)}
+                "frac": eff / FP64_PEAK_TFLOPS, "traffic": _traffic_for("gemm_f64_dense", n, k)}
     else:
         tops = slices * (slices + 1) / 2 * flops / (ms_prod * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": tops, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
@@ -172,6 +225,7 @@ def bench_dense(args, rf, torch, np):
         octx = rf.RefineContext(A, k, norm_a=P.norm_a, precision=oprec, slices=oslices)
         Xo = X0.clone()
         osec, ost1, ost_last, Xo_first = _time_steps(octx, Xo, args.steps, args.warmup, torch)
+        _progress("%s form timed: %.4f ms per step" % (oprec, osec * 1e3))
         oms = octx.time_product(X0.clone(), args.product_reps)
         octx.close()
         other = {"precision": oprec, "slices": oslices, "eigvecs_per_s": k / osec,
@@ -188,22 +242,32 @@ def bench_dense(args, rf, torch, np):
         import oracle
         A_h = A.cpu().numpy()
         X0_h = X0.cpu().numpy()
+        # FP64 oracle steps from the same start until about 10 s have passed
         ts = time.perf_counter()
-        r = oracle.refine_step(A_h, X0_h, norm_a=P.norm_a)
-        t_cpu = time.perf_counter() - ts
+        reps = 0
+        while reps == 0 or time.perf_counter() - ts < 10.0:
+            r = oracle.refine_step(A_h, X0_h, norm_a=P.norm_a)
+            reps += 1
+        t_cpu = (time.perf_counter() - ts) / reps
+        _progress("FP64 oracle: %d steps, %.2f s each" % (reps, t_cpu))
         g = X_first.cpu().numpy()
         errs["err_vs_fp64_oracle_first_step"] = _aligned_err(g, r.X)
         cpu = {"value": k / t_cpu, "unit": "eigvecs/s", "cores": _cores(), "kind": "oracle",
-               "sample": "one full FP64 oracle step of the same workload (n=%d, k=%d), %.1f s"
-                         % (n, k, t_cpu)}
-        if args.dd_check:
+               "cpu": _cpu_model(),
+               "sample": "%d full FP64 oracle steps of the same workload (n=%d, k=%d), %.2f s each"
+                         % (reps, n, k, t_cpu)}
+        if not args.no_dd_check:
+            _progress("double-double oracle step")
             rd = oracle.refine_step(A_h, X0_h, norm_a=P.norm_a, dd=True)
             errs["err_vs_dd_oracle_first_step"] = _aligned_err(g, rd.X)
             if Xo_first is not None:
                 other["err_vs_dd_oracle_first_step"] = _aligned_err(Xo_first.cpu().numpy(), rd.X)
+            if other is not None:
+                other["err_vs_fp64_oracle_first_step"] = _aligned_err(Xo_first.cpu().numpy(), r.X)
 
     split_block = None
     if other is not None:
+        other["meets_targets"] = _meets(other)
         if main_prec == "fp64":
             split_block = dict(other)
             split_block["speed_ratio_split_over_fp64"] = other["eigvecs_per_s"] / value
@@ -220,6 +284,10 @@ def bench_dense(args, rf, torch, np):
            "rayleigh_ritz_ms": rr_ms,
            "split": split_block}
     cfg.update(errs)
+    # the accuracy targets: max |dX| <= 1e-13 against the double-double oracle
+    # step, orthogonality max |X^T X - I| <= 1e-14 after all steps
+    cfg["targets"] = {"err_vs_dd_oracle": 1e-13, "orthogonality": 1e-14}
+    cfg["meets_targets"] = _meets(cfg)
     return {"value": value, "ms_per_step": sec * 1e3, "unit": "eigvecs/s",
             "dtype": "f64" if main_prec == "fp64" else "i8", "config": cfg, "roofline": roof,
             "cpu_baseline": cpu}
@@ -266,7 +334,7 @@ def bench_laplacian(args, rf, torch, np):
         t_cpu = time.perf_counter() - ts
         cfg["err_vs_fp64_oracle_first_step"] = _aligned_err(X_first.cpu().numpy(), r.X)
         cpu = {"value": k / t_cpu, "unit": "eigvecs/s", "cores": _cores(), "kind": "oracle",
-               "sample": "one full FP64 oracle step of the same workload, %.1f s" % t_cpu}
+               "cpu": _cpu_model(), "sample": "one full FP64 oracle step of the same workload, %.1f s" % t_cpu}
     return {"value": k / sec, "ms_per_step": sec * 1e3, "unit": "eigvecs/s", "dtype": "f64",
             "config": cfg, "roofline": roof, "cpu_baseline": cpu}
 
@@ -314,7 +382,7 @@ def bench_kron(args, rf, torch, np):
         t_cpu = (time.perf_counter() - ts) / reps
         cfg["err_vs_fp64_oracle_first_step"] = _aligned_err(X_first.cpu().numpy(), r.X)
         cpu = {"value": k / t_cpu, "unit": "eigvecs/s", "cores": _cores(), "kind": "oracle",
-               "sample": "%d FP64 oracle steps of the same workload, %.3f s each" % (reps, t_cpu)}
+               "cpu": _cpu_model(), "sample": "%d FP64 oracle steps of the same workload, %.3f s each" % (reps, t_cpu)}
     return {"value": k / sec, "ms_per_step": sec * 1e3, "unit": "eigvecs/s", "dtype": "f64",
             "config": cfg, "roofline": roof, "cpu_baseline": cpu}
 
@@ -356,7 +424,7 @@ def bench_smallest_abs(args, rf, torch, np):
         t_cpu = time.perf_counter() - ts
         cfg["err_vs_fp64_oracle_first_step"] = _aligned_err(X_first.cpu().numpy(), r.X)
         cpu = {"value": k / t_cpu, "unit": "eigvecs/s", "cores": _cores(), "kind": "oracle",
-               "sample": "one full FP64 oracle step of the same workload, %.1f s" % t_cpu}
+               "cpu": _cpu_model(), "sample": "one full FP64 oracle step of the same workload, %.1f s" % t_cpu}
     return {"value": k / sec, "ms_per_step": sec * 1e3, "unit": "eigvecs/s", "dtype": "f64",
             "config": cfg, "roofline": roof, "cpu_baseline": cpu}
 
@@ -386,6 +454,12 @@ def bench_batch(args, rf, torch, np):
             b.run(Xs, steps_per_graph, sync=False)
         torch.cuda.synchronize()
         sec = (time.perf_counter() - t0) / (reps * steps_per_graph)
+        # every timed step of every problem was applied
+        rc2, per = b.run(Xs, 0)
+        for p, st in enumerate(per):
+            _check_applied(st.status, steps_per_graph * (reps + 1), st.iters,
+                           "%s batch, problem %d" % (prec, p))
+        _progress("%s batch timed" % prec)
         ms_prod = b.time_product(args.product_reps)
         Xr = [x.clone() for x in X0s]
         torch.cuda.synchronize()
@@ -429,7 +503,7 @@ def bench_batch(args, rf, torch, np):
         cfg["err_sample"] = "problems 0..%d, 5 steps each, double-double oracle" % (len(sample) - 1)
         kk = sum(ks[p] for p in sample) * steps_per_graph
         cpu = {"value": kk / tcpu, "unit": "eigvecs/s", "cores": _cores(), "kind": "oracle",
-               "sample": "double-double oracle, 5 steps of problems 0..%d (%.1f s)"
+               "cpu": _cpu_model(), "sample": "double-double oracle, 5 steps of problems 0..%d (%.1f s)"
                          % (len(sample) - 1, tcpu)}
     return {"value": ksum / main["sec"], "ms_per_step": main["sec"] * 1e3, "unit": "eigvecs/s",
             "dtype": "f64", "config": cfg, "roofline": roof, "cpu_baseline": cpu}
@@ -440,7 +514,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="logspace",
+    ap.add_argument("--workload", default="uniform_top",
                     choices=["logspace", "uniform_top", "laplacian", "batch", "kron",
                              "smallest_abs"])
     ap.add_argument("--n", type=int, default=0,
@@ -452,8 +526,9 @@ def main() -> int:
     ap.add_argument("--slices", type=int, default=0,
                     help="split slices (default 9; 10 for the clustered batch)")
     ap.add_argument("--no-split", action="store_true", help="skip the split-form comparison")
-    ap.add_argument("--dd-check", action="store_true",
-                    help="dense: also compare the first step with the double-double oracle")
+    ap.add_argument("--no-dd-check", action="store_true",
+                    help="dense: skip the comparison of the first step with the double-double "
+                         "oracle (about a minute of host time at n = 16384)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--product-reps", type=int, default=20)
     ap.add_argument("--product-only", action="store_true",

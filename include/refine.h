@@ -66,8 +66,17 @@ typedef enum { REFINE_DENSE = 0, REFINE_CSR = 1 } refine_kind;
  *     slices with exact INT32 accumulation on the matrix cores, recombined
  *     into a double-double W; the residual R = W - X diag(d) is then formed
  *     with an exact product, the rest of the step in double (the
- *     mixed-precision direction of Sec. 3.1.3).  Dense only. */
-typedef enum { REFINE_FP64 = 0, REFINE_SPLIT_INT8 = 1 } refine_precision;
+ *     mixed-precision direction of Sec. 3.1.3).  Dense only.
+ *   REFINE_SPLIT_FP8: declared and rejected (refine_init returns
+ *     REFINE_EINVAL).  On this hardware FP8 and INT8 matrix products run at
+ *     the same dense rate, and an FP8 (e4m3) slice holds an exact signed digit
+ *     of 4 bits against INT8's 8, so an FP8 split needs about twice the slices
+ *     and four times the slice products of the INT8 one for the same W. */
+typedef enum {
+  REFINE_FP64 = 0,
+  REFINE_SPLIT_INT8 = 1,
+  REFINE_SPLIT_FP8 = 2
+} refine_precision;
 
 /* Which eigenpairs are targeted (eq. condition and Sec. 5.1):
  *   LARGEST_ABS: mu = 0, the k eigenvalues of largest |lambda|;
@@ -156,8 +165,12 @@ int refine_init(refine_ctx** ctx, const refine_matrix* A, int32_t k,
  * error status or a refine_run: a caller that restarts from new values in
  * the same buffer calls refine_run (or passes another buffer) to start a
  * new history.  stats == NULL: the step is only enqueued (no host
- * synchronisation) and errors surface at the next call that reports them;
- * otherwise the stream is synchronised and *stats filled. */
+ * synchronisation).  A step enqueued that way that fails keeps its status in
+ * the context and the steps enqueued after it do nothing; the next call that
+ * reports (refine_step with stats, refine_run, refine_rayleigh_ritz,
+ * refine_sign_flip, refine_time_product, or a step on another X) returns
+ * that status first, without doing its own work, and clears it.  Otherwise
+ * (stats != NULL) the stream is synchronised and *stats filled. */
 int refine_step(refine_ctx* ctx, double* X, int64_t ldx, refine_stats* stats);
 
 /* Up to max_iters steps, stopping early when the rule `stop` meets tol or on
@@ -225,7 +238,9 @@ int refine_batch_init(refine_batch** b, int32_t count, const refine_matrix* As,
                       void* hip_stream);
 
 /* iters steps on all problems (Xs[p]: device n_p x k_p row-major, ld ldxs[p]).
- * per_problem (count entries) may be NULL: no host synchronisation. */
+ * per_problem (count entries) may be NULL: no host synchronisation; a failure
+ * of such a run is returned (first failing problem's status) by the next
+ * batch call that reports, before it does its own work, as for refine_step. */
 int refine_batch_run(refine_batch* b, double* const* Xs, const int64_t* ldxs,
                      int32_t iters, refine_stats* per_problem);
 

@@ -35,7 +35,7 @@ ENONFINITE = -6
 ERANK = -7
 
 DENSE, CSR = 0, 1
-FP64, SPLIT_INT8 = 0, 1
+FP64, SPLIT_INT8, SPLIT_FP8 = 0, 1, 2
 TARGETS = {"largest_abs": 0, "smallest": 1, "largest": 2, "shift": 3, "smallest_abs": 4}
 BETAS = {"half_gram": 0, "zero": 1}
 STOPS = {"iters": 0, "correction": 1, "residual": 2}

@@ -19,6 +19,7 @@
 
 #include "common.h"
 #include "refine.h"
+#include "refine_debug.h"
 #include "split.h"
 
 namespace rfk {
@@ -644,6 +645,7 @@ struct refine_ctx {
   double* cur_x = nullptr;
   int64_t cur_ldx = -1;
   int stop_mode = 0;
+  bool pending = false;     // steps enqueued without statistics since the last report
 };
 
 struct refine_batch {
@@ -655,6 +657,7 @@ struct refine_batch {
   std::vector<double*> cur_x;
   std::vector<int64_t> cur_ldx;
   double* d_xs = nullptr;   // staging: (x, ldx) pairs
+  bool pending = false;     // runs enqueued without statistics since the last report
 };
 
 namespace {
@@ -671,6 +674,7 @@ int validate_matrix(const refine_matrix* A, int32_t k, const refine_options& opt
   } else {
     return REFINE_EINVAL;
   }
+  // REFINE_SPLIT_FP8 is declared but not offered (refine.h states why)
   if (opt.precision != REFINE_FP64 && opt.precision != REFINE_SPLIT_INT8) return REFINE_EINVAL;
   if (opt.precision == REFINE_SPLIT_INT8 &&
       (A->n > SPLIT_NMAX || (opt.slices != 0 && (opt.slices < SPLIT_S_MIN || opt.slices > SPLIT_S_MAX))))
@@ -829,9 +833,33 @@ int refine_init(refine_ctx** out, const refine_matrix* A, int32_t k, const refin
   return REFINE_OK;
 }
 
-static int set_x(refine_ctx* c, double* X, int64_t ldx) {
+// Steps enqueued without statistics leave an error status in the control
+// word, where later steps see it and do nothing.  Every call that resets the
+// control word first reports such a status (and clears it), so that an error
+// surfaces at the next call that reports one instead of being reset away.
+static int take_pending(refine_ctx* c, refine_stats* stats) {
+  if (!c->pending) return REFINE_OK;
+  c->pending = false;
+  std::vector<Ctrl> cs;
+  int rc = read_ctrl(c->plan, c->stream, cs);
+  if (rc != REFINE_OK) return rc;
+  const int st = cs[0].status;
+  if (st == 0) return REFINE_OK;
+  if (stats) {
+    stats->corr_fro = cs[0].corr_fro;
+    stats->resid_rel = cs[0].resid_rel;
+    stats->iters = cs[0].iters;
+    stats->status = st;
+  }
+  if (launch_ctrl_reset(c->plan.dprob, 1, 0, 0.0, c->stream) != hipSuccess) return REFINE_EHIP;
+  return st;
+}
+
+static int set_x(refine_ctx* c, double* X, int64_t ldx, refine_stats* stats = nullptr) {
   if (!X || ldx < c->k) return REFINE_EINVAL;
   if (X != c->cur_x || ldx != c->cur_ldx) {
+    int prc = take_pending(c, stats);
+    if (prc != REFINE_OK) return prc;
     if (launch_set_x(c->plan.dprob, 0, X, ldx, c->stream) != hipSuccess) return REFINE_EHIP;
     if (c->plan.square && launch_set_x(c->plan.dprob1, 0, X, ldx, c->stream) != hipSuccess)
       return REFINE_EHIP;
@@ -848,7 +876,11 @@ int refine_step(refine_ctx* c, double* X, int64_t ldx, refine_stats* stats) {
   int rc = set_x(c, X, ldx);
   if (rc != REFINE_OK) return rc;
   if (hipGraphLaunch(c->plan.exec, c->stream) != hipSuccess) return REFINE_EHIP;
-  if (!stats) return REFINE_OK;
+  if (!stats) {
+    c->pending = true;
+    return REFINE_OK;
+  }
+  c->pending = false;
   std::vector<Ctrl> cs;
   rc = read_ctrl(c->plan, c->stream, cs);
   if (rc != REFINE_OK) return rc;
@@ -868,6 +900,7 @@ int refine_rayleigh_ritz(refine_ctx* c, double* X, int64_t ldx) {
   if (!c) return REFINE_EINVAL;
   int rc = set_x(c, X, ldx);
   if (rc != REFINE_OK) return rc;
+  if ((rc = take_pending(c, nullptr)) != REFINE_OK) return rc;
   Plan& pl = c->plan;
   hipStream_t st = c->stream;
   hipError_t e = launch_ctrl_reset(pl.dprob, 1, 0, 0.0, st);
@@ -893,6 +926,7 @@ int refine_sign_flip(refine_ctx* c, double* X, int64_t ldx, int32_t* sigma) {
   if (!c) return REFINE_EINVAL;
   int rc = set_x(c, X, ldx);
   if (rc != REFINE_OK) return rc;
+  if ((rc = take_pending(c, nullptr)) != REFINE_OK) return rc;
   Plan& pl = c->plan;
   hipStream_t st = c->stream;
   hipError_t e = launch_ctrl_reset(pl.dprob, 1, 0, 0.0, st);
@@ -922,8 +956,9 @@ int refine_run(refine_ctx* c, double* X, int64_t ldx, int32_t max_iters, refine_
   if (!c || max_iters < 0) return REFINE_EINVAL;
   if (stop != REFINE_STOP_ITERS && stop != REFINE_STOP_CORRECTION && stop != REFINE_STOP_RESIDUAL)
     return REFINE_EINVAL;
-  int rc = set_x(c, X, ldx);
+  int rc = set_x(c, X, ldx, stats);
   if (rc != REFINE_OK) return rc;
+  if ((rc = take_pending(c, stats)) != REFINE_OK) return rc;
   if (launch_ctrl_reset(c->plan.dprob, 1, (int)stop, tol, c->stream) != hipSuccess) return REFINE_EHIP;
   std::vector<Ctrl> cs(1);
   int done = 0;
@@ -956,6 +991,7 @@ int refine_time_product(refine_ctx* c, double* X, int64_t ldx, int32_t reps, flo
   if (!c || reps <= 0 || !ms) return REFINE_EINVAL;
   int rc = set_x(c, X, ldx);
   if (rc != REFINE_OK) return rc;
+  if ((rc = take_pending(c, nullptr)) != REFINE_OK) return rc;
   if (launch_ctrl_reset(c->plan.dprob, 1, 0, 0.0, c->stream) != hipSuccess) return REFINE_EHIP;
   hipEvent_t e0, e1;
   RF_CHECK(hipEventCreate(&e0));
@@ -1058,6 +1094,30 @@ int refine_batch_init(refine_batch** out, int32_t count, const refine_matrix* As
   return REFINE_OK;
 }
 
+// As take_pending, for the runs of a batch enqueued without statistics:
+// returns the first failing problem's status (REFINE_OK if none) and fills
+// per (count entries) when given.
+static int take_pending_batch(refine_batch* b, refine_stats* per) {
+  if (!b->pending) return REFINE_OK;
+  b->pending = false;
+  const int np = (int)b->As.size();
+  std::vector<Ctrl> cs;
+  int rc = read_ctrl(b->plan, b->stream, cs);
+  if (rc != REFINE_OK) return rc;
+  int worst = REFINE_OK;
+  for (int p = 0; p < np; ++p)
+    if (cs[p].status != 0 && worst == REFINE_OK) worst = cs[p].status;
+  if (worst == REFINE_OK) return REFINE_OK;
+  for (int p = 0; per && p < np; ++p) {
+    per[p].corr_fro = cs[p].corr_fro;
+    per[p].resid_rel = cs[p].resid_rel;
+    per[p].iters = cs[p].iters;
+    per[p].status = cs[p].status;
+  }
+  if (launch_ctrl_reset(b->plan.dprob, np, 0, 0.0, b->stream) != hipSuccess) return REFINE_EHIP;
+  return worst;
+}
+
 // Binds the problems' iterates (device descriptors rewritten only on change).
 static int bind_batch_x(refine_batch* b, double* const* Xs, const int64_t* ldxs) {
   const int np = (int)b->As.size();
@@ -1068,6 +1128,9 @@ static int bind_batch_x(refine_batch* b, double* const* Xs, const int64_t* ldxs)
     if (Xs[p] != b->cur_x[p] || ld != b->cur_ldx[p]) changed = true;
   }
   if (changed) {
+    // an error of the old iterates is reported before their history is reset
+    int prc = take_pending_batch(b, nullptr);
+    if (prc != REFINE_OK) return prc;
     // descriptors are rewritten in place; wait for queued work first
     if (hipStreamSynchronize(b->stream) != hipSuccess) return REFINE_EHIP;
     for (int p = 0; p < np; ++p) {
@@ -1093,7 +1156,11 @@ int refine_batch_run(refine_batch* b, double* const* Xs, const int64_t* ldxs, in
   int brc = bind_batch_x(b, Xs, ldxs);
   if (brc != REFINE_OK) return brc;
   if (launch_steps(b->plan, iters, b->stream) != hipSuccess) return REFINE_EHIP;
-  if (!per) return REFINE_OK;
+  if (!per) {
+    b->pending = true;
+    return REFINE_OK;
+  }
+  b->pending = false;
   std::vector<Ctrl> cs;
   int rc = read_ctrl(b->plan, b->stream, cs);
   if (rc != REFINE_OK) return rc;
@@ -1120,6 +1187,7 @@ int refine_batch_rayleigh_ritz(refine_batch* b, double* const* Xs, const int64_t
   const int np = (int)b->As.size();
   int rc = bind_batch_x(b, Xs, ldxs);
   if (rc != REFINE_OK) return rc;
+  if ((rc = take_pending_batch(b, nullptr)) != REFINE_OK) return rc;
   Plan& pl = b->plan;
   hipStream_t st = b->stream;
   hipError_t e = launch_ctrl_reset(pl.dprob, np, 0, 0.0, st);
@@ -1148,6 +1216,7 @@ int refine_batch_sign_flip(refine_batch* b, double* const* Xs, const int64_t* ld
   const int np = (int)b->As.size();
   int rc = bind_batch_x(b, Xs, ldxs);
   if (rc != REFINE_OK) return rc;
+  if ((rc = take_pending_batch(b, nullptr)) != REFINE_OK) return rc;
   Plan& pl = b->plan;
   hipStream_t st = b->stream;
   hipError_t e = launch_ctrl_reset(pl.dprob, np, 0, 0.0, st);
@@ -1171,6 +1240,8 @@ int refine_batch_time_product(refine_batch* b, int32_t reps, float* ms) {
   if (!b || reps <= 0 || !ms) return REFINE_EINVAL;
   for (double* x : b->cur_x)
     if (!x) return REFINE_EINVAL;  // no X bound yet
+  int prc = take_pending_batch(b, nullptr);
+  if (prc != REFINE_OK) return prc;
   Plan& pl = b->plan;
   const int np = (int)pl.hprob.size();
   hipEvent_t e0, e1;
@@ -1206,9 +1277,9 @@ int refine_batch_destroy(refine_batch* b) {
 
 }  // extern "C"
 
-// Diagnostic hook (not part of refine.h): device addresses of the workspace
-// of a single-problem context, in the order w, wlo, xn, kk, vec, ctrl, wp,
-// part, gpart.  Used by the tests to inspect intermediate quantities.
+// Diagnostic hook declared in refine_debug.h: device addresses of the
+// workspace of a single-problem context, in the order w, wlo, xn, kk, vec,
+// ctrl, wp, part, gpart.  Used by the tests to inspect intermediate quantities.
 extern "C" int refine_debug_workspace(const refine_ctx* c, void** out, int32_t count) {
   if (!c || !out || count < 1) return REFINE_EINVAL;
   const Prob& P = c->plan.hprob[0];

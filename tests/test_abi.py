@@ -7,11 +7,23 @@ import re
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared():
-    with open(os.path.join(ROOT, "include", "refine.h")) as f:
+def _declared(header="refine.h"):
+    with open(os.path.join(ROOT, "include", header)) as f:
         src = f.read()
     names = set(re.findall(r"^\s*(?:int|void|const char\*)\s+(refine_\w+)\s*\(", src, re.M))
     return names
+
+
+def test_every_header_declares_only_exported_symbols():
+    import glob
+    import paper_2602_23778_amd as rf
+    lib = rf.load_library()
+    headers = sorted(os.path.basename(h) for h in glob.glob(os.path.join(ROOT, "include", "*.h")))
+    assert "refine.h" in headers and "refine_debug.h" in headers
+    for h in headers:
+        for n in _declared(h):
+            assert hasattr(lib, n), (h, n)
+    assert _declared("refine_debug.h") == {"refine_debug_workspace"}
 
 
 def test_header_declares_the_boundary():
@@ -37,6 +49,12 @@ def test_host_only_entry_points():
     assert o.delta_c == 10.0 and o.normalize == 1 and o.precision == rf.FP64
     assert "singular" in rf.refine_status_string(rf.EWY_SINGULAR)
     assert rf.refine_status_string(rf.OK) == "ok"
+    # FP8 slices are declared and rejected on the host (refine.h)
+    o.precision = rf.SPLIT_FP8
+    m0 = rf.refine_matrix()
+    m0.kind, m0.n, m0.a, m0.lda = rf.DENSE, 10, 1, 10
+    assert rf.refine_init(ctypes.c_void_p(), m0, 3, o, None) == rf.EINVAL
+    o.precision = rf.FP64
     # invalid arguments are rejected on the host before any device work
     ctx = ctypes.c_void_p()
     m = rf.refine_matrix()

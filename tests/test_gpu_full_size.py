@@ -7,7 +7,8 @@ the C ABI and compares with the CPU oracle:
 * dense n = 8192, k = 64 and n = 16384, k = 128: one step, every entry, FP64
   form against the FP64 oracle step and the split form against the same
   oracle step (the split product is at least as accurate as FP64, and the
-  two forms agree to a few ulps on these well-separated spectra);
+  two forms agree to a few ulps on these well-separated spectra); n = 8192
+  also over the workload's six steps, with the orthogonality of the result;
 * CSR 3-D Laplacian on a 128^3 grid, k = 32: one step, every entry;
 * CSR Kronecker-banded 53^3 (148,877 rows, 70.7 nonzeros per row), k = 5:
   one step, every entry;
@@ -47,6 +48,12 @@ def _err(g, o):
     return float(np.max(np.abs(align_signs(g, o) - o)))
 
 
+def _orth(X):
+    """max |X^T X - I| in extended precision."""
+    Xl = np.asarray(X, dtype=np.longdouble)
+    return float(np.max(np.abs(Xl.T @ Xl - np.eye(X.shape[1], dtype=np.longdouble))))
+
+
 def _dense_case(P, n, k, slices):
     rf = _lib()
     A_h = P.A.cpu().numpy()
@@ -72,6 +79,42 @@ def test_full_dense_logspace_n8192_k64():
     _say("case: dense log-spaced n=8192 k=64, one step, FP64 and split")
     P = synth.dense_logspace(8192, 64, device="cuda:0", torch_out=True)
     _dense_case(P, 8192, 64, 9)
+
+
+def test_full_dense_logspace_n8192_k64_six_steps():
+    """The log-spaced workload's six steps: both forms against the FP64 oracle
+    after every step, and the orthogonality of the final iterate (measured in
+    extended precision): at most 1e-14 for the split form, and within a few
+    times the oracle's own for the FP64 form."""
+    _say("case: dense log-spaced n=8192 k=64, six steps, FP64 and split")
+    rf = _lib()
+    n, k = 8192, 64
+    P = synth.dense_logspace(n, k, device="cuda:0", torch_out=True)
+    A_h = P.A.cpu().numpy()
+    Xo = P.X0.cpu().numpy()
+    ref = []
+    for _ in range(6):
+        r = oracle.refine_step(A_h, Xo, norm_a=P.norm_a)
+        assert r.status == 0
+        Xo = r.X
+        ref.append((Xo, r.corr_fro))
+    orth_o = _orth(Xo)
+    for prec, s in (("fp64", 0), ("split_int8", 9)):
+        ctx = rf.RefineContext(P.A, k, norm_a=P.norm_a, precision=prec, slices=s)
+        X = P.X0.cuda().contiguous().clone()
+        for step, (Xr, cf) in enumerate(ref):
+            st = ctx.step(X)
+            assert st.status == rf.OK and st.iters == step + 1, rf.status_string(st.status)
+            err = _err(X.cpu().numpy(), Xr)
+            assert err <= TOL, "%s step %d: max |dX| = %.3e" % (prec, step, err)
+        ctx.close()
+        orth = _orth(X.cpu().numpy())
+        _say("%s: six steps max |dX| <= %.1e, orthogonality %.3e (oracle %.3e)"
+             % (prec, TOL, orth, orth_o))
+        if prec == "split_int8":
+            assert orth <= 1e-14
+        else:
+            assert orth <= 4 * orth_o + 1e-15
 
 
 def test_full_dense_uniform_top_n16384_k128():

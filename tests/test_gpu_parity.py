@@ -109,6 +109,15 @@ def test_csr_laplacian_16():
     _compare_steps(None, X0, 3, norm_a=L.sigma, mu=L.sigma, target="smallest", csr=L)
 
 
+def test_csr_laplacian_32_iid_diagonal_k32():
+    """The sparse workload's parity size: the 32^3 Laplacian (n = 32768) with
+    the iid U[0, 1) diagonal, the k = 32 smallest through mu = sigma, from
+    shift-invert Lanczos vectors plus N(0, (1e-6)^2) noise; three steps."""
+    L = synth.laplacian3d(32, seed=synth.SEED_BASE + 4)
+    X0 = synth.laplacian_start(L, 32, seed=5, noise=1e-6, exact=True)
+    _compare_steps(None, X0, 3, norm_a=L.sigma, mu=L.sigma, target="smallest", csr=L)
+
+
 @pytest.mark.parametrize("k", [1, 2, 3, 5, 6, 13, 20, 32, 64, 100, 128])
 def test_csr_every_row_width(k):
     """CSR product widths: k picks the lanes per row (1 to 32); for odd k the
@@ -233,6 +242,43 @@ def test_singular_y1_and_nonfinite_are_reported():
     st = ctx.step(Xn)
     assert st.status == rf.ENONFINITE
     ctx.close()
+
+
+def test_error_of_an_unsynchronised_step_is_reported_not_reset():
+    """A step enqueued without statistics that fails (a NaN in X) keeps its
+    status; the next reporting call returns it instead of resetting it away:
+    refine_run on the same X, refine_time_product, and a batch call after an
+    unsynchronised batch run.  A good start then steps normally again."""
+    rf = _lib()
+    P = synth.dense_spectrum(200, 6, 9300)
+    ctx = rf.RefineContext(_dev(P.A), 6, norm_a=1.0)
+    X = _dev(P.X0).clone()
+    X[7, 3] = float("nan")
+    ctx.step(X, sync=False)
+    ctx.step(X, sync=False)
+    st = ctx.run(X, 3)
+    assert st.status == rf.ENONFINITE
+    ctx.step(X, sync=False)
+    with pytest.raises(rf.RefineError) as ei:
+        ctx.time_product(X, 2)
+    assert ei.value.status == rf.ENONFINITE
+    Xg = _dev(P.X0).clone()
+    st = ctx.run(Xg, 3)
+    assert st.status == rf.OK and st.iters == 3
+    ctx.close()
+    shapes = [(150, 4), (200, 6)]
+    probs = [synth.dense_spectrum(n, k, 9310 + i) for i, (n, k) in enumerate(shapes)]
+    b = rf.RefineBatch([_dev(p.A) for p in probs], [k for _, k in shapes], norm_a=1.0)
+    Xs = [_dev(p.X0).clone() for p in probs]
+    Xs[1][3, 2] = float("nan")
+    b.run(Xs, 2, sync=False)
+    with pytest.raises(rf.RefineError) as ei:
+        b.time_product(2)
+    assert ei.value.status == rf.ENONFINITE
+    Xs[1] = _dev(probs[1].X0).clone()
+    rc, per = b.run(Xs, 2)
+    assert rc == rf.OK and [s.iters for s in per] == [2, 2]
+    b.close()
 
 
 @pytest.mark.parametrize("k", [8, 40])
