@@ -58,7 +58,7 @@ class _Opts(ctypes.Structure):
                 ("shift_in_denominators", ctypes.c_int32),
                 ("plant_printed_sign", ctypes.c_int32),
                 ("split_slices", ctypes.c_int32), ("rr_zero_top", ctypes.c_int32),
-                ("square", ctypes.c_int32)]
+                ("square", ctypes.c_int32), ("crt_moduli", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -87,6 +87,10 @@ def _load():
                                          vp, vp]
         lib.orc_gemm_split.argtypes = [i64, i64, vp, i64, vp, i64, ctypes.c_int32, vp, vp, i64]
         lib.orc_gemm_split.restype = ctypes.c_int
+        lib.orc_crt_bits.argtypes = [ctypes.c_int32, i64, vp, vp]
+        lib.orc_crt_bits.restype = ctypes.c_int
+        lib.orc_gemm_crt.argtypes = [i64, i64, vp, i64, vp, i64, ctypes.c_int32, vp, vp, i64]
+        lib.orc_gemm_crt.restype = ctypes.c_int
         lib.orc_norm_inf_dense.argtypes = [i64, vp, i64]
         lib.orc_norm_inf_dense.restype = dbl
         lib.orc_norm_inf_csr.argtypes = [i64, vp, vp]
@@ -167,6 +171,41 @@ def matmul_split(A, X, s: int):
     rc = lib.orc_gemm_split(n, k, _p(A), A.shape[1], _p(X), k, s, _p(W), _p(Wlo), k)
     if rc != OK:
         raise ValueError("orc_gemm_split: status %d" % rc)
+    return W, Wlo
+
+
+CRT_MODULI_MIN = 8
+CRT_MODULI_MAX = 16
+
+
+def crt_bits(nmod: int, n: int):
+    """Bit budgets (bA, bX) of the modular form (Sec. 3.1.3's accelerator
+    direction; Ozaki scheme II): with L the bit length of the product M of the
+    first nmod moduli 256, 255, 253, ..., bA + bX = L - 3 - ceil(log2 n),
+    bA = ceil and bX = floor of half of it, so that n 2^(bA+bX) < M/2."""
+    lib = _load()
+    a = ctypes.c_int32(0)
+    b = ctypes.c_int32(0)
+    rc = lib.orc_crt_bits(int(nmod), int(n), ctypes.byref(a), ctypes.byref(b))
+    if rc != OK:
+        raise ValueError("orc_crt_bits: status %d" % rc)
+    return a.value, b.value
+
+
+def matmul_crt(A, X, nmod: int):
+    """The product step of Algorithm 4 by the modular form with nmod moduli:
+    A' = rint(A_il 2^(bA - E_i)) (row exponents E), X' = rint(X_lj 2^(bX - F_j))
+    (column exponents F), W = 2^(E_i + F_j - bA - bX) (A'X')_ij with the integer
+    product exact (what the Chinese remainder theorem recovers from the
+    residue products); returns (W_hi, W_lo).  A need not be symmetric."""
+    lib = _load()
+    A, X = _f64(A), _f64(X)
+    n, k = X.shape
+    W = np.empty((n, k))
+    Wlo = np.empty((n, k))
+    rc = lib.orc_gemm_crt(n, k, _p(A), A.shape[1], _p(X), k, int(nmod), _p(W), _p(Wlo), k)
+    if rc != OK:
+        raise ValueError("orc_gemm_crt: status %d" % rc)
     return W, Wlo
 
 
@@ -255,13 +294,14 @@ def refine_step(A, X, *, mu: float = 0.0, norm_a: float | None = None,
                 normalize: bool = True, dd: bool = False,
                 shift_in_denominators: bool = False,
                 plant_printed_sign: bool = False, split: int = 0,
-                rr_top: bool = False, square: bool = False) -> StepResult:
+                rr_top: bool = False, square: bool = False, crt: int = 0) -> StepResult:
     """One step of Algorithm 4 (with Algorithm 1) on A (dense or Csr).
 
     mu: the method runs on A - mu I (Sec. 5.1); norm_a: ||A|| in delta and in
     the residual statistic (default ||A||_inf); dd: line 1 in double-double;
     split: line 1 by the split form with that many slices (dense A), its
-    pair (W_hi, W_lo) then used like the double-double one.
+    pair (W_hi, W_lo) then used like the double-double one; crt: line 1 by
+    the modular form with that many moduli (dense A), used the same way.
     rr_top: X is a Rayleigh-Ritz basis (the output of rayleigh_ritz); the
     leading k x k block of E_L is then zero (Sec. 3.4, clustered eigenvalues).
     square: the method runs on B = A^2 - mu I (Sec. 5.2, eigenvectors of the
@@ -287,7 +327,7 @@ def refine_step(A, X, *, mu: float = 0.0, norm_a: float | None = None,
         m.a, m.lda = _p(A), A.shape[1]
     o = _Opts(mu, delta_c, norm_a, int(beta_zero), int(normalize), int(dd),
               int(shift_in_denominators), int(plant_printed_sign), int(split), int(rr_top),
-              int(square))
+              int(square), int(crt))
     st = _Stats()
     Xout = np.zeros((n, k))
     d = np.zeros(k)

@@ -216,6 +216,125 @@ int orc_gemm_split(int64_t n, int64_t k, const double* A, int64_t lda,
   return ORC_OK;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Modular form of the split product (the accelerator direction of          */
+/* Sec. 3.1.3 by the integer route of Ozaki scheme II: Ozaki, Uchino and     */
+/* Imamura 2025).                                                            */
+/*                                                                           */
+/* Scaling to integers.  Row i of A gets the exponent E_i and column j of X  */
+/* the exponent F_j (the smallest integers with max |entry| < 2^E, 0 for a   */
+/* zero line), and                                                           */
+/*     A'_il = rint(a_il 2^(bA - E_i)),   X'_lj = rint(x_lj 2^(bX - F_j)),   */
+/* integers with |A'| <= 2^bA and |X'| <= 2^bX (each is the rounding of one   */
+/* double, so it is itself a double; the scaling is exact).                  */
+/*                                                                           */
+/* Moduli.  N pairwise coprime moduli, the largest that fit one signed byte  */
+/* as balanced residues: 256, 255, 253, ... (table below); M = m_1 ... m_N,   */
+/* L = the bit length of M.  The bit budget bA + bX = L - 3 - c with          */
+/* c = ceil(log2 n) and bA = ceil, bX = floor of half of it gives             */
+/*     |sum_l A'_il X'_lj| <= n 2^(bA + bX) <= 2^(L-3) < M/2,                 */
+/* so the integer product A'X' is fixed by its residues modulo every m_t:    */
+/* the method forms the N residue products (A' mod m_t)(X' mod m_t) with      */
+/* INT8 operands and exact INT32 sums, and recovers A'X' by the Chinese       */
+/* remainder theorem.  The recovered value is the exact integer product, so   */
+/* this oracle forms that product directly (128-bit integer sums; N <= 16     */
+/* keeps every sum below 2^125) and rounds                                   */
+/*     W_ij = 2^(E_i + F_j - bA - bX) (A'X')_ij                               */
+/* to a double-double pair (hi = the nearest double, lo = the nearest double */
+/* to the rest).                                                             */
+/* ------------------------------------------------------------------------ */
+static const int32_t ORC_CRT_MODULI[16] = {256, 255, 253, 251, 247, 241, 239, 233,
+                                           229, 227, 223, 217, 211, 199, 197, 193};
+#define ORC_CRT_NMIN 8
+#define ORC_CRT_NMAX 16
+
+/* Bit budgets of the scaled operands for N moduli and contraction length n.
+ * M is formed exactly in 32-bit limbs.  Returns ORC_EINVAL when N is out of
+ * range or the budget leaves fewer than one bit per operand. */
+int orc_crt_bits(int32_t nmod, int64_t n, int32_t* bA, int32_t* bX) {
+  if (nmod < ORC_CRT_NMIN || nmod > ORC_CRT_NMAX || n < 1) return ORC_EINVAL;
+  uint32_t limb[8] = {1, 0, 0, 0, 0, 0, 0, 0};
+  for (int t = 0; t < nmod; ++t) {
+    uint64_t carry = 0;
+    for (int w = 0; w < 8; ++w) {
+      uint64_t v = (uint64_t)limb[w] * (uint64_t)ORC_CRT_MODULI[t] + carry;
+      limb[w] = (uint32_t)v;
+      carry = v >> 32;
+    }
+  }
+  int L = 0;
+  for (int w = 7; w >= 0; --w)
+    if (limb[w]) {
+      int b = 32;
+      while (!(limb[w] >> (b - 1))) --b;
+      L = 32 * w + b;
+      break;
+    }
+  int c = 0;
+  while (((int64_t)1 << c) < n) ++c;
+  const int B = L - 3 - c;
+  if (B < 2) return ORC_EINVAL;
+  *bA = (B + 1) / 2;
+  *bX = B / 2;
+  return ORC_OK;
+}
+
+/* Integer images of a rows x cols row-major matrix (leading dimension ld):
+ * Q = rint(m 2^(b - E)) with one exponent per row (by_row) or per column. */
+static void orc_crt_scale(int64_t rows, int64_t cols, const double* M, int64_t ld,
+                          int by_row, int32_t b, int64_t* Q, int32_t* Eexp) {
+  const int64_t nline = by_row ? rows : cols;
+  for (int64_t a = 0; a < nline; ++a) {
+    double mx = 0.0;
+    const int64_t len = by_row ? cols : rows;
+    for (int64_t t = 0; t < len; ++t) {
+      double v = by_row ? M[a * ld + t] : M[t * ld + a];
+      if (fabs(v) > mx) mx = fabs(v);
+    }
+    int e = 0;
+    if (mx > 0.0) frexp(mx, &e);
+    Eexp[a] = e;
+  }
+  for (int64_t i = 0; i < rows; ++i)
+    for (int64_t j = 0; j < cols; ++j) {
+      const int e = Eexp[by_row ? i : j];
+      Q[i * cols + j] = (int64_t)rint(ldexp(M[i * ld + j], b - e));
+    }
+}
+
+/* W = A X by the modular form with N moduli (ORC_CRT_NMIN..ORC_CRT_NMAX).
+ * A is n x n (row-major, lda; rows of A are scaled), X is n x k (ldx,
+ * columns scaled); W and Wlo are n x k (ldw). */
+int orc_gemm_crt(int64_t n, int64_t k, const double* A, int64_t lda,
+                 const double* X, int64_t ldx, int32_t nmod, double* Whi,
+                 double* Wlo, int64_t ldw) {
+  int32_t bA = 0, bX = 0;
+  if (orc_crt_bits(nmod, n, &bA, &bX) != ORC_OK) return ORC_EINVAL;
+  int64_t* QA = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n * n));
+  int64_t* QX = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n * k));
+  int32_t* EA = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t* EX = (int32_t*)malloc(sizeof(int32_t) * (size_t)k);
+  if (!QA || !QX || !EA || !EX) {
+    free(QA); free(QX); free(EA); free(EX);
+    return ORC_ENOMEM;
+  }
+  orc_crt_scale(n, n, A, lda, 1, bA, QA, EA);
+  orc_crt_scale(n, k, X, ldx, 0, bX, QX, EX);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < k; ++j) {
+      __int128 tot = 0;
+      for (int64_t l = 0; l < n; ++l) tot += (__int128)QA[i * n + l] * (__int128)QX[l * k + j];
+      double hi = (double)tot;
+      double lo = (double)(tot - (__int128)hi);
+      const int sc = EA[i] + EX[j] - bA - bX;
+      Whi[i * ldw + j] = ldexp(hi, sc);
+      Wlo[i * ldw + j] = ldexp(lo, sc);
+    }
+  free(QA); free(QX); free(EA); free(EX);
+  return ORC_OK;
+}
+
 /* W = A * X for A in CSR form (row_ptr[n+1], col_idx[nnz], val[nnz]).        */
 void orc_gemm_csr(int64_t n, int64_t k, const int32_t* row_ptr,
                   const int32_t* col_idx, const double* val, const double* X,
@@ -407,6 +526,8 @@ typedef struct {
   int32_t square;        /* 1: the method runs on B = A^2 - mu I (Sec. 5.2, the
                             smallest |lambda|): line 1 forms A (A X), so A^2 is
                             never formed (plain FP64 only) */
+  int32_t crt_moduli;    /* > 0: W by the modular form with that many moduli
+                            (dense only), kept as a pair like dd */
 } orc_opts;
 
 typedef struct {
@@ -441,9 +562,13 @@ int orc_refine_step(const orc_matrix* M, int64_t k, const double* X,
     goto done;
   }
 
-  /* Product: W = A X  (double-double pair when o->dd or split). */
-  const int pair = o->dd || o->split_slices > 0;
-  if (o->split_slices > 0) {
+  /* Product: W = A X  (double-double pair when o->dd, split or modular). */
+  const int pair = o->dd || o->split_slices > 0 || o->crt_moduli > 0;
+  if (o->crt_moduli > 0) {
+    if (M->kind != 0 || o->split_slices > 0) { rc = ORC_EINVAL; goto done; }
+    rc = orc_gemm_crt(n, k, M->a, M->lda, X, ldx, o->crt_moduli, W, Wlo, k);
+    if (rc != ORC_OK) goto done;
+  } else if (o->split_slices > 0) {
     if (M->kind != 0) { rc = ORC_EINVAL; goto done; }
     rc = orc_gemm_split(n, k, M->a, M->lda, X, ldx, o->split_slices, W, Wlo, k);
     if (rc != ORC_OK) goto done;

@@ -551,6 +551,170 @@ def test_split_step_agrees_with_double_double_step():
     assert np.max(np.abs(r_s1.X - r_dd.X)) > 1e-6
 
 
+# --------------------------------------------------------------------------
+# Modular form of the product step (Sec. 3.1.3's accelerator direction by the
+# integer route of Ozaki scheme II)
+# --------------------------------------------------------------------------
+def _greedy_moduli(count):
+    """The largest pairwise coprime integers <= 256, taken greedily from 256
+    down: the definition of the moduli, derived here independently."""
+    ms = []
+    m = 256
+    while len(ms) < count:
+        if all(math.gcd(m, q) == 1 for q in ms):
+            ms.append(m)
+        m -= 1
+    return ms
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 40, 1000, 16384, 65536])
+def test_crt_bit_budget_against_the_exact_moduli_product(n):
+    """bA + bX = L - 3 - ceil(log2 n), L the bit length of M (Python big
+    integers), bA the larger half: then n 2^(bA+bX) < M/2, so the exact
+    integer product is the one value in [-M/2, M/2) with its residues."""
+    for N in range(oracle.CRT_MODULI_MIN, oracle.CRT_MODULI_MAX + 1):
+        M = math.prod(_greedy_moduli(N))
+        bA, bX = oracle.crt_bits(N, n)
+        c = max(0, (n - 1).bit_length())
+        assert bA + bX == M.bit_length() - 3 - c
+        assert bA - bX in (0, 1)
+        assert n * 2 ** (bA + bX) < M // 2
+    with pytest.raises(ValueError):
+        oracle.crt_bits(oracle.CRT_MODULI_MIN - 1, 100)
+    with pytest.raises(ValueError):
+        oracle.crt_bits(oracle.CRT_MODULI_MAX + 1, 100)
+
+
+def _garner_balanced(res, ms):
+    """Balanced mixed-radix digits of the integer with residues `res` modulo
+    `ms` (Garner), evaluated back to an integer: the reconstruction the
+    method uses, written in Python integers."""
+    v = []
+    for t, m in enumerate(ms):
+        P = 1
+        acc = 0
+        for s_ in range(t):
+            acc += v[s_] * P
+            P *= ms[s_]
+        d = ((res[t] - acc) * pow(P, -1, m)) % m
+        if d >= (m + 1) // 2:
+            d -= m
+        v.append(d)
+    x, P = 0, 1
+    for t, m in enumerate(ms):
+        x += v[t] * P
+        P *= m
+    return x
+
+
+def test_crt_reconstruction_recovers_products_within_the_budget():
+    """The reading of the method behind the modular form: with the budget of
+    crt_bits, residue products modulo each m_t (each operand reduced to a
+    balanced residue first) determine the exact integer sum through
+    balanced Garner digits, also at the extremes +-n 2^(bA+bX); with one
+    modulus fewer the same extremes wrap."""
+    rng = np.random.default_rng(5)
+    for N, n in ((8, 17), (12, 64), (16, 300)):
+        ms = _greedy_moduli(N)
+        bA, bX = oracle.crt_bits(N, n)
+        cases = [([2 ** bA] * n, [2 ** bX] * n), ([2 ** bA] * n, [-(2 ** bX)] * n)]
+        for _ in range(5):
+            a = [int(v) for v in rng.integers(-(2 ** 62), 2 ** 62, n)]
+            x = [int(v) for v in rng.integers(-(2 ** 62), 2 ** 62, n)]
+            cases.append(([v >> (62 - bA) for v in a], [v >> (62 - bX) for v in x]))
+        for a, x in cases:
+            exact = sum(p * q for p, q in zip(a, x))
+            def bal(v, m):
+                r = v % m
+                return r - m if r >= (m + 1) // 2 else r
+            res = [sum(bal(p, m) * bal(q, m) for p, q in zip(a, x)) % m for m in ms]
+            assert _garner_balanced(res, ms) == exact
+        a, x = cases[0]
+        exact = sum(p * q for p, q in zip(a, x))
+        short = ms[:-1]
+        res = [sum(p * q for p, q in zip(a, x)) % m for m in short]
+        assert _garner_balanced(res, short) != exact
+
+
+def _short_integer_matrix(rows, cols, bits, seed, by_row):
+    """Integers below 2^bits in magnitude times a power of two per line: the
+    scaled images rint(m 2^(b - E)) are exact when b >= bits + 1."""
+    rng = np.random.default_rng(seed)
+    m = rng.integers(-(2 ** bits) + 1, 2 ** bits, (rows, cols)).astype(np.float64)
+    ex = rng.integers(-20, 20, rows if by_row else cols)
+    scale = np.exp2(ex)
+    return m * (scale[:, None] if by_row else scale[None, :])
+
+
+@pytest.mark.parametrize("N,bits", [(12, 20), (16, 48)])
+def test_crt_product_is_exact_when_nothing_is_truncated(N, bits):
+    """Operands of at most `bits` significant bits per line scale are
+    represented exactly by the scaled integers, so the modular form must
+    return the exact product (Python integers) as its (hi, lo) pair: hi the
+    nearest double, lo the nearest double to the rest.  A is not symmetric,
+    so a transposed operand or a swapped scale fails."""
+    n, k = 40, 6
+    bA, bX = oracle.crt_bits(N, n)
+    assert bX >= bits + 1
+    A = _short_integer_matrix(n, n, bits, 91 + N, True)
+    X = _short_integer_matrix(n, k, bits, 92 + N, False)
+    assert not np.array_equal(A, A.T)
+    hi, lo = oracle.matmul_crt(A, X, N)
+    ex = _exact_product(A, X)
+    for i in range(n):
+        for j in range(k):
+            rest = ex[i][j] - Fraction(float(hi[i, j]))
+            assert Fraction(float(hi[i, j])) == Fraction(float(ex[i][j]))  # nearest double
+            assert Fraction(float(lo[i, j])) == Fraction(float(rest))
+    if bits > 30:
+        assert np.any(lo != 0.0)                     # the pair is needed
+
+
+def test_crt_product_truncation_bound_and_rate():
+    """Full 53-bit operands: the modular form stays within the truncation
+    bound 2^(E_i-bA-1) sum_l |x_lj| + 2^(F_j-bX-1) sum_l |a_il| + n 2^(E_i+F_j-bA-bX-2)
+    (each scaled image is off by at most half a unit) plus the pair's own
+    rounding, and four more moduli (about 31 bits more budget) cut the error
+    by at least 2^12."""
+    n, k = 29, 4
+    A = _wide_range_matrix(n, n, 83)
+    X = _wide_range_matrix(n, k, 84)
+    ex = _exact_product(A, X)
+    _, EA = oracle.split_digits(A, 1, True)
+    _, EX = oracle.split_digits(X, 1, False)
+    worst = {}
+    for N in (8, 12, 16):
+        bA, bX = oracle.crt_bits(N, n)
+        hi, lo = oracle.matmul_crt(A, X, N)
+        w = 0.0
+        for i in range(n):
+            sa = sum(Fraction(abs(float(v))) for v in A[i])
+            for j in range(k):
+                sx = sum(Fraction(abs(float(v))) for v in X[:, j])
+                ua = Fraction(2) ** (int(EA[i]) - bA - 1)
+                ux = Fraction(2) ** (int(EX[j]) - bX - 1)
+                bound = ua * sx + ux * sa + n * ua * ux + abs(ex[i][j]) * Fraction(2) ** -104
+                err = abs(Fraction(float(hi[i, j])) + Fraction(float(lo[i, j])) - ex[i][j])
+                assert err <= bound
+                w = max(w, float(err / Fraction(2) ** (int(EA[i]) + int(EX[j]))))
+        worst[N] = w
+    assert worst[12] < worst[8] * 2.0 ** -12
+    assert worst[16] < worst[12] * 2.0 ** -12
+
+
+def test_crt_step_agrees_with_double_double_step():
+    """A step whose line 1 comes from the modular form with 16 moduli (about
+    56 bits per operand at n = 256) matches the Dot2 step to about u; with 8
+    moduli (about 24 bits) it must not."""
+    P = synth.dense_well_separated(256, 8)
+    r_dd = oracle.refine_step(P.A, P.X0, norm_a=P.norm_a, dd=True)
+    r_16 = oracle.refine_step(P.A, P.X0, norm_a=P.norm_a, crt=16)
+    r_8 = oracle.refine_step(P.A, P.X0, norm_a=P.norm_a, crt=8)
+    assert r_16.status == 0 and r_dd.status == 0
+    assert np.max(np.abs(r_16.X - r_dd.X)) < 1e-15
+    assert np.max(np.abs(r_8.X - r_dd.X)) > 1e-9
+
+
 def test_separable_laplacian_generator_eigenpairs():
     """The separable-diagonal Laplacian used for the largest sparse timing
     run: its Kronecker-product eigenvectors are eigenvectors of the CSR
