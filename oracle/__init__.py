@@ -194,10 +194,12 @@ def crt_bits(nmod: int, n: int):
 
 def matmul_crt(A, X, nmod: int):
     """The product step of Algorithm 4 by the modular form with nmod moduli:
-    A' = rint(A_il 2^(bA - E_i)) (row exponents E), X' = rint(X_lj 2^(bX - F_j))
-    (column exponents F), W = 2^(E_i + F_j - bA - bX) (A'X')_ij with the integer
+    A' = rint(A_il 2^(bA - E_i)) off the diagonal (A'_ii = 0; E_i from the
+    off-diagonal row maxima), X' = rint(X_lj 2^(bX - F_j)) (column exponents
+    F), W = 2^(E_i + F_j - bA - bX) (A'X')_ij + a_ii x_ij with the integer
     product exact (what the Chinese remainder theorem recovers from the
-    residue products); returns (W_hi, W_lo).  A need not be symmetric."""
+    residue products) and the diagonal's part added exactly; returns
+    (W_hi, W_lo).  A need not be symmetric (it must be square)."""
     lib = _load()
     A, X = _f64(A), _f64(X)
     n, k = X.shape

@@ -221,10 +221,18 @@ int orc_gemm_split(int64_t n, int64_t k, const double* A, int64_t lda,
 /* Sec. 3.1.3 by the integer route of Ozaki scheme II: Ozaki, Uchino and     */
 /* Imamura 2025).                                                            */
 /*                                                                           */
-/* Scaling to integers.  Row i of A gets the exponent E_i and column j of X  */
-/* the exponent F_j (the smallest integers with max |entry| < 2^E, 0 for a   */
-/* zero line), and                                                           */
-/*     A'_il = rint(a_il 2^(bA - E_i)),   X'_lj = rint(x_lj 2^(bX - F_j)),   */
+/* Diagonal.  The diagonal of A is kept out of the integer image and its     */
+/* part of the product, a_ii x_ij, is added exactly: the off-diagonal row    */
+/* maxima then set the scales, which keeps several more bits of the         */
+/* off-diagonal entries where the diagonal dominates the row (as in          */
+/* A = Q diag(lambda) Q^T, whose diagonal is the mean eigenvalue while the   */
+/* off-diagonal entries shrink like 1/sqrt(n)).                              */
+/*                                                                           */
+/* Scaling to integers.  Row i of A gets the exponent E_i (the smallest       */
+/* integer with max_{l != i} |a_il| < 2^E_i, 0 for a zero line) and column j */
+/* of X the exponent F_j (the same over the column), and                     */
+/*     A'_il = rint(a_il 2^(bA - E_i)) (l != i, A'_ii = 0),                  */
+/*     X'_lj = rint(x_lj 2^(bX - F_j)),                                       */
 /* integers with |A'| <= 2^bA and |X'| <= 2^bX (each is the rounding of one   */
 /* double, so it is itself a double; the scaling is exact).                  */
 /*                                                                           */
@@ -238,10 +246,12 @@ int orc_gemm_split(int64_t n, int64_t k, const double* A, int64_t lda,
 /* INT8 operands and exact INT32 sums, and recovers A'X' by the Chinese       */
 /* remainder theorem.  The recovered value is the exact integer product, so   */
 /* this oracle forms that product directly (128-bit integer sums; N <= 16     */
-/* keeps every sum below 2^125) and rounds                                   */
-/*     W_ij = 2^(E_i + F_j - bA - bX) (A'X')_ij                               */
-/* to a double-double pair (hi = the nearest double, lo = the nearest double */
-/* to the rest).                                                             */
+/* keeps every sum below 2^125) and returns                                   */
+/*     W_ij = 2^(E_i + F_j - bA - bX) (A'X')_ij + a_ii x_ij                   */
+/* as a double-double pair: the scaled integer rounded to a pair (hi the     */
+/* nearest double, lo the nearest double to the rest), a_ii x_ij as an exact */
+/* pair (TwoProduct), and the two pairs added with both parts' errors kept  */
+/* (relative error of the sum about 2^-105).                                 */
 /* ------------------------------------------------------------------------ */
 static const int32_t ORC_CRT_MODULI[16] = {256, 255, 253, 251, 247, 241, 239, 233,
                                            229, 227, 223, 217, 211, 199, 197, 193};
@@ -281,13 +291,15 @@ int orc_crt_bits(int32_t nmod, int64_t n, int32_t* bA, int32_t* bX) {
 
 /* Integer images of a rows x cols row-major matrix (leading dimension ld):
  * Q = rint(m 2^(b - E)) with one exponent per row (by_row) or per column. */
+/* skip_diag: the entries (i, i) are left out of the maxima and imaged as 0. */
 static void orc_crt_scale(int64_t rows, int64_t cols, const double* M, int64_t ld,
-                          int by_row, int32_t b, int64_t* Q, int32_t* Eexp) {
+                          int by_row, int skip_diag, int32_t b, int64_t* Q, int32_t* Eexp) {
   const int64_t nline = by_row ? rows : cols;
   for (int64_t a = 0; a < nline; ++a) {
     double mx = 0.0;
     const int64_t len = by_row ? cols : rows;
     for (int64_t t = 0; t < len; ++t) {
+      if (skip_diag && t == a) continue;
       double v = by_row ? M[a * ld + t] : M[t * ld + a];
       if (fabs(v) > mx) mx = fabs(v);
     }
@@ -298,7 +310,7 @@ static void orc_crt_scale(int64_t rows, int64_t cols, const double* M, int64_t l
   for (int64_t i = 0; i < rows; ++i)
     for (int64_t j = 0; j < cols; ++j) {
       const int e = Eexp[by_row ? i : j];
-      Q[i * cols + j] = (int64_t)rint(ldexp(M[i * ld + j], b - e));
+      Q[i * cols + j] = (skip_diag && i == j) ? 0 : (int64_t)rint(ldexp(M[i * ld + j], b - e));
     }
 }
 
@@ -318,8 +330,8 @@ int orc_gemm_crt(int64_t n, int64_t k, const double* A, int64_t lda,
     free(QA); free(QX); free(EA); free(EX);
     return ORC_ENOMEM;
   }
-  orc_crt_scale(n, n, A, lda, 1, bA, QA, EA);
-  orc_crt_scale(n, k, X, ldx, 0, bX, QX, EX);
+  orc_crt_scale(n, n, A, lda, 1, 1, bA, QA, EA);
+  orc_crt_scale(n, k, X, ldx, 0, 0, bX, QX, EX);
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i)
     for (int64_t j = 0; j < k; ++j) {
@@ -328,8 +340,17 @@ int orc_gemm_crt(int64_t n, int64_t k, const double* A, int64_t lda,
       double hi = (double)tot;
       double lo = (double)(tot - (__int128)hi);
       const int sc = EA[i] + EX[j] - bA - bX;
-      Whi[i * ldw + j] = ldexp(hi, sc);
-      Wlo[i * ldw + j] = ldexp(lo, sc);
+      hi = ldexp(hi, sc);
+      lo = ldexp(lo, sc);
+      /* + a_ii x_ij: (hi, lo) + (p, pe), both parts' errors kept */
+      double p, pe, s1, e1, s2, e2;
+      two_prod(A[i * lda + i], X[i * ldx + j], &p, &pe);
+      two_sum(hi, p, &s1, &e1);
+      two_sum(lo, pe, &s2, &e2);
+      e1 += s2;
+      two_sum(s1, e1, &s1, &e1);
+      e1 += e2;
+      two_sum(s1, e1, &Whi[i * ldw + j], &Wlo[i * ldw + j]);
     }
   free(QA); free(QX); free(EA); free(EX);
   return ORC_OK;

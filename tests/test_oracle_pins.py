@@ -670,36 +670,68 @@ def test_crt_product_is_exact_when_nothing_is_truncated(N, bits):
         assert np.any(lo != 0.0)                     # the pair is needed
 
 
-def test_crt_product_truncation_bound_and_rate():
-    """Full 53-bit operands: the modular form stays within the truncation
-    bound 2^(E_i-bA-1) sum_l |x_lj| + 2^(F_j-bX-1) sum_l |a_il| + n 2^(E_i+F_j-bA-bX-2)
-    (each scaled image is off by at most half a unit) plus the pair's own
-    rounding, and four more moduli (about 31 bits more budget) cut the error
-    by at least 2^12."""
-    n, k = 29, 4
-    A = _wide_range_matrix(n, n, 83)
-    X = _wide_range_matrix(n, k, 84)
+def _offdiag_exponents(A):
+    """E_i: the smallest integer with max_{l != i} |a_il| < 2^E_i (0 for a
+    zero line), in exact arithmetic."""
+    E = []
+    for i, row in enumerate(A):
+        mx = max((abs(float(v)) for l, v in enumerate(row) if l != i), default=0.0)
+        E.append(math.frexp(mx)[1] if mx > 0.0 else 0)
+    return E
+
+
+def _crt_error_check(A, X, moduli):
+    """Largest error of the modular product relative to the line scales, after
+    checking every entry against the truncation bound 2^(E_i-bA-1) sum_{l!=i}
+    |x_lj| + 2^(F_j-bX-1) sum_{l!=i} |a_il| + n 2^(E_i+F_j-bA-bX-2) (each scaled
+    image off by at most half a unit; E_i from the off-diagonal maxima, the
+    diagonal's part exact) plus the pair's own rounding."""
+    n, k = X.shape
     ex = _exact_product(A, X)
-    _, EA = oracle.split_digits(A, 1, True)
+    EA = _offdiag_exponents(A)
     _, EX = oracle.split_digits(X, 1, False)
     worst = {}
-    for N in (8, 12, 16):
+    for N in moduli:
         bA, bX = oracle.crt_bits(N, n)
         hi, lo = oracle.matmul_crt(A, X, N)
         w = 0.0
         for i in range(n):
-            sa = sum(Fraction(abs(float(v))) for v in A[i])
+            sa = sum(Fraction(abs(float(v))) for l, v in enumerate(A[i]) if l != i)
             for j in range(k):
-                sx = sum(Fraction(abs(float(v))) for v in X[:, j])
-                ua = Fraction(2) ** (int(EA[i]) - bA - 1)
+                sx = sum(Fraction(abs(float(X[l, j]))) for l in range(n) if l != i)
+                ua = Fraction(2) ** (EA[i] - bA - 1)
                 ux = Fraction(2) ** (int(EX[j]) - bX - 1)
                 bound = ua * sx + ux * sa + n * ua * ux + abs(ex[i][j]) * Fraction(2) ** -104
                 err = abs(Fraction(float(hi[i, j])) + Fraction(float(lo[i, j])) - ex[i][j])
-                assert err <= bound
-                w = max(w, float(err / Fraction(2) ** (int(EA[i]) + int(EX[j]))))
+                assert err <= bound, (N, i, j, float(err), float(bound))
+                w = max(w, float(err / Fraction(2) ** (EA[i] + int(EX[j]))))
         worst[N] = w
+    return worst
+
+
+def test_crt_product_truncation_bound_and_rate():
+    """Full 53-bit operands: every entry within the truncation bound, and four
+    more moduli (about 31 bits more budget) cut the error by at least 2^12."""
+    n, k = 29, 4
+    A = _wide_range_matrix(n, n, 83)
+    X = _wide_range_matrix(n, k, 84)
+    worst = _crt_error_check(A, X, (8, 12, 16))
     assert worst[12] < worst[8] * 2.0 ** -12
     assert worst[16] < worst[12] * 2.0 ** -12
+
+
+def test_crt_product_keeps_the_diagonal_out_of_the_image():
+    """A diagonal 2^30 times the off-diagonal entries: the scales come from the
+    off-diagonal maxima, so the error stays within the off-diagonal bound
+    (about 2^-30 of what a full-row scale would give), and the diagonal's
+    part a_ii x_ij is present exactly (an image that drops it, or rounds it
+    to the off-diagonal unit, fails the bound)."""
+    n, k = 24, 3
+    rng = np.random.default_rng(87)
+    A = rng.standard_normal((n, n))
+    A[np.arange(n), np.arange(n)] = 2.0 ** 30 * (1.0 + rng.random(n))
+    X = rng.standard_normal((n, k))
+    _crt_error_check(A, X, (12,))
 
 
 def test_crt_step_agrees_with_double_double_step():
