@@ -169,6 +169,44 @@ def _time_rayleigh_ritz(ctx, X0, torch, reps=3):
     return best
 
 
+FORMS = {"fp64": ("fp64", "FP64 plain"), "split": ("split_int8", "split INT8 slices"),
+         "crt": ("split_crt", "modular INT8 (Ozaki scheme II)")}
+
+
+def _form_slices(args, prec):
+    return {"fp64": 0, "split_int8": args.slices, "split_crt": args.moduli}[prec]
+
+
+def _product_roofline(prec, n, k, s, ms_prod):
+    """Roofline of the form's product, timed with HIP events on the context's
+    stream: FP64 against the FP64 matrix peak (AI = k/4 flop/B past the
+    ridge); the slice form against the INT8 peak (s(s+1)/2 products, the
+    binding unit at these k); the modular form against HBM (s residue planes
+    of n^2 bytes, each read once by one INT8 product of AI = 2k op/B, below
+    the INT8 ridge of 625)."""
+    flops = 2.0 * n * n * k
+    if prec == "fp64":
+        eff = flops / (ms_prod * 1e-3) / 1e12
+        return {"bound": "mfma", "achieved": eff, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": eff / FP64_PEAK_TFLOPS, "traffic": _traffic_for("gemm_f64_dense", n, k)}
+    if prec == "split_int8":
+        tops = s * (s + 1) / 2 * flops / (ms_prod * 1e-3) / 1e12
+        return {"bound": "mfma", "achieved": tops, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
+                "frac": tops / INT8_PEAK_TOPS, "traffic": None}
+    byts = _crt_bytes(n, k, s)
+    gbs = byts / (ms_prod * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "traffic": _traffic_for("crt", n, k)}
+
+
+def _crt_bytes(n, k, nmod):
+    """Algorithmic bytes of the modular product: the nmod residue planes of A
+    (n^2 bytes each) and of X (n k bytes each) read, the residues of the nmod
+    products (n k bytes each) written and read back, X read twice (column
+    maxima, residues) and W written as a pair (16 n k)."""
+    return nmod * (n * n + 3.0 * n * k) + 16.0 * n * k + 16.0 * n * k
+
+
 def bench_dense(args, rf, torch, np):
     import synth
     dev = "cuda:0"
@@ -186,58 +224,41 @@ def bench_dense(args, rf, torch, np):
     X0 = P.X0.to(dev).contiguous()
     torch.cuda.synchronize()
 
-    main_prec = "split_int8" if args.precision == "split" else "fp64"
-    slices = args.slices if main_prec == "split_int8" else 0
-    ctx = rf.RefineContext(A, k, norm_a=P.norm_a, precision=main_prec, slices=slices)
-    X = X0.clone()
+    main_prec = FORMS[args.precision][0]
     if args.product_only:
+        ctx = rf.RefineContext(A, k, norm_a=P.norm_a, precision=main_prec,
+                               slices=_form_slices(args, main_prec))
         Acopy = A.clone()          # reads and writes 8 n^2 bytes
         torch.cuda.synchronize()
         del Acopy
-        ms = ctx.time_product(X, args.product_reps)
+        ms = ctx.time_product(X0.clone(), args.product_reps)
         print(json.dumps({"product_ms": ms, "n": n, "k": k, "precision": main_prec,
-                          "slices": slices, "copy_bytes": 8 * n * n}), flush=True)
+                          "slices": _form_slices(args, main_prec), "copy_bytes": 8 * n * n}),
+              flush=True)
         ctx.close()
         return None
-    sec, st1, st_last, X_first = _time_steps(ctx, X, args.steps, args.warmup, torch)
-    value = k / sec
-    _progress("%s form timed: %.4f ms per step" % (main_prec, sec * 1e3))
-    # dominant kernel: the product W = A X, timed with HIP events on the
-    # context's stream, same launch configuration as inside the step
-    ms_prod = ctx.time_product(X0.clone(), args.product_reps)
-    rr_ms = _time_rayleigh_ritz(ctx, X0, torch)
-    ctx.close()
-    flops = 2.0 * n * n * k
-    eff = flops / (ms_prod * 1e-3) / 1e12
-    if main_prec == "fp64":
-        roof = {"bound": "mfma", "achieved": eff, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": eff / FP64_PEAK_TFLOPS, "traffic": _traffic_for("gemm_f64_dense", n, k)}
-    else:
-        tops = slices * (slices + 1) / 2 * flops / (ms_prod * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": tops, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
-                "frac": tops / INT8_PEAK_TOPS, "traffic": None}
 
-    other = None
-    Xo_first = None
+    forms = [main_prec]
     if not args.no_split:
-        oprec = "fp64" if main_prec == "split_int8" else "split_int8"
-        oslices = 0 if oprec == "fp64" else args.slices
-        octx = rf.RefineContext(A, k, norm_a=P.norm_a, precision=oprec, slices=oslices)
-        Xo = X0.clone()
-        osec, ost1, ost_last, Xo_first = _time_steps(octx, Xo, args.steps, args.warmup, torch)
-        _progress("%s form timed: %.4f ms per step" % (oprec, osec * 1e3))
-        oms = octx.time_product(X0.clone(), args.product_reps)
-        octx.close()
-        other = {"precision": oprec, "slices": oslices, "eigvecs_per_s": k / osec,
-                 "ms_per_step": osec * 1e3, "product_us": oms * 1e3,
-                 "product_eff_gflops": flops / (oms * 1e-3) / 1e9,
-                 "corr_fro_last": ost_last.corr_fro,
-                 "orthogonality_last": _orthogonality(Xo.cpu().numpy())}
-        other["max_dx_first_step_vs_main"] = _aligned_err(X_first.cpu().numpy(),
-                                                          Xo_first.cpu().numpy())
+        forms += [FORMS[f][0] for f in ("fp64", "split", "crt") if FORMS[f][0] != main_prec]
+    res = {}
+    for prec in forms:
+        s = _form_slices(args, prec)
+        ctx = rf.RefineContext(A, k, norm_a=P.norm_a, precision=prec, slices=s)
+        X = X0.clone()
+        sec, st1, st_last, X_first = _time_steps(ctx, X, args.steps, args.warmup, torch)
+        _progress("%s form timed: %.4f ms per step" % (prec, sec * 1e3))
+        # the product W = A X alone, timed with HIP events on the context's
+        # stream, same launch configuration as inside the step
+        ms_prod = ctx.time_product(X0.clone(), args.product_reps)
+        rr_ms = _time_rayleigh_ritz(ctx, X0, torch) if prec == main_prec else None
+        ctx.close()
+        res[prec] = {"slices": s, "sec": sec, "st1": st1, "st_last": st_last,
+                     "X_first": X_first.cpu().numpy(), "ms_prod": ms_prod, "rr_ms": rr_ms,
+                     "orth": _orthogonality(X.cpu().numpy())}
 
+    errs = {p: {} for p in forms}
     cpu = None
-    errs = {}
     if not args.no_cpu_baseline:
         import oracle
         A_h = A.cpu().numpy()
@@ -250,8 +271,8 @@ def bench_dense(args, rf, torch, np):
             reps += 1
         t_cpu = (time.perf_counter() - ts) / reps
         _progress("FP64 oracle: %d steps, %.2f s each" % (reps, t_cpu))
-        g = X_first.cpu().numpy()
-        errs["err_vs_fp64_oracle_first_step"] = _aligned_err(g, r.X)
+        for p in forms:
+            errs[p]["err_vs_fp64_oracle_first_step"] = _aligned_err(res[p]["X_first"], r.X)
         cpu = {"value": k / t_cpu, "unit": "eigvecs/s", "cores": _cores(), "kind": "oracle",
                "cpu": _cpu_model(),
                "sample": "%d full FP64 oracle steps of the same workload (n=%d, k=%d), %.2f s each"
@@ -259,36 +280,48 @@ def bench_dense(args, rf, torch, np):
         if not args.no_dd_check:
             _progress("double-double oracle step")
             rd = oracle.refine_step(A_h, X0_h, norm_a=P.norm_a, dd=True)
-            errs["err_vs_dd_oracle_first_step"] = _aligned_err(g, rd.X)
-            if Xo_first is not None:
-                other["err_vs_dd_oracle_first_step"] = _aligned_err(Xo_first.cpu().numpy(), rd.X)
-            if other is not None:
-                other["err_vs_fp64_oracle_first_step"] = _aligned_err(Xo_first.cpu().numpy(), r.X)
+            for p in forms:
+                errs[p]["err_vs_dd_oracle_first_step"] = _aligned_err(res[p]["X_first"], rd.X)
 
-    split_block = None
-    if other is not None:
-        other["meets_targets"] = _meets(other)
-        if main_prec == "fp64":
-            split_block = dict(other)
-            split_block["speed_ratio_split_over_fp64"] = other["eigvecs_per_s"] / value
-        else:
-            split_block = {"fp64": other,
-                           "speed_ratio_split_over_fp64": value / other["eigvecs_per_s"]}
-    cfg = {"workload": ("%s form, " % ("FP64 plain" if main_prec == "fp64" else
-                                       "split INT8 s=%d" % slices)) + desc,
-           "n": n, "k": k, "precision": main_prec,
-           "product_us": ms_prod * 1e3, "product_eff_gflops": eff * 1e3,
-           "corr_fro_first": st1.corr_fro, "corr_fro_last": st_last.corr_fro,
-           "resid_rel_last": st_last.resid_rel,
-           "orthogonality_last": _orthogonality(X.cpu().numpy()),
-           "rayleigh_ritz_ms": rr_ms,
-           "split": split_block}
-    cfg.update(errs)
+    flops = 2.0 * n * n * k
+
+    def block(p):
+        r = res[p]
+        b = {"precision": p, "slices": r["slices"], "eigvecs_per_s": k / r["sec"],
+             "ms_per_step": r["sec"] * 1e3, "product_us": r["ms_prod"] * 1e3,
+             "product_eff_gflops": flops / (r["ms_prod"] * 1e-3) / 1e9,
+             "product_roofline": _product_roofline(p, n, k, r["slices"], r["ms_prod"]),
+             "corr_fro_first": r["st1"].corr_fro, "corr_fro_last": r["st_last"].corr_fro,
+             "resid_rel_last": r["st_last"].resid_rel, "orthogonality_last": r["orth"]}
+        b.update(errs[p])
+        if p != main_prec:
+            b["max_dx_first_step_vs_main"] = _aligned_err(r["X_first"], res[main_prec]["X_first"])
+        b["meets_targets"] = _meets(b)
+        return b
+
+    blocks = {p: block(p) for p in forms}
+    main = res[main_prec]
+    value = k / main["sec"]
+    roof = blocks[main_prec].pop("product_roofline")
+    cfg = {"workload": "%s form, " % FORMS[args.precision][1] + desc,
+           "n": n, "k": k, "precision": main_prec, "slices": main["slices"],
+           "rayleigh_ritz_ms": main["rr_ms"]}
+    cfg.update({kk: vv for kk, vv in blocks[main_prec].items() if kk not in ("precision", "slices")})
+    # the other forms on the same input, each with its speed against FP64
+    t64 = res["fp64"]["sec"] if "fp64" in res else None
+    for p in forms:
+        if p == main_prec:
+            continue
+        b = blocks[p]
+        if t64 is not None and p != "fp64":
+            b["speed_ratio_split_over_fp64"] = t64 / res[p]["sec"]
+        cfg[{"fp64": "fp64", "split_int8": "split", "split_crt": "split_crt"}[p]] = b
+    if main_prec != "fp64" and t64 is not None:
+        cfg["speed_ratio_split_over_fp64"] = t64 / main["sec"]
     # the accuracy targets: max |dX| <= 1e-13 against the double-double oracle
     # step, orthogonality max |X^T X - I| <= 1e-14 after all steps
     cfg["targets"] = {"err_vs_dd_oracle": 1e-13, "orthogonality": 1e-14}
-    cfg["meets_targets"] = _meets(cfg)
-    return {"value": value, "ms_per_step": sec * 1e3, "unit": "eigvecs/s",
+    return {"value": value, "ms_per_step": main["sec"] * 1e3, "unit": "eigvecs/s",
             "dtype": "f64" if main_prec == "fp64" else "i8", "config": cfg, "roofline": roof,
             "cpu_baseline": cpu}
 
@@ -522,10 +555,12 @@ def main() -> int:
     ap.add_argument("--k", type=int, default=0)
     ap.add_argument("--count", type=int, default=512, help="batch: number of problems")
     ap.add_argument("--sample", type=int, default=8, help="batch: problems checked on the CPU")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "split"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "split", "crt"],
+                    help="dense: the main form (the other two run on the same input)")
     ap.add_argument("--slices", type=int, default=0,
                     help="split slices (default 9; 10 for the clustered batch)")
-    ap.add_argument("--no-split", action="store_true", help="skip the split-form comparison")
+    ap.add_argument("--moduli", type=int, default=16, help="modular form: moduli (12..16)")
+    ap.add_argument("--no-split", action="store_true", help="skip the other forms")
     ap.add_argument("--no-dd-check", action="store_true",
                     help="dense: skip the comparison of the first step with the double-double "
                          "oracle (about a minute of host time at n = 16384)")

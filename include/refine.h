@@ -71,11 +71,24 @@ typedef enum { REFINE_DENSE = 0, REFINE_CSR = 1 } refine_kind;
  *     REFINE_EINVAL).  On this hardware FP8 and INT8 matrix products run at
  *     the same dense rate, and an FP8 (e4m3) slice holds an exact signed digit
  *     of 4 bits against INT8's 8, so an FP8 split needs about twice the slices
- *     and four times the slice products of the INT8 one for the same W. */
+ *     and four times the slice products of the INT8 one for the same W.
+ *   REFINE_SPLIT_CRT: A X by the modular route to the same double-double W
+ *     (Ozaki scheme II, the integer direction of Sec. 3.1.3): A and X are
+ *     scaled by powers of two per row and per column and rounded to integers
+ *     A', X' of bA and bX bits; N coprime moduli m_t <= 256 (256, 255, 253,
+ *     ...) with bA + bX = L - 3 - ceil(log2 n), L the bit length of their
+ *     product M, make A'X' the one integer in [-M/2, M/2) with the residues
+ *     of the N INT8 products (A' mod m_t)(X' mod m_t) (exact INT32 sums), and
+ *     the Chinese remainder theorem (Garner's mixed radix) recovers it; W is
+ *     that integer scaled back, as a double-double pair.  One product per
+ *     modulus instead of s(s+1)/2 slice products; A's residues take N n^2
+ *     bytes (made at init), which is what a step streams.  Dense, one
+ *     problem (refine_batch_init returns REFINE_EINVAL). */
 typedef enum {
   REFINE_FP64 = 0,
   REFINE_SPLIT_INT8 = 1,
-  REFINE_SPLIT_FP8 = 2
+  REFINE_SPLIT_FP8 = 2,
+  REFINE_SPLIT_CRT = 3
 } refine_precision;
 
 /* Which eigenpairs are targeted (eq. condition and Sec. 5.1):
@@ -134,10 +147,12 @@ typedef struct {
   double norm_a;           /* ||A|| for delta and the residual statistic; <= 0: ||A||_inf */
   refine_beta beta;
   int32_t normalize;       /* 1: normalise columns after each update (Sec. 3.1.3) */
-  int32_t slices;          /* split mode: INT8 digit slices per operand, 7..10;
-                              0 = 9 (45 slice products; W then carries about
-                              2^-60 of the row and column scales, below the
-                              rounding of an FP64 product) */
+  int32_t slices;          /* REFINE_SPLIT_INT8: INT8 digit slices per operand,
+                              7..10; 0 = 9 (45 slice products; W then carries
+                              about 2^-60 of the row and column scales, below
+                              the rounding of an FP64 product).
+                              REFINE_SPLIT_CRT: moduli N, 12..16; 0 = 16
+                              (bA, bX = 55, 54 bits at n = 16384) */
 } refine_options;
 
 typedef struct {

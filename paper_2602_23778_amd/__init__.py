@@ -35,7 +35,7 @@ ENONFINITE = -6
 ERANK = -7
 
 DENSE, CSR = 0, 1
-FP64, SPLIT_INT8, SPLIT_FP8 = 0, 1, 2
+FP64, SPLIT_INT8, SPLIT_FP8, SPLIT_CRT = 0, 1, 2, 3
 TARGETS = {"largest_abs": 0, "smallest": 1, "largest": 2, "shift": 3, "smallest_abs": 4}
 BETAS = {"half_gram": 0, "zero": 1}
 STOPS = {"iters": 0, "correction": 1, "residual": 2}
@@ -226,7 +226,7 @@ def make_options(precision="fp64", target="largest_abs", shift=0.0, delta_c=10.0
                  beta="half_gram", normalize=True, slices=0) -> refine_options:
     o = refine_options()
     refine_options_default(o)
-    o.precision = {"fp64": FP64, "split_int8": SPLIT_INT8}[precision]
+    o.precision = {"fp64": FP64, "split_int8": SPLIT_INT8, "split_crt": SPLIT_CRT}[precision]
     o.target = TARGETS[target]
     o.shift = float(shift)
     o.delta_c = float(delta_c)

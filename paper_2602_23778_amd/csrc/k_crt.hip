@@ -1,0 +1,718 @@
+// Modular form of the product step of Algorithm 4, W = A X, for the
+// accelerator direction of Sec. 3.1.3: the integer route of Ozaki scheme II
+// (Ozaki, Uchino and Imamura 2025).  Where the slice form multiplies s digit
+// slices pairwise (s(s+1)/2 INT8 products), this form multiplies residues:
+// one INT8 product per modulus.
+//
+// Diagonal.  The diagonal of A stays out of the integer image; its part of
+// the product, a_ii x_ij, is added exactly in the reconstruction.  The row
+// scales then come from the off-diagonal entries, which keeps more of their
+// bits where the diagonal dominates a row (as in A = Q diag(lambda) Q^T,
+// whose diagonal is the mean eigenvalue while the rest shrinks like
+// 1/sqrt(n)).
+//
+// Scaling.  Row i of A gets the exponent E_i (max_{l != i} |a_il| < 2^E_i)
+// and column j of X the exponent F_j (max_l |x_lj| < 2^F_j), the smallest
+// such integers (0 for a zero line), and
+//     A'_il = rint(a_il 2^(bA - E_i)) (l != i; A'_ii = 0),
+//     X'_lj = rint(x_lj 2^(bX - F_j)),
+// integers with |A'| <= 2^bA, |X'| <= 2^bX.  Each is the rounding of one
+// double, so it is itself a double (at most 53 significant bits).
+//
+// Moduli.  N pairwise coprime moduli m_0..m_{N-1} (256, 255, 253, ...: the
+// largest whose balanced residues fit a signed byte), M their product, L the
+// bit length of M.  The budget bA + bX = L - 3 - ceil(log2 n) (bA the larger
+// half) keeps |(A'X')_ij| <= n 2^(bA+bX) <= 2^(L-3) < M/2, so A'X' is the one
+// integer in [-M/2, M/2) with the residues of the N products
+//     C_t = (A' mod m_t)(X' mod m_t)  (mod m_t),
+// each an INT8 x INT8 product summed exactly in INT32 (|terms| <= 2^14, so
+// n <= 2^17 keeps the sums exact).
+//
+// Reconstruction (Garner, balanced digits).  With P_t = m_0 ... m_{t-1},
+// A'X' = sum_t v_t P_t with v_0 in [-128, 127] and v_t in [-(m_t-1)/2,
+// (m_t-1)/2]; this representation covers exactly [-M/2, M/2) and
+//     v_t = (c_t - sum_{s<t} v_s (P_s mod m_t)) (P_t mod m_t)^-1   (mod m_t),
+// whose inner sum stays below 2^19 in magnitude, so one exact reduction per
+// digit suffices.  The value is then formed by Horner's rule in
+// double-double (exact while it fits 106 bits, relative error below 2^-104
+// beyond), scaled by 2^(E_i + F_j - bA - bX), and a_ii x_ij (an exact
+// product pair) is added with both parts' errors kept: W = (W_hi, W_lo).
+//
+// Layouts (bytes).  A's residues: N planes, each tile-major like the slices
+// of the slice form with one digit per value: rows in blocks of BM, per
+// block the 32-wide contraction chunks one after another, per chunk the BM
+// rows of 32 bytes: plane t, row i = BM b + r, chunk c at
+//     ares + t ares_plane + ((b nchp + c) BM + r) 32.
+// X^T's residues: N planes of nchp chunks, each chunk kpad columns of 32
+// bytes: xres + t xres_plane + (c kpad + j) 32.  The residues of the
+// products: N planes of rows_pad x kpad bytes.  Chunks are padded with
+// zeros to a multiple of XG_PAD (nchp), rows to a multiple of 256.
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "dev_util.h"
+#include "split.h"
+
+namespace rfk {
+
+namespace {
+
+typedef int v16i __attribute__((ext_vector_type(16)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
+
+// The moduli: pairwise coprime, the largest that fit a signed byte as
+// balanced residues.
+constexpr int CRT_MOD[CRT_N_MAX] = {256, 255, 253, 251, 247, 241, 239, 233,
+                                    229, 227, 223, 217, 211, 199, 197, 193};
+
+// Chunk counts of the contraction are padded to a multiple of this (the
+// largest chunk group of the product), and the residue planes of A are laid
+// out in tiles of CRT_TILE rows.
+constexpr int XG_PAD = 8;
+constexpr int CRT_TILE = 128;
+
+constexpr int cmod(long long a, int m) {
+  long long r = a % m;
+  return (int)(r < 0 ? r + m : r);
+}
+// Inverse of a modulo m (a and m coprime), by the extended Euclidean algorithm.
+constexpr int cinv(int a, int m) {
+  long long r0 = m, r1 = cmod(a, m), s0 = 0, s1 = 1;
+  while (r1 != 0) {
+    const long long q = r0 / r1, r2 = r0 - q * r1, s2 = s0 - q * s1;
+    r0 = r1;
+    r1 = r2;
+    s0 = s1;
+    s1 = s2;
+  }
+  return cmod(s0, m);
+}
+
+// Garner tables: PM[s][t] = P_s mod m_t (s < t) and PINV[t] = (P_t mod m_t)^-1.
+struct Garner {
+  int pm[CRT_N_MAX][CRT_N_MAX];
+  int pinv[CRT_N_MAX];
+  constexpr Garner() : pm(), pinv() {
+    for (int t = 0; t < CRT_N_MAX; ++t) {
+      long long p = 1;  // P_s mod m_t
+      for (int s = 0; s < t; ++s) {
+        pm[s][t] = (int)p;
+        p = p * CRT_MOD[s] % CRT_MOD[t];
+      }
+      pinv[t] = t == 0 ? 1 : cinv((int)p, CRT_MOD[t]);
+    }
+  }
+};
+constexpr Garner GARNER{};
+
+// Balanced residue of an integer-valued double v (|v| < 2^62) modulo m, in
+// [-128, 127] for m = 256 and [-(m-1)/2, (m-1)/2] for odd m.  Both steps are
+// exact: q is an integer near v/m (|v/m - q| < 6 from the rounding of v/m),
+// so v - q m is a small integer and the fused multiply-add returns it
+// exactly; the second step then rounds a small quotient correctly (an odd m
+// leaves no halfway case, m = 256 maps the one tie, 128, to -128).
+__device__ __forceinline__ int bal_res(double v, int m, double inv) {
+  double r = __builtin_fma(-__builtin_rint(v * inv), (double)m, v);
+  r = __builtin_fma(-__builtin_rint(r * inv), (double)m, r);
+  int ri = (int)r;
+  if (ri == 128) ri = -128;  // only m = 256 can produce it
+  return ri;
+}
+
+__device__ __forceinline__ int scale_exp(double mx) {
+  int e = 0;
+  if (mx > 0.0) (void)frexp(mx, &e);  // mx = f 2^e, f in [1/2, 1): mx < 2^e
+  return e;
+}
+
+__device__ __forceinline__ unsigned pack4(int a, int b, int c, int d) {
+  return ((unsigned)a & 0xffu) | (((unsigned)b & 0xffu) << 8) | (((unsigned)c & 0xffu) << 16) |
+         ((unsigned)d << 24);
+}
+
+struct CrtArgs {
+  const int8_t* ares;
+  int64_t ares_plane;
+  int8_t* xres;
+  int64_t xres_plane;
+  int8_t* cres;
+  int64_t cres_plane;  // rows_pad * kpad
+  const double* adiag; // a_ii (rows_pad entries, 0 past n)
+  int nchp;            // contraction chunks, padded to a multiple of XG_PAD
+  int ba, bx;
+};
+
+// ---------------------------------------------------------------------------
+// Row exponents of A from the off-diagonal maxima, and the diagonal (once, at
+// init): one wavefront per row (rows >= n get 0).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void crt_aexp_kernel(const double* __restrict__ a, int64_t lda,
+                                                       int n, int rows_pad,
+                                                       int32_t* __restrict__ aexp,
+                                                       double* __restrict__ adiag) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= rows_pad) return;
+  double m = 0.0;
+  if (row < n)
+    for (int c = lane; c < n; c += 64)
+      if (c != row) m = fmax(m, fabs(a[(int64_t)row * lda + c]));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  if (lane == 0) {
+    aexp[row] = scale_exp(m);
+    adiag[row] = row < n ? a[(int64_t)row * lda + row] : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Residues of A (once, at init): one thread per 16-column unit (row, chunk,
+// half), the diagonal entry imaged as 0.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(256) void crt_ares_kernel(const double* __restrict__ a, int64_t lda,
+                                                       int n, int rows_pad, int bm, CrtArgs ca,
+                                                       const int32_t* __restrict__ aexp) {
+  const int nchp = ca.nchp;
+  const int64_t units = (int64_t)rows_pad * nchp * 2;
+  for (int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x; u < units;
+       u += (int64_t)gridDim.x * 256) {
+    const int row = (int)(u / (2 * nchp));
+    const int cu = (int)(u - (int64_t)row * 2 * nchp);  // 2 * chunk + half
+    const int col0 = cu * 16;
+    const int sh = ca.ba - aexp[row];
+    double v[16];
+#pragma unroll
+    for (int b = 0; b < 16; ++b)
+      v[b] = (row < n && col0 + b < n && col0 + b != row)
+                 ? __builtin_rint(ldexp(a[(int64_t)row * lda + col0 + b], sh))
+                 : 0.0;
+    const int rb = row / bm, c = cu >> 1;
+    const int64_t off = (((int64_t)rb * nchp + c) * bm + (row - rb * bm)) * 32 + (cu & 1) * 16;
+#pragma unroll
+    for (int t = 0; t < N; ++t) {
+      const int m = CRT_MOD[t];
+      const double inv = 1.0 / CRT_MOD[t];
+      int r[16];
+#pragma unroll
+      for (int b = 0; b < 16; ++b) r[b] = bal_res(v[b], m, inv);
+      const u4v o = {pack4(r[0], r[1], r[2], r[3]), pack4(r[4], r[5], r[6], r[7]),
+                     pack4(r[8], r[9], r[10], r[11]), pack4(r[12], r[13], r[14], r[15])};
+      *reinterpret_cast<u4v*>(const_cast<int8_t*>(ca.ares) + t * ca.ares_plane + off) = o;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Residues of X^T (every step): one thread per unit (chunk, column, half),
+// 16 rows of one column; the column exponent comes from the maxima of |X|.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(256) void crt_xres_kernel(const Prob* __restrict__ probs, CrtArgs ca) {
+  const Prob& P = probs[0];
+  if (P.ctrl->stopped) return;
+  const int kpad = P.kpad, k = P.k, n = P.n;
+  const int64_t units = (int64_t)ca.nchp * kpad * 2;
+  const unsigned long long* mx = reinterpret_cast<const unsigned long long*>(P.xmaxp);
+  for (int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x; u < units;
+       u += (int64_t)gridDim.x * 256) {
+    const int h = (int)(u & 1);
+    const int64_t cj = u >> 1;
+    const int c = (int)(cj / kpad);
+    const int j = (int)(cj - (int64_t)c * kpad);
+    const int e = j < k ? scale_exp(__longlong_as_double((long long)mx[j])) : 0;
+    if (c == 0 && h == 0) P.xexp[j] = e;
+    const int sh = ca.bx - e;
+    const int r0 = c * 32 + h * 16;
+    double v[16];
+#pragma unroll
+    for (int b = 0; b < 16; ++b)
+      v[b] = (j < k && r0 + b < n) ? __builtin_rint(ldexp(*gld(P.x + (int64_t)(r0 + b) * P.ldx + j), sh))
+                                   : 0.0;
+#pragma unroll
+    for (int t = 0; t < N; ++t) {
+      const int m = CRT_MOD[t];
+      const double inv = 1.0 / CRT_MOD[t];
+      int r[16];
+#pragma unroll
+      for (int b = 0; b < 16; ++b) r[b] = bal_res(v[b], m, inv);
+      const u4v o = {pack4(r[0], r[1], r[2], r[3]), pack4(r[4], r[5], r[6], r[7]),
+                     pack4(r[8], r[9], r[10], r[11]), pack4(r[12], r[13], r[14], r[15])};
+      *reinterpret_cast<u4v*>(ca.xres + t * ca.xres_plane + u * 16) = o;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The residue products.  Work item (modulus t = item.split, row block
+// row0 = item.row0 of BM = 32 WAVES W rows); item.k0 < 0 marks an empty slot of
+// the XCD-aware dispatch order.  Wavefront w owns the rows row0 + 32 w .. +31
+// of W and all kpad columns (KT tiles of 32).  Per group of XG 32-wide
+// contraction chunks a wavefront loads its A fragments (16 bytes per lane per
+// chunk) straight from the residue plane into registers, two groups ahead
+// through three register stages (the group loop is unrolled by three so that
+// every stage keeps its registers), and reads the KT X^T fragments of each
+// chunk from LDS, where the block stages X^T's residues a group at a time
+// (double buffered, rows padded to 48 bytes so that the 16-byte fragment
+// reads of 16 lanes fall on distinct banks).  Per group the X^T group of the
+// next step is requested before the A group two steps ahead, so the wait
+// that precedes its LDS store leaves the A requests in flight.  Loads past
+// the last group are clamped to it (valid memory, never used), which keeps
+// the compiler's wait counts exact across the loop.
+//
+// v_mfma_i32_32x32x32_i8 (gfx950): lane l supplies a[m = l%32][kk = 16(l/32)
+// + b] and b[kk = 16(l/32) + b][n = l%32] for the bytes b of its 16-byte
+// operand; register r of the result holds c[m = 8(r/4) + 4(l/32) + r%4][n =
+// l%32].  The X^T fragment is the a operand (m = column j of W), the A
+// fragment the b operand (n = row i of W).
+// ---------------------------------------------------------------------------
+template <int KT, int WAVES, int XG>
+__global__ __launch_bounds__(WAVES * 64) void crt_gemm_kernel(const Prob* __restrict__ probs,
+                                                              const GemmItem* __restrict__ items,
+                                                              CrtArgs ca) {
+  constexpr int NT = WAVES * 64, KP = 32 * KT;
+  constexpr int XROW = 48;                    // padded LDS row (bytes)
+  constexpr int XSTAGE = XG * KP * XROW;      // bytes per stage
+  constexpr int XUNITS = XG * KP * 2;         // 16-byte units per stage
+  constexpr int XPT = (XUNITS + NT - 1) / NT; // units per thread
+  __shared__ __attribute__((aligned(16))) int8_t xs[2 * XSTAGE];
+
+  const GemmItem item = items[blockIdx.x];
+  const Prob& P = probs[0];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // the column maxima of this step have been consumed by the residue pass
+  if (item.k0 == 0 && item.row0 == 0 && item.split == 0 && tid < KP)
+    reinterpret_cast<unsigned long long*>(P.xmaxp)[tid] = 0ull;
+  if (item.k0 < 0 || P.ctrl->stopped) return;
+  const int t = item.split;
+  const int nchp = ca.nchp, ngroups = nchp / XG;
+  // this wavefront's 32 rows sit in the plane's tile of CRT_TILE rows that
+  // holds them
+  const int wrow = item.row0 + 32 * wave;
+  const int8_t* __restrict__ Ab = ca.ares + t * ca.ares_plane +
+                                  (int64_t)(wrow / CRT_TILE) * nchp * CRT_TILE * 32 +
+                                  ((wrow % CRT_TILE) + (lane & 31)) * 32 + (lane >> 5) * 16;
+  const int8_t* __restrict__ Xp = ca.xres + t * ca.xres_plane;
+
+  v16i acc[KT];
+#pragma unroll
+  for (int q = 0; q < KT; ++q) acc[q] = v16i{};
+
+  v4i a0[XG], a1[XG], a2[XG];
+  u4v xr[XPT];
+  auto load_a = [&](v4i(&dst)[XG], int g) {
+    g = min(g, ngroups - 1);
+#pragma unroll
+    for (int cc = 0; cc < XG; ++cc)
+      dst[cc] = __builtin_nontemporal_load(
+          gld(reinterpret_cast<const v4i*>(Ab + (int64_t)(g * XG + cc) * CRT_TILE * 32)));
+  };
+  auto load_x = [&](int g) {
+    g = min(g, ngroups - 1);
+#pragma unroll
+    for (int u = 0; u < XPT; ++u) {
+      const int e = min(tid + u * NT, XUNITS - 1);
+      xr[u] = *gld(reinterpret_cast<const u4v*>(Xp + (int64_t)g * XG * KP * 32 + e * 16));
+    }
+  };
+  auto store_x = [&](int8_t* dst) {
+#pragma unroll
+    for (int u = 0; u < XPT; ++u) {
+      const int e = tid + u * NT;
+      if (e < XUNITS) {
+        const int row = e >> 1;  // chunk-in-group * KP + column
+        *reinterpret_cast<u4v*>(dst + row * XROW + (e & 1) * 16) = xr[u];
+      }
+    }
+  };
+  auto group = [&](int g, const v4i(&cur)[XG], v4i(&ahead)[XG]) {
+    const int8_t* xst = xs + (g & 1) * XSTAGE;
+    load_x(g + 1);
+    load_a(ahead, g + 2);
+#pragma unroll
+    for (int cc = 0; cc < XG; ++cc) {
+#pragma unroll
+      for (int q = 0; q < KT; ++q) {
+        const v4i xf = *reinterpret_cast<const v4i*>(
+            xst + (cc * KP + 32 * q + (lane & 31)) * XROW + (lane >> 5) * 16);
+        acc[q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xf, cur[cc], acc[q], 0, 0, 0);
+      }
+    }
+    store_x(xs + ((g + 1) & 1) * XSTAGE);
+    __syncthreads();
+  };
+
+  load_x(0);
+  load_a(a0, 0);
+  store_x(xs);
+  load_a(a1, 1);
+  __syncthreads();
+  for (int g = 0; g < ngroups; g += 3) {
+    group(g, a0, a2);
+    if (g + 1 < ngroups) group(g + 1, a1, a0);
+    if (g + 2 < ngroups) group(g + 2, a2, a1);
+  }
+
+  // residues of the INT32 sums (|sum| <= n 2^14 < 2^31), one byte each
+  const int m = CRT_MOD[t];
+  const double inv = 1.0 / (double)m;
+  const int i = wrow + (lane & 31);
+  int8_t* out = ca.cres + t * ca.cres_plane + (int64_t)i * KP;
+#pragma unroll
+  for (int q = 0; q < KT; ++q)
+#pragma unroll
+    for (int g4 = 0; g4 < 4; ++g4) {
+      int r4[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) r4[e] = bal_res((double)acc[q][4 * g4 + e], m, inv);
+      // registers 4 g4 .. 4 g4 + 3 hold the columns 32 q + 8 g4 + 4 (l/32) + 0..3
+      *gst(reinterpret_cast<unsigned*>(out + 32 * q + 8 * g4 + 4 * (lane >> 5))) =
+          pack4(r4[0], r4[1], r4[2], r4[3]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Reconstruction: work item = row block of RROWS rows; thread (row, column)
+// with the columns spread over pow2ceil(k) threads.  Writes W_hi, W_lo and
+// the block's Rayleigh partials (x w_hi, x x).
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(256) void crt_recon_kernel(const Prob* __restrict__ probs,
+                                                        const RowItem* __restrict__ items,
+                                                        int rrows, CrtArgs ca) {
+  constexpr int NT = 256;
+  __shared__ double red[2 * NT];
+  const Prob& P = probs[0];
+  if (P.ctrl->stopped) return;
+  const int blk = items[blockIdx.x].blk;
+  const int n = P.n, k = P.k, kpad = P.kpad, kp = pow2ceil(k), tr = NT / kp;
+  const int tid = threadIdx.x, j = tid % kp, trow = tid / kp;
+  const int r0 = blk * rrows, r1 = min(n, r0 + rrows);
+  const int sbase = j < k ? P.xexp[j] - ca.ba - ca.bx : 0;
+  double sxw = 0.0, sxx = 0.0;
+  for (int i = r0 + trow; i < r1; i += tr) {
+    if (j >= k) continue;
+    int c[N];
+#pragma unroll
+    for (int t = 0; t < N; ++t) c[t] = *gld(ca.cres + t * ca.cres_plane + (int64_t)i * kpad + j);
+    // balanced mixed-radix digits (Garner)
+    int v[N];
+    v[0] = c[0];
+#pragma unroll
+    for (int t = 1; t < N; ++t) {
+      int s = 0;
+#pragma unroll
+      for (int u = 0; u < t; ++u) s += v[u] * GARNER.pm[u][t];
+      const int m = CRT_MOD[t];
+      // |c - s| < 2^19, times pinv < 2^8: exact in int32 and in double
+      v[t] = bal_res((double)((c[t] - s) * GARNER.pinv[t]), m, 1.0 / CRT_MOD[t]);
+    }
+    // Horner in double-double from the leading digit
+    double h = (double)v[N - 1], l = 0.0;
+#pragma unroll
+    for (int t = N - 2; t >= 0; --t) {
+      double p, pe;
+      two_prod(h, (double)CRT_MOD[t], p, pe);
+      double s, se;
+      two_sum(p, (double)v[t], s, se);
+      const double lo = l * (double)CRT_MOD[t] + (pe + se);
+      two_sum(s, lo, h, l);
+    }
+    const int sc = sbase + *gld(P.aexp + i);
+    h = ldexp(h, sc);
+    l = ldexp(l, sc);
+    // + a_ii x_ij: (h, l) + (p, pe), both parts' errors kept
+    const double x = *gld(P.x + (int64_t)i * P.ldx + j);
+    double p, pe, s1, e1, s2, e2, wh, wl;
+    two_prod(*gld(ca.adiag + i), x, p, pe);
+    two_sum(h, p, s1, e1);
+    two_sum(l, pe, s2, e2);
+    e1 += s2;
+    two_sum(s1, e1, s1, e1);
+    e1 += e2;
+    two_sum(s1, e1, wh, wl);
+    P.w[(int64_t)i * k + j] = wh;
+    P.wlo[(int64_t)i * k + j] = wl;
+    sxw = __builtin_fma(x, wh, sxw);
+    sxx = __builtin_fma(x, x, sxx);
+  }
+  rayleigh_block_partial<NT>(P, blk, sxw, sxx, red);
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+constexpr int CRT_RROWS = 32;  // rows per reconstruction block
+
+// Launch shapes of the residue products: wavefronts per block (32 W rows
+// each) and chunks per group.  The tuner times each at init.
+struct CrtShape {
+  int waves, xg;
+};
+constexpr CrtShape CRT_SHAPES[] = {{4, 4}, {4, 8}, {8, 4}, {8, 8}, {4, 2}};
+constexpr int CRT_NSHAPES = sizeof(CRT_SHAPES) / sizeof(CRT_SHAPES[0]);
+
+int rows_pad_of(int64_t n) { return (int)((n + SPLIT_ROW_PAD - 1) / SPLIT_ROW_PAD * SPLIT_ROW_PAD); }
+
+CrtArgs args_of(const SplitPlan& sp, int64_t n) {
+  CrtArgs ca{};
+  const int64_t nch = (n + 31) / 32;
+  ca.ares = sp.ares;
+  ca.ares_plane = sp.ares_plane;
+  ca.xres = sp.xres;
+  ca.xres_plane = sp.xres_plane;
+  ca.cres = sp.cres;
+  ca.cres_plane = (int64_t)rows_pad_of(n) * sp.kpad;
+  ca.adiag = sp.adiag;
+  ca.nchp = (int)((nch + XG_PAD - 1) / XG_PAD * XG_PAD);
+  ca.ba = sp.crt_ba;
+  ca.bx = sp.crt_bx;
+  return ca;
+}
+
+template <int KT, int WAVES, int XG>
+void launch_gemm_shape(const SplitPlan& sp, const Prob* dprob, const CrtArgs& ca, hipStream_t st) {
+  hipLaunchKernelGGL((crt_gemm_kernel<KT, WAVES, XG>), dim3(sp.nitems), dim3(WAVES * 64), 0, st,
+                     dprob, sp.items, ca);
+}
+
+template <int KT>
+hipError_t launch_gemm_kt(const SplitPlan& sp, const Prob* dprob, const CrtArgs& ca,
+                          hipStream_t st) {
+  const CrtShape s = CRT_SHAPES[sp.crt_shape];
+  if (s.waves == 4 && s.xg == 4) launch_gemm_shape<KT, 4, 4>(sp, dprob, ca, st);
+  else if (s.waves == 4 && s.xg == 8) launch_gemm_shape<KT, 4, 8>(sp, dprob, ca, st);
+  else if (s.waves == 8 && s.xg == 4) launch_gemm_shape<KT, 8, 4>(sp, dprob, ca, st);
+  else if (s.waves == 8 && s.xg == 8) launch_gemm_shape<KT, 8, 8>(sp, dprob, ca, st);
+  else if (s.waves == 4 && s.xg == 2) launch_gemm_shape<KT, 4, 2>(sp, dprob, ca, st);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t launch_all_n(const SplitPlan& sp, const Prob* dprob, const CrtArgs& ca, int64_t units,
+                        hipStream_t st) {
+  const int grid = (int)std::min<int64_t>((units + 255) / 256, 8192);
+  hipLaunchKernelGGL((crt_xres_kernel<N>), dim3(grid), dim3(256), 0, st, dprob, ca);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  switch (sp.kpad / 32) {
+    case 1: e = launch_gemm_kt<1>(sp, dprob, ca, st); break;
+    case 2: e = launch_gemm_kt<2>(sp, dprob, ca, st); break;
+    case 3: e = launch_gemm_kt<3>(sp, dprob, ca, st); break;
+    case 4: e = launch_gemm_kt<4>(sp, dprob, ca, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((crt_recon_kernel<N>), dim3(sp.n_rec), dim3(256), 0, st, dprob, sp.rec_items,
+                     sp.crt_rrows, ca);
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t launch_ares_n(const refine_matrix& A, int rows_pad, const CrtArgs& ca,
+                         const int32_t* aexp, hipStream_t st) {
+  const int64_t units = (int64_t)rows_pad * ca.nchp * 2;
+  const int grid = (int)std::min<int64_t>((units + 255) / 256, 16384);
+  hipLaunchKernelGGL((crt_ares_kernel<N>), dim3(grid), dim3(256), 0, st, A.a, A.lda, (int)A.n,
+                     rows_pad, CRT_TILE, ca, aexp);
+  return hipGetLastError();
+}
+
+#define RFK_CRT_SWITCH(N, CALL) \
+  switch (N) {                  \
+    case 12: return CALL(12);   \
+    case 13: return CALL(13);   \
+    case 14: return CALL(14);   \
+    case 15: return CALL(15);   \
+    case 16: return CALL(16);   \
+    default: return hipErrorInvalidValue; \
+  }
+
+template <class T>
+hipError_t upload_items(T** dst, const std::vector<T>& v) {
+  (void)hipFree(*dst);
+  *dst = nullptr;
+  if (v.empty()) return hipSuccess;
+  hipError_t e = hipMalloc((void**)dst, sizeof(T) * v.size());
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice);
+}
+
+// Product items for blocks of bm rows, XCD-aware: the (modulus, row block)
+// pairs in modulus-major order are cut into eight contiguous ranges, and
+// range x takes the dispatch slots x, x + 8, x + 16, ... (workgroups go to
+// the eight XCDs in turn), so that each XCD works through one or two moduli
+// at a time and keeps their X^T residues in its own L2.
+std::vector<GemmItem> product_items(int nmod, int64_t n, int bm) {
+  const int nrb = (int)((n + bm - 1) / bm);
+  const int total = nmod * nrb;
+  const int per = (total + 7) / 8;
+  std::vector<GemmItem> gi((size_t)per * 8);
+  for (int s = 0; s < per * 8; ++s) {
+    const int x = s % 8, u = s / 8;
+    const int lin = x * per + u;
+    GemmItem g{};
+    if (lin < total) {
+      g.split = lin / nrb;
+      g.row0 = (lin % nrb) * bm;
+      g.k0 = 0;
+    } else {
+      g.k0 = -1;
+    }
+    gi[s] = g;
+  }
+  return gi;
+}
+
+int install_shape(SplitPlan& sp, int shape, int nmod, int64_t n) {
+  sp.crt_shape = shape;
+  sp.crt_bm = 32 * CRT_SHAPES[shape].waves;
+  const std::vector<GemmItem> gi = product_items(nmod, n, sp.crt_bm);
+  if (upload_items(&sp.items, gi) != hipSuccess) return REFINE_ENOMEM;
+  sp.nitems = (int)gi.size();
+  return REFINE_OK;
+}
+
+}  // namespace
+
+int crt_bits(int nmod, int64_t n, int* ba, int* bx) {
+  if (nmod < CRT_N_MIN || nmod > CRT_N_MAX || n < 1) return REFINE_EINVAL;
+  // M < 2^126 for N <= 16: exact in 128 bits
+  unsigned __int128 M = 1;
+  for (int t = 0; t < nmod; ++t) M *= (unsigned)CRT_MOD[t];
+  int L = 0;
+  while (L < 128 && (M >> L) != 0) ++L;
+  int c = 0;
+  while (((int64_t)1 << c) < n) ++c;
+  const int B = L - 3 - c;
+  if (B < 2) return REFINE_EINVAL;
+  *ba = (B + 1) / 2;
+  *bx = B / 2;
+  return REFINE_OK;
+}
+
+hipError_t crt_product(const SplitPlan& sp, const Prob* dprob, hipStream_t st) {
+  hipError_t e = split_xmax(sp, dprob, st);
+  if (e != hipSuccess) return e;
+  const int64_t n = sp.nk0 / sp.kmax;
+  const CrtArgs ca = args_of(sp, n);
+  const int64_t units = (int64_t)ca.nchp * sp.kpad * 2;
+#define RFK_CRT_ALL(N) launch_all_n<N>(sp, dprob, ca, units, st)
+  RFK_CRT_SWITCH(sp.crt, RFK_CRT_ALL)
+#undef RFK_CRT_ALL
+}
+
+int crt_init(SplitPlan& sp, const refine_matrix& A, int k, int nmod, std::vector<Prob>& hp,
+             Prob* dprob, hipStream_t st) {
+  const int64_t n = A.n;
+  int ba = 0, bx = 0;
+  if (A.kind != REFINE_DENSE || n > SPLIT_NMAX || crt_bits(nmod, n, &ba, &bx) != REFINE_OK)
+    return REFINE_EINVAL;
+  sp.crt = nmod;
+  sp.crt_ba = ba;
+  sp.crt_bx = bx;
+  sp.crt_rrows = CRT_RROWS;
+  const int rows_pad = rows_pad_of(n);
+  const int64_t nch = (n + 31) / 32, nchp = (nch + XG_PAD - 1) / XG_PAD * XG_PAD;
+  sp.ares_plane = (int64_t)rows_pad * nchp * 32;
+  sp.xres_plane = nchp * sp.kpad * 32;
+  const int64_t cres_plane = (int64_t)rows_pad * sp.kpad;
+  if (hipMalloc((void**)&sp.ares, (size_t)sp.ares_plane * nmod) != hipSuccess ||
+      hipMalloc((void**)&sp.aexp, sizeof(int32_t) * rows_pad) != hipSuccess ||
+      hipMalloc((void**)&sp.adiag, sizeof(double) * rows_pad) != hipSuccess ||
+      hipMalloc((void**)&sp.xres, (size_t)sp.xres_plane * nmod) != hipSuccess ||
+      hipMalloc((void**)&sp.cres, (size_t)cres_plane * nmod) != hipSuccess)
+    return REFINE_ENOMEM;
+  hipError_t e = hipMemsetAsync(sp.xres, 0, (size_t)sp.xres_plane * nmod, st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(crt_aexp_kernel, dim3((unsigned)((rows_pad + 3) / 4)), dim3(256), 0, st,
+                       A.a, A.lda, (int)n, rows_pad, sp.aexp, sp.adiag);
+    e = hipGetLastError();
+  }
+  const CrtArgs ca = args_of(sp, n);
+  if (e == hipSuccess) {
+#define RFK_CRT_ARES(N) launch_ares_n<N>(A, rows_pad, ca, sp.aexp, st)
+    e = [&]() -> hipError_t { RFK_CRT_SWITCH(nmod, RFK_CRT_ARES) }();
+#undef RFK_CRT_ARES
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return REFINE_EHIP;
+
+  std::vector<RowItem> rec;
+  const int nrec = (int)((n + CRT_RROWS - 1) / CRT_RROWS);
+  for (int b = 0; b < nrec; ++b) rec.push_back(RowItem{0, b});
+  if (upload_items(&sp.rec_items, rec) != hipSuccess) return REFINE_ENOMEM;
+  sp.n_rec = nrec;
+  sp.ks = 1;
+  Prob& P = hp[0];
+  P.aexp = sp.aexp;
+  P.ksplit = 1;
+  P.ndp = nrec;
+  P.nch = (int)nch;
+  P.kpad = sp.kpad;
+  if (hipMemcpy(dprob, hp.data(), sizeof(Prob) * hp.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return REFINE_EHIP;
+
+  // Launch shape of the residue products: REFINE_CRT_SHAPE=<index> forces
+  // one; otherwise each is timed once (on a zero X, the workspace copy of
+  // the update) and the fastest kept.
+  int best = -1;
+  if (const char* env = getenv("REFINE_CRT_SHAPE")) {
+    const int v = atoi(env);
+    if (v >= 0 && v < CRT_NSHAPES) best = v;
+  }
+  if (best < 0) {
+    const double* saved_x = hp[0].x;
+    const int64_t saved_ld = hp[0].ldx;
+    hp[0].x = hp[0].xn;
+    hp[0].ldx = hp[0].k;
+    if (hipMemcpy(dprob, hp.data(), sizeof(Prob) * hp.size(), hipMemcpyHostToDevice) != hipSuccess)
+      return REFINE_EHIP;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return REFINE_EHIP;
+    float best_t = 1e30f;
+    for (int sh = 0; sh < CRT_NSHAPES && e == hipSuccess; ++sh) {
+      int rc = install_shape(sp, sh, nmod, n);
+      if (rc != REFINE_OK) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return rc;
+      }
+      float t = 0.f;
+      e = crt_product(sp, dprob, st);  // warm-up
+      if (e == hipSuccess) e = hipEventRecord(e0, st);
+      for (int r = 0; r < 3 && e == hipSuccess; ++r) e = crt_product(sp, dprob, st);
+      if (e == hipSuccess) e = hipEventRecord(e1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+      if (getenv("REFINE_LOG") && atoi(getenv("REFINE_LOG")) >= 2)
+        fprintf(stderr, "refine: tune crt n=%lld k=%d N=%d shape %d (waves %d, group %d): %.1f us\n",
+                (long long)n, k, nmod, sh, CRT_SHAPES[sh].waves, CRT_SHAPES[sh].xg,
+                t * 1000.f / 3.f);
+      if (e == hipSuccess && t < best_t) {
+        best_t = t;
+        best = sh;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    hp[0].x = const_cast<double*>(saved_x);
+    hp[0].ldx = saved_ld;
+    if (e != hipSuccess || best < 0) return REFINE_EHIP;
+    sp.ms = best_t / 3.f;
+    if (getenv("REFINE_LOG"))
+      fprintf(stderr, "refine: crt product n=%lld k=%d N=%d: shape %d, %.1f us\n", (long long)n, k,
+              nmod, best, best_t * 1000.f / 3.f);
+  }
+  int rc = install_shape(sp, best, nmod, n);
+  if (rc != REFINE_OK) return rc;
+  if (hipMemcpy(dprob, hp.data(), sizeof(Prob) * hp.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return REFINE_EHIP;
+  return REFINE_OK;
+}
+
+}  // namespace rfk

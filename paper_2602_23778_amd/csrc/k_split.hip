@@ -796,11 +796,22 @@ int install_items(SplitPlan& sp, int ks, std::vector<Prob>& hp, Prob* dprob) {
 
 int split_rows_per_block(int k) { return 32 * layout_for(k).wm; }
 
-hipError_t split_product(const SplitPlan& sp, const Prob* dprob, hipStream_t st) {
-  hipError_t e;
+hipError_t split_xmax(const SplitPlan& sp, const Prob* dprob, hipStream_t st) {
   hipLaunchKernelGGL(split_xmax_kernel, dim3(std::min(sp.n_xmax, 8192)), dim3(256), 0, st, dprob,
                      sp.xmax_items, sp.n_xmax);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t split_aexp(const refine_matrix& A, int rows_pad, int32_t* aexp, hipStream_t st) {
+  hipLaunchKernelGGL(split_aexp_kernel, dim3((unsigned)((rows_pad + 3) / 4)), dim3(256), 0, st,
+                     A.a, A.lda, (int)A.n, rows_pad, aexp);
+  return hipGetLastError();
+}
+
+hipError_t split_product(const SplitPlan& sp, const Prob* dprob, hipStream_t st) {
+  if (sp.crt) return crt_product(sp, dprob, st);
+  hipError_t e;
+  if ((e = split_xmax(sp, dprob, st)) != hipSuccess) return e;
   if ((e = launch_xslice(sp.s, dprob, sp.xsl_items, sp.n_xsl, st)) != hipSuccess) return e;
   if ((e = launch_product(sp.s, layout_for(sp.kmax), sp.variant, dprob, sp.items, sp.nitems, st)) !=
       hipSuccess)
@@ -815,9 +826,41 @@ hipError_t split_product(const SplitPlan& sp, const Prob* dprob, hipStream_t st)
 }
 
 int split_init(SplitPlan& sp, const std::vector<refine_matrix>& As, const std::vector<int>& ks,
-               int slices, std::vector<Prob>& hp, Prob* dprob, hipStream_t st) {
+               int slices, int crt, std::vector<Prob>& hp, Prob* dprob, hipStream_t st) {
   sp = SplitPlan();
   const int np = (int)As.size();
+  if (crt) {
+    // modular form: one problem; the column-maximum pass is shared
+    if (np != 1 || ks[0] < 1 || ks[0] > KMAX) return REFINE_EINVAL;
+    const Layout L = layout_for(ks[0]);
+    sp.kmax = ks[0];
+    sp.kpad = 32 * L.wn;
+    sp.np = 1;
+    sp.nk0 = As[0].n * ks[0];
+    constexpr int XROWS = 64;
+    std::vector<RowItem> xm;
+    Prob& P = hp[0];
+    P.xrows = XROWS;
+    P.nbx = (int)((As[0].n + XROWS - 1) / XROWS);
+    for (int b = 0; b < P.nbx; ++b) xm.push_back(RowItem{0, b});
+    if (hipMalloc((void**)&sp.xexp, sizeof(int32_t) * sp.kpad) != hipSuccess ||
+        hipMalloc((void**)&sp.xmaxp, sizeof(double) * sp.kpad) != hipSuccess ||
+        upload_vec(&sp.xmax_items, xm) != hipSuccess) {
+      split_free(sp);
+      return REFINE_ENOMEM;
+    }
+    sp.n_xmax = (int)xm.size();
+    P.xexp = sp.xexp;
+    P.xmaxp = sp.xmaxp;
+    if (hipMemsetAsync(sp.xmaxp, 0, sizeof(double) * sp.kpad, st) != hipSuccess ||
+        hipMemsetAsync(sp.xexp, 0, sizeof(int32_t) * sp.kpad, st) != hipSuccess) {
+      split_free(sp);
+      return REFINE_EHIP;
+    }
+    const int rc = crt_init(sp, As[0], ks[0], crt, hp, dprob, st);
+    if (rc != REFINE_OK) split_free(sp);
+    return rc;
+  }
   if (np < 1 || slices < SPLIT_S_MIN || slices > SPLIT_S_MAX) return REFINE_EINVAL;
   int kmax = 0;
   for (int p = 0; p < np; ++p) {
@@ -1002,6 +1045,11 @@ void split_free(SplitPlan& sp) {
   (void)hipFree(sp.items);
   (void)hipFree(sp.xmax_items);
   (void)hipFree(sp.xsl_items);
+  (void)hipFree(sp.ares);
+  (void)hipFree(sp.xres);
+  (void)hipFree(sp.cres);
+  (void)hipFree(sp.adiag);
+  (void)hipFree(sp.rec_items);
   sp = SplitPlan();
 }
 

@@ -383,7 +383,7 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
   const int np = (int)As.size();
   const bool single = np == 1;
   pl.csr = As[0].kind == REFINE_CSR;
-  pl.split = opt.precision == REFINE_SPLIT_INT8;
+  pl.split = opt.precision == REFINE_SPLIT_INT8 || opt.precision == REFINE_SPLIT_CRT;
   pl.square = opt.target == REFINE_TARGET_SMALLEST_ABS;
   pl.spmm_lanes = pl.csr ? spmm_row_lanes(ks[0], As[0].n, As[0].nnz) : 0;
   pl.kxk_pipeline = single && ks[0] > KXK_ONE_WG_MAX;
@@ -675,9 +675,14 @@ int validate_matrix(const refine_matrix* A, int32_t k, const refine_options& opt
     return REFINE_EINVAL;
   }
   // REFINE_SPLIT_FP8 is declared but not offered (refine.h states why)
-  if (opt.precision != REFINE_FP64 && opt.precision != REFINE_SPLIT_INT8) return REFINE_EINVAL;
+  if (opt.precision != REFINE_FP64 && opt.precision != REFINE_SPLIT_INT8 &&
+      opt.precision != REFINE_SPLIT_CRT)
+    return REFINE_EINVAL;
   if (opt.precision == REFINE_SPLIT_INT8 &&
       (A->n > SPLIT_NMAX || (opt.slices != 0 && (opt.slices < SPLIT_S_MIN || opt.slices > SPLIT_S_MAX))))
+    return REFINE_EINVAL;
+  if (opt.precision == REFINE_SPLIT_CRT &&
+      (A->n > SPLIT_NMAX || (opt.slices != 0 && (opt.slices < CRT_N_MIN || opt.slices > CRT_N_MAX))))
     return REFINE_EINVAL;
   if (!(opt.delta_c >= 0.0)) return REFINE_EINVAL;
   if (opt.target < REFINE_TARGET_LARGEST_ABS || opt.target > REFINE_TARGET_SMALLEST_ABS)
@@ -817,7 +822,9 @@ int refine_init(refine_ctx** out, const refine_matrix* A, int32_t k, const refin
   std::vector<int> ks{k};
   rc = build_plan(c->plan, As, ks, opt, {c->mu}, {c->delta}, {c->norm_used});
   if (rc == REFINE_OK && c->plan.split) {
-    rc = split_init(c->plan.sp, {*A}, {k}, opt.slices > 0 ? opt.slices : SPLIT_S_DEFAULT, c->plan.hprob,
+    const bool crt = opt.precision == REFINE_SPLIT_CRT;
+    rc = split_init(c->plan.sp, {*A}, {k}, crt ? 0 : (opt.slices > 0 ? opt.slices : SPLIT_S_DEFAULT),
+                    crt ? (opt.slices > 0 ? opt.slices : CRT_N_DEFAULT) : 0, c->plan.hprob,
                     c->plan.dprob, c->stream);
   }
   if (rc == REFINE_OK) rc = capture_graph(c->plan, RUN_CHUNK);
@@ -1046,6 +1053,9 @@ int refine_batch_init(refine_batch** out, int32_t count, const refine_matrix* As
     opt = *optp;
   else
     refine_options_default(&opt);
+  // the modular form serves one problem (its product is bound by the residue
+  // planes' bytes, more than a batch's FP64 product reads)
+  if (opt.precision == REFINE_SPLIT_CRT) return REFINE_EINVAL;
   for (int p = 0; p < count; ++p) {
     if (As[p].kind != REFINE_DENSE) return REFINE_EINVAL;
     int rc = validate_matrix(&As[p], ks[p], opt);
@@ -1074,7 +1084,7 @@ int refine_batch_init(refine_batch** out, int32_t count, const refine_matrix* As
   }
   int rc = build_plan(b->plan, b->As, b->ks, opt, mus, deltas, norms);
   if (rc == REFINE_OK && b->plan.split)
-    rc = split_init(b->plan.sp, b->As, b->ks, opt.slices > 0 ? opt.slices : SPLIT_S_DEFAULT,
+    rc = split_init(b->plan.sp, b->As, b->ks, opt.slices > 0 ? opt.slices : SPLIT_S_DEFAULT, 0,
                     b->plan.hprob, b->plan.dprob, b->stream);
   if (rc == REFINE_OK) rc = capture_graph(b->plan, BATCH_GRAPH_STEPS);
   if (rc == REFINE_OK && hipMalloc((void**)&b->d_xs, sizeof(double*) * 2 * count) != hipSuccess)

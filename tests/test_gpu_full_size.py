@@ -5,10 +5,11 @@ steps per graph for the batch).
 Each case builds the benchmark's own seeded input, runs the GPU path through
 the C ABI and compares with the CPU oracle:
 * dense n = 8192, k = 64 and n = 16384, k = 128: one step, every entry, FP64
-  form against the FP64 oracle step and the split form against the same
-  oracle step (the split product is at least as accurate as FP64, and the
-  two forms agree to a few ulps on these well-separated spectra); n = 8192
-  also over the workload's six steps, with the orthogonality of the result;
+  form against the FP64 oracle step and the two split forms (INT8 slices,
+  and the modular form with 16 moduli) against the same oracle step (the
+  split products are at least as accurate as FP64, and the forms agree to
+  a few ulps on these well-separated spectra); n = 8192 also over the
+  workload's six steps, with the orthogonality of the result;
 * CSR 3-D Laplacian on a 128^3 grid, k = 32: one step, every entry;
 * CSR Kronecker-banded 53^3 (148,877 rows, 70.7 nonzeros per row), k = 5:
   one step, every entry;
@@ -62,7 +63,8 @@ def _dense_case(P, n, k, slices):
     r = oracle.refine_step(A_h, X0_h, norm_a=P.norm_a)
     assert r.status == 0
     _say("n=%d k=%d: oracle step %.1f s" % (n, k, time.perf_counter() - t0))
-    for prec, s in (("fp64", 0), ("split_int8", slices)):
+    for prec, s in (("fp64", 0), ("split_int8", slices), ("split_crt", 16)):
+        _say("n=%d k=%d %s" % (n, k, prec))
         ctx = rf.RefineContext(P.A, k, norm_a=P.norm_a, precision=prec, slices=s)
         X = P.X0.cuda().contiguous().clone()
         st = ctx.step(X)
@@ -99,7 +101,7 @@ def test_full_dense_logspace_n8192_k64_six_steps():
         Xo = r.X
         ref.append((Xo, r.corr_fro))
     orth_o = _orth(Xo)
-    for prec, s in (("fp64", 0), ("split_int8", 9)):
+    for prec, s in (("fp64", 0), ("split_int8", 9), ("split_crt", 16)):
         ctx = rf.RefineContext(P.A, k, norm_a=P.norm_a, precision=prec, slices=s)
         X = P.X0.cuda().contiguous().clone()
         for step, (Xr, cf) in enumerate(ref):
@@ -111,7 +113,7 @@ def test_full_dense_logspace_n8192_k64_six_steps():
         orth = _orth(X.cpu().numpy())
         _say("%s: six steps max |dX| <= %.1e, orthogonality %.3e (oracle %.3e)"
              % (prec, TOL, orth, orth_o))
-        if prec == "split_int8":
+        if prec != "fp64":
             assert orth <= 1e-14
         else:
             assert orth <= 4 * orth_o + 1e-15
