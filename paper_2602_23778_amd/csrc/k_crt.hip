@@ -28,15 +28,19 @@
 // each an INT8 x INT8 product summed exactly in INT32 (|terms| <= 2^14, so
 // n <= 2^17 keeps the sums exact).
 //
-// Reconstruction (Garner, balanced digits).  With P_t = m_0 ... m_{t-1},
-// A'X' = sum_t v_t P_t with v_0 in [-128, 127] and v_t in [-(m_t-1)/2,
-// (m_t-1)/2]; this representation covers exactly [-M/2, M/2) and
-//     v_t = (c_t - sum_{s<t} v_s (P_s mod m_t)) (P_t mod m_t)^-1   (mod m_t),
-// whose inner sum stays below 2^19 in magnitude, so one exact reduction per
-// digit suffices.  The value is then formed by Horner's rule in
-// double-double (exact while it fits 106 bits, relative error below 2^-104
-// beyond), scaled by 2^(E_i + F_j - bA - bX), and a_ii x_ij (an exact
-// product pair) is added with both parts' errors kept: W = (W_hi, W_lo).
+// Reconstruction (Chinese remainder sum).  With e_t = (M/m_t)((M/m_t)^-1 mod
+// m_t) < M (so e_t = 1 mod m_t and 0 modulo the other moduli), the balanced
+// residues c_t of the products give S = sum_t c_t e_t = A'X' (mod M), and
+// A'X' = S - q M with q the integer nearest S/M: |A'X'| <= 2^(L-3) <= M/4
+// puts S/M within 1/4 of q, so an FP64 estimate of S/M rounds to q.  All of
+// it is exact in FP64 pieces: e_t and M are split into four 32-bit pieces,
+// S_k = sum_t c_t e_tk (|S_k| < 2^43) and D_k = S_k - q M_k (|D_k| < 2^44)
+// are exact, and A'X' = sum_k D_k 2^(32k) is summed into a double-double
+// from the top (relative error about 2^-105 when it needs more than 106
+// bits).  The pair is scaled by 2^(E_i + F_j - bA - bX), and a_ii x_ij (an
+// exact product pair) is added with both parts' errors kept:
+// W = (W_hi, W_lo).  Against Garner's mixed radix (N^2/2 modular steps and
+// a Horner evaluation) this is 4N fused multiply-adds per entry.
 //
 // Layouts (bytes).  A's residues: N planes, each tile-major like the slices
 // of the slice form with one digit per value: rows in blocks of BM, per
@@ -45,8 +49,12 @@
 //     ares + t ares_plane + ((b nchp + c) BM + r) 32.
 // X^T's residues: N planes of nchp chunks, each chunk kpad columns of 32
 // bytes: xres + t xres_plane + (c kpad + j) 32.  The residues of the
-// products: N planes of rows_pad x kpad bytes.  Chunks are padded with
-// zeros to a multiple of XG_PAD (nchp), rows to a multiple of 256.
+// products: N planes of rows_pad x kpad bytes, residue t of entry (i, j)
+// at cres + t cres_plane + i kpad + j, so that each wavefront of the product
+// writes whole lines of one plane (an entry-major layout, 16 bytes per
+// entry, made the product's 16 workgroups per line each write back a
+// partial line: 10x the written bytes).  Chunks are padded with zeros to a
+// multiple of XG_PAD (nchp), rows to a multiple of 256.
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -73,39 +81,41 @@ constexpr int CRT_MOD[CRT_N_MAX] = {256, 255, 253, 251, 247, 241, 239, 233,
 constexpr int XG_PAD = 8;
 constexpr int CRT_TILE = 128;
 
-constexpr int cmod(long long a, int m) {
-  long long r = a % m;
-  return (int)(r < 0 ? r + m : r);
+// Constants of the Chinese remainder sum for the first N moduli, in 32-bit
+// pieces held exactly as doubles: e_t = (M/m_t) ((M/m_t)^-1 mod m_t) and M
+// (M < 2^126 for N <= 16, so 128-bit integers hold every value).
+constexpr unsigned __int128 cmul_mod(unsigned __int128 a, unsigned b, unsigned m) {
+  return (a % m) * b % m;
 }
-// Inverse of a modulo m (a and m coprime), by the extended Euclidean algorithm.
-constexpr int cinv(int a, int m) {
-  long long r0 = m, r1 = cmod(a, m), s0 = 0, s1 = 1;
-  while (r1 != 0) {
-    const long long q = r0 / r1, r2 = r0 - q * r1, s2 = s0 - q * s1;
-    r0 = r1;
-    r1 = r2;
-    s0 = s1;
-    s1 = s2;
-  }
-  return cmod(s0, m);
-}
-
-// Garner tables: PM[s][t] = P_s mod m_t (s < t) and PINV[t] = (P_t mod m_t)^-1.
-struct Garner {
-  int pm[CRT_N_MAX][CRT_N_MAX];
-  int pinv[CRT_N_MAX];
-  constexpr Garner() : pm(), pinv() {
-    for (int t = 0; t < CRT_N_MAX; ++t) {
-      long long p = 1;  // P_s mod m_t
-      for (int s = 0; s < t; ++s) {
-        pm[s][t] = (int)p;
-        p = p * CRT_MOD[s] % CRT_MOD[t];
-      }
-      pinv[t] = t == 0 ? 1 : cinv((int)p, CRT_MOD[t]);
+template <int N>
+struct CrtSum {
+  double e[N][4];
+  double mk[4];
+  double m_d;     // M rounded to a double
+  double minv;    // 1 / M rounded
+  constexpr CrtSum() : e(), mk(), m_d(0.0), minv(0.0) {
+    unsigned __int128 M = 1;
+    for (int t = 0; t < N; ++t) M *= (unsigned)CRT_MOD[t];
+    for (int t = 0; t < N; ++t) {
+      const unsigned m = (unsigned)CRT_MOD[t];
+      const unsigned __int128 Mt = M / m;
+      // inverse of Mt modulo m by exponentiation-free search (m <= 256)
+      unsigned r = (unsigned)(Mt % m), inv = 0;
+      for (unsigned c = 1; c < m; ++c)
+        if ((unsigned __int128)r * c % m == 1) {
+          inv = c;
+          break;
+        }
+      const unsigned __int128 et = Mt * inv;
+      for (int k = 0; k < 4; ++k) e[t][k] = (double)(unsigned long long)((et >> (32 * k)) & 0xffffffffu);
     }
+    for (int k = 0; k < 4; ++k) mk[k] = (double)(unsigned long long)((M >> (32 * k)) & 0xffffffffu);
+    double md = 0.0;
+    for (int k = 3; k >= 0; --k) md = md * 4294967296.0 + mk[k];
+    m_d = md;
+    minv = 1.0 / md;
   }
 };
-constexpr Garner GARNER{};
 
 // Balanced residue of an integer-valued double v (|v| < 2^62) modulo m, in
 // [-128, 127] for m = 256 and [-(m-1)/2, (m-1)/2] for odd m.  Both steps are
@@ -137,7 +147,7 @@ struct CrtArgs {
   int64_t ares_plane;
   int8_t* xres;
   int64_t xres_plane;
-  int8_t* cres;
+  int8_t* cres;        // residues of the products, N planes
   int64_t cres_plane;  // rows_pad * kpad
   const double* adiag; // a_ii (rows_pad entries, 0 past n)
   int nchp;            // contraction chunks, padded to a multiple of XG_PAD
@@ -247,20 +257,23 @@ __global__ __launch_bounds__(256) void crt_xres_kernel(const Prob* __restrict__ 
 
 // ---------------------------------------------------------------------------
 // The residue products.  Work item (modulus t = item.split, row block
-// row0 = item.row0 of BM = 32 WAVES W rows); item.k0 < 0 marks an empty slot of
-// the XCD-aware dispatch order.  Wavefront w owns the rows row0 + 32 w .. +31
-// of W and all kpad columns (KT tiles of 32).  Per group of XG 32-wide
-// contraction chunks a wavefront loads its A fragments (16 bytes per lane per
-// chunk) straight from the residue plane into registers, two groups ahead
-// through three register stages (the group loop is unrolled by three so that
-// every stage keeps its registers), and reads the KT X^T fragments of each
-// chunk from LDS, where the block stages X^T's residues a group at a time
-// (double buffered, rows padded to 48 bytes so that the 16-byte fragment
-// reads of 16 lanes fall on distinct banks).  Per group the X^T group of the
-// next step is requested before the A group two steps ahead, so the wait
-// that precedes its LDS store leaves the A requests in flight.  Loads past
-// the last group are clamped to it (valid memory, never used), which keeps
-// the compiler's wait counts exact across the loop.
+// row0 = item.row0 of BM = 32 WAVES W rows); item.k0 < 0 marks an empty slot.
+// Wavefront w owns the rows row0 + 32 w .. +31 of W and all kpad columns (KT
+// tiles of 32).  Per group of XG 32-wide contraction chunks a wavefront loads
+// its A fragments (16 bytes per lane per chunk) straight from the residue
+// plane into registers, and the block its share of the group's X^T residues,
+// both PF groups ahead through PF + 1 register stages (the group loop is
+// unrolled by PF + 1 so that every stage keeps its registers); the X^T group
+// one ahead, requested a group earlier, goes to the LDS stage the next group
+// reads (double buffered, rows padded to 48 bytes so that the 16-byte
+// fragment reads of 16 lanes fall on distinct banks), so the wait before
+// that store is for loads a whole group old.  Loads past the last group are
+// clamped to it (valid memory, never used), which keeps the compiler's wait
+// counts exact across the loop.  A variant that staged X^T only one group
+// ahead spent about 20 % more time (it waited each group for the X^T
+// requests just issued); one that read the X^T fragments straight from
+// memory per wavefront, without LDS, took twice as long (eight wavefronts
+// re-reading each fragment through the vector L1).
 //
 // v_mfma_i32_32x32x32_i8 (gfx950): lane l supplies a[m = l%32][kk = 16(l/32)
 // + b] and b[kk = 16(l/32) + b][n = l%32] for the bytes b of its 16-byte
@@ -268,7 +281,7 @@ __global__ __launch_bounds__(256) void crt_xres_kernel(const Prob* __restrict__ 
 // l%32].  The X^T fragment is the a operand (m = column j of W), the A
 // fragment the b operand (n = row i of W).
 // ---------------------------------------------------------------------------
-template <int KT, int WAVES, int XG>
+template <int KT, int WAVES, int XG, int PF>
 __global__ __launch_bounds__(WAVES * 64) void crt_gemm_kernel(const Prob* __restrict__ probs,
                                                               const GemmItem* __restrict__ items,
                                                               CrtArgs ca) {
@@ -277,6 +290,7 @@ __global__ __launch_bounds__(WAVES * 64) void crt_gemm_kernel(const Prob* __rest
   constexpr int XSTAGE = XG * KP * XROW;      // bytes per stage
   constexpr int XUNITS = XG * KP * 2;         // 16-byte units per stage
   constexpr int XPT = (XUNITS + NT - 1) / NT; // units per thread
+  constexpr int S = PF + 1;                   // register stages
   __shared__ __attribute__((aligned(16))) int8_t xs[2 * XSTAGE];
 
   const GemmItem item = items[blockIdx.x];
@@ -300,8 +314,8 @@ __global__ __launch_bounds__(WAVES * 64) void crt_gemm_kernel(const Prob* __rest
 #pragma unroll
   for (int q = 0; q < KT; ++q) acc[q] = v16i{};
 
-  v4i a0[XG], a1[XG], a2[XG];
-  u4v xr[XPT];
+  v4i a[S][XG];
+  u4v x[S][XPT];
   auto load_a = [&](v4i(&dst)[XG], int g) {
     g = min(g, ngroups - 1);
 #pragma unroll
@@ -309,28 +323,31 @@ __global__ __launch_bounds__(WAVES * 64) void crt_gemm_kernel(const Prob* __rest
       dst[cc] = __builtin_nontemporal_load(
           gld(reinterpret_cast<const v4i*>(Ab + (int64_t)(g * XG + cc) * CRT_TILE * 32)));
   };
-  auto load_x = [&](int g) {
+  auto load_x = [&](u4v(&dst)[XPT], int g) {
     g = min(g, ngroups - 1);
 #pragma unroll
     for (int u = 0; u < XPT; ++u) {
       const int e = min(tid + u * NT, XUNITS - 1);
-      xr[u] = *gld(reinterpret_cast<const u4v*>(Xp + (int64_t)g * XG * KP * 32 + e * 16));
+      dst[u] = *gld(reinterpret_cast<const u4v*>(Xp + (int64_t)g * XG * KP * 32 + e * 16));
     }
   };
-  auto store_x = [&](int8_t* dst) {
+  auto store_x = [&](const u4v(&src)[XPT], int8_t* dst) {
 #pragma unroll
     for (int u = 0; u < XPT; ++u) {
       const int e = tid + u * NT;
       if (e < XUNITS) {
         const int row = e >> 1;  // chunk-in-group * KP + column
-        *reinterpret_cast<u4v*>(dst + row * XROW + (e & 1) * 16) = xr[u];
+        *reinterpret_cast<u4v*>(dst + row * XROW + (e & 1) * 16) = src[u];
       }
     }
   };
-  auto group = [&](int g, const v4i(&cur)[XG], v4i(&ahead)[XG]) {
+  // group g (register stage g % S): request the X^T and A groups PF ahead,
+  // multiply group g, store the X^T group one ahead for the next group
+  auto group = [&](int g, const v4i(&cur)[XG], v4i(&ahead)[XG], const u4v(&xnext)[XPT],
+                   u4v(&xahead)[XPT]) {
     const int8_t* xst = xs + (g & 1) * XSTAGE;
-    load_x(g + 1);
-    load_a(ahead, g + 2);
+    load_x(xahead, g + PF);
+    load_a(ahead, g + PF);
 #pragma unroll
     for (int cc = 0; cc < XG; ++cc) {
 #pragma unroll
@@ -340,22 +357,26 @@ __global__ __launch_bounds__(WAVES * 64) void crt_gemm_kernel(const Prob* __rest
         acc[q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(xf, cur[cc], acc[q], 0, 0, 0);
       }
     }
-    store_x(xs + ((g + 1) & 1) * XSTAGE);
+    store_x(xnext, xs + ((g + 1) & 1) * XSTAGE);
     __syncthreads();
   };
 
-  load_x(0);
-  load_a(a0, 0);
-  store_x(xs);
-  load_a(a1, 1);
+#pragma unroll
+  for (int u = 0; u < PF; ++u) {
+    load_x(x[u], u);
+    load_a(a[u], u);
+  }
+  store_x(x[0], xs);
   __syncthreads();
-  for (int g = 0; g < ngroups; g += 3) {
-    group(g, a0, a2);
-    if (g + 1 < ngroups) group(g + 1, a1, a0);
-    if (g + 2 < ngroups) group(g + 2, a2, a1);
+  for (int g = 0; g < ngroups; g += S) {
+#pragma unroll
+    for (int u = 0; u < S; ++u)
+      if (g + u < ngroups) group(g + u, a[u], a[(u + PF) % S], x[(u + 1) % S], x[(u + PF) % S]);
   }
 
-  // residues of the INT32 sums (|sum| <= n 2^14 < 2^31), one byte each
+  // residues of the INT32 sums (|sum| <= n 2^14 < 2^31), one byte each;
+  // registers 4 g4 .. 4 g4 + 3 of tile q hold the columns 32 q + 8 g4 +
+  // 4 (l/32) + 0..3 of row i
   const int m = CRT_MOD[t];
   const double inv = 1.0 / (double)m;
   const int i = wrow + (lane & 31);
@@ -367,7 +388,6 @@ __global__ __launch_bounds__(WAVES * 64) void crt_gemm_kernel(const Prob* __rest
       int r4[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) r4[e] = bal_res((double)acc[q][4 * g4 + e], m, inv);
-      // registers 4 g4 .. 4 g4 + 3 hold the columns 32 q + 8 g4 + 4 (l/32) + 0..3
       *gst(reinterpret_cast<unsigned*>(out + 32 * q + 8 * g4 + 4 * (lane >> 5))) =
           pack4(r4[0], r4[1], r4[2], r4[3]);
     }
@@ -383,62 +403,98 @@ __global__ __launch_bounds__(256) void crt_recon_kernel(const Prob* __restrict__
                                                         const RowItem* __restrict__ items,
                                                         int rrows, CrtArgs ca) {
   constexpr int NT = 256;
-  __shared__ double red[2 * NT];
+  constexpr CrtSum<N> K{};
+  __shared__ double red[8 * NT];
   const Prob& P = probs[0];
   if (P.ctrl->stopped) return;
   const int blk = items[blockIdx.x].blk;
-  const int n = P.n, k = P.k, kpad = P.kpad, kp = pow2ceil(k), tr = NT / kp;
-  const int tid = threadIdx.x, j = tid % kp, trow = tid / kp;
+  const int n = P.n, k = P.k, kpad = P.kpad;
+  // thread (trow, quad): columns 4 quad .. 4 quad + 3 of the rows trow,
+  // trow + tr, ...; the Rayleigh partials then go through the column layout
+  // of rayleigh_block_partial (thread (row, column) of pow2ceil(k) columns)
+  const int nq = kpad / 4, tr = NT / nq;
+  const int tid = threadIdx.x, quad = tid % nq, trow = tid / nq;
   const int r0 = blk * rrows, r1 = min(n, r0 + rrows);
-  const int sbase = j < k ? P.xexp[j] - ca.ba - ca.bx : 0;
-  double sxw = 0.0, sxx = 0.0;
-  for (int i = r0 + trow; i < r1; i += tr) {
-    if (j >= k) continue;
-    int c[N];
+  int sbase[4];
 #pragma unroll
-    for (int t = 0; t < N; ++t) c[t] = *gld(ca.cres + t * ca.cres_plane + (int64_t)i * kpad + j);
-    // balanced mixed-radix digits (Garner)
-    int v[N];
-    v[0] = c[0];
-#pragma unroll
-    for (int t = 1; t < N; ++t) {
-      int s = 0;
-#pragma unroll
-      for (int u = 0; u < t; ++u) s += v[u] * GARNER.pm[u][t];
-      const int m = CRT_MOD[t];
-      // |c - s| < 2^19, times pinv < 2^8: exact in int32 and in double
-      v[t] = bal_res((double)((c[t] - s) * GARNER.pinv[t]), m, 1.0 / CRT_MOD[t]);
-    }
-    // Horner in double-double from the leading digit
-    double h = (double)v[N - 1], l = 0.0;
-#pragma unroll
-    for (int t = N - 2; t >= 0; --t) {
-      double p, pe;
-      two_prod(h, (double)CRT_MOD[t], p, pe);
-      double s, se;
-      two_sum(p, (double)v[t], s, se);
-      const double lo = l * (double)CRT_MOD[t] + (pe + se);
-      two_sum(s, lo, h, l);
-    }
-    const int sc = sbase + *gld(P.aexp + i);
-    h = ldexp(h, sc);
-    l = ldexp(l, sc);
-    // + a_ii x_ij: (h, l) + (p, pe), both parts' errors kept
-    const double x = *gld(P.x + (int64_t)i * P.ldx + j);
-    double p, pe, s1, e1, s2, e2, wh, wl;
-    two_prod(*gld(ca.adiag + i), x, p, pe);
-    two_sum(h, p, s1, e1);
-    two_sum(l, pe, s2, e2);
-    e1 += s2;
-    two_sum(s1, e1, s1, e1);
-    e1 += e2;
-    two_sum(s1, e1, wh, wl);
-    P.w[(int64_t)i * k + j] = wh;
-    P.wlo[(int64_t)i * k + j] = wl;
-    sxw = __builtin_fma(x, wh, sxw);
-    sxx = __builtin_fma(x, x, sxx);
+  for (int e = 0; e < 4; ++e) {
+    const int j = 4 * quad + e;
+    sbase[e] = (trow < tr && j < k) ? P.xexp[j] - ca.ba - ca.bx : 0;
   }
-  rayleigh_block_partial<NT>(P, blk, sxw, sxx, red);
+  double sxw[4] = {0.0, 0.0, 0.0, 0.0}, sxx[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = r0 + trow; i < r1 && trow < tr; i += tr) {
+    unsigned raw[N];
+#pragma unroll
+    for (int t = 0; t < N; ++t)
+      raw[t] = *gld(reinterpret_cast<const unsigned*>(ca.cres + t * ca.cres_plane +
+                                                     (int64_t)i * kpad + 4 * quad));
+    const int ea = *gld(P.aexp + i);
+    const double dii = *gld(ca.adiag + i);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int j = 4 * quad + e;
+      if (j >= k) continue;
+      // S_k = sum_t c_t e_tk, exact (|S_k| < 2^43)
+      double S[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int t = 0; t < N; ++t) {
+        const double c = (double)(int)(int8_t)((raw[t] >> (8 * e)) & 0xffu);
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) S[kk] = __builtin_fma(c, K.e[t][kk], S[kk]);
+      }
+      // q = round(S / M); D_k = S_k - q M_k exact; A'X' = sum_k D_k 2^(32 k)
+      const double sapp =
+          ((S[3] * 4294967296.0 + S[2]) * 4294967296.0 + S[1]) * 4294967296.0 + S[0];
+      const double q = __builtin_rint(sapp * K.minv);
+      double D[4];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) D[kk] = __builtin_fma(-q, K.mk[kk], S[kk]);
+      double h = D[3] * 0x1p96, l = 0.0;
+#pragma unroll
+      for (int kk = 2; kk >= 0; --kk) {
+        double s1, e1;
+        two_sum(h, D[kk] * (kk == 2 ? 0x1p64 : kk == 1 ? 0x1p32 : 1.0), s1, e1);
+        e1 += l;
+        two_sum(s1, e1, h, l);
+      }
+      const int sc = sbase[e] + ea;
+      h = ldexp(h, sc);
+      l = ldexp(l, sc);
+      // + a_ii x_ij: (h, l) + (p, pe), both parts' errors kept
+      const double xv = *gld(P.x + (int64_t)i * P.ldx + j);
+      double p, pe, s1, e1, s2, e2, wh, wl;
+      two_prod(dii, xv, p, pe);
+      two_sum(h, p, s1, e1);
+      two_sum(l, pe, s2, e2);
+      e1 += s2;
+      two_sum(s1, e1, s1, e1);
+      e1 += e2;
+      two_sum(s1, e1, wh, wl);
+      P.w[(int64_t)i * k + j] = wh;
+      P.wlo[(int64_t)i * k + j] = wl;
+      sxw[e] = __builtin_fma(xv, wh, sxw[e]);
+      sxx[e] = __builtin_fma(xv, xv, sxx[e]);
+    }
+  }
+  // column sums of the block (the Rayleigh partials): thread (trow, quad)
+  // holds its 4 columns at red[trow kpad + 4 quad + e] = red[4 tid + e]; the
+  // rows of threads are then added in a fixed order, so the sums do not
+  // depend on scheduling
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    red[4 * tid + e] = trow < tr ? sxw[e] : 0.0;
+    red[4 * NT + 4 * tid + e] = trow < tr ? sxx[e] : 0.0;
+  }
+  __syncthreads();
+  for (int c = tid; c < k; c += NT) {
+    double a = 0.0, b = 0.0;
+    for (int r = 0; r < tr; ++r) {
+      a += red[r * kpad + c];
+      b += red[4 * NT + r * kpad + c];
+    }
+    P.dpart[(int64_t)blk * 2 * k + c] = a;
+    P.dpart[(int64_t)blk * 2 * k + k + c] = b;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -450,9 +506,9 @@ constexpr int CRT_RROWS = 32;  // rows per reconstruction block
 // Launch shapes of the residue products: wavefronts per block (32 W rows
 // each) and chunks per group.  The tuner times each at init.
 struct CrtShape {
-  int waves, xg;
+  int waves, xg, pf;
 };
-constexpr CrtShape CRT_SHAPES[] = {{4, 4}, {4, 8}, {8, 4}, {8, 8}, {4, 2}};
+constexpr CrtShape CRT_SHAPES[] = {{8, 2, 2}, {8, 2, 3}, {8, 1, 4}, {8, 4, 2}, {4, 2, 3}, {4, 4, 2}};
 constexpr int CRT_NSHAPES = sizeof(CRT_SHAPES) / sizeof(CRT_SHAPES[0]);
 
 int rows_pad_of(int64_t n) { return (int)((n + SPLIT_ROW_PAD - 1) / SPLIT_ROW_PAD * SPLIT_ROW_PAD); }
@@ -473,22 +529,26 @@ CrtArgs args_of(const SplitPlan& sp, int64_t n) {
   return ca;
 }
 
-template <int KT, int WAVES, int XG>
+template <int KT, int WAVES, int XG, int PF>
 void launch_gemm_shape(const SplitPlan& sp, const Prob* dprob, const CrtArgs& ca, hipStream_t st) {
-  hipLaunchKernelGGL((crt_gemm_kernel<KT, WAVES, XG>), dim3(sp.nitems), dim3(WAVES * 64), 0, st,
-                     dprob, sp.items, ca);
+  hipLaunchKernelGGL((crt_gemm_kernel<KT, WAVES, XG, PF>), dim3(sp.nitems), dim3(WAVES * 64), 0,
+                     st, dprob, sp.items, ca);
 }
 
 template <int KT>
 hipError_t launch_gemm_kt(const SplitPlan& sp, const Prob* dprob, const CrtArgs& ca,
                           hipStream_t st) {
   const CrtShape s = CRT_SHAPES[sp.crt_shape];
-  if (s.waves == 4 && s.xg == 4) launch_gemm_shape<KT, 4, 4>(sp, dprob, ca, st);
-  else if (s.waves == 4 && s.xg == 8) launch_gemm_shape<KT, 4, 8>(sp, dprob, ca, st);
-  else if (s.waves == 8 && s.xg == 4) launch_gemm_shape<KT, 8, 4>(sp, dprob, ca, st);
-  else if (s.waves == 8 && s.xg == 8) launch_gemm_shape<KT, 8, 8>(sp, dprob, ca, st);
-  else if (s.waves == 4 && s.xg == 2) launch_gemm_shape<KT, 4, 2>(sp, dprob, ca, st);
-  else return hipErrorInvalidValue;
+#define RFK_SHAPE(W, G, F) \
+  if (s.waves == W && s.xg == G && s.pf == F) launch_gemm_shape<KT, W, G, F>(sp, dprob, ca, st); else
+  RFK_SHAPE(8, 2, 2)
+  RFK_SHAPE(8, 2, 3)
+  RFK_SHAPE(8, 1, 4)
+  RFK_SHAPE(8, 4, 2)
+  RFK_SHAPE(4, 2, 3)
+  RFK_SHAPE(4, 4, 2)
+  { return hipErrorInvalidValue; }
+#undef RFK_SHAPE
   return hipGetLastError();
 }
 
@@ -542,28 +602,20 @@ hipError_t upload_items(T** dst, const std::vector<T>& v) {
   return hipMemcpy(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice);
 }
 
-// Product items for blocks of bm rows, XCD-aware: the (modulus, row block)
-// pairs in modulus-major order are cut into eight contiguous ranges, and
-// range x takes the dispatch slots x, x + 8, x + 16, ... (workgroups go to
-// the eight XCDs in turn), so that each XCD works through one or two moduli
-// at a time and keeps their X^T residues in its own L2.
+// Product items for blocks of bm rows: the (modulus, row block) pairs in
+// modulus-major order, so that the blocks running together share one or a
+// few moduli, whose X^T residues every XCD's L2 then holds.  Giving each XCD
+// a contiguous range of the pairs instead (dispatch slot s to XCD s % 8)
+// measured 2-8 % slower.
 std::vector<GemmItem> product_items(int nmod, int64_t n, int bm) {
   const int nrb = (int)((n + bm - 1) / bm);
-  const int total = nmod * nrb;
-  const int per = (total + 7) / 8;
-  std::vector<GemmItem> gi((size_t)per * 8);
-  for (int s = 0; s < per * 8; ++s) {
-    const int x = s % 8, u = s / 8;
-    const int lin = x * per + u;
+  std::vector<GemmItem> gi((size_t)nmod * nrb);
+  for (int lin = 0; lin < nmod * nrb; ++lin) {
     GemmItem g{};
-    if (lin < total) {
-      g.split = lin / nrb;
-      g.row0 = (lin % nrb) * bm;
-      g.k0 = 0;
-    } else {
-      g.k0 = -1;
-    }
-    gi[s] = g;
+    g.split = lin / nrb;
+    g.row0 = (lin % nrb) * bm;
+    g.k0 = 0;
+    gi[lin] = g;
   }
   return gi;
 }
@@ -620,12 +672,12 @@ int crt_init(SplitPlan& sp, const refine_matrix& A, int k, int nmod, std::vector
   const int64_t nch = (n + 31) / 32, nchp = (nch + XG_PAD - 1) / XG_PAD * XG_PAD;
   sp.ares_plane = (int64_t)rows_pad * nchp * 32;
   sp.xres_plane = nchp * sp.kpad * 32;
-  const int64_t cres_plane = (int64_t)rows_pad * sp.kpad;
+  const int64_t cres_bytes = (int64_t)rows_pad * sp.kpad * nmod;
   if (hipMalloc((void**)&sp.ares, (size_t)sp.ares_plane * nmod) != hipSuccess ||
       hipMalloc((void**)&sp.aexp, sizeof(int32_t) * rows_pad) != hipSuccess ||
       hipMalloc((void**)&sp.adiag, sizeof(double) * rows_pad) != hipSuccess ||
       hipMalloc((void**)&sp.xres, (size_t)sp.xres_plane * nmod) != hipSuccess ||
-      hipMalloc((void**)&sp.cres, (size_t)cres_plane * nmod) != hipSuccess)
+      hipMalloc((void**)&sp.cres, (size_t)cres_bytes) != hipSuccess)
     return REFINE_ENOMEM;
   hipError_t e = hipMemsetAsync(sp.xres, 0, (size_t)sp.xres_plane * nmod, st);
   if (e == hipSuccess) {
@@ -690,9 +742,9 @@ int crt_init(SplitPlan& sp, const refine_matrix& A, int k, int nmod, std::vector
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
       if (getenv("REFINE_LOG") && atoi(getenv("REFINE_LOG")) >= 2)
-        fprintf(stderr, "refine: tune crt n=%lld k=%d N=%d shape %d (waves %d, group %d): %.1f us\n",
+        fprintf(stderr, "refine: tune crt n=%lld k=%d N=%d shape %d (waves %d, group %d, ahead %d): %.1f us\n",
                 (long long)n, k, nmod, sh, CRT_SHAPES[sh].waves, CRT_SHAPES[sh].xg,
-                t * 1000.f / 3.f);
+                CRT_SHAPES[sh].pf, t * 1000.f / 3.f);
       if (e == hipSuccess && t < best_t) {
         best_t = t;
         best = sh;

@@ -66,7 +66,7 @@ struct SplitPlan {
   int64_t ares_plane = 0;     // bytes per plane
   int8_t* xres = nullptr;     // residues of X^T, crt planes of nch x kpad x 32 bytes
   int64_t xres_plane = 0;
-  int8_t* cres = nullptr;     // residues of A'X', crt planes of n x kpad bytes
+  int8_t* cres = nullptr;     // residues of A'X', 16 bytes per entry (rows_pad x kpad)
   RowItem* rec_items = nullptr;   // (problem, row block) of the reconstruction
   int n_rec = 0;
 };
