@@ -6,11 +6,16 @@ Q^T with Q a product of 16384 seeded Householder reflectors, lam iid U[0,
 the true eigenvectors rounded to FP32.  A step is the whole hot path: W = A X,
 Rayleigh quotients, residual, compact-WY factors, correction matrix, WY
 update and normalisation, replayed as one HIP graph.  `value` is the main
-form's refined eigenvectors per second (k / seconds per step); the other form
-(FP64 or split: INT8 slices on the matrix cores, double-double W) runs on the
-same input and is reported in config.split with the speed ratio.  The first
-step of both forms is compared with the double-double oracle step and the
-FP64 oracle step; orthogonality is measured in extended precision.
+form's refined eigenvectors per second (k / seconds per step).  The main form
+(--precision, default crt) is the modular split form: W = A X through 16
+INT8 residue products on the matrix cores and a Chinese-remainder
+reconstruction into a double-double W (Ozaki scheme II).  The other two forms
+run on the same input and are reported beside it: FP64 (config.fp64) and the
+slice split form (INT8 digit slices, config.split), each with its speed ratio
+against FP64.  The first step of every form is compared with the
+double-double oracle step and the FP64 oracle step, and orthogonality is
+measured in extended precision after all timed steps; meets_targets says
+whether a form reached both accuracy targets (1e-13 and 1e-14).
 
 Other workloads (--workload):
   logspace     dense n = 8192, k = 64, log-spaced spectrum, gap ratio 1.05;
@@ -177,34 +182,42 @@ def _form_slices(args, prec):
     return {"fp64": 0, "split_int8": args.slices, "split_crt": args.moduli}[prec]
 
 
-def _product_roofline(prec, n, k, s, ms_prod):
-    """Roofline of the form's product, timed with HIP events on the context's
-    stream: FP64 against the FP64 matrix peak (AI = k/4 flop/B past the
-    ridge); the slice form against the INT8 peak (s(s+1)/2 products, the
-    binding unit at these k); the modular form against HBM (s residue planes
-    of n^2 bytes, each read once by one INT8 product of AI = 2k op/B, below
-    the INT8 ridge of 625)."""
+# The dominant kernel of each form's product (index in the launch order that
+# refine_time_product_parts reports) and the roofline it is held to.
+DOMINANT = {"fp64": 0, "split_int8": 2, "split_crt": 2}
+
+
+def _kpad(k):
+    return (k + 31) // 32 * 32
+
+
+def _product_roofline(prec, n, k, s, ms_kernel):
+    """Roofline of the dominant kernel of the form's product, from its mean
+    launch time (HIP events on the context's stream): the FP64 GEMM against
+    the FP64 matrix peak (2 n^2 k flops; AI = k/4 flop/B is past the ridge);
+    the slice products against the INT8 peak (s(s+1)/2 products of 2 n^2 k
+    operations); the residue products of the modular form against HBM: they
+    read the s residue planes of A (n^2 bytes each) and of X (n kpad bytes
+    each) and write the s residue planes of the products (n kpad bytes each),
+    at 2 kpad operations per byte of A, below the INT8 ridge of 625."""
     flops = 2.0 * n * n * k
     if prec == "fp64":
-        eff = flops / (ms_prod * 1e-3) / 1e12
+        eff = flops / (ms_kernel * 1e-3) / 1e12
         return {"bound": "mfma", "achieved": eff, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": eff / FP64_PEAK_TFLOPS, "traffic": _traffic_for("gemm_f64_dense", n, k)}
     if prec == "split_int8":
-        tops = s * (s + 1) / 2 * flops / (ms_prod * 1e-3) / 1e12
+        tops = s * (s + 1) / 2 * flops / (ms_kernel * 1e-3) / 1e12
         return {"bound": "mfma", "achieved": tops, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
                 "frac": tops / INT8_PEAK_TOPS, "traffic": None}
-    byts = _crt_bytes(n, k, s)
-    gbs = byts / (ms_prod * 1e-3) / 1e9
+    byts = _crt_gemm_bytes(n, k, s)
+    gbs = byts / (ms_kernel * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": gbs / HBM_PEAK_GBS, "traffic": _traffic_for("crt", n, k)}
+            "frac": gbs / HBM_PEAK_GBS, "traffic": _traffic_for("crt_gemm", n, k)}
 
 
-def _crt_bytes(n, k, nmod):
-    """Algorithmic bytes of the modular product: the nmod residue planes of A
-    (n^2 bytes each) and of X (n k bytes each) read, the residues of the nmod
-    products (n k bytes each) written and read back, X read twice (column
-    maxima, residues) and W written as a pair (16 n k)."""
-    return nmod * (n * n + 3.0 * n * k) + 16.0 * n * k + 16.0 * n * k
+def _crt_gemm_bytes(n, k, nmod):
+    """Algorithmic bytes of one launch of the modular form's residue products."""
+    return nmod * (float(n) * n + 2.0 * n * _kpad(k))
 
 
 def bench_dense(args, rf, torch, np):
@@ -248,14 +261,16 @@ def bench_dense(args, rf, torch, np):
         X = X0.clone()
         sec, st1, st_last, X_first = _time_steps(ctx, X, args.steps, args.warmup, torch)
         _progress("%s form timed: %.4f ms per step" % (prec, sec * 1e3))
-        # the product W = A X alone, timed with HIP events on the context's
-        # stream, same launch configuration as inside the step
+        # the product W = A X alone, and each of its kernels, timed with HIP
+        # events on the context's stream, same launch configuration as
+        # inside the step
         ms_prod = ctx.time_product(X0.clone(), args.product_reps)
+        parts = ctx.time_product_parts(X0.clone(), args.product_reps)
         rr_ms = _time_rayleigh_ritz(ctx, X0, torch) if prec == main_prec else None
         ctx.close()
         res[prec] = {"slices": s, "sec": sec, "st1": st1, "st_last": st_last,
                      "X_first": X_first.cpu().numpy(), "ms_prod": ms_prod, "rr_ms": rr_ms,
-                     "orth": _orthogonality(X.cpu().numpy())}
+                     "parts": parts, "orth": _orthogonality(X.cpu().numpy())}
 
     errs = {p: {} for p in forms}
     cpu = None
@@ -287,10 +302,12 @@ def bench_dense(args, rf, torch, np):
 
     def block(p):
         r = res[p]
+        dom = r["parts"][DOMINANT[p]]
         b = {"precision": p, "slices": r["slices"], "eigvecs_per_s": k / r["sec"],
              "ms_per_step": r["sec"] * 1e3, "product_us": r["ms_prod"] * 1e3,
+             "product_kernels_us": [t * 1e3 for t in r["parts"]],
              "product_eff_gflops": flops / (r["ms_prod"] * 1e-3) / 1e9,
-             "product_roofline": _product_roofline(p, n, k, r["slices"], r["ms_prod"]),
+             "product_roofline": _product_roofline(p, n, k, r["slices"], dom),
              "corr_fro_first": r["st1"].corr_fro, "corr_fro_last": r["st_last"].corr_fro,
              "resid_rel_last": r["st_last"].resid_rel, "orthogonality_last": r["orth"]}
         b.update(errs[p])
@@ -555,7 +572,7 @@ def main() -> int:
     ap.add_argument("--k", type=int, default=0)
     ap.add_argument("--count", type=int, default=512, help="batch: number of problems")
     ap.add_argument("--sample", type=int, default=8, help="batch: problems checked on the CPU")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "split", "crt"],
+    ap.add_argument("--precision", default="crt", choices=["fp64", "split", "crt"],
                     help="dense: the main form (the other two run on the same input)")
     ap.add_argument("--slices", type=int, default=0,
                     help="split slices (default 9; 10 for the clustered batch)")

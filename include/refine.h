@@ -242,6 +242,23 @@ int refine_destroy(refine_ctx* ctx);
  * copy of W is overwritten, so call it between steps, not inside one. */
 int refine_time_product(refine_ctx* ctx, double* X, int64_t ldx, int32_t reps, float* ms);
 
+/* Measurement hook, per kernel: as refine_time_product, but the kernels of
+ * the product are timed one by one (HIP events on the context's stream
+ * between consecutive launches), after one untimed launch of the whole
+ * product.  ms[i] receives the mean time of the product's i-th kernel over
+ * `reps` launches (1 <= reps <= 64), in launch order:
+ *   FP64 dense: the GEMM (refine_time_product leaves the K-split sum out
+ *     alike);
+ *   REFINE_SPLIT_INT8: column maxima of |X|, slicing of X, the slice
+ *     products, and the K-split sum when there is one;
+ *   REFINE_SPLIT_CRT: column maxima of |X|, residues of X, the residue
+ *     products, the reconstruction of W;
+ *   CSR: the SpMM.
+ * *nparts receives the number of kernels (at most max_parts are stored).
+ * X is only read; call it between steps. */
+int refine_time_product_parts(refine_ctx* ctx, double* X, int64_t ldx, int32_t reps, float* ms,
+                              int32_t max_parts, int32_t* nparts);
+
 /* Batched problems (independent dense A_p, n_p x n_p, with k_p targets):
  * every step of every problem runs in one grouped launch per kernel, over
  * (problem, tile) work items, and the whole step is one HIP graph.  Options

@@ -62,7 +62,7 @@ EXPORTS = ("refine_options_default", "refine_init", "refine_step", "refine_run",
            "refine_get_info", "refine_destroy", "refine_batch_init", "refine_batch_run",
            "refine_batch_destroy", "refine_status_string", "refine_time_product",
            "refine_batch_time_product", "refine_rayleigh_ritz", "refine_batch_rayleigh_ritz",
-           "refine_sign_flip", "refine_batch_sign_flip")
+           "refine_sign_flip", "refine_batch_sign_flip", "refine_time_product_parts")
 
 _lib = None
 
@@ -95,6 +95,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.refine_batch_run.argtypes = [vp, P(vp), P(i64), i32, P(refine_stats)]
     lib.refine_batch_destroy.argtypes = [vp]
     lib.refine_time_product.argtypes = [vp, vp, i64, i32, P(ctypes.c_float)]
+    lib.refine_time_product_parts.argtypes = [vp, vp, i64, i32, P(ctypes.c_float), i32, P(i32)]
     lib.refine_rayleigh_ritz.argtypes = [vp, vp, i64]
     lib.refine_batch_rayleigh_ritz.argtypes = [vp, P(vp), P(i64), P(i32)]
     lib.refine_sign_flip.argtypes = [vp, vp, i64, P(i32)]
@@ -108,7 +109,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                  "refine_batch_init", "refine_batch_run", "refine_batch_destroy",
                  "refine_batch_time_product", "refine_rayleigh_ritz",
                  "refine_batch_rayleigh_ritz", "refine_time_product", "refine_sign_flip",
-                 "refine_batch_sign_flip"):
+                 "refine_batch_sign_flip", "refine_time_product_parts"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -159,6 +160,13 @@ def refine_time_product(ctx, X_ptr: int, ldx: int, reps: int):
     ms = ctypes.c_float()
     rc = _l().refine_time_product(ctx, X_ptr, ldx, reps, ctypes.byref(ms))
     return rc, ms.value
+
+
+def refine_time_product_parts(ctx, X_ptr: int, ldx: int, reps: int, max_parts: int = 8):
+    ms = (ctypes.c_float * max_parts)()
+    n = ctypes.c_int32()
+    rc = _l().refine_time_product_parts(ctx, X_ptr, ldx, reps, ms, max_parts, ctypes.byref(n))
+    return rc, [ms[i] for i in range(min(n.value, max_parts))]
 
 
 def refine_batch_time_product(b, reps: int):
@@ -330,6 +338,15 @@ class RefineContext:
         rc, ms = refine_time_product(self._ctx, X.data_ptr(), X.stride(0), reps)
         if rc != OK:
             raise RefineError(rc, "refine_time_product")
+        return ms
+
+    def time_product_parts(self, X: torch.Tensor, reps: int):
+        """Mean milliseconds of each kernel of the product W = A X, in launch
+        order (include/refine.h lists the kernels of each form)."""
+        self._check_x(X)
+        rc, ms = refine_time_product_parts(self._ctx, X.data_ptr(), X.stride(0), reps)
+        if rc != OK:
+            raise RefineError(rc, "refine_time_product_parts")
         return ms
 
     def debug_product(self):

@@ -559,6 +559,7 @@ hipError_t launch_all_n(const SplitPlan& sp, const Prob* dprob, const CrtArgs& c
   hipLaunchKernelGGL((crt_xres_kernel<N>), dim3(grid), dim3(256), 0, st, dprob, ca);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  product_mark(st);
   switch (sp.kpad / 32) {
     case 1: e = launch_gemm_kt<1>(sp, dprob, ca, st); break;
     case 2: e = launch_gemm_kt<2>(sp, dprob, ca, st); break;
@@ -567,9 +568,12 @@ hipError_t launch_all_n(const SplitPlan& sp, const Prob* dprob, const CrtArgs& c
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;
+  product_mark(st);
   hipLaunchKernelGGL((crt_recon_kernel<N>), dim3(sp.n_rec), dim3(256), 0, st, dprob, sp.rec_items,
                      sp.crt_rrows, ca);
-  return hipGetLastError();
+  e = hipGetLastError();
+  product_mark(st);
+  return e;
 }
 
 template <int N>

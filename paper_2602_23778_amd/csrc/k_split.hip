@@ -799,6 +799,7 @@ int split_rows_per_block(int k) { return 32 * layout_for(k).wm; }
 hipError_t split_xmax(const SplitPlan& sp, const Prob* dprob, hipStream_t st) {
   hipLaunchKernelGGL(split_xmax_kernel, dim3(std::min(sp.n_xmax, 8192)), dim3(256), 0, st, dprob,
                      sp.xmax_items, sp.n_xmax);
+  product_mark(st);
   return hipGetLastError();
 }
 
@@ -813,14 +814,17 @@ hipError_t split_product(const SplitPlan& sp, const Prob* dprob, hipStream_t st)
   hipError_t e;
   if ((e = split_xmax(sp, dprob, st)) != hipSuccess) return e;
   if ((e = launch_xslice(sp.s, dprob, sp.xsl_items, sp.n_xsl, st)) != hipSuccess) return e;
+  product_mark(st);
   if ((e = launch_product(sp.s, layout_for(sp.kmax), sp.variant, dprob, sp.items, sp.nitems, st)) !=
       hipSuccess)
     return e;
+  product_mark(st);
   if (sp.ks > 1) {
     const int64_t nk = sp.nk0;
     const int grid = (int)std::min<int64_t>((nk + 255) / 256, 4096);
     hipLaunchKernelGGL(split_wsum_kernel, dim3(grid), dim3(256), 0, st, dprob);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    product_mark(st);
   }
   return hipSuccess;
 }

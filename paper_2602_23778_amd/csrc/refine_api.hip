@@ -840,6 +840,21 @@ int refine_init(refine_ctx** out, const refine_matrix* A, int32_t k, const refin
   return REFINE_OK;
 }
 
+// Events of refine_time_product_parts: one before each timed launch of the
+// product and one after each of its kernels (product_mark).
+constexpr int PART_MAX = 8;        // kernels of one product launch, at most
+constexpr int PART_REPS_MAX = 64;  // timed launches per call
+struct PartTimer {
+  hipEvent_t ev[(PART_MAX + 1) * PART_REPS_MAX] = {};
+  int cap = 0, used = 0;
+  bool overflow = false;
+  void destroy() {
+    for (hipEvent_t& v : ev)
+      if (v) (void)hipEventDestroy(v), v = nullptr;
+  }
+};
+static PartTimer* g_part_timer = nullptr;
+
 // Steps enqueued without statistics leave an error status in the control
 // word, where later steps see it and do nothing.  Every call that resets the
 // control word first reports such a status (and clears it), so that an error
@@ -1022,6 +1037,66 @@ int refine_time_product(refine_ctx* c, double* X, int64_t ldx, int32_t reps, flo
   (void)hipEventDestroy(e1);
   if (e != hipSuccess) return REFINE_EHIP;
   *ms = t / (float)reps;
+  if (launch_ctrl_reset(c->plan.dprob, 1, 0, 0.0, c->stream) != hipSuccess) return REFINE_EHIP;
+  return REFINE_OK;
+}
+
+int refine_time_product_parts(refine_ctx* c, double* X, int64_t ldx, int32_t reps, float* ms,
+                              int32_t max_parts, int32_t* nparts) {
+  if (!c || reps <= 0 || reps > PART_REPS_MAX || !ms || max_parts <= 0 || !nparts)
+    return REFINE_EINVAL;
+  int rc = set_x(c, X, ldx);
+  if (rc != REFINE_OK) return rc;
+  if ((rc = take_pending(c, nullptr)) != REFINE_OK) return rc;
+  if (launch_ctrl_reset(c->plan.dprob, 1, 0, 0.0, c->stream) != hipSuccess) return REFINE_EHIP;
+  Plan& pl = c->plan;
+  PartTimer tm;
+  hipError_t e = hipSuccess;
+  const int cap = (PART_MAX + 1) * reps;
+  for (int i = 0; i < cap && e == hipSuccess; ++i) e = hipEventCreate(&tm.ev[i]);
+  if (e != hipSuccess) {
+    tm.destroy();
+    return REFINE_EHIP;
+  }
+  tm.cap = cap;
+  // a warm-up launch, then reps launches, each bracketed by its own events
+  auto one = [&]() -> hipError_t {
+    if (pl.csr) {
+      hipError_t r = launch_spmm(pl.dprob, pl.spmm_items, pl.n_spmm, pl.hprob[0].k, pl.spmm_lanes,
+                                 c->stream);
+      product_mark(c->stream);
+      return r;
+    }
+    if (pl.split) return split_product(pl.sp, pl.dprob, c->stream);
+    hipError_t r = launch_gemm_f64(pl.dprob, pl.gemm_items, pl.n_gemm, pl.kmax, pl.vec2,
+                                   pl.gemm_cfg, c->stream);
+    product_mark(c->stream);
+    return r;
+  };
+  e = one();
+  int parts = 0;
+  for (int r = 0; r < reps && e == hipSuccess; ++r) {
+    const int first = tm.used;
+    e = hipEventRecord(tm.ev[tm.used++], c->stream);
+    g_part_timer = &tm;
+    if (e == hipSuccess) e = one();
+    g_part_timer = nullptr;
+    const int p = tm.used - first - 1;
+    if (r == 0) parts = p;
+    if (p != parts || tm.overflow) e = hipErrorInvalidValue;
+  }
+  if (e == hipSuccess) e = hipEventSynchronize(tm.ev[tm.used - 1]);
+  std::vector<double> sum(parts, 0.0);
+  for (int r = 0; r < reps && e == hipSuccess; ++r)
+    for (int i = 0; i < parts && e == hipSuccess; ++i) {
+      float t = 0.f;
+      e = hipEventElapsedTime(&t, tm.ev[r * (parts + 1) + i], tm.ev[r * (parts + 1) + i + 1]);
+      sum[i] += t;
+    }
+  tm.destroy();
+  if (e != hipSuccess) return REFINE_EHIP;
+  *nparts = parts;
+  for (int i = 0; i < parts && i < max_parts; ++i) ms[i] = (float)(sum[i] / reps);
   if (launch_ctrl_reset(c->plan.dprob, 1, 0, 0.0, c->stream) != hipSuccess) return REFINE_EHIP;
   return REFINE_OK;
 }
@@ -1297,3 +1372,16 @@ extern "C" int refine_debug_workspace(const refine_ctx* c, void** out, int32_t c
   for (int i = 0; i < 9 && i < count; ++i) out[i] = v[i];
   return REFINE_OK;
 }
+
+
+namespace rfk {
+void product_mark(hipStream_t st) {
+  PartTimer* t = g_part_timer;
+  if (!t) return;
+  if (t->used >= t->cap) {
+    t->overflow = true;
+    return;
+  }
+  (void)hipEventRecord(t->ev[t->used++], st);
+}
+}  // namespace rfk

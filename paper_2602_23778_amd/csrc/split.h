@@ -95,6 +95,10 @@ int crt_init(SplitPlan& sp, const refine_matrix& A, int k, int nmod, std::vector
 // Column maxima and residues of X, the residue products and the
 // reconstruction of W (hi, lo) with the Rayleigh partials.
 hipError_t crt_product(const SplitPlan& sp, const Prob* dprob, hipStream_t st);
+// Measurement hook of refine_time_product_parts (in refine_api.hip): while a
+// timing is armed, records an event on `st` after each launch of the
+// product; otherwise does nothing.
+void product_mark(hipStream_t st);
 // Column maxima of |X| for both forms, and row exponents of A (in k_split.hip).
 hipError_t split_xmax(const SplitPlan& sp, const Prob* dprob, hipStream_t st);
 hipError_t split_aexp(const refine_matrix& A, int rows_pad, int32_t* aexp, hipStream_t st);
