@@ -259,6 +259,28 @@ int refine_time_product(refine_ctx* ctx, double* X, int64_t ldx, int32_t reps, f
 int refine_time_product_parts(refine_ctx* ctx, double* X, int64_t ldx, int32_t reps, float* ms,
                               int32_t max_parts, int32_t* nparts);
 
+/* One refinement step that allocates nothing, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the step of refine_step for a dense FP64
+ * problem, with every buffer it needs beyond A and X (descriptor, work items,
+ * W, the update, the block partials, the k x k area, the control word) in a
+ * static 64 MiB array the library keeps on each GPU until the process ends.
+ * No context: each call starts from scratch (a first step; no divergence
+ * history, no warm start of the k x k solve) and uses a fixed launch
+ * configuration.  A, X (device, X updated in place, ld ldx >= k), k and the
+ * options as for refine_init and refine_step, except: precision FP64 only;
+ * target LARGEST_ABS or SHIFT (mu = options.shift); options.norm_a must be
+ * given (> 0), since ||A||_inf would need a host round trip.  The whole
+ * workspace must fit the array: about 16 n k + 8 (2k^2 + k) min(n, 64 row
+ * blocks) bytes plus small tables (n k up to about 2^21 at k = 128); a larger
+ * problem returns REFINE_EINVAL.  Work is enqueued on hip_stream.  stats ==
+ * NULL: no host synchronisation, and a failed step is not reported (X is
+ * left unchanged by a rejected correction); otherwise the stream is
+ * synchronised, *stats filled and the step's status returned.  Calls that
+ * overlap on one GPU share the array and race. */
+int refine_step_static(const refine_matrix* A, int32_t k, const refine_options* opt, double* X,
+                       int64_t ldx, void* hip_stream, refine_stats* stats);
+
 /* Batched problems (independent dense A_p, n_p x n_p, with k_p targets):
  * every step of every problem runs in one grouped launch per kernel, over
  * (problem, tile) work items, and the whole step is one HIP graph.  Options

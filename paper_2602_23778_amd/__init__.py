@@ -62,7 +62,8 @@ EXPORTS = ("refine_options_default", "refine_init", "refine_step", "refine_run",
            "refine_get_info", "refine_destroy", "refine_batch_init", "refine_batch_run",
            "refine_batch_destroy", "refine_status_string", "refine_time_product",
            "refine_batch_time_product", "refine_rayleigh_ritz", "refine_batch_rayleigh_ritz",
-           "refine_sign_flip", "refine_batch_sign_flip", "refine_time_product_parts")
+           "refine_sign_flip", "refine_batch_sign_flip", "refine_time_product_parts",
+           "refine_step_static")
 
 _lib = None
 
@@ -96,6 +97,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.refine_batch_destroy.argtypes = [vp]
     lib.refine_time_product.argtypes = [vp, vp, i64, i32, P(ctypes.c_float)]
     lib.refine_time_product_parts.argtypes = [vp, vp, i64, i32, P(ctypes.c_float), i32, P(i32)]
+    lib.refine_step_static.argtypes = [P(refine_matrix), i32, P(refine_options), vp, i64, vp,
+                                       P(refine_stats)]
     lib.refine_rayleigh_ritz.argtypes = [vp, vp, i64]
     lib.refine_batch_rayleigh_ritz.argtypes = [vp, P(vp), P(i64), P(i32)]
     lib.refine_sign_flip.argtypes = [vp, vp, i64, P(i32)]
@@ -109,7 +112,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                  "refine_batch_init", "refine_batch_run", "refine_batch_destroy",
                  "refine_batch_time_product", "refine_rayleigh_ritz",
                  "refine_batch_rayleigh_ritz", "refine_time_product", "refine_sign_flip",
-                 "refine_batch_sign_flip", "refine_time_product_parts"):
+                 "refine_batch_sign_flip", "refine_time_product_parts", "refine_step_static"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -243,6 +246,23 @@ def make_options(precision="fp64", target="largest_abs", shift=0.0, delta_c=10.0
     o.normalize = 1 if normalize else 0
     o.slices = int(slices)
     return o
+
+
+def step_static(A: torch.Tensor, X: torch.Tensor, k: int, stream=None, sync: bool = True,
+                **options):
+    """One step through refine_step_static (no allocation, no context): A
+    dense (n, n) float64 on the GPU, X (n, k) float64 updated in place;
+    options as make_options (norm_a required).  Returns (status, Stats or
+    None)."""
+    _require_cuda(A, torch.float64, "A")
+    _require_cuda(X, torch.float64, "X")
+    m = refine_matrix()
+    m.kind, m.n, m.a, m.lda = DENSE, A.shape[0], A.data_ptr(), A.stride(0)
+    o = make_options(**options)
+    st = refine_stats()
+    rc = _l().refine_step_static(ctypes.byref(m), k, ctypes.byref(o), X.data_ptr(), X.stride(0),
+                                 _stream_handle(stream), ctypes.byref(st) if sync else None)
+    return rc, (Stats(st.corr_fro, st.resid_rel, st.iters, st.status) if sync else None)
 
 
 @dataclass

@@ -1373,6 +1373,196 @@ extern "C" int refine_debug_workspace(const refine_ctx* c, void** out, int32_t c
   return REFINE_OK;
 }
 
+// ---------------------------------------------------------------------------
+// One step without any allocation (refine_step_static).
+//
+// Every piece of device memory the step needs beyond A and X -- the problem
+// descriptor, the work-item tables and the workspace (W, the update, the
+// block partials, the k x k area and the control word) -- lives in the
+// file-scope array below, carved up per call.  Host code never passes the
+// array's name to a kernel: its device address on the current GPU comes from
+// hipGetSymbolAddress on the first call made on that GPU and is kept per
+// device.  A setup kernel writes the descriptor and the items and clears the
+// workspace (a fill kernel, not a memset, so that a caller may capture the
+// call in a graph), then the step's kernels run as in refine_step with a
+// fixed launch configuration (no tuner, no K split).  Every call on a GPU
+// uses that GPU's array: calls that overlap on one GPU race.
+// ---------------------------------------------------------------------------
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)64 << 20;  // 64 MiB per GPU
+static __device__ __align__(256) char scratch[STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int STATIC_GEMM_CFG = 3;   // 4 wavefronts, 64 rows per block, 32-row K chunks
+constexpr int STATIC_MAX_GRAM_BLOCKS = 64;
+constexpr int STATIC_MAX_DEVICES = 64;
+char* g_scratch[STATIC_MAX_DEVICES] = {};
+
+__global__ void static_setup_kernel(Prob p, Prob* dprob, GemmItem* gi, int n_gemm, int bm,
+                                    RowItem* ri, int n_row, RowItem* gri, int n_gram,
+                                    GramRedItem* rr, int n_gred, double* ws, int64_t ws_words) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t T = (int64_t)gridDim.x * blockDim.x;
+  if (tid == 0) *dprob = p;
+  for (int64_t i = tid; i < n_gemm; i += T) {
+    GemmItem g{};
+    g.row0 = (int)i * bm;
+    g.k1 = p.n;
+    gi[i] = g;
+  }
+  for (int64_t i = tid; i < n_row; i += T) ri[i] = RowItem{0, (int)i};
+  for (int64_t i = tid; i < n_gram; i += T) gri[i] = RowItem{0, (int)i};
+  for (int64_t i = tid; i < n_gred; i += T) rr[i] = GramRedItem{0, (int)i * 64};
+  for (int64_t i = tid; i < ws_words; i += T) ws[i] = 0.0;
+}
+
+struct StaticLayout {
+  Shape s;
+  int n_gemm, n_row, n_gram, n_gred, gh;
+  size_t o_prob, o_gemm, o_row, o_gram, o_gred, o_ws;
+  size_t o_w, o_xn, o_part, o_dpart, o_gpart, o_kk, o_kpp, o_vec, o_ctrl, total;
+};
+
+StaticLayout static_layout(int64_t n, int k) {
+  StaticLayout L{};
+  L.s = choose_shape(n, k, true, false);
+  // Gram blocks: at most STATIC_MAX_GRAM_BLOCKS, so that their k x k partials
+  // stay a small part of the array
+  const int64_t per = (n + STATIC_MAX_GRAM_BLOCKS - 1) / STATIC_MAX_GRAM_BLOCKS;
+  L.s.gbrows = (int)std::max<int64_t>(L.s.gbrows, (per + 3) / 4 * 4);
+  L.s.ngb = iceil(n, L.s.gbrows);
+  L.s.ksplit = 1;
+  L.gh = gram_halves(k);
+  L.n_gemm = iceil(n, gemm_rows_per_block(STATIC_GEMM_CFG));
+  L.n_row = L.s.nrb;
+  L.n_gram = L.s.ngb * L.gh;
+  L.n_gred = iceil(2 * (int64_t)k * k + k, 64);
+  size_t o = 0;
+  L.o_prob = o;  o += align_up(sizeof(Prob));
+  L.o_gemm = o;  o += align_up(sizeof(GemmItem) * L.n_gemm);
+  L.o_row = o;   o += align_up(sizeof(RowItem) * L.n_row);
+  L.o_gram = o;  o += align_up(sizeof(RowItem) * L.n_gram);
+  L.o_gred = o;  o += align_up(sizeof(GramRedItem) * L.n_gred);
+  L.o_ws = o;
+  const size_t nk = (size_t)n * k * sizeof(double);
+  L.o_w = o;     o += align_up(nk);
+  L.o_xn = o;    o += align_up(nk);
+  L.o_part = o;  o += align_up((size_t)L.s.nrb * 5 * k * sizeof(double));
+  L.o_dpart = o; o += align_up((size_t)std::max(L.n_gemm, L.s.nrb) * 2 * k * sizeof(double));
+  L.o_gpart = o; o += align_up((size_t)L.s.ngb * (2 * k * k + k) * sizeof(double));
+  L.o_kk = o;    o += align_up((size_t)KK_COUNT * k * k * sizeof(double));
+  L.o_kpp = o;   o += align_up((size_t)(16 + 16 * k) * sizeof(double));
+  L.o_vec = o;   o += align_up((size_t)VEC_COUNT * k * sizeof(double));
+  L.o_ctrl = o;  o += align_up(sizeof(Ctrl));
+  L.total = o;
+  return L;
+}
+
+// The array's device address on the current GPU (hipGetSymbolAddress once
+// per device, with that device current).
+int static_scratch(char** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= STATIC_MAX_DEVICES) return REFINE_EHIP;
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return REFINE_EHIP;
+    g_scratch[dev] = (char*)p;
+  }
+  *out = g_scratch[dev];
+  return REFINE_OK;
+}
+
+}  // namespace
+
+extern "C" int refine_step_static(const refine_matrix* A, int32_t k, const refine_options* optp,
+                                  double* X, int64_t ldx, void* hip_stream, refine_stats* stats) {
+  refine_options opt;
+  if (optp)
+    opt = *optp;
+  else
+    refine_options_default(&opt);
+  if (!A || A->kind != REFINE_DENSE || !A->a || A->n <= 0 || A->n >= (int64_t)1 << 31 ||
+      A->lda < A->n || k < 1 || k > KMAX || (int64_t)k >= A->n || !X || ldx < k)
+    return REFINE_EINVAL;
+  if (opt.precision != REFINE_FP64 || !(opt.norm_a > 0.0) || !(opt.delta_c >= 0.0) ||
+      (opt.target != REFINE_TARGET_LARGEST_ABS && opt.target != REFINE_TARGET_SHIFT))
+    return REFINE_EINVAL;
+  const int64_t n = A->n;
+  const StaticLayout L = static_layout(n, k);
+  if (L.total > STATIC_SCRATCH_BYTES) return REFINE_EINVAL;
+  char* base = nullptr;
+  int rc = static_scratch(&base);
+  if (rc != REFINE_OK) return rc;
+  hipStream_t st = (hipStream_t)hip_stream;
+
+  Prob P;
+  memset(&P, 0, sizeof(P));
+  P.a = A->a;
+  P.lda = A->lda;
+  P.x = X;
+  P.ldx = ldx;
+  P.n = (int32_t)n;
+  P.k = k;
+  P.kind = REFINE_DENSE;
+  P.ksplit = 1;
+  P.nrb = L.s.nrb;
+  P.rbrows = L.s.rbrows;
+  P.ngb = L.s.ngb;
+  P.gbrows = L.s.gbrows;
+  P.w = (double*)(base + L.o_w);
+  P.xn = (double*)(base + L.o_xn);
+  P.part = (double*)(base + L.o_part);
+  P.dpart = (double*)(base + L.o_dpart);
+  P.ndp = L.n_gemm;
+  P.gpart = (double*)(base + L.o_gpart);
+  P.kk = (double*)(base + L.o_kk);
+  P.kpp = (double*)(base + L.o_kpp);
+  P.vec = (double*)(base + L.o_vec);
+  P.ctrl = (Ctrl*)(base + L.o_ctrl);
+  P.mu = opt.target == REFINE_TARGET_SHIFT ? opt.shift : 0.0;
+  P.delta = opt.delta_c * opt.norm_a * UNIT_ROUNDOFF;
+  P.norm_a = opt.norm_a;
+  P.beta_zero = opt.beta == REFINE_BETA_ZERO;
+  P.normalize = opt.normalize != 0;
+  Prob* dprob = (Prob*)(base + L.o_prob);
+  GemmItem* gi = (GemmItem*)(base + L.o_gemm);
+  RowItem* ri = (RowItem*)(base + L.o_row);
+  RowItem* gri = (RowItem*)(base + L.o_gram);
+  GramRedItem* rr = (GramRedItem*)(base + L.o_gred);
+  const int64_t ws_words = (int64_t)((L.total - L.o_ws) / sizeof(double));
+  const bool vec2 = !((A->lda & 1) || (n & 1) || ((uintptr_t)A->a & 15));
+  const bool fused = k <= 32, pipeline = k > KXK_ONE_WG_MAX;
+
+  hipLaunchKernelGGL(static_setup_kernel, dim3(1024), dim3(256), 0, st, P, dprob, gi, L.n_gemm,
+                     gemm_rows_per_block(STATIC_GEMM_CFG), ri, L.n_row, gri, L.n_gram, rr, L.n_gred,
+                     (double*)(base + L.o_ws), ws_words);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = launch_ctrl_reset(dprob, 1, 0, 0.0, st);
+  if (e == hipSuccess) e = launch_gemm_f64(dprob, gi, L.n_gemm, k, vec2, STATIC_GEMM_CFG, st);
+  if (e == hipSuccess) e = launch_fin_d(dprob, 1, st);
+  if (e == hipSuccess) e = launch_gram(dprob, gri, L.n_gram, k, st);
+  if (e == hipSuccess) e = launch_gram_reduce(dprob, rr, L.n_gred, st);
+  if (e == hipSuccess) e = launch_kxk(dprob, 1, k, pipeline, st);
+  if (fused) {
+    if (e == hipSuccess) e = launch_fin_pre(dprob, 1, st);
+    if (e == hipSuccess) e = launch_update(dprob, ri, L.n_row, k, true, st);
+  } else {
+    if (e == hipSuccess) e = launch_update(dprob, ri, L.n_row, k, false, st);
+    if (e == hipSuccess) e = launch_fin_stats(dprob, 1, st);
+    if (e == hipSuccess) e = launch_normalize(dprob, ri, L.n_row, st);
+  }
+  if (e != hipSuccess) return REFINE_EHIP;
+  if (!stats) return REFINE_OK;
+  Ctrl c;
+  e = hipMemcpyAsync(&c, base + L.o_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return REFINE_EHIP;
+  stats->corr_fro = c.corr_fro;
+  stats->resid_rel = c.resid_rel;
+  stats->iters = c.iters;
+  stats->status = c.status;
+  return c.status;
+}
 
 namespace rfk {
 void product_mark(hipStream_t st) {
