@@ -220,6 +220,19 @@ def _crt_gemm_bytes(n, k, nmod):
     return nmod * (float(n) * n + 2.0 * n * _kpad(k))
 
 
+def _product_only(ctx, X0, args, torch, info):
+    """Counter runs: one plain copy of 2 GiB (a kernel of known size, for
+    calibrating byte counters), then --product-reps launches of the product
+    alone; prints their mean time."""
+    buf = torch.empty(1 << 28, dtype=torch.float64, device=X0.device)
+    cp = buf.clone()           # reads and writes 2 GiB
+    torch.cuda.synchronize()
+    del cp, buf
+    ms = ctx.time_product(X0.clone(), args.product_reps)
+    info.update({"product_ms": ms, "copy_bytes": 1 << 31})
+    print(json.dumps(info), flush=True)
+
+
 def bench_dense(args, rf, torch, np):
     import synth
     dev = "cuda:0"
@@ -241,13 +254,8 @@ def bench_dense(args, rf, torch, np):
     if args.product_only:
         ctx = rf.RefineContext(A, k, norm_a=P.norm_a, precision=main_prec,
                                slices=_form_slices(args, main_prec))
-        Acopy = A.clone()          # reads and writes 8 n^2 bytes
-        torch.cuda.synchronize()
-        del Acopy
-        ms = ctx.time_product(X0.clone(), args.product_reps)
-        print(json.dumps({"product_ms": ms, "n": n, "k": k, "precision": main_prec,
-                          "slices": _form_slices(args, main_prec), "copy_bytes": 8 * n * n}),
-              flush=True)
+        _product_only(ctx, X0, args, torch, {"n": n, "k": k, "precision": main_prec,
+                                             "slices": _form_slices(args, main_prec)})
         ctx.close()
         return None
 
@@ -353,6 +361,10 @@ def bench_laplacian(args, rf, torch, np):
     C = rf.CsrMatrix(n, dev(L.row_ptr), dev(L.col_idx), dev(L.val))
     ctx = rf.RefineContext(C, k, target="smallest", norm_a=L.sigma)
     X0 = dev(X0h)
+    if args.product_only:
+        _product_only(ctx, X0, args, torch, {"n": n, "k": k, "nnz": nnz})
+        ctx.close()
+        return None
     X = X0.clone()
     sec, st1, st_last, X_first = _time_steps(ctx, X, args.steps, args.warmup, torch)
     ms_prod = ctx.time_product(X0.clone(), args.product_reps)
@@ -399,6 +411,10 @@ def bench_kron(args, rf, torch, np):
     C = rf.CsrMatrix(n, dev(K.row_ptr), dev(K.col_idx), dev(K.val))
     ctx = rf.RefineContext(C, k, norm_a=K.sigma)
     X0 = dev(X0h)
+    if args.product_only:
+        _product_only(ctx, X0, args, torch, {"n": n, "k": k, "nnz": nnz})
+        ctx.close()
+        return None
     X = X0.clone()
     sec, st1, st_last, X_first = _time_steps(ctx, X, args.steps, args.warmup, torch)
     ms_prod = ctx.time_product(X0.clone(), args.product_reps)
@@ -584,9 +600,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--product-reps", type=int, default=20)
     ap.add_argument("--product-only", action="store_true",
-                    help="counter runs (dense): one copy of A (a plain copy kernel of known "
-                         "size, for calibrating byte counters) then --product-reps launches of "
-                         "the product alone; prints their mean time")
+                    help="counter runs (dense, laplacian, kron): one copy of 2 GiB (a plain "
+                         "copy kernel of known size, for calibrating byte counters) then "
+                         "--product-reps launches of the product alone; prints their mean time")
     args = ap.parse_args()
     if args.slices == 0:
         args.slices = 10 if args.workload == "batch" else 9
@@ -609,8 +625,12 @@ def main() -> int:
             return 0
     elif args.workload == "laplacian":
         r = bench_laplacian(args, rf, torch, np)
+        if r is None:
+            return 0
     elif args.workload == "kron":
         r = bench_kron(args, rf, torch, np)
+        if r is None:
+            return 0
     elif args.workload == "smallest_abs":
         r = bench_smallest_abs(args, rf, torch, np)
     else:

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "librefine.so")
 ARCH = os.environ.get("REFINE_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["k_gemm.hip", "k_step.hip", "k_kxk.hip", "k_csr.hip", "k_split.hip", "k_crt.hip", "k_rr.hip", "k_flip.hip",
-           "refine_api.hip"]
+           "tune_cache.hip", "refine_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for all device code.

@@ -62,6 +62,7 @@
 
 #include "dev_util.h"
 #include "split.h"
+#include "tune_cache.h"
 
 namespace rfk {
 
@@ -721,6 +722,12 @@ int crt_init(SplitPlan& sp, const refine_matrix& A, int k, int nmod, std::vector
     const int v = atoi(env);
     if (v >= 0 && v < CRT_NSHAPES) best = v;
   }
+  const std::vector<int64_t> key{n, k, nmod};
+  if (best < 0) {
+    std::vector<int> hit;
+    if (tune_cache_get("crt", key, &hit) && hit.size() == 1 && hit[0] >= 0 && hit[0] < CRT_NSHAPES)
+      best = hit[0];
+  }
   if (best < 0) {
     const double* saved_x = hp[0].x;
     const int64_t saved_ld = hp[0].ldx;
@@ -760,6 +767,7 @@ int crt_init(SplitPlan& sp, const refine_matrix& A, int k, int nmod, std::vector
     hp[0].ldx = saved_ld;
     if (e != hipSuccess || best < 0) return REFINE_EHIP;
     sp.ms = best_t / 3.f;
+    tune_cache_put("crt", key, {best});
     if (getenv("REFINE_LOG"))
       fprintf(stderr, "refine: crt product n=%lld k=%d N=%d: shape %d, %.1f us\n", (long long)n, k,
               nmod, best, best_t * 1000.f / 3.f);

@@ -44,6 +44,7 @@
 
 #include "dev_util.h"
 #include "split.h"
+#include "tune_cache.h"
 
 namespace rfk {
 
@@ -752,20 +753,6 @@ std::vector<GemmItem> split_items(const std::vector<Prob>& hp, int bm, int ks, i
   return gi;
 }
 
-struct SplitKey {
-  int64_t n;
-  int k, s, np;
-  bool operator<(const SplitKey& o) const {
-    if (n != o.n) return n < o.n;
-    if (k != o.k) return k < o.k;
-    if (s != o.s) return s < o.s;
-    return np < o.np;
-  }
-};
-std::map<SplitKey, std::pair<int, int>>& split_tune_cache() {
-  static std::map<SplitKey, std::pair<int, int>> m;
-  return m;
-}
 
 template <class T>
 hipError_t upload_vec(T** dst, const std::vector<T>& v) {
@@ -968,12 +955,13 @@ int split_init(SplitPlan& sp, const std::vector<refine_matrix>& As, const std::v
       best_var = got == 2 ? var : 0;
     }
   }
-  const SplitKey key{np == 1 ? As[0].n : nsum, kmax, s, np};
+  const std::vector<int64_t> key{np == 1 ? As[0].n : nsum, kmax, s, np};
   if (!best_ks) {
-    auto hit = split_tune_cache().find(key);
-    if (hit != split_tune_cache().end()) {
-      best_ks = hit->second.first;
-      best_var = hit->second.second;
+    std::vector<int> hit;
+    if (tune_cache_get("split", key, &hit) && hit.size() == 2 && hit[0] >= 1 &&
+        hit[0] <= ks_cap && fits(hit[0]) && hit[1] >= 0 && hit[1] <= 2) {
+      best_ks = hit[0];
+      best_var = hit[1];
     }
   }
   if (!best_ks) {
@@ -1012,7 +1000,7 @@ int split_init(SplitPlan& sp, const std::vector<refine_matrix>& As, const std::v
         }
         if (getenv("REFINE_LOG") && atoi(getenv("REFINE_LOG")) >= 2)
           fprintf(stderr, "refine: tune split np=%d n=%lld k=%d s=%d variant %d ks %d: %.1f us\n",
-                  np, (long long)key.n, kmax, s, var, ksp, t * 1000.f / 3.f);
+                  np, (long long)key[0], kmax, s, var, ksp, t * 1000.f / 3.f);
         if (t < best) {
           best = t;
           best_ks = ksp;
@@ -1026,10 +1014,10 @@ int split_init(SplitPlan& sp, const std::vector<refine_matrix>& As, const std::v
       hp[p].ldx = saved[p].second;
     }
     sp.ms = best / 3.f;
-    split_tune_cache()[key] = {best_ks, best_var};
+    tune_cache_put("split", key, {best_ks, best_var});
     if (getenv("REFINE_LOG"))
       fprintf(stderr, "refine: split product np=%d n=%lld k=%d s=%d: variant %d, K split %d, %.1f us\n",
-              np, (long long)key.n, kmax, s, best_var, best_ks, best * 1000.f / 3.f);
+              np, (long long)key[0], kmax, s, best_var, best_ks, best * 1000.f / 3.f);
   }
   if (!best_ks) {
     split_free(sp);

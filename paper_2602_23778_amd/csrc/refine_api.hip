@@ -21,6 +21,7 @@
 #include "refine.h"
 #include "refine_debug.h"
 #include "split.h"
+#include "tune_cache.h"
 
 namespace rfk {
 hipError_t launch_gemm_f64(const Prob*, const GemmItem*, int, int, bool, int, hipStream_t);
@@ -281,18 +282,6 @@ int install_gemm(Plan& pl, const std::vector<refine_matrix>& As, int cfg, int ks
   return upload_square_descs(pl);
 }
 
-// Tuning cache: (n, k, vector width) -> (launch configuration, K split).
-struct TuneKey {
-  int64_t n;
-  int k, vec2;
-  bool operator<(const TuneKey& o) const {
-    return n != o.n ? n < o.n : (k != o.k ? k < o.k : vec2 < o.vec2);
-  }
-};
-std::map<TuneKey, std::pair<int, int>>& tune_cache() {
-  static std::map<TuneKey, std::pair<int, int>> m;
-  return m;
-}
 
 // Picks the product's launch configuration: REFINE_GEMM="cfg,ks" forces one;
 // batches use a fixed configuration; a single problem times every
@@ -306,12 +295,16 @@ int choose_gemm(Plan& pl, const std::vector<refine_matrix>& As, bool single,
         ks <= shapes[0].ksplit)
       return install_gemm(pl, As, cfg, single ? ks : 1);
   }
+  // tuning-cache key: (n, k, vector width) of one problem; a batch by its
+  // total size, count and largest k
   int64_t nsum = 0;
   for (const auto& a : As) nsum += a.n;
-  const TuneKey key{single ? As[0].n : -nsum - (int64_t)As.size(), single ? pl.hprob[0].k : pl.kmax,
-                    pl.vec2 ? 1 : 0};
-  auto hit = tune_cache().find(key);
-  if (hit != tune_cache().end()) return install_gemm(pl, As, hit->second.first, hit->second.second);
+  const std::vector<int64_t> key{single ? As[0].n : -nsum - (int64_t)As.size(),
+                                 single ? pl.hprob[0].k : pl.kmax, pl.vec2 ? 1 : 0};
+  std::vector<int> hit;
+  if (tune_cache_get("gemm_f64", key, &hit) && hit.size() == 2 && hit[0] >= 0 &&
+      hit[0] < gemm_num_cfgs() && hit[1] >= 1 && hit[1] <= (single ? shapes[0].ksplit : 1))
+    return install_gemm(pl, As, hit[0], hit[1]);
   // time the candidates on a zero X (the workspace copy of the update)
   Prob& P = pl.hprob[0];
   std::vector<std::pair<double*, int64_t>> saved;
@@ -367,7 +360,7 @@ int choose_gemm(Plan& pl, const std::vector<refine_matrix>& As, bool single,
     pl.hprob[q].x = saved[q].first;
     pl.hprob[q].ldx = saved[q].second;
   }
-  tune_cache()[key] = {best_cfg, best_ks};
+  tune_cache_put("gemm_f64", key, {best_cfg, best_ks});
   pl.gemm_ms = best / 3.f;
   if (getenv("REFINE_LOG"))
     fprintf(stderr, "refine: product n=%lld k=%d: cfg %d, K split %d, %.1f us\n", (long long)As[0].n,
