@@ -89,9 +89,13 @@ __global__ __launch_bounds__(WAVES * 64) void gemm_f64_t_kernel(const Prob* __re
         const double* p = A + (int64_t)kk * lda;
         if (VECA && RT == 2) {
           typedef double v2d __attribute__((ext_vector_type(2)));
-          // (even n here: jl <= n - 2 for every valid pair)
+          // the pair (jl, jl + 1), clamped to the last pair (n - 2, n - 1) of
+          // the row; for odd n the lane whose jl is the last column n - 1
+          // takes the pair's second entry (its second column, n, is never
+          // stored).  Rows of odd leading dimension make every other pair
+          // 8-byte aligned only, which gfx9 global loads accept.
           const v2d v = __builtin_nontemporal_load(gld(reinterpret_cast<const v2d*>(p + min(jl, n - 2))));
-          dst[s][0] = v.x;
+          dst[s][0] = jl == n - 1 ? v.y : v.x;
           dst[s][RT - 1] = v.y;
         } else {
 #pragma unroll

@@ -414,8 +414,10 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
     }
     bytes += b;
     if (As[p].kind == REFINE_DENSE) {
-      // pairs of columns per lane: aligned rows, and no pair straddling n
-      if ((As[p].lda & 1) || (As[p].n & 1) || ((uintptr_t)As[p].a & 15)) pl.vec2 = false;
+      // pairs of columns per lane: any n and leading dimension (an odd one
+      // leaves every other row's pairs 8-byte aligned, which the loads
+      // accept), A itself at least 8-byte aligned
+      if ((uintptr_t)As[p].a & 7) pl.vec2 = false;
     }
   }
   const size_t ctrl_off = bytes;
@@ -1523,7 +1525,7 @@ extern "C" int refine_step_static(const refine_matrix* A, int32_t k, const refin
   RowItem* gri = (RowItem*)(base + L.o_gram);
   GramRedItem* rr = (GramRedItem*)(base + L.o_gred);
   const int64_t ws_words = (int64_t)((L.total - L.o_ws) / sizeof(double));
-  const bool vec2 = !((A->lda & 1) || (n & 1) || ((uintptr_t)A->a & 15));
+  const bool vec2 = ((uintptr_t)A->a & 7) == 0;
   const bool fused = k <= 32, pipeline = k > KXK_ONE_WG_MAX;
 
   hipLaunchKernelGGL(static_setup_kernel, dim3(1024), dim3(256), 0, st, P, dprob, gi, L.n_gemm,
