@@ -373,7 +373,7 @@ def bench_laplacian(args, rf, torch, np):
     byts = 12.0 * nnz + 4.0 * (n + 1) + 16.0 * n * k
     gbs = byts / (ms_prod * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": gbs / HBM_PEAK_GBS, "traffic": None}
+            "frac": gbs / HBM_PEAK_GBS, "traffic": _traffic_for("spmm_csr", n, k)}
     Xg = X.cpu().numpy()
     cfg = {"workload": "CSR FP64, 3-D 7-point Laplacian %d^3 (n=%d, nnz=%d), diagonal 6 + "
                        "dx+dy+dz with d* iid U[0, 1/3), k=%d smallest via the Gershgorin shift"
@@ -423,7 +423,7 @@ def bench_kron(args, rf, torch, np):
     byts = 12.0 * nnz + 4.0 * (n + 1) + 16.0 * n * k
     gbs = byts / (ms_prod * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": gbs / HBM_PEAK_GBS, "traffic": None}
+            "frac": gbs / HBM_PEAK_GBS, "traffic": _traffic_for("spmm_csr", n, k)}
     Xg = X.cpu().numpy()
     cfg = {"workload": "CSR FP64, Kronecker product of three banded %d x %d factors "
                        "(half-bandwidths 2, 2, 1; n=%d, nnz=%d, %.1f per row), k=%d largest |lambda|"

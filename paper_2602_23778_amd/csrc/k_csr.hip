@@ -19,16 +19,18 @@ namespace rfk {
 // Rows per chunk of the SpMM (a block takes every gridDim-th chunk).
 constexpr int SPMM_ROWS = 256;
 
-// Vector form: G lanes per row, four columns per lane (k <= 4 G), so an X
-// row gather is G lanes x 32 bytes (two 16-byte loads per lane when X rows
-// are 16-byte aligned) and a wavefront gathers 64 / G rows per instruction.
-// Per chunk the block first copies the chunk's row pointers and, when they
-// fit (at most NZL), its column indices and values into LDS with coalesced
-// loads, so a row round costs one dependent trip to memory (the X gathers)
-// instead of three.  A row's G nonzeros of a round are gathered together
-// (the lanes past the row's end use a = 0 and the row's own X row, adding
-// exact zeros); the sum runs in CSR order.  Chunks are taken block-strided
-// as in the scalar form; the block's Rayleigh partial goes to
+// Vector form: G lanes per row, four columns per lane (k <= 4 G) as two
+// pairs, columns 2 gl, 2 gl + 1 and 2 G + 2 gl, 2 G + 2 gl + 1 of lane gl,
+// so that one 16-byte load instruction takes whole 128-byte lines of G x 16
+// bytes from each of the 64 / G rows it touches (four consecutive columns per
+// lane would touch twice the lines, each half used: 5 % slower at 128^3,
+// k = 32).  Per chunk the block first copies the chunk's row pointers and,
+// when they fit (at most NZL), its column indices and values into LDS with
+// coalesced loads, so a row round costs one dependent trip to memory (the X
+// gathers) instead of three.  A row's G nonzeros of a round are gathered
+// together; slots past the row's end load nothing (on the 7-point stencil,
+// one slot in eight), and the sum runs in CSR order.  Chunks are taken
+// block-strided as in the scalar form; the block's Rayleigh partial goes to
 // dpart[blockIdx.x].
 template <int NT, int G>
 __global__ __launch_bounds__(NT) void spmm_vec_kernel(const Prob* __restrict__ probs,
@@ -41,7 +43,7 @@ __global__ __launch_bounds__(NT) void spmm_vec_kernel(const Prob* __restrict__ p
   __shared__ int32_t sci[NZL];
   __shared__ int32_t srp[SPMM_ROWS + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int gl = lane % G, c0 = 4 * gl;
+  const int gl = lane % G;
   const Prob& P = probs[0];
   if (P.ctrl->stopped) return;
   const int n = P.n, k = P.k;
@@ -51,18 +53,30 @@ __global__ __launch_bounds__(NT) void spmm_vec_kernel(const Prob* __restrict__ p
   const double* __restrict__ X = P.x;
   const int64_t ldx = P.ldx;
   double* __restrict__ W = P.w;
-  // this lane's valid columns; the paired loads need 16-byte aligned rows
-  const int vc = max(0, min(4, k - c0));
-  const bool vec = vc == 4 && (ldx & 1) == 0 && (((uintptr_t)X) & 15) == 0 && (k & 1) == 0;
-  auto load4 = [&](int64_t row, double (&v)[4]) {
-    const double* p = X + row * ldx + c0;
-    if (vec) {
-      const v2d a = *gld(reinterpret_cast<const v2d*>(p));
-      const v2d b = *gld(reinterpret_cast<const v2d*>(p + 2));
-      v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
-    } else {
+  // this lane's columns: pair h starts at column 2 G h + 2 gl; whole pairs
+  // move as 16-byte loads (stores) when the rows of X (W) are 16-byte aligned
+  int col[2];
+  bool px[2], pw[2];
+  const bool xal = (ldx & 1) == 0 && (((uintptr_t)X) & 15) == 0;
+  const bool wal = (k & 1) == 0 && (((uintptr_t)W) & 15) == 0;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) v[q] = q < vc ? *gld(p + q) : 0.0;
+  for (int h = 0; h < 2; ++h) {
+    col[h] = 2 * G * h + 2 * gl;
+    px[h] = xal && col[h] + 1 < k;
+    pw[h] = wal && col[h] + 1 < k;
+  }
+  auto load4 = [&](int64_t row, double (&v)[4]) {
+    const double* p = X + row * ldx;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (px[h]) {
+        const v2d a = *gld(reinterpret_cast<const v2d*>(p + col[h]));
+        v[2 * h] = a.x;
+        v[2 * h + 1] = a.y;
+      } else {
+        v[2 * h] = col[h] < k ? *gld(p + col[h]) : 0.0;
+        v[2 * h + 1] = col[h] + 1 < k ? *gld(p + col[h] + 1) : 0.0;
+      }
     }
   };
   double sxw[4] = {0.0, 0.0, 0.0, 0.0}, sxx[4] = {0.0, 0.0, 0.0, 0.0};
@@ -101,21 +115,29 @@ __global__ __launch_bounds__(NT) void spmm_vec_kernel(const Prob* __restrict__ p
         }
         double xv[G][4];
 #pragma unroll
-        for (int z = 0; z < G; ++z) load4(cz[z], xv[z]);
+        for (int z = 0; z < G; ++z) {
+          if (eb + z < e1) {
+            load4(cz[z], xv[z]);
+          } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) xv[z][q] = 0.0;
+          }
+        }
 #pragma unroll
         for (int z = 0; z < G; ++z)
 #pragma unroll
           for (int q = 0; q < 4; ++q) w[q] = __builtin_fma(az[z], xv[z][q], w[q]);
       }
       if (rok) {
-        double* wp = W + (int64_t)row * k + c0;
-        if (vec) {
-          *gst(reinterpret_cast<v2d*>(wp)) = v2d{w[0], w[1]};
-          *gst(reinterpret_cast<v2d*>(wp + 2)) = v2d{w[2], w[3]};
-        } else {
+        double* wp = W + (int64_t)row * k;
 #pragma unroll
-          for (int q = 0; q < 4; ++q)
-            if (q < vc) *gst(wp + q) = w[q];
+        for (int h = 0; h < 2; ++h) {
+          if (pw[h]) {
+            *gst(reinterpret_cast<v2d*>(wp + col[h])) = v2d{w[2 * h], w[2 * h + 1]};
+          } else {
+            if (col[h] < k) *gst(wp + col[h]) = w[2 * h];
+            if (col[h] + 1 < k) *gst(wp + col[h] + 1) = w[2 * h + 1];
+          }
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -137,8 +159,8 @@ __global__ __launch_bounds__(NT) void spmm_vec_kernel(const Prob* __restrict__ p
   if (lane < G) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      red[0][wave][c0 + q] = sxw[q];
-      red[1][wave][c0 + q] = sxx[q];
+      red[0][wave][col[q / 2] + q % 2] = sxw[q];
+      red[1][wave][col[q / 2] + q % 2] = sxx[q];
     }
   }
   __syncthreads();
@@ -164,18 +186,18 @@ __global__ __launch_bounds__(NT) void spmm_vec_kernel(const Prob* __restrict__ p
 // (the terms are associated differently from CSR order, within the rounding
 // of any FP64 order).  Lane j < k of the row owns column j: it writes w_rj
 // and keeps column j's Rayleigh terms.  Chunks of ROW_CHUNK rows, taken
-// block-strided as in the vector form, over a grid sized to the occupancy.
-// 32 rows: a 149k-row matrix gives 4.7k chunks, two or three per block of
-// the grid, so the last round of chunks leaves few CUs idle (64-row chunks,
-// one or two per block, measured 4.6 % slower on that shape).
-constexpr int ROW_CHUNK = 32;
-constexpr int ROW_GRID = 2048;
+// block-strided as in the vector form, over a grid of as many blocks as are
+// resident at once.  16 rows: a 149k-row matrix gives 9.3k chunks, about
+// five per block, so the last round leaves few CUs idle (32-row chunks
+// measured 7 % slower on that shape, 8-row chunks 43 %).
+constexpr int ROW_CHUNK = 16;
 
 template <int NT, int L, int KC>
 __global__ __launch_bounds__(NT) void spmm_row_kernel(const Prob* __restrict__ probs,
                                                      const RowItem* __restrict__ items, int nitems,
                                                      int chunk_rows) {
   static_assert(64 % L == 0 && KC <= L, "row groups must tile a wavefront");
+  typedef double v2d __attribute__((ext_vector_type(2)));
   constexpr int NW = NT / 64, RPB = NT / L;
   __shared__ double red[2][NW][KC];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -189,6 +211,24 @@ __global__ __launch_bounds__(NT) void spmm_row_kernel(const Prob* __restrict__ p
   const double* __restrict__ X = P.x;
   const int64_t ldx = P.ldx;
   double* __restrict__ W = P.w;
+  // an X row of k = KC doubles as 16-byte pairs (8-byte aligned, which
+  // global loads accept) and one last double for odd k: 3 loads instead of
+  // 5 at k = 5
+  auto xrow = [&](int c, double (&v)[KC]) {
+    const double* p = X + (int64_t)c * ldx;
+    if (k == KC) {
+#pragma unroll
+      for (int q = 0; q + 1 < KC; q += 2) {
+        const v2d a = *gld(reinterpret_cast<const v2d*>(p + q));
+        v[q] = a.x;
+        v[q + 1] = a.y;
+      }
+      if (KC & 1) v[KC - 1] = *gld(p + KC - 1);
+    } else {
+#pragma unroll
+      for (int q = 0; q < KC; ++q) v[q] = q < k ? *gld(p + q) : 0.0;
+    }
+  };
   double sxw = 0.0, sxx = 0.0;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const RowItem item = items[it];
@@ -213,11 +253,8 @@ __global__ __launch_bounds__(NT) void spmm_row_kernel(const Prob* __restrict__ p
       fetch(e0 + j, ca, aa, cb, ab);
       for (int e = e0 + j; e < e1; e += 2 * L) {
         double xa[KC], xb[KC];
-#pragma unroll
-        for (int q = 0; q < KC; ++q) {
-          xa[q] = q < k ? *gld(X + (int64_t)ca * ldx + q) : 0.0;
-          xb[q] = q < k ? *gld(X + (int64_t)cb * ldx + q) : 0.0;
-        }
+        xrow(ca, xa);
+        xrow(cb, xb);
         int nca, ncb;
         double naa, nab;
         fetch(e + 2 * L, nca, naa, ncb, nab);
@@ -266,13 +303,9 @@ __global__ __launch_bounds__(NT) void spmm_row_kernel(const Prob* __restrict__ p
   }
 }
 
-// Grid: three resident 256-thread blocks on each of the 256 CUs.
-constexpr int SPMM_GRID = 768;
-
-// Rows per chunk and grid of either form; REFINE_SPMM_CHUNK and
-// REFINE_SPMM_GRID override them (tuning hooks, read once per process; the
-// vector form's chunk stays within its LDS copy of SPMM_ROWS + 1 row
-// pointers).
+// Rows per chunk of either form; REFINE_SPMM_CHUNK overrides it (a tuning
+// hook, read once per process; the vector form's chunk stays within its LDS
+// copy of SPMM_ROWS + 1 row pointers).
 static int env_int(const char* name) {
   const char* env = getenv(name);
   return env ? atoi(env) : 0;
@@ -282,15 +315,70 @@ static int chunk_rows_for(bool row_form) {
   if (row_form) return (c >= 8 && c <= 1024) ? c : ROW_CHUNK;
   return (c >= 8 && c <= SPMM_ROWS) ? c : SPMM_ROWS;
 }
-static int grid_for(bool row_form) {
-  static const int g = env_int("REFINE_SPMM_GRID");
-  if (g >= 64 && g <= 65536) return g;
-  return row_form ? ROW_GRID : SPMM_GRID;
-}
 
 int spmm_chunk_rows(int lanes) { return chunk_rows_for(lanes != 0); }
-int spmm_grid(int nitems, int lanes) {
-  const int g = grid_for(lanes != 0);
+
+typedef void (*SpmmKernel)(const Prob*, const RowItem*, int, int);
+
+template <int L>
+static SpmmKernel row_kernel_for(int k) {
+  switch (k) {
+    case 1: return spmm_row_kernel<256, L, 1>;
+    case 2: return spmm_row_kernel<256, L, 2>;
+    case 3: return spmm_row_kernel<256, L, 3>;
+    case 4: return spmm_row_kernel<256, L, 4>;
+    case 5: return spmm_row_kernel<256, L, 5>;
+    case 6: return spmm_row_kernel<256, L, 6>;
+    case 7: return spmm_row_kernel<256, L, 7>;
+    case 8: return spmm_row_kernel<256, L, 8>;
+    default: return nullptr;
+  }
+}
+
+// The kernel of the product for k columns and `lanes` lanes per row (0: the
+// vector form with G = pow2ceil(k) / 4 lanes per row, at least 1).
+static SpmmKernel spmm_kernel_for(int k, int lanes) {
+  if (lanes == 8) return row_kernel_for<8>(k);
+  if (lanes == 16) return row_kernel_for<16>(k);
+  if (lanes == 32) return row_kernel_for<32>(k);
+  if (lanes) return nullptr;
+  int kp = 1;
+  while (kp < k) kp *= 2;
+  switch (std::max(1, kp / 4)) {
+    case 1: return spmm_vec_kernel<256, 1>;
+    case 2: return spmm_vec_kernel<256, 2>;
+    case 4: return spmm_vec_kernel<256, 4>;
+    case 8: return spmm_vec_kernel<256, 8>;
+    case 16: return spmm_vec_kernel<256, 16>;
+    case 32: return spmm_vec_kernel<256, 32>;
+    default: return nullptr;
+  }
+}
+
+// Grid of the product over nitems chunks on the current device: as many
+// 256-thread blocks as are resident at once (the occupancy of the kernel's
+// registers and LDS times the CU count: 3 x 256 for the vector form at
+// k = 32, 7 x 256 for the row form at k = 5), at most one per chunk.
+// REFINE_SPMM_GRID overrides it (a tuning hook).  0 if k or lanes has no
+// kernel.
+int spmm_grid(int nitems, int k, int lanes) {
+  const SpmmKernel fn = spmm_kernel_for(k, lanes);
+  if (!fn || nitems <= 0) return 0;
+  static const int genv = env_int("REFINE_SPMM_GRID");
+  int g = 0;
+  if (genv >= 64 && genv <= 65536) {
+    g = genv;
+  } else {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn), 256, 0) !=
+            hipSuccess ||
+        per_cu <= 0)
+      per_cu = 1;
+    g = per_cu * cus;
+  }
   return nitems < g ? nitems : g;
 }
 
@@ -310,45 +398,11 @@ int spmm_row_lanes(int k, int64_t n, int64_t nnz) {
   return mean < 16.0 ? 0 : mean < 160.0 ? 8 : 16;
 }
 
-template <int L>
-hipError_t launch_spmm_row(const Prob* probs, const RowItem* items, int nitems, int k, int grid,
-                           hipStream_t st) {
-  switch (k) {
-#define RFK_SPMM_ROW(KV)                                                                         \
-  case KV:                                                                                       \
-    hipLaunchKernelGGL((spmm_row_kernel<256, L, KV>), dim3(grid), dim3(256), 0, st, probs, items, \
-                       nitems, chunk_rows_for(true));                                            \
-    break;
-    RFK_SPMM_ROW(1) RFK_SPMM_ROW(2) RFK_SPMM_ROW(3) RFK_SPMM_ROW(4)
-    RFK_SPMM_ROW(5) RFK_SPMM_ROW(6) RFK_SPMM_ROW(7) RFK_SPMM_ROW(8)
-#undef RFK_SPMM_ROW
-    default:
-      return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_spmm(const Prob* probs, const RowItem* items, int nitems, int k, int lanes,
+hipError_t launch_spmm(const Prob* probs, const RowItem* items, int nitems, int k, int lanes, int grid,
                        hipStream_t st) {
-  const int grid = spmm_grid(nitems, lanes);
-  if (lanes == 8) return launch_spmm_row<8>(probs, items, nitems, k, grid, st);
-  if (lanes == 16) return launch_spmm_row<16>(probs, items, nitems, k, grid, st);
-  if (lanes == 32) return launch_spmm_row<32>(probs, items, nitems, k, grid, st);
-  if (lanes) return hipErrorInvalidValue;
-  int kp = 1;
-  while (kp < k) kp *= 2;
-  const int g = std::max(1, kp / 4);
-  switch (g) {
-#define RFK_SPMM(GV)                                                                            \
-  case GV:                                                                                      \
-    hipLaunchKernelGGL((spmm_vec_kernel<256, GV>), dim3(grid), dim3(256), 0, st, probs, items, \
-                       nitems, chunk_rows_for(false));                                          \
-    break;
-    RFK_SPMM(1) RFK_SPMM(2) RFK_SPMM(4) RFK_SPMM(8) RFK_SPMM(16) RFK_SPMM(32)
-#undef RFK_SPMM
-    default:
-      return hipErrorInvalidValue;
-  }
+  const SpmmKernel fn = spmm_kernel_for(k, lanes);
+  if (!fn || grid <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(256), 0, st, probs, items, nitems, chunk_rows_for(lanes != 0));
   return hipGetLastError();
 }
 

@@ -41,7 +41,7 @@ hipError_t launch_fin_d(const Prob*, int, hipStream_t);
 hipError_t launch_fin_stats(const Prob*, int, hipStream_t);
 hipError_t launch_ctrl_reset(const Prob*, int, int, double, hipStream_t);
 hipError_t launch_set_x(Prob*, int, double*, int64_t, hipStream_t);
-hipError_t launch_spmm(const Prob*, const RowItem*, int, int, int, hipStream_t);
+hipError_t launch_spmm(const Prob*, const RowItem*, int, int, int, int, hipStream_t);
 int spmm_row_lanes(int k, int64_t n, int64_t nnz);
 int gram_halves(int kmax);
 hipError_t launch_rr_prep(const Prob*, int, hipStream_t);
@@ -50,7 +50,7 @@ hipError_t launch_rr_apply(const Prob*, const RowItem*, int, hipStream_t);
 hipError_t launch_flip_sigma(const Prob*, int, hipStream_t);
 hipError_t launch_flip_apply(const Prob*, const RowItem*, int, hipStream_t);
 int spmm_chunk_rows(int lanes);
-int spmm_grid(int nitems, int lanes);
+int spmm_grid(int nitems, int k, int lanes);
 hipError_t launch_rowstats(int, int, const double*, int64_t, const int32_t*, const int32_t*,
                            const double*, double*, int, hipStream_t);
 }  // namespace rfk
@@ -77,6 +77,7 @@ struct Plan {
   RowItem* spmm_items = nullptr;  // CSR product: chunks of spmm_chunk_rows(lanes) rows
   int n_spmm = 0;
   int spmm_lanes = 0;             // lanes per row of the row form (0: vector form)
+  int spmm_grid = 0;              // blocks of the CSR product (one Rayleigh partial each)
   bool kxk_pipeline = false;      // one problem: k x k stage by the panel pipeline
   bool fused = false;             // k <= 32: statistics before the update, X written in place
   GramRedItem* gred_items = nullptr;
@@ -172,7 +173,7 @@ constexpr int KXK_ONE_WG_MAX = 48;
 // blocks and K splits, or the CSR product's grid.
 int64_t dpart_count(int64_t n, const Shape& s, const Plan& pl) {
   const int64_t d = dpart_entries(n, s, pl.split);
-  return pl.csr ? std::max<int64_t>(d, spmm_grid(iceil(n, spmm_chunk_rows(pl.spmm_lanes)), pl.spmm_lanes)) : d;
+  return pl.csr ? std::max<int64_t>(d, pl.spmm_grid) : d;
 }
 
 template <class T>
@@ -379,6 +380,10 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
   pl.split = opt.precision == REFINE_SPLIT_INT8 || opt.precision == REFINE_SPLIT_CRT;
   pl.square = opt.target == REFINE_TARGET_SMALLEST_ABS;
   pl.spmm_lanes = pl.csr ? spmm_row_lanes(ks[0], As[0].n, As[0].nnz) : 0;
+  if (pl.csr) {
+    pl.spmm_grid = spmm_grid(iceil(As[0].n, spmm_chunk_rows(pl.spmm_lanes)), ks[0], pl.spmm_lanes);
+    if (pl.spmm_grid <= 0) return REFINE_EINVAL;
+  }
   pl.kxk_pipeline = single && ks[0] > KXK_ONE_WG_MAX;
   if (const char* env = getenv("REFINE_KXK_PIPE")) pl.kxk_pipeline = single && atoi(env) != 0;
   pl.hprob.resize(np);
@@ -471,7 +476,7 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
     base += align_up((size_t)s.nrb * 5 * k * sizeof(double));
     P.dpart = (double*)base;
     // CSR: one partial per product block; dense: set with the product's items
-    P.ndp = pl.csr ? spmm_grid(iceil(n, spmm_chunk_rows(pl.spmm_lanes)), pl.spmm_lanes) : s.nrb;
+    P.ndp = pl.csr ? pl.spmm_grid : s.nrb;
     base += align_up((size_t)dpart_count(n, s, pl) * 2 * k * sizeof(double));
     P.gpart = (double*)base;
     base += align_up((size_t)s.ngb * (2 * k * k + k) * sizeof(double));
@@ -534,8 +539,8 @@ hipError_t enqueue_product_on(Plan& pl, const Prob* probs, hipStream_t st) {
   hipError_t e;
   const int np = (int)pl.hprob.size();
   if (pl.csr) {
-    if ((e = launch_spmm(probs, pl.spmm_items, pl.n_spmm, pl.hprob[0].k, pl.spmm_lanes, st)) !=
-        hipSuccess)
+    if ((e = launch_spmm(probs, pl.spmm_items, pl.n_spmm, pl.hprob[0].k, pl.spmm_lanes, pl.spmm_grid,
+                         st)) != hipSuccess)
       return e;
   } else {
     if (pl.split) {
@@ -1017,7 +1022,8 @@ int refine_time_product(refine_ctx* c, double* X, int64_t ldx, int32_t reps, flo
   hipError_t e = hipEventRecord(e0, c->stream);
   for (int i = 0; i < reps && e == hipSuccess; ++i) {
     if (pl.csr)
-      e = launch_spmm(pl.dprob, pl.spmm_items, pl.n_spmm, pl.hprob[0].k, pl.spmm_lanes, c->stream);
+      e = launch_spmm(pl.dprob, pl.spmm_items, pl.n_spmm, pl.hprob[0].k, pl.spmm_lanes, pl.spmm_grid,
+                      c->stream);
     else if (pl.split)
       e = split_product(pl.sp, pl.dprob, c->stream);
     else
@@ -1058,7 +1064,7 @@ int refine_time_product_parts(refine_ctx* c, double* X, int64_t ldx, int32_t rep
   auto one = [&]() -> hipError_t {
     if (pl.csr) {
       hipError_t r = launch_spmm(pl.dprob, pl.spmm_items, pl.n_spmm, pl.hprob[0].k, pl.spmm_lanes,
-                                 c->stream);
+                                 pl.spmm_grid, c->stream);
       product_mark(c->stream);
       return r;
     }

@@ -183,6 +183,41 @@ def test_csr_kron_banded(m, bands, k, lanes, monkeypatch):
     _compare_steps(None, X0, 3, norm_a=K.sigma, csr=K)
 
 
+@pytest.mark.parametrize("k,pad,kron", [(20, 5, False), (20, 6, False), (32, 1, False), (32, 2, False),
+                                        (3, 1, False), (5, 3, True), (5, 4, True)])
+def test_csr_x_inside_wider_buffer(k, pad, kron):
+    """X held inside a wider buffer (ldx = k + pad): an odd ldx leaves X rows
+    without 16-byte alignment (single-double loads in the vector form), an
+    even one keeps the paired loads at a stride other than k; the row form
+    (Kronecker workload, k = 5) loads X rows as 8-byte-aligned pairs at any
+    ldx.  The step touches only the (n, k) view."""
+    rf = _lib()
+    if kron:
+        C, lam, Xt, X0 = synth.kron_banded(m=14, bands=(2, 2, 1), k=k)
+        mu, target = 0.0, "largest_abs"
+    else:
+        C, lam, Xt, X0 = synth.laplacian3d_separable(12, k)
+        mu, target = C.sigma, "smallest"
+    Ad = rf.CsrMatrix(C.n, _dev(C.row_ptr), _dev(C.col_idx), _dev(C.val))
+    Xbuf = torch.full((C.n, k + pad), 7.0, dtype=torch.float64, device="cuda")
+    Xbuf[:, :k] = _dev(X0)
+    X = Xbuf[:, :k]
+    assert X.stride(0) == k + pad
+    ctx = rf.RefineContext(Ad, k, target=target, norm_a=C.sigma)
+    assert ctx.info()["mu"] == pytest.approx(mu, abs=1e-12)
+    A_host = oracle.Csr(C.n, C.row_ptr, C.col_idx, C.val)
+    Xo = np.array(X0, copy=True)
+    for s in range(2):
+        st = ctx.step(X)
+        assert st.status == rf.OK, rf.status_string(st.status)
+        r = oracle.refine_step(A_host, Xo, mu=mu, norm_a=C.sigma)
+        Xo = r.X
+        err = float(np.max(np.abs(align_signs(X.cpu().numpy(), Xo) - Xo)))
+        assert err <= TOL, "step %d: max |dX| = %.3e" % (s, err)
+    ctx.close()
+    assert bool(torch.all(Xbuf[:, k:] == 7.0))
+
+
 def test_new_iterate_starts_a_new_divergence_history():
     """Steps on one X, then a restart from the start block in another buffer:
     the first step of the restart has a larger correction than the last steps
