@@ -400,10 +400,10 @@ __global__ __launch_bounds__(WAVES * 64) void crt_gemm_kernel(const Prob* __rest
 // the block's Rayleigh partials (x w_hi, x x).
 // ---------------------------------------------------------------------------
 template <int N>
-__global__ __launch_bounds__(256) void crt_recon_kernel(const Prob* __restrict__ probs,
+__global__ __launch_bounds__(512) void crt_recon_kernel(const Prob* __restrict__ probs,
                                                         const RowItem* __restrict__ items,
                                                         int rrows, CrtArgs ca) {
-  constexpr int NT = 256;
+  constexpr int NT = 512;
   constexpr CrtSum<N> K{};
   __shared__ double red[8 * NT];
   const Prob& P = probs[0];
@@ -502,7 +502,10 @@ __global__ __launch_bounds__(256) void crt_recon_kernel(const Prob* __restrict__
 // Host side
 // ---------------------------------------------------------------------------
 
-constexpr int CRT_RROWS = 32;  // rows per reconstruction block
+// rows per reconstruction block: 512 threads on 64 rows keep two wavefronts
+// per SIMD at n = 16384 while halving the Rayleigh partials that the
+// reduction after the product reads, against 256 threads on 32 rows
+constexpr int CRT_RROWS = 64;
 
 // Launch shapes of the residue products: wavefronts per block (32 W rows
 // each) and chunks per group.  The tuner times each at init.
@@ -570,7 +573,7 @@ hipError_t launch_all_n(const SplitPlan& sp, const Prob* dprob, const CrtArgs& c
   }
   if (e != hipSuccess) return e;
   product_mark(st);
-  hipLaunchKernelGGL((crt_recon_kernel<N>), dim3(sp.n_rec), dim3(256), 0, st, dprob, sp.rec_items,
+  hipLaunchKernelGGL((crt_recon_kernel<N>), dim3(sp.n_rec), dim3(512), 0, st, dprob, sp.rec_items,
                      sp.crt_rrows, ca);
   e = hipGetLastError();
   product_mark(st);
@@ -716,7 +719,9 @@ int crt_init(SplitPlan& sp, const refine_matrix& A, int k, int nmod, std::vector
 
   // Launch shape of the residue products: REFINE_CRT_SHAPE=<index> forces
   // one; otherwise each is timed once (on a zero X, the workspace copy of
-  // the update) and the fastest kept.
+  // the update) and a later shape replaces the one kept only when it is
+  // more than 2 % faster, so that shapes within the timing noise of each
+  // other do not alternate between processes.
   int best = -1;
   if (const char* env = getenv("REFINE_CRT_SHAPE")) {
     const int v = atoi(env);
@@ -756,7 +761,7 @@ int crt_init(SplitPlan& sp, const refine_matrix& A, int k, int nmod, std::vector
         fprintf(stderr, "refine: tune crt n=%lld k=%d N=%d shape %d (waves %d, group %d, ahead %d): %.1f us\n",
                 (long long)n, k, nmod, sh, CRT_SHAPES[sh].waves, CRT_SHAPES[sh].xg,
                 CRT_SHAPES[sh].pf, t * 1000.f / 3.f);
-      if (e == hipSuccess && t < best_t) {
+      if (e == hipSuccess && t < 0.98f * best_t) {
         best_t = t;
         best = sh;
       }
