@@ -628,7 +628,9 @@ __global__ __launch_bounds__(256) void update_kernel(const Prob* __restrict__ pr
 // and acceptance are already known, so an accepted step writes the
 // normalised iterate straight into X (each block reads its rows before it
 // overwrites them, and no other block reads them), with no partial sums and
-// no normalisation pass afterwards.
+// no normalisation pass afterwards.  E21 itself is then not needed, so the
+// bottom rows take one product, X~2 = X2 + R2 Delta - X2 (M Delta + N), half
+// the matrix-core work of X2 M and X2 N.
 template <int CT, bool FUSED>
 __global__ __launch_bounds__(256) void update_small_kernel(const Prob* __restrict__ probs,
                                                           const RowItem* __restrict__ items,
@@ -636,7 +638,9 @@ __global__ __launch_bounds__(256) void update_small_kernel(const Prob* __restric
   typedef double v2d __attribute__((ext_vector_type(2)));
   static_assert(CT <= 2, "tall-skinny form");
   constexpr int NT = 256, WAVES = 4, TR = 64, KP = CT * 16, LDXS = KP + 1;
-  constexpr int BW = 2 * KP, LDC = BW + 2;
+  // fused: one product X2 C with C = M Delta + N (the form of the statistics
+  // formed before the update); otherwise X2 M and X2 N, since E21 is needed
+  constexpr int BW = (FUSED ? 1 : 2) * KP, LDC = BW + 2;
   constexpr int UNITS = TR * KP / 2, UPT = (UNITS + NT - 1) / NT;  // 2-double units per tile
   __shared__ double Cs[KP * LDC];
   __shared__ double Xs[TR * LDXS];
@@ -668,11 +672,19 @@ __global__ __launch_bounds__(256) void update_small_kernel(const Prob* __restric
       xsq[t] = 0.0;
       esq[t] = 0.0;
     }
-    // [M | N] rows < KP (zero past k)
+    // [M | N] (or C = M Delta + N) rows < KP (zero past k)
     for (int e = tid; e < KP * BW; e += NT) {
       const int rr = e / BW, cc = e - rr * BW;
       const int half = cc / KP, cj = cc - half * KP;
-      Cs[rr * LDC + cc] = (rr < k && cj < k) ? *gld(Cm + rr * k2 + half * k + cj) : 0.0;
+      double v = 0.0;
+      if (rr < k && cj < k) {
+        if (FUSED)
+          v = __builtin_fma(*gld(Cm + rr * k2 + cj), *gld(P.vec + VEC_DINV * k + cj),
+                            *gld(Cm + rr * k2 + k + cj));
+        else
+          v = *gld(Cm + rr * k2 + half * k + cj);
+      }
+      Cs[rr * LDC + cc] = v;
     }
     // one 64-row tile of X as UPT pairs of doubles per thread (zero past n or k)
     auto load_tile = [&](int rc, v2d (&buf)[UPT]) {
@@ -731,7 +743,7 @@ __global__ __launch_bounds__(256) void update_small_kernel(const Prob* __restric
 #pragma unroll
         for (int t = 0; t < CT; ++t) {
           accM[t] = mfma_f64(av, brow[t * 16], accM[t]);
-          accN[t] = mfma_f64(av, brow[KP + t * 16], accN[t]);
+          if (!FUSED) accN[t] = mfma_f64(av, brow[KP + t * 16], accN[t]);
         }
       }
       // epilogue: register r holds row rc + wave*16 + mfma_row(g, r), column t*16 + r16
@@ -749,9 +761,14 @@ __global__ __launch_bounds__(256) void update_small_kernel(const Prob* __restric
               } else {
                 const double x = Xs[lr * LDXS + c];
                 const double rr = residual(ew[t][r], el[t][r], x, dv[t], has_lo);
-                const double e = (rr - accM[t][r]) * di[t];
-                xt = (x + e) - accN[t][r];
-                esq[t] = __builtin_fma(e, e, esq[t]);
+                if (FUSED) {
+                  // x + r / (d - mu) - (x C)_j, the two small terms first
+                  xt = x + __builtin_fma(rr, di[t], -accM[t][r]);
+                } else {
+                  const double e = (rr - accM[t][r]) * di[t];
+                  xt = (x + e) - accN[t][r];
+                  esq[t] = __builtin_fma(e, e, esq[t]);
+                }
               }
               if (FUSED) {
                 *gst(P.x + (int64_t)row * ldx + c) = xt * sc[t];

@@ -121,9 +121,15 @@ Shape choose_shape(int64_t n, int k, bool single, bool csr) {
   // at least 64 rows for one problem and about 1024 blocks for a long one
   // (four per CU to overlap their latencies; twice as many, smaller blocks
   // each pay the fixed latency of staging [M | N] and of the partial writes,
-  // which measured slower at n = 150k and 2M); 256 rows per block in a batch.
+  // which measured slower at n = 150k and 2M).  From n = 2^20 on with
+  // k <= 32, about 4096 blocks of 256 rows or more: the fused update writes
+  // no partials and runs three blocks per CU (at n = 2M, k = 32: 1.001 ms
+  // per step against 1.049 with 1024 blocks, which leave the third round of
+  // blocks a third full; at n = 150k, 64-row blocks measured slower).  256
+  // rows per block in a batch.
   if (single) {
-    s.rbrows = (int)std::max<int64_t>(64, (n + 1023) / 1024 + 63) / 64 * 64;
+    const int64_t target = (k <= 32 && n >= (int64_t)1 << 20) ? 4096 : 1024;
+    s.rbrows = (int)std::max<int64_t>(64, (n + target - 1) / target + 63) / 64 * 64;
   } else {
     s.rbrows = 256;
   }
