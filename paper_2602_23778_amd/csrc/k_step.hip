@@ -208,8 +208,10 @@ __global__ __launch_bounds__(CT * RG * 64) void gram_kernel(const Prob* __restri
 // requested before their products.  Loads never branch (clamped addresses,
 // masked values), which keeps the compiler's wait counts exact.  The RG
 // wavefronts of a block take interleaved runs of 4U rows; their tiles and
-// column sums are added in LDS in a fixed order.
-template <int CT, int RG, int U>
+// column sums are added in LDS in a fixed order.  LO (W has a low part) is a
+// template argument, so the FP64 form carries no registers for it (166
+// registers at CT = 2 in both forms, against 193 with a runtime flag).
+template <int CT, int RG, int U, bool LO>
 __global__ __launch_bounds__(RG * 64) void gram_all_kernel(const Prob* __restrict__ probs,
                                                           const RowItem* __restrict__ items,
                                                           int nitems) {
@@ -225,10 +227,10 @@ __global__ __launch_bounds__(RG * 64) void gram_all_kernel(const Prob* __restric
     if (P.ctrl->stopped) continue;
     const int n = P.n, k = P.k;
     const int ct_used = (k + 15) / 16;
-    const bool has_lo = P.wlo != nullptr;
+    const bool has_lo = LO;  // launched for the form of W (with a low part or not)
     const double* __restrict__ X = P.x;
     const double* __restrict__ Wh = P.w;
-    const double* __restrict__ Wl = has_lo ? P.wlo : P.w;
+    const double* __restrict__ Wl = LO ? P.wlo : P.w;
     const int64_t ldx = P.ldx;
     const int r0 = item.blk * P.gbrows, r1 = min(n, r0 + P.gbrows);
     const int kk2 = k * k;
@@ -266,7 +268,7 @@ __global__ __launch_bounds__(RG * 64) void gram_all_kernel(const Prob* __restric
           for (int t = 0; t < CT; ++t) {
             xv[u][t] = *gld(X + (int64_t)rr * ldx + cc[t]);
             wv[u][t] = *gld(Wh + (int64_t)rr * k + cc[t]);
-            if (has_lo) lv[u][t] = *gld(Wl + (int64_t)rr * k + cc[t]);
+            lv[u][t] = LO ? *gld(Wl + (int64_t)rr * k + cc[t]) : 0.0;
           }
         }
 #pragma unroll
@@ -1126,7 +1128,8 @@ __global__ void set_x_kernel(Prob* __restrict__ probs, int p, double* x, int64_t
 // ---------------------------------------------------------------------------
 constexpr int ROW_NT = 1024;
 
-hipError_t launch_gram(const Prob* probs, const RowItem* items, int nitems, int kmax,
+// lo: W carries a low part (the split forms).
+hipError_t launch_gram(const Prob* probs, const RowItem* items, int nitems, int kmax, bool lo,
                        hipStream_t st) {
   const int ct = (kmax + 15) / 16;
 #define RFK_CASE(CTV, RGV)                                                                   \
@@ -1139,12 +1142,18 @@ hipError_t launch_gram(const Prob* probs, const RowItem* items, int nitems, int 
                          probs, items, nitems);                                              \
     break;
   if (ct <= 2) {
-    if (ct == 1)
-      hipLaunchKernelGGL((gram_all_kernel<1, 8, 4>), dim3(nitems), dim3(512), 0, st, probs, items,
-                         nitems);
+#define RFK_GRAM_ALL(CTV, LOV)                                                                     \
+  hipLaunchKernelGGL((gram_all_kernel<CTV, 8, 4, LOV>), dim3(nitems), dim3(512), 0, st, probs, items, \
+                     nitems)
+    if (ct == 1 && lo)
+      RFK_GRAM_ALL(1, true);
+    else if (ct == 1)
+      RFK_GRAM_ALL(1, false);
+    else if (lo)
+      RFK_GRAM_ALL(2, true);
     else
-      hipLaunchKernelGGL((gram_all_kernel<2, 8, 4>), dim3(nitems), dim3(512), 0, st, probs, items,
-                         nitems);
+      RFK_GRAM_ALL(2, false);
+#undef RFK_GRAM_ALL
     return hipGetLastError();
   }
   switch (ct) {

@@ -27,7 +27,7 @@ namespace rfk {
 hipError_t launch_gemm_f64(const Prob*, const GemmItem*, int, int, bool, int, hipStream_t);
 int gemm_rows_per_block(int cfg);
 int gemm_num_cfgs();
-hipError_t launch_gram(const Prob*, const RowItem*, int, int, hipStream_t);
+hipError_t launch_gram(const Prob*, const RowItem*, int, int, bool, hipStream_t);
 struct GramRedItem {
   int32_t prob, s0;
 };
@@ -578,7 +578,7 @@ hipError_t enqueue_step(Plan& pl, hipStream_t st) {
   const int np = (int)pl.hprob.size();
   if ((e = enqueue_product(pl, st)) != hipSuccess) return e;
   if ((e = launch_fin_d(pl.dprob, np, st)) != hipSuccess) return e;
-  if ((e = launch_gram(pl.dprob, pl.gram_items, pl.n_gram, pl.kmax, st)) != hipSuccess) return e;
+  if ((e = launch_gram(pl.dprob, pl.gram_items, pl.n_gram, pl.kmax, pl.split, st)) != hipSuccess) return e;
   if ((e = launch_gram_reduce(pl.dprob, pl.gred_items, pl.n_gred, st)) != hipSuccess) return e;
   if ((e = launch_kxk(pl.dprob, np, pl.kmax, pl.kxk_pipeline, st)) != hipSuccess) return e;
   if (pl.fused) {
@@ -934,7 +934,7 @@ int refine_rayleigh_ritz(refine_ctx* c, double* X, int64_t ldx) {
   hipError_t e = launch_ctrl_reset(pl.dprob, 1, 0, 0.0, st);
   if (e == hipSuccess) e = enqueue_product(pl, st);
   if (e == hipSuccess) e = launch_rr_prep(pl.dprob, 1, st);
-  if (e == hipSuccess) e = launch_gram(pl.dprob, pl.gram_items, pl.n_gram, pl.kmax, st);
+  if (e == hipSuccess) e = launch_gram(pl.dprob, pl.gram_items, pl.n_gram, pl.kmax, pl.split, st);
   if (e == hipSuccess) e = launch_gram_reduce(pl.dprob, pl.gred_items, pl.n_gred, st);
   if (e == hipSuccess) e = launch_rr_solve(pl.dprob, 1, st);
   if (e == hipSuccess) e = launch_rr_apply(pl.dprob, pl.row_items, pl.n_row, st);
@@ -1285,7 +1285,7 @@ int refine_batch_rayleigh_ritz(refine_batch* b, double* const* Xs, const int64_t
   hipError_t e = launch_ctrl_reset(pl.dprob, np, 0, 0.0, st);
   if (e == hipSuccess) e = enqueue_product(pl, st);
   if (e == hipSuccess) e = launch_rr_prep(pl.dprob, np, st);
-  if (e == hipSuccess) e = launch_gram(pl.dprob, pl.gram_items, pl.n_gram, pl.kmax, st);
+  if (e == hipSuccess) e = launch_gram(pl.dprob, pl.gram_items, pl.n_gram, pl.kmax, pl.split, st);
   if (e == hipSuccess) e = launch_gram_reduce(pl.dprob, pl.gred_items, pl.n_gred, st);
   if (e == hipSuccess) e = launch_rr_solve(pl.dprob, np, st);
   if (e == hipSuccess) e = launch_rr_apply(pl.dprob, pl.row_items, pl.n_row, st);
@@ -1547,7 +1547,7 @@ extern "C" int refine_step_static(const refine_matrix* A, int32_t k, const refin
   if (e == hipSuccess) e = launch_ctrl_reset(dprob, 1, 0, 0.0, st);
   if (e == hipSuccess) e = launch_gemm_f64(dprob, gi, L.n_gemm, k, vec2, STATIC_GEMM_CFG, st);
   if (e == hipSuccess) e = launch_fin_d(dprob, 1, st);
-  if (e == hipSuccess) e = launch_gram(dprob, gri, L.n_gram, k, st);
+  if (e == hipSuccess) e = launch_gram(dprob, gri, L.n_gram, k, false, st);
   if (e == hipSuccess) e = launch_gram_reduce(dprob, rr, L.n_gred, st);
   if (e == hipSuccess) e = launch_kxk(dprob, 1, k, pipeline, st);
   if (fused) {
