@@ -132,6 +132,20 @@ __device__ __forceinline__ int bal_res(double v, int m, double inv) {
   return ri;
 }
 
+// The same residue with one rounded quotient per modulus, for values split
+// once as v = vh 2^28 + vl (vh = rint(v 2^-28), both parts exact):
+// t = vh (2^28 mod m) + vl is congruent to v and exact (|t| < 2^43), so
+// rint(t / m) is correct (its rounding error is far below 1/(2m)), and
+// r = t - m rint(t / m) in [-m/2, m/2] is exact.  The byte is read from the
+// binary64 of r + 1.5 2^52, whose low mantissa bits hold r in two's
+// complement (a plain add instead of a conversion; the tie of m = 256, +-128,
+// gives the byte 0x80 either way).  Equal to bal_res byte for byte.
+__device__ __forceinline__ int bal_res_split(double vh, double vl, int m, double inv) {
+  const double t = __builtin_fma(vh, (double)((1 << 28) % m), vl);
+  const double r = __builtin_fma(-__builtin_rint(t * inv), (double)m, t);
+  return (int)(unsigned)(unsigned long long)__double_as_longlong(r + 0x1.8p52);
+}
+
 __device__ __forceinline__ int scale_exp(double mx) {
   int e = 0;
   if (mx > 0.0) (void)frexp(mx, &e);  // mx = f 2^e, f in [1/2, 1): mx < 2^e
@@ -217,41 +231,47 @@ __global__ __launch_bounds__(256) void crt_ares_kernel(const double* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// Residues of X^T (every step): one thread per unit (chunk, column, half),
-// 16 rows of one column; the column exponent comes from the maxima of |X|.
+// Residues of X^T (every step): one thread per half unit, 8 rows of one
+// column (a unit is a chunk, column and half: 16 rows, 16 bytes per modulus
+// plane), so that the residue arithmetic spreads over twice the wavefronts
+// of a thread per unit; the column exponent comes from the maxima of |X|.
 // ---------------------------------------------------------------------------
 template <int N>
 __global__ __launch_bounds__(256) void crt_xres_kernel(const Prob* __restrict__ probs, CrtArgs ca) {
+  typedef unsigned u2v __attribute__((ext_vector_type(2)));
   const Prob& P = probs[0];
   if (P.ctrl->stopped) return;
   const int kpad = P.kpad, k = P.k, n = P.n;
-  const int64_t units = (int64_t)ca.nchp * kpad * 2;
+  const int64_t halves = (int64_t)ca.nchp * kpad * 4;
   const unsigned long long* mx = reinterpret_cast<const unsigned long long*>(P.xmaxp);
-  for (int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x; u < units;
-       u += (int64_t)gridDim.x * 256) {
-    const int h = (int)(u & 1);
+  for (int64_t su = (int64_t)blockIdx.x * 256 + threadIdx.x; su < halves;
+       su += (int64_t)gridDim.x * 256) {
+    const int64_t u = su >> 1;
+    const int q = (int)(su & 1), h = (int)(u & 1);
     const int64_t cj = u >> 1;
     const int c = (int)(cj / kpad);
     const int j = (int)(cj - (int64_t)c * kpad);
     const int e = j < k ? scale_exp(__longlong_as_double((long long)mx[j])) : 0;
-    if (c == 0 && h == 0) P.xexp[j] = e;
+    if (c == 0 && h == 0 && q == 0) P.xexp[j] = e;
     const int sh = ca.bx - e;
-    const int r0 = c * 32 + h * 16;
-    double v[16];
+    const int r0 = c * 32 + h * 16 + q * 8;
+    double vh[8], vl[8];
 #pragma unroll
-    for (int b = 0; b < 16; ++b)
-      v[b] = (j < k && r0 + b < n) ? __builtin_rint(ldexp(*gld(P.x + (int64_t)(r0 + b) * P.ldx + j), sh))
-                                   : 0.0;
+    for (int b = 0; b < 8; ++b) {
+      const double v = (j < k && r0 + b < n) ? __builtin_rint(ldexp(*gld(P.x + (int64_t)(r0 + b) * P.ldx + j), sh))
+                                             : 0.0;
+      vh[b] = __builtin_rint(v * 0x1p-28);
+      vl[b] = __builtin_fma(-vh[b], 0x1p28, v);
+    }
 #pragma unroll
     for (int t = 0; t < N; ++t) {
       const int m = CRT_MOD[t];
       const double inv = 1.0 / CRT_MOD[t];
-      int r[16];
+      int r[8];
 #pragma unroll
-      for (int b = 0; b < 16; ++b) r[b] = bal_res(v[b], m, inv);
-      const u4v o = {pack4(r[0], r[1], r[2], r[3]), pack4(r[4], r[5], r[6], r[7]),
-                     pack4(r[8], r[9], r[10], r[11]), pack4(r[12], r[13], r[14], r[15])};
-      *reinterpret_cast<u4v*>(ca.xres + t * ca.xres_plane + u * 16) = o;
+      for (int b = 0; b < 8; ++b) r[b] = bal_res_split(vh[b], vl[b], m, inv);
+      const u2v o = {pack4(r[0], r[1], r[2], r[3]), pack4(r[4], r[5], r[6], r[7])};
+      *reinterpret_cast<u2v*>(ca.xres + t * ca.xres_plane + su * 8) = o;
     }
   }
 }
@@ -559,7 +579,7 @@ hipError_t launch_gemm_kt(const SplitPlan& sp, const Prob* dprob, const CrtArgs&
 template <int N>
 hipError_t launch_all_n(const SplitPlan& sp, const Prob* dprob, const CrtArgs& ca, int64_t units,
                         hipStream_t st) {
-  const int grid = (int)std::min<int64_t>((units + 255) / 256, 8192);
+  const int grid = (int)std::min<int64_t>((2 * units + 255) / 256, 16384);
   hipLaunchKernelGGL((crt_xres_kernel<N>), dim3(grid), dim3(256), 0, st, dprob, ca);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

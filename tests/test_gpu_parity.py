@@ -70,10 +70,13 @@ def test_dense_n256_k8_five_steps():
     assert np.max(np.abs(align_signs(X, P.X_true) - P.X_true)) < np.max(np.abs(P.X0 - P.X_true))
 
 
-@pytest.mark.parametrize("n,k", [(1000, 13), (777, 5), (300, 1), (640, 64), (513, 17)])
+@pytest.mark.parametrize("n,k", [(1000, 13), (777, 5), (300, 1), (640, 64), (513, 17), (701, 37),
+                                 (900, 99)])
 def test_dense_ragged_shapes(n, k):
     """Ragged n (not a multiple of the 128-row tiles, odd leading dimension)
-    and ragged k (not a multiple of 16), including k = 1."""
+    and ragged k (not a multiple of 16), including k = 1; odd k above 32 takes
+    the statistics after the update, whose partials (stride 5k) are then
+    summed one slot per thread instead of in pairs."""
     lam = np.concatenate([np.linspace(0.01, 0.6, n - k), np.linspace(0.8, 1.0, k)])
     Q = synth.householder_q(n, n, 123 + n).numpy()
     A = (Q * lam) @ Q.T
