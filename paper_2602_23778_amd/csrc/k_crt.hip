@@ -532,8 +532,12 @@ constexpr int CRT_RROWS = 64;
 struct CrtShape {
   int waves, xg, pf;
 };
-constexpr CrtShape CRT_SHAPES[] = {{8, 2, 2}, {8, 2, 3}, {8, 1, 4}, {8, 4, 2}, {4, 2, 3}, {4, 4, 2}};
+constexpr CrtShape CRT_SHAPES[] = {{8, 2, 2}, {8, 2, 3}, {8, 1, 4}, {8, 4, 2}, {4, 2, 3},
+                                     {4, 4, 2}, {16, 2, 2}, {16, 2, 3}};
 constexpr int CRT_NSHAPES = sizeof(CRT_SHAPES) / sizeof(CRT_SHAPES[0]);
+// order in which the tuner times them: 16 wavefronts (512 W rows, half the
+// blocks of 8) first, since they lead where the row count allows them
+constexpr int CRT_TRY_ORDER[CRT_NSHAPES] = {6, 7, 0, 1, 2, 3, 4, 5};
 
 int rows_pad_of(int64_t n) { return (int)((n + SPLIT_ROW_PAD - 1) / SPLIT_ROW_PAD * SPLIT_ROW_PAD); }
 
@@ -571,6 +575,8 @@ hipError_t launch_gemm_kt(const SplitPlan& sp, const Prob* dprob, const CrtArgs&
   RFK_SHAPE(8, 4, 2)
   RFK_SHAPE(4, 2, 3)
   RFK_SHAPE(4, 4, 2)
+  RFK_SHAPE(16, 2, 2)
+  RFK_SHAPE(16, 2, 3)
   { return hipErrorInvalidValue; }
 #undef RFK_SHAPE
   return hipGetLastError();
@@ -739,19 +745,23 @@ int crt_init(SplitPlan& sp, const refine_matrix& A, int k, int nmod, std::vector
 
   // Launch shape of the residue products: REFINE_CRT_SHAPE=<index> forces
   // one; otherwise each is timed once (on a zero X, the workspace copy of
-  // the update) and a later shape replaces the one kept only when it is
-  // more than 2 % faster, so that shapes within the timing noise of each
+  // the update) in the order above, and a later shape replaces the one kept
+  // only when it is more than 2 % faster, so that shapes within the timing noise of each
   // other do not alternate between processes.
+  // a shape's row block (32 W rows per wavefront) must divide the padded row
+  // count, which bounds the residue planes the products read and write
+  auto fits = [&](int sh) {
+    return sh >= 0 && sh < CRT_NSHAPES && rows_pad % (32 * CRT_SHAPES[sh].waves) == 0;
+  };
   int best = -1;
   if (const char* env = getenv("REFINE_CRT_SHAPE")) {
     const int v = atoi(env);
-    if (v >= 0 && v < CRT_NSHAPES) best = v;
+    if (fits(v)) best = v;
   }
   const std::vector<int64_t> key{n, k, nmod};
   if (best < 0) {
     std::vector<int> hit;
-    if (tune_cache_get("crt", key, &hit) && hit.size() == 1 && hit[0] >= 0 && hit[0] < CRT_NSHAPES)
-      best = hit[0];
+    if (tune_cache_get("crt", key, &hit) && hit.size() == 1 && fits(hit[0])) best = hit[0];
   }
   if (best < 0) {
     const double* saved_x = hp[0].x;
@@ -763,7 +773,9 @@ int crt_init(SplitPlan& sp, const refine_matrix& A, int k, int nmod, std::vector
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return REFINE_EHIP;
     float best_t = 1e30f;
-    for (int sh = 0; sh < CRT_NSHAPES && e == hipSuccess; ++sh) {
+    for (int i = 0; i < CRT_NSHAPES && e == hipSuccess; ++i) {
+      const int sh = CRT_TRY_ORDER[i];
+      if (!fits(sh)) continue;
       int rc = install_shape(sp, sh, nmod, n);
       if (rc != REFINE_OK) {
         (void)hipEventDestroy(e0);
