@@ -154,6 +154,16 @@ __device__ __forceinline__ RFK_GLOBAL T* gst(T* p) {
   return (RFK_GLOBAL T*)p;
 }
 
+// base[i] where ok holds, else zero, by an unconditional load of base[ok ? i
+// : 0] (base[0] must be readable).  A guarded load (ok ? base[i] : 0) becomes
+// a branch around the load, and the join waits for it, so a run of them
+// costs one memory round trip each; these can all be in flight at once.
+template <class T>
+__device__ __forceinline__ T ld_or0(bool ok, const T* base, int64_t i) {
+  const T v = *gld(base + (ok ? i : 0));
+  return ok ? v : T(0);
+}
+
 // Exact transformations used by the accurate residual (Dekker / Knuth).
 // Floating-point contraction is off inside them: a product fused into a
 // later subtraction would be rounded differently from the product the error

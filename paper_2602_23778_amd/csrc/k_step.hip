@@ -26,177 +26,171 @@
 namespace rfk {
 
 // ---------------------------------------------------------------------------
-// pass 2: Gram partials on the matrix cores.  A work item is one row block
-// and one of CH groups of TH column tiles (CH = 2 from k > 48 on: twice the
-// workgroups, each with half the accumulators and operand loads; the groups
-// write disjoint entries of the block's partial).  Wavefront (ti, rg) owns
-// the 16-column tile ti of the left factor for row group rg: it accumulates
-// the tiles (ti, tj) of X^T R for the item's tj and of X^T X for those
-// tj >= ti (X^T X is symmetric; the reduction mirrors the rest) over every
-// RG-th 4-row step of the block.  Lane l reads row (r + l/16) at column
-// (t*16 + l%16), so both MFMA operands are plain row-major reads.  The RG row
-// groups are summed in LDS in a fixed order before the item writes its part
-// of the partial.
+// pass 2: Gram partials on the matrix cores (k > 32).  One work item per
+// (row block, 16-column tile tj of R): the block's RG wavefronts take
+// interleaved 4-row steps of the block's rows.  Each computes r for tile tj
+// only, so every W value is read once, and accumulates the tiles (ti, tj) of
+// X^T R for every left tile ti and (ti, tj), ti <= tj, of X^T X (the upper
+// tiles; the reduction mirrors the rest).  Lane l reads row (r + l/16) at
+// column (t*16 + l%16), so both MFMA operands are plain row-major reads.
+// Loads never branch: rows past the block repeat its first row and columns
+// past k repeat column 0, masked afterwards, so U steps are requested before
+// their products.  The wavefronts' tiles are summed in LDS in a fixed order.
+// Rows < k (block 0 only) go straight to X1^T R1 and X1^T X1, the latter
+// written in full (its lower tiles mirrored), and r itself to R1.
 // ---------------------------------------------------------------------------
-int gram_halves(int kmax) { return (kmax + 15) / 16 >= 4 ? 2 : 1; }
+int gram_groups(int kmax) { return kmax <= 32 ? 1 : (kmax + 15) / 16; }
 
-template <int CT, int RG, int CH>
-__global__ __launch_bounds__(CT * RG * 64) void gram_kernel(const Prob* __restrict__ probs,
+template <int CT, int RG, int U, bool LO>
+__global__ __launch_bounds__(RG * 64) void gram_tile_kernel(const Prob* __restrict__ probs,
                                                            const RowItem* __restrict__ items,
                                                            int nitems) {
-  constexpr int TH = (CT + CH - 1) / CH;
-  constexpr int XR = RG > 1 ? RG - 1 : 1;
-  __shared__ double xch[XR][CT][256];
-  __shared__ double rsq_x[RG][TH * 64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int ti = wave % CT, rg = wave / CT;
+  constexpr int QB = 4;  // tiles per LDS exchange round
+  __shared__ double xch[RG][QB][256];
+  __shared__ double rsq_x[RG][64];
+  const int lane = threadIdx.x & 63, rg = threadIdx.x >> 6;
   const int g = lane >> 4, r16 = lane & 15;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const RowItem item = items[it];
     const Prob& P = probs[item.prob];
     if (P.ctrl->stopped) continue;
-    const int blk = item.blk / CH, t0 = (item.blk % CH) * TH;
     const int n = P.n, k = P.k;
     const int ct_used = (k + 15) / 16;
-    const bool has_lo = P.wlo != nullptr;
+    const int blk = item.blk / ct_used, tj = item.blk - blk * ct_used;
     const double* __restrict__ X = P.x;
+    const double* __restrict__ Wh = P.w;
+    const double* __restrict__ Wl = LO ? P.wlo : P.w;
     const int64_t ldx = P.ldx;
     const int r0 = blk * P.gbrows, r1 = min(n, r0 + P.gbrows);
     const int kk2 = k * k;
-    const bool active = ti < ct_used;
-    double dv[TH];
-    bool cok[TH];
+    const int c = tj * 16 + r16;
+    const bool cok = c < k;
+    const int cc = cok ? c : 0;
+    int ca[CT];
+    bool aok[CT];
 #pragma unroll
-    for (int u = 0; u < TH; ++u) {
-      const int c = (t0 + u) * 16 + r16;
-      cok[u] = t0 + u < CT && c < k;
-      dv[u] = cok[u] ? *gld(P.vec + VEC_D * k + c) : 0.0;
+    for (int ti = 0; ti < CT; ++ti) {
+      const int a = ti * 16 + r16;
+      aok[ti] = a < k;
+      ca[ti] = aok[ti] ? a : 0;
     }
-    const int ca = ti * 16 + r16;
-    const bool aok = ca < k;
-    double rsq[TH];
-#pragma unroll
-    for (int u = 0; u < TH; ++u) rsq[u] = 0.0;
+    const double dv = *gld(P.vec + VEC_D * k + cc);
+    double rsq = 0.0;
 
-    // phase 0: rows < k (only block 0 has them); phase 1: rows >= k
+    // phase 0: rows < k (only block 0 has them); phase 1: rows >= k, whose
+    // partial is written even when the block has none (zeros)
     for (int phase = 0; phase < 2; ++phase) {
       const int lo = phase == 0 ? r0 : max(r0, k);
       const int hi = phase == 0 ? min(r1, k) : r1;
-      if (lo >= hi) continue;
-      v4d accP[TH], accG[TH];
+      if (phase == 0 && lo >= hi) continue;
+      v4d accP[CT], accG[CT];
 #pragma unroll
-      for (int u = 0; u < TH; ++u) {
-        accP[u] = v4d{0.0, 0.0, 0.0, 0.0};
-        accG[u] = v4d{0.0, 0.0, 0.0, 0.0};
+      for (int t = 0; t < CT; ++t) {
+        accP[t] = v4d{0.0, 0.0, 0.0, 0.0};
+        accG[t] = v4d{0.0, 0.0, 0.0, 0.0};
       }
-      if (active) {
-#pragma unroll 2
-        for (int rb = lo + 4 * rg; rb < hi; rb += 4 * RG) {
-          const int row = rb + g;
+      // operands of the U steps from row base on (rows past hi repeat lo)
+      auto load = [&](int base, double(&xa)[U][CT], double(&xt)[U], double(&wv)[U], double(&lv)[U]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int row = base + 4 * u + g;
+          const int rr = row < hi ? row : lo;
+          const double* xr = X + (int64_t)rr * ldx;
+#pragma unroll
+          for (int ti = 0; ti < CT; ++ti) xa[u][ti] = *gld(xr + ca[ti]);
+          xt[u] = *gld(xr + cc);
+          wv[u] = *gld(Wh + (int64_t)rr * k + cc);
+          lv[u] = LO ? *gld(Wl + (int64_t)rr * k + cc) : 0.0;
+        }
+      };
+      // products of the U steps from row base on (rows past hi add zeros)
+      auto step = [&](int base, const double(&xa)[U][CT], const double(&xt)[U], const double(&wv)[U],
+                      const double(&lv)[U]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int row = base + 4 * u + g;
           const bool rok = row < hi;
-          const double* xr = X + (int64_t)(rok ? row : lo) * ldx;
-          const double* wr = P.w + (int64_t)(rok ? row : lo) * k;
-          const double* wl = has_lo ? P.wlo + (int64_t)(rok ? row : lo) * k : nullptr;
-          const double xa = (rok && aok) ? *gld(xr + ca) : 0.0;
-          double xv[TH], rv[TH];
+          const bool ok = rok && cok;
+          const double xm_t = ok ? xt[u] : 0.0;
+          const double rv = ok ? residual(wv[u], lv[u], xt[u], dv, LO) : 0.0;
+          rsq = __builtin_fma(rv, rv, rsq);
 #pragma unroll
-          for (int u = 0; u < TH; ++u) {
-            const int c = (t0 + u) * 16 + r16;
-            if (rok && cok[u]) {
-              const double x = *gld(xr + c);
-              xv[u] = x;
-              rv[u] = residual(*gld(wr + c), has_lo ? *gld(wl + c) : 0.0, x, dv[u], has_lo);
-            } else {
-              xv[u] = 0.0;
-              rv[u] = 0.0;
+          for (int ti = 0; ti < CT; ++ti) {
+            if (ti < ct_used) {
+              const double xm = (rok && aok[ti]) ? xa[u][ti] : 0.0;
+              accP[ti] = mfma_f64(xm, rv, accP[ti]);
+              if (ti <= tj) accG[ti] = mfma_f64(xm, xm_t, accG[ti]);
             }
           }
-#pragma unroll
-          for (int u = 0; u < TH; ++u) {
-            const int t = t0 + u;
-            if (t < ct_used) {
-              accP[u] = mfma_f64(xa, rv[u], accP[u]);
-              if (t >= ti) accG[u] = mfma_f64(xa, xv[u], accG[u]);
-            }
-          }
-          if (ti == 0) {
-#pragma unroll
-            for (int u = 0; u < TH; ++u) rsq[u] = __builtin_fma(rv[u], rv[u], rsq[u]);
-            if (phase == 0 && rok) {
-#pragma unroll
-              for (int u = 0; u < TH; ++u)
-                if (cok[u]) *gst(P.kk + KK_R1 * kk2 + row * k + (t0 + u) * 16 + r16) = rv[u];
-            }
-          }
+          if (phase == 0 && ok) *gst(P.kk + KK_R1 * kk2 + row * k + c) = rv;
         }
+      };
+      // two register sets: the next U steps are requested before the
+      // current ones are multiplied
+      constexpr int STRIDE = RG * 4 * U;
+      double xa0[U][CT], xt0[U], wv0[U], lv0[U], xa1[U][CT], xt1[U], wv1[U], lv1[U];
+      int base = lo + rg * 4 * U;
+      if (base < hi) load(base, xa0, xt0, wv0, lv0);
+      for (; base < hi; base += 2 * STRIDE) {
+        load(base + STRIDE, xa1, xt1, wv1, lv1);
+        step(base, xa0, xt0, wv0, lv0);
+        if (base + STRIDE >= hi) break;
+        load(base + 2 * STRIDE, xa0, xt0, wv0, lv0);
+        step(base + STRIDE, xa1, xt1, wv1, lv1);
       }
-      // sum the row groups into row group 0, one tile at a time
-      if (RG > 1) {
-#pragma unroll
-        for (int t = 0; t < 2 * TH; ++t) {
-          v4d& v = t < TH ? accP[t] : accG[t - TH];
-          if (rg > 0) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) xch[rg - 1][ti][lane * 4 + r] = v[r];
-          }
-          __syncthreads();
-          if (rg == 0) {
-            for (int q = 0; q < RG - 1; ++q) {
-#pragma unroll
-              for (int r = 0; r < 4; ++r) v[r] += xch[q][ti][lane * 4 + r];
-            }
-          }
-          __syncthreads();
-        }
+      double* dstP;
+      double* dstG;
+      if (phase == 0) {
+        dstP = P.kk + KK_PT * kk2;
+        dstG = P.kk + KK_GT * kk2;
+      } else {
+        dstP = P.gpart + (int64_t)blk * (2 * kk2 + k);
+        dstG = dstP + kk2;
       }
-      if (rg == 0 && active) {
-        // register r holds entry (ti*16 + mfma_row(g, r), t*16 + r16)
-        double* dstP;
-        double* dstG;
-        if (phase == 0) {
-          dstP = P.kk + KK_PT * kk2;
-          dstG = P.kk + KK_GT * kk2;
-        } else {
-          dstP = P.gpart + (int64_t)blk * (2 * kk2 + k);
-          dstG = dstP + kk2;
-        }
+      // tile q < CT is (q, tj) of X^T R, q >= CT is (q - CT, tj) of X^T X;
+      // QB tiles a round, each summed over the wavefronts by one of them
 #pragma unroll
-        for (int u = 0; u < TH; ++u) {
-          const int t = t0 + u;
-          const int c = t * 16 + r16;
-          if (t < ct_used && c < k) {
+      for (int q0 = 0; q0 < 2 * CT; q0 += QB) {
+#pragma unroll
+        for (int qq = 0; qq < QB; ++qq) {
+          const int q = q0 + qq;
+          if (q < 2 * CT) {
+            const v4d& v = q < CT ? accP[q < CT ? q : 0] : accG[q >= CT ? q - CT : 0];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) xch[rg][qq][lane * 4 + r] = v[r];
+          }
+        }
+        __syncthreads();
+        for (int qq = rg; qq < QB; qq += RG) {
+          const int q = q0 + qq;
+          const bool is_g = q >= CT;
+          const int ti = is_g ? q - CT : q;
+          if (q < 2 * CT && ti < ct_used && (!is_g || ti <= tj) && cok) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
+              double a = xch[0][qq][lane * 4 + r];
+              for (int w = 1; w < RG; ++w) a += xch[w][qq][lane * 4 + r];
               const int i = ti * 16 + mfma_row(g, r);
               if (i < k) {
-                *gst(dstP + i * k + c) = accP[u][r];
-                if (t >= ti) *gst(dstG + i * k + c) = accG[u][r];
+                *gst((is_g ? dstG : dstP) + i * k + c) = a;
+                if (is_g && phase == 0 && ti < tj) *gst(dstG + c * k + i) = a;
               }
             }
           }
         }
+        __syncthreads();
       }
     }
-    // blocks without rows >= k still publish zero partials (the first column
-    // group writes them all)
-    if (max(r0, k) >= r1 && t0 == 0) {
-      double* dst = P.gpart + (int64_t)blk * (2 * kk2 + k);
-      for (int e = threadIdx.x; e < 2 * kk2; e += blockDim.x) *gst(dst + e) = 0.0;
-    }
-    // column sums of r^2 over the block's rows, for this item's columns
-    if (ti == 0) {
-#pragma unroll
-      for (int u = 0; u < TH; ++u) rsq_x[rg][u * 64 + lane] = rsq[u];
-    }
+    // column sums of r^2 over the block's rows, tile tj
+    rsq_x[rg][lane] = rsq;
     __syncthreads();
-    if (threadIdx.x < TH * 16) {
-      const int u = threadIdx.x / 16, c16 = threadIdx.x % 16, c = (t0 + u) * 16 + c16;
-      if (t0 + u < CT && c < k) {
+    if (threadIdx.x < 16) {
+      const int c16 = threadIdx.x, cs = tj * 16 + c16;
+      if (cs < k) {
         double s = 0.0;
         for (int q = 0; q < RG; ++q)
-          s += (rsq_x[q][u * 64 + c16] + rsq_x[q][u * 64 + 16 + c16]) +
-               (rsq_x[q][u * 64 + 32 + c16] + rsq_x[q][u * 64 + 48 + c16]);
-        *gst(P.gpart + (int64_t)blk * (2 * kk2 + k) + 2 * kk2 + c) = s;
+          s += (rsq_x[q][c16] + rsq_x[q][16 + c16]) + (rsq_x[q][32 + c16] + rsq_x[q][48 + c16]);
+        *gst(P.gpart + (int64_t)blk * (2 * kk2 + k) + 2 * kk2 + cs) = s;
       }
     }
     __syncthreads();
@@ -344,7 +338,11 @@ __global__ __launch_bounds__(RG * 64) void gram_all_kernel(const Prob* __restric
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               const int i = ti * 16 + mfma_row(g, r);
-              if (i < k) *gst((q < NTP ? dstP : dstG) + i * k + c) = sum[r];
+              if (i < k) {
+                *gst((q < NTP ? dstP : dstG) + i * k + c) = sum[r];
+                // X1^T X1 is read in full: its lower tile mirrored
+                if (q >= NTP && phase == 0 && ti < t) *gst(dstG + c * k + i) = sum[r];
+              }
             }
           }
         }
@@ -467,11 +465,12 @@ __global__ __launch_bounds__(256) void update_kernel(const Prob* __restrict__ pr
     for (int t = 0; t < CT; ++t) {
       const int c = t * 16 + r16;
       cok[t] = c < k;
-      dv[t] = cok[t] ? *gld(P.vec + VEC_D * k + c) : 0.0;
-      di[t] = cok[t] ? *gld(P.vec + VEC_DINV * k + c) : 0.0;
+      dv[t] = ld_or0(cok[t], P.vec + VEC_D * k, c);
+      di[t] = ld_or0(cok[t], P.vec + VEC_DINV * k, c);
       xsq[t] = 0.0;
       esq[t] = 0.0;
     }
+    const double* wlb = has_lo ? P.wlo : P.w;  // a readable base either way
     // stage rows [kc0, kc0 + KCH) of [M | N] (columns padded to 16 CT)
     // (every thread issues sixteen loads before their LDS stores)
     auto stage = [&](int kc0) {
@@ -485,7 +484,10 @@ __global__ __launch_bounds__(256) void update_kernel(const Prob* __restrict__ pr
           const int rr = e / BW, cc = e - rr * BW;
           const int half = cc / (CT * 16), cj = cc - half * (CT * 16);
           const int kr = kc0 + rr;
-          v[u] = (e < KCH * BW && kr < k && cj < k) ? *gld(Cm + kr * k2 + half * k + cj) : 0.0;
+          // rows past k meet zero A values and columns past k are not
+          // written, so those entries need only be finite: they repeat row
+          // and column 0 (an unmasked load does not wait on the one before)
+          v[u] = *gld(Cm + (kr < k ? kr : 0) * k2 + half * k + (cj < k ? cj : 0));
         }
 #pragma unroll
         for (int u = 0; u < BAT; ++u) {
@@ -516,7 +518,7 @@ __global__ __launch_bounds__(256) void update_kernel(const Prob* __restrict__ pr
 #pragma unroll
         for (int q = 0; q < AQ; ++q) {
           const int kk = kc0 + 4 * q + g;
-          a_ch[q] = (arok && kk < k) ? *gld(xr + kk) : 0.0;
+          a_ch[q] = ld_or0(arok && kk < k, xr, kk);
         }
       };
       load_a(0);
@@ -529,9 +531,9 @@ __global__ __launch_bounds__(256) void update_kernel(const Prob* __restrict__ pr
             const int row = rc + wave * 16 + mfma_row(g, r);
             const bool ok = cok[t] && row < r1 && row >= k;
             const int64_t o = (int64_t)row * k + t * 16 + r16;
-            ex[t][r] = ok ? *gld(X + (int64_t)row * ldx + t * 16 + r16) : 0.0;
-            ew[t][r] = ok ? *gld(P.w + o) : 0.0;
-            el[t][r] = (ok && has_lo) ? *gld(P.wlo + o) : 0.0;
+            ex[t][r] = ld_or0(ok, X, (int64_t)row * ldx + t * 16 + r16);
+            ew[t][r] = ld_or0(ok, P.w, o);
+            el[t][r] = ld_or0(ok && has_lo, wlb, o);
           }
       }
       for (int kc0 = 0; kc0 < k; kc0 += KCH) {
@@ -555,37 +557,55 @@ __global__ __launch_bounds__(256) void update_kernel(const Prob* __restrict__ pr
           }
         }
       }
-      // epilogue: register r holds row rc + wave*16 + mfma_row(g, r), column t*16 + r16
+      // epilogue: register r holds row rc + wave*16 + mfma_row(g, r), column
+      // t*16 + r16.  Past k = 64, X, W (and W_lo) of EG column tiles at a
+      // time are requested together before any of them is used.
+      constexpr int EG = PRE ? CT : 4;
 #pragma unroll
-      for (int t = 0; t < CT; ++t) {
-        const int c = t * 16 + r16;
-        if (cok[t]) {
+      for (int t0 = 0; t0 < CT; t0 += EG) {
+        double gx[EG][4], gw[EG][4], gl[EG][4];
+#pragma unroll
+        for (int u = 0; u < EG; ++u)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int row = rc + wave * 16 + mfma_row(g, r);
-            if (row < r1) {
-              double xt;
-              if (row < k) {
-                xt = *gld(X1n + row * k + c);
-              } else {
-                const int64_t o = (int64_t)row * k + c;
-                double x, w, wl;
-                if (PRE) {
-                  x = ex[t < PC ? t : 0][r];
-                  w = ew[t < PC ? t : 0][r];
-                  wl = el[t < PC ? t : 0][r];
+            const int t = t0 + u < CT ? t0 + u : CT - 1;
+            if (PRE) {
+              gx[u][r] = ex[t < PC ? t : 0][r];
+              gw[u][r] = ew[t < PC ? t : 0][r];
+              gl[u][r] = el[t < PC ? t : 0][r];
+            } else {
+              const int row = rc + wave * 16 + mfma_row(g, r);
+              const int c = t * 16 + r16;
+              const bool ok = t0 + u < CT && cok[t] && row < r1 && row >= k;
+              const int64_t o = (int64_t)row * k + c;
+              gx[u][r] = ld_or0(ok, X, (int64_t)row * ldx + c);
+              gw[u][r] = ld_or0(ok, P.w, o);
+              gl[u][r] = ld_or0(ok && has_lo, wlb, o);
+            }
+          }
+#pragma unroll
+        for (int u = 0; u < EG; ++u) {
+          const int t = t0 + u;
+          if (t >= CT) break;
+          const int c = t * 16 + r16;
+          if (cok[t]) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = rc + wave * 16 + mfma_row(g, r);
+              if (row < r1) {
+                double xt;
+                if (row < k) {
+                  xt = *gld(X1n + row * k + c);
                 } else {
-                  x = *gld(X + (int64_t)row * ldx + c);
-                  w = *gld(P.w + o);
-                  wl = has_lo ? *gld(P.wlo + o) : 0.0;
+                  const double x = gx[u][r];
+                  const double rr = residual(gw[u][r], gl[u][r], x, dv[t], has_lo);
+                  const double e = (rr - accM[t][r]) * di[t];
+                  xt = (x + e) - accN[t][r];
+                  esq[t] = __builtin_fma(e, e, esq[t]);
                 }
-                const double rr = residual(w, wl, x, dv[t], has_lo);
-                const double e = (rr - accM[t][r]) * di[t];
-                xt = (x + e) - accN[t][r];
-                esq[t] = __builtin_fma(e, e, esq[t]);
+                *gst(P.xn + (int64_t)row * k + c) = xt;
+                xsq[t] = __builtin_fma(xt, xt, xsq[t]);
               }
-              *gst(P.xn + (int64_t)row * k + c) = xt;
-              xsq[t] = __builtin_fma(xt, xt, xsq[t]);
             }
           }
         }
@@ -1132,15 +1152,6 @@ constexpr int ROW_NT = 1024;
 hipError_t launch_gram(const Prob* probs, const RowItem* items, int nitems, int kmax, bool lo,
                        hipStream_t st) {
   const int ct = (kmax + 15) / 16;
-#define RFK_CASE(CTV, RGV)                                                                   \
-  case CTV:                                                                                  \
-    if (gram_halves(kmax) == 2)                                                              \
-      hipLaunchKernelGGL((gram_kernel<CTV, RGV, 2>), dim3(nitems), dim3(CTV * RGV * 64), 0, st, \
-                         probs, items, nitems);                                              \
-    else                                                                                     \
-      hipLaunchKernelGGL((gram_kernel<CTV, RGV, 1>), dim3(nitems), dim3(CTV * RGV * 64), 0, st, \
-                         probs, items, nitems);                                              \
-    break;
   if (ct <= 2) {
 #define RFK_GRAM_ALL(CTV, LOV)                                                                     \
   hipLaunchKernelGGL((gram_all_kernel<CTV, 8, 4, LOV>), dim3(nitems), dim3(512), 0, st, probs, items, \
@@ -1156,9 +1167,17 @@ hipError_t launch_gram(const Prob* probs, const RowItem* items, int nitems, int 
 #undef RFK_GRAM_ALL
     return hipGetLastError();
   }
+#define RFK_CASE(CTV)                                                                               \
+  case CTV:                                                                                         \
+    if (lo)                                                                                         \
+      hipLaunchKernelGGL((gram_tile_kernel<CTV, 4, 4, true>), dim3(nitems), dim3(256), 0, st, probs, \
+                         items, nitems);                                                            \
+    else                                                                                            \
+      hipLaunchKernelGGL((gram_tile_kernel<CTV, 4, 4, false>), dim3(nitems), dim3(256), 0, st, probs, \
+                         items, nitems);                                                            \
+    break;
   switch (ct) {
-    RFK_CASE(3, 2) RFK_CASE(4, 2)
-    RFK_CASE(5, 1) RFK_CASE(6, 1) RFK_CASE(7, 1) RFK_CASE(8, 1)
+    RFK_CASE(3) RFK_CASE(4) RFK_CASE(5) RFK_CASE(6) RFK_CASE(7) RFK_CASE(8)
     default:
       return hipErrorInvalidValue;
   }

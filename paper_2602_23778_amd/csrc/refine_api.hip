@@ -43,7 +43,7 @@ hipError_t launch_ctrl_reset(const Prob*, int, int, double, hipStream_t);
 hipError_t launch_set_x(Prob*, int, double*, int64_t, hipStream_t);
 hipError_t launch_spmm(const Prob*, const RowItem*, int, int, int, int, hipStream_t);
 int spmm_row_lanes(int k, int64_t n, int64_t nnz);
-int gram_halves(int kmax);
+int gram_groups(int kmax);
 hipError_t launch_rr_prep(const Prob*, int, hipStream_t);
 hipError_t launch_rr_solve(const Prob*, int, hipStream_t);
 hipError_t launch_rr_apply(const Prob*, const RowItem*, int, hipStream_t);
@@ -134,12 +134,15 @@ Shape choose_shape(int64_t n, int k, bool single, bool csr) {
     s.rbrows = 256;
   }
   // Gram blocks: at least k rows (the leading k rows must sit in block 0);
-  // about 512 blocks for one long problem (fewer k-by-k partials to reduce),
+  // for one long problem about 512 blocks when k <= 32, and past k = 32,
+  // where each block is one work item per 16-column tile, about 256 / tiles
+  // blocks (one item per CU, and k-by-k partials of few blocks to reduce);
   // 512 rows in a batch (1.3 % faster steps than 256 or 1024 on 512 problems
   // of n <= 2048).
   {
     const int64_t kr = (k + 3) / 4 * 4;
-    const int64_t per = single ? std::max<int64_t>(64, ((n + 511) / 512 + 3) / 4 * 4) : 512;
+    const int64_t nblk = k <= 32 ? 512 : std::max<int64_t>(1, 256 / ((k + 15) / 16));
+    const int64_t per = single ? std::max<int64_t>(64, ((n + nblk - 1) / nblk + 3) / 4 * 4) : 512;
     s.gbrows = (int)std::max<int64_t>(std::max<int64_t>(kr, per), 16);
   }
   // tuning hooks: REFINE_RBROWS, REFINE_GBROWS (rows per streaming / Gram
@@ -439,7 +442,6 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
   pl.ctrl = (Ctrl*)(pl.ws + ctrl_off);
 
   std::vector<RowItem> ri, gri;
-  const int gh = gram_halves(pl.kmax);
   pl.fused = pl.kmax <= 32;
   std::vector<GramRedItem> rr;
   for (int p = 0; p < np; ++p) {
@@ -506,7 +508,24 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
     P.normalize = opt.normalize != 0;
 
     for (int b = 0; b < s.nrb; ++b) ri.push_back(RowItem{p, b});
-    for (int b = 0; b < s.ngb * gh; ++b) gri.push_back(RowItem{p, b});  // (row block, column group)
+    // Gram items: (row block, column tile) as blk = block * tiles + tile
+    // past k = 32 (the kernel is chosen by the batch's largest k)
+    const int gg = pl.kmax <= 32 ? 1 : (k + 15) / 16;
+    if (single && gg > 1) {
+      // the tiles of one row block on one XCD (workgroups go to the eight
+      // XCDs in turn), so that its L2 holds the block's X rows for all of them
+      std::vector<std::vector<int>> q(8);
+      for (int rb = 0; rb < s.ngb; ++rb)
+        for (int t = 0; t < gg; ++t) q[rb % 8].push_back(rb * gg + t);
+      std::vector<size_t> pos(8, 0);
+      for (int b = 0; b < s.ngb * gg; ++b) {
+        int x = b % 8;
+        while (pos[x] == q[x].size()) x = (x + 1) % 8;
+        gri.push_back(RowItem{p, q[x][pos[x]++]});
+      }
+    } else {
+      for (int b = 0; b < s.ngb * gg; ++b) gri.push_back(RowItem{p, b});
+    }
     const int S = 2 * k * k + k;
     for (int s0 = 0; s0 < S; s0 += 64) rr.push_back(GramRedItem{p, s0});
   }
@@ -1439,7 +1458,7 @@ StaticLayout static_layout(int64_t n, int k) {
   L.s.gbrows = (int)std::max<int64_t>(L.s.gbrows, (per + 3) / 4 * 4);
   L.s.ngb = iceil(n, L.s.gbrows);
   L.s.ksplit = 1;
-  L.gh = gram_halves(k);
+  L.gh = gram_groups(k);
   L.n_gemm = iceil(n, gemm_rows_per_block(STATIC_GEMM_CFG));
   L.n_row = L.s.nrb;
   L.n_gram = L.s.ngb * L.gh;

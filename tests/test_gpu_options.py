@@ -105,6 +105,26 @@ def test_close_pair_takes_the_diagonal_block_rule(beta):
     _steps(rf, _dev(A), A, X0, 3, norm_a=1.0, delta_c=c, beta=beta)
 
 
+@pytest.mark.parametrize("k", [24, 40, 80])
+def test_close_group_across_column_tiles(k):
+    """Four targets 1e-9 apart at columns 14-17 (and 30-33 from k = 40 on),
+    across the 16-column tiles of the Gram pass, with delta raised to about
+    1e-7: those pairs take -x_i^T x_j / 2, which needs X^T X in full, the
+    leading rows' part of the tiles below the diagonal included (k = 24: the
+    one-wavefront Gram pass; 40: the per-tile Gram pass; 80: that and the
+    panel pipeline of the k x k stage)."""
+    rf = _lib()
+    n, c = 400, 1e9
+    top = np.linspace(1.0, 0.85, k)
+    for g0 in (14, 30):
+        if g0 + 4 <= k:
+            top[g0:g0 + 4] = top[g0] - 1e-9 * np.arange(4)
+    lam = np.concatenate([top, np.linspace(0.0, 0.7, n - k)])
+    A, Q = _spectral(lam, 304 + k)
+    X0 = synth.fp32_round(Q[:, :k])
+    _steps(rf, _dev(A), A, X0, 3, norm_a=1.0, delta_c=c)
+
+
 def test_residual_stopping_rule():
     """refine_run stops at the first step whose input has ||R||_F / ||A||
     <= tol; the tolerance is the geometric mean of two of the oracle's
