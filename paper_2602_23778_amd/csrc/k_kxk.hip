@@ -721,31 +721,46 @@ __global__ __launch_bounds__(KS_NT) void kxk_small_kernel(const Prob* __restrict
 // ---------------------------------------------------------------------------
 constexpr int PP_LDA = KMAX + 4;  // LDS panel row stride (doubles)
 
+// Loads are never behind a branch, which would make each one wait before
+// the next is issued, and carry no masks: an index past k is clamped to
+// k - 1 (FULL: k = 4 KQ, 64 or 128, where none is past k).  A right
+// operand's rows past k meet the zero-padded columns of the panel in LDS,
+// its columns past k and the elementwise operands past k only feed results
+// that are not stored, so the clamped entries need only be finite.  The
+// k x k offsets are 32-bit from a uniform base, one register per address.
+template <bool FULL>
+__device__ __forceinline__ int pp_cl(int i, int k) {
+  return FULL || i < k ? i : k - 1;
+}
+// base[i] for p < np (partial sums), zero past np
+__device__ __forceinline__ double pp_part(bool ok, const double* base, unsigned i) {
+  const double v = *gld(base + (ok ? i : 0u));
+  return ok ? v : 0.0;
+}
+
 // The right operand b (k x k, read from global memory) of a panel product,
 // fetched into registers for the 16x16 result tile tj: lane l holds
-// b(4q + l/16, tj*16 + l%16) for q < KQ (KQ >= ceil(k/4)), zero past k, so
-// that a kernel can issue every fetch it needs in one round before any of
-// them is consumed.
-template <int KQ, class FB>
+// b(4q + l/16, tj*16 + l%16) for q < KQ (KQ >= ceil(k/4)), indices clamped
+// to k - 1, so that a kernel can issue every fetch it needs in one round
+// before any of them is consumed.
+template <int KQ, bool FULL, class FB>
 __device__ __forceinline__ void pp_fetch(int k, FB b, int tj, double (&bv)[KQ]) {
   const int lane = threadIdx.x & 63, g = lane >> 4, r16 = lane & 15;
   const int j = tj * 16 + r16;
-  const bool jok = j < k;
-  const int kq = (k + 3) / 4;
 #pragma unroll
   for (int q = 0; q < KQ; ++q) {
     const int l = 4 * q + g;
-    bv[q] = (q < kq && l < k && jok) ? b(l, j) : 0.0;
+    bv[q] = b(pp_cl<FULL>(l, k), pp_cl<FULL>(j, k));
   }
 }
 
 // (16 x k panel in LDS, row stride PP_LDA) x (fetched right operand): the
 // 16x16 result tile tj; register r of lane l holds row pi*16 + l/16 + 4r and
 // column tj*16 + l%16.
-template <int KQ>
+template <int KQ, bool FULL>
 __device__ __forceinline__ v4d pp_mul(int k, const double* As, const double (&bv)[KQ]) {
   const int lane = threadIdx.x & 63, g = lane >> 4, r16 = lane & 15;
-  const int kq = (k + 3) / 4;
+  const int kq = FULL ? KQ : (k + 3) / 4;
   v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int q = 0; q < KQ; q += 2) {
@@ -760,33 +775,39 @@ __device__ __forceinline__ v4d pp_mul(int k, const double* As, const double (&bv
 // most (16 * kp <= 4 * blockDim for kp <= 16 np, blockDim = 64 np), all
 // issued before the first LDS store.  No closing barrier: several panels can
 // be requested together, and the caller synchronises.
-template <class FA>
+template <int KQ, bool FULL, class FA>
 __device__ __forceinline__ void pp_load_nb(int k, int pi, double* As, FA a) {
-  const int kp = (k + 3) / 4 * 4;
+  const int kp = FULL ? 4 * KQ : (k + 3) / 4 * 4;
   double v[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int e = threadIdx.x + u * blockDim.x;
     const int r = e / kp, l = e - r * kp;
     const int i = pi * 16 + r;
-    v[u] = (e < 16 * kp && i < k && l < k) ? a(i, l) : 0.0;
+    if constexpr (FULL) {
+      v[u] = a(i, l);
+    } else {
+      const bool ok = e < 16 * kp && i < k && l < k;
+      const double t = a(ok ? i : 0, ok ? l : 0);
+      v[u] = ok ? t : 0.0;
+    }
   }
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int e = threadIdx.x + u * blockDim.x;
-    if (e < 16 * kp) As[(e / kp) * PP_LDA + e % kp] = v[u];
+    if (FULL || e < 16 * kp) As[(e / kp) * PP_LDA + e % kp] = v[u];
   }
 }
 
 // Calls f(i, j, v) for the valid entries of a tile result.
-template <class FS>
+template <bool FULL, class FS>
 __device__ __forceinline__ void pp_each(int k, int pi, int tj, const v4d& acc, FS f) {
   const int lane = threadIdx.x & 63, g = lane >> 4, r16 = lane & 15;
   const int j = tj * 16 + r16;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int i = pi * 16 + mfma_row(g, r);
-    if (i < k && j < k) f(i, j, acc[r]);
+    if (FULL || (i < k && j < k)) f(i, j, acc[r]);
   }
 }
 
@@ -807,8 +828,9 @@ __device__ __forceinline__ double pp_y1(const Prob& P, int i, int l) {
 
 // Every kernel of the pipeline requests all it needs (panels, right
 // operands, partial sums) in one round at its start, so that it waits on
-// memory once rather than once per product.
-template <int KQ>
+// memory once rather than once per product (past k = 64 a third right
+// operand comes once the first products are done, within the register file).
+template <int KQ, bool FULL>
 __global__ __launch_bounds__(512) void pp_res_kernel(const Prob* __restrict__ probs) {
   __shared__ double As[16 * PP_LDA];
   __shared__ double red[8];
@@ -829,47 +851,50 @@ __global__ __launch_bounds__(512) void pp_res_kernel(const Prob* __restrict__ pr
   const double* R1 = P.kk + KK_R1 * kk2;
   const double* d = P.vec + VEC_D * k;
   const double* alpha = P.vec + VEC_ALPHA * k;
+  const bool rr_top = ctrl->rr_top != 0;
+  const double delta = P.delta;
+  const bool beta_zero = P.beta_zero != 0;
   // this lane's four entries (rows pi*16 + g + 4r, column tj*16 + r16), the
   // right operand Y1 and the panel of Z0
   const int j = tj * 16 + r16;
   double by[KQ];
-  pp_fetch<KQ>(k, [&](int l, int jj) { return pp_y1(P, l, jj); }, tj, by);
+  pp_fetch<KQ, FULL>(k, [&](int l, int jj) { return pp_y1(P, l, jj); }, tj, by);
   double vpt[4], vp2[4], vr1[4], vg[4], di[4], ai[4];
-  const double dj = j < k ? *gld(d + j) : 0.0;
+  const int jc = pp_cl<FULL>(j, k);
+  const double dj = *gld(d + jc);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const int i = pi * 16 + mfma_row(g, r);
-    const bool ok = i < k && j < k;
-    const int e = ok ? i * k + j : 0;
-    vpt[r] = ok ? *gld(PT + e) : 0.0;
-    vp2[r] = ok ? *gld(P2 + e) : 0.0;
-    vr1[r] = ok ? *gld(R1 + e) : 0.0;
-    vg[r] = ok ? *gld(GT + e) + *gld(G2 + e) : 0.0;
-    di[r] = i < k ? *gld(d + i) : 0.0;
-    ai[r] = i < k ? *gld(alpha + i) : 0.0;
+    const int ic = pp_cl<FULL>(pi * 16 + mfma_row(g, r), k);
+    const unsigned e = (unsigned)(ic * k + jc);
+    vpt[r] = *gld(PT + e);
+    vp2[r] = *gld(P2 + e);
+    vr1[r] = *gld(R1 + e);
+    vg[r] = *gld(GT + e) + *gld(G2 + e);
+    di[r] = *gld(d + ic);
+    ai[r] = *gld(alpha + ic);
   }
-  pp_load_nb(k, pi, As, [&](int i, int l) { return *gld(Zg + i * k + l); });
+  pp_load_nb<KQ, FULL>(k, pi, As, [&](int i, int l) { return *gld(Zg + (unsigned)(i * k + l)); });
   __syncthreads();
   // F0 = I - Z0 Y1
-  const v4d acc = pp_mul<KQ>(k, As, by);
+  const v4d acc = pp_mul<KQ, FULL>(k, As, by);
   double f2 = 0.0, e2 = 0.0;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int i = pi * 16 + mfma_row(g, r);
-    if (i < k && j < k) {
-      const int e = i * k + j;
+    if (FULL || (i < k && j < k)) {
+      const unsigned e = (unsigned)(i * k + j);
       const double f = (i == j ? 1.0 : 0.0) - acc[r];
       *gst(F0 + e) = f;
       f2 = __builtin_fma(f, f, f2);
       const double v1 = vpt[r] + vp2[r];
       *gst(Cb + e) = v1 - vr1[r];
       double ev;
-      if (ctrl->rr_top)
+      if (rr_top)
         ev = 0.0;  // X is a Rayleigh-Ritz basis (Sec. 3.4, clustered eigenvalues)
       else if (i == j)
         ev = (1.0 - ai[r]) * 0.5;
-      else if (fabs(dj - di[r]) <= P.delta)
-        ev = P.beta_zero ? 0.0 : -vg[r] * 0.5;
+      else if (fabs(dj - di[r]) <= delta)
+        ev = beta_zero ? 0.0 : -vg[r] * 0.5;
       else
         ev = v1 / (dj - di[r]);
       *gst(E1 + e) = ev;
@@ -884,30 +909,35 @@ __global__ __launch_bounds__(512) void pp_res_kernel(const Prob* __restrict__ pr
   }
 }
 
-template <int KQ>
+template <int KQ, bool FULL>
 __global__ __launch_bounds__(512) void pp_ns_kernel(const Prob* __restrict__ probs) {
   __shared__ double As[16 * PP_LDA];
   __shared__ double Bs[16 * PP_LDA];
   const Prob& P = probs[0];
   Ctrl* ctrl = P.ctrl;
   if (ctrl->stopped) return;
-  const int k = P.k, kk2 = k * k, pi = blockIdx.x, tj = threadIdx.x >> 6;
-  const int np = (k + 15) / 16;
+  const int k = P.k, kk2 = k * k, pi = blockIdx.x;
+  const int tj = threadIdx.x >> 6;
+  const int np = FULL ? KQ / 4 : (k + 15) / 16;
   const double* Zg = P.kk + KK_Z * kk2;
   const double* F0 = P.kk + KK_S0 * kk2;
   const double* Cb = P.kk + (KK_S0 + 1) * kk2;
   double* Zn = P.kk + (KK_S0 + 3) * kk2;
   double* Cm = P.kk + KK_CM * kk2;
-  // one round: F0, Z0 and C as right operands, the panel of F0 and the
-  // partial norms of F0 (fetched before the acceptance test; unused if the
-  // warm start is rejected)
+  // one round: F0 and Z0 as right operands, the panel of F0 and the partial
+  // norms of F0 (fetched before the acceptance test; unused if the warm
+  // start is rejected); C follows past k = 64, once F0^3 is formed
   double bF[KQ], bZ[KQ], bC[KQ];
-  pp_fetch<KQ>(k, [&](int l, int j) { return *gld(F0 + l * k + j); }, tj, bF);
-  pp_fetch<KQ>(k, [&](int l, int j) { return *gld(Zg + l * k + j); }, tj, bZ);
-  pp_fetch<KQ>(k, [&](int l, int j) { return *gld(Cb + l * k + j); }, tj, bC);
-  pp_load_nb(k, pi, As, [&](int i, int l) { return *gld(F0 + i * k + l); });  // As = F0 panel
+  auto fetch_c = [&]() {
+    pp_fetch<KQ, FULL>(k, [&](int l, int j) { return *gld(Cb + (unsigned)(l * k + j)); }, tj, bC);
+  };
+  pp_fetch<KQ, FULL>(k, [&](int l, int j) { return *gld(F0 + (unsigned)(l * k + j)); }, tj, bF);
+  pp_fetch<KQ, FULL>(k, [&](int l, int j) { return *gld(Zg + (unsigned)(l * k + j)); }, tj, bZ);
+  if constexpr (KQ <= 16) fetch_c();
+  pp_load_nb<KQ, FULL>(k, pi, As, [&](int i, int l) { return *gld(F0 + (unsigned)(i * k + l)); });
   double f2 = 0.0;
-  for (int p = 0; p < np; ++p) f2 += P.kpp[p];
+#pragma unroll
+  for (int p = 0; p < 8; ++p) f2 += pp_part(p < np, P.kpp, (unsigned)p);  // np <= 8
   const double eres = sqrt(f2);
   const double tol = 16.0 * k * UNIT_ROUNDOFF;
   const bool accept = (eres * eres) * (eres * eres) <= tol;
@@ -916,38 +946,39 @@ __global__ __launch_bounds__(512) void pp_ns_kernel(const Prob* __restrict__ pro
   __syncthreads();
   // T = I + F0 + F0^2 + F0^3 on this panel, accumulated in Bs
   {
-    const int kp = (k + 3) / 4 * 4;
+    const int kp = FULL ? 4 * KQ : (k + 3) / 4 * 4;
     for (int e = threadIdx.x; e < 16 * kp; e += blockDim.x) {
       const int r = e / kp, l = e - r * kp;
       const int i = pi * 16 + r;
-      Bs[r * PP_LDA + l] = (i < k && l < k) ? As[r * PP_LDA + l] + (i == l ? 1.0 : 0.0) : 0.0;
+      Bs[r * PP_LDA + l] = (FULL || (i < k && l < k)) ? As[r * PP_LDA + l] + (i == l ? 1.0 : 0.0) : 0.0;
     }
   }
   for (int pw = 2; pw <= 3; ++pw) {
     // As <- As F0 (F0^pw on the panel); Bs += As
-    const v4d acc = pp_mul<KQ>(k, As, bF);
+    const v4d acc = pp_mul<KQ, FULL>(k, As, bF);
     __syncthreads();
-    pp_each(k, pi, tj, acc, [&](int i, int j, double v) {
+    pp_each<FULL>(k, pi, tj, acc, [&](int i, int j, double v) {
       const int r = i - pi * 16;
       As[r * PP_LDA + j] = v;
       Bs[r * PP_LDA + j] += v;
     });
     __syncthreads();
   }
+  if constexpr (KQ > 16) fetch_c();
   // Z = T Z0 on this panel -> As and Zn
   {
-    const v4d acc = pp_mul<KQ>(k, Bs, bZ);
+    const v4d acc = pp_mul<KQ, FULL>(k, Bs, bZ);
     __syncthreads();
-    pp_each(k, pi, tj, acc, [&](int i, int j, double v) {
+    pp_each<FULL>(k, pi, tj, acc, [&](int i, int j, double v) {
       As[(i - pi * 16) * PP_LDA + j] = v;
-      *gst(Zn + i * k + j) = v;
+      *gst(Zn + (unsigned)(i * k + j)) = v;
     });
     __syncthreads();
   }
   // M = -Z C
   {
-    const v4d acc = pp_mul<KQ>(k, As, bC);
-    pp_each(k, pi, tj, acc, [&](int i, int j, double v) { *gst(Cm + i * 2 * k + j) = -v; });
+    const v4d acc = pp_mul<KQ, FULL>(k, As, bC);
+    pp_each<FULL>(k, pi, tj, acc, [&](int i, int j, double v) { *gst(Cm + (unsigned)(i * 2 * k + j)) = -v; });
   }
   // column sums of |Z| over the panel's rows
   for (int j = threadIdx.x; j < k; j += blockDim.x) {
@@ -957,7 +988,7 @@ __global__ __launch_bounds__(512) void pp_ns_kernel(const Prob* __restrict__ pro
   }
 }
 
-template <int KQ>
+template <int KQ, bool FULL>
 __global__ __launch_bounds__(512) void pp_f_kernel(const Prob* __restrict__ probs) {
   __shared__ double As[3][16 * PP_LDA];
   const Prob& P = probs[0];
@@ -979,41 +1010,43 @@ __global__ __launch_bounds__(512) void pp_f_kernel(const Prob* __restrict__ prob
   // (past k = 64 the third operand is fetched once the first two are used,
   // which keeps the three within the register file)
   double bE[KQ], bM[KQ], bZt[KQ];
-  auto fetch_zt = [&]() { pp_fetch<KQ>(k, [&](int l, int jj) { return *gld(Zn + jj * k + l); }, tj, bZt); };
-  pp_fetch<KQ>(k, [&](int l, int jj) { return *gld(E1 + l * k + jj); }, tj, bE);
-  pp_fetch<KQ>(k, [&](int l, int jj) { return *gld(Cm + l * 2 * k + jj); }, tj, bM);
+  auto fetch_zt = [&]() {
+    pp_fetch<KQ, FULL>(k, [&](int l, int jj) { return *gld(Zn + (unsigned)(jj * k + l)); }, tj, bZt);
+  };
+  pp_fetch<KQ, FULL>(k, [&](int l, int jj) { return *gld(E1 + (unsigned)(l * k + jj)); }, tj, bE);
+  pp_fetch<KQ, FULL>(k, [&](int l, int jj) { return *gld(Cm + (unsigned)(l * 2 * k + jj)); }, tj, bM);
   if constexpr (KQ <= 16) fetch_zt();
   double vp2[4], ve1[4], zc[4];
-  const double dj = j < k ? *gld(P.vec + VEC_DINV * k + j) : 0.0;
+  const int jc = pp_cl<FULL>(j, k);
+  const double dj = *gld(P.vec + VEC_DINV * k + jc);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const int i = pi * 16 + mfma_row(g, r);
-    const bool ok = i < k && j < k;
-    const int e = ok ? i * k + j : 0;
-    vp2[r] = ok ? *gld(P2 + e) : 0.0;
-    ve1[r] = ok ? *gld(E1 + e) : 0.0;
-    zc[r] = ok ? *gld(Zn + e) : 0.0;
+    const int ic = pp_cl<FULL>(pi * 16 + mfma_row(g, r), k);
+    const unsigned e = (unsigned)(ic * k + jc);
+    vp2[r] = *gld(P2 + e);
+    ve1[r] = *gld(E1 + e);
+    zc[r] = *gld(Zn + e);
   }
-  pp_load_nb(k, pi, As[0], [&](int i, int l) { return *gld(P.x + (int64_t)l * P.ldx + i); });
-  pp_load_nb(k, pi, As[1], [&](int i, int l) { return *gld(G2 + i * k + l); });
-  pp_load_nb(k, pi, As[2], [&](int i, int l) { return pp_y1(P, i, l); });
+  pp_load_nb<KQ, FULL>(k, pi, As[0], [&](int i, int l) { return *gld(P.x + (int64_t)l * P.ldx + i); });
+  pp_load_nb<KQ, FULL>(k, pi, As[1], [&](int i, int l) { return *gld(G2 + (unsigned)(i * k + l)); });
+  pp_load_nb<KQ, FULL>(k, pi, As[2], [&](int i, int l) { return pp_y1(P, i, l); });
   __syncthreads();
   // F = X1^T E11 + (P2 - G2 M) diag(dinv) - E11
-  const v4d fa = pp_mul<KQ>(k, As[0], bE);
-  const v4d fb = pp_mul<KQ>(k, As[1], bM);
+  const v4d fa = pp_mul<KQ, FULL>(k, As[0], bE);
+  const v4d fb = pp_mul<KQ, FULL>(k, As[1], bM);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int i = pi * 16 + mfma_row(g, r);
-    if (i < k && j < k) {
-      const int e = i * k + j;
+    if (FULL || (i < k && j < k)) {
+      const unsigned e = (unsigned)(i * k + j);
       *gst(Fm + e) = fa[r] + (vp2[r] - fb[r]) * dj - ve1[r];
       *gst(Zg + e) = zc[r];  // the next step's warm start
     }
   }
   // Q = Y1 Z^T, and the column sums of |Y1| over this panel's rows
   if constexpr (KQ > 16) fetch_zt();
-  const v4d qa = pp_mul<KQ>(k, As[2], bZt);
-  pp_each(k, pi, tj, qa, [&](int i, int jj, double v) { *gst(Q + i * k + jj) = v; });
+  const v4d qa = pp_mul<KQ, FULL>(k, As[2], bZt);
+  pp_each<FULL>(k, pi, tj, qa, [&](int i, int jj, double v) { *gst(Q + (unsigned)(i * k + jj)) = v; });
   for (int c = threadIdx.x; c < k; c += blockDim.x) {
     double a = 0.0;
     for (int r = 0; r < 16; ++r) a += fabs(As[2][r * PP_LDA + c]);  // zero rows beyond k
@@ -1021,7 +1054,7 @@ __global__ __launch_bounds__(512) void pp_f_kernel(const Prob* __restrict__ prob
   }
 }
 
-template <int KQ>
+template <int KQ, bool FULL>
 __global__ __launch_bounds__(512) void pp_n_kernel(const Prob* __restrict__ probs) {
   __shared__ double As[2][16 * PP_LDA];
   __shared__ double red[2][8];
@@ -1030,7 +1063,7 @@ __global__ __launch_bounds__(512) void pp_n_kernel(const Prob* __restrict__ prob
   if (ctrl->stopped || ctrl->kxk_fb) return;
   const int n = P.n, k = P.k, kk2 = k * k, pi = blockIdx.x, tj = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63, g = lane >> 4, r16 = lane & 15;
-  const int np = (k + 15) / 16;
+  const int np = FULL ? KQ / 4 : (k + 15) / 16;
   const double* Zn = P.kk + (KK_S0 + 3) * kk2;
   const double* Fm = P.kk + KK_S0 * kk2;
   const double* E1 = P.kk + (KK_S0 + 2) * kk2;
@@ -1041,28 +1074,40 @@ __global__ __launch_bounds__(512) void pp_n_kernel(const Prob* __restrict__ prob
   // one round: F as the right operand of both products, the panels of Z^T
   // and Q, the elementwise parts and the column sums for cond_1
   double bF[KQ];
-  pp_fetch<KQ>(k, [&](int l, int jj) { return *gld(Fm + l * k + jj); }, tj, bF);
+  pp_fetch<KQ, FULL>(k, [&](int l, int jj) { return *gld(Fm + (unsigned)(l * k + jj)); }, tj, bF);
   double vx[4], ve1[4];
+  const int jc = pp_cl<FULL>(j, k);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const int i = pi * 16 + mfma_row(g, r);
-    const bool ok = i < k && j < k;
-    vx[r] = ok ? *gld(P.x + (int64_t)i * P.ldx + j) : 0.0;
-    ve1[r] = ok ? *gld(E1 + i * k + j) : 0.0;
+    const int ic = pp_cl<FULL>(pi * 16 + mfma_row(g, r), k);
+    vx[r] = *gld(P.x + (int64_t)ic * P.ldx + jc);
+    ve1[r] = *gld(E1 + (unsigned)(ic * k + jc));
   }
-  pp_load_nb(k, pi, As[0], [&](int i, int l) { return *gld(Zn + l * k + i); });
-  pp_load_nb(k, pi, As[1], [&](int i, int l) { return *gld(Q + i * k + l); });
+  pp_load_nb<KQ, FULL>(k, pi, As[0], [&](int i, int l) { return *gld(Zn + (unsigned)(l * k + i)); });
+  pp_load_nb<KQ, FULL>(k, pi, As[1], [&](int i, int l) { return *gld(Q + (unsigned)(i * k + l)); });
   // cond_1(Y1) = ||Y1||_1 ||Z||_1 from the panel column sums (the same in
   // every block); a failure stops the step before the update applies it
+  // (k <= blockDim: one column per thread, its partials requested together)
   double cy = 0.0, cz = 0.0;
-  for (int c = threadIdx.x; c < k; c += blockDim.x) {
-    double a = 0.0, b = 0.0;
-    for (int p = 0; p < np; ++p) {
-      a += P.kpp[16 + p * k + c];
-      b += P.kpp[16 + 8 * k + p * k + c];
+  {
+    constexpr int NPM = FULL ? KQ / 4 : 8;  // np <= 8
+    const int c = (int)threadIdx.x < k ? (int)threadIdx.x : 0;
+    double va[NPM], vb[NPM];
+#pragma unroll
+    for (int p = 0; p < NPM; ++p) {
+      va[p] = pp_part(FULL || p < np, P.kpp + 16 + c, (unsigned)(p * k));
+      vb[p] = pp_part(FULL || p < np, P.kpp + 16 + 8 * k + c, (unsigned)(p * k));
     }
-    cy = fmax(cy, a);
-    cz = fmax(cz, b);
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int p = 0; p < NPM; ++p) {
+      a += va[p];
+      b += vb[p];
+    }
+    if ((int)threadIdx.x < k) {
+      cy = a;
+      cz = b;
+    }
   }
   for (int o = 32; o >= 1; o /= 2) {
     cy = fmax(cy, __shfl_xor(cy, o));
@@ -1086,18 +1131,19 @@ __global__ __launch_bounds__(512) void pp_n_kernel(const Prob* __restrict__ prob
     return;
   }
   // N = -Z^T F
-  const v4d na = pp_mul<KQ>(k, As[0], bF);
-  pp_each(k, pi, tj, na, [&](int i, int jj, double v) { *gst(Cm + i * 2 * k + k + jj) = -v; });
+  const v4d na = pp_mul<KQ, FULL>(k, As[0], bF);
+  pp_each<FULL>(k, pi, tj, na, [&](int i, int jj, double v) { *gst(Cm + (unsigned)(i * 2 * k + k + jj)) = -v; });
   // X1 + E11 + Q F
-  const v4d xa = pp_mul<KQ>(k, As[1], bF);
+  const v4d xa = pp_mul<KQ, FULL>(k, As[1], bF);
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int i = pi * 16 + mfma_row(g, r);
-    if (i < k && j < k) *gst(X1n + i * k + j) = vx[r] + ve1[r] + xa[r];
+    if (FULL || (i < k && j < k)) *gst(X1n + (unsigned)(i * k + j)) = vx[r] + ve1[r] + xa[r];
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     double e2 = 0.0;
-    for (int p = 0; p < np; ++p) e2 += P.kpp[8 + p];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) e2 += pp_part(p < np, P.kpp + 8, (unsigned)p);
     P.vec[VEC_E1SQ * k] = e2;
   }
 }
@@ -1113,24 +1159,27 @@ hipError_t launch_kxk(const Prob* probs, int nprob, int kmax, bool pipeline, hip
     const int np = (kmax + 15) / 16;
     const dim3 grid(np), block(64 * np);
     const bool q16 = kmax <= 64;  // contraction in groups of four: 16 or 32 groups
-    if (q16) {
-      hipLaunchKernelGGL(pp_res_kernel<16>, grid, block, 0, st, probs);
-      hipLaunchKernelGGL(pp_ns_kernel<16>, grid, block, 0, st, probs);
-    } else {
-      hipLaunchKernelGGL(pp_res_kernel<32>, grid, block, 0, st, probs);
-      hipLaunchKernelGGL(pp_ns_kernel<32>, grid, block, 0, st, probs);
-    }
+    const bool full = kmax == 64 || kmax == 128;  // k = 4 KQ: no entry masked
+#define RFK_PP(KERNEL)                                                         \
+  do {                                                                         \
+    if (q16 && full)                                                           \
+      hipLaunchKernelGGL((KERNEL<16, true>), grid, block, 0, st, probs);       \
+    else if (q16)                                                              \
+      hipLaunchKernelGGL((KERNEL<16, false>), grid, block, 0, st, probs);      \
+    else if (full)                                                             \
+      hipLaunchKernelGGL((KERNEL<32, true>), grid, block, 0, st, probs);       \
+    else                                                                       \
+      hipLaunchKernelGGL((KERNEL<32, false>), grid, block, 0, st, probs);      \
+  } while (0)
+    RFK_PP(pp_res_kernel);
+    RFK_PP(pp_ns_kernel);
     if (kmax <= KS_K)
       hipLaunchKernelGGL(kxk_small_kernel, dim3(1), dim3(KS_NT), 0, st, probs, 1, 1);
     else
       hipLaunchKernelGGL(kxk_kernel<false>, dim3(1), dim3(KXK_NT), 0, st, probs, 1, 1);
-    if (q16) {
-      hipLaunchKernelGGL(pp_f_kernel<16>, grid, block, 0, st, probs);
-      hipLaunchKernelGGL(pp_n_kernel<16>, grid, block, 0, st, probs);
-    } else {
-      hipLaunchKernelGGL(pp_f_kernel<32>, grid, block, 0, st, probs);
-      hipLaunchKernelGGL(pp_n_kernel<32>, grid, block, 0, st, probs);
-    }
+    RFK_PP(pp_f_kernel);
+    RFK_PP(pp_n_kernel);
+#undef RFK_PP
     return hipGetLastError();
   }
   if (kmax <= KS_K)
