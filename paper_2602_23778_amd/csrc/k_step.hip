@@ -639,6 +639,176 @@ __global__ __launch_bounds__(256) void update_kernel(const Prob* __restrict__ pr
   }
 }
 
+// The same pass for 64 < k <= 128 (CT 5..8): one 64-row tile of X at a time
+// in LDS (read once, with consecutive threads on consecutive entries),
+// shared by the block's four wavefronts.  Wavefront w owns the column tiles
+// w and w + 4 of X~ for all 64 rows, so it needs only the matching columns
+// of M and N, which it streams from L2 (the same for every tile) DB K-steps
+// ahead of its products; W and W_lo of its entries are requested with the
+// tile.  Each wavefront's products are 4 row tiles x 2 column tiles x {M, N},
+// the same count for every wavefront at k = 128, against the staging of all
+// of [M | N] through LDS in the form above.  Rows past the item's end and
+// columns past k are clamped (finite, never stored); the tile's columns from
+// k to the next multiple of 4 are zero, which bounds the contraction.
+template <int CT>
+__global__ __launch_bounds__(256) void update_wide_kernel(const Prob* __restrict__ probs,
+                                                         const RowItem* __restrict__ items, int nitems) {
+  constexpr int WAVES = 4, TW = 2, ROWS = 64, LDX = KMAX + 4, DB = 4;
+  static_assert(CT > 4 && CT <= WAVES * TW, "64 < k <= 128");
+  __shared__ double Xs[ROWS * LDX];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, r16 = lane & 15;
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const RowItem item = items[it];
+    const Prob& P = probs[item.prob];
+    if (P.ctrl->stopped) continue;
+    const int n = P.n, k = P.k, kk2 = k * k, k2 = 2 * k;
+    const int kq = (k + 3) / 4, kp = 4 * kq;
+    const bool has_lo = P.wlo != nullptr;
+    const double* __restrict__ X = P.x;
+    const int64_t ldx = P.ldx;
+    const double* __restrict__ Cm = P.kk + KK_CM * kk2;
+    const double* __restrict__ X1n = P.kk + KK_X1N * kk2;
+    const double* wlb = has_lo ? P.wlo : P.w;  // a readable base either way
+    const int r0 = item.blk * P.rbrows, r1 = min(n, r0 + P.rbrows);
+    // this wavefront's columns
+    int cc[TW];
+    bool cok[TW];
+    double dv[TW], di[TW], xsq[TW], esq[TW];
+#pragma unroll
+    for (int u = 0; u < TW; ++u) {
+      const int c = (wave + WAVES * u) * 16 + r16;
+      cok[u] = c < k;
+      cc[u] = cok[u] ? c : k - 1;
+      dv[u] = *gld(P.vec + VEC_D * k + cc[u]);
+      di[u] = *gld(P.vec + VEC_DINV * k + cc[u]);
+      xsq[u] = 0.0;
+      esq[u] = 0.0;
+    }
+    const bool busy = wave < (k + 15) / 16;  // owns at least one column tile
+    for (int rc = r0; rc < r1; rc += ROWS) {
+      __syncthreads();  // the previous tile's LDS reads are done
+      // the X tile (rows past r1 repeat row r1 - 1), columns to kp: wavefront
+      // w reads rows 16w..16w+15, lane l columns l and l + 64, all at once
+      {
+        double xv[16][2];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int row = min(rc + wave * 16 + i, r1 - 1);
+#pragma unroll
+          for (int h = 0; h < 2; ++h) xv[i][h] = *gld(X + (int64_t)row * ldx + min(lane + 64 * h, k - 1));
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int col = lane + 64 * h;
+            if (col < kp) Xs[(wave * 16 + i) * LDX + col] = col < k ? xv[i][h] : 0.0;
+          }
+      }
+      // W and W_lo of this wavefront's entries
+      double wv[4][TW][4], lv[4][TW][4];
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int u = 0; u < TW; ++u)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = min(rc + rt * 16 + mfma_row(g, r), r1 - 1);
+            const int64_t o = (int64_t)row * k + cc[u];
+            wv[rt][u][r] = *gld(P.w + o);
+            lv[rt][u][r] = *gld(wlb + o);
+          }
+      v4d accM[4][TW], accN[4][TW];
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int u = 0; u < TW; ++u) {
+          accM[rt][u] = v4d{0.0, 0.0, 0.0, 0.0};
+          accN[rt][u] = v4d{0.0, 0.0, 0.0, 0.0};
+        }
+      // B fragments of K-step q: lane l holds [M | N](4q + l/16, column)
+      double bM[DB][TW], bN[DB][TW];
+      auto load_b = [&](int q, double(&m)[TW], double(&nn)[TW]) {
+        const int kr = min(4 * q + g, k - 1);
+#pragma unroll
+        for (int u = 0; u < TW; ++u) {
+          m[u] = *gld(Cm + (unsigned)(kr * k2 + cc[u]));
+          nn[u] = *gld(Cm + (unsigned)(kr * k2 + k + cc[u]));
+        }
+      };
+#pragma unroll
+      for (int s = 0; s < DB; ++s) load_b(s, bM[s], bN[s]);
+      __syncthreads();  // the tile is in LDS
+      if (busy) {
+        for (int q0 = 0; q0 < kq; q0 += DB) {
+#pragma unroll
+          for (int s = 0; s < DB; ++s) {
+            const int q = q0 + s;
+            if (q < kq) {
+              double a[4];
+#pragma unroll
+              for (int rt = 0; rt < 4; ++rt) a[rt] = Xs[(rt * 16 + r16) * LDX + 4 * q + g];
+#pragma unroll
+              for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                for (int u = 0; u < TW; ++u) {
+                  if (wave + WAVES * u < CT) {
+                    accM[rt][u] = mfma_f64(a[rt], bM[s][u], accM[rt][u]);
+                    accN[rt][u] = mfma_f64(a[rt], bN[s][u], accN[rt][u]);
+                  }
+                }
+              load_b(q + DB, bM[s], bN[s]);  // clamped past k: harmless
+            }
+          }
+        }
+      }
+      // epilogue: register r of tile (rt, u) holds row rc + rt*16 + mfma_row(g, r)
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int u = 0; u < TW; ++u) {
+          const int c = (wave + WAVES * u) * 16 + r16;
+          if (cok[u]) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int lr = rt * 16 + mfma_row(g, r), row = rc + lr;
+              if (row < r1) {
+                double xt;
+                if (row < k) {
+                  xt = *gld(X1n + row * k + c);
+                } else {
+                  const double x = Xs[lr * LDX + c];
+                  const double rr = residual(wv[rt][u][r], lv[rt][u][r], x, dv[u], has_lo);
+                  const double e = (rr - accM[rt][u][r]) * di[u];
+                  xt = (x + e) - accN[rt][u][r];
+                  esq[u] = __builtin_fma(e, e, esq[u]);
+                }
+                *gst(P.xn + (int64_t)row * k + c) = xt;
+                xsq[u] = __builtin_fma(xt, xt, xsq[u]);
+              }
+            }
+          }
+        }
+    }
+    // block partials of sum x~^2 and sum e^2 per column (this wavefront's)
+    const int stride = 5 * k;
+#pragma unroll
+    for (int u = 0; u < TW; ++u) {
+      double a = xsq[u], b = esq[u];
+      a += __shfl_xor(a, 16);
+      a += __shfl_xor(a, 32);
+      b += __shfl_xor(b, 16);
+      b += __shfl_xor(b, 32);
+      const int c = (wave + WAVES * u) * 16 + r16;
+      if (g == 0 && c < k) {
+        *gst(P.part + (int64_t)item.blk * stride + 2 * k + c) = a;
+        *gst(P.part + (int64_t)item.blk * stride + 3 * k + c) = b;
+      }
+    }
+  }
+}
+
 // The same pass for k <= 32 (CT <= 2), for long problems: the block's X rows
 // come in 64-row tiles read with coalesced 16-byte loads (one tile ahead, in
 // registers) into LDS, where the wavefronts take both the MFMA A operand
@@ -1213,8 +1383,13 @@ hipError_t launch_update(const Prob* probs, const RowItem* items, int nitems, in
     hipLaunchKernelGGL((update_kernel<CTV>), dim3(nitems), dim3(256), 0, st, probs, items, \
                        nitems);                                                         \
     break;
+#define RFK_WIDE(CTV)                                                                        \
+  case CTV:                                                                                  \
+    hipLaunchKernelGGL((update_wide_kernel<CTV>), dim3(nitems), dim3(256), 0, st, probs, items, \
+                       nitems);                                                              \
+    break;
   switch (ct) {
-    RFK_CASE(1) RFK_CASE(2) RFK_CASE(3) RFK_CASE(4) RFK_CASE(5) RFK_CASE(6) RFK_CASE(7) RFK_CASE(8)
+    RFK_CASE(1) RFK_CASE(2) RFK_CASE(3) RFK_CASE(4) RFK_WIDE(5) RFK_WIDE(6) RFK_WIDE(7) RFK_WIDE(8)
     default:
       return hipErrorInvalidValue;
   }
