@@ -251,15 +251,22 @@ __global__ __launch_bounds__(256) void crt_xres_kernel(const Prob* __restrict__ 
     const int64_t cj = u >> 1;
     const int c = (int)(cj / kpad);
     const int j = (int)(cj - (int64_t)c * kpad);
-    const int e = j < k ? scale_exp(__longlong_as_double((long long)mx[j])) : 0;
+    // the column maximum and the 8 entries are requested together (indices
+    // clamped into X, entries past it masked to zero afterwards)
+    const bool jok = j < k;
+    const int jc = jok ? j : k - 1;
+    const int r0 = c * 32 + h * 16 + q * 8;
+    const unsigned long long mxj = *gld(mx + jc);
+    double xv[8];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) xv[b] = *gld(P.x + (int64_t)min(r0 + b, n - 1) * P.ldx + jc);
+    const int e = jok ? scale_exp(__longlong_as_double((long long)mxj)) : 0;
     if (c == 0 && h == 0 && q == 0) P.xexp[j] = e;
     const int sh = ca.bx - e;
-    const int r0 = c * 32 + h * 16 + q * 8;
     double vh[8], vl[8];
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-      const double v = (j < k && r0 + b < n) ? __builtin_rint(ldexp(*gld(P.x + (int64_t)(r0 + b) * P.ldx + j), sh))
-                                             : 0.0;
+      const double v = (jok && r0 + b < n) ? __builtin_rint(ldexp(xv[b], sh)) : 0.0;
       vh[b] = __builtin_rint(v * 0x1p-28);
       vl[b] = __builtin_fma(-vh[b], 0x1p28, v);
     }
@@ -440,7 +447,8 @@ __global__ __launch_bounds__(512) void crt_recon_kernel(const Prob* __restrict__
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int j = 4 * quad + e;
-    sbase[e] = (trow < tr && j < k) ? P.xexp[j] - ca.ba - ca.bx : 0;
+    const int xe = *gld(P.xexp + min(j, k - 1));  // requested together
+    sbase[e] = (trow < tr && j < k) ? xe - ca.ba - ca.bx : 0;
   }
   double sxw[4] = {0.0, 0.0, 0.0, 0.0}, sxx[4] = {0.0, 0.0, 0.0, 0.0};
   for (int i = r0 + trow; i < r1 && trow < tr; i += tr) {
@@ -451,6 +459,10 @@ __global__ __launch_bounds__(512) void crt_recon_kernel(const Prob* __restrict__
                                                      (int64_t)i * kpad + 4 * quad));
     const int ea = *gld(P.aexp + i);
     const double dii = *gld(ca.adiag + i);
+    // the row's X entries with its residue words (columns past k clamped)
+    double xr[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) xr[e] = *gld(P.x + (int64_t)i * P.ldx + min(4 * quad + e, k - 1));
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int j = 4 * quad + e;
@@ -482,7 +494,7 @@ __global__ __launch_bounds__(512) void crt_recon_kernel(const Prob* __restrict__
       h = ldexp(h, sc);
       l = ldexp(l, sc);
       // + a_ii x_ij: (h, l) + (p, pe), both parts' errors kept
-      const double xv = *gld(P.x + (int64_t)i * P.ldx + j);
+      const double xv = xr[e];
       double p, pe, s1, e1, s2, e2, wh, wl;
       two_prod(dii, xv, p, pe);
       two_sum(h, p, s1, e1);
