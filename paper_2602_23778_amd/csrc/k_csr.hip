@@ -84,15 +84,37 @@ __global__ __launch_bounds__(NT) void spmm_vec_kernel(const Prob* __restrict__ p
     const RowItem item = items[it];
     const int r0 = item.blk * chunk_rows, r1 = min(n, r0 + chunk_rows);
     __syncthreads();  // the previous chunk's LDS copies are no longer read
-    for (int i = tid; i <= r1 - r0; i += NT) srp[i] = *gld(rp + r0 + i);
+    // the copies into LDS request all their entries before storing any
+    // (indices clamped into the chunk): a loop of load-then-store would wait
+    // one round trip per pass
+    {
+      constexpr int RU = (SPMM_ROWS + NT) / NT;  // passes over rows 0..chunk
+      int v[RU];
+#pragma unroll
+      for (int u = 0; u < RU; ++u) v[u] = *gld(rp + r0 + min(tid + u * NT, r1 - r0));
+#pragma unroll
+      for (int u = 0; u < RU; ++u)
+        if (tid + u * NT <= r1 - r0) srp[tid + u * NT] = v[u];
+    }
     __syncthreads();
     const int E0 = srp[0], nz = srp[r1 - r0] - E0;
     const bool staged = nz <= NZL;
-    if (staged) {
-      for (int i = tid; i < nz; i += NT) {
-        sci[i] = *gld(ci + E0 + i);
-        sav[i] = *gld(av + E0 + i);
+    if (staged && nz > 0) {
+      constexpr int ZU = NZL / NT;
+      int cv[ZU];
+      double avv[ZU];
+#pragma unroll
+      for (int u = 0; u < ZU; ++u) {
+        const int i = min(tid + u * NT, nz - 1);
+        cv[u] = *gld(ci + E0 + i);
+        avv[u] = *gld(av + E0 + i);
       }
+#pragma unroll
+      for (int u = 0; u < ZU; ++u)
+        if (tid + u * NT < nz) {
+          sci[tid + u * NT] = cv[u];
+          sav[tid + u * NT] = avv[u];
+        }
     }
     __syncthreads();
     for (int rb = r0; rb < r1; rb += RPB) {
