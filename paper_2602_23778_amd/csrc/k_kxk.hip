@@ -392,10 +392,15 @@ __device__ __forceinline__ void ks_mm(int k, FA a, FB b, v4d (&res)[KS_SLOTS]) {
         double av[QC], bv[QC];
 #pragma unroll
         for (int q = 0; q < QC; ++q) {
+          // unconditional reads at clamped indices, masked afterwards: a
+          // guarded read (some operands are in global memory) would wait
+          // for each before the next
           const int l = 4 * (q0 + q) + g;
           const bool lok = q0 + q < kq && l < k;
-          av[q] = (iok && lok) ? a(i, l) : 0.0;
-          bv[q] = (jok && lok) ? b(l, j) : 0.0;
+          const int lc = min(l, k - 1);
+          const double ta = a(min(i, k - 1), lc), tb = b(lc, min(j, k - 1));
+          av[q] = (iok && lok) ? ta : 0.0;
+          bv[q] = (jok && lok) ? tb : 0.0;
         }
 #pragma unroll
         for (int q = 0; q < QC; q += 2) {
@@ -475,10 +480,11 @@ __global__ __launch_bounds__(KS_NT) void kxk_small_kernel(const Prob* __restrict
       double xv[KS_EPT], zv[KS_EPT];
 #pragma unroll
       for (int q = 0; q < KS_EPT; ++q) {
-        const int e = tid + q * KS_NT;
-        const int i = e / k, j = e - i * k;
-        xv[q] = e < kk2 ? X[(int64_t)i * ldx + j] : 0.0;
-        zv[q] = e < kk2 ? Zg[e] : 0.0;
+        const int e = tid + q * KS_NT, ec = min(e, kk2 - 1);
+        const int i = ec / k, j = ec - i * k;
+        const double tx = *gld(X + (int64_t)i * ldx + j), tz = *gld(Zg + ec);
+        xv[q] = e < kk2 ? tx : 0.0;
+        zv[q] = e < kk2 ? tz : 0.0;
       }
 #pragma unroll
       for (int q = 0; q < KS_EPT; ++q) {
@@ -604,8 +610,9 @@ __global__ __launch_bounds__(KS_NT) void kxk_small_kernel(const Prob* __restrict
       double cv[KS_EPT];
 #pragma unroll
       for (int q = 0; q < KS_EPT; ++q) {
-        const int e = tid + q * KS_NT;
-        cv[q] = e < kk2 ? (PT[e] + P2[e]) - R1[e] : 0.0;
+        const int e = tid + q * KS_NT, ec = min(e, kk2 - 1);
+        const double t = (*gld(PT + ec) + *gld(P2 + ec)) - *gld(R1 + ec);
+        cv[q] = e < kk2 ? t : 0.0;
       }
 #pragma unroll
       for (int q = 0; q < KS_EPT; ++q) {
@@ -628,13 +635,20 @@ __global__ __launch_bounds__(KS_NT) void kxk_small_kernel(const Prob* __restrict
     // E11 (correction step of Algorithm 4) -> B2
     double e1sq = 0.0;
     {
-      double pv[KS_EPT], gv[KS_EPT];
+      double pv[KS_EPT], gv[KS_EPT], di[KS_EPT], dj[KS_EPT], ai[KS_EPT];
       const double delta = P.delta;
+      const bool rr_top = ctrl->rr_top != 0;
+      // every operand of the sweep requested together (indices clamped)
 #pragma unroll
       for (int q = 0; q < KS_EPT; ++q) {
-        const int e = tid + q * KS_NT;
-        pv[q] = e < kk2 ? PT[e] + P2[e] : 0.0;
-        gv[q] = (e < kk2 && !P.beta_zero) ? GT[e] + G2[e] : 0.0;
+        const int e = tid + q * KS_NT, ec = min(e, kk2 - 1);
+        const int i = ec / k, j = ec - i * k;
+        const double tp = *gld(PT + ec) + *gld(P2 + ec), tg = *gld(GT + ec) + *gld(G2 + ec);
+        pv[q] = e < kk2 ? tp : 0.0;
+        gv[q] = (e < kk2 && !P.beta_zero) ? tg : 0.0;
+        di[q] = *gld(d + i);
+        dj[q] = *gld(d + j);
+        ai[q] = *gld(alpha + i);
       }
 #pragma unroll
       for (int q = 0; q < KS_EPT; ++q) {
@@ -642,14 +656,14 @@ __global__ __launch_bounds__(KS_NT) void kxk_small_kernel(const Prob* __restrict
         if (e < kk2) {
           const int i = e / k, j = e - i * k;
           double v;
-          if (ctrl->rr_top)
+          if (rr_top)
             v = 0.0;  // X is a Rayleigh-Ritz basis (Sec. 3.4, clustered eigenvalues)
           else if (i == j)
-            v = (1.0 - alpha[i]) * 0.5;
-          else if (fabs(d[j] - d[i]) <= delta)
+            v = (1.0 - ai[q]) * 0.5;
+          else if (fabs(dj[q] - di[q]) <= delta)
             v = P.beta_zero ? 0.0 : -gv[q] * 0.5;
           else
-            v = pv[q] / (d[j] - d[i]);
+            v = pv[q] / (dj[q] - di[q]);
           B2[e] = v;
           e1sq = __builtin_fma(v, v, e1sq);
         }
@@ -658,7 +672,7 @@ __global__ __launch_bounds__(KS_NT) void kxk_small_kernel(const Prob* __restrict
     e1sq = ks_sum(e1sq, red);
     // F = X1^T E11 + (X2^T R2 - X2^T X2 M) diag(1/(d - mu)) - E11 -> B3 (replacing M)
     ks_zero(res);
-    ks_mm(k, [&](int i, int l) { return G2[i * k + l]; }, [&](int l, int j) { return B3[l * k + j]; },
+    ks_mm(k, [&](int i, int l) { return *gld(G2 + i * k + l); }, [&](int l, int j) { return B3[l * k + j]; },
           res);
     {
       const int lane = tid & 63, wave = tid >> 6, g = lane >> 4, r16 = lane & 15;
@@ -668,12 +682,16 @@ __global__ __launch_bounds__(KS_NT) void kxk_small_kernel(const Prob* __restrict
         const int t = wave + sl * KS_NW;
         if (t < nt * nt) {
           const int ti = t / nt, tj = t - ti * nt;
-          const int j = tj * 16 + r16;
+          const int j = tj * 16 + r16, jc = min(j, k - 1);
+          // P2 and dinv of the tile requested together (indices clamped)
+          double p2[4];
+          const double dv = *gld(dinv + jc);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) p2[r] = *gld(P2 + min(ti * 16 + mfma_row(g, r), k - 1) * k + jc);
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int row = ti * 16 + mfma_row(g, r);
-            if (row < k && j < k)
-              res[sl][r] = (P2[row * k + j] - res[sl][r]) * dinv[j] - B2[row * k + j];
+            if (row < k && j < k) res[sl][r] = (p2[r] - res[sl][r]) * dv - B2[row * k + j];
           }
         }
       }
