@@ -431,19 +431,18 @@ __global__ __launch_bounds__(1024) void gram_reduce_kernel(const Prob* __restric
 }
 
 // ---------------------------------------------------------------------------
-// pass 3: update of the bottom rows on the matrix cores.  Each wavefront owns
-// 16 rows; the B operand [M | N] (k x 2k) is staged in LDS (whole when
-// k <= 64, else in chunks of 32 rows) and shared by the block's four
-// wavefronts; A is the X row block.  The block writes per-column partials of
-// sum x~^2 and sum e^2; fin_stats finishes them.
+// pass 3: update of the bottom rows on the matrix cores (32 < k <= 64).
+// Each wavefront owns 16 rows; the B operand [M | N] (k x 2k) is staged
+// whole in LDS and shared by the block's four wavefronts; A is the X row
+// block.  The epilogue's X, W and W_lo are requested with the A operand,
+// before the products.  The block writes per-column partials of sum x~^2
+// and sum e^2; fin_stats finishes them.  (Past k = 64: update_wide_kernel.)
 // ---------------------------------------------------------------------------
 template <int CT>
 __global__ __launch_bounds__(256) void update_kernel(const Prob* __restrict__ probs,
                                                     const RowItem* __restrict__ items, int nitems) {
-  constexpr int NT = 256, WAVES = 4, KCH = CT <= 4 ? 64 : 32, BW = 2 * CT * 16, LDC = BW + 2;
-  // k <= 64: the epilogue's X and W values are loaded before the products
-  constexpr bool PRE = CT <= 4;
-  constexpr int PC = PRE ? CT : 1;
+  static_assert(CT <= 4, "k <= 64");
+  constexpr int NT = 256, WAVES = 4, KCH = 64, BW = 2 * CT * 16, LDC = BW + 2;
   __shared__ double Cs[KCH * LDC];
   __shared__ double colred[2][WAVES][CT * 16];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -471,9 +470,9 @@ __global__ __launch_bounds__(256) void update_kernel(const Prob* __restrict__ pr
       esq[t] = 0.0;
     }
     const double* wlb = has_lo ? P.wlo : P.w;  // a readable base either way
-    // stage rows [kc0, kc0 + KCH) of [M | N] (columns padded to 16 CT)
-    // (every thread issues sixteen loads before their LDS stores)
-    auto stage = [&](int kc0) {
+    // stage [M | N] (columns padded to 16 CT), sixteen loads per thread
+    // issued before their LDS stores
+    {
       constexpr int PER = (KCH * BW + NT - 1) / NT, BAT = PER < 16 ? PER : 16;
 #pragma unroll 1
       for (int u0 = 0; u0 < PER; u0 += BAT) {
@@ -483,11 +482,10 @@ __global__ __launch_bounds__(256) void update_kernel(const Prob* __restrict__ pr
           const int e = tid + (u0 + u) * NT;
           const int rr = e / BW, cc = e - rr * BW;
           const int half = cc / (CT * 16), cj = cc - half * (CT * 16);
-          const int kr = kc0 + rr;
           // rows past k meet zero A values and columns past k are not
           // written, so those entries need only be finite: they repeat row
           // and column 0 (an unmasked load does not wait on the one before)
-          v[u] = *gld(Cm + (kr < k ? kr : 0) * k2 + half * k + (cj < k ? cj : 0));
+          v[u] = *gld(Cm + (rr < k ? rr : 0) * k2 + half * k + (cj < k ? cj : 0));
         }
 #pragma unroll
         for (int u = 0; u < BAT; ++u) {
@@ -495,12 +493,8 @@ __global__ __launch_bounds__(256) void update_kernel(const Prob* __restrict__ pr
           if (e < KCH * BW) Cs[(e / BW) * LDC + e % BW] = v[u];
         }
       }
-    };
-    const bool one_stage = k <= KCH;
-    if (one_stage) {
-      stage(0);
-      __syncthreads();
     }
+    __syncthreads();
     for (int rc = r0; rc < r1; rc += WAVES * 16) {
       v4d accM[CT], accN[CT];
 #pragma unroll
@@ -511,101 +505,59 @@ __global__ __launch_bounds__(256) void update_kernel(const Prob* __restrict__ pr
       const int arow = rc + wave * 16 + r16;
       const bool arok = arow < r1;
       const double* xr = X + (int64_t)(arok ? arow : r0) * ldx;
-      // the A operand of one K chunk (all of K when k <= 64), loaded at once
+      // the A operand (all of K), then the epilogue's X, W and W_lo
       constexpr int AQ = KCH / 4;
       double a_ch[AQ];
-      auto load_a = [&](int kc0) {
 #pragma unroll
-        for (int q = 0; q < AQ; ++q) {
-          const int kk = kc0 + 4 * q + g;
-          a_ch[q] = ld_or0(arok && kk < k, xr, kk);
+      for (int q = 0; q < AQ; ++q) {
+        const int kk = 4 * q + g;
+        a_ch[q] = ld_or0(arok && kk < k, xr, kk);
+      }
+      double ex[CT][4], ew[CT][4], el[CT][4];
+#pragma unroll
+      for (int t = 0; t < CT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = rc + wave * 16 + mfma_row(g, r);
+          const bool ok = cok[t] && row < r1 && row >= k;
+          const int64_t o = (int64_t)row * k + t * 16 + r16;
+          ex[t][r] = ld_or0(ok, X, (int64_t)row * ldx + t * 16 + r16);
+          ew[t][r] = ld_or0(ok, P.w, o);
+          el[t][r] = ld_or0(ok && has_lo, wlb, o);
         }
-      };
-      load_a(0);
-      double ex[PC][4], ew[PC][4], el[PC][4];
-      if (PRE) {
+      for (int kc = 0; kc < k; kc += 16) {
 #pragma unroll
-        for (int t = 0; t < PC; ++t)
+        for (int s = 0; s < 4; ++s) {
+          const double av = a_ch[kc / 4 + s];
+          const double* brow = Cs + (kc + 4 * s + g) * LDC + r16;
+#pragma unroll
+          for (int t = 0; t < CT; ++t) {
+            accM[t] = mfma_f64(av, brow[t * 16], accM[t]);
+            accN[t] = mfma_f64(av, brow[CT * 16 + t * 16], accN[t]);
+          }
+        }
+      }
+      // epilogue: register r holds row rc + wave*16 + mfma_row(g, r), column t*16 + r16
+#pragma unroll
+      for (int t = 0; t < CT; ++t) {
+        const int c = t * 16 + r16;
+        if (cok[t]) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int row = rc + wave * 16 + mfma_row(g, r);
-            const bool ok = cok[t] && row < r1 && row >= k;
-            const int64_t o = (int64_t)row * k + t * 16 + r16;
-            ex[t][r] = ld_or0(ok, X, (int64_t)row * ldx + t * 16 + r16);
-            ew[t][r] = ld_or0(ok, P.w, o);
-            el[t][r] = ld_or0(ok && has_lo, wlb, o);
-          }
-      }
-      for (int kc0 = 0; kc0 < k; kc0 += KCH) {
-        if (!one_stage) {
-          if (kc0 > 0) load_a(kc0);
-          __syncthreads();
-          stage(kc0);
-          __syncthreads();
-        }
-        const int kend = min(k, kc0 + KCH);
-        for (int kc = kc0; kc < kend; kc += 16) {
-#pragma unroll
-          for (int s = 0; s < 4; ++s) {
-            const double av = a_ch[(kc - kc0) / 4 + s];
-            const double* brow = Cs + (kc - kc0 + 4 * s + g) * LDC + r16;
-#pragma unroll
-            for (int t = 0; t < CT; ++t) {
-              accM[t] = mfma_f64(av, brow[t * 16], accM[t]);
-              accN[t] = mfma_f64(av, brow[CT * 16 + t * 16], accN[t]);
-            }
-          }
-        }
-      }
-      // epilogue: register r holds row rc + wave*16 + mfma_row(g, r), column
-      // t*16 + r16.  Past k = 64, X, W (and W_lo) of EG column tiles at a
-      // time are requested together before any of them is used.
-      constexpr int EG = PRE ? CT : 4;
-#pragma unroll
-      for (int t0 = 0; t0 < CT; t0 += EG) {
-        double gx[EG][4], gw[EG][4], gl[EG][4];
-#pragma unroll
-        for (int u = 0; u < EG; ++u)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int t = t0 + u < CT ? t0 + u : CT - 1;
-            if (PRE) {
-              gx[u][r] = ex[t < PC ? t : 0][r];
-              gw[u][r] = ew[t < PC ? t : 0][r];
-              gl[u][r] = el[t < PC ? t : 0][r];
-            } else {
-              const int row = rc + wave * 16 + mfma_row(g, r);
-              const int c = t * 16 + r16;
-              const bool ok = t0 + u < CT && cok[t] && row < r1 && row >= k;
-              const int64_t o = (int64_t)row * k + c;
-              gx[u][r] = ld_or0(ok, X, (int64_t)row * ldx + c);
-              gw[u][r] = ld_or0(ok, P.w, o);
-              gl[u][r] = ld_or0(ok && has_lo, wlb, o);
-            }
-          }
-#pragma unroll
-        for (int u = 0; u < EG; ++u) {
-          const int t = t0 + u;
-          if (t >= CT) break;
-          const int c = t * 16 + r16;
-          if (cok[t]) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int row = rc + wave * 16 + mfma_row(g, r);
-              if (row < r1) {
-                double xt;
-                if (row < k) {
-                  xt = *gld(X1n + row * k + c);
-                } else {
-                  const double x = gx[u][r];
-                  const double rr = residual(gw[u][r], gl[u][r], x, dv[t], has_lo);
-                  const double e = (rr - accM[t][r]) * di[t];
-                  xt = (x + e) - accN[t][r];
-                  esq[t] = __builtin_fma(e, e, esq[t]);
-                }
-                *gst(P.xn + (int64_t)row * k + c) = xt;
-                xsq[t] = __builtin_fma(xt, xt, xsq[t]);
+            if (row < r1) {
+              double xt;
+              if (row < k) {
+                xt = *gld(X1n + row * k + c);
+              } else {
+                const double x = ex[t][r];
+                const double rr = residual(ew[t][r], el[t][r], x, dv[t], has_lo);
+                const double e = (rr - accM[t][r]) * di[t];
+                xt = (x + e) - accN[t][r];
+                esq[t] = __builtin_fma(e, e, esq[t]);
               }
+              *gst(P.xn + (int64_t)row * k + c) = xt;
+              xsq[t] = __builtin_fma(xt, xt, xsq[t]);
             }
           }
         }
@@ -1389,7 +1341,7 @@ hipError_t launch_update(const Prob* probs, const RowItem* items, int nitems, in
                        nitems);                                                              \
     break;
   switch (ct) {
-    RFK_CASE(1) RFK_CASE(2) RFK_CASE(3) RFK_CASE(4) RFK_WIDE(5) RFK_WIDE(6) RFK_WIDE(7) RFK_WIDE(8)
+    RFK_CASE(3) RFK_CASE(4) RFK_WIDE(5) RFK_WIDE(6) RFK_WIDE(7) RFK_WIDE(8)
     default:
       return hipErrorInvalidValue;
   }
