@@ -190,13 +190,19 @@ __global__ __launch_bounds__(256) void split_xslice_kernel(const Prob* __restric
     const int64_t cj = u >> 1;
     const int c = (int)(cj / kpad);
     const int j = (int)(cj - (int64_t)c * kpad);
-    const int e = j < k ? scale_exponent(__longlong_as_double((long long)mx[j])) : 0;
-    if (c == 0 && h == 0) P.xexp[j] = e;
+    // the column maximum and the 16 entries are requested together (indices
+    // clamped into X, entries past it masked to zero afterwards)
+    const bool jok = j < k;
+    const int jc = jok ? j : k - 1;
     const int r0 = c * 32 + h * 16;
+    const unsigned long long mxj = *gld(mx + jc);
     double v[16];
 #pragma unroll
-    for (int b = 0; b < 16; ++b)
-      v[b] = (j < k && r0 + b < n) ? *gld(P.x + (int64_t)(r0 + b) * P.ldx + j) : 0.0;
+    for (int b = 0; b < 16; ++b) v[b] = *gld(P.x + (int64_t)min(r0 + b, n - 1) * P.ldx + jc);
+#pragma unroll
+    for (int b = 0; b < 16; ++b) v[b] = (jok && r0 + b < n) ? v[b] : 0.0;
+    const int e = jok ? scale_exponent(__longlong_as_double((long long)mxj)) : 0;
+    if (c == 0 && h == 0) P.xexp[j] = e;
     u4v out[S];
     digits16<S>(v, e, out);
     u4v* dst = reinterpret_cast<u4v*>(P.xsl + u * 16 * S);
