@@ -294,9 +294,10 @@ int install_gemm(Plan& pl, const std::vector<refine_matrix>& As, int cfg, int ks
 
 
 // Picks the product's launch configuration: REFINE_GEMM="cfg,ks" forces one;
-// batches use a fixed configuration; a single problem times every
-// configuration and K split on its own shape (a few milliseconds, once per
-// shape and process) and keeps the fastest.
+// otherwise every configuration is timed (with each K split for a single
+// problem, K split 1 for a batch) on the plan's own shapes, a few
+// milliseconds once per shape and process, and the fastest is kept (and
+// stored in the tuning cache when one is set).
 int choose_gemm(Plan& pl, const std::vector<refine_matrix>& As, bool single,
                 const std::vector<Shape>& shapes) {
   if (const char* env = getenv("REFINE_GEMM")) {
