@@ -1166,13 +1166,102 @@ __global__ __launch_bounds__(512) void pp_n_kernel(const Prob* __restrict__ prob
   }
 }
 
+// Statistics of the fused update (one problem through the panel pipeline,
+// k > 64), one workgroup per 16-row panel after pp_n (which completes N; on a
+// step that took the one-workgroup fallback, that solver wrote M and N).
+// With C = M Delta + N and a_j the column j of I - C, the bottom rows update
+// as X~2 = X2 + R2 Delta - X2 C, and the column norms of the step are
+// quadratic forms in k x k quantities (fin_post_kernel):
+//   ||x~_j||^2  = ||x~1_j||^2 + a_j^T G2 a_j + 2 Delta_j a_j^T p_j + Delta_j^2 s_j,
+//   ||e21_j||^2 = Delta_j^2 (s_j - 2 m_j^T p_j + m_j^T G2 m_j),
+// with G2 = X2^T X2 and p_j, m_j the columns j of X2^T R2 and M.  This
+// launch writes C's panel rows (the update's right operand) and, per column,
+// the panel rows' parts of a_j^T G2 a_j, m_j^T G2 m_j, a_j^T p_j, m_j^T p_j
+// (using (G2 a_j)_i = G2_ij - (G2 C)_ij), ||x~1_j||^2 and ||r1_j||^2.
+template <int KQ, bool FULL>
+__global__ __launch_bounds__(512) void pp_q_kernel(const Prob* __restrict__ probs) {
+  __shared__ double As[16 * PP_LDA];
+  const Prob& P = probs[0];
+  if (P.ctrl->stopped) return;
+  const int k = P.k, kk2 = k * k, k2 = 2 * k, pi = blockIdx.x, tj = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, g = lane >> 4, r16 = lane & 15;
+  const double* G2 = P.kk + KK_G2 * kk2;
+  const double* P2 = P.kk + KK_P2 * kk2;
+  const double* Cm = P.kk + KK_CM * kk2;
+  const double* X1n = P.kk + KK_X1N * kk2;
+  const double* R1 = P.kk + KK_R1 * kk2;
+  double* Cc = P.kk + KK_FC * kk2;
+  double* Qp = P.kk + KK_FQ * kk2;
+  const int j = tj * 16 + r16;
+  // one round: M and N as right operands, the lane's entries, G2's panel
+  double bM[KQ], bC[KQ];
+  pp_fetch<KQ, FULL>(k, [&](int l, int jj) { return *gld(Cm + (unsigned)(l * k2 + jj)); }, tj, bM);
+  pp_fetch<KQ, FULL>(k, [&](int l, int jj) { return *gld(Cm + (unsigned)(l * k2 + k + jj)); }, tj, bC);
+  const int jc = pp_cl<FULL>(j, k);
+  const double dj = *gld(P.vec + VEC_DINV * k + jc);
+  double vm[4], vn[4], vg[4], vp[4], vx[4], vr[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int ic = pp_cl<FULL>(pi * 16 + mfma_row(g, r), k);
+    vm[r] = *gld(Cm + (unsigned)(ic * k2 + jc));
+    vn[r] = *gld(Cm + (unsigned)(ic * k2 + k + jc));
+    vg[r] = *gld(G2 + (unsigned)(ic * k + jc));
+    vp[r] = *gld(P2 + (unsigned)(ic * k + jc));
+    vx[r] = *gld(X1n + (unsigned)(ic * k + jc));
+    vr[r] = *gld(R1 + (unsigned)(ic * k + jc));
+  }
+  pp_load_nb<KQ, FULL>(k, pi, As, [&](int i, int l) { return *gld(G2 + (unsigned)(i * k + l)); });
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < KQ; ++q) bC[q] = __builtin_fma(bM[q], dj, bC[q]);  // C = M Delta + N
+  const v4d gc = pp_mul<KQ, FULL>(k, As, bC);
+  const v4d gm = pp_mul<KQ, FULL>(k, As, bM);
+  double sA = 0.0, sM = 0.0, pA = 0.0, pM = 0.0, top = 0.0, r1 = 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = pi * 16 + mfma_row(g, r);
+    if (FULL || (i < k && j < k)) {
+      const double c = __builtin_fma(vm[r], dj, vn[r]);
+      const double a = (i == j ? 1.0 : 0.0) - c;
+      *gst(Cc + (unsigned)(i * k + j)) = c;
+      sA = __builtin_fma(a, vg[r] - gc[r], sA);
+      sM = __builtin_fma(vm[r], gm[r], sM);
+      pA = __builtin_fma(a, vp[r], pA);
+      pM = __builtin_fma(vm[r], vp[r], pM);
+      top = __builtin_fma(vx[r], vx[r], top);
+      r1 = __builtin_fma(vr[r], vr[r], r1);
+    }
+  }
+  // the panel's rows of column j sit in the four lane groups
+#pragma unroll
+  for (int o = 16; o <= 32; o *= 2) {
+    sA += __shfl_xor(sA, o);
+    sM += __shfl_xor(sM, o);
+    pA += __shfl_xor(pA, o);
+    pM += __shfl_xor(pM, o);
+    top += __shfl_xor(top, o);
+    r1 += __shfl_xor(r1, o);
+  }
+  if (g == 0 && j < k) {
+    double* q = Qp + (unsigned)(pi * 6 * k + j);
+    *gst(q) = sA;
+    *gst(q + k) = sM;
+    *gst(q + 2 * k) = pA;
+    *gst(q + 3 * k) = pM;
+    *gst(q + 4 * k) = top;
+    *gst(q + 5 * k) = r1;
+  }
+}
+
 // One problem: the panel pipeline with the one-workgroup solver as its
 // fallback (which runs only when the warm start is not close enough).
 // Batches: the one-workgroup solver per problem.
 // pipeline: one problem through the four-launch panel pipeline (the
 // one-workgroup kernel only as its fallback); otherwise the whole stage runs
-// in one workgroup per problem.
-hipError_t launch_kxk(const Prob* probs, int nprob, int kmax, bool pipeline, hipStream_t st) {
+// in one workgroup per problem.  fused (with pipeline): a fifth launch forms
+// the statistics of the fused update (pp_q_kernel).
+hipError_t launch_kxk(const Prob* probs, int nprob, int kmax, bool pipeline, bool fused,
+                      hipStream_t st) {
   if (nprob == 1 && pipeline) {
     const int np = (kmax + 15) / 16;
     const dim3 grid(np), block(64 * np);
@@ -1197,6 +1286,7 @@ hipError_t launch_kxk(const Prob* probs, int nprob, int kmax, bool pipeline, hip
       hipLaunchKernelGGL(kxk_kernel<false>, dim3(1), dim3(KXK_NT), 0, st, probs, 1, 1);
     RFK_PP(pp_f_kernel);
     RFK_PP(pp_n_kernel);
+    if (fused) RFK_PP(pp_q_kernel);
 #undef RFK_PP
     return hipGetLastError();
   }

@@ -602,7 +602,15 @@ __global__ __launch_bounds__(256) void update_kernel(const Prob* __restrict__ pr
 // of [M | N] through LDS in the form above.  Rows past the item's end and
 // columns past k are clamped (finite, never stored); the tile's columns from
 // k to the next multiple of 4 are zero, which bounds the contraction.
-template <int CT>
+//
+// FUSED (after pp_q_kernel and fin_post_kernel, which formed the statistics,
+// the scale factors and the decision from k x k quantities): an accepted
+// step writes the normalised iterate straight into X (each block reads its
+// rows before it overwrites them), from the one product X~2 = X2 + R2 Delta
+// - X2 C with C = M Delta + N, so each wavefront streams only its columns of
+// C and does half the products, with no partial sums and no normalisation
+// pass afterwards.
+template <int CT, bool FUSED>
 __global__ __launch_bounds__(256) void update_wide_kernel(const Prob* __restrict__ probs,
                                                          const RowItem* __restrict__ items, int nitems) {
   constexpr int WAVES = 4, TW = 2, ROWS = 64, LDX = KMAX + 4, DB = 4;
@@ -613,20 +621,21 @@ __global__ __launch_bounds__(256) void update_wide_kernel(const Prob* __restrict
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const RowItem item = items[it];
     const Prob& P = probs[item.prob];
-    if (P.ctrl->stopped) continue;
+    if (FUSED ? !P.ctrl->apply : P.ctrl->stopped) continue;
     const int n = P.n, k = P.k, kk2 = k * k, k2 = 2 * k;
     const int kq = (k + 3) / 4, kp = 4 * kq;
     const bool has_lo = P.wlo != nullptr;
     const double* __restrict__ X = P.x;
     const int64_t ldx = P.ldx;
     const double* __restrict__ Cm = P.kk + KK_CM * kk2;
+    const double* __restrict__ Cf = P.kk + KK_FC * kk2;
     const double* __restrict__ X1n = P.kk + KK_X1N * kk2;
     const double* wlb = has_lo ? P.wlo : P.w;  // a readable base either way
     const int r0 = item.blk * P.rbrows, r1 = min(n, r0 + P.rbrows);
     // this wavefront's columns
     int cc[TW];
     bool cok[TW];
-    double dv[TW], di[TW], xsq[TW], esq[TW];
+    double dv[TW], di[TW], sc[TW], xsq[TW], esq[TW];
 #pragma unroll
     for (int u = 0; u < TW; ++u) {
       const int c = (wave + WAVES * u) * 16 + r16;
@@ -634,6 +643,7 @@ __global__ __launch_bounds__(256) void update_wide_kernel(const Prob* __restrict
       cc[u] = cok[u] ? c : k - 1;
       dv[u] = *gld(P.vec + VEC_D * k + cc[u]);
       di[u] = *gld(P.vec + VEC_DINV * k + cc[u]);
+      sc[u] = FUSED ? *gld(P.vec + VEC_SCALE * k + cc[u]) : 1.0;
       xsq[u] = 0.0;
       esq[u] = 0.0;
     }
@@ -680,13 +690,18 @@ __global__ __launch_bounds__(256) void update_wide_kernel(const Prob* __restrict
           accN[rt][u] = v4d{0.0, 0.0, 0.0, 0.0};
         }
       // B fragments of K-step q: lane l holds [M | N](4q + l/16, column)
+      // (FUSED: C(4q + l/16, column) in the first array)
       double bM[DB][TW], bN[DB][TW];
       auto load_b = [&](int q, double(&m)[TW], double(&nn)[TW]) {
         const int kr = min(4 * q + g, k - 1);
 #pragma unroll
         for (int u = 0; u < TW; ++u) {
-          m[u] = *gld(Cm + (unsigned)(kr * k2 + cc[u]));
-          nn[u] = *gld(Cm + (unsigned)(kr * k2 + k + cc[u]));
+          if constexpr (FUSED) {
+            m[u] = *gld(Cf + (unsigned)(kr * k + cc[u]));
+          } else {
+            m[u] = *gld(Cm + (unsigned)(kr * k2 + cc[u]));
+            nn[u] = *gld(Cm + (unsigned)(kr * k2 + k + cc[u]));
+          }
         }
       };
 #pragma unroll
@@ -707,7 +722,7 @@ __global__ __launch_bounds__(256) void update_wide_kernel(const Prob* __restrict
                 for (int u = 0; u < TW; ++u) {
                   if (wave + WAVES * u < CT) {
                     accM[rt][u] = mfma_f64(a[rt], bM[s][u], accM[rt][u]);
-                    accN[rt][u] = mfma_f64(a[rt], bN[s][u], accN[rt][u]);
+                    if constexpr (!FUSED) accN[rt][u] = mfma_f64(a[rt], bN[s][u], accN[rt][u]);
                   }
                 }
               load_b(q + DB, bM[s], bN[s]);  // clamped past k: harmless
@@ -729,6 +744,10 @@ __global__ __launch_bounds__(256) void update_wide_kernel(const Prob* __restrict
                 double xt;
                 if (row < k) {
                   xt = *gld(X1n + row * k + c);
+                } else if constexpr (FUSED) {
+                  const double x = Xs[lr * LDX + c];
+                  const double rr = residual(wv[rt][u][r], lv[rt][u][r], x, dv[u], has_lo);
+                  xt = __builtin_fma(rr, di[u], x) - accM[rt][u][r];
                 } else {
                   const double x = Xs[lr * LDX + c];
                   const double rr = residual(wv[rt][u][r], lv[rt][u][r], x, dv[u], has_lo);
@@ -736,14 +755,19 @@ __global__ __launch_bounds__(256) void update_wide_kernel(const Prob* __restrict
                   xt = (x + e) - accN[rt][u][r];
                   esq[u] = __builtin_fma(e, e, esq[u]);
                 }
-                *gst(P.xn + (int64_t)row * k + c) = xt;
-                xsq[u] = __builtin_fma(xt, xt, xsq[u]);
+                if constexpr (FUSED) {
+                  *gst(P.x + (int64_t)row * ldx + c) = xt * sc[u];
+                } else {
+                  *gst(P.xn + (int64_t)row * k + c) = xt;
+                  xsq[u] = __builtin_fma(xt, xt, xsq[u]);
+                }
               }
             }
           }
         }
     }
     // block partials of sum x~^2 and sum e^2 per column (this wavefront's)
+    if constexpr (FUSED) continue;
     const int stride = 5 * k;
 #pragma unroll
     for (int u = 0; u < TW; ++u) {
@@ -1022,6 +1046,65 @@ __global__ __launch_bounds__(1024) void fin_stats_kernel(const Prob* __restrict_
   }
 }
 
+// The decision of a fused step from its column norms in LDS, colv0[j] =
+// ||x~_j||^2 and colv1[j] = ||e21_j||^2 (j < k): the normalisation factors,
+// ||E_L||_F, ||R||_F / ||A|| and the rules of fin_stats_kernel.  All threads
+// of the block call it; fin holds 2 (blockDim / 64) doubles of LDS.
+__device__ void fused_decide(const Prob& P, const double* colv0, const double* colv1, double* fin) {
+  const int NT = blockDim.x, NW = NT / 64, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int k = P.k;
+  Ctrl* C = P.ctrl;
+  const double* rsq = P.vec + VEC_RSQ * k;
+  double e2 = 0.0, r2 = 0.0;
+  int bad = 0;
+  for (int j = tid; j < k; j += NT) {
+    const double xs = colv0[j];
+    P.vec[VEC_SCALE * k + j] = P.normalize ? 1.0 / sqrt(xs) : 1.0;
+    if (!__builtin_isfinite(xs) || !(xs > 0.0)) bad = 1;
+    e2 += colv1[j];
+    r2 += *gld(rsq + j);
+  }
+  for (int o = 32; o >= 1; o /= 2) {
+    e2 += __shfl_xor(e2, o);
+    r2 += __shfl_xor(r2, o);
+  }
+  if (lane == 0) {
+    fin[wave] = e2;
+    fin[NW + wave] = r2;
+  }
+  bad = __syncthreads_or(bad);
+  if (tid == 0) {
+    double se = P.vec[VEC_E1SQ * k], sr = 0.0;
+    for (int w = 0; w < NW; ++w) {
+      se += fin[w];
+      sr += fin[NW + w];
+    }
+    const double corr = sqrt(se);
+    const double resid = sqrt(sr) / P.norm_a;
+    C->corr_fro = corr;
+    C->resid_rel = resid;
+    const bool finite = !bad && __builtin_isfinite(corr) && __builtin_isfinite(resid);
+    const int h = C->iters;
+    const bool grew = h >= 3 && corr > 10.0 * C->hist[(h - 3) & 3];
+    if (!finite) {
+      C->status = -6;
+      C->stopped = 1;
+    } else if (corr >= 1.0 || grew) {
+      C->status = -5;
+      C->stopped = 1;
+    } else {
+      C->apply = 1;
+      C->rr_top = 0;  // a Rayleigh-Ritz basis serves one step
+      C->hist[h & 3] = corr;
+      C->iters = h + 1;
+      if ((C->stop_mode == 1 && corr <= C->tol) || (C->stop_mode == 2 && resid <= C->tol)) {
+        C->converged = 1;
+        C->stopped = 1;
+      }
+    }
+  }
+}
+
 // Statistics, normalisation factors and the accept/reject decision before
 // the update, for k <= 32, one workgroup per problem.  The bottom rows update
 // as X~2 = X2 A + R2 Delta with A = I - N - M Delta and Delta =
@@ -1103,55 +1186,41 @@ __global__ __launch_bounds__(256) void fin_pre_kernel(const Prob* __restrict__ p
       }
     }
     __syncthreads();
-    double e2 = 0.0, r2 = 0.0;
-    int bad = 0;
-    for (int j = tid; j < k; j += NT) {
-      const double xs = colv[0][j];
-      P.vec[VEC_SCALE * k + j] = P.normalize ? 1.0 / sqrt(xs) : 1.0;
-      if (!__builtin_isfinite(xs) || !(xs > 0.0)) bad = 1;
-      e2 += colv[1][j];
-      r2 += *gld(rsq + j);
-    }
-    for (int o = 32; o >= 1; o /= 2) {
-      e2 += __shfl_xor(e2, o);
-      r2 += __shfl_xor(r2, o);
-    }
-    if (lane == 0) {
-      fin[0][wave] = e2;
-      fin[1][wave] = r2;
-    }
-    bad = __syncthreads_or(bad);
-    if (tid == 0) {
-      double se = P.vec[VEC_E1SQ * k], sr = 0.0;
-      for (int w = 0; w < NW; ++w) {
-        se += fin[0][w];
-        sr += fin[1][w];
-      }
-      const double corr = sqrt(se);
-      const double resid = sqrt(sr) / P.norm_a;
-      C->corr_fro = corr;
-      C->resid_rel = resid;
-      const bool finite = !bad && __builtin_isfinite(corr) && __builtin_isfinite(resid);
-      const int h = C->iters;
-      const bool grew = h >= 3 && corr > 10.0 * C->hist[(h - 3) & 3];
-      if (!finite) {
-        C->status = -6;
-        C->stopped = 1;
-      } else if (corr >= 1.0 || grew) {
-        C->status = -5;
-        C->stopped = 1;
-      } else {
-        C->apply = 1;
-        C->rr_top = 0;  // a Rayleigh-Ritz basis serves one step
-        C->hist[h & 3] = corr;
-        C->iters = h + 1;
-        if ((C->stop_mode == 1 && corr <= C->tol) || (C->stop_mode == 2 && resid <= C->tol)) {
-          C->converged = 1;
-          C->stopped = 1;
-        }
-      }
-    }
+    fused_decide(P, colv[0], colv[1], &fin[0][0]);
   }
+}
+
+// The same statistics for one problem past k = 64 (the fused wide update),
+// one workgroup after pp_q_kernel: per column j, the panels' parts of the
+// quadratic forms, ||x~1_j||^2 and ||r1_j||^2 summed in a fixed order, then
+// the norms of fin_pre_kernel and the decision.
+__global__ __launch_bounds__(1024) void fin_post_kernel(const Prob* __restrict__ probs) {
+  constexpr int NT = 1024, NW = NT / 64, TPC = 8;  // threads per column: one per panel
+  __shared__ double colv[2][KMAX];
+  __shared__ double fin[2 * NW];
+  const Prob& P = probs[0];
+  const int tid = threadIdx.x;
+  if (P.ctrl->stopped) return;  // set before this launch: the same in every thread
+  const int k = P.k, kk2 = k * k, np = (k + 15) / 16;
+  const double* Qp = P.kk + KK_FQ * kk2;
+  const int j = tid / TPC, part = tid % TPC;
+  const int jc = j < k ? j : k - 1;
+  double q[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) q[c] = ld_or0(part < np, Qp, (int64_t)(part * 6 + c) * k + jc);
+#pragma unroll
+  for (int o = 1; o < TPC; o *= 2)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) q[c] += __shfl_xor(q[c], o);
+  if (j < k && part == 0) {
+    const double sA = q[0], sM = q[1], pA = q[2], pM = q[3], top = q[4], r1 = q[5];
+    const double D = *gld(P.vec + VEC_DINV * k + j);
+    const double s2 = fmax(*gld(P.vec + VEC_RSQ * k + j) - r1, 0.0);
+    colv[0][j] = top + sA + 2.0 * D * pA + D * D * s2;
+    colv[1][j] = fmax(D * D * (s2 - 2.0 * pM + sM), 0.0);
+  }
+  __syncthreads();
+  fused_decide(P, colv[0], colv[1], fin);
 }
 
 // Rayleigh quotients, one workgroup per problem: sums the partials of
@@ -1313,11 +1382,13 @@ hipError_t launch_gram_reduce(const Prob* probs, const GramRedItem* items, int n
   return hipGetLastError();
 }
 
-// fused: k <= 32 only (fin_pre_kernel has run; X written in place).
+// fused: X written in place, normalised, after the statistics were formed
+// from k x k quantities: k <= 32 (fin_pre_kernel has run) or 64 < k <= 128
+// (one problem through the panel pipeline; pp_q_kernel and fin_post_kernel).
 hipError_t launch_update(const Prob* probs, const RowItem* items, int nitems, int kmax, bool fused,
                          hipStream_t st) {
   const int ct = (kmax + 15) / 16;
-  if (fused && ct > 2) return hipErrorInvalidValue;
+  if (fused && (ct == 3 || ct == 4)) return hipErrorInvalidValue;
   if (ct <= 2) {
     const dim3 grid(nitems), block(256);
     if (ct == 1 && fused)
@@ -1335,10 +1406,14 @@ hipError_t launch_update(const Prob* probs, const RowItem* items, int nitems, in
     hipLaunchKernelGGL((update_kernel<CTV>), dim3(nitems), dim3(256), 0, st, probs, items, \
                        nitems);                                                         \
     break;
-#define RFK_WIDE(CTV)                                                                        \
-  case CTV:                                                                                  \
-    hipLaunchKernelGGL((update_wide_kernel<CTV>), dim3(nitems), dim3(256), 0, st, probs, items, \
-                       nitems);                                                              \
+#define RFK_WIDE(CTV)                                                                           \
+  case CTV:                                                                                     \
+    if (fused)                                                                                  \
+      hipLaunchKernelGGL((update_wide_kernel<CTV, true>), dim3(nitems), dim3(256), 0, st, probs,  \
+                         items, nitems);                                                        \
+    else                                                                                        \
+      hipLaunchKernelGGL((update_wide_kernel<CTV, false>), dim3(nitems), dim3(256), 0, st, probs, \
+                         items, nitems);                                                        \
     break;
   switch (ct) {
     RFK_CASE(3) RFK_CASE(4) RFK_WIDE(5) RFK_WIDE(6) RFK_WIDE(7) RFK_WIDE(8)
@@ -1346,6 +1421,7 @@ hipError_t launch_update(const Prob* probs, const RowItem* items, int nitems, in
       return hipErrorInvalidValue;
   }
 #undef RFK_CASE
+#undef RFK_WIDE
   return hipGetLastError();
 }
 
@@ -1357,6 +1433,11 @@ hipError_t launch_wsum(const Prob* probs, int p, int64_t n, int k, hipStream_t s
 
 hipError_t launch_fin_d(const Prob* probs, int nprob, hipStream_t st) {
   hipLaunchKernelGGL(fin_d_kernel, dim3(nprob), dim3(1024), 0, st, probs, nprob);
+  return hipGetLastError();
+}
+
+hipError_t launch_fin_post(const Prob* probs, hipStream_t st) {
+  hipLaunchKernelGGL(fin_post_kernel, dim3(1), dim3(1024), 0, st, probs);
   return hipGetLastError();
 }
 

@@ -32,9 +32,10 @@ struct GramRedItem {
   int32_t prob, s0;
 };
 hipError_t launch_gram_reduce(const Prob*, const GramRedItem*, int, hipStream_t);
-hipError_t launch_kxk(const Prob*, int, int, bool, hipStream_t);
+hipError_t launch_kxk(const Prob*, int, int, bool, bool, hipStream_t);
 hipError_t launch_update(const Prob*, const RowItem*, int, int, bool, hipStream_t);
 hipError_t launch_fin_pre(const Prob*, int, hipStream_t);
+hipError_t launch_fin_post(const Prob*, hipStream_t);
 hipError_t launch_normalize(const Prob*, const RowItem*, int, hipStream_t);
 hipError_t launch_wsum(const Prob*, int, int64_t, int, hipStream_t);
 hipError_t launch_fin_d(const Prob*, int, hipStream_t);
@@ -80,6 +81,7 @@ struct Plan {
   int spmm_grid = 0;              // blocks of the CSR product (one Rayleigh partial each)
   bool kxk_pipeline = false;      // one problem: k x k stage by the panel pipeline
   bool fused = false;             // k <= 32: statistics before the update, X written in place
+  bool fused_wide = false;        // one problem, 64 < k <= 128, panel pipeline: the same
   GramRedItem* gred_items = nullptr;
   int n_gred = 0;
   int kmax = 0;
@@ -444,6 +446,10 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
 
   std::vector<RowItem> ri, gri;
   pl.fused = pl.kmax <= 32;
+  // one problem through the panel pipeline past k = 64: the statistics before
+  // the update as well (REFINE_FUSED_WIDE=0: update, statistics, normalisation)
+  pl.fused_wide = pl.kxk_pipeline && pl.kmax > 64;
+  if (const char* env = getenv("REFINE_FUSED_WIDE")) pl.fused_wide = pl.fused_wide && atoi(env) != 0;
   std::vector<GramRedItem> rr;
   for (int p = 0; p < np; ++p) {
     const refine_matrix& A = As[p];
@@ -600,7 +606,15 @@ hipError_t enqueue_step(Plan& pl, hipStream_t st) {
   if ((e = launch_fin_d(pl.dprob, np, st)) != hipSuccess) return e;
   if ((e = launch_gram(pl.dprob, pl.gram_items, pl.n_gram, pl.kmax, pl.split, st)) != hipSuccess) return e;
   if ((e = launch_gram_reduce(pl.dprob, pl.gred_items, pl.n_gred, st)) != hipSuccess) return e;
-  if ((e = launch_kxk(pl.dprob, np, pl.kmax, pl.kxk_pipeline, st)) != hipSuccess) return e;
+  if ((e = launch_kxk(pl.dprob, np, pl.kmax, pl.kxk_pipeline, pl.fused_wide, st)) != hipSuccess)
+    return e;
+  if (pl.fused_wide) {
+    // one problem past k = 64: the statistics from k x k quantities after the
+    // pipeline, then the update writes the normalised iterate in place
+    if ((e = launch_fin_post(pl.dprob, st)) != hipSuccess) return e;
+    if ((e = launch_update(pl.dprob, pl.row_items, pl.n_row, pl.kmax, true, st)) != hipSuccess) return e;
+    return hipSuccess;
+  }
   if (pl.fused) {
     // k <= 32: statistics and scale factors from k x k quantities, then the
     // update writes the normalised iterate in place
@@ -1569,7 +1583,7 @@ extern "C" int refine_step_static(const refine_matrix* A, int32_t k, const refin
   if (e == hipSuccess) e = launch_fin_d(dprob, 1, st);
   if (e == hipSuccess) e = launch_gram(dprob, gri, L.n_gram, k, false, st);
   if (e == hipSuccess) e = launch_gram_reduce(dprob, rr, L.n_gred, st);
-  if (e == hipSuccess) e = launch_kxk(dprob, 1, k, pipeline, st);
+  if (e == hipSuccess) e = launch_kxk(dprob, 1, k, pipeline, false, st);
   if (fused) {
     if (e == hipSuccess) e = launch_fin_pre(dprob, 1, st);
     if (e == hipSuccess) e = launch_update(dprob, ri, L.n_row, k, true, st);
