@@ -613,7 +613,7 @@ __global__ __launch_bounds__(256) void update_kernel(const Prob* __restrict__ pr
 template <int CT, bool FUSED>
 __global__ __launch_bounds__(256) void update_wide_kernel(const Prob* __restrict__ probs,
                                                          const RowItem* __restrict__ items, int nitems) {
-  constexpr int WAVES = 4, TW = 2, ROWS = 64, LDX = KMAX + 4, DB = 4;
+  constexpr int WAVES = 4, TW = 2, ROWS = 64, LDX = KMAX + 4, DB = FUSED ? 8 : 4;
   static_assert(CT > 4 && CT <= WAVES * TW, "64 < k <= 128");
   __shared__ double Xs[ROWS * LDX];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
