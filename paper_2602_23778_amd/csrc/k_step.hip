@@ -20,6 +20,12 @@
 //                      fin_stats forms the normalisation factors and the
 //                      statistics, and accepts or rejects the step.
 //   pass 4  (normalize) X = scaled update, only when the step was accepted.
+//
+// Fused order (k <= 32, and one problem past k = 64): the column norms of the
+// update and of E21 come from k x k quadratic forms after the k-by-k part
+// (fin_pre, or pp_q + fin_post), so the statistics and the decision come
+// first and pass 3 writes the normalised iterate into X itself; pass 4 and
+// the n x k copy of the update are not needed.
 #include "common.h"
 #include "dev_util.h"
 
