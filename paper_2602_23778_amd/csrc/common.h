@@ -101,9 +101,9 @@ enum {
   KK_CM = 5,    // [M | N], k x 2k (occupies 5 and 6)
   KK_X1N = 7,   // updated leading rows
   KK_S0 = 8,    // scratch for the k-by-k solver when it does not fit in LDS (8..11)
-  KK_FC = 9,    // fused update past k = 64: C = M Delta + N (in the slot of X^T R - R1,
+  KK_FC = 9,    // fused update after the panel pipeline: C = M Delta + N (in the slot of X^T R - R1,
                 //   which the product for M consumed)
-  KK_FQ = 10,   // fused update past k = 64: per-panel column parts of the statistics
+  KK_FQ = 10,   // fused update after the panel pipeline: per-panel column parts of the statistics
                 //   (in the slot of E11, which X1's update consumed)
   KK_Z = 12,    // Y1^{-1} of the previous step (warm start)
   KK_Q = 13,    // Y1 Z^T (panel pipeline)

@@ -1167,7 +1167,7 @@ __global__ __launch_bounds__(512) void pp_n_kernel(const Prob* __restrict__ prob
 }
 
 // Statistics of the fused update (one problem through the panel pipeline,
-// k > 64), one workgroup per 16-row panel after pp_n (which completes N; on a
+// k > 32), one workgroup per 16-row panel after pp_n (which completes N; on a
 // step that took the one-workgroup fallback, that solver wrote M and N).
 // With C = M Delta + N and a_j the column j of I - C, the bottom rows update
 // as X~2 = X2 + R2 Delta - X2 C, and the column norms of the step are

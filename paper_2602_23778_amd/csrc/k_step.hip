@@ -21,11 +21,11 @@
 //                      statistics, and accepts or rejects the step.
 //   pass 4  (normalize) X = scaled update, only when the step was accepted.
 //
-// Fused order (k <= 32, and one problem past k = 64): the column norms of the
-// update and of E21 come from k x k quadratic forms after the k-by-k part
-// (fin_pre, or pp_q + fin_post), so the statistics and the decision come
-// first and pass 3 writes the normalised iterate into X itself; pass 4 and
-// the n x k copy of the update are not needed.
+// Fused order (k <= 32, and one problem through the k-by-k panel pipeline):
+// the column norms of the update and of E21 come from k x k quadratic forms
+// after the k-by-k part (fin_pre, or pp_q + fin_post), so the statistics and
+// the decision come first and pass 3 writes the normalised iterate into X
+// itself; pass 4 and the n x k copy of the update are not needed.
 #include "common.h"
 #include "dev_util.h"
 
@@ -443,12 +443,15 @@ __global__ __launch_bounds__(1024) void gram_reduce_kernel(const Prob* __restric
 // block.  The epilogue's X, W and W_lo are requested with the A operand,
 // before the products.  The block writes per-column partials of sum x~^2
 // and sum e^2; fin_stats finishes them.  (Past k = 64: update_wide_kernel.)
+// FUSED (one problem through the panel pipeline, after pp_q_kernel and
+// fin_post_kernel): the B operand is C = M Delta + N alone, and an accepted
+// step writes the normalised iterate into X, as in update_wide_kernel.
 // ---------------------------------------------------------------------------
-template <int CT>
+template <int CT, bool FUSED>
 __global__ __launch_bounds__(256) void update_kernel(const Prob* __restrict__ probs,
                                                     const RowItem* __restrict__ items, int nitems) {
   static_assert(CT <= 4, "k <= 64");
-  constexpr int NT = 256, WAVES = 4, KCH = 64, BW = 2 * CT * 16, LDC = BW + 2;
+  constexpr int NT = 256, WAVES = 4, KCH = 64, BW = (FUSED ? 1 : 2) * CT * 16, LDC = BW + 2;
   __shared__ double Cs[KCH * LDC];
   __shared__ double colred[2][WAVES][CT * 16];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -456,15 +459,16 @@ __global__ __launch_bounds__(256) void update_kernel(const Prob* __restrict__ pr
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const RowItem item = items[it];
     const Prob& P = probs[item.prob];
-    if (P.ctrl->stopped) continue;
+    if (FUSED ? !P.ctrl->apply : P.ctrl->stopped) continue;
     const int n = P.n, k = P.k, kk2 = k * k, k2 = 2 * k;
     const bool has_lo = P.wlo != nullptr;
     const double* __restrict__ X = P.x;
     const int64_t ldx = P.ldx;
     const double* __restrict__ Cm = P.kk + KK_CM * kk2;
+    const double* __restrict__ Cf = P.kk + KK_FC * kk2;
     const double* __restrict__ X1n = P.kk + KK_X1N * kk2;
     const int r0 = item.blk * P.rbrows, r1 = min(n, r0 + P.rbrows);
-    double dv[CT], di[CT], xsq[CT], esq[CT];
+    double dv[CT], di[CT], sc[CT], xsq[CT], esq[CT];
     bool cok[CT];
 #pragma unroll
     for (int t = 0; t < CT; ++t) {
@@ -472,12 +476,13 @@ __global__ __launch_bounds__(256) void update_kernel(const Prob* __restrict__ pr
       cok[t] = c < k;
       dv[t] = ld_or0(cok[t], P.vec + VEC_D * k, c);
       di[t] = ld_or0(cok[t], P.vec + VEC_DINV * k, c);
+      sc[t] = FUSED ? ld_or0(cok[t], P.vec + VEC_SCALE * k, c) : 1.0;
       xsq[t] = 0.0;
       esq[t] = 0.0;
     }
     const double* wlb = has_lo ? P.wlo : P.w;  // a readable base either way
-    // stage [M | N] (columns padded to 16 CT), sixteen loads per thread
-    // issued before their LDS stores
+    // stage [M | N] (FUSED: C) (columns padded to 16 CT), sixteen loads per
+    // thread issued before their LDS stores
     {
       constexpr int PER = (KCH * BW + NT - 1) / NT, BAT = PER < 16 ? PER : 16;
 #pragma unroll 1
@@ -491,7 +496,10 @@ __global__ __launch_bounds__(256) void update_kernel(const Prob* __restrict__ pr
           // rows past k meet zero A values and columns past k are not
           // written, so those entries need only be finite: they repeat row
           // and column 0 (an unmasked load does not wait on the one before)
-          v[u] = *gld(Cm + (rr < k ? rr : 0) * k2 + half * k + (cj < k ? cj : 0));
+          if constexpr (FUSED)
+            v[u] = *gld(Cf + (rr < k ? rr : 0) * k + (cj < k ? cj : 0));
+          else
+            v[u] = *gld(Cm + (rr < k ? rr : 0) * k2 + half * k + (cj < k ? cj : 0));
         }
 #pragma unroll
         for (int u = 0; u < BAT; ++u) {
@@ -539,7 +547,7 @@ __global__ __launch_bounds__(256) void update_kernel(const Prob* __restrict__ pr
 #pragma unroll
           for (int t = 0; t < CT; ++t) {
             accM[t] = mfma_f64(av, brow[t * 16], accM[t]);
-            accN[t] = mfma_f64(av, brow[CT * 16 + t * 16], accN[t]);
+            if constexpr (!FUSED) accN[t] = mfma_f64(av, brow[CT * 16 + t * 16], accN[t]);
           }
         }
       }
@@ -555,6 +563,10 @@ __global__ __launch_bounds__(256) void update_kernel(const Prob* __restrict__ pr
               double xt;
               if (row < k) {
                 xt = *gld(X1n + row * k + c);
+              } else if constexpr (FUSED) {
+                const double x = ex[t][r];
+                const double rr = residual(ew[t][r], el[t][r], x, dv[t], has_lo);
+                xt = __builtin_fma(rr, di[t], x) - accM[t][r];
               } else {
                 const double x = ex[t][r];
                 const double rr = residual(ew[t][r], el[t][r], x, dv[t], has_lo);
@@ -562,14 +574,19 @@ __global__ __launch_bounds__(256) void update_kernel(const Prob* __restrict__ pr
                 xt = (x + e) - accN[t][r];
                 esq[t] = __builtin_fma(e, e, esq[t]);
               }
-              *gst(P.xn + (int64_t)row * k + c) = xt;
-              xsq[t] = __builtin_fma(xt, xt, xsq[t]);
+              if constexpr (FUSED) {
+                *gst(P.x + (int64_t)row * ldx + c) = xt * sc[t];
+              } else {
+                *gst(P.xn + (int64_t)row * k + c) = xt;
+                xsq[t] = __builtin_fma(xt, xt, xsq[t]);
+              }
             }
           }
         }
       }
     }
     // block partials of sum x~^2 and sum e^2 per column
+    if constexpr (FUSED) continue;
 #pragma unroll
     for (int t = 0; t < CT; ++t) {
       double a = xsq[t], b = esq[t];
@@ -1196,7 +1213,7 @@ __global__ __launch_bounds__(256) void fin_pre_kernel(const Prob* __restrict__ p
   }
 }
 
-// The same statistics for one problem past k = 64 (the fused wide update),
+// The same statistics for one problem through the panel pipeline (k > 32),
 // one workgroup after pp_q_kernel: per column j, the panels' parts of the
 // quadratic forms, ||x~1_j||^2 and ||r1_j||^2 summed in a fixed order, then
 // the norms of fin_pre_kernel and the decision.
@@ -1389,12 +1406,11 @@ hipError_t launch_gram_reduce(const Prob* probs, const GramRedItem* items, int n
 }
 
 // fused: X written in place, normalised, after the statistics were formed
-// from k x k quantities: k <= 32 (fin_pre_kernel has run) or 64 < k <= 128
-// (one problem through the panel pipeline; pp_q_kernel and fin_post_kernel).
+// from k x k quantities: k <= 32 (fin_pre_kernel has run) or k > 32 (one
+// problem through the panel pipeline; pp_q_kernel and fin_post_kernel).
 hipError_t launch_update(const Prob* probs, const RowItem* items, int nitems, int kmax, bool fused,
                          hipStream_t st) {
   const int ct = (kmax + 15) / 16;
-  if (fused && (ct == 3 || ct == 4)) return hipErrorInvalidValue;
   if (ct <= 2) {
     const dim3 grid(nitems), block(256);
     if (ct == 1 && fused)
@@ -1407,10 +1423,14 @@ hipError_t launch_update(const Prob* probs, const RowItem* items, int nitems, in
       hipLaunchKernelGGL((update_small_kernel<2, false>), grid, block, 0, st, probs, items, nitems);
     return hipGetLastError();
   }
-#define RFK_CASE(CTV)                                                                   \
-  case CTV:                                                                             \
-    hipLaunchKernelGGL((update_kernel<CTV>), dim3(nitems), dim3(256), 0, st, probs, items, \
-                       nitems);                                                         \
+#define RFK_CASE(CTV)                                                                          \
+  case CTV:                                                                                    \
+    if (fused)                                                                                 \
+      hipLaunchKernelGGL((update_kernel<CTV, true>), dim3(nitems), dim3(256), 0, st, probs, items, \
+                         nitems);                                                              \
+    else                                                                                       \
+      hipLaunchKernelGGL((update_kernel<CTV, false>), dim3(nitems), dim3(256), 0, st, probs,     \
+                         items, nitems);                                                       \
     break;
 #define RFK_WIDE(CTV)                                                                           \
   case CTV:                                                                                     \

@@ -81,7 +81,7 @@ struct Plan {
   int spmm_grid = 0;              // blocks of the CSR product (one Rayleigh partial each)
   bool kxk_pipeline = false;      // one problem: k x k stage by the panel pipeline
   bool fused = false;             // k <= 32: statistics before the update, X written in place
-  bool fused_wide = false;        // one problem, 64 < k <= 128, panel pipeline: the same
+  bool fused_pipe = false;        // one problem past k = 32 through the panel pipeline: the same
   GramRedItem* gred_items = nullptr;
   int n_gred = 0;
   int kmax = 0;
@@ -446,10 +446,10 @@ int build_plan(Plan& pl, const std::vector<refine_matrix>& As, const std::vector
 
   std::vector<RowItem> ri, gri;
   pl.fused = pl.kmax <= 32;
-  // one problem through the panel pipeline past k = 64: the statistics before
-  // the update as well (REFINE_FUSED_WIDE=0: update, statistics, normalisation)
-  pl.fused_wide = pl.kxk_pipeline && pl.kmax > 64;
-  if (const char* env = getenv("REFINE_FUSED_WIDE")) pl.fused_wide = pl.fused_wide && atoi(env) != 0;
+  // one problem past k = 32 through the panel pipeline: the statistics before
+  // the update as well (REFINE_FUSED_PIPE=0: update, statistics, normalisation)
+  pl.fused_pipe = pl.kxk_pipeline && pl.kmax > 32;
+  if (const char* env = getenv("REFINE_FUSED_PIPE")) pl.fused_pipe = pl.fused_pipe && atoi(env) != 0;
   std::vector<GramRedItem> rr;
   for (int p = 0; p < np; ++p) {
     const refine_matrix& A = As[p];
@@ -606,11 +606,12 @@ hipError_t enqueue_step(Plan& pl, hipStream_t st) {
   if ((e = launch_fin_d(pl.dprob, np, st)) != hipSuccess) return e;
   if ((e = launch_gram(pl.dprob, pl.gram_items, pl.n_gram, pl.kmax, pl.split, st)) != hipSuccess) return e;
   if ((e = launch_gram_reduce(pl.dprob, pl.gred_items, pl.n_gred, st)) != hipSuccess) return e;
-  if ((e = launch_kxk(pl.dprob, np, pl.kmax, pl.kxk_pipeline, pl.fused_wide, st)) != hipSuccess)
+  if ((e = launch_kxk(pl.dprob, np, pl.kmax, pl.kxk_pipeline, pl.fused_pipe, st)) != hipSuccess)
     return e;
-  if (pl.fused_wide) {
-    // one problem past k = 64: the statistics from k x k quantities after the
-    // pipeline, then the update writes the normalised iterate in place
+  if (pl.fused_pipe) {
+    // one problem through the panel pipeline: the statistics from k x k
+    // quantities after it, then the update writes the normalised iterate in
+    // place
     if ((e = launch_fin_post(pl.dprob, st)) != hipSuccess) return e;
     if ((e = launch_update(pl.dprob, pl.row_items, pl.n_row, pl.kmax, true, st)) != hipSuccess) return e;
     return hipSuccess;
