@@ -565,6 +565,33 @@ def test_kxk_panel_pipeline_steps(n, k, monkeypatch):
     assert flags[0] == 1 and flags[-1] == 0, flags
 
 
+@pytest.mark.parametrize("fused", ["1", "0"])
+@pytest.mark.parametrize("n,k,prec", [(1500, 128, "fp64"), (1100, 100, "split_crt"),
+                                      (900, 64, "fp64"), (700, 53, "split_int8")])
+def test_pipeline_update_orders_match_oracle(n, k, prec, fused, monkeypatch):
+    """One problem through the k x k panel pipeline, with the statistics
+    formed from k x k quadratic forms before an update that writes the
+    normalised iterate (REFINE_FUSED_PIPE=1, the default) and in the order
+    update, statistics, normalisation (0): both match the oracle's steps,
+    and the step statistics agree with the oracle's."""
+    monkeypatch.setenv("REFINE_FUSED_PIPE", fused)
+    P = synth.dense_spectrum(n, k, 7100 + n)
+    rf = _lib()
+    ctx = rf.RefineContext(_dev(P.A), k, norm_a=1.0, precision=prec)
+    form = {"fp64": {}, "split_int8": {"split": 9}, "split_crt": {"crt": 16}}[prec]
+    Xg = _dev(P.X0).clone()
+    Xo = np.array(P.X0, copy=True)
+    for s in range(3):
+        st = ctx.step(Xg)
+        assert st.status == rf.OK
+        r = oracle.refine_step(P.A, Xo, norm_a=1.0, **form)
+        Xo = r.X
+        err = float(np.max(np.abs(align_signs(Xg.cpu().numpy(), Xo) - Xo)))
+        assert err <= TOL, "step %d: %.3e" % (s, err)
+        assert st.corr_fro == pytest.approx(r.corr_fro, rel=1e-6)
+    ctx.close()
+
+
 @pytest.mark.parametrize("variant", [None, 2])
 def test_split_batched_matches_oracle_per_problem(variant, monkeypatch):
     """Batched split-mode steps (uneven n and k, one grouped launch per
